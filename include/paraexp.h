@@ -1,0 +1,196 @@
+/*
+ * paraexp.h -- C ABI of the MI355X Paraexp direct-adjoint gradient library.
+ *
+ * The library computes one gradient of a PDE-constrained cost per instance,
+ * following the direct-adjoint loop of Skene, Eggl & Schmid, "A
+ * parallel-in-time approach for accelerating direct-adjoint studies"
+ * (section 2) with the Paraexp time decomposition of section 3:
+ *
+ *  - the direct equation is split over P equal time slices; the P
+ *    inhomogeneous sub-problems start from zero data and run as one batch
+ *    (section 3.1, eq. linInhomEqus) with fixed-step classical RK4;
+ *  - their end states are propagated to the final time by the action of
+ *    the matrix exponential (eq. hom), computed with Arnoldi/Krylov
+ *    projection and a small dense exponential of the Hessenberg matrix
+ *    (section 4.1), either polynomial Krylov or shift-and-invert Krylov;
+ *  - the solution is the superposition of all pieces (eq. fullsol0);
+ *  - the adjoint (eq. adjEquation) starts from q^dagger(T) = dJ/dq(T)
+ *    (eq. adjFinalTime) and, being linear, is propagated the same way
+ *    (eq. adjHomNormal, adjhomfinal), with its time integral against the
+ *    forcing modulation evaluated inside the Krylov space;
+ *  - the gradient follows eq. paramupdate (forcing amplitudes) or
+ *    eq. initupdate (initial-condition amplitudes).
+ *
+ * Conventions
+ *  - Every array argument is a DEVICE pointer (HIP global memory) unless
+ *    stated otherwise; `pb` and scalars are host memory read during the
+ *    call only.  The caller owns every buffer.
+ *  - A batch of `batch` instances is described by `pb[0..batch-1]`.  Arrays
+ *    of grid size are packed instance after instance: instance i occupies
+ *    elements [off_i, off_i + nx_i*ny_i) with off_i the prefix sum of the
+ *    sizes; control-sized arrays are packed the same way with K_i.  2D grids
+ *    are row-major with x fastest.
+ *  - The calls never allocate device memory and never synchronise the
+ *    stream: work is enqueued on `stream` (a hipStream_t; NULL = default
+ *    stream) and uses only the caller's workspace `ws` of `ws_bytes`
+ *    bytes (query with pxp_workspace_size).  Calls that share a workspace
+ *    must not overlap.
+ *  - Argument errors are detected on the host before anything is enqueued
+ *    and nothing is written in that case.  Conditions found on the device
+ *    (Krylov non-convergence, non-finite values) are recorded in the
+ *    workspace and read back with pxp_device_status after the stream has
+ *    been synchronised.
+ *  - Double precision is used at the boundary in all modes.
+ */
+#ifndef PARAEXP_H
+#define PARAEXP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PXP_OK = 0,
+    PXP_EINVAL = 1,          /* malformed argument (sizes, nulls, steps)      */
+    PXP_EUNSUPPORTED = 2,    /* valid but not implemented for this operator   */
+    PXP_EWORKSPACE = 3,      /* workspace missing or too small                */
+    PXP_EUNSTABLE_DT = 4,    /* dt outside the RK4 stability region bound     */
+    PXP_EKRYLOV_NOCONV = 5,  /* device: Krylov estimate above tolerance       */
+    PXP_ENONFINITE = 6,      /* device: NaN/Inf met                           */
+    PXP_EHIP = 7             /* a HIP runtime call failed                     */
+} pxp_status;
+
+/* Operators (paper section 4.2 and 4.3; periodic grids, spacing L/n). */
+enum {
+    PXP_OP_ADVDIFF1D = 0,        /* -c u_x + nu u_xx, central differences     */
+    PXP_OP_ADVDIFF2D_UPWIND = 1, /* -vx u_x - vy u_y + nu lap u, upwind adv.  */
+    PXP_OP_BURGERS1D = 2         /* -u u_x + nu u_xx, central differences     */
+};
+enum { PXP_FP64 = 0, PXP_FP32_BULK = 1 };
+/* Controls: forcing amplitudes a_k of f(x,t) = sin(omega t) sum_k a_k G_k(x)
+ * (eq. paramupdate), or initial-condition amplitudes q0 = sum_k a_k phi_k
+ * (eq. initupdate). */
+enum { PXP_CTRL_FORCING = 0, PXP_CTRL_IC = 1 };
+/* Krylov flavour for the homogeneous exponentials. */
+enum { PXP_KRYLOV_POLY = 0, PXP_KRYLOV_SHIFT_INVERT = 1 };
+/* Schedule of the direct homogeneous pieces: CLASSIC = P-1 independent
+ * pieces exp((T - T_{p+1}) A) v_p (eq. hom); CHAIN = nested sum
+ * w <- exp(dT A) w + v_p, one piece after the other. */
+enum { PXP_SCHED_CLASSIC = 0, PXP_SCHED_CHAIN = 1 };
+/* Method: PARAEXP = the time-parallel path; SERIAL = plain RK4 stepping of
+ * the direct equation and its exact discrete adjoint (the comparison). */
+enum { PXP_METHOD_PARAEXP = 0, PXP_METHOD_SERIAL = 1 };
+
+typedef struct {
+    int32_t op, prec, ctrl, krylov;  /* enums above                           */
+    int32_t sched, nx, ny, P;        /* ny = 1 in 1D; P = number of slices     */
+    int32_t m, K, ckpt_every, block; /* Krylov dimension, #controls, Burgers
+                                        checkpoint interval (steps), threads
+                                        per workgroup for the 1D marches
+                                        (0 = library default)                 */
+    int64_t n_steps;                 /* RK4 steps; n_steps % P == 0            */
+    double L, vx, vy, nu;            /* box [0,L)^d, velocity, viscosity       */
+    double T, omega, beta;           /* horizon, s(t) = sin(omega t), weight   */
+    double krylov_tol;               /* relative a-posteriori tolerance        */
+    double si_gamma;                 /* shift-and-invert shift as a fraction of
+                                        the exponential's time (0 = 0.2)      */
+} pxp_problem;
+
+/* Bytes of device workspace the calls below need for this batch.
+ * Returns PXP_EINVAL/PXP_EUNSUPPORTED for problems the calls would reject. */
+pxp_status pxp_workspace_size(const pxp_problem* pb, int32_t batch,
+                              size_t* bytes);
+
+/* Zero the device status block at the start of a fresh workspace (enqueued
+ * on `stream` as a kernel).  Call once after allocating `ws`. */
+pxp_status pxp_workspace_init(void* ws, size_t ws_bytes, void* stream);
+
+/* Direct solve (section 3.1, eqs. linInhomEqus, hom, fullsol0):
+ *   q0  [sum n]  initial state (device)
+ *   F   [sum n]  forcing pattern f(x), modulated by sin(omega t) (nullable:
+ *                no forcing)
+ *   qT  [sum n]  output q(T)
+ * For PXP_OP_BURGERS1D the direct march is serial (section 3.3) and writes
+ * the checkpoints every ckpt_every steps into the workspace for the
+ * adjoint. */
+pxp_status paraexp_direct(const pxp_problem* pb, int32_t batch,
+                          const double* q0, const double* F, double* qT,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint solve (eqs. adjEquation, adjFinalTime, adjHomNormal,
+ * adjhomfinal) from the final condition lamT (= dJ/dq(T)):
+ *   lam0    [sum n]  output q^dagger(0) (nullable)
+ *   Lambda  [sum n]  output int_0^T sin(omega t) q^dagger(t) dt (nullable)
+ * Burgers instances need the checkpoints of the preceding paraexp_direct
+ * call in the same workspace. */
+pxp_status paraexp_adjoint(const pxp_problem* pb, int32_t batch,
+                           const double* lamT, double* lam0, double* Lambda,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* Full direct-adjoint loop (section 2): control -> J and dJ/da.
+ *   ctrl   [sum K]      control amplitudes a
+ *   basis  [sum K*n]    G_k (forcing) or phi_k (initial condition), row k of
+ *                       instance i at koff_i*n_i + k*n_i
+ *   q0     [sum n]      base initial state (nullable = zero)
+ *   u_tgt  [sum n]      target state of J = 1/2 |q(T) - u_tgt|^2 + beta |a|^2
+ *   J      [batch]      output cost
+ *   grad   [sum K]      output dJ/da
+ *   qT     [sum n]      output q(T) (nullable)
+ *   lam_out [sum n]     output Lambda (forcing) or lambda_0 (IC) (nullable)
+ * method selects PXP_METHOD_PARAEXP or PXP_METHOD_SERIAL. */
+pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
+                        const double* ctrl, const double* basis,
+                        const double* q0, const double* u_tgt, double* J,
+                        double* grad, double* qT, double* lam_out, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* Same as pxp_gradient with method = PXP_METHOD_PARAEXP: the name of the
+ * spec entry point. */
+pxp_status gradient(const pxp_problem* pb, int32_t batch, const double* ctrl,
+                    const double* basis, const double* q0,
+                    const double* u_tgt, double* J, double* grad, double* qT,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* Synchronises `stream` and returns the device-side status recorded in the
+ * workspace by the last calls (PXP_OK, PXP_EKRYLOV_NOCONV, PXP_ENONFINITE);
+ * `max_est` (host, nullable) receives the largest relative Krylov error
+ * estimate seen.  Clears the recorded status. */
+pxp_status pxp_device_status(void* ws, size_t ws_bytes, void* stream,
+                             double* max_est);
+
+/* Synchronises `stream` and reads the accumulated Krylov counters of the
+ * workspace: accepted substeps and Arnoldi iterations over all pieces since
+ * the last pxp_device_status call (host outputs, nullable). */
+pxp_status pxp_device_counters(void* ws, size_t ws_bytes, void* stream,
+                               uint64_t* substeps, uint64_t* krylov_iters);
+
+/* Launch timing for benchmarks and profiling.  While enabled, every launch
+ * of a kernel class is bracketed by two HIP events recorded on the launch
+ * stream.  pxp_profile_read waits for the recorded events of one class and
+ * returns their summed elapsed time (host outputs) and count, then forgets
+ * them.  Process-wide host state: not thread-safe. */
+enum {
+    PXP_K_SLICES = 0,          /* batched inhomogeneous RK4 slices          */
+    PXP_K_KRYLOV_DIRECT = 1,   /* direct homogeneous pieces (Arnoldi+expm)  */
+    PXP_K_KRYLOV_ADJOINT = 2,  /* adjoint homogeneous piece and integral    */
+    PXP_K_SERIAL_DIRECT = 3,   /* serial RK4 march                          */
+    PXP_K_SERIAL_REVERSE = 4,  /* serial reverse (discrete adjoint) sweep   */
+    PXP_K_LTV_ADJOINT = 5      /* time-varying adjoint pieces (Burgers)     */
+};
+pxp_status pxp_profile_enable(int32_t on);
+pxp_status pxp_profile_read(int32_t kernel_class, double* total_ms,
+                            int32_t* count);
+
+/* Human-readable text for a status code (static storage). */
+const char* pxp_status_str(pxp_status s);
+
+/* Library version string (static storage). */
+const char* pxp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PARAEXP_H */

@@ -1,0 +1,98 @@
+"""Convenience layer over the C ABI: problem descriptions from workload dicts
+and device buffers held as torch tensors.  Marshalling only; the arithmetic
+runs in libparaexp.so."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import _lib
+
+
+def make_problem(inst: dict, krylov: str = "shift_invert", sched: str = "classic",
+                 tol: float = 1e-11, block: int = 0, si_gamma: float = 0.2,
+                 P: int | None = None, m: int | None = None,
+                 prec: str = "fp64") -> _lib.pxp_problem:
+    p = _lib.pxp_problem()
+    p.op = _lib.OP[inst["op"]]
+    p.prec = _lib.PREC[prec]
+    p.ctrl = _lib.CTRL[inst["control"]]
+    p.krylov = _lib.KRYLOV[krylov]
+    p.sched = _lib.SCHED[sched]
+    p.nx = int(inst["nx"])
+    p.ny = int(inst.get("ny", 1))
+    p.P = int(inst["P"] if P is None else P)
+    p.m = int(inst["m"] if m is None else m)
+    p.K = int(np.asarray(inst["basis"]).shape[0])
+    p.ckpt_every = int(inst.get("ckpt_every", 64))
+    p.block = int(block)
+    p.n_steps = int(inst["n_steps"])
+    p.L = float(inst["L"])
+    p.vx = float(inst.get("vx", 0.0))
+    p.vy = float(inst.get("vy", 0.0))
+    p.nu = float(inst["nu"])
+    p.T = float(inst["T"])
+    p.omega = float(inst.get("omega", 1.0))
+    p.beta = float(inst.get("beta", 0.0))
+    p.krylov_tol = float(tol)
+    p.si_gamma = float(si_gamma)
+    return p
+
+
+class GradientRunner:
+    """Device buffers for a batch of instances and one gradient call."""
+
+    def __init__(self, instances, method: str = "paraexp", device: str = "cuda:0",
+                 a=None, **prob_kw):
+        import torch
+        self.torch = torch
+        self.instances = list(instances)
+        self.method = method
+        self.device = torch.device(device)
+        self.problems = [make_problem(inst, **prob_kw) for inst in self.instances]
+        f64 = dict(dtype=torch.float64, device=self.device)
+        ctrl = [np.asarray(inst["a"] if a is None else a[i], dtype=np.float64)
+                for i, inst in enumerate(self.instances)]
+        self.ctrl = torch.tensor(np.concatenate(ctrl), **f64)
+        self.basis = torch.tensor(np.concatenate(
+            [np.asarray(inst["basis"], dtype=np.float64).ravel() for inst in self.instances]), **f64)
+        self.q0 = torch.tensor(np.concatenate(
+            [np.asarray(inst.get("q0", np.zeros(inst["nx"] * inst.get("ny", 1))),
+                        dtype=np.float64) for inst in self.instances]), **f64)
+        self.u_tgt = torch.tensor(np.concatenate(
+            [np.asarray(inst["u_tgt"], dtype=np.float64) for inst in self.instances]), **f64)
+        ntot = self.u_tgt.numel()
+        self.J = torch.zeros(len(self.instances), **f64)
+        self.grad = torch.zeros(self.ctrl.numel(), **f64)
+        self.qT = torch.zeros(ntot, **f64)
+        self.lam = torch.zeros(ntot, **f64)
+        nbytes = _lib.pxp_workspace_size(self.problems)
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        _lib.pxp_workspace_init(self.ws)
+        self.sizes = [int(inst["nx"]) * int(inst.get("ny", 1)) for inst in self.instances]
+        self.ks = [int(np.asarray(inst["basis"]).shape[0]) for inst in self.instances]
+
+    def run(self, stream=None):
+        _lib.pxp_gradient(self.problems, self.method, self.ctrl, self.basis, self.q0,
+                          self.u_tgt, self.J, self.grad, self.qT, self.lam, self.ws,
+                          stream)
+
+    def status(self):
+        return _lib.pxp_device_status(self.ws)
+
+    def counters(self):
+        return _lib.pxp_device_counters(self.ws)
+
+    def results(self):
+        self.torch.cuda.synchronize(self.device)
+        J = self.J.cpu().numpy()
+        g = self.grad.cpu().numpy()
+        qT = self.qT.cpu().numpy()
+        lam = self.lam.cpu().numpy()
+        out = []
+        o = ko = 0
+        for i, (n, K) in enumerate(zip(self.sizes, self.ks)):
+            out.append(dict(J=float(J[i]), grad=g[ko:ko + K], qT=qT[o:o + n],
+                            lam=lam[o:o + n]))
+            o += n
+            ko += K
+        return out

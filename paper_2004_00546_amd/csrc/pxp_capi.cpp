@@ -1,0 +1,615 @@
+// C ABI and host engine: argument validation, workspace layout and the order
+// of the launches that make up the direct solve, the adjoint solve and the
+// full direct-adjoint loop (paper sections 2 and 3).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../../include/paraexp.h"
+#include "pxp_internal.hpp"
+
+namespace pxp {
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int M_MAX_1D = 48;
+
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+    size_t status;           // DevStatus
+    std::vector<size_t> base;  // per-instance region offset
+    size_t total;
+};
+
+// Per-instance buffers (offsets relative to the instance region).
+struct Inst {
+    size_t F, g0, q0eff, slices, pieces, basis, qT, lamT, lam0, Lam, chain,
+        ckpt, seg, J, size;
+};
+
+int64_t grid_n(const pxp_problem& p) { return (int64_t)p.nx * (int64_t)p.ny; }
+
+bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+Tri advdiff_tri(const pxp_problem& p) {
+    const double h = p.L / p.nx;
+    Tri A;
+    A.lo = p.vx / (2.0 * h) + p.nu / (h * h);
+    A.d = -2.0 * p.nu / (h * h);
+    A.up = -p.vx / (2.0 * h) + p.nu / (h * h);
+    return A;
+}
+Tri transpose(Tri A) {
+    Tri B;
+    B.lo = A.up;
+    B.d = A.d;
+    B.up = A.lo;
+    return B;
+}
+
+// max_k |R(dt lambda_k)| for RK4 over the exact eigenvalues of the 1D
+// central advection-diffusion operator (circulant).
+bool rk4_stable_advdiff1d(const pxp_problem& p) {
+    const double h = p.L / p.nx, dt = p.T / (double)p.n_steps;
+    for (int k = 0; k < p.nx; ++k) {
+        const double th = 2.0 * M_PI * k / p.nx;
+        const std::complex<double> lam(p.nu * (2.0 * std::cos(th) - 2.0) / (h * h),
+                                       -p.vx * std::sin(th) / h);
+        const std::complex<double> z = dt * lam;
+        const std::complex<double> R = 1.0 + z + z * z / 2.0 + z * z * z / 6.0 +
+                                       z * z * z * z / 24.0;
+        if (std::abs(R) > 1.0 + 1e-12) return false;
+    }
+    return true;
+}
+
+pxp_status validate(const pxp_problem& p) {
+    if (p.nx < 2 || p.ny < 1 || p.n_steps < 1 || p.P < 1 || p.T <= 0.0 ||
+        p.L <= 0.0 || p.nu < 0.0 || p.K < 0 || !std::isfinite(p.T) ||
+        !std::isfinite(p.nu) || !std::isfinite(p.vx))
+        return PXP_EINVAL;
+    if (p.n_steps % p.P != 0) return PXP_EINVAL;
+    if (p.ctrl != PXP_CTRL_FORCING && p.ctrl != PXP_CTRL_IC) return PXP_EINVAL;
+    if (p.krylov != PXP_KRYLOV_POLY && p.krylov != PXP_KRYLOV_SHIFT_INVERT)
+        return PXP_EINVAL;
+    if (p.sched != PXP_SCHED_CLASSIC && p.sched != PXP_SCHED_CHAIN) return PXP_EINVAL;
+    if (p.prec != PXP_FP64) return PXP_EUNSUPPORTED;
+    if (p.op == PXP_OP_ADVDIFF1D) {
+        if (p.ny != 1) return PXP_EINVAL;
+        if (p.m < 1 || p.m > M_MAX_1D) return PXP_EUNSUPPORTED;
+        int b, pt;
+        if (!march_shape(p.nx, p.block, &b, &pt)) return PXP_EUNSUPPORTED;
+        // cyclic reduction: n a power of two, every thread of a 64-wide
+        // multiple owning whole points
+        if (p.krylov == PXP_KRYLOV_SHIFT_INVERT && (!is_pow2(p.nx) || p.nx < 64))
+            return PXP_EUNSUPPORTED;
+        if (!(p.krylov_tol > 0.0)) return PXP_EINVAL;
+        if (!rk4_stable_advdiff1d(p)) return PXP_EUNSTABLE_DT;
+        return PXP_OK;
+    }
+    if (p.op == PXP_OP_BURGERS1D) {
+        if (p.ny != 1) return PXP_EINVAL;
+        if (p.ctrl != PXP_CTRL_IC) return PXP_EUNSUPPORTED;
+        int b, pt;
+        if (!march_shape(p.nx, p.block, &b, &pt)) return PXP_EUNSUPPORTED;
+        if (p.ckpt_every < 1 || p.n_steps % p.ckpt_every) return PXP_EINVAL;
+        // diffusion part of the spectrum on the negative real axis
+        const double h = p.L / p.nx, dt = p.T / (double)p.n_steps;
+        if (dt * 4.0 * p.nu / (h * h) > 2.785) return PXP_EUNSTABLE_DT;
+        return PXP_OK;
+    }
+    if (p.op == PXP_OP_ADVDIFF2D_UPWIND) return PXP_EUNSUPPORTED;
+    return PXP_EINVAL;
+}
+
+Inst inst_layout(const pxp_problem& p) {
+    const size_t n = (size_t)grid_n(p), d = sizeof(double);
+    const size_t P = (size_t)p.P, m = (size_t)p.m;
+    Inst L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    L.F = take(n * d);
+    L.g0 = take(n * d);
+    L.q0eff = take(n * d);
+    L.qT = take(n * d);
+    L.lamT = take(n * d);
+    L.lam0 = take(n * d);
+    L.Lam = take(n * d);
+    L.chain = take(n * d);
+    L.J = take(d);
+    if (p.op == PXP_OP_ADVDIFF1D) {
+        L.slices = take(P * n * d);
+        L.pieces = take((P > 1 ? P - 1 : 1) * n * d);
+        const size_t npar = (p.sched == PXP_SCHED_CLASSIC && P > 1) ? P - 1 : 1;
+        L.basis = take(npar * (m + 1) * n * d);
+    }
+    if (p.op == PXP_OP_BURGERS1D) {
+        const size_t c = (size_t)p.ckpt_every;
+        L.ckpt = take(((size_t)p.n_steps / c + 1) * n * d);
+        L.seg = take(c * n * d);
+    }
+    L.size = off;
+    return L;
+}
+
+Layout layout(const pxp_problem* pb, int batch) {
+    Layout Ly;
+    size_t off = 0;
+    Ly.status = off;
+    off += align_up(sizeof(DevStatus));
+    for (int i = 0; i < batch; ++i) {
+        Ly.base.push_back(off);
+        off += inst_layout(pb[i]).size;
+    }
+    Ly.total = off;
+    return Ly;
+}
+
+pxp_status check_all(const pxp_problem* pb, int batch) {
+    if (batch < 0 || (batch > 0 && !pb)) return PXP_EINVAL;
+    for (int i = 0; i < batch; ++i) {
+        pxp_status s = validate(pb[i]);
+        if (s != PXP_OK) return s;
+    }
+    return PXP_OK;
+}
+
+#define HIPCHK(x)                               \
+    do {                                        \
+        if ((x) != hipSuccess) return PXP_EHIP; \
+    } while (0)
+
+// Optional launch timing: when enabled, every launch of a kernel class is
+// bracketed by two events recorded on the launch stream.  Host-side state,
+// not thread-safe; meant for benchmarks and profiling runs only.
+struct Profiler {
+    bool on = false;
+    struct Rec {
+        int cls;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+Profiler g_prof;
+
+struct ProfScope {
+    int cls;
+    hipStream_t s;
+    hipEvent_t b = nullptr;
+    ProfScope(int c, hipStream_t st) : cls(c), s(st) {
+        if (!g_prof.on) return;
+        hipEvent_t a = g_prof.get();
+        b = g_prof.get();
+        if (!a || !b) return;
+        hipEventRecord(a, s);
+        g_prof.recs.push_back({cls, a, b});
+    }
+    ~ProfScope() {
+        if (g_prof.on && b) hipEventRecord(b, s);
+    }
+};
+
+struct Ctx {
+    const pxp_problem& p;
+    char* base;
+    Inst L;
+    DevStatus* st;
+    hipStream_t s;
+    double* at(size_t off) const { return reinterpret_cast<double*>(base + off); }
+    int n() const { return (int)grid_n(p); }
+    double dt() const { return p.T / (double)p.n_steps; }
+};
+
+KrylovArgs kargs(const Ctx& c, Tri op) {
+    KrylovArgs a{};
+    a.si = (c.p.krylov == PXP_KRYLOV_SHIFT_INVERT) ? 1 : 0;
+    a.n = c.n();
+    a.m = c.p.m;
+    a.tol = c.p.krylov_tol;
+    a.gamma_frac = (c.p.si_gamma > 0.0) ? c.p.si_gamma : 0.2;
+    a.op = op;
+    a.basis = c.at(c.L.basis);
+    a.status = c.st;
+    return a;
+}
+
+// Direct solve of one linear 1D instance: q0 (device, nullable), F
+// (nullable) -> qT.
+pxp_status direct_lin1d(const Ctx& c, const double* q0, const double* F,
+                        double* qT, int method) {
+    const int n = c.n();
+    const Tri A = advdiff_tri(c.p);
+    const double* g0 = nullptr;
+    if (q0) {
+        // IC shift q~ = q - q0: the source gains A q0 (eq. linzero)
+        HIPCHK(launch_apply_tri(q0, c.at(c.L.g0), n, A, c.s));
+        g0 = c.at(c.L.g0);
+    }
+    if (method == PXP_METHOD_SERIAL) {
+        ProfScope ps(PXP_K_SERIAL_DIRECT, c.s);
+        HIPCHK(launch_rk4_lin1d(F, nullptr, q0, qT, n, 1, c.p.n_steps, c.dt(),
+                                c.p.omega, A, c.p.block, c.s));
+        return PXP_OK;
+    }
+    const int P = c.p.P;
+    const int64_t n_s = c.p.n_steps / P;
+    double* slices = c.at(c.L.slices);
+    // (1) P inhomogeneous sub-problems from zero data, one batch
+    {
+        ProfScope ps(PXP_K_SLICES, c.s);
+        HIPCHK(launch_rk4_lin1d(F, g0, nullptr, slices, n, P, n_s, c.dt(),
+                                c.p.omega, A, c.p.block, c.s));
+    }
+    if (P == 1) {
+        HIPCHK(launch_recombine(q0, slices, nullptr, 0, n, qT, c.st, c.s));
+        return PXP_OK;
+    }
+    const double dT = c.p.T / P;
+    KrylovArgs a = kargs(c, A);
+    a.vin = slices;
+    a.tau = dT;
+    if (c.p.sched == PXP_SCHED_CLASSIC) {
+        // (2) P-1 independent homogeneous pieces exp((T - T_{p+1}) A) v_p
+        a.mode = KM_CLASSIC;
+        a.npieces = P - 1;
+        a.yout = c.at(c.L.pieces);
+        {
+            ProfScope ps(PXP_K_KRYLOV_DIRECT, c.s);
+            HIPCHK(launch_krylov1d(a, 0, c.s));
+        }
+        // (3) superposition q(T) = q0 + v_{P-1} + sum_p pieces
+        HIPCHK(launch_recombine(q0, slices + (size_t)(P - 1) * n, c.at(c.L.pieces),
+                                P - 1, n, qT, c.st, c.s));
+    } else {
+        // nested form of the same sum: w <- exp(dT A) w + v_p
+        a.mode = KM_CHAIN;
+        a.npieces = P;
+        a.yout = c.at(c.L.chain);
+        {
+            ProfScope ps(PXP_K_KRYLOV_DIRECT, c.s);
+            HIPCHK(launch_krylov1d(a, 0, c.s));
+        }
+        HIPCHK(launch_recombine(q0, nullptr, c.at(c.L.chain), 1, n, qT, c.st, c.s));
+    }
+    return PXP_OK;
+}
+
+// Adjoint of one linear 1D instance from lamT: lam0 and/or Lambda.
+pxp_status adjoint_lin1d(const Ctx& c, const double* lamT, double* lam0,
+                         double* Lam, int method) {
+    const int n = c.n();
+    const Tri AT = transpose(advdiff_tri(c.p));
+    if (method == PXP_METHOD_SERIAL) {
+        ProfScope ps(PXP_K_SERIAL_REVERSE, c.s);
+        HIPCHK(launch_rk4_rev_lin1d(lamT, lam0, Lam, n, c.p.n_steps, c.dt(),
+                                    c.p.omega, AT, c.p.block, c.s));
+        return PXP_OK;
+    }
+    // The terminal-cost adjoint is one homogeneous piece from q^dagger(T)
+    // over [T, 0] (eq. adjhomfinal); in tau = T - t it reads
+    // d lam / d tau = A^T lam, and Lambda = int_0^T sin(omega (T - tau))
+    // lam(tau) d tau is formed inside the Krylov space.
+    KrylovArgs a = kargs(c, AT);
+    a.mode = KM_SINGLE;
+    a.npieces = 1;
+    a.vin = lamT;
+    a.yout = lam0;
+    a.iout = Lam;
+    a.tau = c.p.T;
+    a.ia = c.p.omega * c.p.T;
+    a.ib = -c.p.omega;
+    if (!lam0 && !Lam) return PXP_OK;
+    ProfScope ps(PXP_K_KRYLOV_ADJOINT, c.s);
+    HIPCHK(launch_krylov1d(a, 0, c.s));
+    return PXP_OK;
+}
+
+pxp_status direct_burgers(const Ctx& c, const double* q0, double* qT) {
+    ProfScope ps(PXP_K_SERIAL_DIRECT, c.s);
+    HIPCHK(launch_rk4_burgers_direct(q0, qT, c.at(c.L.ckpt), c.n(), c.p.n_steps,
+                                     c.p.ckpt_every, c.dt(), c.p.nu, c.p.L,
+                                     c.p.block, c.s));
+    return PXP_OK;
+}
+
+pxp_status adjoint_burgers(const Ctx& c, const double* lamT, double* lam0) {
+    ProfScope ps(PXP_K_SERIAL_REVERSE, c.s);
+    HIPCHK(launch_rk4_burgers_reverse(c.at(c.L.ckpt), lamT, lam0, c.at(c.L.seg),
+                                      c.n(), c.p.n_steps, c.p.ckpt_every, c.dt(),
+                                      c.p.nu, c.p.L, c.p.block, c.s));
+    return PXP_OK;
+}
+
+pxp_status ws_check(const pxp_problem* pb, int batch, void* ws, size_t ws_bytes,
+                    Layout* Ly) {
+    *Ly = layout(pb, batch);
+    if (!ws || ws_bytes < Ly->total) return PXP_EWORKSPACE;
+    if (reinterpret_cast<uintptr_t>(ws) % ALIGN) return PXP_EWORKSPACE;
+    return PXP_OK;
+}
+
+Ctx make_ctx(const pxp_problem& p, void* ws, const Layout& Ly, int i,
+             hipStream_t s) {
+    char* w = static_cast<char*>(ws);
+    return Ctx{p, w + Ly.base[i], inst_layout(p),
+               reinterpret_cast<DevStatus*>(w + Ly.status), s};
+}
+
+}  // namespace
+}  // namespace pxp
+
+using namespace pxp;
+
+extern "C" {
+
+const char* pxp_version(void) { return "paraexp-mi355x 0.1"; }
+
+const char* pxp_status_str(pxp_status s) {
+    switch (s) {
+        case PXP_OK: return "ok";
+        case PXP_EINVAL: return "invalid argument";
+        case PXP_EUNSUPPORTED: return "unsupported problem";
+        case PXP_EWORKSPACE: return "workspace missing, misaligned or too small";
+        case PXP_EUNSTABLE_DT: return "time step outside the RK4 stability bound";
+        case PXP_EKRYLOV_NOCONV: return "Krylov error estimate above tolerance";
+        case PXP_ENONFINITE: return "non-finite value";
+        case PXP_EHIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+pxp_status pxp_workspace_size(const pxp_problem* pb, int32_t batch,
+                              size_t* bytes) {
+    if (!bytes) return PXP_EINVAL;
+    pxp_status st = check_all(pb, batch);
+    if (st != PXP_OK) return st;
+    *bytes = layout(pb, batch).total;
+    return PXP_OK;
+}
+
+pxp_status pxp_workspace_init(void* ws, size_t ws_bytes, void* stream) {
+    if (!ws || ws_bytes < sizeof(DevStatus)) return PXP_EWORKSPACE;
+    if (launch_zero(static_cast<double*>(ws), sizeof(DevStatus) / sizeof(double),
+                    static_cast<hipStream_t>(stream)) != hipSuccess)
+        return PXP_EHIP;
+    return PXP_OK;
+}
+
+static pxp_status direct_impl(const pxp_problem* pb, int32_t batch,
+                              const double* q0, const double* F, double* qT,
+                              void* ws, size_t ws_bytes, void* stream,
+                              int method) {
+    pxp_status st = check_all(pb, batch);
+    if (st != PXP_OK) return st;
+    if (batch == 0) return PXP_OK;
+    if (!qT) return PXP_EINVAL;
+    Layout Ly;
+    st = ws_check(pb, batch, ws, ws_bytes, &Ly);
+    if (st != PXP_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    size_t off = 0;
+    for (int i = 0; i < batch; ++i) {
+        const pxp_problem& p = pb[i];
+        Ctx c = make_ctx(p, ws, Ly, i, s);
+        const double* q0i = q0 ? q0 + off : nullptr;
+        const double* Fi = F ? F + off : nullptr;
+        if (p.op == PXP_OP_ADVDIFF1D) {
+            st = direct_lin1d(c, q0i, Fi, qT + off, method);
+        } else {
+            if (!q0i) return PXP_EINVAL;
+            st = direct_burgers(c, q0i, qT + off);
+        }
+        if (st != PXP_OK) return st;
+        off += (size_t)grid_n(p);
+    }
+    return PXP_OK;
+}
+
+pxp_status paraexp_direct(const pxp_problem* pb, int32_t batch,
+                          const double* q0, const double* F, double* qT,
+                          void* ws, size_t ws_bytes, void* stream) {
+    return direct_impl(pb, batch, q0, F, qT, ws, ws_bytes, stream,
+                       PXP_METHOD_PARAEXP);
+}
+
+static pxp_status adjoint_impl(const pxp_problem* pb, int32_t batch,
+                               const double* lamT, double* lam0, double* Lambda,
+                               void* ws, size_t ws_bytes, void* stream,
+                               int method) {
+    pxp_status st = check_all(pb, batch);
+    if (st != PXP_OK) return st;
+    if (batch == 0) return PXP_OK;
+    if (!lamT) return PXP_EINVAL;
+    Layout Ly;
+    st = ws_check(pb, batch, ws, ws_bytes, &Ly);
+    if (st != PXP_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    size_t off = 0;
+    for (int i = 0; i < batch; ++i) {
+        const pxp_problem& p = pb[i];
+        Ctx c = make_ctx(p, ws, Ly, i, s);
+        if (p.op == PXP_OP_ADVDIFF1D) {
+            st = adjoint_lin1d(c, lamT + off, lam0 ? lam0 + off : nullptr,
+                               Lambda ? Lambda + off : nullptr, method);
+        } else {
+            if (Lambda) return PXP_EINVAL;  // no forcing control for Burgers
+            if (!lam0) return PXP_EINVAL;
+            st = adjoint_burgers(c, lamT + off, lam0 + off);
+        }
+        if (st != PXP_OK) return st;
+        off += (size_t)grid_n(p);
+    }
+    return PXP_OK;
+}
+
+pxp_status paraexp_adjoint(const pxp_problem* pb, int32_t batch,
+                           const double* lamT, double* lam0, double* Lambda,
+                           void* ws, size_t ws_bytes, void* stream) {
+    return adjoint_impl(pb, batch, lamT, lam0, Lambda, ws, ws_bytes, stream,
+                        PXP_METHOD_PARAEXP);
+}
+
+pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
+                        const double* ctrl, const double* basis,
+                        const double* q0, const double* u_tgt, double* J,
+                        double* grad, double* qT, double* lam_out, void* ws,
+                        size_t ws_bytes, void* stream) {
+    pxp_status st = check_all(pb, batch);
+    if (st != PXP_OK) return st;
+    if (method != PXP_METHOD_PARAEXP && method != PXP_METHOD_SERIAL)
+        return PXP_EINVAL;
+    if (batch == 0) return PXP_OK;
+    if (!u_tgt || !J || !grad) return PXP_EINVAL;
+    Layout Ly;
+    st = ws_check(pb, batch, ws, ws_bytes, &Ly);
+    if (st != PXP_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    size_t off = 0, koff = 0, boff = 0;
+    for (int i = 0; i < batch; ++i) {
+        const pxp_problem& p = pb[i];
+        const int n = (int)grid_n(p);
+        const int K = p.K;
+        if (K > 0 && (!ctrl || !basis)) return PXP_EINVAL;
+        Ctx c = make_ctx(p, ws, Ly, i, s);
+        const double* a = ctrl ? ctrl + koff : nullptr;
+        const double* G = basis ? basis + boff : nullptr;
+        const double* q0i = q0 ? q0 + off : nullptr;
+        double* qTi = qT ? qT + off : c.at(c.L.qT);
+        double* lamT = c.at(c.L.lamT);
+        double* lam0 = c.at(c.L.lam0);
+        double* Lam = c.at(c.L.Lam);
+        // (a1) controls -> forcing pattern or initial state
+        const double* F = nullptr;
+        const double* init = q0i;
+        if (p.ctrl == PXP_CTRL_FORCING) {
+            HIPCHK(launch_combine_basis(a, G, nullptr, c.at(c.L.F), K, n, s));
+            F = c.at(c.L.F);
+        } else {
+            HIPCHK(launch_combine_basis(a, G, q0i, c.at(c.L.q0eff), K, n, s));
+            init = c.at(c.L.q0eff);
+        }
+        // (a2-a4) direct
+        if (p.op == PXP_OP_ADVDIFF1D) {
+            st = direct_lin1d(c, init, F, qTi, method);
+        } else {
+            if (!init) return PXP_EINVAL;
+            st = direct_burgers(c, init, qTi);
+        }
+        if (st != PXP_OK) return st;
+        // (a5) cost and adjoint final condition
+        HIPCHK(launch_cost(qTi, u_tgt + off, a, n, K, p.beta, lamT, J + i, s));
+        // (a6-a8) adjoint
+        const bool forcing = (p.ctrl == PXP_CTRL_FORCING);
+        if (p.op == PXP_OP_ADVDIFF1D) {
+            st = adjoint_lin1d(c, lamT, forcing ? nullptr : lam0,
+                               forcing ? Lam : nullptr, method);
+        } else {
+            st = adjoint_burgers(c, lamT, lam0);
+        }
+        if (st != PXP_OK) return st;
+        // (a9) gradient
+        const double* v = forcing ? Lam : lam0;
+        HIPCHK(launch_grad(G, v, a, K, n, p.beta, grad + koff, s));
+        if (lam_out)
+            HIPCHK(launch_add(nullptr, v, lam_out + off, n, s));
+        off += (size_t)n;
+        koff += (size_t)K;
+        boff += (size_t)K * n;
+    }
+    return PXP_OK;
+}
+
+pxp_status gradient(const pxp_problem* pb, int32_t batch, const double* ctrl,
+                    const double* basis, const double* q0, const double* u_tgt,
+                    double* J, double* grad, double* qT, void* ws,
+                    size_t ws_bytes, void* stream) {
+    return pxp_gradient(pb, batch, PXP_METHOD_PARAEXP, ctrl, basis, q0, u_tgt,
+                        J, grad, qT, nullptr, ws, ws_bytes, stream);
+}
+
+pxp_status pxp_device_status(void* ws, size_t ws_bytes, void* stream,
+                             double* max_est) {
+    if (!ws || ws_bytes < sizeof(DevStatus)) return PXP_EWORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipStreamSynchronize(s) != hipSuccess) return PXP_EHIP;
+    DevStatus h{};
+    if (hipMemcpy(&h, ws, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+        return PXP_EHIP;
+    if (max_est) {
+        double e;
+        std::memcpy(&e, &h.max_est, sizeof(e));
+        *max_est = e;
+    }
+    if (launch_zero(static_cast<double*>(ws), sizeof(DevStatus) / sizeof(double), s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return PXP_EHIP;
+    if (h.flags & ST_NONFINITE) return PXP_ENONFINITE;
+    if (h.flags & ST_NOCONV) return PXP_EKRYLOV_NOCONV;
+    return PXP_OK;
+}
+
+pxp_status pxp_device_counters(void* ws, size_t ws_bytes, void* stream,
+                               uint64_t* substeps, uint64_t* krylov_iters) {
+    if (!ws || ws_bytes < sizeof(DevStatus)) return PXP_EWORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipStreamSynchronize(s) != hipSuccess) return PXP_EHIP;
+    DevStatus h{};
+    if (hipMemcpy(&h, ws, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+        return PXP_EHIP;
+    if (substeps) *substeps = h.substeps;
+    if (krylov_iters) *krylov_iters = h.krylov_iters;
+    return PXP_OK;
+}
+
+pxp_status pxp_profile_enable(int32_t on) {
+    g_prof.on = (on != 0);
+    return PXP_OK;
+}
+
+pxp_status pxp_profile_read(int32_t kernel_class, double* total_ms,
+                            int32_t* count) {
+    if (!total_ms || !count) return PXP_EINVAL;
+    double tot = 0.0;
+    int cnt = 0;
+    std::vector<Profiler::Rec> keep;
+    for (auto& r : g_prof.recs) {
+        if (r.cls != kernel_class) {
+            keep.push_back(r);
+            continue;
+        }
+        if (hipEventSynchronize(r.b) != hipSuccess) return PXP_EHIP;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return PXP_EHIP;
+        tot += ms;
+        ++cnt;
+        g_prof.pool.push_back(r.a);
+        g_prof.pool.push_back(r.b);
+    }
+    g_prof.recs.swap(keep);
+    *total_ms = tot;
+    *count = cnt;
+    return PXP_OK;
+}
+
+}  // extern "C"

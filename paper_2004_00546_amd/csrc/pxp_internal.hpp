@@ -1,0 +1,107 @@
+// Internal launcher interface between the C ABI / host engine and the HIP
+// kernels.  Every launcher enqueues on the given stream and returns the HIP
+// launch status; none allocates or synchronises.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pxp {
+
+// Periodic tridiagonal operator (Op x)_i = lo x_{i-1} + d x_i + up x_{i+1}.
+struct Tri {
+    double lo, d, up;
+};
+
+// Device-side status block at the start of every workspace.
+struct DevStatus {
+    unsigned int flags;          // bit 0: Krylov estimate above tolerance,
+                                 // bit 1: non-finite value met
+    unsigned int pad;
+    unsigned long long max_est;  // bit pattern of the largest relative est.
+    unsigned long long substeps; // accepted Krylov substeps (all pieces)
+    unsigned long long krylov_iters;
+};
+constexpr unsigned int ST_NOCONV = 1u;
+constexpr unsigned int ST_NONFINITE = 2u;
+
+// ---- RK4 marches (1D, one workgroup per slice) ---------------------------
+// Slices p = 0..P-1 of a linear 1D problem, each from zero (or from y0 when
+// given, P must then be 1) over n_s steps starting at global step p*n_s:
+//   y' = A y + sin(omega t) F + g0.
+hipError_t launch_rk4_lin1d(const double* F, const double* g0, const double* y0,
+                            double* out, int n, int P, int64_t n_s, double dt,
+                            double omega, Tri A, int block, hipStream_t s);
+
+// Reverse sweep of the exact discrete adjoint of the linear RK4 march:
+// from lamT to lam0 and Lambda = sum s(t_stage) kbar_stage.
+hipError_t launch_rk4_rev_lin1d(const double* lamT, double* lam0,
+                                double* Lambda, int n, int64_t n_t, double dt,
+                                double omega, Tri AT, int block, hipStream_t s);
+
+// Burgers 1D direct march with checkpoints every c steps (ckpt[k] = state at
+// step k*c, k = 0..n_t/c).
+hipError_t launch_rk4_burgers_direct(const double* y0, double* yT, double* ckpt,
+                                     int n, int64_t n_t, int64_t c, double dt,
+                                     double nu, double L, int block,
+                                     hipStream_t s);
+
+// Burgers reverse sweep, serial, over segments between checkpoints: each
+// segment's step states are recomputed into `seg` (c x n) first.
+hipError_t launch_rk4_burgers_reverse(const double* ckpt, const double* lamT,
+                                      double* lam0, double* seg, int n,
+                                      int64_t n_t, int64_t c, double dt,
+                                      double nu, double L, int block,
+                                      hipStream_t s);
+
+// ---- Krylov exponential pieces (1D tridiagonal operator) -------------------
+enum KrylovMode { KM_CLASSIC = 0, KM_CHAIN = 1, KM_SINGLE = 2 };
+
+struct KrylovArgs {
+    int mode;            // KrylovMode
+    int si;              // 0 polynomial, 1 shift-and-invert
+    int n, m;
+    int npieces;         // classic: P-1 pieces; chain: P slices; single: 1
+    const double* vin;   // classic/chain: slice end states [P][n]; single: [n]
+    double* yout;        // classic: [P-1][n]; chain/single: [n]
+    double* iout;        // single: integral output [n] (nullable)
+    double tau;          // single: time; chain: slice length; classic: slice
+                         // length dT (piece p uses (npieces - p) * dT)
+    double ia, ib;       // integral weight sin(ia + ib * sigma)
+    double tol;          // relative tolerance
+    double gamma_frac;   // shift-and-invert shift = gamma_frac * time
+    Tri op;
+    double* basis;       // [gridDim][m+1][n] workspace
+    DevStatus* status;
+};
+hipError_t launch_krylov1d(const KrylovArgs& a, int block, hipStream_t s);
+size_t krylov1d_lds_bytes(int n, int m, int block, int si);
+
+// ---- small kernels ---------------------------------------------------------
+// out[i] = base[i] (or 0) + sum_k a[k] basis[k*n + i]
+hipError_t launch_combine_basis(const double* a, const double* basis,
+                                const double* base, double* out, int K, int n,
+                                hipStream_t s);
+// out = Op x (tridiagonal, periodic)
+hipError_t launch_apply_tri(const double* x, double* out, int n, Tri op,
+                            hipStream_t s);
+// lamT = qT - tgt;  J = 1/2 |lamT|^2 + beta |a|^2 (one workgroup)
+hipError_t launch_cost(const double* qT, const double* tgt, const double* a,
+                       int n, int K, double beta, double* lamT, double* J,
+                       hipStream_t s);
+// grad[k] = <basis_k, v> + 2 beta a[k] (one workgroup per k)
+hipError_t launch_grad(const double* basis, const double* v, const double* a,
+                       int K, int n, double beta, double* grad, hipStream_t s);
+// out = q0 (or 0) + vlast + sum_{p<np} Y[p]   (checks finiteness)
+hipError_t launch_recombine(const double* q0, const double* vlast,
+                            const double* Y, int np, int n, double* out,
+                            DevStatus* st, hipStream_t s);
+// p[0..n) = 0 (a kernel, so it may be captured in a graph)
+hipError_t launch_zero(double* p, size_t n, hipStream_t s);
+// Threads per workgroup and points per thread of the register-resident
+// 1D marches (false if n has no supported shape).
+bool march_shape(int n, int block_hint, int* block, int* pt);
+// out = (a or 0) + b
+hipError_t launch_add(const double* a, const double* b, double* out, int n,
+                      hipStream_t s);
+
+}  // namespace pxp

@@ -1,0 +1,551 @@
+// Action of the matrix exponential on the homogeneous pieces (paper section
+// 4.1): Arnoldi projection onto the Krylov space, exponential of the small
+// Hessenberg matrix, exp(tau A) v ~ beta V_m exp(tau H_m) e_1.
+//
+// One workgroup owns one piece.  Thread t owns the strided points
+// i = t + r*B (r < PT), so every read of a basis vector is coalesced and each
+// thread only ever reads back basis entries it wrote itself.  The basis lives
+// in HBM (streamed through L2/MALL); the Hessenberg matrix and all small dense
+// work live in LDS.
+//
+// Two Krylov flavours:
+//  - polynomial: K_m(A, v); the time is cut into substeps accepted by the
+//    a-posteriori estimate beta h_{m+1,m} |e_m^T exp(ts H_m) e_1|; a rejected
+//    substep only re-evaluates the small exponential;
+//  - shift-and-invert: K_m((I - gamma A)^{-1}, v), gamma = gamma_frac * tau,
+//    with A ~ (I - H_m^{-1}) / gamma on the space; the periodic tridiagonal
+//    solve is parallel cyclic reduction in LDS (n a power of two).  Error
+//    estimate: difference of the dimension m and m-1 approximations.
+//
+// Optional time integral of the piece against sin(a + b s):
+//   int_0^tau sin(a + b s) exp(s A) v ds ~ beta V_m Im(e^{ia} x),
+//   (Hop + i b I) x = e^{i b tau} exp(tau Hop) e_1 - e_1,
+// one real 2m x 2m solve in LDS after the exponential (Hop = H_m or the
+// shift-and-invert image).
+#include "pxp_internal.hpp"
+#include "pxp_device.hpp"
+
+namespace pxp {
+namespace {
+
+constexpr int M_MAX_1D = 48;
+
+__host__ __device__ inline size_t big_doubles(int n, int m) {
+    const size_t vec = 2 * (size_t)n;
+    const size_t sm = 6 * (size_t)m * m + 5 * (size_t)m + 8;
+    return vec > sm ? vec : sm;
+}
+
+struct Smem {
+    double* red;   // num_waves * ldr (ldr = m+1 rounded up to 8)
+    double* hcol;  // ldr + 8
+    double* H;     // (m+1) x m, ld = m
+    double* big;   // vector buffers (2n) or small matrices
+    // small-matrix region (inside big)
+    double* Mt;    // m x m
+    double* E;     // m x m
+    double* W;     // 4 m^2 + 2 m + 8
+    double* vy;    // m
+    double* vy2;   // m
+    double* vc;    // m
+};
+
+struct Tsplit {
+    double cs, cdf, cc;
+};
+
+// Reduce 8 partial sums per thread over the block in one go: recursive
+// halving inside the wave (7 shuffles), three more butterfly steps, then a
+// cross-wave sum in LDS.  red[w * ld + k0 + q] receives the wave sums.
+__device__ __forceinline__ void wave_reduce8(double (&part)[8], double* red,
+                                             int ld, int k0) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool up = (lane & 32) != 0;
+        const double send = up ? part[q] : part[q + 4];
+        const double keep = up ? part[q + 4] : part[q];
+        part[q] = keep + __shfl_xor(send, 32, WAVE);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const bool up = (lane & 16) != 0;
+        const double send = up ? part[q] : part[q + 2];
+        const double keep = up ? part[q + 2] : part[q];
+        part[q] = keep + __shfl_xor(send, 16, WAVE);
+    }
+    {
+        const bool up = (lane & 8) != 0;
+        const double send = up ? part[0] : part[1];
+        const double keep = up ? part[1] : part[0];
+        part[0] = keep + __shfl_xor(send, 8, WAVE);
+    }
+    double v = part[0];
+    v += __shfl_xor(v, 4, WAVE);
+    v += __shfl_xor(v, 2, WAVE);
+    v += __shfl_xor(v, 1, WAVE);
+    // lane bits 5,4,3 select the value: q = 4*b5 + 2*b4 + b3
+    if ((lane & 7) == 0) red[wave_id() * ld + k0 + (lane >> 3)] = v;
+}
+
+template <int PT, bool SI>
+struct Ctx {
+    const KrylovArgs a;
+    Smem S;
+    double* V;
+    int n, m, B, t, ldr;
+    Tsplit op;
+
+    __device__ Ctx(const KrylovArgs& a_, double* lds, double* V_)
+        : a(a_), V(V_), n(a_.n), m(a_.m), B(blockDim.x), t(threadIdx.x) {
+        const int nw = num_waves();
+        ldr = ((m + 1 + 7) / 8) * 8;
+        S.red = lds;
+        S.hcol = S.red + nw * ldr;
+        S.H = S.hcol + ldr + 8;
+        S.big = S.H + (size_t)(m + 1) * m;
+        S.Mt = S.big;
+        S.E = S.Mt + (size_t)m * m;
+        S.W = S.E + (size_t)m * m;
+        S.vy = S.W + 4 * (size_t)m * m + 2 * m + 8;
+        S.vy2 = S.vy + m;
+        S.vc = S.vy2 + m;
+        op.cs = 0.5 * (a.op.lo + a.op.up);
+        op.cdf = 0.5 * (a.op.up - a.op.lo);
+        op.cc = a.op.d + 2.0 * op.cs;
+    }
+
+    __device__ __forceinline__ int idx(int r) const { return t + r * B; }
+    __device__ __forceinline__ bool own(int r) const { return PT * B == n || idx(r) < n; }
+
+    // z <- Op z (polynomial) or (I - gamma Op)^{-1} z (shift-and-invert).
+    __device__ __forceinline__ void apply(double (&z)[PT], double gamma) {
+        double* b0 = S.big;
+#pragma unroll
+        for (int r = 0; r < PT; ++r)
+            if (own(r)) b0[idx(r)] = z[r];
+        __syncthreads();
+        if (!SI) {
+#pragma unroll
+            for (int r = 0; r < PT; ++r) {
+                if (!own(r)) continue;
+                const int i = idx(r);
+                const double xm = b0[i == 0 ? n - 1 : i - 1];
+                const double xp = b0[i == n - 1 ? 0 : i + 1];
+                const double x0 = b0[i];
+                z[r] = op.cs * ((xp + xm) - 2.0 * x0) + op.cdf * (xp - xm) + op.cc * x0;
+            }
+        } else {
+            // Periodic cyclic reduction on a x_{i-1} + b x_i + c x_{i+1} = d_i
+            // with uniform coefficients: level s eliminates x_{i-s}, x_{i+s}
+            // using equations i-s and i+s; after log2(n)-1 levels equation i
+            // couples only x_i and x_{i+n/2}.
+            double* src = b0;
+            double* dst = b0 + n;
+            double ca = -gamma * a.op.lo, cb = 1.0 - gamma * a.op.d, cc = -gamma * a.op.up;
+            const int mask = n - 1;
+            for (int s = 1; 2 * s < n; s <<= 1) {
+                const double k1 = ca / cb, k2 = cc / cb;
+#pragma unroll
+                for (int r = 0; r < PT; ++r) {
+                    const int i = idx(r);
+                    dst[i] = src[i] - k1 * src[(i - s) & mask] - k2 * src[(i + s) & mask];
+                }
+                const double na = -ca * k1, nc = -cc * k2, nb = cb - cc * k1 - ca * k2;
+                ca = na; cb = nb; cc = nc;
+                __syncthreads();
+                double* tmp = src; src = dst; dst = tmp;
+            }
+            const double e = ca + cc;
+            const double det = cb * cb - e * e;
+            const int hn = n >> 1;
+#pragma unroll
+            for (int r = 0; r < PT; ++r) {
+                const int i = idx(r);
+                z[r] = (cb * src[i] - e * src[(i + hn) & mask]) / det;
+            }
+        }
+        // Readers of `big` finish before any later writer: every later write
+        // is preceded by a block reduction, which begins with a barrier.
+    }
+
+    // hcol[k] = <V_k, z> for k <= j (block-wide, deterministic order).
+    __device__ __forceinline__ void dots(const double (&z)[PT], int j) {
+        __syncthreads();
+        for (int k0 = 0; k0 <= j; k0 += 8) {
+            double part[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                double s = 0.0;
+                const int k = k0 + q;
+                if (k <= j) {
+                    const double* Vk = V + (size_t)k * n;
+#pragma unroll
+                    for (int r = 0; r < PT; ++r)
+                        if (own(r)) s += Vk[idx(r)] * z[r];
+                }
+                part[q] = s;
+            }
+            wave_reduce8(part, S.red, ldr, k0);
+        }
+        __syncthreads();
+        const int nw = num_waves();
+        if (t <= j) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += S.red[w * ldr + t];
+            S.hcol[t] = s;
+        }
+        __syncthreads();
+    }
+
+    // Arnoldi from the (unnormalised) vector held in V_0.  Returns the
+    // dimension reached; beta = |v|; bd = happy breakdown.
+    __device__ __forceinline__ int arnoldi(double gamma, double& beta, bool& bd) {
+        double z[PT];
+        double ss = 0.0;
+#pragma unroll
+        for (int r = 0; r < PT; ++r) {
+            z[r] = own(r) ? V[idx(r)] : 0.0;
+            ss += z[r] * z[r];
+        }
+        beta = sqrt(block_sum(ss, S.red));
+        bd = false;
+        for (int o = t; o < (m + 1) * m; o += B) S.H[o] = 0.0;
+        if (!(beta > 0.0)) {
+            __syncthreads();
+            return 0;
+        }
+        const double ib = 1.0 / beta;
+#pragma unroll
+        for (int r = 0; r < PT; ++r) {
+            z[r] *= ib;
+            if (own(r)) V[idx(r)] = z[r];
+        }
+        int me = m;
+        for (int j = 0; j < m; ++j) {
+            apply(z, gamma);
+            // classical Gram-Schmidt, two passes
+            for (int pass = 0; pass < 2; ++pass) {
+                dots(z, j);
+                if (t <= j) S.H[t * m + j] += S.hcol[t];
+                for (int k = 0; k <= j; ++k) {
+                    const double h = S.hcol[k];
+                    const double* Vk = V + (size_t)k * n;
+#pragma unroll
+                    for (int r = 0; r < PT; ++r)
+                        if (own(r)) z[r] -= h * Vk[idx(r)];
+                }
+            }
+            double s2 = 0.0;
+#pragma unroll
+            for (int r = 0; r < PT; ++r) s2 += own(r) ? z[r] * z[r] : 0.0;
+            const double nrm = sqrt(block_sum(s2, S.red));
+            // |Op v_j|^2 = sum_k h_kj^2 + nrm^2 (the Gram-Schmidt column)
+            double col = nrm * nrm;
+            for (int k = 0; k <= j; ++k) col += S.H[k * m + j] * S.H[k * m + j];
+            __syncthreads();
+            if (t == 0) S.H[(j + 1) * m + j] = nrm;
+            if (!(nrm > 1e-12 * sqrt(col))) {
+                // happy breakdown: K_{j+1} is invariant under Op
+                me = j + 1;
+                bd = true;
+                break;
+            }
+            const double inv = 1.0 / nrm;
+            double* Vn = V + (size_t)(j + 1) * n;
+#pragma unroll
+            for (int r = 0; r < PT; ++r) {
+                z[r] *= inv;
+                if (own(r)) Vn[idx(r)] = z[r];
+            }
+        }
+        __syncthreads();
+        return me;
+    }
+
+    // Mt = scale * (I - H_k^{-1}) / gamma for the leading k x k block.
+    __device__ void si_image(int k, double gamma, double scale) {
+        const int ld = 2 * k;
+        for (int o = t; o < k * ld; o += B) {
+            const int r = o / ld, c = o - r * ld;
+            S.W[o] = (c < k) ? S.H[r * m + c] : ((c - k == r) ? 1.0 : 0.0);
+        }
+        __syncthreads();
+        sm_gauss_jordan(S.W, k, ld, ld, S.red, reinterpret_cast<int*>(S.hcol + ldr));
+        for (int o = t; o < k * k; o += B) {
+            const int r = o / k, c = o - r * k;
+            S.Mt[o] = scale * (((r == c) ? 1.0 : 0.0) - S.W[r * ld + k + c]) / gamma;
+        }
+        __syncthreads();
+    }
+
+    // vec = exp(ts Hop) e_1 (leading k x k block); returns |vec[k-1]|.
+    __device__ double small_exp(int k, double ts, double gamma, double* vec) {
+        if (SI) {
+            si_image(k, gamma, ts);
+        } else {
+            for (int o = t; o < k * k; o += B) {
+                const int r = o / k, c = o - r * k;
+                S.Mt[o] = ts * S.H[r * m + c];
+            }
+            __syncthreads();
+        }
+        sm_expm(S.E, S.Mt, k, k, S.W, S.red);
+        for (int r = t; r < k; r += B) vec[r] = S.E[r * k];
+        __syncthreads();
+        return fabs(vec[k - 1]);
+    }
+
+    // vc = coefficients of int_0^ts sin(ia + ib s) exp(s Hop) e_1 ds, given
+    // vy = exp(ts Hop) e_1.
+    __device__ void small_integral(int k, double ts, double ia, double ib,
+                                   double gamma) {
+        if (SI) si_image(k, gamma, 1.0);  // Mt = Hop
+        const int n2 = 2 * k, ld = n2 + 1;
+        const double cb = cos(ib * ts), sb = sin(ib * ts);
+        for (int o = t; o < n2 * ld; o += B) {
+            const int r = o / ld, c = o - r * ld;
+            const int rr = (r < k) ? r : r - k;
+            const int c2 = (c < k) ? c : c - k;
+            double v;
+            if (c == n2) {
+                v = (r < k) ? (cb * S.vy[rr] - (rr == 0 ? 1.0 : 0.0)) : sb * S.vy[rr];
+            } else if ((r < k) == (c < k)) {
+                v = SI ? S.Mt[rr * k + c2] : S.H[rr * m + c2];
+            } else {
+                // upper-right block -b I, lower-left block +b I
+                v = (rr == c2) ? ((r < k) ? -ib : ib) : 0.0;
+            }
+            S.W[o] = v;
+        }
+        __syncthreads();
+        sm_gauss_jordan(S.W, n2, ld, ld, S.red, reinterpret_cast<int*>(S.hcol + ldr));
+        const double sa = sin(ia), ca = cos(ia);
+        for (int r = t; r < k; r += B) S.vc[r] = sa * S.W[r * ld + n2] + ca * S.W[(r + k) * ld + n2];
+        __syncthreads();
+    }
+
+    // V_0 <- beta * V_k vy  and, when iout, iout += beta * V_k vc.
+    __device__ __forceinline__ void combine(int k, double beta, double* iout) {
+        double y[PT], I[PT];
+#pragma unroll
+        for (int r = 0; r < PT; ++r) {
+            y[r] = 0.0;
+            I[r] = 0.0;
+        }
+        for (int q = 0; q < k; ++q) {
+            const double cy = beta * S.vy[q];
+            const double ci = iout ? beta * S.vc[q] : 0.0;
+            const double* Vq = V + (size_t)q * n;
+#pragma unroll
+            for (int r = 0; r < PT; ++r) {
+                if (!own(r)) continue;
+                const double v = Vq[idx(r)];
+                y[r] += cy * v;
+                I[r] += ci * v;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < PT; ++r) {
+            if (!own(r)) continue;
+            V[idx(r)] = y[r];
+            if (iout) iout[idx(r)] += I[r];
+        }
+    }
+
+    __device__ void report(double est_rel, bool noconv, unsigned substeps,
+                           unsigned iters) {
+        if (t == 0 && a.status) {
+            if (noconv) atomicOr(&a.status->flags, ST_NOCONV);
+            if (!(est_rel == est_rel)) atomicOr(&a.status->flags, ST_NONFINITE);
+            const double e = fabs(est_rel);
+            if (e == e)
+                atomicMax(&a.status->max_est, (unsigned long long)__double_as_longlong(e));
+            atomicAdd(&a.status->substeps, (unsigned long long)substeps);
+            atomicAdd(&a.status->krylov_iters, (unsigned long long)iters);
+        }
+    }
+
+    // V_0 <- exp(tau Op) V_0; if iout, iout += int_0^tau sin(ia + ib s)
+    // exp(s Op) V_0 ds.
+    __device__ void expv(double tau, double ia, double ib, double* iout) {
+        if (!(tau > 0.0)) return;
+        const double tol = a.tol;
+        if (SI) {
+            const double gamma = a.gamma_frac * tau;
+            double beta;
+            bool bd;
+            const int me = arnoldi(gamma, beta, bd);
+            if (me == 0) return;
+            small_exp(me, tau, gamma, S.vy);
+            double est = 0.0;
+            if (iout) small_integral(me, tau, ia, ib, gamma);
+            if (!bd && me > 1) {
+                small_exp(me - 1, tau, gamma, S.vy2);
+                double s = 0.0;
+                for (int q = 0; q < me; ++q) {
+                    const double d = S.vy[q] - (q < me - 1 ? S.vy2[q] : 0.0);
+                    s += d * d;
+                }
+                est = sqrt(s);  // relative to beta
+            }
+            combine(me, beta, iout);
+            report(est, est > tol, 1, me);
+            __syncthreads();
+            return;
+        }
+        // polynomial Krylov with substeps
+        double left = tau, sigma0 = 0.0, ts = tau;
+        double worst = 0.0;
+        bool noconv = false;
+        unsigned nsub = 0, iters = 0;
+        while (left > 0.0) {
+            double beta;
+            bool bd;
+            const int me = arnoldi(0.0, beta, bd);
+            iters += me;
+            if (me == 0) break;
+            const double hnext = bd ? 0.0 : S.H[me * m + (me - 1)];
+            int tries = 0;
+            double est = 0.0, tolb = 0.0;
+            for (;;) {
+                if (ts > left) ts = left;
+                const double e1 = small_exp(me, ts, 0.0, S.vy);
+                est = bd ? 0.0 : beta * hnext * e1;
+                tolb = tol * beta * (ts / tau);
+                if (est <= tolb) break;
+                if (tries >= 40 || ts <= 1e-10 * tau || !(est == est)) {
+                    noconv = true;
+                    break;
+                }
+                double f = 0.9 * pow(tolb / est, 1.0 / (double)me);
+                f = fmin(0.9, fmax(0.1, f));
+                ts *= f;
+                ++tries;
+            }
+            if (beta > 0.0) worst = fmax(worst, est / beta / (ts / tau));
+            if (iout) small_integral(me, ts, ia + ib * sigma0, ib, 0.0);
+            combine(me, beta, iout);
+            ++nsub;
+            sigma0 += ts;
+            left = tau - sigma0;
+            if (left <= 1e-13 * tau) left = 0.0;
+            if (nsub >= 20000 && left > 0.0) {  // give up: flagged, not hidden
+                noconv = true;
+                break;
+            }
+            // grow the next substep when the estimate allows it
+            double g = (est > 0.0) ? 0.9 * pow(tolb / est, 1.0 / (double)me) : 2.0;
+            g = fmin(2.0, fmax(1.0, g));
+            ts *= g;
+            __syncthreads();
+        }
+        report(worst, noconv, nsub, iters);
+    }
+};
+
+template <int PT, bool SI>
+__global__ void __launch_bounds__(256) k_krylov1d(KrylovArgs a) {
+    extern __shared__ double lds[];
+    const int n = a.n, B = blockDim.x, t = threadIdx.x;
+    const int piece = blockIdx.x;
+    double* V = a.basis + (size_t)piece * (a.m + 1) * n;
+    Ctx<PT, SI> c(a, lds, V);
+    // The current vector of the piece lives in V_0 (global memory); every
+    // thread only reads and writes its own points of it.
+    if (a.mode == KM_CLASSIC) {
+        const double* vin = a.vin + (size_t)piece * n;
+        for (int r = 0; r < PT; ++r)
+            if (c.own(r)) V[t + r * B] = vin[t + r * B];
+        const double tau = (double)(a.npieces - piece) * a.tau;
+        c.expv(tau, 0.0, 0.0, nullptr);
+        double* y = a.yout + (size_t)piece * n;
+        for (int r = 0; r < PT; ++r)
+            if (c.own(r)) y[t + r * B] = V[t + r * B];
+    } else if (a.mode == KM_CHAIN) {
+        for (int r = 0; r < PT; ++r)
+            if (c.own(r)) V[t + r * B] = a.vin[t + r * B];
+        for (int q = 1; q < a.npieces; ++q) {
+            c.expv(a.tau, 0.0, 0.0, nullptr);
+            const double* vq = a.vin + (size_t)q * n;
+            for (int r = 0; r < PT; ++r)
+                if (c.own(r)) V[t + r * B] += vq[t + r * B];
+        }
+        for (int r = 0; r < PT; ++r)
+            if (c.own(r)) a.yout[t + r * B] = V[t + r * B];
+    } else {
+        for (int r = 0; r < PT; ++r) {
+            if (!c.own(r)) continue;
+            V[t + r * B] = a.vin[t + r * B];
+            if (a.iout) a.iout[t + r * B] = 0.0;
+        }
+        c.expv(a.tau, a.ia, a.ib, a.iout);
+        if (a.yout) {
+            for (int r = 0; r < PT; ++r)
+                if (c.own(r)) a.yout[t + r * B] = V[t + r * B];
+        }
+    }
+}
+
+template <bool SI>
+hipError_t launch_pt(const KrylovArgs& a, int B, int pt, int grid, size_t lds,
+                     hipStream_t s) {
+    switch (pt) {
+#define PXP_K(PTV)                                                               \
+    case PTV: {                                                                \
+        auto kern = k_krylov1d<PTV, SI>;                                 \
+        hipFuncSetAttribute((const void*)kern,                                 \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        kern<<<grid, B, lds, s>>>(a);                                          \
+        break;                                                                 \
+    }
+        PXP_K(1)
+        PXP_K(2)
+        PXP_K(4)
+        PXP_K(8)
+        PXP_K(16)
+        PXP_K(32)
+#undef PXP_K
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+bool krylov_shape(int n, int block_hint, int* B, int* pt) {
+    int b = block_hint;
+    if (b <= 0) b = 256;
+    if (b > n) b = ((n + 63) / 64) * 64;
+    if (b % 64 || b > 256) return false;
+    const int p = (n + b - 1) / b;
+    if (!(p == 1 || p == 2 || p == 4 || p == 8 || p == 16 || p == 32)) return false;
+    *B = b;
+    *pt = p;
+    return true;
+}
+
+}  // namespace
+
+size_t krylov1d_lds_bytes(int n, int m, int block, int si) {
+    (void)si;
+    const int nw = block / 64;
+    const int ldr = ((m + 1 + 7) / 8) * 8;
+    const size_t d = (size_t)nw * ldr + ldr + 8 + (size_t)(m + 1) * m + big_doubles(n, m);
+    return d * sizeof(double);
+}
+
+hipError_t launch_krylov1d(const KrylovArgs& a, int block_hint, hipStream_t s) {
+    if (a.m < 1 || a.m > M_MAX_1D || a.n < 2) return hipErrorInvalidValue;
+    if (a.si && (a.n & (a.n - 1))) return hipErrorInvalidValue;
+    int B, pt;
+    if (!krylov_shape(a.n, block_hint, &B, &pt)) return hipErrorInvalidValue;
+    if (a.si && pt * B != a.n) return hipErrorInvalidValue;
+    const size_t lds = krylov1d_lds_bytes(a.n, a.m, B, a.si);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const int grid = (a.mode == KM_CLASSIC) ? a.npieces : 1;
+    if (grid <= 0) return hipSuccess;
+    return a.si ? launch_pt<true>(a, B, pt, grid, lds, s)
+                : launch_pt<false>(a, B, pt, grid, lds, s);
+}
+
+}  // namespace pxp

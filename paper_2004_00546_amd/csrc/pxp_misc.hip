@@ -1,0 +1,143 @@
+// Small kernels of the direct-adjoint loop: control -> forcing/initial state,
+// cost and adjoint final condition (eq. adjFinalTime), gradient reductions
+// (eqs. paramupdate, initupdate) and the superposition of the Paraexp pieces
+// (eq. fullsol0).  All reductions are deterministic (fixed order).
+#include "pxp_internal.hpp"
+#include "pxp_device.hpp"
+
+namespace pxp {
+namespace {
+
+__global__ void k_combine_basis(const double* __restrict__ a,
+                                const double* __restrict__ basis,
+                                const double* __restrict__ base,
+                                double* __restrict__ out, int K, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = base ? base[i] : 0.0;
+    for (int k = 0; k < K; ++k) s += a[k] * basis[(size_t)k * n + i];
+    out[i] = s;
+}
+
+__global__ void k_apply_tri(const double* __restrict__ x, double* __restrict__ out,
+                            int n, Tri op) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double xm = x[i == 0 ? n - 1 : i - 1];
+    const double xp = x[i == n - 1 ? 0 : i + 1];
+    out[i] = op.lo * xm + op.d * x[i] + op.up * xp;
+}
+
+// One workgroup: lamT = qT - tgt, J = 1/2 |lamT|^2 + beta |a|^2.
+__global__ void __launch_bounds__(256)
+k_cost(const double* __restrict__ qT, const double* __restrict__ tgt,
+       const double* __restrict__ a, int n, int K, double beta,
+       double* __restrict__ lamT, double* __restrict__ J) {
+    __shared__ double red[8];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double d = qT[i] - tgt[i];
+        if (lamT) lamT[i] = d;
+        s += d * d;
+    }
+    double r = 0.0;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) r += a[k] * a[k];
+    s = block_sum(s, red);
+    r = block_sum(r, red);
+    if (threadIdx.x == 0) *J = 0.5 * s + beta * r;
+}
+
+// One workgroup per control k: grad[k] = <basis_k, v> + 2 beta a[k].
+__global__ void __launch_bounds__(256)
+k_grad(const double* __restrict__ basis, const double* __restrict__ v,
+       const double* __restrict__ a, int n, double beta,
+       double* __restrict__ grad) {
+    __shared__ double red[8];
+    const int k = blockIdx.x;
+    const double* b = basis + (size_t)k * n;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += b[i] * v[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) grad[k] = s + 2.0 * beta * a[k];
+}
+
+__global__ void k_recombine(const double* __restrict__ q0,
+                            const double* __restrict__ vlast,
+                            const double* __restrict__ Y, int np, int n,
+                            double* __restrict__ out, DevStatus* st) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = q0 ? q0[i] : 0.0;
+    if (vlast) s += vlast[i];
+    for (int p = 0; p < np; ++p) s += Y[(size_t)p * n + i];
+    out[i] = s;
+    if (st && !isfinite(s)) atomicOr(&st->flags, ST_NONFINITE);
+}
+
+__global__ void k_add(const double* __restrict__ a, const double* __restrict__ b,
+                      double* __restrict__ out, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = (a ? a[i] : 0.0) + b[i];
+}
+
+inline int blocks(int n, int b) { return (n + b - 1) / b; }
+
+}  // namespace
+
+hipError_t launch_combine_basis(const double* a, const double* basis,
+                                const double* base, double* out, int K, int n,
+                                hipStream_t s) {
+    k_combine_basis<<<blocks(n, 256), 256, 0, s>>>(a, basis, base, out, K, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_tri(const double* x, double* out, int n, Tri op,
+                            hipStream_t s) {
+    k_apply_tri<<<blocks(n, 256), 256, 0, s>>>(x, out, n, op);
+    return hipGetLastError();
+}
+
+hipError_t launch_cost(const double* qT, const double* tgt, const double* a,
+                       int n, int K, double beta, double* lamT, double* J,
+                       hipStream_t s) {
+    k_cost<<<1, 256, 0, s>>>(qT, tgt, a, n, K, beta, lamT, J);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(const double* basis, const double* v, const double* a,
+                       int K, int n, double beta, double* grad, hipStream_t s) {
+    if (K <= 0) return hipSuccess;
+    k_grad<<<K, 256, 0, s>>>(basis, v, a, n, beta, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_recombine(const double* q0, const double* vlast,
+                            const double* Y, int np, int n, double* out,
+                            DevStatus* st, hipStream_t s) {
+    k_recombine<<<blocks(n, 256), 256, 0, s>>>(q0, vlast, Y, np, n, out, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_add(const double* a, const double* b, double* out, int n,
+                      hipStream_t s) {
+    k_add<<<blocks(n, 256), 256, 0, s>>>(a, b, out, n);
+    return hipGetLastError();
+}
+
+}  // namespace pxp
+
+namespace pxp {
+namespace {
+__global__ void k_zero(double* __restrict__ p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+}  // namespace
+
+hipError_t launch_zero(double* p, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_zero<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+}  // namespace pxp

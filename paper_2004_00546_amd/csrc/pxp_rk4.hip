@@ -1,0 +1,540 @@
+// Classical RK4 marches for the 1D operators (paper section 4.2/4.3).
+//
+// Layout: one workgroup marches one state vector of n points; thread t owns
+// the contiguous chunk [t*PT, (t+1)*PT) in registers for the whole march, so
+// a step touches HBM only for checkpoints.  A stencil needs one neighbour on
+// each side of a chunk: the chunk edges are exchanged through LDS with one
+// barrier per stage (double-buffered, so no second barrier is needed).
+//
+// Used for
+//  - the P inhomogeneous sub-problems of the Paraexp direct solve, one
+//    workgroup per slice, each from zero data (section 3.1, eq.
+//    linInhomEqus);
+//  - the serial march (P = 1) that Paraexp is compared with;
+//  - the reverse sweep of the exact discrete adjoint of that march;
+//  - the serial Burgers direct march with checkpoints (section 3.3, 3.5).
+#include "pxp_internal.hpp"
+#include "pxp_device.hpp"
+
+namespace pxp {
+namespace {
+
+// Exchange the chunk edges of NA arrays with one barrier.  edge is LDS of
+// 2 buffers of NB x 2 x B doubles (NB >= NA: the same buffer stride must be
+// used by every exchange of a kernel so the two buffers never overlap).
+template <int PT, int NA, int NB = NA>
+__device__ __forceinline__ void exch(const double* const (&arrs)[NA], double* edge,
+                                     int& buf, double (&left)[NA],
+                                     double (&right)[NA]) {
+    static_assert(NB >= NA, "buffer stride");
+    const int t = threadIdx.x, B = blockDim.x;
+    double* e = edge + buf * 2 * NB * B;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        e[(2 * a) * B + t] = arrs[a][0];
+        e[(2 * a + 1) * B + t] = arrs[a][PT - 1];
+    }
+    __syncthreads();
+    const int tl = (t == 0) ? B - 1 : t - 1;
+    const int tr = (t == B - 1) ? 0 : t + 1;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        left[a] = e[(2 * a + 1) * B + tl];
+        right[a] = e[(2 * a) * B + tr];
+    }
+    buf ^= 1;
+}
+
+// Coefficients of a tridiagonal operator split for accuracy:
+// lo x_{i-1} + d x_i + up x_{i+1} = cs ((x_{i+1} + x_{i-1}) - 2 x_i)
+//                                  + cdf (x_{i+1} - x_{i-1}) + cc x_i
+struct TriSplit {
+    double cs, cdf, cc;
+};
+__host__ __device__ inline TriSplit split(Tri a) {
+    TriSplit s;
+    s.cs = 0.5 * (a.lo + a.up);
+    s.cdf = 0.5 * (a.up - a.lo);
+    s.cc = a.d + 2.0 * s.cs;
+    return s;
+}
+
+template <int PT>
+__device__ __forceinline__ void tri_rhs(const double (&Y)[PT], double l, double r,
+                                        const TriSplit& A, double (&k)[PT]) {
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+        const double ym = (q == 0) ? l : Y[q - 1];
+        const double yp = (q == PT - 1) ? r : Y[q + 1];
+        k[q] = A.cs * ((yp + ym) - 2.0 * Y[q]) + A.cdf * (yp - ym) + A.cc * Y[q];
+    }
+}
+
+template <int PT>
+__global__ void __launch_bounds__(1024)
+k_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
+            const double* __restrict__ y0, double* __restrict__ out, int n,
+            int64_t n_s, double dt, double omega, TriSplit A) {
+    extern __shared__ double lds[];
+    const int t = threadIdx.x;
+    const int p = blockIdx.x;
+    const int base = t * PT;
+    double f[PT], g[PT], y[PT], acc[PT], Y[PT], k[PT];
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+        f[q] = F ? F[base + q] : 0.0;
+        g[q] = g0 ? g0[base + q] : 0.0;
+        y[q] = y0 ? y0[base + q] : 0.0;
+    }
+    int buf = 0;
+    const int64_t step0 = (int64_t)p * n_s;
+    const double h2 = 0.5 * dt, h6 = dt / 6.0;
+    for (int64_t s = 0; s < n_s; ++s) {
+        const double tn = (double)(step0 + s) * dt;
+        const double s1 = sin(omega * tn);
+        const double s2 = sin(omega * (tn + 0.5 * dt));
+        const double s4 = sin(omega * (tn + dt));
+        double l[1], r[1];
+        {
+            const double* arr[1] = {y};
+            exch<PT, 1>(arr, lds, buf, l, r);
+        }
+        tri_rhs<PT>(y, l[0], r[0], A, k);
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            k[q] += s1 * f[q] + g[q];
+            acc[q] = k[q];
+            Y[q] = y[q] + h2 * k[q];
+        }
+        {
+            const double* arr[1] = {Y};
+            exch<PT, 1>(arr, lds, buf, l, r);
+        }
+        tri_rhs<PT>(Y, l[0], r[0], A, k);
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            k[q] += s2 * f[q] + g[q];
+            acc[q] += 2.0 * k[q];
+            Y[q] = y[q] + h2 * k[q];
+        }
+        {
+            const double* arr[1] = {Y};
+            exch<PT, 1>(arr, lds, buf, l, r);
+        }
+        tri_rhs<PT>(Y, l[0], r[0], A, k);
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            k[q] += s2 * f[q] + g[q];
+            acc[q] += 2.0 * k[q];
+            Y[q] = y[q] + dt * k[q];
+        }
+        {
+            const double* arr[1] = {Y};
+            exch<PT, 1>(arr, lds, buf, l, r);
+        }
+        tri_rhs<PT>(Y, l[0], r[0], A, k);
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            k[q] += s4 * f[q] + g[q];
+            y[q] = y[q] + h6 * (acc[q] + k[q]);
+        }
+    }
+    double* o = out + (size_t)p * n;
+#pragma unroll
+    for (int q = 0; q < PT; ++q) o[base + q] = y[q];
+}
+
+// Reverse sweep: y_{s+1} = y_s + dt sum_i b_i k_i with k_i = A Y_i + ...
+// gives kbar_i = dt b_i lam (+ the chain through later stages), Ybar_i =
+// A^T kbar_i, lam_s = lam_{s+1} + sum_i Ybar_i.
+template <int PT>
+__global__ void __launch_bounds__(1024)
+k_rk4_rev_lin1d(const double* __restrict__ lamT, double* __restrict__ lam0,
+                double* __restrict__ Lambda, int n, int64_t n_t, double dt,
+                double omega, TriSplit AT) {
+    extern __shared__ double lds[];
+    const int t = threadIdx.x;
+    const int base = t * PT;
+    double lam[PT], Lam[PT], kb[PT], Yb[PT], nl[PT];
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+        lam[q] = lamT[base + q];
+        Lam[q] = 0.0;
+    }
+    int buf = 0;
+    const double d6 = dt / 6.0, d3 = dt / 3.0, d2 = 0.5 * dt;
+    for (int64_t s = n_t - 1; s >= 0; --s) {
+        const double tn = (double)s * dt;
+        const double s1 = sin(omega * tn);
+        const double s2 = sin(omega * (tn + 0.5 * dt));
+        const double s4 = sin(omega * (tn + dt));
+        double l[1], r[1];
+        // stage 4
+#pragma unroll
+        for (int q = 0; q < PT; ++q) kb[q] = d6 * lam[q];
+        {
+            const double* arr[1] = {kb};
+            exch<PT, 1>(arr, lds, buf, l, r);
+        }
+        tri_rhs<PT>(kb, l[0], r[0], AT, Yb);
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            nl[q] = lam[q] + Yb[q];
+            Lam[q] += s4 * kb[q];
+            kb[q] = d3 * lam[q] + dt * Yb[q];
+        }
+        // stage 3
+        {
+            const double* arr[1] = {kb};
+            exch<PT, 1>(arr, lds, buf, l, r);
+        }
+        tri_rhs<PT>(kb, l[0], r[0], AT, Yb);
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            nl[q] += Yb[q];
+            Lam[q] += s2 * kb[q];
+            kb[q] = d3 * lam[q] + d2 * Yb[q];
+        }
+        // stage 2
+        {
+            const double* arr[1] = {kb};
+            exch<PT, 1>(arr, lds, buf, l, r);
+        }
+        tri_rhs<PT>(kb, l[0], r[0], AT, Yb);
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            nl[q] += Yb[q];
+            Lam[q] += s2 * kb[q];
+            kb[q] = d6 * lam[q] + d2 * Yb[q];
+        }
+        // stage 1
+        {
+            const double* arr[1] = {kb};
+            exch<PT, 1>(arr, lds, buf, l, r);
+        }
+        tri_rhs<PT>(kb, l[0], r[0], AT, Yb);
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            Lam[q] += s1 * kb[q];
+            lam[q] = nl[q] + Yb[q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+        if (lam0) lam0[base + q] = lam[q];
+        if (Lambda) Lambda[base + q] = Lam[q];
+    }
+}
+
+// ---- Burgers: N(u)_i = -u_i (u_{i+1} - u_{i-1})/(2h) + nu lap(u)_i -------
+
+struct BurgersC {
+    double inv2h, nuh2;
+};
+
+template <int PT>
+__device__ __forceinline__ void burgers_rhs(const double (&Y)[PT], double l,
+                                            double r, const BurgersC& c,
+                                            double (&k)[PT]) {
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+        const double ym = (q == 0) ? l : Y[q - 1];
+        const double yp = (q == PT - 1) ? r : Y[q + 1];
+        k[q] = -Y[q] * ((yp - ym) * c.inv2h) + c.nuh2 * ((yp + ym) - 2.0 * Y[q]);
+    }
+}
+
+// One Burgers RK4 step in registers (stages exchanged through LDS).
+template <int PT, int NB>
+__device__ __forceinline__ void burgers_step(double (&y)[PT], double dt,
+                                             const BurgersC& c, double* lds,
+                                             int& buf) {
+    double acc[PT], Y[PT], k[PT], l[1], r[1];
+    {
+        const double* arr[1] = {y};
+        exch<PT, 1, NB>(arr, lds, buf, l, r);
+    }
+    burgers_rhs<PT>(y, l[0], r[0], c, k);
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+        acc[q] = k[q];
+        Y[q] = y[q] + 0.5 * dt * k[q];
+    }
+    {
+        const double* arr[1] = {Y};
+        exch<PT, 1, NB>(arr, lds, buf, l, r);
+    }
+    burgers_rhs<PT>(Y, l[0], r[0], c, k);
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+        acc[q] += 2.0 * k[q];
+        Y[q] = y[q] + 0.5 * dt * k[q];
+    }
+    {
+        const double* arr[1] = {Y};
+        exch<PT, 1, NB>(arr, lds, buf, l, r);
+    }
+    burgers_rhs<PT>(Y, l[0], r[0], c, k);
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+        acc[q] += 2.0 * k[q];
+        Y[q] = y[q] + dt * k[q];
+    }
+    {
+        const double* arr[1] = {Y};
+        exch<PT, 1, NB>(arr, lds, buf, l, r);
+    }
+    burgers_rhs<PT>(Y, l[0], r[0], c, k);
+#pragma unroll
+    for (int q = 0; q < PT; ++q) y[q] = y[q] + (dt / 6.0) * (acc[q] + k[q]);
+}
+
+template <int PT>
+__global__ void __launch_bounds__(1024)
+k_rk4_burgers_direct(const double* __restrict__ y0, double* __restrict__ yT,
+                     double* __restrict__ ckpt, int n, int64_t n_t, int64_t c,
+                     double dt, BurgersC bc) {
+    extern __shared__ double lds[];
+    const int base = threadIdx.x * PT;
+    double y[PT];
+#pragma unroll
+    for (int q = 0; q < PT; ++q) y[q] = y0[base + q];
+    if (ckpt) {
+#pragma unroll
+        for (int q = 0; q < PT; ++q) ckpt[base + q] = y[q];
+    }
+    int buf = 0;
+    for (int64_t s = 0; s < n_t; ++s) {
+        burgers_step<PT, 1>(y, dt, bc, lds, buf);
+        if (ckpt && ((s + 1) % c) == 0) {
+            double* o = ckpt + (size_t)((s + 1) / c) * n;
+#pragma unroll
+            for (int q = 0; q < PT; ++q) o[base + q] = y[q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < PT; ++q) yT[base + q] = y[q];
+}
+
+// (J(U)^T v)_i = ((U v)_{i+1} - (U v)_{i-1})/(2h) - (U_{i+1} - U_{i-1}) v_i/(2h)
+//               + nu lap(v)_i
+template <int PT>
+__device__ __forceinline__ void burgers_jt(const double (&U)[PT], double Ul,
+                                           double Ur, const double (&v)[PT],
+                                           const BurgersC& c, double* lds,
+                                           int& buf, double (&out)[PT]) {
+    double uv[PT];
+#pragma unroll
+    for (int q = 0; q < PT; ++q) uv[q] = U[q] * v[q];
+    double l[2], r[2];
+    {
+        const double* arr[2] = {v, uv};
+        exch<PT, 2>(arr, lds, buf, l, r);
+    }
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+        const double vm = (q == 0) ? l[0] : v[q - 1];
+        const double vp = (q == PT - 1) ? r[0] : v[q + 1];
+        const double wm = (q == 0) ? l[1] : uv[q - 1];
+        const double wp = (q == PT - 1) ? r[1] : uv[q + 1];
+        const double Um = (q == 0) ? Ul : U[q - 1];
+        const double Up = (q == PT - 1) ? Ur : U[q + 1];
+        out[q] = (wp - wm) * c.inv2h - (Up - Um) * c.inv2h * v[q]
+                 + c.nuh2 * ((vp + vm) - 2.0 * v[q]);
+    }
+}
+
+template <int PT>
+__global__ void __launch_bounds__(1024)
+k_rk4_burgers_reverse(const double* __restrict__ ckpt,
+                      const double* __restrict__ lamT, double* __restrict__ lam0,
+                      double* __restrict__ seg, int n, int64_t n_t, int64_t c,
+                      double dt, BurgersC bc) {
+    extern __shared__ double lds[];
+    const int base = threadIdx.x * PT;
+    double lam[PT];
+#pragma unroll
+    for (int q = 0; q < PT; ++q) lam[q] = lamT[base + q];
+    int buf = 0;
+    const int64_t nseg = n_t / c;
+    for (int64_t g = nseg - 1; g >= 0; --g) {
+        // recompute the segment's step states from its checkpoint
+        double y[PT];
+        const double* ck = ckpt + (size_t)g * n;
+#pragma unroll
+        for (int q = 0; q < PT; ++q) y[q] = ck[base + q];
+        for (int64_t q2 = 0; q2 < c; ++q2) {
+            double* o = seg + (size_t)q2 * n;
+#pragma unroll
+            for (int q = 0; q < PT; ++q) o[base + q] = y[q];
+            if (q2 + 1 < c) burgers_step<PT, 2>(y, dt, bc, lds, buf);
+        }
+        // reverse over the segment
+        for (int64_t q2 = c - 1; q2 >= 0; --q2) {
+            const double* ys = seg + (size_t)q2 * n;
+            double Y1[PT], Y2[PT], Y3[PT], Y4[PT], k[PT];
+            double Ul[4], Ur[4], l[1], r[1];
+#pragma unroll
+            for (int q = 0; q < PT; ++q) Y1[q] = ys[base + q];
+            {
+                const double* arr[1] = {Y1};
+                exch<PT, 1, 2>(arr, lds, buf, l, r);
+            }
+            Ul[0] = l[0]; Ur[0] = r[0];
+            burgers_rhs<PT>(Y1, l[0], r[0], bc, k);
+#pragma unroll
+            for (int q = 0; q < PT; ++q) Y2[q] = Y1[q] + 0.5 * dt * k[q];
+            {
+                const double* arr[1] = {Y2};
+                exch<PT, 1, 2>(arr, lds, buf, l, r);
+            }
+            Ul[1] = l[0]; Ur[1] = r[0];
+            burgers_rhs<PT>(Y2, l[0], r[0], bc, k);
+#pragma unroll
+            for (int q = 0; q < PT; ++q) Y3[q] = Y1[q] + 0.5 * dt * k[q];
+            {
+                const double* arr[1] = {Y3};
+                exch<PT, 1, 2>(arr, lds, buf, l, r);
+            }
+            Ul[2] = l[0]; Ur[2] = r[0];
+            burgers_rhs<PT>(Y3, l[0], r[0], bc, k);
+#pragma unroll
+            for (int q = 0; q < PT; ++q) Y4[q] = Y1[q] + dt * k[q];
+            {
+                const double* arr[1] = {Y4};
+                exch<PT, 1, 2>(arr, lds, buf, l, r);
+            }
+            Ul[3] = l[0]; Ur[3] = r[0];
+            // adjoint stages
+            double kb[PT], Yb[PT], nl[PT];
+#pragma unroll
+            for (int q = 0; q < PT; ++q) kb[q] = (dt / 6.0) * lam[q];
+            burgers_jt<PT>(Y4, Ul[3], Ur[3], kb, bc, lds, buf, Yb);
+#pragma unroll
+            for (int q = 0; q < PT; ++q) {
+                nl[q] = lam[q] + Yb[q];
+                kb[q] = (dt / 3.0) * lam[q] + dt * Yb[q];
+            }
+            burgers_jt<PT>(Y3, Ul[2], Ur[2], kb, bc, lds, buf, Yb);
+#pragma unroll
+            for (int q = 0; q < PT; ++q) {
+                nl[q] += Yb[q];
+                kb[q] = (dt / 3.0) * lam[q] + 0.5 * dt * Yb[q];
+            }
+            burgers_jt<PT>(Y2, Ul[1], Ur[1], kb, bc, lds, buf, Yb);
+#pragma unroll
+            for (int q = 0; q < PT; ++q) {
+                nl[q] += Yb[q];
+                kb[q] = (dt / 6.0) * lam[q] + 0.5 * dt * Yb[q];
+            }
+            burgers_jt<PT>(Y1, Ul[0], Ur[0], kb, bc, lds, buf, Yb);
+#pragma unroll
+            for (int q = 0; q < PT; ++q) lam[q] = nl[q] + Yb[q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < PT; ++q) lam0[base + q] = lam[q];
+}
+
+// Threads per workgroup and points per thread for an n-point march.
+bool pick_shape(int n, int block_hint, int* block, int* pt) {
+    if (block_hint > 0) {
+        if (n % block_hint) return false;
+        const int p = n / block_hint;
+        if (p == 1 || p == 2 || p == 4 || p == 8 || p == 16) {
+            *block = block_hint;
+            *pt = p;
+            return block_hint <= 1024;
+        }
+        return false;
+    }
+    static const int cands[] = {64, 128, 256, 512, 1024};
+    for (int b : cands) {
+        if (n % b == 0 && n / b <= 16) {
+            const int p = n / b;
+            if (p == 1 || p == 2 || p == 4 || p == 8 || p == 16) {
+                *block = b;
+                *pt = p;
+                return true;
+            }
+        }
+    }
+    if (n <= 1024) {
+        *block = n;
+        *pt = 1;
+        return true;
+    }
+    return false;
+}
+
+}  // namespace
+
+#define PXP_DISPATCH_PT(pt, KERNEL, ...)                                       \
+    switch (pt) {                                                              \
+        case 1: KERNEL<1> __VA_ARGS__; break;                                  \
+        case 2: KERNEL<2> __VA_ARGS__; break;                                  \
+        case 4: KERNEL<4> __VA_ARGS__; break;                                  \
+        case 8: KERNEL<8> __VA_ARGS__; break;                                  \
+        case 16: KERNEL<16> __VA_ARGS__; break;                                \
+        default: return hipErrorInvalidValue;                                  \
+    }
+
+bool march_shape(int n, int block_hint, int* block, int* pt) {
+    return pick_shape(n, block_hint, block, pt);
+}
+
+hipError_t launch_rk4_lin1d(const double* F, const double* g0, const double* y0,
+                            double* out, int n, int P, int64_t n_s, double dt,
+                            double omega, Tri A, int block_hint, hipStream_t s) {
+    int block, pt;
+    if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
+    const size_t lds = sizeof(double) * 4 * block;
+    const TriSplit sp = split(A);
+    PXP_DISPATCH_PT(pt, k_rk4_lin1d,
+                    <<<P, block, lds, s>>>(F, g0, y0, out, n, n_s, dt, omega, sp))
+    return hipGetLastError();
+}
+
+hipError_t launch_rk4_rev_lin1d(const double* lamT, double* lam0,
+                                double* Lambda, int n, int64_t n_t, double dt,
+                                double omega, Tri AT, int block_hint,
+                                hipStream_t s) {
+    int block, pt;
+    if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
+    const size_t lds = sizeof(double) * 4 * block;
+    const TriSplit sp = split(AT);
+    PXP_DISPATCH_PT(pt, k_rk4_rev_lin1d,
+                    <<<1, block, lds, s>>>(lamT, lam0, Lambda, n, n_t, dt, omega, sp))
+    return hipGetLastError();
+}
+
+hipError_t launch_rk4_burgers_direct(const double* y0, double* yT, double* ckpt,
+                                     int n, int64_t n_t, int64_t c, double dt,
+                                     double nu, double L, int block_hint,
+                                     hipStream_t s) {
+    int block, pt;
+    if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
+    const double h = L / n;
+    BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
+    const size_t lds = sizeof(double) * 4 * block;
+    PXP_DISPATCH_PT(pt, k_rk4_burgers_direct,
+                    <<<1, block, lds, s>>>(y0, yT, ckpt, n, n_t, c, dt, bc))
+    return hipGetLastError();
+}
+
+hipError_t launch_rk4_burgers_reverse(const double* ckpt, const double* lamT,
+                                      double* lam0, double* seg, int n,
+                                      int64_t n_t, int64_t c, double dt,
+                                      double nu, double L, int block_hint,
+                                      hipStream_t s) {
+    int block, pt;
+    if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
+    const double h = L / n;
+    BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
+    const size_t lds = sizeof(double) * 8 * block;
+    PXP_DISPATCH_PT(pt, k_rk4_burgers_reverse,
+                    <<<1, block, lds, s>>>(ckpt, lamT, lam0, seg, n, n_t, c, dt, bc))
+    return hipGetLastError();
+}
+
+}  // namespace pxp
