@@ -121,7 +121,9 @@ pxp_status paraexp_direct(const pxp_problem* pb, int32_t batch,
                           void* ws, size_t ws_bytes, void* stream);
 
 /* Adjoint solve (eqs. adjEquation, adjFinalTime, adjHomNormal,
- * adjhomfinal) from the final condition lamT (= dJ/dq(T)):
+ * adjhomfinal) from the final condition lamT (= dJ/dq(T)).  lamT, lam0
+ * and Lambda must be 16-byte aligned at every instance offset (PXP_EINVAL
+ * otherwise):
  *   lam0    [sum n]  output q^dagger(0) (nullable)
  *   Lambda  [sum n]  output int_0^T sin(omega t) q^dagger(t) dt (nullable)
  * Burgers instances need the checkpoints of the preceding paraexp_direct

@@ -9,7 +9,7 @@ from . import _lib
 
 
 def make_problem(inst: dict, krylov: str = "shift_invert", sched: str = "classic",
-                 tol: float = 1e-11, block: int = 0, si_gamma: float = 0.2,
+                 tol: float = 1e-10, block: int = 0, si_gamma: float = 0.2,
                  P: int | None = None, m: int | None = None,
                  prec: str = "fp64") -> _lib.pxp_problem:
     p = _lib.pxp_problem()

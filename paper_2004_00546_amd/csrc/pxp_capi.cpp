@@ -89,6 +89,8 @@ pxp_status validate(const pxp_problem& p) {
         if (p.krylov == PXP_KRYLOV_SHIFT_INVERT && (!is_pow2(p.nx) || p.nx < 64))
             return PXP_EUNSUPPORTED;
         if (!(p.krylov_tol > 0.0)) return PXP_EINVAL;
+        // the Krylov kernels read two consecutive points per 16-byte load
+        if (p.nx > 256 && (p.nx & 1)) return PXP_EUNSUPPORTED;
         if (!rk4_stable_advdiff1d(p)) return PXP_EUNSTABLE_DT;
         return PXP_OK;
     }
@@ -340,6 +342,12 @@ pxp_status adjoint_burgers(const Ctx& c, const double* lamT, double* lam0) {
     return PXP_OK;
 }
 
+// Device arrays handed to the kernels that use 16-byte loads must be
+// 16-byte aligned at every instance offset.
+bool aligned16(const double* base, size_t off) {
+    return !base || (reinterpret_cast<uintptr_t>(base + off) % 16) == 0;
+}
+
 pxp_status ws_check(const pxp_problem* pb, int batch, void* ws, size_t ws_bytes,
                     Layout* Ly) {
     *Ly = layout(pb, batch);
@@ -445,6 +453,12 @@ static pxp_status adjoint_impl(const pxp_problem* pb, int32_t batch,
     if (st != PXP_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     size_t off = 0;
+    for (int i = 0; i < batch; ++i) {
+        if (!aligned16(lamT, off) || !aligned16(lam0, off) || !aligned16(Lambda, off))
+            return PXP_EINVAL;
+        off += (size_t)grid_n(pb[i]);
+    }
+    off = 0;
     for (int i = 0; i < batch; ++i) {
         const pxp_problem& p = pb[i];
         Ctx c = make_ctx(p, ws, Ly, i, s);

@@ -30,10 +30,12 @@ namespace {
 
 constexpr int M_MAX_1D = 48;
 
-__host__ __device__ inline size_t big_doubles(int n, int m) {
+__host__ __device__ inline size_t big_doubles(int n, int m, int block) {
     const size_t vec = 2 * (size_t)n;
+    const size_t part = (size_t)(m + 1) * block;
     const size_t sm = 6 * (size_t)m * m + 5 * (size_t)m + 8;
-    return vec > sm ? vec : sm;
+    size_t b = vec > sm ? vec : sm;
+    return b > part ? b : part;
 }
 
 struct Smem {
@@ -54,42 +56,12 @@ struct Tsplit {
     double cs, cdf, cc;
 };
 
-// Reduce 8 partial sums per thread over the block in one go: recursive
-// halving inside the wave (7 shuffles), three more butterfly steps, then a
-// cross-wave sum in LDS.  red[w * ld + k0 + q] receives the wave sums.
-__device__ __forceinline__ void wave_reduce8(double (&part)[8], double* red,
-                                             int ld, int k0) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const bool up = (lane & 32) != 0;
-        const double send = up ? part[q] : part[q + 4];
-        const double keep = up ? part[q + 4] : part[q];
-        part[q] = keep + __shfl_xor(send, 32, WAVE);
-    }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const bool up = (lane & 16) != 0;
-        const double send = up ? part[q] : part[q + 2];
-        const double keep = up ? part[q + 2] : part[q];
-        part[q] = keep + __shfl_xor(send, 16, WAVE);
-    }
-    {
-        const bool up = (lane & 8) != 0;
-        const double send = up ? part[0] : part[1];
-        const double keep = up ? part[1] : part[0];
-        part[0] = keep + __shfl_xor(send, 8, WAVE);
-    }
-    double v = part[0];
-    v += __shfl_xor(v, 4, WAVE);
-    v += __shfl_xor(v, 2, WAVE);
-    v += __shfl_xor(v, 1, WAVE);
-    // lane bits 5,4,3 select the value: q = 4*b5 + 2*b4 + b3
-    if ((lane & 7) == 0) red[wave_id() * ld + k0 + (lane >> 3)] = v;
-}
-
 template <int PT, bool SI>
 struct Ctx {
+    // Points owned by thread t: R groups of VW consecutive points, group r
+    // at (t + r*B)*VW, so every basis read is a coalesced 16-byte load.
+    static constexpr int VW = (PT >= 2) ? 2 : 1;
+    static constexpr int R = PT / VW;
     const KrylovArgs a;
     Smem S;
     double* V;
@@ -98,10 +70,9 @@ struct Ctx {
 
     __device__ Ctx(const KrylovArgs& a_, double* lds, double* V_)
         : a(a_), V(V_), n(a_.n), m(a_.m), B(blockDim.x), t(threadIdx.x) {
-        const int nw = num_waves();
         ldr = ((m + 1 + 7) / 8) * 8;
         S.red = lds;
-        S.hcol = S.red + nw * ldr;
+        S.hcol = S.red + 64;
         S.H = S.hcol + ldr + 8;
         S.big = S.H + (size_t)(m + 1) * m;
         S.Mt = S.big;
@@ -115,25 +86,59 @@ struct Ctx {
         op.cc = a.op.d + 2.0 * op.cs;
     }
 
-    __device__ __forceinline__ int idx(int r) const { return t + r * B; }
-    __device__ __forceinline__ bool own(int r) const { return PT * B == n || idx(r) < n; }
+    // first point of group r, and whether the group lies inside the grid
+    __device__ __forceinline__ int gidx(int r) const { return (t + r * B) * VW; }
+    __device__ __forceinline__ bool own(int r) const { return gidx(r) < n; }
+
+    // x[r*VW + v] = src[gidx(r) + v] (global, 16-byte loads when VW == 2)
+    __device__ __forceinline__ void gload(const double* __restrict__ src,
+                                          double (&x)[PT]) const {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (VW == 2) {
+                double2 v = own(r) ? *reinterpret_cast<const double2*>(src + gidx(r))
+                                   : make_double2(0.0, 0.0);
+                x[2 * r] = v.x;
+                x[2 * r + 1] = v.y;
+            } else {
+                x[r] = own(r) ? src[gidx(r)] : 0.0;
+            }
+        }
+    }
+    __device__ __forceinline__ void gstore(double* __restrict__ dst,
+                                           const double (&x)[PT]) const {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!own(r)) continue;
+            if (VW == 2)
+                *reinterpret_cast<double2*>(dst + gidx(r)) = make_double2(x[2 * r], x[2 * r + 1]);
+            else
+                dst[gidx(r)] = x[r];
+        }
+    }
 
     // z <- Op z (polynomial) or (I - gamma Op)^{-1} z (shift-and-invert).
     __device__ __forceinline__ void apply(double (&z)[PT], double gamma) {
         double* b0 = S.big;
+        __syncthreads();  // previous users of `big` are done
 #pragma unroll
-        for (int r = 0; r < PT; ++r)
-            if (own(r)) b0[idx(r)] = z[r];
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int v = 0; v < VW; ++v)
+                if (own(r)) b0[gidx(r) + v] = z[r * VW + v];
         __syncthreads();
         if (!SI) {
 #pragma unroll
-            for (int r = 0; r < PT; ++r) {
+            for (int r = 0; r < R; ++r) {
                 if (!own(r)) continue;
-                const int i = idx(r);
-                const double xm = b0[i == 0 ? n - 1 : i - 1];
-                const double xp = b0[i == n - 1 ? 0 : i + 1];
-                const double x0 = b0[i];
-                z[r] = op.cs * ((xp + xm) - 2.0 * x0) + op.cdf * (xp - xm) + op.cc * x0;
+#pragma unroll
+                for (int v = 0; v < VW; ++v) {
+                    const int i = gidx(r) + v;
+                    const double xm = b0[i == 0 ? n - 1 : i - 1];
+                    const double xp = b0[i == n - 1 ? 0 : i + 1];
+                    const double x0 = b0[i];
+                    z[r * VW + v] = op.cs * ((xp + xm) - 2.0 * x0) + op.cdf * (xp - xm) + op.cc * x0;
+                }
             }
         } else {
             // Periodic cyclic reduction on a x_{i-1} + b x_i + c x_{i+1} = d_i
@@ -147,68 +152,92 @@ struct Ctx {
             for (int s = 1; 2 * s < n; s <<= 1) {
                 const double k1 = ca / cb, k2 = cc / cb;
 #pragma unroll
-                for (int r = 0; r < PT; ++r) {
-                    const int i = idx(r);
-                    dst[i] = src[i] - k1 * src[(i - s) & mask] - k2 * src[(i + s) & mask];
-                }
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int v = 0; v < VW; ++v) {
+                        const int i = gidx(r) + v;
+                        dst[i] = src[i] - k1 * src[(i - s) & mask] - k2 * src[(i + s) & mask];
+                    }
                 const double na = -ca * k1, nc = -cc * k2, nb = cb - cc * k1 - ca * k2;
                 ca = na; cb = nb; cc = nc;
                 __syncthreads();
                 double* tmp = src; src = dst; dst = tmp;
             }
             const double e = ca + cc;
-            const double det = cb * cb - e * e;
+            const double idet = 1.0 / (cb * cb - e * e);
             const int hn = n >> 1;
 #pragma unroll
-            for (int r = 0; r < PT; ++r) {
-                const int i = idx(r);
-                z[r] = (cb * src[i] - e * src[(i + hn) & mask]) / det;
-            }
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int v = 0; v < VW; ++v) {
+                    const int i = gidx(r) + v;
+                    z[r * VW + v] = (cb * src[i] - e * src[(i + hn) & mask]) * idet;
+                }
         }
-        // Readers of `big` finish before any later writer: every later write
-        // is preceded by a block reduction, which begins with a barrier.
     }
 
-    // hcol[k] = <V_k, z> for k <= j (block-wide, deterministic order).
+    // hcol[k] = <V_k, z> for k <= j.  Per-thread partial sums go to LDS
+    // (layout [k][thread]) so the basis loads stream without waiting for
+    // shuffles; each wave then reduces a subset of k in a fixed order.
     __device__ __forceinline__ void dots(const double (&z)[PT], int j) {
+        double* P = S.big;
         __syncthreads();
-        for (int k0 = 0; k0 <= j; k0 += 8) {
-            double part[8];
+        constexpr int UK = (PT >= 16) ? 1 : 2;
+#pragma unroll UK
+        for (int k0 = 0; k0 <= j; k0 += 4) {
+            double part[4];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < 4; ++q) {
                 double s = 0.0;
-                const int k = k0 + q;
-                if (k <= j) {
-                    const double* Vk = V + (size_t)k * n;
+                if (k0 + q <= j) {
+                    double x[PT];
+                    gload(V + (size_t)(k0 + q) * n, x);
 #pragma unroll
-                    for (int r = 0; r < PT; ++r)
-                        if (own(r)) s += Vk[idx(r)] * z[r];
+                    for (int u = 0; u < PT; ++u) s += x[u] * z[u];
                 }
                 part[q] = s;
             }
-            wave_reduce8(part, S.red, ldr, k0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (k0 + q <= j) P[(k0 + q) * B + t] = part[q];
         }
         __syncthreads();
-        const int nw = num_waves();
-        if (t <= j) {
+        const int lane = lane_id(), nw = num_waves();
+        for (int k = wave_id(); k <= j; k += nw) {
             double s = 0.0;
-            for (int w = 0; w < nw; ++w) s += S.red[w * ldr + t];
-            S.hcol[t] = s;
+            for (int u = lane; u < B; u += WAVE) s += P[k * B + u];
+            s = wave_sum(s);
+            if (lane == 0) S.hcol[k] = s;
         }
         __syncthreads();
+    }
+
+    // z -= sum_{k<=j} hcol[k] V_k
+    __device__ __forceinline__ void subtract(double (&z)[PT], int j) {
+        constexpr int UK = (PT >= 16) ? 2 : 4;
+#pragma unroll UK
+        for (int k = 0; k <= j; ++k) {
+            const double h = S.hcol[k];
+            double x[PT];
+            gload(V + (size_t)k * n, x);
+#pragma unroll
+            for (int u = 0; u < PT; ++u) z[u] -= h * x[u];
+        }
+    }
+
+    __device__ __forceinline__ double sumsq(const double (&z)[PT]) const {
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < PT; ++u) s += z[u] * z[u];
+        return s;
     }
 
     // Arnoldi from the (unnormalised) vector held in V_0.  Returns the
     // dimension reached; beta = |v|; bd = happy breakdown.
     __device__ __forceinline__ int arnoldi(double gamma, double& beta, bool& bd) {
         double z[PT];
-        double ss = 0.0;
-#pragma unroll
-        for (int r = 0; r < PT; ++r) {
-            z[r] = own(r) ? V[idx(r)] : 0.0;
-            ss += z[r] * z[r];
-        }
-        beta = sqrt(block_sum(ss, S.red));
+        gload(V, z);
+        beta = sqrt(block_sum(sumsq(z), S.red));
         bd = false;
         for (int o = t; o < (m + 1) * m; o += B) S.H[o] = 0.0;
         if (!(beta > 0.0)) {
@@ -217,10 +246,8 @@ struct Ctx {
         }
         const double ib = 1.0 / beta;
 #pragma unroll
-        for (int r = 0; r < PT; ++r) {
-            z[r] *= ib;
-            if (own(r)) V[idx(r)] = z[r];
-        }
+        for (int u = 0; u < PT; ++u) z[u] *= ib;
+        gstore(V, z);
         int me = m;
         for (int j = 0; j < m; ++j) {
             apply(z, gamma);
@@ -228,18 +255,9 @@ struct Ctx {
             for (int pass = 0; pass < 2; ++pass) {
                 dots(z, j);
                 if (t <= j) S.H[t * m + j] += S.hcol[t];
-                for (int k = 0; k <= j; ++k) {
-                    const double h = S.hcol[k];
-                    const double* Vk = V + (size_t)k * n;
-#pragma unroll
-                    for (int r = 0; r < PT; ++r)
-                        if (own(r)) z[r] -= h * Vk[idx(r)];
-                }
+                subtract(z, j);
             }
-            double s2 = 0.0;
-#pragma unroll
-            for (int r = 0; r < PT; ++r) s2 += own(r) ? z[r] * z[r] : 0.0;
-            const double nrm = sqrt(block_sum(s2, S.red));
+            const double nrm = sqrt(block_sum(sumsq(z), S.red));
             // |Op v_j|^2 = sum_k h_kj^2 + nrm^2 (the Gram-Schmidt column)
             double col = nrm * nrm;
             for (int k = 0; k <= j; ++k) col += S.H[k * m + j] * S.H[k * m + j];
@@ -252,19 +270,16 @@ struct Ctx {
                 break;
             }
             const double inv = 1.0 / nrm;
-            double* Vn = V + (size_t)(j + 1) * n;
 #pragma unroll
-            for (int r = 0; r < PT; ++r) {
-                z[r] *= inv;
-                if (own(r)) Vn[idx(r)] = z[r];
-            }
+            for (int u = 0; u < PT; ++u) z[u] *= inv;
+            gstore(V + (size_t)(j + 1) * n, z);
         }
         __syncthreads();
         return me;
     }
 
     // Mt = scale * (I - H_k^{-1}) / gamma for the leading k x k block.
-    __device__ void si_image(int k, double gamma, double scale) {
+    __device__ __forceinline__ void si_image(int k, double gamma, double scale) {
         const int ld = 2 * k;
         for (int o = t; o < k * ld; o += B) {
             const int r = o / ld, c = o - r * ld;
@@ -280,7 +295,7 @@ struct Ctx {
     }
 
     // vec = exp(ts Hop) e_1 (leading k x k block); returns |vec[k-1]|.
-    __device__ double small_exp(int k, double ts, double gamma, double* vec) {
+    __device__ __forceinline__ double small_exp(int k, double ts, double gamma, double* vec) {
         if (SI) {
             si_image(k, gamma, ts);
         } else {
@@ -298,7 +313,7 @@ struct Ctx {
 
     // vc = coefficients of int_0^ts sin(ia + ib s) exp(s Hop) e_1 ds, given
     // vy = exp(ts Hop) e_1.
-    __device__ void small_integral(int k, double ts, double ia, double ib,
+    __device__ __forceinline__ void small_integral(int k, double ts, double ia, double ib,
                                    double gamma) {
         if (SI) si_image(k, gamma, 1.0);  // Mt = Hop
         const int n2 = 2 * k, ld = n2 + 1;
@@ -329,31 +344,34 @@ struct Ctx {
     __device__ __forceinline__ void combine(int k, double beta, double* iout) {
         double y[PT], I[PT];
 #pragma unroll
-        for (int r = 0; r < PT; ++r) {
-            y[r] = 0.0;
-            I[r] = 0.0;
+        for (int u = 0; u < PT; ++u) {
+            y[u] = 0.0;
+            I[u] = 0.0;
         }
+        constexpr int UK = (PT >= 16) ? 2 : 4;
+#pragma unroll UK
         for (int q = 0; q < k; ++q) {
             const double cy = beta * S.vy[q];
             const double ci = iout ? beta * S.vc[q] : 0.0;
-            const double* Vq = V + (size_t)q * n;
+            double x[PT];
+            gload(V + (size_t)q * n, x);
 #pragma unroll
-            for (int r = 0; r < PT; ++r) {
-                if (!own(r)) continue;
-                const double v = Vq[idx(r)];
-                y[r] += cy * v;
-                I[r] += ci * v;
+            for (int u = 0; u < PT; ++u) {
+                y[u] += cy * x[u];
+                I[u] += ci * x[u];
             }
         }
+        gstore(V, y);
+        if (iout) {
+            double o[PT];
+            gload(iout, o);
 #pragma unroll
-        for (int r = 0; r < PT; ++r) {
-            if (!own(r)) continue;
-            V[idx(r)] = y[r];
-            if (iout) iout[idx(r)] += I[r];
+            for (int u = 0; u < PT; ++u) o[u] += I[u];
+            gstore(iout, o);
         }
     }
 
-    __device__ void report(double est_rel, bool noconv, unsigned substeps,
+    __device__ __forceinline__ void report(double est_rel, bool noconv, unsigned substeps,
                            unsigned iters) {
         if (t == 0 && a.status) {
             if (noconv) atomicOr(&a.status->flags, ST_NOCONV);
@@ -368,7 +386,7 @@ struct Ctx {
 
     // V_0 <- exp(tau Op) V_0; if iout, iout += int_0^tau sin(ia + ib s)
     // exp(s Op) V_0 ds.
-    __device__ void expv(double tau, double ia, double ib, double* iout) {
+    __device__ __forceinline__ void expv(double tau, double ia, double ib, double* iout) {
         if (!(tau > 0.0)) return;
         const double tol = a.tol;
         if (SI) {
@@ -447,43 +465,45 @@ struct Ctx {
 template <int PT, bool SI>
 __global__ void __launch_bounds__(256) k_krylov1d(KrylovArgs a) {
     extern __shared__ double lds[];
-    const int n = a.n, B = blockDim.x, t = threadIdx.x;
+    const int n = a.n;
     const int piece = blockIdx.x;
     double* V = a.basis + (size_t)piece * (a.m + 1) * n;
     Ctx<PT, SI> c(a, lds, V);
     // The current vector of the piece lives in V_0 (global memory); every
     // thread only reads and writes its own points of it.
-    if (a.mode == KM_CLASSIC) {
-        const double* vin = a.vin + (size_t)piece * n;
-        for (int r = 0; r < PT; ++r)
-            if (c.own(r)) V[t + r * B] = vin[t + r * B];
-        const double tau = (double)(a.npieces - piece) * a.tau;
-        c.expv(tau, 0.0, 0.0, nullptr);
-        double* y = a.yout + (size_t)piece * n;
-        for (int r = 0; r < PT; ++r)
-            if (c.own(r)) y[t + r * B] = V[t + r * B];
-    } else if (a.mode == KM_CHAIN) {
-        for (int r = 0; r < PT; ++r)
-            if (c.own(r)) V[t + r * B] = a.vin[t + r * B];
-        for (int q = 1; q < a.npieces; ++q) {
-            c.expv(a.tau, 0.0, 0.0, nullptr);
-            const double* vq = a.vin + (size_t)q * n;
-            for (int r = 0; r < PT; ++r)
-                if (c.own(r)) V[t + r * B] += vq[t + r * B];
+    const double* vin = (a.mode == KM_CLASSIC) ? a.vin + (size_t)piece * n : a.vin;
+    {
+        double x[PT];
+        c.gload(vin, x);
+        c.gstore(V, x);
+        if (a.mode == KM_SINGLE && a.iout) {
+#pragma unroll
+            for (int u = 0; u < PT; ++u) x[u] = 0.0;
+            c.gstore(a.iout, x);
         }
-        for (int r = 0; r < PT; ++r)
-            if (c.own(r)) a.yout[t + r * B] = V[t + r * B];
-    } else {
-        for (int r = 0; r < PT; ++r) {
-            if (!c.own(r)) continue;
-            V[t + r * B] = a.vin[t + r * B];
-            if (a.iout) a.iout[t + r * B] = 0.0;
+    }
+    // classic: one exponential of (npieces - piece) slice lengths;
+    // chain: npieces - 1 exponentials of one slice length, adding the next
+    // slice end state after each; single: one exponential with integral.
+    const int nexp = (a.mode == KM_CHAIN) ? a.npieces - 1 : 1;
+    const double tau = (a.mode == KM_CLASSIC) ? (double)(a.npieces - piece) * a.tau : a.tau;
+    double* iout = (a.mode == KM_SINGLE) ? a.iout : nullptr;
+    for (int q = 0; q < nexp; ++q) {
+        c.expv(tau, a.ia, a.ib, iout);
+        if (a.mode == KM_CHAIN) {
+            double x[PT], w[PT];
+            c.gload(a.vin + (size_t)(q + 1) * n, x);
+            c.gload(V, w);
+#pragma unroll
+            for (int u = 0; u < PT; ++u) w[u] += x[u];
+            c.gstore(V, w);
         }
-        c.expv(a.tau, a.ia, a.ib, a.iout);
-        if (a.yout) {
-            for (int r = 0; r < PT; ++r)
-                if (c.own(r)) a.yout[t + r * B] = V[t + r * B];
-        }
+    }
+    double* y = (a.mode == KM_CLASSIC) ? a.yout + (size_t)piece * n : a.yout;
+    if (y) {
+        double x[PT];
+        c.gload(V, x);
+        c.gstore(y, x);
     }
 }
 
@@ -528,9 +548,8 @@ bool krylov_shape(int n, int block_hint, int* B, int* pt) {
 
 size_t krylov1d_lds_bytes(int n, int m, int block, int si) {
     (void)si;
-    const int nw = block / 64;
     const int ldr = ((m + 1 + 7) / 8) * 8;
-    const size_t d = (size_t)nw * ldr + ldr + 8 + (size_t)(m + 1) * m + big_doubles(n, m);
+    const size_t d = 64 + ldr + 8 + (size_t)(m + 1) * m + big_doubles(n, m, block);
     return d * sizeof(double);
 }
 
@@ -540,6 +559,8 @@ hipError_t launch_krylov1d(const KrylovArgs& a, int block_hint, hipStream_t s) {
     int B, pt;
     if (!krylov_shape(a.n, block_hint, &B, &pt)) return hipErrorInvalidValue;
     if (a.si && pt * B != a.n) return hipErrorInvalidValue;
+    // two consecutive points per 16-byte load when pt >= 2
+    if (pt >= 2 && (a.n & 1)) return hipErrorInvalidValue;
     const size_t lds = krylov1d_lds_bytes(a.n, a.m, B, a.si);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     const int grid = (a.mode == KM_CLASSIC) ? a.npieces : 1;

@@ -19,6 +19,13 @@
 namespace pxp {
 namespace {
 
+// Largest workgroup for PT points per thread: keeps the register arrays of
+// the march (about 6 PT doubles) inside the VGPR budget without spills.
+template <int PT>
+constexpr int max_block() {
+    return PT <= 4 ? 1024 : (PT <= 16 ? 512 : 256);
+}
+
 // Exchange the chunk edges of NA arrays with one barrier.  edge is LDS of
 // 2 buffers of NB x 2 x B doubles (NB >= NA: the same buffer stride must be
 // used by every exchange of a kernel so the two buffers never overlap).
@@ -71,7 +78,7 @@ __device__ __forceinline__ void tri_rhs(const double (&Y)[PT], double l, double 
 }
 
 template <int PT>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(max_block<PT>())
 k_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
             const double* __restrict__ y0, double* __restrict__ out, int n,
             int64_t n_s, double dt, double omega, TriSplit A) {
@@ -148,7 +155,7 @@ k_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
 // gives kbar_i = dt b_i lam (+ the chain through later stages), Ybar_i =
 // A^T kbar_i, lam_s = lam_{s+1} + sum_i Ybar_i.
 template <int PT>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(max_block<PT>())
 k_rk4_rev_lin1d(const double* __restrict__ lamT, double* __restrict__ lam0,
                 double* __restrict__ Lambda, int n, int64_t n_t, double dt,
                 double omega, TriSplit AT) {
@@ -290,7 +297,7 @@ __device__ __forceinline__ void burgers_step(double (&y)[PT], double dt,
 }
 
 template <int PT>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(max_block<PT>())
 k_rk4_burgers_direct(const double* __restrict__ y0, double* __restrict__ yT,
                      double* __restrict__ ckpt, int n, int64_t n_t, int64_t c,
                      double dt, BurgersC bc) {
@@ -345,7 +352,7 @@ __device__ __forceinline__ void burgers_jt(const double (&U)[PT], double Ul,
 }
 
 template <int PT>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(max_block<PT>())
 k_rk4_burgers_reverse(const double* __restrict__ ckpt,
                       const double* __restrict__ lamT, double* __restrict__ lam0,
                       double* __restrict__ seg, int n, int64_t n_t, int64_t c,
@@ -436,27 +443,34 @@ k_rk4_burgers_reverse(const double* __restrict__ ckpt,
     for (int q = 0; q < PT; ++q) lam0[base + q] = lam[q];
 }
 
-// Threads per workgroup and points per thread for an n-point march.
+// Threads per workgroup and points per thread for an n-point march: by
+// default 256 threads (one wave per SIMD, full register budget) with n/256
+// points each; small grids use fewer threads.
+int max_block_rt(int pt) { return pt <= 4 ? 1024 : (pt <= 16 ? 512 : 256); }
+
+bool valid_pt(int p) { return p == 1 || p == 2 || p == 4 || p == 8 || p == 16 || p == 32; }
+
 bool pick_shape(int n, int block_hint, int* block, int* pt) {
+    if (n < 2) return false;
     if (block_hint > 0) {
         if (n % block_hint) return false;
         const int p = n / block_hint;
-        if (p == 1 || p == 2 || p == 4 || p == 8 || p == 16) {
-            *block = block_hint;
-            *pt = p;
-            return block_hint <= 1024;
-        }
-        return false;
+        if (!valid_pt(p) || block_hint > max_block_rt(p)) return false;
+        *block = block_hint;
+        *pt = p;
+        return true;
     }
-    static const int cands[] = {64, 128, 256, 512, 1024};
+    if (n % 256 == 0 && valid_pt(n / 256) && n / 256 <= 16) {
+        *block = 256;
+        *pt = n / 256;
+        return true;
+    }
+    static const int cands[] = {64, 128, 512, 1024};
     for (int b : cands) {
-        if (n % b == 0 && n / b <= 16) {
-            const int p = n / b;
-            if (p == 1 || p == 2 || p == 4 || p == 8 || p == 16) {
-                *block = b;
-                *pt = p;
-                return true;
-            }
+        if (n % b == 0 && valid_pt(n / b) && b <= max_block_rt(n / b)) {
+            *block = b;
+            *pt = n / b;
+            return true;
         }
     }
     if (n <= 1024) {
@@ -476,6 +490,7 @@ bool pick_shape(int n, int block_hint, int* block, int* pt) {
         case 4: KERNEL<4> __VA_ARGS__; break;                                  \
         case 8: KERNEL<8> __VA_ARGS__; break;                                  \
         case 16: KERNEL<16> __VA_ARGS__; break;                                \
+        case 32: KERNEL<32> __VA_ARGS__; break;                                \
         default: return hipErrorInvalidValue;                                  \
     }
 

@@ -58,7 +58,7 @@ def small_advdiff(n=64, T=0.5, nt=500, P=4, m=30, K=3, seed=0, nu=0.05):
 
 @pytest.mark.parametrize("n", [64, 128, 2048])
 def test_serial_matches_oracle_to_rounding(torch, orc, n):
-    inst = small_advdiff(n=n, T=0.25, nt=250 if n <= 512 else 2500,
+    inst = small_advdiff(n=n, T=0.25, nt=250 if n <= 512 else 2500, P=5,
                          nu=0.01 if n > 512 else 0.05)
     say("serial parity n=%d" % n)
     got = run(inst, "serial")
@@ -141,7 +141,10 @@ def test_krylov_full_dimension_is_exact(torch):
                                           ("shift_invert", "chain")])
 def test_paraexp_workload_n128(torch, orc, krylov, sched):
     inst = workloads.make("advdiff1d_n128")[0]
-    got = run(inst, krylov=krylov, sched=sched)
+    # per-piece estimate tolerance; m = 30 shift-and-invert spaces on this
+    # mildly stiff grid estimate about 2e-10 for the longest piece
+    got = run(inst, krylov=krylov, sched=sched,
+              tol=1e-9 if krylov == "shift_invert" else 1e-10)
     want = orc.gradient(inst)
     eq, eg = rel(got["qT"], want["qT"]), rel(got["grad"], want["grad"])
     say("n128 paraexp %s/%s: qT %.2e grad %.2e est %.1e st %d"
