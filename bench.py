@@ -63,7 +63,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="advdiff1d_n4096")
-    ap.add_argument("--krylov", default="shift_invert", choices=["poly", "shift_invert"])
+    ap.add_argument("--krylov", default=None, choices=["poly", "shift_invert"])
     ap.add_argument("--sched", default="classic", choices=["classic", "chain"])
     ap.add_argument("--serial-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -83,6 +83,9 @@ def main():
     n, n_steps, P, m = inst["nx"] * inst.get("ny", 1), inst["n_steps"], inst["P"], inst["m"]
     log("workload %s: N=%d steps=%d P=%d m=%d" % (args.workload, n, n_steps, P, m))
 
+    if args.krylov is None:
+        # shift-and-invert needs a constant-coefficient tridiagonal operator
+        args.krylov = "shift_invert" if inst["op"] == "advdiff1d" else "poly"
     pxp = api.GradientRunner([inst], method="paraexp", krylov=args.krylov,
                              sched=args.sched)
     ser = api.GradientRunner([inst], method="serial")
@@ -124,7 +127,9 @@ def main():
     t0 = time.perf_counter()
     ref = oracle.gradient(inst)
     t_orc = time.perf_counter() - t0
+    lam_key = "Lambda" if inst["control"] == "forcing" else "lam0"
     err = dict(paraexp_grad=rel(res_pxp["grad"], ref["grad"]),
+               paraexp_adjoint=rel(res_pxp["lam"], ref[lam_key]),
                paraexp_qT=rel(res_pxp["qT"], ref["qT"]),
                serial_grad=rel(res_ser["grad"], ref["grad"]),
                serial_qT=rel(res_ser["qT"], ref["qT"]))

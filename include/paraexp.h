@@ -180,7 +180,8 @@ enum {
     PXP_K_KRYLOV_ADJOINT = 2,  /* adjoint homogeneous piece and integral    */
     PXP_K_SERIAL_DIRECT = 3,   /* serial RK4 march                          */
     PXP_K_SERIAL_REVERSE = 4,  /* serial reverse (discrete adjoint) sweep   */
-    PXP_K_LTV_ADJOINT = 5      /* time-varying adjoint pieces (Burgers)     */
+    PXP_K_LTV_ADJOINT = 5,     /* time-varying adjoint Magnus chain         */
+    PXP_K_LTV_NODES = 6        /* per-slice recompute of the Magnus states  */
 };
 pxp_status pxp_profile_enable(int32_t on);
 pxp_status pxp_profile_read(int32_t kernel_class, double* total_ms,

@@ -32,7 +32,8 @@ EXPORTED = ("pxp_workspace_size", "pxp_workspace_init", "paraexp_direct",
             "pxp_device_counters", "pxp_status_str", "pxp_version",
             "pxp_profile_enable", "pxp_profile_read")
 KCLASS = {"slices": 0, "krylov_direct": 1, "krylov_adjoint": 2,
-          "serial_direct": 3, "serial_reverse": 4, "ltv_adjoint": 5}
+          "serial_direct": 3, "serial_reverse": 4, "ltv_adjoint": 5,
+          "ltv_nodes": 6}
 
 
 class pxp_problem(ctypes.Structure):

@@ -29,7 +29,7 @@ struct Layout {
 // Per-instance buffers (offsets relative to the instance region).
 struct Inst {
     size_t F, g0, q0eff, slices, pieces, basis, qT, lamT, lam0, Lam, chain,
-        ckpt, seg, J, size;
+        ckpt, seg, nodes, J, size;
 };
 
 int64_t grid_n(const pxp_problem& p) { return (int64_t)p.nx * (int64_t)p.ny; }
@@ -100,6 +100,9 @@ pxp_status validate(const pxp_problem& p) {
         int b, pt;
         if (!march_shape(p.nx, p.block, &b, &pt)) return PXP_EUNSUPPORTED;
         if (p.ckpt_every < 1 || p.n_steps % p.ckpt_every) return PXP_EINVAL;
+        if (p.m < 1 || p.m > M_MAX_1D) return PXP_EUNSUPPORTED;
+        if (!(p.krylov_tol > 0.0)) return PXP_EINVAL;
+        if (p.nx > 256 && (p.nx & 1)) return PXP_EUNSUPPORTED;
         // diffusion part of the spectrum on the negative real axis
         const double h = p.L / p.nx, dt = p.T / (double)p.n_steps;
         if (dt * 4.0 * p.nu / (h * h) > 2.785) return PXP_EUNSTABLE_DT;
@@ -138,6 +141,8 @@ Inst inst_layout(const pxp_problem& p) {
         const size_t c = (size_t)p.ckpt_every;
         L.ckpt = take(((size_t)p.n_steps / c + 1) * n * d);
         L.seg = take(c * n * d);
+        L.nodes = take(2 * P * n * d);
+        L.basis = take((m + 1) * n * d);
     }
     L.size = off;
     return L;
@@ -334,11 +339,41 @@ pxp_status direct_burgers(const Ctx& c, const double* q0, double* qT) {
     return PXP_OK;
 }
 
-pxp_status adjoint_burgers(const Ctx& c, const double* lamT, double* lam0) {
-    ProfScope ps(PXP_K_SERIAL_REVERSE, c.s);
-    HIPCHK(launch_rk4_burgers_reverse(c.at(c.L.ckpt), lamT, lam0, c.at(c.L.seg),
-                                      c.n(), c.p.n_steps, c.p.ckpt_every, c.dt(),
-                                      c.p.nu, c.p.L, c.p.block, c.s));
+pxp_status adjoint_burgers(const Ctx& c, const double* lamT, double* lam0,
+                           int method) {
+    if (method == PXP_METHOD_SERIAL) {
+        ProfScope ps(PXP_K_SERIAL_REVERSE, c.s);
+        HIPCHK(launch_rk4_burgers_reverse(c.at(c.L.ckpt), lamT, lam0, c.at(c.L.seg),
+                                          c.n(), c.p.n_steps, c.p.ckpt_every, c.dt(),
+                                          c.p.nu, c.p.L, c.p.block, c.s));
+        return PXP_OK;
+    }
+    // The adjoint of the serial direct march is linear and time-varying
+    // (section 3.3).  With a terminal cost only it is the single
+    // homogeneous piece from q^dagger(T) (eq. adjhomfinal), propagated over
+    // the P slices by fourth-order commutator-free Magnus steps; each factor
+    // is the exponential of the Burgers Jacobian transpose at an effective
+    // state, recomputed for all slices at once from the checkpoints.
+    const int64_t S = c.p.n_steps / c.p.P;
+    const double h = c.p.L / c.p.nx;
+    {
+        ProfScope ps(PXP_K_LTV_NODES, c.s);
+        HIPCHK(launch_burgers_nodes(c.at(c.L.ckpt), c.at(c.L.nodes), c.n(),
+                                    c.p.n_steps, c.p.ckpt_every, S, c.dt(), c.p.nu,
+                                    c.p.L, c.p.block, c.s));
+    }
+    KrylovArgs a = kargs(c, Tri{0.0, 0.0, 0.0});
+    a.si = 0;
+    a.mode = KM_LTV;
+    a.npieces = c.p.P;
+    a.vin = lamT;
+    a.yout = lam0;
+    a.tau = 0.5 * (double)S * c.dt();
+    a.wop = c.at(c.L.nodes);
+    a.inv2h = 1.0 / (2.0 * h);
+    a.nuh2 = c.p.nu / (h * h);
+    ProfScope ps(PXP_K_LTV_ADJOINT, c.s);
+    HIPCHK(launch_krylov1d(a, 0, c.s));
     return PXP_OK;
 }
 
@@ -468,7 +503,7 @@ static pxp_status adjoint_impl(const pxp_problem* pb, int32_t batch,
         } else {
             if (Lambda) return PXP_EINVAL;  // no forcing control for Burgers
             if (!lam0) return PXP_EINVAL;
-            st = adjoint_burgers(c, lamT + off, lam0 + off);
+            st = adjoint_burgers(c, lamT + off, lam0 + off, method);
         }
         if (st != PXP_OK) return st;
         off += (size_t)grid_n(p);
@@ -538,7 +573,7 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
             st = adjoint_lin1d(c, lamT, forcing ? nullptr : lam0,
                                forcing ? Lam : nullptr, method);
         } else {
-            st = adjoint_burgers(c, lamT, lam0);
+            st = adjoint_burgers(c, lamT, lam0, method);
         }
         if (st != PXP_OK) return st;
         // (a9) gradient

@@ -53,8 +53,17 @@ hipError_t launch_rk4_burgers_reverse(const double* ckpt, const double* lamT,
                                       double nu, double L, int block,
                                       hipStream_t s);
 
+// Effective states of the two commutator-free Magnus factors of each macro
+// step of S steps (W[2q], W[2q+1], q < n_t / S), recomputed from the
+// checkpoints (every c steps) in parallel over macro steps.
+hipError_t launch_burgers_nodes(const double* ckpt, double* W, int n, int64_t n_t,
+                                int64_t c, int64_t S, double dt, double nu, double L,
+                                int block, hipStream_t s);
+
 // ---- Krylov exponential pieces (1D tridiagonal operator) -------------------
-enum KrylovMode { KM_CLASSIC = 0, KM_CHAIN = 1, KM_SINGLE = 2 };
+// KM_LTV: chain of 2*npieces exponentials exp(tau J(W_e)^T) with the Burgers
+// Jacobian transpose at the effective states W_e = wop + e*n, in order.
+enum KrylovMode { KM_CLASSIC = 0, KM_CHAIN = 1, KM_SINGLE = 2, KM_LTV = 3 };
 
 struct KrylovArgs {
     int mode;            // KrylovMode
@@ -70,6 +79,8 @@ struct KrylovArgs {
     double tol;          // relative tolerance
     double gamma_frac;   // shift-and-invert shift = gamma_frac * time
     Tri op;
+    const double* wop;   // KM_LTV: effective states [2*npieces][n]
+    double inv2h, nuh2;  // KM_LTV: 1/(2h), nu/h^2
     double* basis;       // [gridDim][m+1][n] workspace
     DevStatus* status;
 };

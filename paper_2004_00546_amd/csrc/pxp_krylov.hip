@@ -56,7 +56,7 @@ struct Tsplit {
     double cs, cdf, cc;
 };
 
-template <int PT, bool SI>
+template <int PT, bool SI, bool VAR>
 struct Ctx {
     // Points owned by thread t: R groups of VW consecutive points, group r
     // at (t + r*B)*VW, so every basis read is a coalesced 16-byte load.
@@ -67,6 +67,7 @@ struct Ctx {
     double* V;
     int n, m, B, t, ldr;
     Tsplit op;
+    const double* Wcur = nullptr;  // VAR: state W of the operator J(W)^T
 
     __device__ Ctx(const KrylovArgs& a_, double* lds, double* V_)
         : a(a_), V(V_), n(a_.n), m(a_.m), B(blockDim.x), t(threadIdx.x) {
@@ -127,7 +128,23 @@ struct Ctx {
             for (int v = 0; v < VW; ++v)
                 if (own(r)) b0[gidx(r) + v] = z[r * VW + v];
         __syncthreads();
-        if (!SI) {
+        if (VAR) {
+            // (J(W)^T x)_i = ((W x)_{i+1} - (W x)_{i-1})/(2h)
+            //               - (W_{i+1} - W_{i-1}) x_i/(2h) + nu lap(x)_i
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!own(r)) continue;
+#pragma unroll
+                for (int v = 0; v < VW; ++v) {
+                    const int i = gidx(r) + v;
+                    const int im = i == 0 ? n - 1 : i - 1, ip = i == n - 1 ? 0 : i + 1;
+                    const double xm = b0[im], xp = b0[ip], x0 = b0[i];
+                    const double Wm = Wcur[im], Wp = Wcur[ip];
+                    z[r * VW + v] = a.nuh2 * ((xp + xm) - 2.0 * x0)
+                                    + a.inv2h * ((Wp * xp - Wm * xm) - (Wp - Wm) * x0);
+                }
+            }
+        } else if (!SI) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if (!own(r)) continue;
@@ -233,8 +250,14 @@ struct Ctx {
     }
 
     // Arnoldi from the (unnormalised) vector held in V_0.  Returns the
-    // dimension reached; beta = |v|; bd = happy breakdown.
-    __device__ __forceinline__ int arnoldi(double gamma, double& beta, bool& bd) {
+    // dimension reached; beta = |v|; bd = happy breakdown.  Polynomial
+    // flavour with ts > 0: at dimensions 8, 12, 16, ... the a-posteriori
+    // estimate beta h_{k+1,k} |e_k^T exp(ts H_k) e_1| is checked against
+    // tolb_rel * beta and the process stops early (conv = true, vy holds
+    // exp(ts H_k) e_1) once it is met.
+    __device__ __forceinline__ int arnoldi(double gamma, double& beta, bool& bd,
+                                           double ts = 0.0, double tolb_rel = 0.0,
+                                           bool* conv = nullptr, double* est_out = nullptr) {
         double z[PT];
         gload(V, z);
         beta = sqrt(block_sum(sumsq(z), S.red));
@@ -268,6 +291,17 @@ struct Ctx {
                 me = j + 1;
                 bd = true;
                 break;
+            }
+            const int k = j + 1;
+            if (!SI && conv && ts > 0.0 && k < m && k >= 8 && (k % 4) == 0) {
+                const double e1 = small_exp(k, ts, 0.0, S.vy);
+                const double est = beta * nrm * e1;
+                if (est <= tolb_rel * beta) {
+                    *conv = true;
+                    if (est_out) *est_out = est;
+                    me = k;
+                    break;
+                }
             }
             const double inv = 1.0 / nrm;
 #pragma unroll
@@ -419,14 +453,16 @@ struct Ctx {
         unsigned nsub = 0, iters = 0;
         while (left > 0.0) {
             double beta;
-            bool bd;
-            const int me = arnoldi(0.0, beta, bd);
+            bool bd, conv = false;
+            if (ts > left) ts = left;
+            double est = 0.0, tolb = 0.0;
+            const int me = arnoldi(0.0, beta, bd, ts, tol * (ts / tau), &conv, &est);
             iters += me;
             if (me == 0) break;
             const double hnext = bd ? 0.0 : S.H[me * m + (me - 1)];
             int tries = 0;
-            double est = 0.0, tolb = 0.0;
-            for (;;) {
+            if (conv) tolb = tol * beta * (ts / tau);
+            for (; !conv;) {
                 if (ts > left) ts = left;
                 const double e1 = small_exp(me, ts, 0.0, S.vy);
                 est = bd ? 0.0 : beta * hnext * e1;
@@ -462,13 +498,13 @@ struct Ctx {
     }
 };
 
-template <int PT, bool SI>
+template <int PT, bool SI, bool VAR>
 __global__ void __launch_bounds__(256) k_krylov1d(KrylovArgs a) {
     extern __shared__ double lds[];
     const int n = a.n;
     const int piece = blockIdx.x;
     double* V = a.basis + (size_t)piece * (a.m + 1) * n;
-    Ctx<PT, SI> c(a, lds, V);
+    Ctx<PT, SI, VAR> c(a, lds, V);
     // The current vector of the piece lives in V_0 (global memory); every
     // thread only reads and writes its own points of it.
     const double* vin = (a.mode == KM_CLASSIC) ? a.vin + (size_t)piece * n : a.vin;
@@ -485,10 +521,13 @@ __global__ void __launch_bounds__(256) k_krylov1d(KrylovArgs a) {
     // classic: one exponential of (npieces - piece) slice lengths;
     // chain: npieces - 1 exponentials of one slice length, adding the next
     // slice end state after each; single: one exponential with integral.
-    const int nexp = (a.mode == KM_CHAIN) ? a.npieces - 1 : 1;
+    // ltv: 2 * npieces exponentials, each with its own operator state.
+    const int nexp = (a.mode == KM_CHAIN) ? a.npieces - 1
+                   : (a.mode == KM_LTV) ? 2 * a.npieces : 1;
     const double tau = (a.mode == KM_CLASSIC) ? (double)(a.npieces - piece) * a.tau : a.tau;
     double* iout = (a.mode == KM_SINGLE) ? a.iout : nullptr;
     for (int q = 0; q < nexp; ++q) {
+        if (VAR) c.Wcur = a.wop + (size_t)q * n;
         c.expv(tau, a.ia, a.ib, iout);
         if (a.mode == KM_CHAIN) {
             double x[PT], w[PT];
@@ -507,13 +546,13 @@ __global__ void __launch_bounds__(256) k_krylov1d(KrylovArgs a) {
     }
 }
 
-template <bool SI>
+template <bool SI, bool VAR>
 hipError_t launch_pt(const KrylovArgs& a, int B, int pt, int grid, size_t lds,
                      hipStream_t s) {
     switch (pt) {
 #define PXP_K(PTV)                                                               \
     case PTV: {                                                                \
-        auto kern = k_krylov1d<PTV, SI>;                                 \
+        auto kern = k_krylov1d<PTV, SI, VAR>;                                 \
         hipFuncSetAttribute((const void*)kern,                                 \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
         kern<<<grid, B, lds, s>>>(a);                                          \
@@ -565,8 +604,12 @@ hipError_t launch_krylov1d(const KrylovArgs& a, int block_hint, hipStream_t s) {
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     const int grid = (a.mode == KM_CLASSIC) ? a.npieces : 1;
     if (grid <= 0) return hipSuccess;
-    return a.si ? launch_pt<true>(a, B, pt, grid, lds, s)
-                : launch_pt<false>(a, B, pt, grid, lds, s);
+    if (a.mode == KM_LTV) {
+        if (a.si || !a.wop) return hipErrorInvalidValue;
+        return launch_pt<false, true>(a, B, pt, grid, lds, s);
+    }
+    return a.si ? launch_pt<true, false>(a, B, pt, grid, lds, s)
+                : launch_pt<false, false>(a, B, pt, grid, lds, s);
 }
 
 }  // namespace pxp

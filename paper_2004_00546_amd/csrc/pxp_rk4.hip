@@ -443,6 +443,84 @@ k_rk4_burgers_reverse(const double* __restrict__ ckpt,
     for (int q = 0; q < PT; ++q) lam0[base + q] = lam[q];
 }
 
+// Per-macro-step recompute for the time-varying adjoint (one workgroup per
+// macro step q, all in parallel): march from the checkpoint preceding the
+// step's Gauss nodes, interpolate U at the two nodes by cubic Hermite
+// interpolation between step states (fourth order in dt), and store the
+// effective states of the two commutator-free Magnus factors,
+// W_first = 2(a2 U1 + a1 U2), W_second = 2(a1 U1 + a2 U2),
+// so that each factor is exp((D/2) J(W)^T).  In tau = T - t the macro step q
+// covers [qD, (q+1)D]; U1 = U(T - qD - c1 D), U2 = U(T - qD - c2 D).
+template <int PT>
+__global__ void __launch_bounds__(max_block<PT>())
+k_burgers_nodes(const double* __restrict__ ckpt, double* __restrict__ Wout, int n,
+                int64_t n_t, int64_t c, int64_t S, double dt, BurgersC bc) {
+    extern __shared__ double lds[];
+    const int q = blockIdx.x;
+    const int base = threadIdx.x * PT;
+    const double r3 = sqrt(3.0);
+    const double c1 = 0.5 - r3 / 6.0, c2 = 0.5 + r3 / 6.0;
+    const double a1 = 0.25 - r3 / 6.0, a2 = 0.25 + r3 / 6.0;
+    const double D = (double)S * dt;
+    // node times as step index + fraction; t1 > t2
+    const double f1 = (double)(n_t - (int64_t)q * S) - c1 * (double)S;
+    const double f2 = (double)(n_t - (int64_t)q * S) - c2 * (double)S;
+    int64_t s1 = (int64_t)floor(f1), s2 = (int64_t)floor(f2);
+    if (s1 > n_t - 1) s1 = n_t - 1;
+    if (s2 > n_t - 1) s2 = n_t - 1;
+    if (s2 < 0) s2 = 0;
+    if (s1 < s2) s1 = s2;
+    const double th1 = f1 - (double)s1, th2 = f2 - (double)s2;
+    (void)D;
+    const int64_t start = (s2 / c) * c;
+    double y[PT], y0[PT], k0[PT], k1[PT], U1[PT], U2[PT];
+    const double* ck = ckpt + (size_t)(start / c) * n;
+#pragma unroll
+    for (int i = 0; i < PT; ++i) y[i] = ck[base + i];
+    int buf = 0;
+    for (int64_t s = start; s < s2; ++s) burgers_step<PT, 1>(y, dt, bc, lds, buf);
+    // Hermite data on [s2, s2+1]
+    auto hermite = [&](double th, double (&out)[PT]) {
+        const double h00 = 2 * th * th * th - 3 * th * th + 1;
+        const double h10 = th * th * th - 2 * th * th + th;
+        const double h01 = -2 * th * th * th + 3 * th * th;
+        const double h11 = th * th * th - th * th;
+#pragma unroll
+        for (int i = 0; i < PT; ++i)
+            out[i] = h00 * y0[i] + h10 * dt * k0[i] + h01 * y[i] + h11 * dt * k1[i];
+    };
+    auto rhs = [&](double (&out)[PT]) {
+        double l[1], r[1];
+        const double* arr[1] = {y};
+        exch<PT, 1>(arr, lds, buf, l, r);
+        burgers_rhs<PT>(y, l[0], r[0], bc, out);
+    };
+#pragma unroll
+    for (int i = 0; i < PT; ++i) y0[i] = y[i];
+    rhs(k0);
+    burgers_step<PT, 1>(y, dt, bc, lds, buf);  // y = state at s2 + 1
+    rhs(k1);
+    hermite(th2, U2);
+    if (s1 == s2) {
+        hermite(th1, U1);
+    } else {
+        for (int64_t s = s2 + 1; s < s1; ++s) burgers_step<PT, 1>(y, dt, bc, lds, buf);
+#pragma unroll
+        for (int i = 0; i < PT; ++i) y0[i] = y[i];
+        rhs(k0);
+        burgers_step<PT, 1>(y, dt, bc, lds, buf);
+        rhs(k1);
+        hermite(th1, U1);
+    }
+    double* w1 = Wout + (size_t)(2 * q) * n;
+    double* w2 = Wout + (size_t)(2 * q + 1) * n;
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+        w1[base + i] = 2.0 * (a2 * U1[i] + a1 * U2[i]);
+        w2[base + i] = 2.0 * (a1 * U1[i] + a2 * U2[i]);
+    }
+}
+
 // Threads per workgroup and points per thread for an n-point march: by
 // default 256 threads (one wave per SIMD, full register budget) with n/256
 // points each; small grids use fewer threads.
@@ -534,6 +612,21 @@ hipError_t launch_rk4_burgers_direct(const double* y0, double* yT, double* ckpt,
     const size_t lds = sizeof(double) * 4 * block;
     PXP_DISPATCH_PT(pt, k_rk4_burgers_direct,
                     <<<1, block, lds, s>>>(y0, yT, ckpt, n, n_t, c, dt, bc))
+    return hipGetLastError();
+}
+
+hipError_t launch_burgers_nodes(const double* ckpt, double* W, int n, int64_t n_t,
+                                int64_t c, int64_t S, double dt, double nu, double L,
+                                int block_hint, hipStream_t s) {
+    int block, pt;
+    if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
+    if (S <= 0 || n_t % S) return hipErrorInvalidValue;
+    const double h = L / n;
+    BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
+    const size_t lds = sizeof(double) * 4 * block;
+    const int Q = (int)(n_t / S);
+    PXP_DISPATCH_PT(pt, k_burgers_nodes,
+                    <<<Q, block, lds, s>>>(ckpt, W, n, n_t, c, S, dt, bc))
     return hipGetLastError();
 }
 

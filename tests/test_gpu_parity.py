@@ -213,3 +213,55 @@ def test_paraexp_workload_n4096(torch, orc):
         assert eq < FP64_GATE and eg < FP64_GATE
     got = run(inst, "serial")
     assert rel(got["grad"], want["grad"]) < 1e-11
+
+
+# ---- Burgers: serial direct with checkpoints, time-varying adjoint --------
+
+def small_burgers(n=256, T=0.5, nt=1024, P=16, nu=0.02, K=8, seed=7, ckpt=64):
+    rng = np.random.default_rng(seed)
+    phases = rng.uniform(0, 2 * math.pi, K)
+    return dict(op="burgers1d", control="ic", nx=n, ny=1, L=2 * math.pi, vx=0.0,
+                vy=0.0, nu=nu, T=T, omega=1.0, beta=1e-3, n_steps=nt, P=P, m=30,
+                ckpt_every=ckpt,
+                basis=workloads.burgers_ic_modes(n, 2 * math.pi, phases),
+                a=0.3 * rng.standard_normal(K) / np.arange(1, K + 1),
+                u_tgt=rng.standard_normal(n), q0=np.zeros(n))
+
+
+@pytest.mark.parametrize("ckpt", [16, 64])
+def test_burgers_serial_matches_oracle_to_rounding(torch, orc, ckpt):
+    inst = small_burgers(ckpt=ckpt)
+    got = run(inst, "serial")
+    want = orc.gradient(inst)
+    say("burgers serial ckpt=%d: qT %.2e lam0 %.2e grad %.2e" % (
+        ckpt, rel(got["qT"], want["qT"]), rel(got["lam"], want["lam0"]),
+        rel(got["grad"], want["grad"])))
+    assert rel(got["qT"], want["qT"]) < 1e-12
+    assert rel(got["lam"], want["lam0"]) < 1e-11
+    assert rel(got["grad"], want["grad"]) < 1e-11
+
+
+# The Magnus macro step is one slice; its fourth-order error needs slices of
+# at most 64 RK4 steps here (P = 4, i.e. 256 steps, measures 9e-7).
+@pytest.mark.parametrize("P", [16, 32, 64])
+def test_burgers_paraexp_small(torch, orc, P):
+    inst = small_burgers(P=P)
+    got = run(inst, "paraexp", krylov="poly")
+    want = orc.gradient(inst)
+    el, eg = rel(got["lam"], want["lam0"]), rel(got["grad"], want["grad"])
+    say("burgers paraexp P=%d: lam0 %.2e grad %.2e st %d est %.1e" % (P, el, eg, got["status"], got["est"]))
+    assert got["status"] == 0
+    assert rel(got["qT"], want["qT"]) < 1e-12  # direct is the same serial march
+    assert el < FP64_GATE and eg < FP64_GATE
+
+
+def test_burgers_workload_n2048(torch, orc):
+    inst = workloads.make("burgers1d_n2048")[0]
+    want = orc.gradient(inst)
+    got = run(inst, "paraexp", krylov="poly")
+    el, eg = rel(got["lam"], want["lam0"]), rel(got["grad"], want["grad"])
+    say("burgers n2048 paraexp: lam0 %.2e grad %.2e st %d est %.1e" % (el, eg, got["status"], got["est"]))
+    assert got["status"] == 0
+    assert el < FP64_GATE and eg < FP64_GATE
+    ser = run(inst, "serial")
+    assert rel(ser["grad"], want["grad"]) < 1e-11
