@@ -156,6 +156,26 @@ pxp_status gradient(const pxp_problem* pb, int32_t batch, const double* ctrl,
                     const double* u_tgt, double* J, double* grad, double* qT,
                     void* ws, size_t ws_bytes, void* stream);
 
+/* The three short steps of the loop on their own, for callers that drive
+ * the direct and adjoint solves separately (e.g. an autograd wrapper):
+ *   pxp_assemble         out = base + sum_k ctrl_k basis_k per instance
+ *                        (forcing pattern or initial state; base nullable)
+ *   pxp_cost             J_i = 1/2 |qT - u_tgt|^2 + beta |ctrl|^2 and
+ *                        lamT = qT - u_tgt (eq. adjFinalTime; lamT nullable)
+ *   pxp_reduce_gradient  grad_k = <basis_k, v> + 2 beta ctrl_k with v the
+ *                        adjoint integral Lambda (forcing, eq. paramupdate)
+ *                        or lambda_0 (initial condition, eq. initupdate)
+ * Device arrays packed as for pxp_gradient; enqueued on `stream`. */
+pxp_status pxp_assemble(const pxp_problem* pb, int32_t batch, const double* ctrl,
+                        const double* basis, const double* base, double* out,
+                        void* stream);
+pxp_status pxp_cost(const pxp_problem* pb, int32_t batch, const double* qT,
+                    const double* u_tgt, const double* ctrl, double* J,
+                    double* lamT, void* stream);
+pxp_status pxp_reduce_gradient(const pxp_problem* pb, int32_t batch,
+                               const double* basis, const double* v,
+                               const double* ctrl, double* grad, void* stream);
+
 /* Synchronises `stream` and returns the device-side status recorded in the
  * workspace by the last calls (PXP_OK, PXP_EKRYLOV_NOCONV, PXP_ENONFINITE);
  * `max_est` (host, nullable) receives the largest relative Krylov error

@@ -30,7 +30,8 @@ STATUS_NAMES = {0: "PXP_OK", 1: "PXP_EINVAL", 2: "PXP_EUNSUPPORTED",
 EXPORTED = ("pxp_workspace_size", "pxp_workspace_init", "paraexp_direct",
             "paraexp_adjoint", "pxp_gradient", "gradient", "pxp_device_status",
             "pxp_device_counters", "pxp_status_str", "pxp_version",
-            "pxp_profile_enable", "pxp_profile_read")
+            "pxp_profile_enable", "pxp_profile_read", "pxp_assemble",
+            "pxp_cost", "pxp_reduce_gradient")
 KCLASS = {"slices": 0, "krylov_direct": 1, "krylov_adjoint": 2,
           "serial_direct": 3, "serial_reverse": 4, "ltv_adjoint": 5,
           "ltv_nodes": 6}
@@ -85,6 +86,9 @@ def load() -> ctypes.CDLL:
         "pxp_device_counters": (st, [vp, sz, vp, ctypes.POINTER(ctypes.c_uint64),
                                      ctypes.POINTER(ctypes.c_uint64)]),
         "pxp_status_str": (ctypes.c_char_p, [st]),
+        "pxp_assemble": (st, [P, i32, vp, vp, vp, vp, vp]),
+        "pxp_cost": (st, [P, i32, vp, vp, vp, vp, vp, vp]),
+        "pxp_reduce_gradient": (st, [P, i32, vp, vp, vp, vp, vp]),
         "pxp_profile_enable": (st, [i32]),
         "pxp_profile_read": (st, [i32, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int32)]),
@@ -194,3 +198,22 @@ def pxp_profile_read(kernel_class) -> tuple[float, int]:
     _check(load().pxp_profile_read(k, ctypes.byref(ms), ctypes.byref(cnt)),
            "pxp_profile_read")
     return ms.value, cnt.value
+
+
+def pxp_assemble(problems, ctrl, basis, base, out, stream=None):
+    arr, n = problems_array(problems)
+    _check(load().pxp_assemble(arr, n, _ptr(ctrl), _ptr(basis), _ptr(base),
+                               _ptr(out), _stream(stream)), "pxp_assemble")
+
+
+def pxp_cost(problems, qT, u_tgt, ctrl, J, lamT, stream=None):
+    arr, n = problems_array(problems)
+    _check(load().pxp_cost(arr, n, _ptr(qT), _ptr(u_tgt), _ptr(ctrl), _ptr(J),
+                           _ptr(lamT), _stream(stream)), "pxp_cost")
+
+
+def pxp_reduce_gradient(problems, basis, v, ctrl, grad, stream=None):
+    arr, n = problems_array(problems)
+    _check(load().pxp_reduce_gradient(arr, n, _ptr(basis), _ptr(v), _ptr(ctrl),
+                                      _ptr(grad), _stream(stream)),
+           "pxp_reduce_gradient")

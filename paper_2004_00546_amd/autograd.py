@@ -1,0 +1,80 @@
+"""torch.autograd.Function over the C ABI.
+
+``ParaexpLoss.apply(a, problem)`` returns J(a) for one instance; its backward
+returns dJ/da.  Forward: ``pxp_assemble`` (controls -> forcing pattern or
+initial state), ``paraexp_direct`` (for Burgers the serial march that keeps
+its checkpoints in the problem's workspace, paper section 3.5),
+``pxp_cost`` (J and lambda_T).  Backward: ``paraexp_adjoint`` from lambda_T
+(Krylov pieces, or the Magnus chain for Burgers) and
+``pxp_reduce_gradient`` (eqs. paramupdate, initupdate); the incoming
+gradient gJ scales the result.  Every step runs in libparaexp.so; torch only
+holds the device buffers.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib, api
+
+
+class Problem:
+    """Device-resident description of one instance and its workspace."""
+
+    def __init__(self, inst: dict, device="cuda:0", **prob_kw):
+        self.inst = inst
+        self.device = torch.device(device)
+        self.p = api.make_problem(inst, **prob_kw)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.basis = torch.tensor(np.asarray(inst["basis"], dtype=np.float64), **f64)
+        n = self.basis.shape[1]
+        self.q0 = torch.tensor(np.asarray(inst.get("q0", np.zeros(n)), dtype=np.float64), **f64)
+        self.u_tgt = torch.tensor(np.asarray(inst["u_tgt"], dtype=np.float64), **f64)
+        self.forcing = inst["control"] == "forcing"
+        nbytes = _lib.pxp_workspace_size([self.p])
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        _lib.pxp_workspace_init(self.ws)
+        self.n = n
+
+
+class ParaexpLoss(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, a: torch.Tensor, prob: Problem):
+        a = a.detach().to(prob.device, torch.float64).contiguous()
+        f64 = dict(dtype=torch.float64, device=prob.device)
+        field = torch.empty(prob.n, **f64)
+        if prob.forcing:
+            _lib.pxp_assemble([prob.p], a, prob.basis, None, field)
+            q0, F = prob.q0, field
+        else:
+            _lib.pxp_assemble([prob.p], a, prob.basis, prob.q0, field)
+            q0, F = field, None
+        qT = torch.empty(prob.n, **f64)
+        _lib.paraexp_direct([prob.p], q0, F, qT, prob.ws)
+        J = torch.empty(1, **f64)
+        lamT = torch.empty(prob.n, **f64)
+        _lib.pxp_cost([prob.p], qT, prob.u_tgt, a, J, lamT)
+        ctx.prob = prob
+        ctx.save_for_backward(a, lamT)
+        return J[0]
+
+    @staticmethod
+    def backward(ctx, gJ):
+        a, lamT = ctx.saved_tensors
+        prob = ctx.prob
+        f64 = dict(dtype=torch.float64, device=prob.device)
+        v = torch.empty(prob.n, **f64)
+        if prob.forcing:
+            _lib.paraexp_adjoint([prob.p], lamT, None, v, prob.ws)
+        else:
+            _lib.paraexp_adjoint([prob.p], lamT, v, None, prob.ws)
+        code, _ = _lib.pxp_device_status(prob.ws)
+        if code != _lib.PXP_OK:
+            raise _lib.PxpError(code, "paraexp_adjoint (device status)")
+        grad = torch.empty_like(a)
+        _lib.pxp_reduce_gradient([prob.p], prob.basis, v, a, grad)
+        return gJ * grad, None
+
+
+def paraexp_loss(a: torch.Tensor, prob: Problem) -> torch.Tensor:
+    return ParaexpLoss.apply(a, prob)

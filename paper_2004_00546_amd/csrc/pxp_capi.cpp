@@ -596,6 +596,66 @@ pxp_status gradient(const pxp_problem* pb, int32_t batch, const double* ctrl,
                         J, grad, qT, nullptr, ws, ws_bytes, stream);
 }
 
+pxp_status pxp_assemble(const pxp_problem* pb, int32_t batch, const double* ctrl,
+                        const double* basis, const double* base, double* out,
+                        void* stream) {
+    pxp_status st = check_all(pb, batch);
+    if (st != PXP_OK) return st;
+    if (batch > 0 && !out) return PXP_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    size_t off = 0, koff = 0, boff = 0;
+    for (int i = 0; i < batch; ++i) {
+        const int n = (int)grid_n(pb[i]), K = pb[i].K;
+        if (K > 0 && (!ctrl || !basis)) return PXP_EINVAL;
+        HIPCHK(launch_combine_basis(ctrl ? ctrl + koff : nullptr,
+                                    basis ? basis + boff : nullptr,
+                                    base ? base + off : nullptr, out + off, K, n, s));
+        off += (size_t)n;
+        koff += (size_t)K;
+        boff += (size_t)K * n;
+    }
+    return PXP_OK;
+}
+
+pxp_status pxp_cost(const pxp_problem* pb, int32_t batch, const double* qT,
+                    const double* u_tgt, const double* ctrl, double* J,
+                    double* lamT, void* stream) {
+    pxp_status st = check_all(pb, batch);
+    if (st != PXP_OK) return st;
+    if (batch > 0 && (!qT || !u_tgt || !J)) return PXP_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    size_t off = 0, koff = 0;
+    for (int i = 0; i < batch; ++i) {
+        const int n = (int)grid_n(pb[i]), K = pb[i].K;
+        if (K > 0 && !ctrl) return PXP_EINVAL;
+        HIPCHK(launch_cost(qT + off, u_tgt + off, ctrl ? ctrl + koff : nullptr, n,
+                           ctrl ? K : 0, pb[i].beta, lamT ? lamT + off : nullptr,
+                           J + i, s));
+        off += (size_t)n;
+        koff += (size_t)K;
+    }
+    return PXP_OK;
+}
+
+pxp_status pxp_reduce_gradient(const pxp_problem* pb, int32_t batch,
+                               const double* basis, const double* v,
+                               const double* ctrl, double* grad, void* stream) {
+    pxp_status st = check_all(pb, batch);
+    if (st != PXP_OK) return st;
+    if (batch > 0 && (!basis || !v || !ctrl || !grad)) return PXP_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    size_t off = 0, koff = 0, boff = 0;
+    for (int i = 0; i < batch; ++i) {
+        const int n = (int)grid_n(pb[i]), K = pb[i].K;
+        HIPCHK(launch_grad(basis + boff, v + off, ctrl + koff, K, n, pb[i].beta,
+                           grad + koff, s));
+        off += (size_t)n;
+        koff += (size_t)K;
+        boff += (size_t)K * n;
+    }
+    return PXP_OK;
+}
+
 pxp_status pxp_device_status(void* ws, size_t ws_bytes, void* stream,
                              double* max_est) {
     if (!ws || ws_bytes < sizeof(DevStatus)) return PXP_EWORKSPACE;

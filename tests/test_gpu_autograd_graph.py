@@ -1,0 +1,86 @@
+"""torch.autograd.Function over the C ABI, and hipGraph capture of the
+whole gradient call."""
+import numpy as np
+import pytest
+
+from conftest import rel
+from paper_2004_00546_amd import _lib, api, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    _lib.load()
+    return _t
+
+
+@pytest.mark.parametrize("wl,krylov", [("advdiff1d_n128", "poly"),
+                                       ("advdiff1d_n128", "shift_invert"),
+                                       ("burgers1d_n2048", "poly")])
+def test_autograd_matches_oracle(torch, orc, wl, krylov):
+    from paper_2004_00546_amd.autograd import Problem, paraexp_loss
+    inst = workloads.make(wl)[0]
+    prob = Problem(inst, krylov=krylov, tol=1e-9 if krylov == "shift_invert" else 1e-10)
+    a = torch.tensor(inst["a"], dtype=torch.float64, device="cuda:0", requires_grad=True)
+    J = paraexp_loss(a, prob)
+    (3.0 * J).backward()
+    want = orc.gradient(inst)
+    print("autograd %s/%s: J %.2e grad %.2e" % (wl, krylov, abs(J.item() - want["J"]) / want["J"],
+                                                rel(a.grad.cpu().numpy() / 3.0, want["grad"])),
+          flush=True)
+    assert abs(J.item() - want["J"]) < 1e-8 * abs(want["J"])
+    assert rel(a.grad.cpu().numpy() / 3.0, want["grad"]) < 1e-8
+
+
+def test_autograd_gradient_vs_central_differences(torch):
+    """J is quadratic in a for the linear problem: central differences of
+    the GPU forward are exact up to rounding and the Krylov tolerance."""
+    from paper_2004_00546_amd.autograd import Problem, paraexp_loss
+    inst = workloads.make("advdiff1d_n128")[0]
+    prob = Problem(inst, krylov="poly")
+    a0 = torch.tensor(inst["a"], dtype=torch.float64, device="cuda:0", requires_grad=True)
+    paraexp_loss(a0, prob).backward()
+    g = a0.grad.cpu().numpy()
+    for d in inst["fd_dirs"][:4]:
+        dd = torch.tensor(d, dtype=torch.float64, device="cuda:0")
+        eps = 1e-2
+        jp = paraexp_loss(a0.detach() + eps * dd, prob).item()
+        jm = paraexp_loss(a0.detach() - eps * dd, prob).item()
+        fd = (jp - jm) / (2 * eps)
+        assert abs(fd - g @ d) < 1e-7 * (abs(fd) + np.linalg.norm(g))
+
+
+@pytest.mark.parametrize("wl,krylov", [("advdiff1d_n128", "shift_invert"),
+                                       ("burgers1d_n2048", "poly")])
+def test_graph_replay_equals_eager(torch, wl, krylov):
+    inst = workloads.make(wl)[0]
+    r = api.GradientRunner([inst], krylov=krylov, tol=1e-9)
+    r.run()
+    eager = r.results()[0]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        r.run()  # warm up on the side stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        r.run()
+    for rep in range(3):
+        r.J.zero_()
+        r.grad.zero_()
+        r.qT.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = r.results()[0]
+        assert np.array_equal(got["grad"], eager["grad"]), rep
+        assert np.array_equal(got["qT"], eager["qT"]), rep
+        assert got["J"] == eager["J"]
+        # eager work between replays
+        r.run()
+        torch.cuda.synchronize()
