@@ -78,7 +78,7 @@ pxp_status validate(const pxp_problem& p) {
     if (p.krylov != PXP_KRYLOV_POLY && p.krylov != PXP_KRYLOV_SHIFT_INVERT)
         return PXP_EINVAL;
     if (p.sched != PXP_SCHED_CLASSIC && p.sched != PXP_SCHED_CHAIN) return PXP_EINVAL;
-    if (p.prec != PXP_FP64) return PXP_EUNSUPPORTED;
+    if (p.prec != PXP_FP64 && p.prec != PXP_FP32_BULK) return PXP_EINVAL;
     if (p.op == PXP_OP_ADVDIFF1D) {
         if (p.ny != 1) return PXP_EINVAL;
         if (p.m < 1 || p.m > M_MAX_1D) return PXP_EUNSUPPORTED;
@@ -225,6 +225,7 @@ struct Ctx {
     double* at(size_t off) const { return reinterpret_cast<double*>(base + off); }
     int n() const { return (int)grid_n(p); }
     double dt() const { return p.T / (double)p.n_steps; }
+    int fp32() const { return p.prec == PXP_FP32_BULK ? 1 : 0; }
 };
 
 KrylovArgs kargs(const Ctx& c, Tri op) {
@@ -237,6 +238,7 @@ KrylovArgs kargs(const Ctx& c, Tri op) {
     a.op = op;
     a.basis = c.at(c.L.basis);
     a.status = c.st;
+    a.fp32 = c.fp32();
     return a;
 }
 
@@ -255,7 +257,7 @@ pxp_status direct_lin1d(const Ctx& c, const double* q0, const double* F,
     if (method == PXP_METHOD_SERIAL) {
         ProfScope ps(PXP_K_SERIAL_DIRECT, c.s);
         HIPCHK(launch_rk4_lin1d(F, nullptr, q0, qT, n, 1, c.p.n_steps, c.dt(),
-                                c.p.omega, A, c.p.block, c.s));
+                                c.p.omega, A, c.p.block, c.fp32(), c.s));
         return PXP_OK;
     }
     const int P = c.p.P;
@@ -265,7 +267,7 @@ pxp_status direct_lin1d(const Ctx& c, const double* q0, const double* F,
     {
         ProfScope ps(PXP_K_SLICES, c.s);
         HIPCHK(launch_rk4_lin1d(F, g0, nullptr, slices, n, P, n_s, c.dt(),
-                                c.p.omega, A, c.p.block, c.s));
+                                c.p.omega, A, c.p.block, c.fp32(), c.s));
     }
     if (P == 1) {
         HIPCHK(launch_recombine(q0, slices, nullptr, 0, n, qT, c.st, c.s));
@@ -309,7 +311,7 @@ pxp_status adjoint_lin1d(const Ctx& c, const double* lamT, double* lam0,
     if (method == PXP_METHOD_SERIAL) {
         ProfScope ps(PXP_K_SERIAL_REVERSE, c.s);
         HIPCHK(launch_rk4_rev_lin1d(lamT, lam0, Lam, n, c.p.n_steps, c.dt(),
-                                    c.p.omega, AT, c.p.block, c.s));
+                                    c.p.omega, AT, c.p.block, c.fp32(), c.s));
         return PXP_OK;
     }
     // The terminal-cost adjoint is one homogeneous piece from q^dagger(T)
@@ -335,7 +337,7 @@ pxp_status direct_burgers(const Ctx& c, const double* q0, double* qT) {
     ProfScope ps(PXP_K_SERIAL_DIRECT, c.s);
     HIPCHK(launch_rk4_burgers_direct(q0, qT, c.at(c.L.ckpt), c.n(), c.p.n_steps,
                                      c.p.ckpt_every, c.dt(), c.p.nu, c.p.L,
-                                     c.p.block, c.s));
+                                     c.p.block, c.fp32(), c.s));
     return PXP_OK;
 }
 
@@ -345,7 +347,7 @@ pxp_status adjoint_burgers(const Ctx& c, const double* lamT, double* lam0,
         ProfScope ps(PXP_K_SERIAL_REVERSE, c.s);
         HIPCHK(launch_rk4_burgers_reverse(c.at(c.L.ckpt), lamT, lam0, c.at(c.L.seg),
                                           c.n(), c.p.n_steps, c.p.ckpt_every, c.dt(),
-                                          c.p.nu, c.p.L, c.p.block, c.s));
+                                          c.p.nu, c.p.L, c.p.block, c.fp32(), c.s));
         return PXP_OK;
     }
     // The adjoint of the serial direct march is linear and time-varying
@@ -360,7 +362,7 @@ pxp_status adjoint_burgers(const Ctx& c, const double* lamT, double* lam0,
         ProfScope ps(PXP_K_LTV_NODES, c.s);
         HIPCHK(launch_burgers_nodes(c.at(c.L.ckpt), c.at(c.L.nodes), c.n(),
                                     c.p.n_steps, c.p.ckpt_every, S, c.dt(), c.p.nu,
-                                    c.p.L, c.p.block, c.s));
+                                    c.p.L, c.p.block, c.fp32(), c.s));
     }
     KrylovArgs a = kargs(c, Tri{0.0, 0.0, 0.0});
     a.si = 0;

@@ -25,24 +25,28 @@ constexpr unsigned int ST_NOCONV = 1u;
 constexpr unsigned int ST_NONFINITE = 2u;
 
 // ---- RK4 marches (1D, one workgroup per slice) ---------------------------
+// fp32 != 0: stencil and RK arithmetic in FP32 with compensated (Kahan)
+// accumulation of the state and adjoint sums; inputs, outputs and
+// checkpoints stay FP64 (an FP32 compensated pair is exact in FP64).
 // Slices p = 0..P-1 of a linear 1D problem, each from zero (or from y0 when
 // given, P must then be 1) over n_s steps starting at global step p*n_s:
 //   y' = A y + sin(omega t) F + g0.
 hipError_t launch_rk4_lin1d(const double* F, const double* g0, const double* y0,
                             double* out, int n, int P, int64_t n_s, double dt,
-                            double omega, Tri A, int block, hipStream_t s);
+                            double omega, Tri A, int block, int fp32, hipStream_t s);
 
 // Reverse sweep of the exact discrete adjoint of the linear RK4 march:
 // from lamT to lam0 and Lambda = sum s(t_stage) kbar_stage.
 hipError_t launch_rk4_rev_lin1d(const double* lamT, double* lam0,
                                 double* Lambda, int n, int64_t n_t, double dt,
-                                double omega, Tri AT, int block, hipStream_t s);
+                                double omega, Tri AT, int block, int fp32,
+                                hipStream_t s);
 
 // Burgers 1D direct march with checkpoints every c steps (ckpt[k] = state at
 // step k*c, k = 0..n_t/c).
 hipError_t launch_rk4_burgers_direct(const double* y0, double* yT, double* ckpt,
                                      int n, int64_t n_t, int64_t c, double dt,
-                                     double nu, double L, int block,
+                                     double nu, double L, int block, int fp32,
                                      hipStream_t s);
 
 // Burgers reverse sweep, serial, over segments between checkpoints: each
@@ -50,7 +54,7 @@ hipError_t launch_rk4_burgers_direct(const double* y0, double* yT, double* ckpt,
 hipError_t launch_rk4_burgers_reverse(const double* ckpt, const double* lamT,
                                       double* lam0, double* seg, int n,
                                       int64_t n_t, int64_t c, double dt,
-                                      double nu, double L, int block,
+                                      double nu, double L, int block, int fp32,
                                       hipStream_t s);
 
 // Effective states of the two commutator-free Magnus factors of each macro
@@ -58,7 +62,7 @@ hipError_t launch_rk4_burgers_reverse(const double* ckpt, const double* lamT,
 // checkpoints (every c steps) in parallel over macro steps.
 hipError_t launch_burgers_nodes(const double* ckpt, double* W, int n, int64_t n_t,
                                 int64_t c, int64_t S, double dt, double nu, double L,
-                                int block, hipStream_t s);
+                                int block, int fp32, hipStream_t s);
 
 // ---- Krylov exponential pieces (1D tridiagonal operator) -------------------
 // KM_LTV: chain of 2*npieces exponentials exp(tau J(W_e)^T) with the Burgers
@@ -79,6 +83,7 @@ struct KrylovArgs {
     double tol;          // relative tolerance
     double gamma_frac;   // shift-and-invert shift = gamma_frac * time
     Tri op;
+    int fp32;            // operator stencil in FP32 (polynomial flavour)
     const double* wop;   // KM_LTV: effective states [2*npieces][n]
     double inv2h, nuh2;  // KM_LTV: 1/(2h), nu/h^2
     double* basis;       // [gridDim][m+1][n] workspace

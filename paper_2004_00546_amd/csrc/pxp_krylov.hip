@@ -140,8 +140,15 @@ struct Ctx {
                     const int im = i == 0 ? n - 1 : i - 1, ip = i == n - 1 ? 0 : i + 1;
                     const double xm = b0[im], xp = b0[ip], x0 = b0[i];
                     const double Wm = Wcur[im], Wp = Wcur[ip];
-                    z[r * VW + v] = a.nuh2 * ((xp + xm) - 2.0 * x0)
-                                    + a.inv2h * ((Wp * xp - Wm * xm) - (Wp - Wm) * x0);
+                    if (a.fp32) {
+                        const float fxm = (float)xm, fxp = (float)xp, fx0 = (float)x0;
+                        const float fWm = (float)Wm, fWp = (float)Wp;
+                        z[r * VW + v] = (double)((float)a.nuh2 * ((fxp + fxm) - 2.0f * fx0)
+                                        + (float)a.inv2h * ((fWp * fxp - fWm * fxm) - (fWp - fWm) * fx0));
+                    } else {
+                        z[r * VW + v] = a.nuh2 * ((xp + xm) - 2.0 * x0)
+                                        + a.inv2h * ((Wp * xp - Wm * xm) - (Wp - Wm) * x0);
+                    }
                 }
             }
         } else if (!SI) {
@@ -154,7 +161,13 @@ struct Ctx {
                     const double xm = b0[i == 0 ? n - 1 : i - 1];
                     const double xp = b0[i == n - 1 ? 0 : i + 1];
                     const double x0 = b0[i];
-                    z[r * VW + v] = op.cs * ((xp + xm) - 2.0 * x0) + op.cdf * (xp - xm) + op.cc * x0;
+                    if (a.fp32) {
+                        const float fxm = (float)xm, fxp = (float)xp, fx0 = (float)x0;
+                        z[r * VW + v] = (double)((float)op.cs * ((fxp + fxm) - 2.0f * fx0)
+                                        + (float)op.cdf * (fxp - fxm) + (float)op.cc * fx0);
+                    } else {
+                        z[r * VW + v] = op.cs * ((xp + xm) - 2.0 * x0) + op.cdf * (xp - xm) + op.cc * x0;
+                    }
                 }
             }
         } else {

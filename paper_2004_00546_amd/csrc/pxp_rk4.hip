@@ -27,15 +27,14 @@ constexpr int max_block() {
 }
 
 // Exchange the chunk edges of NA arrays with one barrier.  edge is LDS of
-// 2 buffers of NB x 2 x B doubles (NB >= NA: the same buffer stride must be
+// 2 buffers of NB x 2 x B values (NB >= NA: the same buffer stride must be
 // used by every exchange of a kernel so the two buffers never overlap).
-template <int PT, int NA, int NB = NA>
-__device__ __forceinline__ void exch(const double* const (&arrs)[NA], double* edge,
-                                     int& buf, double (&left)[NA],
-                                     double (&right)[NA]) {
+template <int PT, int NA, int NB = NA, typename R>
+__device__ __forceinline__ void exch(const R* const (&arrs)[NA], R* edge, int& buf,
+                                     R (&left)[NA], R (&right)[NA]) {
     static_assert(NB >= NA, "buffer stride");
     const int t = threadIdx.x, B = blockDim.x;
-    double* e = edge + buf * 2 * NB * B;
+    R* e = edge + buf * 2 * NB * B;
 #pragma unroll
     for (int a = 0; a < NA; ++a) {
         e[(2 * a) * B + t] = arrs[a][0];
@@ -52,6 +51,32 @@ __device__ __forceinline__ void exch(const double* const (&arrs)[NA], double* ed
     buf ^= 1;
 }
 
+// Compensated accumulation s += inc (Kahan) in FP32; plain in FP64.
+template <typename R>
+__device__ __forceinline__ void kadd(R& s, R& c, R inc) {
+    if constexpr (sizeof(R) == 4) {
+        const R yk = inc - c;
+        const R t = s + yk;
+        c = (t - s) - yk;
+        s = t;
+    } else {
+        (void)c;
+        s += inc;
+    }
+}
+
+// value of a compensated pair in FP64
+template <typename R>
+__device__ __forceinline__ double hilo(R s, R c) {
+    return (double)s - (double)c;
+}
+// split an FP64 value into a compensated pair (exact for FP32 pairs)
+template <typename R>
+__device__ __forceinline__ void split_hilo(double v, R& s, R& c) {
+    s = (R)v;
+    c = (sizeof(R) == 4) ? (R)((double)s - v) : (R)0;
+}
+
 // Coefficients of a tridiagonal operator split for accuracy:
 // lo x_{i-1} + d x_i + up x_{i+1} = cs ((x_{i+1} + x_{i-1}) - 2 x_i)
 //                                  + cdf (x_{i+1} - x_{i-1}) + cc x_i
@@ -66,47 +91,49 @@ __host__ __device__ inline TriSplit split(Tri a) {
     return s;
 }
 
-template <int PT>
-__device__ __forceinline__ void tri_rhs(const double (&Y)[PT], double l, double r,
-                                        const TriSplit& A, double (&k)[PT]) {
+template <int PT, typename R>
+__device__ __forceinline__ void tri_rhs(const R (&Y)[PT], R l, R r, R cs, R cdf,
+                                        R cc, R (&k)[PT]) {
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
-        const double ym = (q == 0) ? l : Y[q - 1];
-        const double yp = (q == PT - 1) ? r : Y[q + 1];
-        k[q] = A.cs * ((yp + ym) - 2.0 * Y[q]) + A.cdf * (yp - ym) + A.cc * Y[q];
+        const R ym = (q == 0) ? l : Y[q - 1];
+        const R yp = (q == PT - 1) ? r : Y[q + 1];
+        k[q] = cs * ((yp + ym) - (R)2 * Y[q]) + cdf * (yp - ym) + cc * Y[q];
     }
 }
 
-template <int PT>
+template <int PT, typename R>
 __global__ void __launch_bounds__(max_block<PT>())
 k_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
             const double* __restrict__ y0, double* __restrict__ out, int n,
             int64_t n_s, double dt, double omega, TriSplit A) {
-    extern __shared__ double lds[];
+    extern __shared__ double lds_d[];
+    R* lds = reinterpret_cast<R*>(lds_d);
     const int t = threadIdx.x;
     const int p = blockIdx.x;
     const int base = t * PT;
-    double f[PT], g[PT], y[PT], acc[PT], Y[PT], k[PT];
+    const R cs = (R)A.cs, cdf = (R)A.cdf, cc = (R)A.cc;
+    R f[PT], g[PT], y[PT], yc[PT], acc[PT], Y[PT], k[PT];
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
-        f[q] = F ? F[base + q] : 0.0;
-        g[q] = g0 ? g0[base + q] : 0.0;
-        y[q] = y0 ? y0[base + q] : 0.0;
+        f[q] = F ? (R)F[base + q] : (R)0;
+        g[q] = g0 ? (R)g0[base + q] : (R)0;
+        split_hilo<R>(y0 ? y0[base + q] : 0.0, y[q], yc[q]);
     }
     int buf = 0;
     const int64_t step0 = (int64_t)p * n_s;
-    const double h2 = 0.5 * dt, h6 = dt / 6.0;
+    const R h2 = (R)(0.5 * dt), h6 = (R)(dt / 6.0), h1 = (R)dt;
     for (int64_t s = 0; s < n_s; ++s) {
         const double tn = (double)(step0 + s) * dt;
-        const double s1 = sin(omega * tn);
-        const double s2 = sin(omega * (tn + 0.5 * dt));
-        const double s4 = sin(omega * (tn + dt));
-        double l[1], r[1];
+        const R s1 = (R)sin(omega * tn);
+        const R s2 = (R)sin(omega * (tn + 0.5 * dt));
+        const R s4 = (R)sin(omega * (tn + dt));
+        R l[1], r[1];
         {
-            const double* arr[1] = {y};
+            const R* arr[1] = {y};
             exch<PT, 1>(arr, lds, buf, l, r);
         }
-        tri_rhs<PT>(y, l[0], r[0], A, k);
+        tri_rhs<PT, R>(y, l[0], r[0], cs, cdf, cc, k);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
             k[q] += s1 * f[q] + g[q];
@@ -114,122 +141,125 @@ k_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
             Y[q] = y[q] + h2 * k[q];
         }
         {
-            const double* arr[1] = {Y};
+            const R* arr[1] = {Y};
             exch<PT, 1>(arr, lds, buf, l, r);
         }
-        tri_rhs<PT>(Y, l[0], r[0], A, k);
+        tri_rhs<PT, R>(Y, l[0], r[0], cs, cdf, cc, k);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
             k[q] += s2 * f[q] + g[q];
-            acc[q] += 2.0 * k[q];
+            acc[q] += (R)2 * k[q];
             Y[q] = y[q] + h2 * k[q];
         }
         {
-            const double* arr[1] = {Y};
+            const R* arr[1] = {Y};
             exch<PT, 1>(arr, lds, buf, l, r);
         }
-        tri_rhs<PT>(Y, l[0], r[0], A, k);
+        tri_rhs<PT, R>(Y, l[0], r[0], cs, cdf, cc, k);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
             k[q] += s2 * f[q] + g[q];
-            acc[q] += 2.0 * k[q];
-            Y[q] = y[q] + dt * k[q];
+            acc[q] += (R)2 * k[q];
+            Y[q] = y[q] + h1 * k[q];
         }
         {
-            const double* arr[1] = {Y};
+            const R* arr[1] = {Y};
             exch<PT, 1>(arr, lds, buf, l, r);
         }
-        tri_rhs<PT>(Y, l[0], r[0], A, k);
+        tri_rhs<PT, R>(Y, l[0], r[0], cs, cdf, cc, k);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
             k[q] += s4 * f[q] + g[q];
-            y[q] = y[q] + h6 * (acc[q] + k[q]);
+            kadd<R>(y[q], yc[q], h6 * (acc[q] + k[q]));
         }
     }
     double* o = out + (size_t)p * n;
 #pragma unroll
-    for (int q = 0; q < PT; ++q) o[base + q] = y[q];
+    for (int q = 0; q < PT; ++q) o[base + q] = hilo<R>(y[q], yc[q]);
 }
 
 // Reverse sweep: y_{s+1} = y_s + dt sum_i b_i k_i with k_i = A Y_i + ...
 // gives kbar_i = dt b_i lam (+ the chain through later stages), Ybar_i =
-// A^T kbar_i, lam_s = lam_{s+1} + sum_i Ybar_i.
-template <int PT>
+// A^T kbar_i, lam_s = lam_{s+1} + sum_i Ybar_i, Lambda += s(t_i) kbar_i.
+template <int PT, typename R>
 __global__ void __launch_bounds__(max_block<PT>())
 k_rk4_rev_lin1d(const double* __restrict__ lamT, double* __restrict__ lam0,
                 double* __restrict__ Lambda, int n, int64_t n_t, double dt,
                 double omega, TriSplit AT) {
-    extern __shared__ double lds[];
+    extern __shared__ double lds_d[];
+    R* lds = reinterpret_cast<R*>(lds_d);
     const int t = threadIdx.x;
     const int base = t * PT;
-    double lam[PT], Lam[PT], kb[PT], Yb[PT], nl[PT];
+    const R cs = (R)AT.cs, cdf = (R)AT.cdf, cc = (R)AT.cc;
+    R lam[PT], lamc[PT], Lam[PT], Lamc[PT], kb[PT], Yb[PT], nl[PT];
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
-        lam[q] = lamT[base + q];
-        Lam[q] = 0.0;
+        split_hilo<R>(lamT[base + q], lam[q], lamc[q]);
+        Lam[q] = (R)0;
+        Lamc[q] = (R)0;
     }
     int buf = 0;
-    const double d6 = dt / 6.0, d3 = dt / 3.0, d2 = 0.5 * dt;
+    const R d6 = (R)(dt / 6.0), d3 = (R)(dt / 3.0), d2 = (R)(0.5 * dt), d1 = (R)dt;
     for (int64_t s = n_t - 1; s >= 0; --s) {
         const double tn = (double)s * dt;
-        const double s1 = sin(omega * tn);
-        const double s2 = sin(omega * (tn + 0.5 * dt));
-        const double s4 = sin(omega * (tn + dt));
-        double l[1], r[1];
+        const R s1 = (R)sin(omega * tn);
+        const R s2 = (R)sin(omega * (tn + 0.5 * dt));
+        const R s4 = (R)sin(omega * (tn + dt));
+        R l[1], r[1];
         // stage 4
 #pragma unroll
         for (int q = 0; q < PT; ++q) kb[q] = d6 * lam[q];
         {
-            const double* arr[1] = {kb};
+            const R* arr[1] = {kb};
             exch<PT, 1>(arr, lds, buf, l, r);
         }
-        tri_rhs<PT>(kb, l[0], r[0], AT, Yb);
+        tri_rhs<PT, R>(kb, l[0], r[0], cs, cdf, cc, Yb);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
-            nl[q] = lam[q] + Yb[q];
-            Lam[q] += s4 * kb[q];
-            kb[q] = d3 * lam[q] + dt * Yb[q];
+            nl[q] = Yb[q];
+            kadd<R>(Lam[q], Lamc[q], s4 * kb[q]);
+            kb[q] = d3 * lam[q] + d1 * Yb[q];
         }
         // stage 3
         {
-            const double* arr[1] = {kb};
+            const R* arr[1] = {kb};
             exch<PT, 1>(arr, lds, buf, l, r);
         }
-        tri_rhs<PT>(kb, l[0], r[0], AT, Yb);
+        tri_rhs<PT, R>(kb, l[0], r[0], cs, cdf, cc, Yb);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
             nl[q] += Yb[q];
-            Lam[q] += s2 * kb[q];
+            kadd<R>(Lam[q], Lamc[q], s2 * kb[q]);
             kb[q] = d3 * lam[q] + d2 * Yb[q];
         }
         // stage 2
         {
-            const double* arr[1] = {kb};
+            const R* arr[1] = {kb};
             exch<PT, 1>(arr, lds, buf, l, r);
         }
-        tri_rhs<PT>(kb, l[0], r[0], AT, Yb);
+        tri_rhs<PT, R>(kb, l[0], r[0], cs, cdf, cc, Yb);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
             nl[q] += Yb[q];
-            Lam[q] += s2 * kb[q];
+            kadd<R>(Lam[q], Lamc[q], s2 * kb[q]);
             kb[q] = d6 * lam[q] + d2 * Yb[q];
         }
         // stage 1
         {
-            const double* arr[1] = {kb};
+            const R* arr[1] = {kb};
             exch<PT, 1>(arr, lds, buf, l, r);
         }
-        tri_rhs<PT>(kb, l[0], r[0], AT, Yb);
+        tri_rhs<PT, R>(kb, l[0], r[0], cs, cdf, cc, Yb);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
-            Lam[q] += s1 * kb[q];
-            lam[q] = nl[q] + Yb[q];
+            kadd<R>(Lam[q], Lamc[q], s1 * kb[q]);
+            kadd<R>(lam[q], lamc[q], nl[q] + Yb[q]);
         }
     }
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
-        if (lam0) lam0[base + q] = lam[q];
-        if (Lambda) Lambda[base + q] = Lam[q];
+        if (lam0) lam0[base + q] = hilo<R>(lam[q], lamc[q]);
+        if (Lambda) Lambda[base + q] = hilo<R>(Lam[q], Lamc[q]);
     }
 }
 
@@ -239,208 +269,210 @@ struct BurgersC {
     double inv2h, nuh2;
 };
 
-template <int PT>
-__device__ __forceinline__ void burgers_rhs(const double (&Y)[PT], double l,
-                                            double r, const BurgersC& c,
-                                            double (&k)[PT]) {
+template <int PT, typename R>
+__device__ __forceinline__ void burgers_rhs(const R (&Y)[PT], R l, R r, R inv2h,
+                                            R nuh2, R (&k)[PT]) {
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
-        const double ym = (q == 0) ? l : Y[q - 1];
-        const double yp = (q == PT - 1) ? r : Y[q + 1];
-        k[q] = -Y[q] * ((yp - ym) * c.inv2h) + c.nuh2 * ((yp + ym) - 2.0 * Y[q]);
+        const R ym = (q == 0) ? l : Y[q - 1];
+        const R yp = (q == PT - 1) ? r : Y[q + 1];
+        k[q] = -Y[q] * ((yp - ym) * inv2h) + nuh2 * ((yp + ym) - (R)2 * Y[q]);
     }
 }
 
-// One Burgers RK4 step in registers (stages exchanged through LDS).
-template <int PT, int NB>
-__device__ __forceinline__ void burgers_step(double (&y)[PT], double dt,
-                                             const BurgersC& c, double* lds,
-                                             int& buf) {
-    double acc[PT], Y[PT], k[PT], l[1], r[1];
+// One Burgers RK4 step in registers (stages exchanged through LDS); the
+// state is the compensated pair (y, yc).
+template <int PT, int NB, typename R>
+__device__ __forceinline__ void burgers_step(R (&y)[PT], R (&yc)[PT], R dt,
+                                             R inv2h, R nuh2, R* lds, int& buf) {
+    R acc[PT], Y[PT], k[PT], l[1], r[1];
     {
-        const double* arr[1] = {y};
+        const R* arr[1] = {y};
         exch<PT, 1, NB>(arr, lds, buf, l, r);
     }
-    burgers_rhs<PT>(y, l[0], r[0], c, k);
+    burgers_rhs<PT, R>(y, l[0], r[0], inv2h, nuh2, k);
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
         acc[q] = k[q];
-        Y[q] = y[q] + 0.5 * dt * k[q];
+        Y[q] = y[q] + (R)0.5 * dt * k[q];
     }
     {
-        const double* arr[1] = {Y};
+        const R* arr[1] = {Y};
         exch<PT, 1, NB>(arr, lds, buf, l, r);
     }
-    burgers_rhs<PT>(Y, l[0], r[0], c, k);
+    burgers_rhs<PT, R>(Y, l[0], r[0], inv2h, nuh2, k);
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
-        acc[q] += 2.0 * k[q];
-        Y[q] = y[q] + 0.5 * dt * k[q];
+        acc[q] += (R)2 * k[q];
+        Y[q] = y[q] + (R)0.5 * dt * k[q];
     }
     {
-        const double* arr[1] = {Y};
+        const R* arr[1] = {Y};
         exch<PT, 1, NB>(arr, lds, buf, l, r);
     }
-    burgers_rhs<PT>(Y, l[0], r[0], c, k);
+    burgers_rhs<PT, R>(Y, l[0], r[0], inv2h, nuh2, k);
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
-        acc[q] += 2.0 * k[q];
+        acc[q] += (R)2 * k[q];
         Y[q] = y[q] + dt * k[q];
     }
     {
-        const double* arr[1] = {Y};
+        const R* arr[1] = {Y};
         exch<PT, 1, NB>(arr, lds, buf, l, r);
     }
-    burgers_rhs<PT>(Y, l[0], r[0], c, k);
+    burgers_rhs<PT, R>(Y, l[0], r[0], inv2h, nuh2, k);
 #pragma unroll
-    for (int q = 0; q < PT; ++q) y[q] = y[q] + (dt / 6.0) * (acc[q] + k[q]);
+    for (int q = 0; q < PT; ++q) kadd<R>(y[q], yc[q], (dt / (R)6) * (acc[q] + k[q]));
 }
 
-template <int PT>
+template <int PT, typename R>
 __global__ void __launch_bounds__(max_block<PT>())
 k_rk4_burgers_direct(const double* __restrict__ y0, double* __restrict__ yT,
                      double* __restrict__ ckpt, int n, int64_t n_t, int64_t c,
                      double dt, BurgersC bc) {
-    extern __shared__ double lds[];
+    extern __shared__ double lds_d[];
+    R* lds = reinterpret_cast<R*>(lds_d);
     const int base = threadIdx.x * PT;
-    double y[PT];
+    const R inv2h = (R)bc.inv2h, nuh2 = (R)bc.nuh2, rdt = (R)dt;
+    R y[PT], yc[PT];
 #pragma unroll
-    for (int q = 0; q < PT; ++q) y[q] = y0[base + q];
+    for (int q = 0; q < PT; ++q) split_hilo<R>(y0[base + q], y[q], yc[q]);
     if (ckpt) {
 #pragma unroll
-        for (int q = 0; q < PT; ++q) ckpt[base + q] = y[q];
+        for (int q = 0; q < PT; ++q) ckpt[base + q] = hilo<R>(y[q], yc[q]);
     }
     int buf = 0;
     for (int64_t s = 0; s < n_t; ++s) {
-        burgers_step<PT, 1>(y, dt, bc, lds, buf);
+        burgers_step<PT, 1, R>(y, yc, rdt, inv2h, nuh2, lds, buf);
         if (ckpt && ((s + 1) % c) == 0) {
             double* o = ckpt + (size_t)((s + 1) / c) * n;
 #pragma unroll
-            for (int q = 0; q < PT; ++q) o[base + q] = y[q];
+            for (int q = 0; q < PT; ++q) o[base + q] = hilo<R>(y[q], yc[q]);
         }
     }
 #pragma unroll
-    for (int q = 0; q < PT; ++q) yT[base + q] = y[q];
+    for (int q = 0; q < PT; ++q) yT[base + q] = hilo<R>(y[q], yc[q]);
 }
 
 // (J(U)^T v)_i = ((U v)_{i+1} - (U v)_{i-1})/(2h) - (U_{i+1} - U_{i-1}) v_i/(2h)
 //               + nu lap(v)_i
-template <int PT>
-__device__ __forceinline__ void burgers_jt(const double (&U)[PT], double Ul,
-                                           double Ur, const double (&v)[PT],
-                                           const BurgersC& c, double* lds,
-                                           int& buf, double (&out)[PT]) {
-    double uv[PT];
+template <int PT, typename R>
+__device__ __forceinline__ void burgers_jt(const R (&U)[PT], R Ul, R Ur,
+                                           const R (&v)[PT], R inv2h, R nuh2,
+                                           R* lds, int& buf, R (&out)[PT]) {
+    R uv[PT];
 #pragma unroll
     for (int q = 0; q < PT; ++q) uv[q] = U[q] * v[q];
-    double l[2], r[2];
+    R l[2], r[2];
     {
-        const double* arr[2] = {v, uv};
+        const R* arr[2] = {v, uv};
         exch<PT, 2>(arr, lds, buf, l, r);
     }
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
-        const double vm = (q == 0) ? l[0] : v[q - 1];
-        const double vp = (q == PT - 1) ? r[0] : v[q + 1];
-        const double wm = (q == 0) ? l[1] : uv[q - 1];
-        const double wp = (q == PT - 1) ? r[1] : uv[q + 1];
-        const double Um = (q == 0) ? Ul : U[q - 1];
-        const double Up = (q == PT - 1) ? Ur : U[q + 1];
-        out[q] = (wp - wm) * c.inv2h - (Up - Um) * c.inv2h * v[q]
-                 + c.nuh2 * ((vp + vm) - 2.0 * v[q]);
+        const R vm = (q == 0) ? l[0] : v[q - 1];
+        const R vp = (q == PT - 1) ? r[0] : v[q + 1];
+        const R wm = (q == 0) ? l[1] : uv[q - 1];
+        const R wp = (q == PT - 1) ? r[1] : uv[q + 1];
+        const R Um = (q == 0) ? Ul : U[q - 1];
+        const R Up = (q == PT - 1) ? Ur : U[q + 1];
+        out[q] = (wp - wm) * inv2h - (Up - Um) * inv2h * v[q] + nuh2 * ((vp + vm) - (R)2 * v[q]);
     }
 }
 
-template <int PT>
+template <int PT, typename R>
 __global__ void __launch_bounds__(max_block<PT>())
 k_rk4_burgers_reverse(const double* __restrict__ ckpt,
                       const double* __restrict__ lamT, double* __restrict__ lam0,
                       double* __restrict__ seg, int n, int64_t n_t, int64_t c,
                       double dt, BurgersC bc) {
-    extern __shared__ double lds[];
+    extern __shared__ double lds_d[];
+    R* lds = reinterpret_cast<R*>(lds_d);
     const int base = threadIdx.x * PT;
-    double lam[PT];
+    const R inv2h = (R)bc.inv2h, nuh2 = (R)bc.nuh2, rdt = (R)dt;
+    R lam[PT], lamc[PT];
 #pragma unroll
-    for (int q = 0; q < PT; ++q) lam[q] = lamT[base + q];
+    for (int q = 0; q < PT; ++q) split_hilo<R>(lamT[base + q], lam[q], lamc[q]);
     int buf = 0;
     const int64_t nseg = n_t / c;
     for (int64_t g = nseg - 1; g >= 0; --g) {
-        // recompute the segment's step states from its checkpoint
-        double y[PT];
+        // recompute the segment's step states from its checkpoint (stored
+        // exactly as FP64 values of the compensated pairs)
+        R y[PT], yc[PT];
         const double* ck = ckpt + (size_t)g * n;
 #pragma unroll
-        for (int q = 0; q < PT; ++q) y[q] = ck[base + q];
+        for (int q = 0; q < PT; ++q) split_hilo<R>(ck[base + q], y[q], yc[q]);
         for (int64_t q2 = 0; q2 < c; ++q2) {
             double* o = seg + (size_t)q2 * n;
 #pragma unroll
-            for (int q = 0; q < PT; ++q) o[base + q] = y[q];
-            if (q2 + 1 < c) burgers_step<PT, 2>(y, dt, bc, lds, buf);
+            for (int q = 0; q < PT; ++q) o[base + q] = hilo<R>(y[q], yc[q]);
+            if (q2 + 1 < c) burgers_step<PT, 2, R>(y, yc, rdt, inv2h, nuh2, lds, buf);
         }
         // reverse over the segment
         for (int64_t q2 = c - 1; q2 >= 0; --q2) {
             const double* ys = seg + (size_t)q2 * n;
-            double Y1[PT], Y2[PT], Y3[PT], Y4[PT], k[PT];
-            double Ul[4], Ur[4], l[1], r[1];
+            R Y1[PT], Y2[PT], Y3[PT], Y4[PT], k[PT];
+            R Ul[4], Ur[4], l[1], r[1];
 #pragma unroll
-            for (int q = 0; q < PT; ++q) Y1[q] = ys[base + q];
+            for (int q = 0; q < PT; ++q) Y1[q] = (R)ys[base + q];
             {
-                const double* arr[1] = {Y1};
+                const R* arr[1] = {Y1};
                 exch<PT, 1, 2>(arr, lds, buf, l, r);
             }
             Ul[0] = l[0]; Ur[0] = r[0];
-            burgers_rhs<PT>(Y1, l[0], r[0], bc, k);
+            burgers_rhs<PT, R>(Y1, l[0], r[0], inv2h, nuh2, k);
 #pragma unroll
-            for (int q = 0; q < PT; ++q) Y2[q] = Y1[q] + 0.5 * dt * k[q];
+            for (int q = 0; q < PT; ++q) Y2[q] = Y1[q] + (R)0.5 * rdt * k[q];
             {
-                const double* arr[1] = {Y2};
+                const R* arr[1] = {Y2};
                 exch<PT, 1, 2>(arr, lds, buf, l, r);
             }
             Ul[1] = l[0]; Ur[1] = r[0];
-            burgers_rhs<PT>(Y2, l[0], r[0], bc, k);
+            burgers_rhs<PT, R>(Y2, l[0], r[0], inv2h, nuh2, k);
 #pragma unroll
-            for (int q = 0; q < PT; ++q) Y3[q] = Y1[q] + 0.5 * dt * k[q];
+            for (int q = 0; q < PT; ++q) Y3[q] = Y1[q] + (R)0.5 * rdt * k[q];
             {
-                const double* arr[1] = {Y3};
+                const R* arr[1] = {Y3};
                 exch<PT, 1, 2>(arr, lds, buf, l, r);
             }
             Ul[2] = l[0]; Ur[2] = r[0];
-            burgers_rhs<PT>(Y3, l[0], r[0], bc, k);
+            burgers_rhs<PT, R>(Y3, l[0], r[0], inv2h, nuh2, k);
 #pragma unroll
-            for (int q = 0; q < PT; ++q) Y4[q] = Y1[q] + dt * k[q];
+            for (int q = 0; q < PT; ++q) Y4[q] = Y1[q] + rdt * k[q];
             {
-                const double* arr[1] = {Y4};
+                const R* arr[1] = {Y4};
                 exch<PT, 1, 2>(arr, lds, buf, l, r);
             }
             Ul[3] = l[0]; Ur[3] = r[0];
             // adjoint stages
-            double kb[PT], Yb[PT], nl[PT];
+            R kb[PT], Yb[PT], nl[PT];
 #pragma unroll
-            for (int q = 0; q < PT; ++q) kb[q] = (dt / 6.0) * lam[q];
-            burgers_jt<PT>(Y4, Ul[3], Ur[3], kb, bc, lds, buf, Yb);
-#pragma unroll
-            for (int q = 0; q < PT; ++q) {
-                nl[q] = lam[q] + Yb[q];
-                kb[q] = (dt / 3.0) * lam[q] + dt * Yb[q];
-            }
-            burgers_jt<PT>(Y3, Ul[2], Ur[2], kb, bc, lds, buf, Yb);
+            for (int q = 0; q < PT; ++q) kb[q] = (rdt / (R)6) * lam[q];
+            burgers_jt<PT, R>(Y4, Ul[3], Ur[3], kb, inv2h, nuh2, lds, buf, Yb);
 #pragma unroll
             for (int q = 0; q < PT; ++q) {
-                nl[q] += Yb[q];
-                kb[q] = (dt / 3.0) * lam[q] + 0.5 * dt * Yb[q];
+                nl[q] = Yb[q];
+                kb[q] = (rdt / (R)3) * lam[q] + rdt * Yb[q];
             }
-            burgers_jt<PT>(Y2, Ul[1], Ur[1], kb, bc, lds, buf, Yb);
+            burgers_jt<PT, R>(Y3, Ul[2], Ur[2], kb, inv2h, nuh2, lds, buf, Yb);
 #pragma unroll
             for (int q = 0; q < PT; ++q) {
                 nl[q] += Yb[q];
-                kb[q] = (dt / 6.0) * lam[q] + 0.5 * dt * Yb[q];
+                kb[q] = (rdt / (R)3) * lam[q] + (R)0.5 * rdt * Yb[q];
             }
-            burgers_jt<PT>(Y1, Ul[0], Ur[0], kb, bc, lds, buf, Yb);
+            burgers_jt<PT, R>(Y2, Ul[1], Ur[1], kb, inv2h, nuh2, lds, buf, Yb);
 #pragma unroll
-            for (int q = 0; q < PT; ++q) lam[q] = nl[q] + Yb[q];
+            for (int q = 0; q < PT; ++q) {
+                nl[q] += Yb[q];
+                kb[q] = (rdt / (R)6) * lam[q] + (R)0.5 * rdt * Yb[q];
+            }
+            burgers_jt<PT, R>(Y1, Ul[0], Ur[0], kb, inv2h, nuh2, lds, buf, Yb);
+#pragma unroll
+            for (int q = 0; q < PT; ++q) kadd<R>(lam[q], lamc[q], nl[q] + Yb[q]);
         }
     }
 #pragma unroll
-    for (int q = 0; q < PT; ++q) lam0[base + q] = lam[q];
+    for (int q = 0; q < PT; ++q) lam0[base + q] = hilo<R>(lam[q], lamc[q]);
 }
 
 // Per-macro-step recompute for the time-varying adjoint (one workgroup per
@@ -451,17 +483,18 @@ k_rk4_burgers_reverse(const double* __restrict__ ckpt,
 // W_first = 2(a2 U1 + a1 U2), W_second = 2(a1 U1 + a2 U2),
 // so that each factor is exp((D/2) J(W)^T).  In tau = T - t the macro step q
 // covers [qD, (q+1)D]; U1 = U(T - qD - c1 D), U2 = U(T - qD - c2 D).
-template <int PT>
+template <int PT, typename R>
 __global__ void __launch_bounds__(max_block<PT>())
 k_burgers_nodes(const double* __restrict__ ckpt, double* __restrict__ Wout, int n,
                 int64_t n_t, int64_t c, int64_t S, double dt, BurgersC bc) {
-    extern __shared__ double lds[];
+    extern __shared__ double lds_d[];
+    R* lds = reinterpret_cast<R*>(lds_d);
     const int q = blockIdx.x;
     const int base = threadIdx.x * PT;
+    const R inv2h = (R)bc.inv2h, nuh2 = (R)bc.nuh2, rdt = (R)dt;
     const double r3 = sqrt(3.0);
     const double c1 = 0.5 - r3 / 6.0, c2 = 0.5 + r3 / 6.0;
     const double a1 = 0.25 - r3 / 6.0, a2 = 0.25 + r3 / 6.0;
-    const double D = (double)S * dt;
     // node times as step index + fraction; t1 > t2
     const double f1 = (double)(n_t - (int64_t)q * S) - c1 * (double)S;
     const double f2 = (double)(n_t - (int64_t)q * S) - c2 * (double)S;
@@ -471,15 +504,14 @@ k_burgers_nodes(const double* __restrict__ ckpt, double* __restrict__ Wout, int 
     if (s2 < 0) s2 = 0;
     if (s1 < s2) s1 = s2;
     const double th1 = f1 - (double)s1, th2 = f2 - (double)s2;
-    (void)D;
     const int64_t start = (s2 / c) * c;
-    double y[PT], y0[PT], k0[PT], k1[PT], U1[PT], U2[PT];
+    R y[PT], yc[PT], y0[PT], k0[PT], k1[PT];
+    double U1[PT], U2[PT];
     const double* ck = ckpt + (size_t)(start / c) * n;
 #pragma unroll
-    for (int i = 0; i < PT; ++i) y[i] = ck[base + i];
+    for (int i = 0; i < PT; ++i) split_hilo<R>(ck[base + i], y[i], yc[i]);
     int buf = 0;
-    for (int64_t s = start; s < s2; ++s) burgers_step<PT, 1>(y, dt, bc, lds, buf);
-    // Hermite data on [s2, s2+1]
+    for (int64_t s = start; s < s2; ++s) burgers_step<PT, 1, R>(y, yc, rdt, inv2h, nuh2, lds, buf);
     auto hermite = [&](double th, double (&out)[PT]) {
         const double h00 = 2 * th * th * th - 3 * th * th + 1;
         const double h10 = th * th * th - 2 * th * th + th;
@@ -487,28 +519,35 @@ k_burgers_nodes(const double* __restrict__ ckpt, double* __restrict__ Wout, int 
         const double h11 = th * th * th - th * th;
 #pragma unroll
         for (int i = 0; i < PT; ++i)
-            out[i] = h00 * y0[i] + h10 * dt * k0[i] + h01 * y[i] + h11 * dt * k1[i];
+            out[i] = h00 * (double)y0[i] + h10 * dt * (double)k0[i] +
+                     h01 * hilo<R>(y[i], yc[i]) + h11 * dt * (double)k1[i];
     };
-    auto rhs = [&](double (&out)[PT]) {
-        double l[1], r[1];
-        const double* arr[1] = {y};
+    auto rhs = [&](R (&out)[PT]) {
+        R l[1], r[1];
+        const R* arr[1] = {y};
         exch<PT, 1>(arr, lds, buf, l, r);
-        burgers_rhs<PT>(y, l[0], r[0], bc, out);
+        burgers_rhs<PT, R>(y, l[0], r[0], inv2h, nuh2, out);
     };
+    R y0c[PT];
 #pragma unroll
-    for (int i = 0; i < PT; ++i) y0[i] = y[i];
+    for (int i = 0; i < PT; ++i) {
+        y0[i] = y[i];
+        y0c[i] = yc[i];
+    }
     rhs(k0);
-    burgers_step<PT, 1>(y, dt, bc, lds, buf);  // y = state at s2 + 1
+    burgers_step<PT, 1, R>(y, yc, rdt, inv2h, nuh2, lds, buf);  // y = state at s2 + 1
     rhs(k1);
+#pragma unroll
+    for (int i = 0; i < PT; ++i) y0[i] = (R)hilo<R>(y0[i], y0c[i]);
     hermite(th2, U2);
     if (s1 == s2) {
         hermite(th1, U1);
     } else {
-        for (int64_t s = s2 + 1; s < s1; ++s) burgers_step<PT, 1>(y, dt, bc, lds, buf);
+        for (int64_t s = s2 + 1; s < s1; ++s) burgers_step<PT, 1, R>(y, yc, rdt, inv2h, nuh2, lds, buf);
 #pragma unroll
-        for (int i = 0; i < PT; ++i) y0[i] = y[i];
+        for (int i = 0; i < PT; ++i) y0[i] = (R)hilo<R>(y[i], yc[i]);
         rhs(k0);
-        burgers_step<PT, 1>(y, dt, bc, lds, buf);
+        burgers_step<PT, 1, R>(y, yc, rdt, inv2h, nuh2, lds, buf);
         rhs(k1);
         hermite(th1, U1);
     }
@@ -561,15 +600,21 @@ bool pick_shape(int n, int block_hint, int* block, int* pt) {
 
 }  // namespace
 
-#define PXP_DISPATCH_PT(pt, KERNEL, ...)                                       \
+#define PXP_DISPATCH_PT(pt, KERNEL, R, ...)                                    \
     switch (pt) {                                                              \
-        case 1: KERNEL<1> __VA_ARGS__; break;                                  \
-        case 2: KERNEL<2> __VA_ARGS__; break;                                  \
-        case 4: KERNEL<4> __VA_ARGS__; break;                                  \
-        case 8: KERNEL<8> __VA_ARGS__; break;                                  \
-        case 16: KERNEL<16> __VA_ARGS__; break;                                \
-        case 32: KERNEL<32> __VA_ARGS__; break;                                \
+        case 1: KERNEL<1, R> __VA_ARGS__; break;                               \
+        case 2: KERNEL<2, R> __VA_ARGS__; break;                               \
+        case 4: KERNEL<4, R> __VA_ARGS__; break;                               \
+        case 8: KERNEL<8, R> __VA_ARGS__; break;                               \
+        case 16: KERNEL<16, R> __VA_ARGS__; break;                             \
+        case 32: KERNEL<32, R> __VA_ARGS__; break;                             \
         default: return hipErrorInvalidValue;                                  \
+    }
+#define PXP_DISPATCH(fp32, pt, KERNEL, ...)                                    \
+    if (fp32) {                                                                \
+        PXP_DISPATCH_PT(pt, KERNEL, float, __VA_ARGS__)                        \
+    } else {                                                                   \
+        PXP_DISPATCH_PT(pt, KERNEL, double, __VA_ARGS__)                       \
     }
 
 bool march_shape(int n, int block_hint, int* block, int* pt) {
@@ -578,46 +623,47 @@ bool march_shape(int n, int block_hint, int* block, int* pt) {
 
 hipError_t launch_rk4_lin1d(const double* F, const double* g0, const double* y0,
                             double* out, int n, int P, int64_t n_s, double dt,
-                            double omega, Tri A, int block_hint, hipStream_t s) {
+                            double omega, Tri A, int block_hint, int fp32,
+                            hipStream_t s) {
     int block, pt;
     if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
     const size_t lds = sizeof(double) * 4 * block;
     const TriSplit sp = split(A);
-    PXP_DISPATCH_PT(pt, k_rk4_lin1d,
-                    <<<P, block, lds, s>>>(F, g0, y0, out, n, n_s, dt, omega, sp))
+    PXP_DISPATCH(fp32, pt, k_rk4_lin1d,
+                 <<<P, block, lds, s>>>(F, g0, y0, out, n, n_s, dt, omega, sp))
     return hipGetLastError();
 }
 
 hipError_t launch_rk4_rev_lin1d(const double* lamT, double* lam0,
                                 double* Lambda, int n, int64_t n_t, double dt,
-                                double omega, Tri AT, int block_hint,
+                                double omega, Tri AT, int block_hint, int fp32,
                                 hipStream_t s) {
     int block, pt;
     if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
     const size_t lds = sizeof(double) * 4 * block;
     const TriSplit sp = split(AT);
-    PXP_DISPATCH_PT(pt, k_rk4_rev_lin1d,
-                    <<<1, block, lds, s>>>(lamT, lam0, Lambda, n, n_t, dt, omega, sp))
+    PXP_DISPATCH(fp32, pt, k_rk4_rev_lin1d,
+                 <<<1, block, lds, s>>>(lamT, lam0, Lambda, n, n_t, dt, omega, sp))
     return hipGetLastError();
 }
 
 hipError_t launch_rk4_burgers_direct(const double* y0, double* yT, double* ckpt,
                                      int n, int64_t n_t, int64_t c, double dt,
-                                     double nu, double L, int block_hint,
+                                     double nu, double L, int block_hint, int fp32,
                                      hipStream_t s) {
     int block, pt;
     if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
     const double h = L / n;
     BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
     const size_t lds = sizeof(double) * 4 * block;
-    PXP_DISPATCH_PT(pt, k_rk4_burgers_direct,
-                    <<<1, block, lds, s>>>(y0, yT, ckpt, n, n_t, c, dt, bc))
+    PXP_DISPATCH(fp32, pt, k_rk4_burgers_direct,
+                 <<<1, block, lds, s>>>(y0, yT, ckpt, n, n_t, c, dt, bc))
     return hipGetLastError();
 }
 
 hipError_t launch_burgers_nodes(const double* ckpt, double* W, int n, int64_t n_t,
                                 int64_t c, int64_t S, double dt, double nu, double L,
-                                int block_hint, hipStream_t s) {
+                                int block_hint, int fp32, hipStream_t s) {
     int block, pt;
     if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
     if (S <= 0 || n_t % S) return hipErrorInvalidValue;
@@ -625,23 +671,23 @@ hipError_t launch_burgers_nodes(const double* ckpt, double* W, int n, int64_t n_
     BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
     const size_t lds = sizeof(double) * 4 * block;
     const int Q = (int)(n_t / S);
-    PXP_DISPATCH_PT(pt, k_burgers_nodes,
-                    <<<Q, block, lds, s>>>(ckpt, W, n, n_t, c, S, dt, bc))
+    PXP_DISPATCH(fp32, pt, k_burgers_nodes,
+                 <<<Q, block, lds, s>>>(ckpt, W, n, n_t, c, S, dt, bc))
     return hipGetLastError();
 }
 
 hipError_t launch_rk4_burgers_reverse(const double* ckpt, const double* lamT,
                                       double* lam0, double* seg, int n,
                                       int64_t n_t, int64_t c, double dt,
-                                      double nu, double L, int block_hint,
+                                      double nu, double L, int block_hint, int fp32,
                                       hipStream_t s) {
     int block, pt;
     if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
     const double h = L / n;
     BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
     const size_t lds = sizeof(double) * 8 * block;
-    PXP_DISPATCH_PT(pt, k_rk4_burgers_reverse,
-                    <<<1, block, lds, s>>>(ckpt, lamT, lam0, seg, n, n_t, c, dt, bc))
+    PXP_DISPATCH(fp32, pt, k_rk4_burgers_reverse,
+                 <<<1, block, lds, s>>>(ckpt, lamT, lam0, seg, n, n_t, c, dt, bc))
     return hipGetLastError();
 }
 
