@@ -21,7 +21,8 @@ constexpr int M_MAX_1D = 48;
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-    size_t status;           // DevStatus
+    size_t status;             // DevStatus
+    size_t btab, ktab;         // ragged Burgers batch tables
     std::vector<size_t> base;  // per-instance region offset
     size_t total;
 };
@@ -153,6 +154,10 @@ Layout layout(const pxp_problem* pb, int batch) {
     size_t off = 0;
     Ly.status = off;
     off += align_up(sizeof(DevStatus));
+    Ly.btab = off;
+    off += align_up((size_t)batch * sizeof(BurgersDesc));
+    Ly.ktab = off;
+    off += align_up((size_t)batch * sizeof(KrylovArgs));
     for (int i = 0; i < batch; ++i) {
         Ly.base.push_back(off);
         off += inst_layout(pb[i]).size;
@@ -379,6 +384,46 @@ pxp_status adjoint_burgers(const Ctx& c, const double* lamT, double* lam0,
     return PXP_OK;
 }
 
+// Burgers instances that the ragged batch kernels take: 256 threads with a
+// supported number of points per thread.
+bool burgers_batchable(const pxp_problem& p) {
+    if (p.op != PXP_OP_BURGERS1D || p.nx % 256) return false;
+    const int pt = p.nx / 256;
+    return pt == 1 || pt == 2 || pt == 4 || pt == 8 || pt == 16 || pt == 32;
+}
+
+// Burgers instances of a call go through one launch per phase when there is
+// more than one of them and all have the same precision.
+struct BurgersBatch {
+    std::vector<int> idx;  // instance indices
+    int fp32 = 0;
+    bool on = false;
+};
+
+BurgersBatch burgers_batch(const pxp_problem* pb, int batch) {
+    BurgersBatch b;
+    for (int i = 0; i < batch; ++i)
+        if (burgers_batchable(pb[i])) b.idx.push_back(i);
+    if (b.idx.size() < 2) {
+        b.idx.clear();
+        return b;
+    }
+    b.fp32 = pb[b.idx[0]].prec == PXP_FP32_BULK;
+    for (int i : b.idx)
+        if ((pb[i].prec == PXP_FP32_BULK) != (b.fp32 != 0)) {
+            b.idx.clear();
+            return b;
+        }
+    b.on = true;
+    return b;
+}
+
+bool in_batch(const BurgersBatch& b, int i) {
+    for (int j : b.idx)
+        if (j == i) return true;
+    return false;
+}
+
 // Device arrays handed to the kernels that use 16-byte loads must be
 // 16-byte aligned at every instance offset.
 bool aligned16(const double* base, size_t off) {
@@ -398,6 +443,95 @@ Ctx make_ctx(const pxp_problem& p, void* ws, const Layout& Ly, int i,
     char* w = static_cast<char*>(ws);
     return Ctx{p, w + Ly.base[i], inst_layout(p),
                reinterpret_cast<DevStatus*>(w + Ly.status), s};
+}
+
+BurgersDesc burgers_desc(const pxp_problem& p, const Ctx& c) {
+    BurgersDesc d{};
+    const double h = p.L / p.nx;
+    d.n = p.nx;
+    d.pt = p.nx / 256;
+    d.n_t = p.n_steps;
+    d.c = p.ckpt_every;
+    d.S = p.n_steps / p.P;
+    d.dt = c.dt();
+    d.inv2h = 1.0 / (2.0 * h);
+    d.nuh2 = p.nu / (h * h);
+    d.ckpt = c.at(c.L.ckpt);
+    d.seg = c.at(c.L.seg);
+    d.nodes = c.at(c.L.nodes);
+    return d;
+}
+
+pxp_status burgers_batch_direct(const pxp_problem* pb, const BurgersBatch& bb,
+                                void* ws, const Layout& Ly,
+                                const std::vector<const double*>& init,
+                                const std::vector<double*>& qT, hipStream_t s) {
+    std::vector<BurgersDesc> tab;
+    for (size_t j = 0; j < bb.idx.size(); ++j) {
+        const int i = bb.idx[j];
+        Ctx c = make_ctx(pb[i], ws, Ly, i, s);
+        BurgersDesc d = burgers_desc(pb[i], c);
+        d.y0 = init[j];
+        d.yT = qT[j];
+        tab.push_back(d);
+    }
+    auto* dtab = reinterpret_cast<BurgersDesc*>(static_cast<char*>(ws) + Ly.btab);
+    HIPCHK(launch_upload(dtab, tab.data(), tab.size() * sizeof(BurgersDesc), s));
+    ProfScope ps(PXP_K_SERIAL_DIRECT, s);
+    HIPCHK(launch_burgers_batch(0, dtab, (int)tab.size(), 0, bb.fp32, s));
+    return PXP_OK;
+}
+
+pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
+                                 void* ws, const Layout& Ly,
+                                 const std::vector<double*>& lamT,
+                                 const std::vector<double*>& lam0, int method,
+                                 hipStream_t s) {
+    std::vector<BurgersDesc> tab;
+    std::vector<KrylovArgs> ktab;
+    int q0 = 0;
+    size_t lds = 0;
+    for (size_t j = 0; j < bb.idx.size(); ++j) {
+        const int i = bb.idx[j];
+        const pxp_problem& p = pb[i];
+        Ctx c = make_ctx(p, ws, Ly, i, s);
+        BurgersDesc d = burgers_desc(p, c);
+        d.lamT = lamT[j];
+        d.lam0 = lam0[j];
+        d.q0 = q0;
+        q0 += p.P;
+        tab.push_back(d);
+        KrylovArgs a = kargs(c, Tri{0.0, 0.0, 0.0});
+        a.si = 0;
+        a.mode = KM_LTV;
+        a.npieces = p.P;
+        a.vin = lamT[j];
+        a.yout = lam0[j];
+        a.tau = 0.5 * (double)d.S * c.dt();
+        a.wop = d.nodes;
+        a.inv2h = d.inv2h;
+        a.nuh2 = d.nuh2;
+        a.pt = d.pt;
+        ktab.push_back(a);
+        const size_t l = krylov1d_lds_bytes(p.nx, p.m, 256, 0);
+        if (l > lds) lds = l;
+    }
+    auto* dtab = reinterpret_cast<BurgersDesc*>(static_cast<char*>(ws) + Ly.btab);
+    HIPCHK(launch_upload(dtab, tab.data(), tab.size() * sizeof(BurgersDesc), s));
+    if (method == PXP_METHOD_SERIAL) {
+        ProfScope ps(PXP_K_SERIAL_REVERSE, s);
+        HIPCHK(launch_burgers_batch(1, dtab, (int)tab.size(), 0, bb.fp32, s));
+        return PXP_OK;
+    }
+    auto* kt = reinterpret_cast<KrylovArgs*>(static_cast<char*>(ws) + Ly.ktab);
+    HIPCHK(launch_upload(kt, ktab.data(), ktab.size() * sizeof(KrylovArgs), s));
+    {
+        ProfScope ps(PXP_K_LTV_NODES, s);
+        HIPCHK(launch_burgers_batch(2, dtab, (int)tab.size(), q0, bb.fp32, s));
+    }
+    ProfScope ps(PXP_K_LTV_ADJOINT, s);
+    HIPCHK(launch_krylov_ltv_batch(kt, nullptr, (int)ktab.size(), lds, s));
+    return PXP_OK;
 }
 
 }  // namespace
@@ -535,57 +669,102 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
     st = ws_check(pb, batch, ws, ws_bytes, &Ly);
     if (st != PXP_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    size_t off = 0, koff = 0, boff = 0;
+    // per-instance pointers
+    struct IP {
+        const double *a, *G, *q0, *F, *init, *tgt;
+        double *qT, *lamT, *lam0, *Lam;
+        int n, K;
+        size_t off, koff;
+    };
+    std::vector<IP> ip(batch);
+    {
+        size_t off = 0, koff = 0, boff = 0;
+        for (int i = 0; i < batch; ++i) {
+            const pxp_problem& p = pb[i];
+            const int n = (int)grid_n(p), K = p.K;
+            if (K > 0 && (!ctrl || !basis)) return PXP_EINVAL;
+            Ctx c = make_ctx(p, ws, Ly, i, s);
+            IP& x = ip[i];
+            x.a = ctrl ? ctrl + koff : nullptr;
+            x.G = basis ? basis + boff : nullptr;
+            x.q0 = q0 ? q0 + off : nullptr;
+            x.tgt = u_tgt + off;
+            x.qT = qT ? qT + off : c.at(c.L.qT);
+            x.lamT = c.at(c.L.lamT);
+            x.lam0 = c.at(c.L.lam0);
+            x.Lam = c.at(c.L.Lam);
+            x.F = (p.ctrl == PXP_CTRL_FORCING) ? c.at(c.L.F) : nullptr;
+            x.init = (p.ctrl == PXP_CTRL_FORCING) ? x.q0 : c.at(c.L.q0eff);
+            if (p.op == PXP_OP_BURGERS1D && !x.init) return PXP_EINVAL;
+            x.n = n;
+            x.K = K;
+            x.off = off;
+            x.koff = koff;
+            off += (size_t)n;
+            koff += (size_t)K;
+            boff += (size_t)K * n;
+        }
+    }
+    const BurgersBatch bb = burgers_batch(pb, batch);
+    // (a1) controls -> forcing pattern or initial state
     for (int i = 0; i < batch; ++i) {
         const pxp_problem& p = pb[i];
-        const int n = (int)grid_n(p);
-        const int K = p.K;
-        if (K > 0 && (!ctrl || !basis)) return PXP_EINVAL;
         Ctx c = make_ctx(p, ws, Ly, i, s);
-        const double* a = ctrl ? ctrl + koff : nullptr;
-        const double* G = basis ? basis + boff : nullptr;
-        const double* q0i = q0 ? q0 + off : nullptr;
-        double* qTi = qT ? qT + off : c.at(c.L.qT);
-        double* lamT = c.at(c.L.lamT);
-        double* lam0 = c.at(c.L.lam0);
-        double* Lam = c.at(c.L.Lam);
-        // (a1) controls -> forcing pattern or initial state
-        const double* F = nullptr;
-        const double* init = q0i;
-        if (p.ctrl == PXP_CTRL_FORCING) {
-            HIPCHK(launch_combine_basis(a, G, nullptr, c.at(c.L.F), K, n, s));
-            F = c.at(c.L.F);
-        } else {
-            HIPCHK(launch_combine_basis(a, G, q0i, c.at(c.L.q0eff), K, n, s));
-            init = c.at(c.L.q0eff);
+        if (p.ctrl == PXP_CTRL_FORCING)
+            HIPCHK(launch_combine_basis(ip[i].a, ip[i].G, nullptr, c.at(c.L.F),
+                                        ip[i].K, ip[i].n, s));
+        else
+            HIPCHK(launch_combine_basis(ip[i].a, ip[i].G, ip[i].q0, c.at(c.L.q0eff),
+                                        ip[i].K, ip[i].n, s));
+    }
+    // (a2-a4, a10) direct
+    std::vector<const double*> binit;
+    std::vector<double*> bqT, blamT, blam0;
+    for (int i = 0; i < batch; ++i) {
+        const pxp_problem& p = pb[i];
+        if (bb.on && in_batch(bb, i)) {
+            binit.push_back(ip[i].init);
+            bqT.push_back(ip[i].qT);
+            blamT.push_back(ip[i].lamT);
+            blam0.push_back(ip[i].lam0);
+            continue;
         }
-        // (a2-a4) direct
-        if (p.op == PXP_OP_ADVDIFF1D) {
-            st = direct_lin1d(c, init, F, qTi, method);
-        } else {
-            if (!init) return PXP_EINVAL;
-            st = direct_burgers(c, init, qTi);
-        }
+        Ctx c = make_ctx(p, ws, Ly, i, s);
+        st = (p.op == PXP_OP_ADVDIFF1D) ? direct_lin1d(c, ip[i].init, ip[i].F, ip[i].qT, method)
+                                        : direct_burgers(c, ip[i].init, ip[i].qT);
         if (st != PXP_OK) return st;
-        // (a5) cost and adjoint final condition
-        HIPCHK(launch_cost(qTi, u_tgt + off, a, n, K, p.beta, lamT, J + i, s));
-        // (a6-a8) adjoint
+    }
+    if (bb.on) {
+        st = burgers_batch_direct(pb, bb, ws, Ly, binit, bqT, s);
+        if (st != PXP_OK) return st;
+    }
+    // (a5) cost and adjoint final condition
+    for (int i = 0; i < batch; ++i)
+        HIPCHK(launch_cost(ip[i].qT, ip[i].tgt, ip[i].a, ip[i].n, ip[i].K, pb[i].beta,
+                           ip[i].lamT, J + i, s));
+    // (a6-a8) adjoint
+    for (int i = 0; i < batch; ++i) {
+        const pxp_problem& p = pb[i];
+        if (bb.on && in_batch(bb, i)) continue;
+        Ctx c = make_ctx(p, ws, Ly, i, s);
         const bool forcing = (p.ctrl == PXP_CTRL_FORCING);
-        if (p.op == PXP_OP_ADVDIFF1D) {
-            st = adjoint_lin1d(c, lamT, forcing ? nullptr : lam0,
-                               forcing ? Lam : nullptr, method);
-        } else {
-            st = adjoint_burgers(c, lamT, lam0, method);
-        }
+        st = (p.op == PXP_OP_ADVDIFF1D)
+                 ? adjoint_lin1d(c, ip[i].lamT, forcing ? nullptr : ip[i].lam0,
+                                 forcing ? ip[i].Lam : nullptr, method)
+                 : adjoint_burgers(c, ip[i].lamT, ip[i].lam0, method);
         if (st != PXP_OK) return st;
-        // (a9) gradient
-        const double* v = forcing ? Lam : lam0;
-        HIPCHK(launch_grad(G, v, a, K, n, p.beta, grad + koff, s));
-        if (lam_out)
-            HIPCHK(launch_add(nullptr, v, lam_out + off, n, s));
-        off += (size_t)n;
-        koff += (size_t)K;
-        boff += (size_t)K * n;
+    }
+    if (bb.on) {
+        st = burgers_batch_adjoint(pb, bb, ws, Ly, blamT, blam0, method, s);
+        if (st != PXP_OK) return st;
+    }
+    // (a9) gradient
+    for (int i = 0; i < batch; ++i) {
+        const bool forcing = (pb[i].ctrl == PXP_CTRL_FORCING);
+        const double* v = forcing ? ip[i].Lam : ip[i].lam0;
+        HIPCHK(launch_grad(ip[i].G, v, ip[i].a, ip[i].K, ip[i].n, pb[i].beta,
+                           grad + ip[i].koff, s));
+        if (lam_out) HIPCHK(launch_add(nullptr, v, lam_out + ip[i].off, ip[i].n, s));
     }
     return PXP_OK;
 }

@@ -64,6 +64,29 @@ hipError_t launch_burgers_nodes(const double* ckpt, double* W, int n, int64_t n_
                                 int64_t c, int64_t S, double dt, double nu, double L,
                                 int block, int fp32, hipStream_t s);
 
+// ---- ragged Burgers batches ----------------------------------------------------
+// One descriptor per instance (device table in the workspace, written by
+// launch_upload).  Every instance uses 256 threads with pt = n / 256.
+struct BurgersDesc {
+    int n, pt, q0, pad;      // q0: prefix count of macro steps (nodes grid)
+    int64_t n_t, c, S;
+    double dt, inv2h, nuh2;
+    const double* y0;
+    double* yT;
+    double* ckpt;
+    double* seg;
+    double* nodes;
+    const double* lamT;
+    double* lam0;
+};
+// which: 0 direct march with checkpoints, 1 serial reverse sweep,
+// 2 Magnus node recompute (grid = total macro steps)
+hipError_t launch_burgers_batch(int which, const BurgersDesc* tab, int count,
+                                int total_blocks, int fp32, hipStream_t s);
+// Copy `bytes` (<= 3072) host bytes, passed by value as kernel arguments, to
+// dst (device): graph-capturable table upload.
+hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s);
+
 // ---- Krylov exponential pieces (1D tridiagonal operator) -------------------
 // KM_LTV: chain of 2*npieces exponentials exp(tau J(W_e)^T) with the Burgers
 // Jacobian transpose at the effective states W_e = wop + e*n, in order.
@@ -84,13 +107,19 @@ struct KrylovArgs {
     double gamma_frac;   // shift-and-invert shift = gamma_frac * time
     Tri op;
     int fp32;            // operator stencil in FP32 (polynomial flavour)
+    int pt;              // batched launches: points per thread (256 threads)
     const double* wop;   // KM_LTV: effective states [2*npieces][n]
     double inv2h, nuh2;  // KM_LTV: 1/(2h), nu/h^2
     double* basis;       // [gridDim][m+1][n] workspace
     DevStatus* status;
 };
 hipError_t launch_krylov1d(const KrylovArgs& a, int block, hipStream_t s);
+// Batched time-varying chains: workgroup i runs tab[i] (KM_LTV, polynomial),
+// 256 threads each; lds = the largest krylov1d_lds_bytes of the batch.
+hipError_t launch_krylov_ltv_batch(const KrylovArgs* tab, const int* pts, int count,
+                                   size_t lds, hipStream_t s);
 size_t krylov1d_lds_bytes(int n, int m, int block, int si);
+bool krylov_shape_pub(int n, int block_hint, int* B, int* pt);
 
 // ---- small kernels ---------------------------------------------------------
 // out[i] = base[i] (or 0) + sum_k a[k] basis[k*n + i]

@@ -512,10 +512,8 @@ struct Ctx {
 };
 
 template <int PT, bool SI, bool VAR>
-__global__ void __launch_bounds__(256) k_krylov1d(KrylovArgs a) {
-    extern __shared__ double lds[];
+__device__ __forceinline__ void dev_krylov1d(const KrylovArgs& a, int piece, double* lds) {
     const int n = a.n;
-    const int piece = blockIdx.x;
     double* V = a.basis + (size_t)piece * (a.m + 1) * n;
     Ctx<PT, SI, VAR> c(a, lds, V);
     // The current vector of the piece lives in V_0 (global memory); every
@@ -556,6 +554,27 @@ __global__ void __launch_bounds__(256) k_krylov1d(KrylovArgs a) {
         double x[PT];
         c.gload(V, x);
         c.gstore(y, x);
+    }
+}
+
+template <int PT, bool SI, bool VAR>
+__global__ void __launch_bounds__(256) k_krylov1d(KrylovArgs a) {
+    extern __shared__ double lds[];
+    dev_krylov1d<PT, SI, VAR>(a, blockIdx.x, lds);
+}
+
+// Ragged batch of time-varying chains: workgroup i runs instance i.
+__global__ void __launch_bounds__(256) k_krylov_ltv_batch(const KrylovArgs* tab) {
+    extern __shared__ double lds[];
+    const KrylovArgs a = tab[blockIdx.x];
+    switch (a.pt) {
+        case 1: dev_krylov1d<1, false, true>(a, 0, lds); break;
+        case 2: dev_krylov1d<2, false, true>(a, 0, lds); break;
+        case 4: dev_krylov1d<4, false, true>(a, 0, lds); break;
+        case 8: dev_krylov1d<8, false, true>(a, 0, lds); break;
+        case 16: dev_krylov1d<16, false, true>(a, 0, lds); break;
+        case 32: dev_krylov1d<32, false, true>(a, 0, lds); break;
+        default: break;
     }
 }
 
@@ -603,6 +622,21 @@ size_t krylov1d_lds_bytes(int n, int m, int block, int si) {
     const int ldr = ((m + 1 + 7) / 8) * 8;
     const size_t d = 64 + ldr + 8 + (size_t)(m + 1) * m + big_doubles(n, m, block);
     return d * sizeof(double);
+}
+
+hipError_t launch_krylov_ltv_batch(const KrylovArgs* tab, const int* pts, int count,
+                                   size_t lds, hipStream_t s) {
+    (void)pts;
+    if (count <= 0) return hipSuccess;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipFuncSetAttribute((const void*)k_krylov_ltv_batch,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_krylov_ltv_batch<<<count, 256, lds, s>>>(tab);
+    return hipGetLastError();
+}
+
+bool krylov_shape_pub(int n, int block_hint, int* B, int* pt) {
+    return krylov_shape(n, block_hint, B, pt);
 }
 
 hipError_t launch_krylov1d(const KrylovArgs& a, int block_hint, hipStream_t s) {

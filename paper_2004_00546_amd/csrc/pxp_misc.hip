@@ -5,6 +5,8 @@
 #include "pxp_internal.hpp"
 #include "pxp_device.hpp"
 
+#include <cstring>
+
 namespace pxp {
 namespace {
 
@@ -134,6 +136,31 @@ __global__ void k_zero(double* __restrict__ p, size_t n) {
     if (i < n) p[i] = 0.0;
 }
 }  // namespace
+
+struct UploadChunk {
+    unsigned char b[3072];
+};
+
+__global__ void k_upload(unsigned char* __restrict__ dst, UploadChunk c, int bytes) {
+    for (int i = threadIdx.x; i < bytes; i += blockDim.x) dst[i] = c.b[i];
+}
+
+hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    unsigned char* d = static_cast<unsigned char*>(dst);
+    const unsigned char* h = static_cast<const unsigned char*>(src);
+    while (bytes > 0) {
+        const size_t nb = bytes > sizeof(UploadChunk) ? sizeof(UploadChunk) : bytes;
+        UploadChunk c;
+        memcpy(c.b, h, nb);
+        k_upload<<<1, 256, 0, s>>>(d, c, (int)nb);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        d += nb;
+        h += nb;
+        bytes -= nb;
+    }
+    return hipSuccess;
+}
 
 hipError_t launch_zero(double* p, size_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;

@@ -326,11 +326,11 @@ __device__ __forceinline__ void burgers_step(R (&y)[PT], R (&yc)[PT], R dt,
 }
 
 template <int PT, typename R>
-__global__ void __launch_bounds__(max_block<PT>())
-k_rk4_burgers_direct(const double* __restrict__ y0, double* __restrict__ yT,
-                     double* __restrict__ ckpt, int n, int64_t n_t, int64_t c,
-                     double dt, BurgersC bc) {
-    extern __shared__ double lds_d[];
+__device__ __forceinline__ void dev_burgers_direct(const double* __restrict__ y0,
+                                                   double* __restrict__ yT,
+                                                   double* __restrict__ ckpt, int n,
+                                                   int64_t n_t, int64_t c, double dt,
+                                                   BurgersC bc, double* lds_d) {
     R* lds = reinterpret_cast<R*>(lds_d);
     const int base = threadIdx.x * PT;
     const R inv2h = (R)bc.inv2h, nuh2 = (R)bc.nuh2, rdt = (R)dt;
@@ -352,6 +352,15 @@ k_rk4_burgers_direct(const double* __restrict__ y0, double* __restrict__ yT,
     }
 #pragma unroll
     for (int q = 0; q < PT; ++q) yT[base + q] = hilo<R>(y[q], yc[q]);
+}
+
+template <int PT, typename R>
+__global__ void __launch_bounds__(max_block<PT>())
+k_rk4_burgers_direct(const double* __restrict__ y0, double* __restrict__ yT,
+                     double* __restrict__ ckpt, int n, int64_t n_t, int64_t c,
+                     double dt, BurgersC bc) {
+    extern __shared__ double lds_d[];
+    dev_burgers_direct<PT, R>(y0, yT, ckpt, n, n_t, c, dt, bc, lds_d);
 }
 
 // (J(U)^T v)_i = ((U v)_{i+1} - (U v)_{i-1})/(2h) - (U_{i+1} - U_{i-1}) v_i/(2h)
@@ -381,12 +390,12 @@ __device__ __forceinline__ void burgers_jt(const R (&U)[PT], R Ul, R Ur,
 }
 
 template <int PT, typename R>
-__global__ void __launch_bounds__(max_block<PT>())
-k_rk4_burgers_reverse(const double* __restrict__ ckpt,
-                      const double* __restrict__ lamT, double* __restrict__ lam0,
-                      double* __restrict__ seg, int n, int64_t n_t, int64_t c,
-                      double dt, BurgersC bc) {
-    extern __shared__ double lds_d[];
+__device__ __forceinline__ void dev_burgers_reverse(const double* __restrict__ ckpt,
+                                                    const double* __restrict__ lamT,
+                                                    double* __restrict__ lam0,
+                                                    double* __restrict__ seg, int n,
+                                                    int64_t n_t, int64_t c, double dt,
+                                                    BurgersC bc, double* lds_d) {
     R* lds = reinterpret_cast<R*>(lds_d);
     const int base = threadIdx.x * PT;
     const R inv2h = (R)bc.inv2h, nuh2 = (R)bc.nuh2, rdt = (R)dt;
@@ -475,6 +484,16 @@ k_rk4_burgers_reverse(const double* __restrict__ ckpt,
     for (int q = 0; q < PT; ++q) lam0[base + q] = hilo<R>(lam[q], lamc[q]);
 }
 
+template <int PT, typename R>
+__global__ void __launch_bounds__(max_block<PT>())
+k_rk4_burgers_reverse(const double* __restrict__ ckpt,
+                      const double* __restrict__ lamT, double* __restrict__ lam0,
+                      double* __restrict__ seg, int n, int64_t n_t, int64_t c,
+                      double dt, BurgersC bc) {
+    extern __shared__ double lds_d[];
+    dev_burgers_reverse<PT, R>(ckpt, lamT, lam0, seg, n, n_t, c, dt, bc, lds_d);
+}
+
 // Per-macro-step recompute for the time-varying adjoint (one workgroup per
 // macro step q, all in parallel): march from the checkpoint preceding the
 // step's Gauss nodes, interpolate U at the two nodes by cubic Hermite
@@ -484,12 +503,12 @@ k_rk4_burgers_reverse(const double* __restrict__ ckpt,
 // so that each factor is exp((D/2) J(W)^T).  In tau = T - t the macro step q
 // covers [qD, (q+1)D]; U1 = U(T - qD - c1 D), U2 = U(T - qD - c2 D).
 template <int PT, typename R>
-__global__ void __launch_bounds__(max_block<PT>())
-k_burgers_nodes(const double* __restrict__ ckpt, double* __restrict__ Wout, int n,
-                int64_t n_t, int64_t c, int64_t S, double dt, BurgersC bc) {
-    extern __shared__ double lds_d[];
+__device__ __forceinline__ void dev_burgers_nodes(const double* __restrict__ ckpt,
+                                                  double* __restrict__ Wout, int n,
+                                                  int64_t n_t, int64_t c, int64_t S,
+                                                  double dt, BurgersC bc, int q,
+                                                  double* lds_d) {
     R* lds = reinterpret_cast<R*>(lds_d);
-    const int q = blockIdx.x;
     const int base = threadIdx.x * PT;
     const R inv2h = (R)bc.inv2h, nuh2 = (R)bc.nuh2, rdt = (R)dt;
     const double r3 = sqrt(3.0);
@@ -558,6 +577,63 @@ k_burgers_nodes(const double* __restrict__ ckpt, double* __restrict__ Wout, int 
         w1[base + i] = 2.0 * (a2 * U1[i] + a1 * U2[i]);
         w2[base + i] = 2.0 * (a1 * U1[i] + a2 * U2[i]);
     }
+}
+
+template <int PT, typename R>
+__global__ void __launch_bounds__(max_block<PT>())
+k_burgers_nodes(const double* __restrict__ ckpt, double* __restrict__ Wout, int n,
+                int64_t n_t, int64_t c, int64_t S, double dt, BurgersC bc) {
+    extern __shared__ double lds_d[];
+    dev_burgers_nodes<PT, R>(ckpt, Wout, n, n_t, c, S, dt, bc, blockIdx.x, lds_d);
+}
+
+// ---- ragged batches: one launch over all instances -------------------------
+// Every workgroup reads its instance from the descriptor table and runs the
+// march for that instance's points per thread (256 threads per workgroup,
+// n = 256 * pt).
+
+#define PXP_BATCH_SWITCH(FN, R, ...)                                           \
+    switch (d.pt) {                                                            \
+        case 1: FN<1, R>(__VA_ARGS__); break;                                  \
+        case 2: FN<2, R>(__VA_ARGS__); break;                                  \
+        case 4: FN<4, R>(__VA_ARGS__); break;                                  \
+        case 8: FN<8, R>(__VA_ARGS__); break;                                  \
+        case 16: FN<16, R>(__VA_ARGS__); break;                                \
+        case 32: FN<32, R>(__VA_ARGS__); break;                                \
+        default: break;                                                        \
+    }
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_burgers_direct_batch(const BurgersDesc* tab) {
+    extern __shared__ double lds_d[];
+    const BurgersDesc d = tab[blockIdx.x];
+    const BurgersC bc{d.inv2h, d.nuh2};
+    PXP_BATCH_SWITCH(dev_burgers_direct, R, d.y0, d.yT, d.ckpt, d.n, d.n_t, d.c, d.dt,
+                     bc, lds_d)
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_burgers_reverse_batch(const BurgersDesc* tab) {
+    extern __shared__ double lds_d[];
+    const BurgersDesc d = tab[blockIdx.x];
+    const BurgersC bc{d.inv2h, d.nuh2};
+    PXP_BATCH_SWITCH(dev_burgers_reverse, R, d.ckpt, d.lamT, d.lam0, d.seg, d.n, d.n_t,
+                     d.c, d.dt, bc, lds_d)
+}
+
+// grid = sum of the instances' macro-step counts; the instance of a
+// workgroup is found by a scan of the table's prefix counts
+template <typename R>
+__global__ void __launch_bounds__(256) k_burgers_nodes_batch(const BurgersDesc* tab,
+                                                             int count) {
+    extern __shared__ double lds_d[];
+    int i = 0;
+    while (i + 1 < count && (int)blockIdx.x >= tab[i + 1].q0) ++i;
+    const BurgersDesc d = tab[i];
+    const BurgersC bc{d.inv2h, d.nuh2};
+    const int q = (int)blockIdx.x - d.q0;
+    PXP_BATCH_SWITCH(dev_burgers_nodes, R, d.ckpt, d.nodes, d.n, d.n_t, d.c, d.S, d.dt,
+                     bc, q, lds_d)
 }
 
 // Threads per workgroup and points per thread for an n-point march: by
@@ -688,6 +764,24 @@ hipError_t launch_rk4_burgers_reverse(const double* ckpt, const double* lamT,
     const size_t lds = sizeof(double) * 8 * block;
     PXP_DISPATCH(fp32, pt, k_rk4_burgers_reverse,
                  <<<1, block, lds, s>>>(ckpt, lamT, lam0, seg, n, n_t, c, dt, bc))
+    return hipGetLastError();
+}
+
+hipError_t launch_burgers_batch(int which, const BurgersDesc* tab, int count,
+                                int total_blocks, int fp32, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const size_t lds = sizeof(double) * 8 * 256;
+    const int grid = (which == 2) ? total_blocks : count;
+    if (which == 0) {
+        if (fp32) k_burgers_direct_batch<float><<<grid, 256, lds, s>>>(tab);
+        else k_burgers_direct_batch<double><<<grid, 256, lds, s>>>(tab);
+    } else if (which == 1) {
+        if (fp32) k_burgers_reverse_batch<float><<<grid, 256, lds, s>>>(tab);
+        else k_burgers_reverse_batch<double><<<grid, 256, lds, s>>>(tab);
+    } else {
+        if (fp32) k_burgers_nodes_batch<float><<<grid, 256, lds, s>>>(tab, count);
+        else k_burgers_nodes_batch<double><<<grid, 256, lds, s>>>(tab, count);
+    }
     return hipGetLastError();
 }
 

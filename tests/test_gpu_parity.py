@@ -298,3 +298,65 @@ def test_fp32_bulk_compensation_matters(torch, orc):
     want = orc.gradient(inst)
     say("fp32 serial n4096 qT %.2e" % rel(got["qT"], want["qT"]))
     assert rel(got["qT"], want["qT"]) < 1e-6
+
+
+# ---- ragged Burgers batches (one launch per phase) -------------------------
+
+def ragged_burgers(seed=21):
+    out = []
+    for i, (n, nu, T) in enumerate([(256, 0.02, 0.4), (512, 0.01, 0.3),
+                                    (1024, 0.02, 0.2), (512, 0.015, 0.5),
+                                    (256, 0.03, 0.25)]):
+        dt = 0.8 * workloads.burgers_dt_bound(n, nu)
+        nt = 64 * int(math.ceil(T / (64 * dt)))
+        # Magnus macro steps of at most T/16 (as in the ragged workload)
+        inst = small_burgers(n=n, T=T, nt=nt, P=nt // 4, nu=nu, seed=seed + i,
+                             ckpt=16)
+        out.append(inst)
+    return out
+
+
+@pytest.mark.parametrize("method", ["paraexp", "serial"])
+def test_ragged_burgers_batch_equals_one_by_one(torch, method):
+    insts = ragged_burgers()
+    r = api.GradientRunner(insts, method=method, krylov="poly")
+    r.run()
+    code, _ = r.status()
+    assert code == 0
+    batch = r.results()
+    for inst, b in zip(insts, batch):
+        one = run(inst, method, krylov="poly")
+        assert np.array_equal(one["qT"], b["qT"])
+        assert np.array_equal(one["grad"], b["grad"]), (inst["nx"], method)
+
+
+def test_ragged_burgers_batch_vs_oracle(torch, orc):
+    insts = ragged_burgers(seed=40)
+    r = api.GradientRunner(insts, method="paraexp", krylov="poly")
+    r.run()
+    for inst, b in zip(insts, r.results()):
+        want = orc.gradient(inst)
+        e = rel(b["grad"], want["grad"])
+        say("ragged n=%d nt=%d P=%d grad %.2e" % (inst["nx"], inst["n_steps"], inst["P"], e))
+        assert e < FP64_GATE
+
+
+def test_ragged_workload_sample_vs_oracle(torch, orc):
+    """Four instances of the 64-instance ragged workload (N = 1024 .. 8192)
+    with the horizon cut to a quarter: same grids, viscosities, time steps
+    and Magnus macro-step lengths, FP32 bulk."""
+    full = workloads.make("burgers1d_ragged")
+    picks = [full[i] for i in (0, 1, 4, 5)]
+    insts = []
+    for inst in picks:
+        nt = inst["n_steps"] // 4
+        insts.append(dict(inst, n_steps=nt, T=inst["T"] / 4, P=inst["P"] // 4))
+    r = api.GradientRunner(insts, method="paraexp", krylov="poly", prec="fp32_bulk", tol=1e-6)
+    r.run()
+    code, _ = r.status()
+    assert code == 0
+    for inst, b in zip(insts, r.results()):
+        want = orc.gradient(inst)
+        e = rel(b["grad"], want["grad"])
+        say("ragged workload n=%d nt=%d fp32 grad %.2e" % (inst["nx"], inst["n_steps"], e))
+        assert e < FP32_GATE
