@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 METRIC = "gradient evals/s, Paraexp vs serial stepping on 1 GPU at rel err ≤1e-8"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 
 
 def log(*a):
@@ -93,6 +94,14 @@ def main():
     ap.add_argument("--serial-steps", type=int, default=5)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32_bulk"])
     ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--block", type=int, default=0,
+                    help="threads per workgroup of the RK4 marches (0 = default)")
+    ap.add_argument("--kblock", type=int, default=0,
+                    help="threads per workgroup of the Krylov kernels (0 = default)")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time replays of the gradient captured in a hipGraph")
+    ap.add_argument("--oracle-budget", type=float, default=2.5e8,
+                    help="point-steps of the oracle accuracy sample for batch workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true",
                     help="skip the CPU accuracy check (profiler runs only; "
@@ -122,17 +131,22 @@ def main():
         print(json.dumps({"copy_calibration_bytes_per_launch": nbytes,
                           "launches": 5}), flush=True)
         return
-    inst = workloads.make(args.workload)[0]
+    insts = workloads.make(args.workload)
+    inst = insts[0]
+    B = len(insts)
     n, n_steps, P, m = inst["nx"] * inst.get("ny", 1), inst["n_steps"], inst["P"], inst["m"]
-    log("workload %s: N=%d steps=%d P=%d m=%d" % (args.workload, n, n_steps, P, m))
+    work = [int(x["nx"]) * int(x.get("ny", 1)) * int(x["n_steps"]) for x in insts]
+    log("workload %s: %d instance(s); first N=%d steps=%d P=%d m=%d; point-steps %.3g"
+        % (args.workload, B, n, n_steps, P, m, sum(work)))
 
     if args.krylov is None:
         # shift-and-invert needs a constant-coefficient tridiagonal operator
         args.krylov = "shift_invert" if inst["op"] == "advdiff1d" else "poly"
     tol = args.tol if args.tol is not None else (1e-10 if args.prec == "fp64" else 1e-6)
-    pxp = api.GradientRunner([inst], method="paraexp", krylov=args.krylov,
-                             sched=args.sched, prec=args.prec, tol=tol)
-    ser = api.GradientRunner([inst], method="serial", prec=args.prec)
+    kw = dict(prec=args.prec, block=args.block, kblock=args.kblock)
+    pxp = api.GradientRunner(insts, method="paraexp", krylov=args.krylov,
+                             sched=args.sched, tol=tol, **kw)
+    ser = api.GradientRunner(insts, method="serial", **kw)
 
     # timed Paraexp region, with per-kernel events on the library's stream
     for _ in range(args.warmup):
@@ -154,70 +168,68 @@ def main():
     for k in _lib.KCLASS:
         ms, cnt = _lib.pxp_profile_read(k)
         if cnt:
-            kern[k] = dict(avg_ms=ms / cnt, launches=cnt)
+            kern[k] = dict(avg_ms=ms / cnt, launches=cnt, per_step_ms=ms / args.steps)
     substeps, iters = _lib.pxp_device_counters(pxp.ws)
     code, est = pxp.status()
-    res_pxp = pxp.results()[0]
-    log("paraexp %.3f ms/gradient  kernels %s  status %d est %.1e"
+    res_pxp = pxp.results()
+    log("paraexp %.3f ms/step  kernels %s  status %d est %.1e"
         % (t_pxp * 1e3, kern, code, est))
 
-    t_ser = time_runner(torch, ser, args.serial_steps, 1)
-    res_ser = ser.results()[0]
-    log("serial %.3f ms/gradient" % (t_ser * 1e3))
+    t_graph = None
+    if args.graph:
+        t_graph = time_graph(torch, pxp, args.steps)
+        log("paraexp, hipGraph replay %.3f ms/step" % (t_graph * 1e3))
 
-    # accuracy against the oracle; the same run is the CPU baseline timing
-    if args.no_oracle:
-        nan = float("nan")
-        ref = dict(grad=res_pxp["grad"] * nan, qT=res_pxp["qT"] * nan,
-                   lam0=res_pxp["lam"] * nan, Lambda=res_pxp["lam"] * nan)
-        t_orc = nan
-        args.no_cpu_baseline = True
-    else:
+    t_ser = time_runner(torch, ser, args.serial_steps, 1)
+    res_ser = ser.results()
+    log("serial %.3f ms/step" % (t_ser * 1e3))
+
+    # accuracy against the oracle on a bounded sample of the instances (all
+    # of them for single-instance workloads); the same runs time the CPU
+    # baseline
+    sample = oracle_sample(insts, work, args.oracle_budget)
+    err = None
+    t_orc = float("nan")
+    if not args.no_oracle:
         import oracle
         oracle.build()
+        err = dict(paraexp_grad=0.0, paraexp_adjoint=0.0, paraexp_qT=0.0,
+                   serial_grad=0.0, serial_qT=0.0)
         t0 = time.perf_counter()
-        ref = oracle.gradient(inst)
+        for i in sample:
+            ref = oracle.gradient(insts[i])
+            lam_key = "Lambda" if insts[i]["control"] == "forcing" else "lam0"
+            e = dict(paraexp_grad=rel(res_pxp[i]["grad"], ref["grad"]),
+                     paraexp_adjoint=rel(res_pxp[i]["lam"], ref[lam_key]),
+                     paraexp_qT=rel(res_pxp[i]["qT"], ref["qT"]),
+                     serial_grad=rel(res_ser[i]["grad"], ref["grad"]),
+                     serial_qT=rel(res_ser[i]["qT"], ref["qT"]))
+            err = {k: max(err[k], v) for k, v in e.items()}
         t_orc = time.perf_counter() - t0
-    lam_key = "Lambda" if inst["control"] == "forcing" else "lam0"
-    err = dict(paraexp_grad=rel(res_pxp["grad"], ref["grad"]),
-               paraexp_adjoint=rel(res_pxp["lam"], ref[lam_key]),
-               paraexp_qT=rel(res_pxp["qT"], ref["qT"]),
-               serial_grad=rel(res_ser["grad"], ref["grad"]),
-               serial_qT=rel(res_ser["qT"], ref["qT"]))
-    log("rel errors", err, "oracle %.2f s" % t_orc)
+        log("rel errors (max over %d sampled instance(s))" % len(sample), err,
+            "oracle %.2f s" % t_orc)
+    else:
+        args.no_cpu_baseline = True
 
-    # Roofline of the HBM-streaming kernel: the direct homogeneous pieces
-    # (P-1 Arnoldi spaces in one launch); the register-resident RK4 slices
-    # are reported against the FP64 vector peak.
-    roof = None
-    if "krylov_direct" in kern and args.sched == "classic" and m_is_full(inst):
-        byts = (P - 1) * krylov_space_bytes(n, m)
-        sec = kern["krylov_direct"]["avg_ms"] * 1e-3
-        ach = byts / sec / 1e9
-        tr = profiled_traffic("k_krylov1d_direct_classic")
-        roof = dict(kernel="k_krylov1d, direct pieces (classic, %d workgroups)" % (P - 1),
-                    bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=ach / HBM_PEAK_GBS, traffic=tr,
-                    algorithmic_bytes_per_launch=byts,
-                    avg_launch_ms=kern["krylov_direct"]["avg_ms"])
-    elif "slices" in kern:
-        ach = rk4_slice_flops(n, n_steps) / (kern["slices"]["avg_ms"] * 1e-3) / 1e12
-        roof = dict(kernel="k_rk4_lin1d (inhomogeneous slices)", bound="alu",
-                    achieved=ach, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=ach / FP64_PEAK_TFLOPS, traffic=None)
-    elif "ltv_adjoint" in kern:
-        sp = substeps / max(1, args.steps)
-        byts = sp * krylov_space_bytes(n, max(1, int(round(iters / max(sp, 1) / max(1, args.steps) * args.steps))))
-        ach = byts / (kern["ltv_adjoint"]["avg_ms"] * 1e-3) / 1e9
-        roof = dict(kernel="k_krylov1d, time-varying Magnus chain (1 workgroup)",
-                    bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=ach / HBM_PEAK_GBS, traffic=None)
+    roof = roofline(kern, insts, args, substeps, iters)
 
     gate = 1e-8 if args.prec == "fp64" else 1e-5
-    ok = err["paraexp_grad"] <= gate and err["paraexp_qT"] <= gate and code == 0
+    ok = (err is not None and err["paraexp_grad"] <= gate and err["paraexp_qT"] <= gate
+          and code == 0)
+    cfg = {"workload": args.workload, "instances": B, "N": n, "T": inst["T"],
+           "n_steps": n_steps, "slices": P, "krylov_m": m, "krylov": args.krylov,
+           "schedule": args.sched, "precision": args.prec, "gate": gate,
+           "controls": int(np.asarray(inst["basis"]).shape[0]),
+           "block": args.block, "kblock": args.kblock}
+    if B > 1:
+        cfg.update(N=sorted({int(x["nx"]) * int(x.get("ny", 1)) for x in insts}),
+                   n_steps=[min(int(x["n_steps"]) for x in insts),
+                            max(int(x["n_steps"]) for x in insts)],
+                   T=[min(x["T"] for x in insts), max(x["T"] for x in insts)],
+                   point_steps=sum(work))
     line = {
         "metric": METRIC,
-        "value": (1.0 / t_pxp) if ok else 0.0,
+        "value": (B / t_pxp) if ok else 0.0,
         "unit": "gradient evals/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -228,26 +240,118 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "N": n, "T": inst["T"],
-                   "n_steps": n_steps, "slices": P, "krylov_m": m,
-                   "krylov": args.krylov, "schedule": args.sched,
-                   "precision": args.prec, "gate": gate,
-                   "controls": int(inst["basis"].shape[0])},
-        "serial_gpu": {"value": 1.0 / t_ser, "ms_per_step": t_ser * 1e3},
+        "config": cfg,
+        "serial_gpu": {"value": B / t_ser, "ms_per_step": t_ser * 1e3},
         "speedup_vs_serial": t_ser / t_pxp,
         "rel_err_vs_oracle": err,
-        "krylov": {"spaces_per_gradient": substeps / max(1, args.steps),
-                   "iters_per_gradient": iters / max(1, args.steps),
+        "oracle_sample": sample,
+        "krylov": {"spaces_per_step": substeps / max(1, args.steps),
+                   "iters_per_step": iters / max(1, args.steps),
                    "max_est": est, "status": code},
         "kernels_ms": {k: v["avg_ms"] for k, v in kern.items()},
         "roofline": roof,
     }
+    if t_graph is not None:
+        line["graph"] = {"value": B / t_graph, "ms_per_step": t_graph * 1e3}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = {"value": 1.0 / t_orc, "unit": "gradient evals/s",
-                                "cores": 1, "kind": "oracle",
-                                "sample": "one full gradient of the workload "
-                                          "(serial FP64 RK4 + exact discrete adjoint)"}
+        w_s = sum(work[i] for i in sample)
+        t_all = t_orc * sum(work) / w_s
+        line["cpu_baseline"] = {
+            "value": B / t_all, "unit": "gradient evals/s", "cores": 1, "kind": "oracle",
+            "sample": ("one full gradient of the workload (serial FP64 RK4 + exact "
+                       "discrete adjoint)" if B == 1 else
+                       "full gradients of instances %s (%.3g of %.3g point-steps, %.1f s), "
+                       "scaled by point-steps to the %d-instance batch"
+                       % (sample, w_s, sum(work), t_orc, B))}
     print(json.dumps(line), flush=True)
+
+
+def oracle_sample(insts, work, budget):
+    """Instances the oracle checks: all of a single-instance workload; for a
+    batch, the cheapest instance of each grid size, then the cheapest others
+    while the point-step budget lasts."""
+    if len(insts) == 1:
+        return [0]
+    order = sorted(range(len(insts)), key=lambda i: work[i])
+    pick, seen, used = [], set(), 0
+    for i in order:
+        nn = int(insts[i]["nx"]) * int(insts[i].get("ny", 1))
+        if nn not in seen:
+            pick.append(i)
+            seen.add(nn)
+            used += work[i]
+    for i in order:
+        if i not in pick and used + work[i] <= budget:
+            pick.append(i)
+            used += work[i]
+    return sorted(pick)
+
+
+def time_graph(torch, r, steps):
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        r.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        r.run()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def roofline(kern, insts, args, substeps, iters):
+    """Roofline object for the kernel class that takes the most time per step."""
+    if not kern:
+        return None
+    top = max(kern, key=lambda k: kern[k]["per_step_ms"])
+    inst = insts[0]
+    n = inst["nx"] * inst.get("ny", 1)
+    P, m = inst["P"], inst["m"]
+    sec = kern[top]["avg_ms"] * 1e-3
+    if top == "krylov_direct" and args.sched == "classic" and len(insts) == 1:
+        byts = (P - 1) * krylov_space_bytes(n, m)
+        ach = byts / sec / 1e9
+        return dict(kernel="k_krylov1d, direct pieces (classic, %d workgroups)" % (P - 1),
+                    bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=ach / HBM_PEAK_GBS,
+                    traffic=profiled_traffic("k_krylov1d_direct_classic"),
+                    algorithmic_bytes_per_launch=byts, avg_launch_ms=kern[top]["avg_ms"])
+    if top == "slices" and len(insts) == 1:
+        ach = rk4_slice_flops(n, inst["n_steps"]) / sec / 1e12
+        return dict(kernel="k_rk4_lin1d (inhomogeneous slices)", bound="alu",
+                    achieved=ach, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=ach / FP64_PEAK_TFLOPS, traffic=None, avg_launch_ms=kern[top]["avg_ms"])
+    if top == "serial_direct" and all(x["op"] == "burgers1d" for x in insts):
+        # one launch marches every instance; 48 flop per point and step
+        per_step = kern[top]["launches"] / args.steps
+        fl = sum(48.0 * x["nx"] * x["n_steps"] for x in insts) / per_step
+        peak = FP64_PEAK_TFLOPS if args.prec == "fp64" else FP32_PEAK_TFLOPS
+        ach = fl / sec / 1e12
+        return dict(kernel="k_burgers_direct_batch (serial Burgers RK4 marches)",
+                    bound="alu", achieved=ach, peak=peak, unit="TFLOP/s",
+                    frac=ach / peak, traffic=None, avg_launch_ms=kern[top]["avg_ms"])
+    if top in ("ltv_adjoint", "krylov_adjoint", "krylov_direct"):
+        # bytes streamed by the Arnoldi steps actually taken (device counters):
+        # step j of a space reads j+1 basis vectors four times and writes one
+        sp = substeps / max(1, args.steps)
+        it = iters / max(1, args.steps)
+        mm = it / max(sp, 1.0)
+        nbar = sum(x["nx"] * x.get("ny", 1) for x in insts) / len(insts)
+        byts = sp * krylov_space_bytes(nbar, max(1, int(round(mm))))
+        launches = kern[top]["launches"] / args.steps
+        ach = byts / launches / sec / 1e9
+        return dict(kernel="k_krylov1d (%s)" % top, bound="hbm", achieved=ach,
+                    peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=None,
+                    avg_launch_ms=kern[top]["avg_ms"])
+    return dict(kernel=top, bound=None, achieved=None, peak=None, unit=None, frac=None,
+                traffic=None, avg_launch_ms=kern[top]["avg_ms"])
 
 
 if __name__ == "__main__":

@@ -91,6 +91,9 @@ typedef struct {
                                         checkpoint interval (steps), threads
                                         per workgroup for the 1D marches
                                         (0 = library default)                 */
+    int32_t kblock, reserved;        /* threads per workgroup of the Krylov
+                                        kernels (multiple of 64, <= 512;
+                                        0 = library default); reserved = 0    */
     int64_t n_steps;                 /* RK4 steps; n_steps % P == 0            */
     double L, vx, vy, nu;            /* box [0,L)^d, velocity, viscosity       */
     double T, omega, beta;           /* horizon, s(t) = sin(omega t), weight   */

@@ -44,6 +44,7 @@ class pxp_problem(ctypes.Structure):
                 ("ny", ctypes.c_int32), ("P", ctypes.c_int32),
                 ("m", ctypes.c_int32), ("K", ctypes.c_int32),
                 ("ckpt_every", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("kblock", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("n_steps", ctypes.c_int64),
                 ("L", ctypes.c_double), ("vx", ctypes.c_double),
                 ("vy", ctypes.c_double), ("nu", ctypes.c_double),

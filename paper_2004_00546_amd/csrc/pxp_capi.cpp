@@ -3,6 +3,7 @@
 // full direct-adjoint loop (paper sections 2 and 3).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -69,6 +70,17 @@ bool rk4_stable_advdiff1d(const pxp_problem& p) {
     return true;
 }
 
+// The Krylov kernels' workgroup shape for this problem exists, fits in LDS,
+// reads two consecutive points per 16-byte load (even n once a thread owns
+// more than one point) and, for shift-and-invert, covers the grid exactly.
+bool krylov_fits(const pxp_problem& p, bool si) {
+    int B, pt;
+    if (!krylov_shape_pub(p.nx, p.kblock, &B, &pt)) return false;
+    if (pt >= 2 && (p.nx & 1)) return false;
+    if (si && pt * B != p.nx) return false;
+    return krylov1d_lds_bytes(p.nx, p.m, B, si) <= 160 * 1024;
+}
+
 pxp_status validate(const pxp_problem& p) {
     if (p.nx < 2 || p.ny < 1 || p.n_steps < 1 || p.P < 1 || p.T <= 0.0 ||
         p.L <= 0.0 || p.nu < 0.0 || p.K < 0 || !std::isfinite(p.T) ||
@@ -80,6 +92,7 @@ pxp_status validate(const pxp_problem& p) {
         return PXP_EINVAL;
     if (p.sched != PXP_SCHED_CLASSIC && p.sched != PXP_SCHED_CHAIN) return PXP_EINVAL;
     if (p.prec != PXP_FP64 && p.prec != PXP_FP32_BULK) return PXP_EINVAL;
+    if (p.reserved != 0 || p.kblock < 0 || p.block < 0) return PXP_EINVAL;
     if (p.op == PXP_OP_ADVDIFF1D) {
         if (p.ny != 1) return PXP_EINVAL;
         if (p.m < 1 || p.m > M_MAX_1D) return PXP_EUNSUPPORTED;
@@ -90,8 +103,7 @@ pxp_status validate(const pxp_problem& p) {
         if (p.krylov == PXP_KRYLOV_SHIFT_INVERT && (!is_pow2(p.nx) || p.nx < 64))
             return PXP_EUNSUPPORTED;
         if (!(p.krylov_tol > 0.0)) return PXP_EINVAL;
-        // the Krylov kernels read two consecutive points per 16-byte load
-        if (p.nx > 256 && (p.nx & 1)) return PXP_EUNSUPPORTED;
+        if (!krylov_fits(p, p.krylov == PXP_KRYLOV_SHIFT_INVERT)) return PXP_EUNSUPPORTED;
         if (!rk4_stable_advdiff1d(p)) return PXP_EUNSTABLE_DT;
         return PXP_OK;
     }
@@ -103,7 +115,7 @@ pxp_status validate(const pxp_problem& p) {
         if (p.ckpt_every < 1 || p.n_steps % p.ckpt_every) return PXP_EINVAL;
         if (p.m < 1 || p.m > M_MAX_1D) return PXP_EUNSUPPORTED;
         if (!(p.krylov_tol > 0.0)) return PXP_EINVAL;
-        if (p.nx > 256 && (p.nx & 1)) return PXP_EUNSUPPORTED;
+        if (!krylov_fits(p, false)) return PXP_EUNSUPPORTED;
         // diffusion part of the spectrum on the negative real axis
         const double h = p.L / p.nx, dt = p.T / (double)p.n_steps;
         if (dt * 4.0 * p.nu / (h * h) > 2.785) return PXP_EUNSTABLE_DT;
@@ -289,7 +301,7 @@ pxp_status direct_lin1d(const Ctx& c, const double* q0, const double* F,
         a.yout = c.at(c.L.pieces);
         {
             ProfScope ps(PXP_K_KRYLOV_DIRECT, c.s);
-            HIPCHK(launch_krylov1d(a, 0, c.s));
+            HIPCHK(launch_krylov1d(a, c.p.kblock, c.s));
         }
         // (3) superposition q(T) = q0 + v_{P-1} + sum_p pieces
         HIPCHK(launch_recombine(q0, slices + (size_t)(P - 1) * n, c.at(c.L.pieces),
@@ -301,7 +313,7 @@ pxp_status direct_lin1d(const Ctx& c, const double* q0, const double* F,
         a.yout = c.at(c.L.chain);
         {
             ProfScope ps(PXP_K_KRYLOV_DIRECT, c.s);
-            HIPCHK(launch_krylov1d(a, 0, c.s));
+            HIPCHK(launch_krylov1d(a, c.p.kblock, c.s));
         }
         HIPCHK(launch_recombine(q0, nullptr, c.at(c.L.chain), 1, n, qT, c.st, c.s));
     }
@@ -334,7 +346,7 @@ pxp_status adjoint_lin1d(const Ctx& c, const double* lamT, double* lam0,
     a.ib = -c.p.omega;
     if (!lam0 && !Lam) return PXP_OK;
     ProfScope ps(PXP_K_KRYLOV_ADJOINT, c.s);
-    HIPCHK(launch_krylov1d(a, 0, c.s));
+    HIPCHK(launch_krylov1d(a, c.p.kblock, c.s));
     return PXP_OK;
 }
 
@@ -380,7 +392,7 @@ pxp_status adjoint_burgers(const Ctx& c, const double* lamT, double* lam0,
     a.inv2h = 1.0 / (2.0 * h);
     a.nuh2 = c.p.nu / (h * h);
     ProfScope ps(PXP_K_LTV_ADJOINT, c.s);
-    HIPCHK(launch_krylov1d(a, 0, c.s));
+    HIPCHK(launch_krylov1d(a, c.p.kblock, c.s));
     return PXP_OK;
 }
 
@@ -489,6 +501,7 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
                                  hipStream_t s) {
     std::vector<BurgersDesc> tab;
     std::vector<KrylovArgs> ktab;
+    std::vector<int> kB;
     int q0 = 0;
     size_t lds = 0;
     for (size_t j = 0; j < bb.idx.size(); ++j) {
@@ -511,11 +524,21 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
         a.wop = d.nodes;
         a.inv2h = d.inv2h;
         a.nuh2 = d.nuh2;
-        a.pt = d.pt;
+        int B = 0, pt = 0;
+        krylov_shape_pub(p.nx, p.kblock, &B, &pt);  // validated
+        a.pt = pt;
         ktab.push_back(a);
-        const size_t l = krylov1d_lds_bytes(p.nx, p.m, 256, 0);
+        kB.push_back(B);
+        const size_t l = krylov1d_lds_bytes(p.nx, p.m, B, 0);
         if (l > lds) lds = l;
     }
+    // one launch per workgroup size, instances of a size contiguous
+    std::vector<int> order(ktab.size());
+    for (size_t j = 0; j < order.size(); ++j) order[j] = (int)j;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return kB[x] < kB[y]; });
+    std::vector<KrylovArgs> ksorted;
+    for (int j : order) ksorted.push_back(ktab[j]);
     auto* dtab = reinterpret_cast<BurgersDesc*>(static_cast<char*>(ws) + Ly.btab);
     HIPCHK(launch_upload(dtab, tab.data(), tab.size() * sizeof(BurgersDesc), s));
     if (method == PXP_METHOD_SERIAL) {
@@ -524,13 +547,18 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
         return PXP_OK;
     }
     auto* kt = reinterpret_cast<KrylovArgs*>(static_cast<char*>(ws) + Ly.ktab);
-    HIPCHK(launch_upload(kt, ktab.data(), ktab.size() * sizeof(KrylovArgs), s));
+    HIPCHK(launch_upload(kt, ksorted.data(), ksorted.size() * sizeof(KrylovArgs), s));
     {
         ProfScope ps(PXP_K_LTV_NODES, s);
         HIPCHK(launch_burgers_batch(2, dtab, (int)tab.size(), q0, bb.fp32, s));
     }
     ProfScope ps(PXP_K_LTV_ADJOINT, s);
-    HIPCHK(launch_krylov_ltv_batch(kt, nullptr, (int)ktab.size(), lds, s));
+    for (size_t j0 = 0; j0 < order.size();) {
+        size_t j1 = j0;
+        while (j1 < order.size() && kB[order[j1]] == kB[order[j0]]) ++j1;
+        HIPCHK(launch_krylov_ltv_batch(kt + j0, kB[order[j0]], (int)(j1 - j0), lds, s));
+        j0 = j1;
+    }
     return PXP_OK;
 }
 

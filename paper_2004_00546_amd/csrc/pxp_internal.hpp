@@ -107,7 +107,7 @@ struct KrylovArgs {
     double gamma_frac;   // shift-and-invert shift = gamma_frac * time
     Tri op;
     int fp32;            // operator stencil in FP32 (polynomial flavour)
-    int pt;              // batched launches: points per thread (256 threads)
+    int pt;              // batched launches: points per thread
     const double* wop;   // KM_LTV: effective states [2*npieces][n]
     double inv2h, nuh2;  // KM_LTV: 1/(2h), nu/h^2
     double* basis;       // [gridDim][m+1][n] workspace
@@ -115,8 +115,9 @@ struct KrylovArgs {
 };
 hipError_t launch_krylov1d(const KrylovArgs& a, int block, hipStream_t s);
 // Batched time-varying chains: workgroup i runs tab[i] (KM_LTV, polynomial),
-// 256 threads each; lds = the largest krylov1d_lds_bytes of the batch.
-hipError_t launch_krylov_ltv_batch(const KrylovArgs* tab, const int* pts, int count,
+// `block` threads each (every entry's shape has that workgroup size);
+// lds = the largest krylov1d_lds_bytes of the batch.
+hipError_t launch_krylov_ltv_batch(const KrylovArgs* tab, int block, int count,
                                    size_t lds, hipStream_t s);
 size_t krylov1d_lds_bytes(int n, int m, int block, int si);
 bool krylov_shape_pub(int n, int block_hint, int* B, int* pt);

@@ -32,10 +32,17 @@ constexpr int M_MAX_1D = 48;
 
 __host__ __device__ inline size_t big_doubles(int n, int m, int block) {
     const size_t vec = 2 * (size_t)n;
-    const size_t part = (size_t)(m + 1) * block;
+    const size_t part = (size_t)(m + 1) * ((block + 63) / 64);
     const size_t sm = 6 * (size_t)m * m + 5 * (size_t)m + 8;
     size_t b = vec > sm ? vec : sm;
     return b > part ? b : part;
+}
+
+// Largest workgroup a kernel instance with PT points per thread is compiled
+// for: the register budget per thread halves each time the wave count per
+// SIMD doubles.
+__host__ __device__ constexpr int krylov_max_block(int pt) {
+    return pt <= 8 ? 512 : 256;
 }
 
 struct Smem {
@@ -206,13 +213,20 @@ struct Ctx {
         }
     }
 
-    // hcol[k] = <V_k, z> for k <= j.  Per-thread partial sums go to LDS
-    // (layout [k][thread]) so the basis loads stream without waiting for
-    // shuffles; each wave then reduces a subset of k in a fixed order.
+    // hcol[k] = <V_k, z> for k <= j, four basis vectors at a time.  The four
+    // per-thread partial sums are reduced inside the wave by recursive
+    // halving (two exchange stages leave lane group g = lane/16 holding
+    // vector g, four more sum within the group); one lane per group writes
+    // the wave's partial to LDS (layout [k][wave]) and the waves' partials
+    // are added in a fixed order at the end, so the loads of the next four
+    // vectors never wait for a barrier.
     __device__ __forceinline__ void dots(const double (&z)[PT], int j) {
         double* P = S.big;
+        const int nw = num_waves(), w = wave_id(), lane = lane_id();
+        const bool up32 = (lane & 32) != 0, up16 = (lane & 16) != 0;
+        const int g = lane >> 4;
         __syncthreads();
-        constexpr int UK = (PT >= 16) ? 1 : 2;
+        constexpr int UK = (PT >= 8) ? 1 : 2;
 #pragma unroll UK
         for (int k0 = 0; k0 <= j; k0 += 4) {
             double part[4];
@@ -228,16 +242,21 @@ struct Ctx {
                 part[q] = s;
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (k0 + q <= j) P[(k0 + q) * B + t] = part[q];
+            for (int q = 0; q < 2; ++q) {
+                const double send = up32 ? part[q] : part[q + 2];
+                const double keep = up32 ? part[q + 2] : part[q];
+                part[q] = keep + __shfl_xor(send, 32, WAVE);
+            }
+            double s = (up16 ? part[1] : part[0]) + __shfl_xor(up16 ? part[0] : part[1], 16, WAVE);
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, WAVE);
+            if ((lane & 15) == 0 && k0 + g <= j) P[(k0 + g) * nw + w] = s;
         }
         __syncthreads();
-        const int lane = lane_id(), nw = num_waves();
-        for (int k = wave_id(); k <= j; k += nw) {
+        for (int k = t; k <= j; k += B) {
             double s = 0.0;
-            for (int u = lane; u < B; u += WAVE) s += P[k * B + u];
-            s = wave_sum(s);
-            if (lane == 0) S.hcol[k] = s;
+            for (int u = 0; u < nw; ++u) s += P[k * nw + u];
+            S.hcol[k] = s;
         }
         __syncthreads();
     }
@@ -558,22 +577,29 @@ __device__ __forceinline__ void dev_krylov1d(const KrylovArgs& a, int piece, dou
 }
 
 template <int PT, bool SI, bool VAR>
-__global__ void __launch_bounds__(256) k_krylov1d(KrylovArgs a) {
+__global__ void __launch_bounds__(krylov_max_block(PT)) k_krylov1d(KrylovArgs a) {
     extern __shared__ double lds[];
     dev_krylov1d<PT, SI, VAR>(a, blockIdx.x, lds);
 }
 
-// Ragged batch of time-varying chains: workgroup i runs instance i.
-__global__ void __launch_bounds__(256) k_krylov_ltv_batch(const KrylovArgs* tab) {
+// Ragged batch of time-varying chains: workgroup i runs instance i; all
+// instances of one launch share the workgroup size, compiled for at most NT.
+template <int PT, int NT>
+__device__ __forceinline__ void ltv_if(const KrylovArgs& a, double* lds) {
+    if constexpr (krylov_max_block(PT) >= NT) dev_krylov1d<PT, false, true>(a, 0, lds);
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_krylov_ltv_batch(const KrylovArgs* tab) {
     extern __shared__ double lds[];
     const KrylovArgs a = tab[blockIdx.x];
     switch (a.pt) {
-        case 1: dev_krylov1d<1, false, true>(a, 0, lds); break;
-        case 2: dev_krylov1d<2, false, true>(a, 0, lds); break;
-        case 4: dev_krylov1d<4, false, true>(a, 0, lds); break;
-        case 8: dev_krylov1d<8, false, true>(a, 0, lds); break;
-        case 16: dev_krylov1d<16, false, true>(a, 0, lds); break;
-        case 32: dev_krylov1d<32, false, true>(a, 0, lds); break;
+        case 1: ltv_if<1, NT>(a, lds); break;
+        case 2: ltv_if<2, NT>(a, lds); break;
+        case 4: ltv_if<4, NT>(a, lds); break;
+        case 8: ltv_if<8, NT>(a, lds); break;
+        case 16: ltv_if<16, NT>(a, lds); break;
+        case 32: ltv_if<32, NT>(a, lds); break;
         default: break;
     }
 }
@@ -603,13 +629,20 @@ hipError_t launch_pt(const KrylovArgs& a, int B, int pt, int grid, size_t lds,
     return hipGetLastError();
 }
 
+bool pow2_pt(int p) { return p == 1 || p == 2 || p == 4 || p == 8 || p == 16 || p == 32; }
+
+// Workgroup size B and points per thread pt for n points.  With a hint the
+// hint is the workgroup size (a multiple of 64, at most 512, cut to n);
+// without one, 512 threads where that shape exists (more waves in flight per
+// compute unit for the basis streams), else 256.
 bool krylov_shape(int n, int block_hint, int* B, int* pt) {
+    if (block_hint <= 0)
+        return krylov_shape(n, 512, B, pt) || krylov_shape(n, 256, B, pt);
     int b = block_hint;
-    if (b <= 0) b = 256;
     if (b > n) b = ((n + 63) / 64) * 64;
-    if (b % 64 || b > 256) return false;
+    if (b % 64 || b > 512) return false;
     const int p = (n + b - 1) / b;
-    if (!(p == 1 || p == 2 || p == 4 || p == 8 || p == 16 || p == 32)) return false;
+    if (!pow2_pt(p) || b > krylov_max_block(p)) return false;
     *B = b;
     *pt = p;
     return true;
@@ -624,14 +657,22 @@ size_t krylov1d_lds_bytes(int n, int m, int block, int si) {
     return d * sizeof(double);
 }
 
-hipError_t launch_krylov_ltv_batch(const KrylovArgs* tab, const int* pts, int count,
+hipError_t launch_krylov_ltv_batch(const KrylovArgs* tab, int block, int count,
                                    size_t lds, hipStream_t s) {
-    (void)pts;
     if (count <= 0) return hipSuccess;
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipFuncSetAttribute((const void*)k_krylov_ltv_batch,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_krylov_ltv_batch<<<count, 256, lds, s>>>(tab);
+    if (lds > 160 * 1024 || block % 64 || block <= 0 || block > 512)
+        return hipErrorInvalidValue;
+#define PXP_LTV(NTV)                                                               \
+    {                                                                            \
+        hipFuncSetAttribute((const void*)k_krylov_ltv_batch<NTV>,                \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        k_krylov_ltv_batch<NTV><<<count, block, lds, s>>>(tab);                   \
+    }
+    if (block <= 256)
+        PXP_LTV(256)
+    else
+        PXP_LTV(512)
+#undef PXP_LTV
     return hipGetLastError();
 }
 

@@ -49,7 +49,7 @@ def test_version_and_status_strings(lib):
 
 def test_struct_layout_matches_header():
     # 12 int32, 1 int64, 9 doubles
-    assert ctypes.sizeof(_lib.pxp_problem) == 12 * 4 + 8 + 9 * 8
+    assert ctypes.sizeof(_lib.pxp_problem) == 14 * 4 + 8 + 9 * 8
 
 
 def _size_status(probs):
