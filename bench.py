@@ -89,7 +89,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="advdiff1d_n4096")
-    ap.add_argument("--krylov", default=None, choices=["poly", "shift_invert"])
+    ap.add_argument("--krylov", default="auto", choices=["poly", "shift_invert", "auto"])
     ap.add_argument("--sched", default="classic", choices=["classic", "chain"])
     ap.add_argument("--serial-steps", type=int, default=5)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32_bulk"])
@@ -139,9 +139,6 @@ def main():
     log("workload %s: %d instance(s); first N=%d steps=%d P=%d m=%d; point-steps %.3g"
         % (args.workload, B, n, n_steps, P, m, sum(work)))
 
-    if args.krylov is None:
-        # shift-and-invert needs a constant-coefficient tridiagonal operator
-        args.krylov = "shift_invert" if inst["op"] == "advdiff1d" else "poly"
     tol = args.tol if args.tol is not None else (1e-10 if args.prec == "fp64" else 1e-6)
     kw = dict(prec=args.prec, block=args.block, kblock=args.kblock)
     pxp = api.GradientRunner(insts, method="paraexp", krylov=args.krylov,

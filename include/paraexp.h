@@ -75,7 +75,10 @@ enum { PXP_FP64 = 0, PXP_FP32_BULK = 1 };
  * (eq. initupdate). */
 enum { PXP_CTRL_FORCING = 0, PXP_CTRL_IC = 1 };
 /* Krylov flavour for the homogeneous exponentials. */
-enum { PXP_KRYLOV_POLY = 0, PXP_KRYLOV_SHIFT_INVERT = 1 };
+/* AUTO: shift-and-invert when tau * rho > 64 (rho = 4 nu/h^2 + |vx|/h, tau
+ * the horizon for the linear pieces or half a slice for the Burgers Magnus
+ * factors) and the grid has the cyclic-reduction shape, else polynomial. */
+enum { PXP_KRYLOV_POLY = 0, PXP_KRYLOV_SHIFT_INVERT = 1, PXP_KRYLOV_AUTO = 2 };
 /* Schedule of the direct homogeneous pieces: CLASSIC = P-1 independent
  * pieces exp((T - T_{p+1}) A) v_p (eq. hom); CHAIN = nested sum
  * w <- exp(dT A) w + v_p, one piece after the other. */

@@ -70,6 +70,25 @@ bool rk4_stable_advdiff1d(const pxp_problem& p) {
     return true;
 }
 
+// Krylov flavour of a problem.  AUTO takes shift-and-invert where the
+// polynomial space would need many dimensions or substeps: when tau * rho,
+// rho = 4 nu / h^2 + |c| / h the spectral radius bound of the diffusion and
+// advection stencil and tau the longest exponential the call takes (the
+// horizon for the linear pieces, half a slice for the Magnus factors),
+// exceeds 64, and the grid allows the cyclic-reduction shape.
+bool use_si(const pxp_problem& p) {
+    if (p.krylov == PXP_KRYLOV_SHIFT_INVERT) return true;
+    if (p.krylov != PXP_KRYLOV_AUTO) return false;
+    const double h = p.L / p.nx;
+    const double rho = 4.0 * p.nu / (h * h) + std::fabs(p.vx) / h;
+    const double tau = p.op == PXP_OP_BURGERS1D ? 0.5 * p.T / p.P : p.T;
+    if (!(tau * rho > 64.0)) return false;
+    int B, pt;
+    if (!krylov_shape_pub(p.nx, p.kblock, &B, &pt)) return false;
+    if (pt * B != p.nx || (B & (B - 1))) return false;
+    return p.op == PXP_OP_BURGERS1D || (is_pow2(p.nx) && p.nx >= 64);
+}
+
 // The Krylov kernels' workgroup shape for this problem exists, fits in LDS,
 // reads two consecutive points per 16-byte load (even n once a thread owns
 // more than one point) and, for shift-and-invert, covers the grid exactly.
@@ -77,7 +96,7 @@ bool krylov_fits(const pxp_problem& p, bool si) {
     int B, pt;
     if (!krylov_shape_pub(p.nx, p.kblock, &B, &pt)) return false;
     if (pt >= 2 && (p.nx & 1)) return false;
-    if (si && pt * B != p.nx) return false;
+    if (si && (pt * B != p.nx || (B & (B - 1)))) return false;
     return krylov1d_lds_bytes(p.nx, p.m, B, si) <= 160 * 1024;
 }
 
@@ -88,7 +107,8 @@ pxp_status validate(const pxp_problem& p) {
         return PXP_EINVAL;
     if (p.n_steps % p.P != 0) return PXP_EINVAL;
     if (p.ctrl != PXP_CTRL_FORCING && p.ctrl != PXP_CTRL_IC) return PXP_EINVAL;
-    if (p.krylov != PXP_KRYLOV_POLY && p.krylov != PXP_KRYLOV_SHIFT_INVERT)
+    if (p.krylov != PXP_KRYLOV_POLY && p.krylov != PXP_KRYLOV_SHIFT_INVERT &&
+        p.krylov != PXP_KRYLOV_AUTO)
         return PXP_EINVAL;
     if (p.sched != PXP_SCHED_CLASSIC && p.sched != PXP_SCHED_CHAIN) return PXP_EINVAL;
     if (p.prec != PXP_FP64 && p.prec != PXP_FP32_BULK) return PXP_EINVAL;
@@ -100,10 +120,9 @@ pxp_status validate(const pxp_problem& p) {
         if (!march_shape(p.nx, p.block, &b, &pt)) return PXP_EUNSUPPORTED;
         // cyclic reduction: n a power of two, every thread of a 64-wide
         // multiple owning whole points
-        if (p.krylov == PXP_KRYLOV_SHIFT_INVERT && (!is_pow2(p.nx) || p.nx < 64))
-            return PXP_EUNSUPPORTED;
+        if (use_si(p) && (!is_pow2(p.nx) || p.nx < 64)) return PXP_EUNSUPPORTED;
         if (!(p.krylov_tol > 0.0)) return PXP_EINVAL;
-        if (!krylov_fits(p, p.krylov == PXP_KRYLOV_SHIFT_INVERT)) return PXP_EUNSUPPORTED;
+        if (!krylov_fits(p, use_si(p))) return PXP_EUNSUPPORTED;
         if (!rk4_stable_advdiff1d(p)) return PXP_EUNSTABLE_DT;
         return PXP_OK;
     }
@@ -115,7 +134,7 @@ pxp_status validate(const pxp_problem& p) {
         if (p.ckpt_every < 1 || p.n_steps % p.ckpt_every) return PXP_EINVAL;
         if (p.m < 1 || p.m > M_MAX_1D) return PXP_EUNSUPPORTED;
         if (!(p.krylov_tol > 0.0)) return PXP_EINVAL;
-        if (!krylov_fits(p, false)) return PXP_EUNSUPPORTED;
+        if (!krylov_fits(p, use_si(p))) return PXP_EUNSUPPORTED;
         // diffusion part of the spectrum on the negative real axis
         const double h = p.L / p.nx, dt = p.T / (double)p.n_steps;
         if (dt * 4.0 * p.nu / (h * h) > 2.785) return PXP_EUNSTABLE_DT;
@@ -155,7 +174,9 @@ Inst inst_layout(const pxp_problem& p) {
         L.ckpt = take(((size_t)p.n_steps / c + 1) * n * d);
         L.seg = take(c * n * d);
         L.nodes = take(2 * P * n * d);
-        L.basis = take((m + 1) * n * d);
+        // basis, then the shift-and-invert factors of the time-varying
+        // operator (5 n + 5 B doubles, B <= 512)
+        L.basis = take(((m + 6) * n + 5 * 512) * d);
     }
     L.size = off;
     return L;
@@ -247,7 +268,7 @@ struct Ctx {
 
 KrylovArgs kargs(const Ctx& c, Tri op) {
     KrylovArgs a{};
-    a.si = (c.p.krylov == PXP_KRYLOV_SHIFT_INVERT) ? 1 : 0;
+    a.si = use_si(c.p) ? 1 : 0;
     a.n = c.n();
     a.m = c.p.m;
     a.tol = c.p.krylov_tol;
@@ -382,7 +403,7 @@ pxp_status adjoint_burgers(const Ctx& c, const double* lamT, double* lam0,
                                     c.p.L, c.p.block, c.fp32(), c.s));
     }
     KrylovArgs a = kargs(c, Tri{0.0, 0.0, 0.0});
-    a.si = 0;
+    a.si = use_si(c.p) ? 1 : 0;
     a.mode = KM_LTV;
     a.npieces = c.p.P;
     a.vin = lamT;
@@ -515,7 +536,7 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
         q0 += p.P;
         tab.push_back(d);
         KrylovArgs a = kargs(c, Tri{0.0, 0.0, 0.0});
-        a.si = 0;
+        a.si = use_si(p) ? 1 : 0;
         a.mode = KM_LTV;
         a.npieces = p.P;
         a.vin = lamT[j];

@@ -31,7 +31,10 @@ namespace {
 constexpr int M_MAX_1D = 48;
 
 __host__ __device__ inline size_t big_doubles(int n, int m, int block) {
-    const size_t vec = 2 * (size_t)n;
+    size_t vec = 2 * (size_t)n;
+    // variable-coefficient solve: padded chunks (n + B) and 8 B for the
+    // interface reduction
+    if ((size_t)n + 9 * (size_t)block > vec) vec = (size_t)n + 9 * (size_t)block;
     const size_t part = (size_t)(m + 1) * ((block + 63) / 64);
     const size_t sm = 6 * (size_t)m * m + 5 * (size_t)m + 8;
     size_t b = vec > sm ? vec : sm;
@@ -75,6 +78,10 @@ struct Ctx {
     int n, m, B, t, ldr;
     Tsplit op;
     const double* Wcur = nullptr;  // VAR: state W of the operator J(W)^T
+    // VAR && SI: factors of (I - gamma J(W)^T) for the current W, in global
+    // memory after the basis: lo, piv, cp, g, h ([l][chunk], 5n doubles),
+    // then the interface rows RA, RB, RC and lo, up at the chunk starts (5B)
+    double* aux = nullptr;
 
     __device__ Ctx(const KrylovArgs& a_, double* lds, double* V_)
         : a(a_), V(V_), n(a_.n), m(a_.m), B(blockDim.x), t(threadIdx.x) {
@@ -135,7 +142,9 @@ struct Ctx {
             for (int v = 0; v < VW; ++v)
                 if (own(r)) b0[gidx(r) + v] = z[r * VW + v];
         __syncthreads();
-        if (VAR) {
+        if (VAR && SI) {
+            var_solve(z);
+        } else if (VAR) {
             // (J(W)^T x)_i = ((W x)_{i+1} - (W x)_{i-1})/(2h)
             //               - (W_{i+1} - W_{i-1}) x_i/(2h) + nu lap(x)_i
 #pragma unroll
@@ -213,25 +222,207 @@ struct Ctx {
         }
     }
 
-    // hcol[k] = <V_k, z> for k <= j, four basis vectors at a time.  The four
-    // per-thread partial sums are reduced inside the wave by recursive
-    // halving (two exchange stages leave lane group g = lane/16 holding
-    // vector g, four more sum within the group); one lane per group writes
-    // the wave's partial to LDS (layout [k][wave]) and the waves' partials
-    // are added in a fixed order at the end, so the loads of the next four
-    // vectors never wait for a barrier.
+    // Row i of (I - gamma J(W)^T): lo x_{i-1} + d x_i + up x_{i+1}, with
+    // (J(W)^T x)_i = (W_{i+1} x_{i+1} - W_{i-1} x_{i-1})/(2h)
+    //               - (W_{i+1} - W_{i-1}) x_i/(2h) + nu (x_{i+1} - 2x_i + x_{i-1})/h^2.
+    __device__ __forceinline__ void var_row(int i, double gamma, double& lo, double& d,
+                                            double& up) const {
+        const int im = i == 0 ? n - 1 : i - 1, ip = i == n - 1 ? 0 : i + 1;
+        const double Wm = Wcur[im], Wp = Wcur[ip];
+        lo = -gamma * (a.nuh2 - a.inv2h * Wm);
+        up = -gamma * (a.nuh2 + a.inv2h * Wp);
+        d = 1.0 + gamma * (2.0 * a.nuh2 + a.inv2h * (Wp - Wm));
+    }
+
+    // Partitioned solve of the periodic tridiagonal system (I - gamma J^T):
+    // thread k owns the PT consecutive points of chunk k (B * PT = n).  The
+    // chunk's interior points 1..PT-1 are a tridiagonal block coupled only to
+    // the chunk's first point x_k and the next chunk's first point x_{k+1}:
+    //   interior = y + g x_k + h x_{k+1},
+    // y the block solve of the right-hand side, g and h its responses to the
+    // two couplings.  Substituting into the rows of the chunk starts leaves a
+    // periodic tridiagonal system in the B values x_k, solved by parallel
+    // cyclic reduction in LDS.  si_setup factors everything that depends only
+    // on W and gamma (Thomas pivots of the blocks, g, h, the interface rows)
+    // once per Krylov space.
+    __device__ __forceinline__ void si_setup(double gamma) {
+        const int k = t, Bn = B;
+        double* ex = S.big + n + B;  // 2B exchange slots
+        double lo[PT], dd[PT], up[PT];
+#pragma unroll
+        for (int l = 0; l < PT; ++l) var_row(k * PT + l, gamma, lo[l], dd[l], up[l]);
+        double g1 = 0.0, h1 = 0.0, glast = 0.0, hlast = 0.0;
+        if constexpr (PT > 1) {
+            double piv[PT], cp[PT], gp[PT], g[PT], h[PT];
+            piv[1] = 1.0 / dd[1];
+            cp[1] = up[1] * piv[1];
+            gp[1] = -lo[1] * piv[1];
+#pragma unroll
+            for (int l = 2; l < PT; ++l) {
+                piv[l] = 1.0 / (dd[l] - lo[l] * cp[l - 1]);
+                cp[l] = up[l] * piv[l];
+                gp[l] = -lo[l] * gp[l - 1] * piv[l];
+            }
+            g[PT - 1] = gp[PT - 1];
+            h[PT - 1] = -up[PT - 1] * piv[PT - 1];
+#pragma unroll
+            for (int l = PT - 2; l >= 1; --l) {
+                g[l] = gp[l] - cp[l] * g[l + 1];
+                h[l] = -cp[l] * h[l + 1];
+            }
+#pragma unroll
+            for (int l = 1; l < PT; ++l) {
+                aux[(size_t)l * Bn + k] = lo[l];
+                aux[(size_t)n + (size_t)l * Bn + k] = piv[l];
+                aux[2 * (size_t)n + (size_t)l * Bn + k] = cp[l];
+                aux[3 * (size_t)n + (size_t)l * Bn + k] = g[l];
+                aux[4 * (size_t)n + (size_t)l * Bn + k] = h[l];
+            }
+            g1 = g[1];
+            h1 = h[1];
+            glast = g[PT - 1];
+            hlast = h[PT - 1];
+        }
+        __syncthreads();
+        ex[k] = glast;
+        ex[Bn + k] = hlast;
+        __syncthreads();
+        const int km = k == 0 ? Bn - 1 : k - 1;
+        double* RI = aux + 5 * (size_t)n;
+        if (PT > 1) {
+            RI[k] = lo[0] * ex[km];
+            RI[Bn + k] = dd[0] + lo[0] * ex[Bn + km] + up[0] * g1;
+            RI[2 * Bn + k] = up[0] * h1;
+        } else {
+            RI[k] = lo[0];
+            RI[Bn + k] = dd[0];
+            RI[2 * Bn + k] = up[0];
+        }
+        RI[3 * Bn + k] = lo[0];
+        RI[4 * Bn + k] = up[0];
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ void var_solve(double (&z)[PT]) {
+        const int k = t, Bn = B;
+        double* X = S.big;          // chunk k at k * (PT + 1), one pad per chunk
+        double* Q = X + n + Bn;     // two buffers of a, b, c, d (8B)
+        // the caller's barrier at the top of apply() has freed `big`
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                const int i = gidx(r) + v;
+                X[(i / PT) * (PT + 1) + (i % PT)] = z[r * VW + v];
+            }
+        __syncthreads();
+        double rr[PT], y[PT];
+#pragma unroll
+        for (int l = 0; l < PT; ++l) rr[l] = X[k * (PT + 1) + l];
+        const double* RI = aux + 5 * (size_t)n;
+        double ca = RI[k], cb = RI[Bn + k], cc = RI[2 * Bn + k];
+        double rhs = rr[0];
+        if constexpr (PT > 1) {
+            y[1] = rr[1] * aux[(size_t)n + Bn + k];
+#pragma unroll
+            for (int l = 2; l < PT; ++l)
+                y[l] = (rr[l] - aux[(size_t)l * Bn + k] * y[l - 1]) *
+                       aux[(size_t)n + (size_t)l * Bn + k];
+#pragma unroll
+            for (int l = PT - 2; l >= 1; --l)
+                y[l] -= aux[2 * (size_t)n + (size_t)l * Bn + k] * y[l + 1];
+            Q[k] = y[PT - 1];
+            __syncthreads();
+            const int km = k == 0 ? Bn - 1 : k - 1;
+            rhs = rr[0] - RI[3 * Bn + k] * Q[km] - RI[4 * Bn + k] * y[1];
+            __syncthreads();
+        }
+        // parallel cyclic reduction on the B interface rows: level s removes
+        // the couplings to k - s and k + s using rows k - s and k + s
+        int buf = 0;
+        for (int sft = 1; 2 * sft < Bn; sft <<= 1) {
+            double* A4 = Q + buf * 4 * Bn;
+            A4[k] = ca;
+            A4[Bn + k] = cb;
+            A4[2 * Bn + k] = cc;
+            A4[3 * Bn + k] = rhs;
+            __syncthreads();
+            const int km = (k - sft) & (Bn - 1), kp = (k + sft) & (Bn - 1);
+            const double al = -ca / A4[Bn + km], be = -cc / A4[Bn + kp];
+            const double na = al * A4[km], nc = be * A4[2 * Bn + kp];
+            cb = cb + al * A4[2 * Bn + km] + be * A4[kp];
+            rhs = rhs + al * A4[3 * Bn + km] + be * A4[3 * Bn + kp];
+            ca = na;
+            cc = nc;
+            buf ^= 1;
+        }
+        // rows k and k + B/2 now couple only to each other
+        double* A4 = Q + buf * 4 * Bn;
+        const double e = ca + cc;
+        A4[k] = e;
+        A4[Bn + k] = cb;
+        A4[3 * Bn + k] = rhs;
+        __syncthreads();
+        const int kh = (k + Bn / 2) & (Bn - 1);
+        const double xk = (A4[Bn + kh] * rhs - e * A4[3 * Bn + kh]) /
+                          (cb * A4[Bn + kh] - e * A4[kh]);
+        // back-substitution into the chunk interiors
+        double* xs = Q + (buf ^ 1) * 4 * Bn;
+        xs[k] = xk;
+        __syncthreads();
+        const double xn = xs[(k + 1) & (Bn - 1)];
+        X[k * (PT + 1)] = xk;
+#pragma unroll
+        for (int l = 1; l < PT; ++l)
+            X[k * (PT + 1) + l] = y[l] + aux[3 * (size_t)n + (size_t)l * Bn + k] * xk +
+                                  aux[4 * (size_t)n + (size_t)l * Bn + k] * xn;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                const int i = gidx(r) + v;
+                z[r * VW + v] = X[(i / PT) * (PT + 1) + (i % PT)];
+            }
+    }
+
+    // hcol[k] = <V_k, z> for k <= j, KD basis vectors at a time (8, or 4
+    // when a thread owns 8 or more points).  The KD per-thread partial sums
+    // are reduced inside the wave by recursive halving (log2 KD exchange
+    // stages leave lane group g = lane / (64/KD) holding vector g, the
+    // remaining stages sum within the group); one lane per group writes the
+    // wave's partial to LDS (layout [k][wave]) and the waves' partials are
+    // added in a fixed order at the end, so the loads of the next vectors
+    // never wait for a barrier.
+    template <int KD, int O>
+    __device__ __forceinline__ void halve(double (&part)[KD], int lane) const {
+        if constexpr (KD > 1) {
+            constexpr int H = KD / 2;
+            const bool up = (lane & O) != 0;
+            double nxt[H];
+#pragma unroll
+            for (int q = 0; q < H; ++q) {
+                const double send = up ? part[q] : part[q + H];
+                const double keep = up ? part[q + H] : part[q];
+                nxt[q] = keep + __shfl_xor(send, O, WAVE);
+            }
+#pragma unroll
+            for (int q = 0; q < H; ++q) part[q] = nxt[q];
+            halve<H, O / 2>(reinterpret_cast<double(&)[H]>(part), lane);
+        }
+    }
+
     __device__ __forceinline__ void dots(const double (&z)[PT], int j) {
+        constexpr int KD = (PT >= 8) ? 4 : 8;
+        constexpr int GS = WAVE / KD;  // lanes per group after the exchanges
         double* P = S.big;
         const int nw = num_waves(), w = wave_id(), lane = lane_id();
-        const bool up32 = (lane & 32) != 0, up16 = (lane & 16) != 0;
-        const int g = lane >> 4;
+        const int g = lane / GS;
         __syncthreads();
-        constexpr int UK = (PT >= 8) ? 1 : 2;
-#pragma unroll UK
-        for (int k0 = 0; k0 <= j; k0 += 4) {
-            double part[4];
+        for (int k0 = 0; k0 <= j; k0 += KD) {
+            double part[KD];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < KD; ++q) {
                 double s = 0.0;
                 if (k0 + q <= j) {
                     double x[PT];
@@ -241,16 +432,11 @@ struct Ctx {
                 }
                 part[q] = s;
             }
+            halve<KD, 32>(part, lane);
+            double s = part[0];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const double send = up32 ? part[q] : part[q + 2];
-                const double keep = up32 ? part[q + 2] : part[q];
-                part[q] = keep + __shfl_xor(send, 32, WAVE);
-            }
-            double s = (up16 ? part[1] : part[0]) + __shfl_xor(up16 ? part[0] : part[1], 16, WAVE);
-#pragma unroll
-            for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, WAVE);
-            if ((lane & 15) == 0 && k0 + g <= j) P[(k0 + g) * nw + w] = s;
+            for (int o = GS / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, WAVE);
+            if ((lane % GS) == 0 && k0 + g <= j) P[(k0 + g) * nw + w] = s;
         }
         __syncthreads();
         for (int k = t; k <= j; k += B) {
@@ -457,6 +643,7 @@ struct Ctx {
         const double tol = a.tol;
         if (SI) {
             const double gamma = a.gamma_frac * tau;
+            if (VAR) si_setup(gamma);
             double beta;
             bool bd;
             const int me = arnoldi(gamma, beta, bd);
@@ -556,6 +743,7 @@ __device__ __forceinline__ void dev_krylov1d(const KrylovArgs& a, int piece, dou
                    : (a.mode == KM_LTV) ? 2 * a.npieces : 1;
     const double tau = (a.mode == KM_CLASSIC) ? (double)(a.npieces - piece) * a.tau : a.tau;
     double* iout = (a.mode == KM_SINGLE) ? a.iout : nullptr;
+    if (VAR && SI) c.aux = V + (size_t)(a.m + 1) * n;
     for (int q = 0; q < nexp; ++q) {
         if (VAR) c.Wcur = a.wop + (size_t)q * n;
         c.expv(tau, a.ia, a.ib, iout);
@@ -586,7 +774,12 @@ __global__ void __launch_bounds__(krylov_max_block(PT)) k_krylov1d(KrylovArgs a)
 // instances of one launch share the workgroup size, compiled for at most NT.
 template <int PT, int NT>
 __device__ __forceinline__ void ltv_if(const KrylovArgs& a, double* lds) {
-    if constexpr (krylov_max_block(PT) >= NT) dev_krylov1d<PT, false, true>(a, 0, lds);
+    if constexpr (krylov_max_block(PT) >= NT) {
+        if (a.si)
+            dev_krylov1d<PT, true, true>(a, 0, lds);
+        else
+            dev_krylov1d<PT, false, true>(a, 0, lds);
+    }
 }
 
 template <int NT>
@@ -611,7 +804,7 @@ hipError_t launch_pt(const KrylovArgs& a, int B, int pt, int grid, size_t lds,
 #define PXP_K(PTV)                                                               \
     case PTV: {                                                                \
         auto kern = k_krylov1d<PTV, SI, VAR>;                                 \
-        hipFuncSetAttribute((const void*)kern,                                 \
+        (void)hipFuncSetAttribute((const void*)kern,                                 \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
         kern<<<grid, B, lds, s>>>(a);                                          \
         break;                                                                 \
@@ -664,7 +857,7 @@ hipError_t launch_krylov_ltv_batch(const KrylovArgs* tab, int block, int count,
         return hipErrorInvalidValue;
 #define PXP_LTV(NTV)                                                               \
     {                                                                            \
-        hipFuncSetAttribute((const void*)k_krylov_ltv_batch<NTV>,                \
+        (void)hipFuncSetAttribute((const void*)k_krylov_ltv_batch<NTV>,                \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
         k_krylov_ltv_batch<NTV><<<count, block, lds, s>>>(tab);                   \
     }
@@ -682,7 +875,7 @@ bool krylov_shape_pub(int n, int block_hint, int* B, int* pt) {
 
 hipError_t launch_krylov1d(const KrylovArgs& a, int block_hint, hipStream_t s) {
     if (a.m < 1 || a.m > M_MAX_1D || a.n < 2) return hipErrorInvalidValue;
-    if (a.si && (a.n & (a.n - 1))) return hipErrorInvalidValue;
+    if (a.si && a.mode != KM_LTV && (a.n & (a.n - 1))) return hipErrorInvalidValue;
     int B, pt;
     if (!krylov_shape(a.n, block_hint, &B, &pt)) return hipErrorInvalidValue;
     if (a.si && pt * B != a.n) return hipErrorInvalidValue;
@@ -693,8 +886,10 @@ hipError_t launch_krylov1d(const KrylovArgs& a, int block_hint, hipStream_t s) {
     const int grid = (a.mode == KM_CLASSIC) ? a.npieces : 1;
     if (grid <= 0) return hipSuccess;
     if (a.mode == KM_LTV) {
-        if (a.si || !a.wop) return hipErrorInvalidValue;
-        return launch_pt<false, true>(a, B, pt, grid, lds, s);
+        if (!a.wop) return hipErrorInvalidValue;
+        if (a.si && (B & (B - 1))) return hipErrorInvalidValue;
+        return a.si ? launch_pt<true, true>(a, B, pt, grid, lds, s)
+                    : launch_pt<false, true>(a, B, pt, grid, lds, s);
     }
     return a.si ? launch_pt<true, false>(a, B, pt, grid, lds, s)
                 : launch_pt<false, false>(a, B, pt, grid, lds, s);

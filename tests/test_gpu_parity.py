@@ -360,3 +360,76 @@ def test_ragged_workload_sample_vs_oracle(torch, orc):
         e = rel(b["grad"], want["grad"])
         say("ragged workload n=%d nt=%d fp32 grad %.2e" % (inst["nx"], inst["n_steps"], e))
         assert e < FP32_GATE
+
+
+# ---- shift-and-invert Magnus factors for the Burgers adjoint ---------------
+# (I - gamma J(W)^T) is periodic tridiagonal with variable coefficients; the
+# kernel solves it by chunk elimination plus cyclic reduction of the chunk
+# interfaces.  n = 256 and 512 give one point per thread (the interface
+# system is the whole system), larger n give 2 and 4 points per chunk.
+
+@pytest.mark.parametrize("n", [256, 512, 1024, 2048])
+def test_burgers_shift_invert_matches_oracle(torch, orc, n):
+    nu = 0.02 if n <= 512 else 0.01
+    dt = 0.8 * workloads.burgers_dt_bound(n, nu)
+    nt = 64 * int(math.ceil(0.4 / (64 * dt)))
+    inst = small_burgers(n=n, T=0.4, nt=nt, P=nt // 4 if nt // 4 <= 64 else 64,
+                         nu=nu, seed=50 + n, ckpt=16)
+    if nt % inst["P"]:
+        inst["P"] = 16
+    got = run(inst, "paraexp", krylov="shift_invert")
+    want = orc.gradient(inst)
+    e = rel(got["grad"], want["grad"])
+    say("burgers SI n=%d nt=%d P=%d: grad %.2e lam0 %.2e" % (
+        n, nt, inst["P"], e, rel(got["lam"], want["lam0"])))
+    assert e < FP64_GATE
+
+
+def test_burgers_shift_invert_workload(torch, orc):
+    inst = workloads.make("burgers1d_n2048")[0]
+    got = run(inst, "paraexp", krylov="shift_invert")
+    want = orc.gradient(inst)
+    e = rel(got["grad"], want["grad"])
+    say("burgers SI C3: grad %.2e" % e)
+    assert e < FP64_GATE
+
+
+def test_ragged_burgers_shift_invert_batch(torch, orc):
+    """Batched shift-and-invert equals one-by-one runs bitwise and the
+    polynomial-Krylov result at the same macro steps (both flavours compute
+    the same Magnus factors); against the oracle with macro steps of two RK4
+    steps, so that the Magnus error stays far below the gate."""
+    insts = ragged_burgers(seed=60)
+    r = api.GradientRunner(insts, method="paraexp", krylov="shift_invert")
+    r.run()
+    code, _ = r.status()
+    assert code == 0
+    for inst, b in zip(insts, r.results()):
+        one = run(inst, "paraexp", krylov="shift_invert")
+        assert np.array_equal(one["grad"], b["grad"]), inst["nx"]
+        poly = run(inst, "paraexp", krylov="poly")
+        d = rel(b["grad"], poly["grad"])
+        fine = dict(inst, P=inst["n_steps"] // 2)
+        sif = run(fine, "paraexp", krylov="shift_invert")
+        want = orc.gradient(inst)["grad"]
+        say("ragged SI n=%d P=%d: SI vs poly %.2e; vs oracle SI %.2e poly %.2e; P=%d SI %.2e"
+            % (inst["nx"], inst["P"], d, rel(b["grad"], want), rel(poly["grad"], want),
+               fine["P"], rel(sif["grad"], want)))
+        assert d < 1e-9
+        assert rel(sif["grad"], want) < FP64_GATE
+
+
+def test_auto_flavour_ragged_equals_explicit_choice(torch):
+    """AUTO picks shift-and-invert per instance where half a slice times the
+    diffusion spectral radius exceeds 64, else the polynomial space; each
+    batched result equals the run with that flavour named explicitly."""
+    insts = ragged_burgers(seed=70)
+    insts[2] = dict(insts[2], P=insts[2]["n_steps"] // 64)  # long macro steps
+    r = api.GradientRunner(insts, method="paraexp", krylov="auto")
+    r.run()
+    assert r.status()[0] == 0
+    for inst, b in zip(insts, r.results()):
+        h = inst["L"] / inst["nx"]
+        si = 0.5 * inst["T"] / inst["P"] * 4 * inst["nu"] / h**2 > 64
+        one = run(inst, "paraexp", krylov="shift_invert" if si else "poly")
+        assert np.array_equal(one["grad"], b["grad"]), (inst["nx"], si)
