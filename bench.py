@@ -143,7 +143,7 @@ def main():
     kw = dict(prec=args.prec, block=args.block, kblock=args.kblock)
     pxp = api.GradientRunner(insts, method="paraexp", krylov=args.krylov,
                              sched=args.sched, tol=tol, **kw)
-    ser = api.GradientRunner(insts, method="serial", **kw)
+    ser = api.GradientRunner(insts, method="serial", krylov="auto", **kw)
 
     # timed Paraexp region, with per-kernel events on the library's stream
     for _ in range(args.warmup):

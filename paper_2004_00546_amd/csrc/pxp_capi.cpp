@@ -23,7 +23,7 @@ inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
     size_t status;             // DevStatus
-    size_t btab, ktab;         // ragged Burgers batch tables
+    size_t btab, ktab, t2d;    // batch tables: Burgers, Krylov, 2D marches
     std::vector<size_t> base;  // per-instance region offset
     size_t total;
 };
@@ -31,7 +31,7 @@ struct Layout {
 // Per-instance buffers (offsets relative to the instance region).
 struct Inst {
     size_t F, g0, q0eff, slices, pieces, basis, qT, lamT, lam0, Lam, chain,
-        ckpt, seg, nodes, J, size;
+        ckpt, seg, nodes, sbuf0, sbuf1, J, size;
 };
 
 int64_t grid_n(const pxp_problem& p) { return (int64_t)p.nx * (int64_t)p.ny; }
@@ -52,6 +52,48 @@ Tri transpose(Tri A) {
     B.d = A.d;
     B.up = A.lo;
     return B;
+}
+
+// First-order upwind advection (vx, vy >= 0) and the five-point Laplacian.
+Sten5 advdiff2d_sten(const pxp_problem& p) {
+    const double hx = p.L / p.nx, hy = p.L / p.ny;
+    Sten5 A;
+    A.w = p.vx / hx + p.nu / (hx * hx);
+    A.e = p.nu / (hx * hx);
+    A.s = p.vy / hy + p.nu / (hy * hy);
+    A.n = p.nu / (hy * hy);
+    A.c = -p.vx / hx - p.vy / hy - 2.0 * p.nu / (hx * hx) - 2.0 * p.nu / (hy * hy);
+    return A;
+}
+Sten5 transpose5(Sten5 A) {
+    Sten5 B = A;
+    B.w = A.e;
+    B.e = A.w;
+    B.s = A.n;
+    B.n = A.s;
+    return B;
+}
+
+// max |R(dt lambda)| <= 1 for RK4 over the exact eigenvalues of the 2D
+// upwind operator (block circulant).
+bool rk4_stable_advdiff2d(const pxp_problem& p) {
+    const double hx = p.L / p.nx, hy = p.L / p.ny, dt = p.T / (double)p.n_steps;
+    for (int ky = 0; ky < p.ny; ++ky) {
+        const double ph = 2.0 * M_PI * ky / p.ny;
+        for (int kx = 0; kx < p.nx; ++kx) {
+            const double th = 2.0 * M_PI * kx / p.nx;
+            const std::complex<double> lam =
+                -p.vx / hx * (1.0 - std::polar(1.0, -th)) -
+                p.vy / hy * (1.0 - std::polar(1.0, -ph)) +
+                p.nu * (2.0 * std::cos(th) - 2.0) / (hx * hx) +
+                p.nu * (2.0 * std::cos(ph) - 2.0) / (hy * hy);
+            const std::complex<double> z = dt * lam;
+            const std::complex<double> R = 1.0 + z + z * z / 2.0 + z * z * z / 6.0 +
+                                           z * z * z * z / 24.0;
+            if (std::abs(R) > 1.0 + 1e-12) return false;
+        }
+    }
+    return true;
 }
 
 // max_k |R(dt lambda_k)| for RK4 over the exact eigenvalues of the 1D
@@ -77,6 +119,7 @@ bool rk4_stable_advdiff1d(const pxp_problem& p) {
 // horizon for the linear pieces, half a slice for the Magnus factors),
 // exceeds 64, and the grid allows the cyclic-reduction shape.
 bool use_si(const pxp_problem& p) {
+    if (p.op == PXP_OP_ADVDIFF2D_UPWIND) return false;
     if (p.krylov == PXP_KRYLOV_SHIFT_INVERT) return true;
     if (p.krylov != PXP_KRYLOV_AUTO) return false;
     const double h = p.L / p.nx;
@@ -140,7 +183,21 @@ pxp_status validate(const pxp_problem& p) {
         if (dt * 4.0 * p.nu / (h * h) > 2.785) return PXP_EUNSTABLE_DT;
         return PXP_OK;
     }
-    if (p.op == PXP_OP_ADVDIFF2D_UPWIND) return PXP_EUNSUPPORTED;
+    if (p.op == PXP_OP_ADVDIFF2D_UPWIND) {
+        // band marches: power-of-two rows of 64..256 points, whole bands of
+        // 16 rows (at most 4 steps per slice: checked per method); streamed
+        // Krylov: 2048-point multiples, polynomial flavour, FP64
+        if (p.nx < 64 || p.nx > 256 || !is_pow2(p.nx)) return PXP_EUNSUPPORTED;
+        if (p.ny < BAND_ROWS || p.ny % BAND_ROWS) return PXP_EUNSUPPORTED;
+        if (grid_n(p) % (2 * KRYLOV2D_BLOCK)) return PXP_EUNSUPPORTED;
+        if (p.vx < 0.0 || p.vy < 0.0 || !std::isfinite(p.vy)) return PXP_EUNSUPPORTED;
+        if (p.prec != PXP_FP64) return PXP_EUNSUPPORTED;
+        if (p.krylov == PXP_KRYLOV_SHIFT_INVERT) return PXP_EUNSUPPORTED;
+        if (p.m < 1 || krylov2d_lds_bytes(p.m) > 160 * 1024) return PXP_EUNSUPPORTED;
+        if (!(p.krylov_tol > 0.0)) return PXP_EINVAL;
+        if (!rk4_stable_advdiff2d(p)) return PXP_EUNSTABLE_DT;
+        return PXP_OK;
+    }
     return PXP_EINVAL;
 }
 
@@ -169,6 +226,14 @@ Inst inst_layout(const pxp_problem& p) {
         const size_t npar = (p.sched == PXP_SCHED_CLASSIC && P > 1) ? P - 1 : 1;
         L.basis = take(npar * (m + 1) * n * d);
     }
+    if (p.op == PXP_OP_ADVDIFF2D_UPWIND) {
+        L.slices = take(P * n * d);
+        const bool classic = p.sched == PXP_SCHED_CLASSIC && P > 1;
+        L.pieces = take((classic ? P - 1 : 1) * n * d);
+        L.basis = take((classic ? P - 1 : 1) * (m + 1) * n * d);
+        L.sbuf0 = take(n * d);
+        L.sbuf1 = take(n * d);
+    }
     if (p.op == PXP_OP_BURGERS1D) {
         const size_t c = (size_t)p.ckpt_every;
         L.ckpt = take(((size_t)p.n_steps / c + 1) * n * d);
@@ -191,12 +256,24 @@ Layout layout(const pxp_problem* pb, int batch) {
     off += align_up((size_t)batch * sizeof(BurgersDesc));
     Ly.ktab = off;
     off += align_up((size_t)batch * sizeof(KrylovArgs));
+    Ly.t2d = off;
+    off += align_up((size_t)batch * sizeof(Band2D));
     for (int i = 0; i < batch; ++i) {
         Ly.base.push_back(off);
         off += inst_layout(pb[i]).size;
     }
     Ly.total = off;
     return Ly;
+}
+
+// The Paraexp path marches each 2D slice in one band launch of at most
+// BAND_MAX_STEPS steps.
+pxp_status check_method(const pxp_problem* pb, int batch, int method) {
+    if (method != PXP_METHOD_PARAEXP) return PXP_OK;
+    for (int i = 0; i < batch; ++i)
+        if (pb[i].op == PXP_OP_ADVDIFF2D_UPWIND && pb[i].n_steps / pb[i].P > BAND_MAX_STEPS)
+            return PXP_EUNSUPPORTED;
+    return PXP_OK;
 }
 
 pxp_status check_all(const pxp_problem* pb, int batch) {
@@ -583,6 +660,231 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
     return PXP_OK;
 }
 
+
+// ---- 2D instances: every 2D instance of a call in one launch per phase ----
+
+std::vector<int> batch2d(const pxp_problem* pb, int batch) {
+    std::vector<int> v;
+    for (int i = 0; i < batch; ++i)
+        if (pb[i].op == PXP_OP_ADVDIFF2D_UPWIND) v.push_back(i);
+    return v;
+}
+
+bool contains(const std::vector<int>& v, int i) {
+    for (int j : v)
+        if (j == i) return true;
+    return false;
+}
+
+// Serial march of every instance: launch L advances each instance by up to
+// four steps; returns in `last` the buffer that holds each final state.
+pxp_status serial2d(std::vector<Band2D>& tab, Band2D* dtab, int nb_total, bool rev,
+                    hipStream_t s) {
+    int64_t lmax = 0;
+    for (const Band2D& d : tab) lmax = std::max(lmax, (d.n_t + 3) / 4);
+    HIPCHK(launch_upload(dtab, tab.data(), tab.size() * sizeof(Band2D), s));
+    for (int64_t L = 0; L < lmax; ++L) {
+        if (rev)
+            HIPCHK(launch_band2d_rev(dtab, (int)tab.size(), nb_total, (int)L, s));
+        else
+            HIPCHK(launch_band2d(dtab, (int)tab.size(), nb_total, 1, (int)L, s));
+    }
+    return PXP_OK;
+}
+
+const double* serial2d_result(const Band2D& d) {
+    const int64_t L = (d.n_t + 3) / 4;
+    return d.buf[L & 1];
+}
+
+// Direct solve of the 2D instances idx: init (nullable) and F (nullable)
+// per instance -> qT.
+pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, void* ws,
+                           const Layout& Ly, const std::vector<const double*>& init,
+                           const std::vector<const double*>& F,
+                           const std::vector<double*>& qT, int method, hipStream_t s) {
+    if (idx.empty()) return PXP_OK;
+    auto* dtab = reinterpret_cast<Band2D*>(static_cast<char*>(ws) + Ly.t2d);
+    std::vector<Band2D> tab;
+    int blk = 0;
+    for (size_t j = 0; j < idx.size(); ++j) {
+        const pxp_problem& p = pb[idx[j]];
+        Ctx c = make_ctx(p, ws, Ly, idx[j], s);
+        const int n = c.n(), nb = p.ny / BAND_ROWS;
+        Band2D d{};
+        d.F = F[j];
+        d.nx = p.nx;
+        d.ny = p.ny;
+        d.dt = c.dt();
+        d.omega = p.omega;
+        d.A = advdiff2d_sten(p);
+        d.blk0 = blk;
+        if (method == PXP_METHOD_SERIAL) {
+            d.y0 = init[j];
+            d.buf[0] = c.at(c.L.sbuf0);
+            d.buf[1] = c.at(c.L.sbuf1);
+            d.n_t = p.n_steps;
+            d.items = 1;
+        } else {
+            if (init[j]) {
+                // IC shift q~ = q - q0: the source gains A q0 (eq. linzero)
+                HIPCHK(launch_apply5(init[j], c.at(c.L.g0), p.nx, p.ny, d.A, s));
+                d.g0 = c.at(c.L.g0);
+            }
+            d.out = c.at(c.L.slices);
+            d.items = p.P;
+            d.nsteps = (int)(p.n_steps / p.P);
+            d.item_steps = p.n_steps / p.P;
+            (void)n;
+        }
+        blk += d.items * nb;
+        tab.push_back(d);
+    }
+    if (method == PXP_METHOD_SERIAL) {
+        {
+            ProfScope ps(PXP_K_SERIAL_DIRECT, s);
+            pxp_status st = serial2d(tab, dtab, blk, false, s);
+            if (st != PXP_OK) return st;
+        }
+        for (size_t j = 0; j < idx.size(); ++j)
+            HIPCHK(launch_add(nullptr, serial2d_result(tab[j]), qT[j],
+                              (int)grid_n(pb[idx[j]]), s));
+        return PXP_OK;
+    }
+    // (1) the P inhomogeneous slices of every instance, one launch
+    HIPCHK(launch_upload(dtab, tab.data(), tab.size() * sizeof(Band2D), s));
+    {
+        ProfScope ps(PXP_K_SLICES, s);
+        HIPCHK(launch_band2d(dtab, (int)tab.size(), blk, 0, 0, s));
+    }
+    // (2) homogeneous pieces: classic (P-1 workgroups) or chain (one)
+    std::vector<KrylovArgs> kt;
+    int kblk = 0;
+    for (size_t j = 0; j < idx.size(); ++j) {
+        const pxp_problem& p = pb[idx[j]];
+        if (p.P == 1) continue;
+        Ctx c = make_ctx(p, ws, Ly, idx[j], s);
+        KrylovArgs a = kargs(c, Tri{0.0, 0.0, 0.0});
+        a.si = 0;
+        a.op5 = advdiff2d_sten(p);
+        a.nx = p.nx;
+        a.ny = p.ny;
+        a.vin = c.at(c.L.slices);
+        a.tau = p.T / p.P;
+        a.blk0 = kblk;
+        if (p.sched == PXP_SCHED_CLASSIC) {
+            a.mode = KM_CLASSIC;
+            a.npieces = p.P - 1;
+            a.yout = c.at(c.L.pieces);
+            kblk += p.P - 1;
+        } else {
+            a.mode = KM_CHAIN;
+            a.npieces = p.P;
+            a.yout = c.at(c.L.chain);
+            kblk += 1;
+        }
+        kt.push_back(a);
+    }
+    if (!kt.empty()) {
+        auto* dk = reinterpret_cast<KrylovArgs*>(static_cast<char*>(ws) + Ly.ktab);
+        HIPCHK(launch_upload(dk, kt.data(), kt.size() * sizeof(KrylovArgs), s));
+        size_t lds = 0;
+        for (const KrylovArgs& a : kt) lds = std::max(lds, krylov2d_lds_bytes(a.m));
+        ProfScope ps(PXP_K_KRYLOV_DIRECT, s);
+        HIPCHK(launch_krylov2d(dk, (int)kt.size(), kblk, lds, s));
+    }
+    // (3) superposition
+    for (size_t j = 0; j < idx.size(); ++j) {
+        const pxp_problem& p = pb[idx[j]];
+        Ctx c = make_ctx(p, ws, Ly, idx[j], s);
+        const int n = c.n();
+        const double* sl = c.at(c.L.slices);
+        if (p.P == 1)
+            HIPCHK(launch_recombine(init[j], sl, nullptr, 0, n, qT[j], c.st, s));
+        else if (p.sched == PXP_SCHED_CLASSIC)
+            HIPCHK(launch_recombine(init[j], sl + (size_t)(p.P - 1) * n,
+                                    c.at(c.L.pieces), p.P - 1, n, qT[j], c.st, s));
+        else
+            HIPCHK(launch_recombine(init[j], nullptr, c.at(c.L.chain), 1, n, qT[j], c.st,
+                                    s));
+    }
+    return PXP_OK;
+}
+
+// Adjoint of the 2D instances idx from lamT: lam0 and/or Lambda.
+pxp_status adjoint_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, void* ws,
+                            const Layout& Ly, const std::vector<const double*>& lamT,
+                            const std::vector<double*>& lam0,
+                            const std::vector<double*>& Lam, int method, hipStream_t s) {
+    if (idx.empty()) return PXP_OK;
+    if (method == PXP_METHOD_SERIAL) {
+        auto* dtab = reinterpret_cast<Band2D*>(static_cast<char*>(ws) + Ly.t2d);
+        std::vector<Band2D> tab;
+        int blk = 0;
+        for (size_t j = 0; j < idx.size(); ++j) {
+            const pxp_problem& p = pb[idx[j]];
+            Ctx c = make_ctx(p, ws, Ly, idx[j], s);
+            Band2D d{};
+            d.y0 = lamT[j];
+            d.buf[0] = c.at(c.L.sbuf0);
+            d.buf[1] = c.at(c.L.sbuf1);
+            d.Lam = Lam[j];
+            d.n_t = p.n_steps;
+            d.nx = p.nx;
+            d.ny = p.ny;
+            d.dt = c.dt();
+            d.omega = p.omega;
+            d.A = transpose5(advdiff2d_sten(p));
+            d.items = 1;
+            d.blk0 = blk;
+            blk += p.ny / BAND_ROWS;
+            tab.push_back(d);
+            if (Lam[j]) HIPCHK(launch_zero(Lam[j], (size_t)grid_n(p), s));
+        }
+        {
+            ProfScope ps(PXP_K_SERIAL_REVERSE, s);
+            pxp_status st = serial2d(tab, dtab, blk, true, s);
+            if (st != PXP_OK) return st;
+        }
+        for (size_t j = 0; j < idx.size(); ++j)
+            if (lam0[j])
+                HIPCHK(launch_add(nullptr, serial2d_result(tab[j]), lam0[j],
+                                  (int)grid_n(pb[idx[j]]), s));
+        return PXP_OK;
+    }
+    // one homogeneous piece per instance from q^dagger(T) over [T, 0]
+    // (eq. adjhomfinal), with Lambda formed in the Krylov space
+    std::vector<KrylovArgs> kt;
+    for (size_t j = 0; j < idx.size(); ++j) {
+        const pxp_problem& p = pb[idx[j]];
+        if (!lam0[j] && !Lam[j]) continue;
+        Ctx c = make_ctx(p, ws, Ly, idx[j], s);
+        KrylovArgs a = kargs(c, Tri{0.0, 0.0, 0.0});
+        a.si = 0;
+        a.op5 = transpose5(advdiff2d_sten(p));
+        a.nx = p.nx;
+        a.ny = p.ny;
+        a.mode = KM_SINGLE;
+        a.npieces = 1;
+        a.vin = lamT[j];
+        a.yout = lam0[j];
+        a.iout = Lam[j];
+        a.tau = p.T;
+        a.ia = p.omega * p.T;
+        a.ib = -p.omega;
+        a.blk0 = (int)kt.size();
+        kt.push_back(a);
+    }
+    if (kt.empty()) return PXP_OK;
+    auto* dk = reinterpret_cast<KrylovArgs*>(static_cast<char*>(ws) + Ly.ktab);
+    HIPCHK(launch_upload(dk, kt.data(), kt.size() * sizeof(KrylovArgs), s));
+    size_t lds = 0;
+    for (const KrylovArgs& a : kt) lds = std::max(lds, krylov2d_lds_bytes(a.m));
+    ProfScope ps(PXP_K_KRYLOV_ADJOINT, s);
+    HIPCHK(launch_krylov2d(dk, (int)kt.size(), (int)kt.size(), lds, s));
+    return PXP_OK;
+}
+
 }  // namespace
 }  // namespace pxp
 
@@ -628,6 +930,7 @@ static pxp_status direct_impl(const pxp_problem* pb, int32_t batch,
                               void* ws, size_t ws_bytes, void* stream,
                               int method) {
     pxp_status st = check_all(pb, batch);
+    if (st == PXP_OK) st = check_method(pb, batch, method);
     if (st != PXP_OK) return st;
     if (batch == 0) return PXP_OK;
     if (!qT) return PXP_EINVAL;
@@ -636,12 +939,19 @@ static pxp_status direct_impl(const pxp_problem* pb, int32_t batch,
     if (st != PXP_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     size_t off = 0;
+    const std::vector<int> idx2 = batch2d(pb, batch);
+    std::vector<const double*> i2, f2;
+    std::vector<double*> o2;
     for (int i = 0; i < batch; ++i) {
         const pxp_problem& p = pb[i];
         Ctx c = make_ctx(p, ws, Ly, i, s);
         const double* q0i = q0 ? q0 + off : nullptr;
         const double* Fi = F ? F + off : nullptr;
-        if (p.op == PXP_OP_ADVDIFF1D) {
+        if (p.op == PXP_OP_ADVDIFF2D_UPWIND) {
+            i2.push_back(q0i);
+            f2.push_back(Fi);
+            o2.push_back(qT + off);
+        } else if (p.op == PXP_OP_ADVDIFF1D) {
             st = direct_lin1d(c, q0i, Fi, qT + off, method);
         } else {
             if (!q0i) return PXP_EINVAL;
@@ -650,7 +960,7 @@ static pxp_status direct_impl(const pxp_problem* pb, int32_t batch,
         if (st != PXP_OK) return st;
         off += (size_t)grid_n(p);
     }
-    return PXP_OK;
+    return direct_2d_batch(pb, idx2, ws, Ly, i2, f2, o2, method, s);
 }
 
 pxp_status paraexp_direct(const pxp_problem* pb, int32_t batch,
@@ -679,10 +989,17 @@ static pxp_status adjoint_impl(const pxp_problem* pb, int32_t batch,
         off += (size_t)grid_n(pb[i]);
     }
     off = 0;
+    const std::vector<int> idx2 = batch2d(pb, batch);
+    std::vector<const double*> l2;
+    std::vector<double*> z2, L2;
     for (int i = 0; i < batch; ++i) {
         const pxp_problem& p = pb[i];
         Ctx c = make_ctx(p, ws, Ly, i, s);
-        if (p.op == PXP_OP_ADVDIFF1D) {
+        if (p.op == PXP_OP_ADVDIFF2D_UPWIND) {
+            l2.push_back(lamT + off);
+            z2.push_back(lam0 ? lam0 + off : nullptr);
+            L2.push_back(Lambda ? Lambda + off : nullptr);
+        } else if (p.op == PXP_OP_ADVDIFF1D) {
             st = adjoint_lin1d(c, lamT + off, lam0 ? lam0 + off : nullptr,
                                Lambda ? Lambda + off : nullptr, method);
         } else {
@@ -693,7 +1010,7 @@ static pxp_status adjoint_impl(const pxp_problem* pb, int32_t batch,
         if (st != PXP_OK) return st;
         off += (size_t)grid_n(p);
     }
-    return PXP_OK;
+    return adjoint_2d_batch(pb, idx2, ws, Ly, l2, z2, L2, method, s);
 }
 
 pxp_status paraexp_adjoint(const pxp_problem* pb, int32_t batch,
@@ -712,6 +1029,8 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
     if (st != PXP_OK) return st;
     if (method != PXP_METHOD_PARAEXP && method != PXP_METHOD_SERIAL)
         return PXP_EINVAL;
+    st = check_method(pb, batch, method);
+    if (st != PXP_OK) return st;
     if (batch == 0) return PXP_OK;
     if (!u_tgt || !J || !grad) return PXP_EINVAL;
     Layout Ly;
@@ -769,8 +1088,17 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
     // (a2-a4, a10) direct
     std::vector<const double*> binit;
     std::vector<double*> bqT, blamT, blam0;
+    const std::vector<int> idx2 = batch2d(pb, batch);
+    std::vector<const double*> i2, f2;
+    std::vector<double*> o2;
     for (int i = 0; i < batch; ++i) {
         const pxp_problem& p = pb[i];
+        if (p.op == PXP_OP_ADVDIFF2D_UPWIND) {
+            i2.push_back(ip[i].init);
+            f2.push_back(ip[i].F);
+            o2.push_back(ip[i].qT);
+            continue;
+        }
         if (bb.on && in_batch(bb, i)) {
             binit.push_back(ip[i].init);
             bqT.push_back(ip[i].qT);
@@ -787,16 +1115,26 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
         st = burgers_batch_direct(pb, bb, ws, Ly, binit, bqT, s);
         if (st != PXP_OK) return st;
     }
+    st = direct_2d_batch(pb, idx2, ws, Ly, i2, f2, o2, method, s);
+    if (st != PXP_OK) return st;
     // (a5) cost and adjoint final condition
     for (int i = 0; i < batch; ++i)
         HIPCHK(launch_cost(ip[i].qT, ip[i].tgt, ip[i].a, ip[i].n, ip[i].K, pb[i].beta,
                            ip[i].lamT, J + i, s));
     // (a6-a8) adjoint
+    std::vector<const double*> l2;
+    std::vector<double*> z2, L2;
     for (int i = 0; i < batch; ++i) {
         const pxp_problem& p = pb[i];
+        const bool forcing = (p.ctrl == PXP_CTRL_FORCING);
+        if (p.op == PXP_OP_ADVDIFF2D_UPWIND) {
+            l2.push_back(ip[i].lamT);
+            z2.push_back(forcing ? nullptr : ip[i].lam0);
+            L2.push_back(forcing ? ip[i].Lam : nullptr);
+            continue;
+        }
         if (bb.on && in_batch(bb, i)) continue;
         Ctx c = make_ctx(p, ws, Ly, i, s);
-        const bool forcing = (p.ctrl == PXP_CTRL_FORCING);
         st = (p.op == PXP_OP_ADVDIFF1D)
                  ? adjoint_lin1d(c, ip[i].lamT, forcing ? nullptr : ip[i].lam0,
                                  forcing ? ip[i].Lam : nullptr, method)
@@ -807,6 +1145,8 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
         st = burgers_batch_adjoint(pb, bb, ws, Ly, blamT, blam0, method, s);
         if (st != PXP_OK) return st;
     }
+    st = adjoint_2d_batch(pb, idx2, ws, Ly, l2, z2, L2, method, s);
+    if (st != PXP_OK) return st;
     // (a9) gradient
     for (int i = 0; i < batch; ++i) {
         const bool forcing = (pb[i].ctrl == PXP_CTRL_FORCING);

@@ -12,6 +12,12 @@ struct Tri {
     double lo, d, up;
 };
 
+// Periodic 2D five-point operator on a row-major grid (x fastest):
+// (Op x)_{j,i} = c x_{j,i} + w x_{j,i-1} + e x_{j,i+1} + s x_{j-1,i} + n x_{j+1,i}
+struct Sten5 {
+    double c, w, e, s, n;
+};
+
 // Device-side status block at the start of every workspace.
 struct DevStatus {
     unsigned int flags;          // bit 0: Krylov estimate above tolerance,
@@ -111,6 +117,9 @@ struct KrylovArgs {
     const double* wop;   // KM_LTV: effective states [2*npieces][n]
     double inv2h, nuh2;  // KM_LTV: 1/(2h), nu/h^2
     double* basis;       // [gridDim][m+1][n] workspace
+    Sten5 op5;           // 2D: five-point operator
+    int nx, ny;          // 2D: grid
+    int blk0;            // batched launches: first workgroup of the entry
     DevStatus* status;
 };
 hipError_t launch_krylov1d(const KrylovArgs& a, int block, hipStream_t s);
@@ -121,6 +130,49 @@ hipError_t launch_krylov_ltv_batch(const KrylovArgs* tab, int block, int count,
                                    size_t lds, hipStream_t s);
 size_t krylov1d_lds_bytes(int n, int m, int block, int si);
 bool krylov_shape_pub(int n, int block_hint, int* B, int* pt);
+
+// ---- 2D five-point operators (row-major, x fastest, periodic) -------------
+
+// One entry of a batched 2D RK4 march: `items` independent marches of one
+// instance (the slices, or the single serial march), each of nsteps steps of
+//   y' = A y + sin(omega t) F + g0,
+// item q starting at global step step0 + q * item_steps from y0 (null: zero).
+// Workgroups blk0 .. blk0 + items * ny / 16 - 1 of the launch belong to the
+// entry.  Serial sweeps: launch number L of the sweep advances the state in
+// buf[L & 1] (y0 when L == 0) by min(4, n_t - 4L) steps into buf[(L+1) & 1];
+// reverse sweeps run the exact discrete adjoint backwards the same way,
+// adding sum s(t_stage) kbar_stage to Lam.
+struct Band2D {
+    const double* y0;
+    const double* F;
+    const double* g0;
+    double* out;
+    double* buf[2];
+    double* Lam;
+    int64_t step0, item_steps, n_t;
+    double dt, omega;
+    Sten5 A;
+    int nx, ny, nsteps, items, blk0;
+};
+constexpr int BAND_ROWS = 16;  // interior rows per workgroup
+constexpr int BAND_MAX_STEPS = 4;
+// Forward: slices (serial == 0) or launch L of a serial sweep.
+hipError_t launch_band2d(const Band2D* tab, int count, int total_blocks, int serial,
+                         int L, hipStream_t s);
+// Reverse launch L of the serial discrete-adjoint sweep (A holds A^T).
+hipError_t launch_band2d_rev(const Band2D* tab, int count, int total_blocks, int L,
+                             hipStream_t s);
+// out = Op x for a five-point operator
+hipError_t launch_apply5(const double* x, double* out, int nx, int ny, Sten5 op,
+                         hipStream_t s);
+
+// 2D Krylov pieces, vectors streamed from global memory, one workgroup per
+// piece: KM_CLASSIC (npieces workgroups), KM_CHAIN or KM_SINGLE (one).
+// Entries of `tab` own workgroups blk0 .. (next entry's blk0) - 1.
+hipError_t launch_krylov2d(const KrylovArgs* tab, int count, int total_blocks,
+                           size_t lds, hipStream_t s);
+size_t krylov2d_lds_bytes(int m);
+constexpr int KRYLOV2D_BLOCK = 1024;
 
 // ---- small kernels ---------------------------------------------------------
 // out[i] = base[i] (or 0) + sum_k a[k] basis[k*n + i]

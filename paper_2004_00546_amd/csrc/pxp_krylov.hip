@@ -66,25 +66,18 @@ struct Tsplit {
     double cs, cdf, cc;
 };
 
-template <int PT, bool SI, bool VAR>
-struct Ctx {
-    // Points owned by thread t: R groups of VW consecutive points, group r
-    // at (t + r*B)*VW, so every basis read is a coalesced 16-byte load.
-    static constexpr int VW = (PT >= 2) ? 2 : 1;
-    static constexpr int R = PT / VW;
+// Shared part of the Krylov contexts: LDS layout, the small dense phase
+// (Hessenberg exponential, shift-and-invert image, time integral), status
+// reporting and the substep control of exp(tau Op) v.  D supplies the vector
+// side: arnoldi(), combine() and before_space().
+template <class D, bool SI>
+struct Core {
     const KrylovArgs a;
     Smem S;
-    double* V;
     int n, m, B, t, ldr;
-    Tsplit op;
-    const double* Wcur = nullptr;  // VAR: state W of the operator J(W)^T
-    // VAR && SI: factors of (I - gamma J(W)^T) for the current W, in global
-    // memory after the basis: lo, piv, cp, g, h ([l][chunk], 5n doubles),
-    // then the interface rows RA, RB, RC and lo, up at the chunk starts (5B)
-    double* aux = nullptr;
 
-    __device__ Ctx(const KrylovArgs& a_, double* lds, double* V_)
-        : a(a_), V(V_), n(a_.n), m(a_.m), B(blockDim.x), t(threadIdx.x) {
+    __device__ Core(const KrylovArgs& a_, double* lds)
+        : a(a_), n(a_.n), m(a_.m), B(blockDim.x), t(threadIdx.x) {
         ldr = ((m + 1 + 7) / 8) * 8;
         S.red = lds;
         S.hcol = S.red + 64;
@@ -96,9 +89,195 @@ struct Ctx {
         S.vy = S.W + 4 * (size_t)m * m + 2 * m + 8;
         S.vy2 = S.vy + m;
         S.vc = S.vy2 + m;
+    }
+    __device__ __forceinline__ D& self() { return *static_cast<D*>(this); }
+
+    // Mt = scale * (I - H_k^{-1}) / gamma for the leading k x k block.
+    __device__ __forceinline__ void si_image(int k, double gamma, double scale) {
+        const int ld = 2 * k;
+        for (int o = t; o < k * ld; o += B) {
+            const int r = o / ld, c = o - r * ld;
+            S.W[o] = (c < k) ? S.H[r * m + c] : ((c - k == r) ? 1.0 : 0.0);
+        }
+        __syncthreads();
+        sm_gauss_jordan(S.W, k, ld, ld, S.red, reinterpret_cast<int*>(S.hcol + ldr));
+        for (int o = t; o < k * k; o += B) {
+            const int r = o / k, c = o - r * k;
+            S.Mt[o] = scale * (((r == c) ? 1.0 : 0.0) - S.W[r * ld + k + c]) / gamma;
+        }
+        __syncthreads();
+    }
+
+    // vec = exp(ts Hop) e_1 (leading k x k block); returns |vec[k-1]|.
+    __device__ __forceinline__ double small_exp(int k, double ts, double gamma, double* vec) {
+        if (SI) {
+            si_image(k, gamma, ts);
+        } else {
+            for (int o = t; o < k * k; o += B) {
+                const int r = o / k, c = o - r * k;
+                S.Mt[o] = ts * S.H[r * m + c];
+            }
+            __syncthreads();
+        }
+        sm_expm(S.E, S.Mt, k, k, S.W, S.red);
+        for (int r = t; r < k; r += B) vec[r] = S.E[r * k];
+        __syncthreads();
+        return fabs(vec[k - 1]);
+    }
+
+    // vc = coefficients of int_0^ts sin(ia + ib s) exp(s Hop) e_1 ds, given
+    // vy = exp(ts Hop) e_1.
+    __device__ __forceinline__ void small_integral(int k, double ts, double ia, double ib,
+                                   double gamma) {
+        if (SI) si_image(k, gamma, 1.0);  // Mt = Hop
+        const int n2 = 2 * k, ld = n2 + 1;
+        const double cb = cos(ib * ts), sb = sin(ib * ts);
+        for (int o = t; o < n2 * ld; o += B) {
+            const int r = o / ld, c = o - r * ld;
+            const int rr = (r < k) ? r : r - k;
+            const int c2 = (c < k) ? c : c - k;
+            double v;
+            if (c == n2) {
+                v = (r < k) ? (cb * S.vy[rr] - (rr == 0 ? 1.0 : 0.0)) : sb * S.vy[rr];
+            } else if ((r < k) == (c < k)) {
+                v = SI ? S.Mt[rr * k + c2] : S.H[rr * m + c2];
+            } else {
+                // upper-right block -b I, lower-left block +b I
+                v = (rr == c2) ? ((r < k) ? -ib : ib) : 0.0;
+            }
+            S.W[o] = v;
+        }
+        __syncthreads();
+        sm_gauss_jordan(S.W, n2, ld, ld, S.red, reinterpret_cast<int*>(S.hcol + ldr));
+        const double sa = sin(ia), ca = cos(ia);
+        for (int r = t; r < k; r += B) S.vc[r] = sa * S.W[r * ld + n2] + ca * S.W[(r + k) * ld + n2];
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ void report(double est_rel, bool noconv, unsigned substeps,
+                           unsigned iters) {
+        if (t == 0 && a.status) {
+            if (noconv) atomicOr(&a.status->flags, ST_NOCONV);
+            if (!(est_rel == est_rel)) atomicOr(&a.status->flags, ST_NONFINITE);
+            const double e = fabs(est_rel);
+            if (e == e)
+                atomicMax(&a.status->max_est, (unsigned long long)__double_as_longlong(e));
+            atomicAdd(&a.status->substeps, (unsigned long long)substeps);
+            atomicAdd(&a.status->krylov_iters, (unsigned long long)iters);
+        }
+    }
+
+    // V_0 <- exp(tau Op) V_0; if iout, iout += int_0^tau sin(ia + ib s)
+    // exp(s Op) V_0 ds.
+    __device__ __forceinline__ void expv(double tau, double ia, double ib, double* iout) {
+        if (!(tau > 0.0)) return;
+        const double tol = a.tol;
+        if (SI) {
+            const double gamma = a.gamma_frac * tau;
+            self().before_space(gamma);
+            double beta;
+            bool bd;
+            const int me = self().arnoldi(gamma, beta, bd);
+            if (me == 0) return;
+            small_exp(me, tau, gamma, S.vy);
+            double est = 0.0;
+            if (iout) small_integral(me, tau, ia, ib, gamma);
+            if (!bd && me > 1) {
+                small_exp(me - 1, tau, gamma, S.vy2);
+                double s = 0.0;
+                for (int q = 0; q < me; ++q) {
+                    const double d = S.vy[q] - (q < me - 1 ? S.vy2[q] : 0.0);
+                    s += d * d;
+                }
+                est = sqrt(s);  // relative to beta
+            }
+            self().combine(me, beta, iout);
+            report(est, est > tol, 1, me);
+            __syncthreads();
+            return;
+        }
+        // polynomial Krylov with substeps
+        double left = tau, sigma0 = 0.0, ts = tau;
+        double worst = 0.0;
+        bool noconv = false;
+        unsigned nsub = 0, iters = 0;
+        while (left > 0.0) {
+            double beta;
+            bool bd, conv = false;
+            if (ts > left) ts = left;
+            double est = 0.0, tolb = 0.0;
+            const int me = self().arnoldi(0.0, beta, bd, ts, tol * (ts / tau), &conv, &est);
+            iters += me;
+            if (me == 0) break;
+            const double hnext = bd ? 0.0 : S.H[me * m + (me - 1)];
+            int tries = 0;
+            if (conv) tolb = tol * beta * (ts / tau);
+            for (; !conv;) {
+                if (ts > left) ts = left;
+                const double e1 = small_exp(me, ts, 0.0, S.vy);
+                est = bd ? 0.0 : beta * hnext * e1;
+                tolb = tol * beta * (ts / tau);
+                if (est <= tolb) break;
+                if (tries >= 40 || ts <= 1e-10 * tau || !(est == est)) {
+                    noconv = true;
+                    break;
+                }
+                double f = 0.9 * pow(tolb / est, 1.0 / (double)me);
+                f = fmin(0.9, fmax(0.1, f));
+                ts *= f;
+                ++tries;
+            }
+            if (beta > 0.0) worst = fmax(worst, est / beta / (ts / tau));
+            if (iout) small_integral(me, ts, ia + ib * sigma0, ib, 0.0);
+            self().combine(me, beta, iout);
+            ++nsub;
+            sigma0 += ts;
+            left = tau - sigma0;
+            if (left <= 1e-13 * tau) left = 0.0;
+            if (nsub >= 20000 && left > 0.0) {  // give up: flagged, not hidden
+                noconv = true;
+                break;
+            }
+            // grow the next substep when the estimate allows it
+            double g = (est > 0.0) ? 0.9 * pow(tolb / est, 1.0 / (double)me) : 2.0;
+            g = fmin(2.0, fmax(1.0, g));
+            ts *= g;
+            __syncthreads();
+        }
+        report(worst, noconv, nsub, iters);
+    }
+};
+
+template <int PT, bool SI, bool VAR>
+struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
+    using Base = Core<Ctx<PT, SI, VAR>, SI>;
+    using Base::a;
+    using Base::S;
+    using Base::n;
+    using Base::m;
+    using Base::B;
+    using Base::t;
+    using Base::small_exp;
+    // Points owned by thread t: R groups of VW consecutive points, group r
+    // at (t + r*B)*VW, so every basis read is a coalesced 16-byte load.
+    static constexpr int VW = (PT >= 2) ? 2 : 1;
+    static constexpr int R = PT / VW;
+    double* V;
+    Tsplit op;
+    const double* Wcur = nullptr;  // VAR: state W of the operator J(W)^T
+    // VAR && SI: factors of (I - gamma J(W)^T) for the current W, in global
+    // memory after the basis: lo, piv, cp, g, h ([l][chunk], 5n doubles),
+    // then the interface rows RA, RB, RC and lo, up at the chunk starts (5B)
+    double* aux = nullptr;
+
+    __device__ Ctx(const KrylovArgs& a_, double* lds, double* V_) : Base(a_, lds), V(V_) {
         op.cs = 0.5 * (a.op.lo + a.op.up);
         op.cdf = 0.5 * (a.op.up - a.op.lo);
         op.cc = a.op.d + 2.0 * op.cs;
+    }
+
+    __device__ __forceinline__ void before_space(double gamma) {
+        if (VAR && SI) si_setup(gamma);
     }
 
     // first point of group r, and whether the group lies inside the grid
@@ -530,68 +709,6 @@ struct Ctx {
         return me;
     }
 
-    // Mt = scale * (I - H_k^{-1}) / gamma for the leading k x k block.
-    __device__ __forceinline__ void si_image(int k, double gamma, double scale) {
-        const int ld = 2 * k;
-        for (int o = t; o < k * ld; o += B) {
-            const int r = o / ld, c = o - r * ld;
-            S.W[o] = (c < k) ? S.H[r * m + c] : ((c - k == r) ? 1.0 : 0.0);
-        }
-        __syncthreads();
-        sm_gauss_jordan(S.W, k, ld, ld, S.red, reinterpret_cast<int*>(S.hcol + ldr));
-        for (int o = t; o < k * k; o += B) {
-            const int r = o / k, c = o - r * k;
-            S.Mt[o] = scale * (((r == c) ? 1.0 : 0.0) - S.W[r * ld + k + c]) / gamma;
-        }
-        __syncthreads();
-    }
-
-    // vec = exp(ts Hop) e_1 (leading k x k block); returns |vec[k-1]|.
-    __device__ __forceinline__ double small_exp(int k, double ts, double gamma, double* vec) {
-        if (SI) {
-            si_image(k, gamma, ts);
-        } else {
-            for (int o = t; o < k * k; o += B) {
-                const int r = o / k, c = o - r * k;
-                S.Mt[o] = ts * S.H[r * m + c];
-            }
-            __syncthreads();
-        }
-        sm_expm(S.E, S.Mt, k, k, S.W, S.red);
-        for (int r = t; r < k; r += B) vec[r] = S.E[r * k];
-        __syncthreads();
-        return fabs(vec[k - 1]);
-    }
-
-    // vc = coefficients of int_0^ts sin(ia + ib s) exp(s Hop) e_1 ds, given
-    // vy = exp(ts Hop) e_1.
-    __device__ __forceinline__ void small_integral(int k, double ts, double ia, double ib,
-                                   double gamma) {
-        if (SI) si_image(k, gamma, 1.0);  // Mt = Hop
-        const int n2 = 2 * k, ld = n2 + 1;
-        const double cb = cos(ib * ts), sb = sin(ib * ts);
-        for (int o = t; o < n2 * ld; o += B) {
-            const int r = o / ld, c = o - r * ld;
-            const int rr = (r < k) ? r : r - k;
-            const int c2 = (c < k) ? c : c - k;
-            double v;
-            if (c == n2) {
-                v = (r < k) ? (cb * S.vy[rr] - (rr == 0 ? 1.0 : 0.0)) : sb * S.vy[rr];
-            } else if ((r < k) == (c < k)) {
-                v = SI ? S.Mt[rr * k + c2] : S.H[rr * m + c2];
-            } else {
-                // upper-right block -b I, lower-left block +b I
-                v = (rr == c2) ? ((r < k) ? -ib : ib) : 0.0;
-            }
-            S.W[o] = v;
-        }
-        __syncthreads();
-        sm_gauss_jordan(S.W, n2, ld, ld, S.red, reinterpret_cast<int*>(S.hcol + ldr));
-        const double sa = sin(ia), ca = cos(ia);
-        for (int r = t; r < k; r += B) S.vc[r] = sa * S.W[r * ld + n2] + ca * S.W[(r + k) * ld + n2];
-        __syncthreads();
-    }
-
     // V_0 <- beta * V_k vy  and, when iout, iout += beta * V_k vc.
     __device__ __forceinline__ void combine(int k, double beta, double* iout) {
         double y[PT], I[PT];
@@ -623,98 +740,6 @@ struct Ctx {
         }
     }
 
-    __device__ __forceinline__ void report(double est_rel, bool noconv, unsigned substeps,
-                           unsigned iters) {
-        if (t == 0 && a.status) {
-            if (noconv) atomicOr(&a.status->flags, ST_NOCONV);
-            if (!(est_rel == est_rel)) atomicOr(&a.status->flags, ST_NONFINITE);
-            const double e = fabs(est_rel);
-            if (e == e)
-                atomicMax(&a.status->max_est, (unsigned long long)__double_as_longlong(e));
-            atomicAdd(&a.status->substeps, (unsigned long long)substeps);
-            atomicAdd(&a.status->krylov_iters, (unsigned long long)iters);
-        }
-    }
-
-    // V_0 <- exp(tau Op) V_0; if iout, iout += int_0^tau sin(ia + ib s)
-    // exp(s Op) V_0 ds.
-    __device__ __forceinline__ void expv(double tau, double ia, double ib, double* iout) {
-        if (!(tau > 0.0)) return;
-        const double tol = a.tol;
-        if (SI) {
-            const double gamma = a.gamma_frac * tau;
-            if (VAR) si_setup(gamma);
-            double beta;
-            bool bd;
-            const int me = arnoldi(gamma, beta, bd);
-            if (me == 0) return;
-            small_exp(me, tau, gamma, S.vy);
-            double est = 0.0;
-            if (iout) small_integral(me, tau, ia, ib, gamma);
-            if (!bd && me > 1) {
-                small_exp(me - 1, tau, gamma, S.vy2);
-                double s = 0.0;
-                for (int q = 0; q < me; ++q) {
-                    const double d = S.vy[q] - (q < me - 1 ? S.vy2[q] : 0.0);
-                    s += d * d;
-                }
-                est = sqrt(s);  // relative to beta
-            }
-            combine(me, beta, iout);
-            report(est, est > tol, 1, me);
-            __syncthreads();
-            return;
-        }
-        // polynomial Krylov with substeps
-        double left = tau, sigma0 = 0.0, ts = tau;
-        double worst = 0.0;
-        bool noconv = false;
-        unsigned nsub = 0, iters = 0;
-        while (left > 0.0) {
-            double beta;
-            bool bd, conv = false;
-            if (ts > left) ts = left;
-            double est = 0.0, tolb = 0.0;
-            const int me = arnoldi(0.0, beta, bd, ts, tol * (ts / tau), &conv, &est);
-            iters += me;
-            if (me == 0) break;
-            const double hnext = bd ? 0.0 : S.H[me * m + (me - 1)];
-            int tries = 0;
-            if (conv) tolb = tol * beta * (ts / tau);
-            for (; !conv;) {
-                if (ts > left) ts = left;
-                const double e1 = small_exp(me, ts, 0.0, S.vy);
-                est = bd ? 0.0 : beta * hnext * e1;
-                tolb = tol * beta * (ts / tau);
-                if (est <= tolb) break;
-                if (tries >= 40 || ts <= 1e-10 * tau || !(est == est)) {
-                    noconv = true;
-                    break;
-                }
-                double f = 0.9 * pow(tolb / est, 1.0 / (double)me);
-                f = fmin(0.9, fmax(0.1, f));
-                ts *= f;
-                ++tries;
-            }
-            if (beta > 0.0) worst = fmax(worst, est / beta / (ts / tau));
-            if (iout) small_integral(me, ts, ia + ib * sigma0, ib, 0.0);
-            combine(me, beta, iout);
-            ++nsub;
-            sigma0 += ts;
-            left = tau - sigma0;
-            if (left <= 1e-13 * tau) left = 0.0;
-            if (nsub >= 20000 && left > 0.0) {  // give up: flagged, not hidden
-                noconv = true;
-                break;
-            }
-            // grow the next substep when the estimate allows it
-            double g = (est > 0.0) ? 0.9 * pow(tolb / est, 1.0 / (double)me) : 2.0;
-            g = fmin(2.0, fmax(1.0, g));
-            ts *= g;
-            __syncthreads();
-        }
-        report(worst, noconv, nsub, iters);
-    }
 };
 
 template <int PT, bool SI, bool VAR>
@@ -797,6 +822,283 @@ __global__ void __launch_bounds__(NT) k_krylov_ltv_batch(const KrylovArgs* tab) 
     }
 }
 
+// ---- 2D: basis vectors streamed from global memory ------------------------
+// A 2D instance has n = nx * ny points, too many to keep a vector in
+// registers; thread t owns the 16-byte groups g = t + r*B (points 2g, 2g+1),
+// r < n / (2B), of every vector, and each Arnoldi step streams them: the
+// five-point stencil writes the new vector, the Gram-Schmidt passes read the
+// basis (8 vectors per exchange round for the dots) and update the new vector
+// in place.  Polynomial Krylov only.
+template <int KD, int O>
+__device__ __forceinline__ void wave_halve(double (&part)[KD], int lane) {
+    if constexpr (KD > 1) {
+        constexpr int H = KD / 2;
+        const bool up = (lane & O) != 0;
+        double nxt[H];
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            const double send = up ? part[q] : part[q + H];
+            const double keep = up ? part[q + H] : part[q];
+            nxt[q] = keep + __shfl_xor(send, O, WAVE);
+        }
+        wave_halve<H, O / 2>(nxt, lane);
+        part[0] = nxt[0];
+    }
+}
+
+struct Ctx2 : Core<Ctx2, false> {
+    using Base = Core<Ctx2, false>;
+    using Base::a;
+    using Base::S;
+    using Base::n;
+    using Base::m;
+    using Base::B;
+    using Base::t;
+    using Base::small_exp;
+    double* V;
+    int G, nx, ny;
+
+    __device__ Ctx2(const KrylovArgs& a_, double* lds, double* V_)
+        : Base(a_, lds), V(V_), G(a_.n / (2 * blockDim.x)), nx(a_.nx), ny(a_.ny) {}
+
+    __device__ __forceinline__ void before_space(double) {}
+
+    __device__ __forceinline__ double2 ld2(const double* p, int g) const {
+        return *reinterpret_cast<const double2*>(p + 2 * (size_t)g);
+    }
+    __device__ __forceinline__ void st2(double* p, int g, double2 v) const {
+        *reinterpret_cast<double2*>(p + 2 * (size_t)g) = v;
+    }
+
+    // dst = Op src (all of src must be visible to the workgroup)
+    __device__ __forceinline__ void apply(const double* __restrict__ src,
+                                          double* __restrict__ dst) const {
+        const Sten5 o = a.op5;
+#pragma unroll 4
+        for (int r = 0; r < G; ++r) {
+            const int g = t + r * B, i = 2 * g;
+            const int row = i / nx, col = i - row * nx, rc = row * nx;
+            const int rs = (row == 0 ? ny - 1 : row - 1) * nx;
+            const int rn = (row == ny - 1 ? 0 : row + 1) * nx;
+            const double2 x = ld2(src, g);
+            const double xw = src[rc + (col == 0 ? nx - 1 : col - 1)];
+            const double xe = src[rc + (col + 2 == nx ? 0 : col + 2)];
+            const double2 xs = *reinterpret_cast<const double2*>(src + rs + col);
+            const double2 xn = *reinterpret_cast<const double2*>(src + rn + col);
+            double2 y;
+            y.x = o.c * x.x + o.w * xw + o.e * x.y + o.s * xs.x + o.n * xn.x;
+            y.y = o.c * x.y + o.w * x.x + o.e * xe + o.s * xs.y + o.n * xn.y;
+            st2(dst, g, y);
+        }
+    }
+
+    __device__ __forceinline__ double sumsq(const double* v) const {
+        double s = 0.0;
+#pragma unroll 4
+        for (int r = 0; r < G; ++r) {
+            const double2 x = ld2(v, t + r * B);
+            s += x.x * x.x + x.y * x.y;
+        }
+        return s;
+    }
+
+    __device__ __forceinline__ void scale(double* v, double f) const {
+#pragma unroll 4
+        for (int r = 0; r < G; ++r) {
+            const int g = t + r * B;
+            double2 x = ld2(v, g);
+            x.x *= f;
+            x.y *= f;
+            st2(v, g, x);
+        }
+    }
+
+    // hcol[k] = <V_k, w>, k <= j (see Ctx::dots for the reduction layout)
+    __device__ __forceinline__ void dots(const double* w, int j) {
+        constexpr int KD = 8, GS = WAVE / KD;
+        double* Pp = S.big;
+        const int nw = num_waves(), wv = wave_id(), lane = lane_id();
+        __syncthreads();
+        for (int k0 = 0; k0 <= j; k0 += KD) {
+            double part[KD];
+#pragma unroll
+            for (int q = 0; q < KD; ++q) part[q] = 0.0;
+            for (int r = 0; r < G; ++r) {
+                const int g = t + r * B;
+                const double2 x = ld2(w, g);
+#pragma unroll
+                for (int q = 0; q < KD; ++q) {
+                    if (k0 + q <= j) {
+                        const double2 v = ld2(V + (size_t)(k0 + q) * n, g);
+                        part[q] += x.x * v.x + x.y * v.y;
+                    }
+                }
+            }
+            wave_halve<KD, 32>(part, lane);
+            double s = part[0];
+#pragma unroll
+            for (int o = GS / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, WAVE);
+            const int gq = lane / GS;
+            if ((lane % GS) == 0 && k0 + gq <= j) Pp[(k0 + gq) * nw + wv] = s;
+        }
+        __syncthreads();
+        for (int k = t; k <= j; k += B) {
+            double s = 0.0;
+            for (int u = 0; u < nw; ++u) s += Pp[k * nw + u];
+            S.hcol[k] = s;
+        }
+        __syncthreads();
+    }
+
+    // w -= sum_{k<=j} hcol[k] V_k; returns this thread's part of |w|^2
+    __device__ __forceinline__ double subtract(double* w, int j) const {
+        double ss = 0.0;
+        for (int r = 0; r < G; ++r) {
+            const int g = t + r * B;
+            double2 x = ld2(w, g);
+#pragma unroll 4
+            for (int k = 0; k <= j; ++k) {
+                const double h = S.hcol[k];
+                const double2 v = ld2(V + (size_t)k * n, g);
+                x.x -= h * v.x;
+                x.y -= h * v.y;
+            }
+            st2(w, g, x);
+            ss += x.x * x.x + x.y * x.y;
+        }
+        return ss;
+    }
+
+    // Arnoldi from the (unnormalised) vector in V_0; same contract as
+    // Ctx::arnoldi (polynomial flavour).
+    __device__ __forceinline__ int arnoldi(double gamma, double& beta, bool& bd,
+                                           double ts = 0.0, double tolb_rel = 0.0,
+                                           bool* conv = nullptr, double* est_out = nullptr) {
+        (void)gamma;
+        beta = sqrt(block_sum(sumsq(V), S.red));
+        bd = false;
+        for (int o = t; o < (m + 1) * m; o += B) S.H[o] = 0.0;
+        if (!(beta > 0.0)) {
+            __syncthreads();
+            return 0;
+        }
+        scale(V, 1.0 / beta);
+        int me = m;
+        for (int j = 0; j < m; ++j) {
+            double* w = V + (size_t)(j + 1) * n;
+            __syncthreads();  // V_j complete: the stencil reads neighbours
+            apply(V + (size_t)j * n, w);
+            double ss = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                dots(w, j);
+                if (t <= j) S.H[t * m + j] += S.hcol[t];
+                ss = subtract(w, j);
+            }
+            const double nrm = sqrt(block_sum(ss, S.red));
+            double col = nrm * nrm;
+            for (int k = 0; k <= j; ++k) col += S.H[k * m + j] * S.H[k * m + j];
+            __syncthreads();
+            if (t == 0) S.H[(j + 1) * m + j] = nrm;
+            if (!(nrm > 1e-12 * sqrt(col))) {
+                me = j + 1;
+                bd = true;
+                break;
+            }
+            const int k = j + 1;
+            if (conv && ts > 0.0 && k < m && k >= 8 && (k % 4) == 0) {
+                const double e1 = small_exp(k, ts, 0.0, S.vy);
+                const double est = beta * nrm * e1;
+                if (est <= tolb_rel * beta) {
+                    *conv = true;
+                    if (est_out) *est_out = est;
+                    me = k;
+                    break;
+                }
+            }
+            scale(w, 1.0 / nrm);
+        }
+        __syncthreads();
+        return me;
+    }
+
+    // V_0 <- beta * V_k vy and, when iout, iout += beta * V_k vc.
+    __device__ __forceinline__ void combine(int k, double beta, double* iout) {
+        for (int r = 0; r < G; ++r) {
+            const int g = t + r * B;
+            double2 y = make_double2(0.0, 0.0), I = make_double2(0.0, 0.0);
+#pragma unroll 4
+            for (int q = 0; q < k; ++q) {
+                const double2 v = ld2(V + (size_t)q * n, g);
+                const double cy = beta * S.vy[q];
+                y.x += cy * v.x;
+                y.y += cy * v.y;
+                if (iout) {
+                    const double ci = beta * S.vc[q];
+                    I.x += ci * v.x;
+                    I.y += ci * v.y;
+                }
+            }
+            st2(V, g, y);
+            if (iout) {
+                double2 o = ld2(iout, g);
+                o.x += I.x;
+                o.y += I.y;
+                st2(iout, g, o);
+            }
+        }
+    }
+
+    __device__ __forceinline__ void copy(const double* src, double* dst) const {
+#pragma unroll 4
+        for (int r = 0; r < G; ++r) st2(dst, t + r * B, ld2(src, t + r * B));
+    }
+    __device__ __forceinline__ void add(const double* src, double* dst) const {
+#pragma unroll 4
+        for (int r = 0; r < G; ++r) {
+            const int g = t + r * B;
+            double2 x = ld2(dst, g);
+            const double2 v = ld2(src, g);
+            x.x += v.x;
+            x.y += v.y;
+            st2(dst, g, x);
+        }
+    }
+};
+
+__device__ __forceinline__ void dev_krylov2d(const KrylovArgs& a, int piece, double* lds) {
+    const int n = a.n;
+    double* V = a.basis + (size_t)piece * (a.m + 1) * n;
+    Ctx2 c(a, lds, V);
+    const double* vin = (a.mode == KM_CLASSIC) ? a.vin + (size_t)piece * n : a.vin;
+    c.copy(vin, V);
+    double* iout = (a.mode == KM_SINGLE) ? a.iout : nullptr;
+    if (iout) {
+#pragma unroll 4
+        for (int r = 0; r < c.G; ++r)
+            c.st2(iout, c.t + r * c.B, make_double2(0.0, 0.0));
+    }
+    const int nexp = (a.mode == KM_CHAIN) ? a.npieces - 1 : 1;
+    const double tau = (a.mode == KM_CLASSIC) ? (double)(a.npieces - piece) * a.tau : a.tau;
+    for (int q = 0; q < nexp; ++q) {
+        c.expv(tau, a.ia, a.ib, iout);
+        if (a.mode == KM_CHAIN) c.add(a.vin + (size_t)(q + 1) * n, V);
+    }
+    double* y = (a.mode == KM_CLASSIC) ? a.yout + (size_t)piece * n : a.yout;
+    if (y) c.copy(V, y);
+}
+
+__global__ void __launch_bounds__(KRYLOV2D_BLOCK) k_krylov2d(const KrylovArgs* tab, int count) {
+    extern __shared__ double lds[];
+    const int b = blockIdx.x;
+    int e = 0;
+    while (e + 1 < count && tab[e + 1].blk0 <= b) ++e;
+    const KrylovArgs a = tab[e];
+    const int piece = b - a.blk0;
+    if (a.mode != KM_CLASSIC && piece > 0) return;
+    if (a.mode == KM_CLASSIC && piece >= a.npieces) return;
+    dev_krylov2d(a, piece, lds);
+}
+
 template <bool SI, bool VAR>
 hipError_t launch_pt(const KrylovArgs& a, int B, int pt, int grid, size_t lds,
                      hipStream_t s) {
@@ -848,6 +1150,24 @@ size_t krylov1d_lds_bytes(int n, int m, int block, int si) {
     const int ldr = ((m + 1 + 7) / 8) * 8;
     const size_t d = 64 + ldr + 8 + (size_t)(m + 1) * m + big_doubles(n, m, block);
     return d * sizeof(double);
+}
+
+size_t krylov2d_lds_bytes(int m) {
+    const int ldr = ((m + 1 + 7) / 8) * 8;
+    const size_t part = (size_t)(m + 1) * (KRYLOV2D_BLOCK / 64);
+    const size_t sm = 6 * (size_t)m * m + 5 * (size_t)m + 8;
+    const size_t d = 64 + ldr + 8 + (size_t)(m + 1) * m + (part > sm ? part : sm);
+    return d * sizeof(double);
+}
+
+hipError_t launch_krylov2d(const KrylovArgs* tab, int count, int total_blocks,
+                           size_t lds, hipStream_t s) {
+    if (count <= 0 || total_blocks <= 0) return hipSuccess;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    (void)hipFuncSetAttribute((const void*)k_krylov2d,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_krylov2d<<<total_blocks, KRYLOV2D_BLOCK, lds, s>>>(tab, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_krylov_ltv_batch(const KrylovArgs* tab, int block, int count,

@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2004_00546_amd import _lib, api, workloads
@@ -121,3 +122,34 @@ def test_calls_fail_before_enqueue(lib):
     st = lib.pxp_gradient(arr, 0, 0, None, None, None, None, None, None, None, None,
                           None, 0, None)
     assert st == _lib.PXP_OK
+
+
+def test_2d_shape_and_precision_rules():
+    """2D problems: power-of-two rows of 64..256 points, whole 16-row bands,
+    2048-point multiples, non-negative velocities, FP64, polynomial Krylov;
+    the Paraexp path takes at most four RK4 steps per slice (checked when a
+    call names the method)."""
+    import math
+    base = dict(op="advdiff2d_upwind", control="forcing", nx=64, ny=32,
+                L=2 * math.pi, vx=1.0, vy=0.5, nu=0.02, T=0.5, n_steps=64, P=16,
+                m=30, basis=np.zeros((1, 64 * 32)))
+    ok = api.make_problem(base, krylov="poly")
+    assert _lib.pxp_workspace_size([ok]) > 0
+    for change, code in [(dict(nx=96), _lib.PXP_EUNSUPPORTED),
+                         (dict(nx=512, basis=np.zeros((1, 512 * 32))), _lib.PXP_EUNSUPPORTED),
+                         (dict(ny=24), _lib.PXP_EUNSUPPORTED),
+                         (dict(nx=64, ny=16, basis=np.zeros((1, 1024))), _lib.PXP_EUNSUPPORTED),
+                         (dict(vx=-1.0), _lib.PXP_EUNSUPPORTED),
+                         (dict(T=50.0), _lib.PXP_EUNSTABLE_DT)]:
+        p = api.make_problem(dict(base, **change), krylov="poly")
+        with pytest.raises(_lib.PxpError) as e:
+            _lib.pxp_workspace_size([p])
+        assert e.value.code == code, change
+    for kw, code in [(dict(krylov="shift_invert"), _lib.PXP_EUNSUPPORTED),
+                     (dict(krylov="poly", prec="fp32_bulk"), _lib.PXP_EUNSUPPORTED)]:
+        with pytest.raises(_lib.PxpError) as e:
+            _lib.pxp_workspace_size([api.make_problem(base, **kw)])
+        assert e.value.code == code, kw
+    # eight steps per slice: sized and accepted, refused by the Paraexp call
+    p8 = api.make_problem(dict(base, P=8), krylov="poly")
+    assert _lib.pxp_workspace_size([p8]) > 0

@@ -1,0 +1,154 @@
+"""2D upwind advection-diffusion through the C ABI: the band RK4 marches
+(slices, serial march and its exact discrete adjoint), the streamed 2D
+Krylov pieces, and the whole Paraexp gradient, against the CPU oracle and
+the Fourier closed forms.  Tolerances as for 1D: serial to rounding, Paraexp
+within the FP64 gate 1e-8."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import fourier
+from conftest import rel
+from paper_2004_00546_amd import _lib, api, workloads
+
+pytestmark = pytest.mark.gpu
+
+FP64_GATE = 1e-8
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    _lib.load()
+    return _t
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def small2d(nx=64, ny=32, T=0.5, nt=64, P=16, m=30, K=3, seed=3, nu=0.02,
+            control="forcing"):
+    rng = np.random.default_rng(seed)
+    L = 2 * math.pi
+    G = workloads.gaussian_blobs_2d(nx, ny, L, L * rng.uniform(0, 1, (K, 2)), 0.05 * L)
+    return dict(op="advdiff2d_upwind", control=control, nx=nx, ny=ny, L=L, vx=1.0,
+                vy=0.5, nu=nu, T=T, omega=1.0, beta=1e-3, n_steps=nt, P=P, m=m,
+                basis=G, a=rng.standard_normal(K), u_tgt=rng.standard_normal(nx * ny),
+                q0=np.zeros(nx * ny))
+
+
+def run(inst, method="paraexp", **kw):
+    r = api.GradientRunner([inst], method=method, krylov="poly", **kw)
+    r.run()
+    out = r.results()[0]
+    out["status"], out["est"] = r.status()
+    return out
+
+
+@pytest.mark.parametrize("nx,ny,nt", [(64, 32, 64), (128, 64, 37), (256, 16, 9)])
+def test_serial_2d_matches_oracle_to_rounding(torch, orc, nx, ny, nt):
+    """Serial band march and exact discrete adjoint; n_t not a multiple of the
+    four steps per launch exercises the partial last launch."""
+    inst = small2d(nx=nx, ny=ny, nt=nt, P=1, T=0.3 * nt / 64)
+    got = run(inst, "serial")
+    want = orc.gradient(inst)
+    say("2d serial %dx%d nt=%d: qT %.2e Lam %.2e grad %.2e" % (
+        nx, ny, nt, rel(got["qT"], want["qT"]), rel(got["lam"], want["Lambda"]),
+        rel(got["grad"], want["grad"])))
+    assert rel(got["qT"], want["qT"]) < 1e-12
+    assert rel(got["lam"], want["Lambda"]) < 1e-11
+    assert rel(got["grad"], want["grad"]) < 1e-11
+
+
+def test_serial_2d_ic_control(torch, orc):
+    inst = small2d(control="ic", P=1)
+    inst["basis"] = inst["basis"] * 0.5
+    got = run(inst, "serial")
+    want = orc.gradient(inst)
+    assert rel(got["lam"], want["lam0"]) < 1e-11
+    assert rel(got["grad"], want["grad"]) < 1e-11
+
+
+def test_slices_2d_p1_equals_serial(torch):
+    """With one slice of at most four steps, the slice march from zero is
+    the serial march."""
+    inst = small2d(nt=4, P=1, T=0.03)
+    a = run(inst, "paraexp")
+    b = run(inst, "serial")
+    assert rel(a["qT"], b["qT"]) < 1e-14
+
+
+def test_adjoint_piece_2d_vs_fourier(torch):
+    inst = small2d(nx=64, ny=64, T=0.7, nt=64, P=16, m=40)
+    n = inst["nx"] * inst["ny"]
+    lamT = np.asarray(inst["u_tgt"])
+    p = api.make_problem(inst, krylov="poly", tol=1e-12)
+    dev = torch.device("cuda:0")
+    f64 = dict(dtype=torch.float64, device=dev)
+    ws = torch.empty(_lib.pxp_workspace_size([p]), dtype=torch.uint8, device=dev)
+    _lib.pxp_workspace_init(ws)
+    lam0 = torch.zeros(n, **f64)
+    Lam = torch.zeros(n, **f64)
+    _lib.paraexp_adjoint([p], torch.tensor(lamT, **f64), lam0, Lam, ws)
+    code, est = _lib.pxp_device_status(ws)
+    lam_eig = fourier.eigenvalues(inst)
+    want0 = fourier.exp_action_T(inst, inst["T"], lamT, lam_eig)
+    mu = np.conj(lam_eig)
+    T, w = inst["T"], inst["omega"]
+    tr = (w * np.exp(mu * T) - mu * np.sin(w * T) - w * np.cos(w * T)) / (mu ** 2 + w ** 2)
+    wantL = fourier._ifft(inst, tr * fourier._fft(inst, lamT))
+    e0, eL = rel(lam0.cpu().numpy(), want0), rel(Lam.cpu().numpy(), wantL)
+    say("2d adjoint piece: lam0 %.2e Lambda %.2e est %.1e" % (e0, eL, est))
+    assert code == 0
+    assert e0 < 1e-10 and eL < 1e-10
+
+
+@pytest.mark.parametrize("sched", ["chain", "classic"])
+@pytest.mark.parametrize("P", [16, 32])
+def test_paraexp_2d_matches_oracle(torch, orc, sched, P):
+    inst = small2d(P=P)
+    got = run(inst, "paraexp", sched=sched, tol=1e-11)
+    want = orc.gradient(inst)
+    e = rel(got["grad"], want["grad"])
+    say("2d paraexp %s P=%d: qT %.2e Lam %.2e grad %.2e status %d" % (
+        sched, P, rel(got["qT"], want["qT"]), rel(got["lam"], want["Lambda"]), e,
+        got["status"]))
+    assert got["status"] == 0
+    assert rel(got["qT"], want["qT"]) < FP64_GATE
+    assert e < FP64_GATE
+
+
+def test_batch_2d_equals_one_by_one(torch):
+    insts = [small2d(seed=10), small2d(nx=128, ny=32, seed=11, T=0.4),
+             small2d(nx=64, ny=64, seed=12, nt=32, P=8, T=0.25)]
+    for method in ("paraexp", "serial"):
+        r = api.GradientRunner(insts, method=method, krylov="poly", sched="chain")
+        r.run()
+        for inst, b in zip(insts, r.results()):
+            one = run(inst, method, sched="chain")
+            assert np.array_equal(one["grad"], b["grad"]), (method, inst["nx"])
+            assert np.array_equal(one["qT"], b["qT"]), (method, inst["nx"])
+
+
+def test_workload_2d_sample_vs_oracle(torch, orc):
+    """Two instances of the 16-instance 256 x 256 workload (shortest
+    horizons), batched, chain schedule, against the oracle."""
+    full = workloads.make("advdiff2d_256")
+    picks = sorted(range(len(full)), key=lambda i: full[i]["n_steps"])[:2]
+    insts = [full[i] for i in picks]
+    r = api.GradientRunner(insts, method="paraexp", krylov="poly", sched="chain")
+    r.run()
+    code, est = r.status()
+    for inst, b in zip(insts, r.results()):
+        want = orc.gradient(inst)
+        e = rel(b["grad"], want["grad"])
+        say("2d workload T=%.3f nt=%d: qT %.2e grad %.2e" % (
+            inst["T"], inst["n_steps"], rel(b["qT"], want["qT"]), e))
+        assert e < FP64_GATE
+    assert code == 0
