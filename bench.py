@@ -100,6 +100,13 @@ def main():
                     help="threads per workgroup of the Krylov kernels (0 = default)")
     ap.add_argument("--graph", action="store_true",
                     help="also time replays of the gradient captured in a hipGraph")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick P, Krylov flavour, schedule and workgroup size with the "
+                         "library's autotuner before timing")
+    ap.add_argument("--p-range", default="8,256",
+                    help="slice counts the autotuner may choose (lo,hi)")
+    ap.add_argument("--instances", type=int, default=0,
+                    help="use only the first K instances of a batch workload (0 = all)")
     ap.add_argument("--oracle-budget", type=float, default=2.5e8,
                     help="point-steps of the oracle accuracy sample for batch workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -132,6 +139,8 @@ def main():
                           "launches": 5}), flush=True)
         return
     insts = workloads.make(args.workload)
+    if args.instances > 0:
+        insts = insts[:args.instances]
     inst = insts[0]
     B = len(insts)
     n, n_steps, P, m = inst["nx"] * inst.get("ny", 1), inst["n_steps"], inst["P"], inst["m"]
@@ -141,8 +150,25 @@ def main():
 
     tol = args.tol if args.tol is not None else (1e-10 if args.prec == "fp64" else 1e-6)
     kw = dict(prec=args.prec, block=args.block, kblock=args.kblock)
-    pxp = api.GradientRunner(insts, method="paraexp", krylov=args.krylov,
-                             sched=args.sched, tol=tol, **kw)
+    tuned = None
+    if args.autotune:
+        lo, hi = (int(v) for v in args.p_range.split(","))
+        t0 = time.perf_counter()
+        probs, rep = api.autotune(insts, p_min=lo, p_max=hi,
+                                  rtol=1e-9 if args.prec == "fp64" else 2e-6,
+                                  krylov=args.krylov, sched=args.sched, tol=tol, **kw)
+        names = {v: k for k, v in _lib.KRYLOV.items()}
+        tuned = {"seconds": time.perf_counter() - t0,
+                 "P": sorted({int(p.P) for p in probs}),
+                 "krylov": sorted({names[int(p.krylov)] for p in probs}),
+                 "sched": sorted({"classic" if p.sched == 0 else "chain" for p in probs}),
+                 "kblock": sorted({int(p.kblock) for p in probs}),
+                 "groups": len({r["group"] for r in rep})}
+        log("autotune", tuned, rep[:4])
+        pxp = api.GradientRunner(insts, method="paraexp", problems=probs)
+    else:
+        pxp = api.GradientRunner(insts, method="paraexp", krylov=args.krylov,
+                                 sched=args.sched, tol=tol, **kw)
     ser = api.GradientRunner(insts, method="serial", krylov="auto", **kw)
 
     # timed Paraexp region, with per-kernel events on the library's stream
@@ -250,6 +276,8 @@ def main():
     }
     if t_graph is not None:
         line["graph"] = {"value": B / t_graph, "ms_per_step": t_graph * 1e3}
+    if tuned is not None:
+        line["config"]["autotune"] = tuned
     if not args.no_cpu_baseline:
         w_s = sum(work[i] for i in sample)
         t_all = t_orc * sum(work) / w_s

@@ -155,8 +155,8 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
                         double* grad, double* qT, double* lam_out, void* ws,
                         size_t ws_bytes, void* stream);
 
-/* Same as pxp_gradient with method = PXP_METHOD_PARAEXP: the name of the
- * spec entry point. */
+/* Same as pxp_gradient with method = PXP_METHOD_PARAEXP, without the
+ * lam_out output: the one-call form of the time-parallel gradient. */
 pxp_status gradient(const pxp_problem* pb, int32_t batch, const double* ctrl,
                     const double* basis, const double* q0,
                     const double* u_tgt, double* J, double* grad, double* qT,
@@ -212,6 +212,41 @@ enum {
 pxp_status pxp_profile_enable(int32_t on);
 pxp_status pxp_profile_read(int32_t kernel_class, double* total_ms,
                             int32_t* count);
+
+/* Autotuner (host-driven: synchronises `stream`, not for graph capture).
+ * Instances that share op, grid, precision and control kind form a group;
+ * for each group the gradient of its longest instance is timed over
+ * candidate settings and the fastest candidate whose gradient agrees with
+ * the serial method's gradient (the exact discrete adjoint of the same RK4
+ * march) to `rtol` (relative L2) is kept.  Candidates: slice counts P among
+ * the divisors of n_steps in [p_min, p_max] (at most six, spread
+ * geometrically; 0 = 8 and 256), polynomial or shift-and-invert Krylov,
+ * classic or chain schedule (linear problems), 256 or 512 Krylov threads
+ * (1D).  Candidates slower than four times the best so far in their warm-up
+ * run are not timed further; `reps` timed runs each (0 = 2).  The other
+ * instances of the group take the tuned krylov, sched and kblock, and the
+ * slice count whose slices last about as long as the tuned ones; each is
+ * checked against its own serial gradient and its slice count doubled (to
+ * the next divisor of n_steps) until it passes, at most four times.  Arrays
+ * are packed as for pxp_gradient; ws must hold pxp_tune_workspace_size bytes
+ * (256-byte aligned); report (host, nullable) receives one entry per
+ * instance (rel_err = -1 when no setting passed: the instance then keeps
+ * its own settings). */
+typedef struct {
+    int32_t P, krylov, sched, kblock;
+    int32_t candidates;  /* candidates tried for the group                */
+    int32_t group;       /* index of the group's timed instance           */
+    double ms;           /* Paraexp gradient time of that instance        */
+    double serial_ms;    /* serial-method gradient time of that instance  */
+    double rel_err;      /* its gradient vs the serial gradient           */
+} pxp_tune_report;
+pxp_status pxp_tune_workspace_size(const pxp_problem* pb, int32_t batch,
+                                   int32_t p_min, int32_t p_max, size_t* bytes);
+pxp_status pxp_autotune(pxp_problem* pb, int32_t batch, const double* ctrl,
+                        const double* basis, const double* q0,
+                        const double* u_tgt, int32_t p_min, int32_t p_max,
+                        double rtol, int32_t reps, void* ws, size_t ws_bytes,
+                        pxp_tune_report* report, void* stream);
 
 /* Human-readable text for a status code (static storage). */
 const char* pxp_status_str(pxp_status s);

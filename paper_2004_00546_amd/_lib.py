@@ -31,7 +31,8 @@ EXPORTED = ("pxp_workspace_size", "pxp_workspace_init", "paraexp_direct",
             "paraexp_adjoint", "pxp_gradient", "gradient", "pxp_device_status",
             "pxp_device_counters", "pxp_status_str", "pxp_version",
             "pxp_profile_enable", "pxp_profile_read", "pxp_assemble",
-            "pxp_cost", "pxp_reduce_gradient")
+            "pxp_cost", "pxp_reduce_gradient", "pxp_tune_workspace_size",
+            "pxp_autotune")
 KCLASS = {"slices": 0, "krylov_direct": 1, "krylov_adjoint": 2,
           "serial_direct": 3, "serial_reverse": 4, "ltv_adjoint": 5,
           "ltv_nodes": 6}
@@ -51,6 +52,14 @@ class pxp_problem(ctypes.Structure):
                 ("T", ctypes.c_double), ("omega", ctypes.c_double),
                 ("beta", ctypes.c_double), ("krylov_tol", ctypes.c_double),
                 ("si_gamma", ctypes.c_double)]
+
+
+class pxp_tune_report(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int32), ("krylov", ctypes.c_int32),
+                ("sched", ctypes.c_int32), ("kblock", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("group", ctypes.c_int32),
+                ("ms", ctypes.c_double), ("serial_ms", ctypes.c_double),
+                ("rel_err", ctypes.c_double)]
 
 
 class PxpError(RuntimeError):
@@ -94,6 +103,9 @@ def load() -> ctypes.CDLL:
         "pxp_profile_read": (st, [i32, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int32)]),
         "pxp_version": (ctypes.c_char_p, []),
+        "pxp_tune_workspace_size": (st, [P, i32, i32, i32, ctypes.POINTER(sz)]),
+        "pxp_autotune": (st, [P, i32, vp, vp, vp, vp, i32, i32, ctypes.c_double, i32,
+                              vp, sz, ctypes.POINTER(pxp_tune_report), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -218,3 +230,26 @@ def pxp_reduce_gradient(problems, basis, v, ctrl, grad, stream=None):
     _check(load().pxp_reduce_gradient(arr, n, _ptr(basis), _ptr(v), _ptr(ctrl),
                                       _ptr(grad), _stream(stream)),
            "pxp_reduce_gradient")
+
+
+def pxp_tune_workspace_size(problems, p_min=0, p_max=0) -> int:
+    arr, n = problems_array(problems)
+    out = ctypes.c_size_t(0)
+    _check(load().pxp_tune_workspace_size(arr, n, p_min, p_max, ctypes.byref(out)),
+           "pxp_tune_workspace_size")
+    return out.value
+
+
+def pxp_autotune(problems, ctrl, basis, q0, u_tgt, ws, p_min=0, p_max=0, rtol=1e-9,
+                 reps=2, stream=None):
+    """Tunes the problems in place (the ctypes structures are updated) and
+    returns the per-instance reports."""
+    arr, n = problems_array(problems)
+    rep = (pxp_tune_report * n)()
+    _check(load().pxp_autotune(arr, n, _ptr(ctrl), _ptr(basis), _ptr(q0), _ptr(u_tgt),
+                               p_min, p_max, rtol, reps, _ptr(ws), ws.numel(), rep,
+                               _stream(stream)), "pxp_autotune")
+    for i in range(n):
+        ctypes.memmove(ctypes.byref(problems[i]), ctypes.byref(arr[i]),
+                       ctypes.sizeof(pxp_problem))
+    return [dict((f, getattr(r, f)) for f, _ in pxp_tune_report._fields_) for r in rep]

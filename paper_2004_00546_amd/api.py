@@ -41,16 +41,19 @@ def make_problem(inst: dict, krylov: str = "shift_invert", sched: str = "classic
 
 
 class GradientRunner:
-    """Device buffers for a batch of instances and one gradient call."""
+    """Device buffers for a batch of instances and one gradient call.
+    ``problems`` (optional) replaces the problem descriptions built from the
+    instances, e.g. by tuned ones."""
 
     def __init__(self, instances, method: str = "paraexp", device: str = "cuda:0",
-                 a=None, **prob_kw):
+                 a=None, problems=None, **prob_kw):
         import torch
         self.torch = torch
         self.instances = list(instances)
         self.method = method
         self.device = torch.device(device)
-        self.problems = [make_problem(inst, **prob_kw) for inst in self.instances]
+        self.problems = (list(problems) if problems is not None else
+                         [make_problem(inst, **prob_kw) for inst in self.instances])
         f64 = dict(dtype=torch.float64, device=self.device)
         ctrl = [np.asarray(inst["a"] if a is None else a[i], dtype=np.float64)
                 for i, inst in enumerate(self.instances)]
@@ -98,3 +101,16 @@ class GradientRunner:
             o += n
             ko += K
         return out
+
+
+def autotune(instances, p_min: int = 0, p_max: int = 0, rtol: float = 1e-9,
+             reps: int = 2, device: str = "cuda:0", **prob_kw):
+    """Run the library's autotuner on the instances (their own controls as
+    the sample point); returns (tuned problems, per-instance reports)."""
+    r = GradientRunner(instances, method="paraexp", device=device, **prob_kw)
+    torch = r.torch
+    nbytes = _lib.pxp_tune_workspace_size(r.problems, p_min, p_max)
+    ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=r.device)
+    rep = _lib.pxp_autotune(r.problems, r.ctrl, r.basis, r.q0, r.u_tgt, ws, p_min, p_max,
+                            rtol, reps)
+    return r.problems, rep

@@ -28,7 +28,7 @@ def lib():
     return _lib.load()
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_three_boundary_calls():
     names = declared_functions()
     for n in ("paraexp_direct", "paraexp_adjoint", "gradient"):
         assert n in names
@@ -153,3 +153,15 @@ def test_2d_shape_and_precision_rules():
     # eight steps per slice: sized and accepted, refused by the Paraexp call
     p8 = api.make_problem(dict(base, P=8), krylov="poly")
     assert _lib.pxp_workspace_size([p8]) > 0
+
+
+def test_tune_workspace_covers_every_candidate():
+    """The tuner's workspace holds the largest candidate's workspace plus the
+    gradient scratch; it is a host-only computation."""
+    inst = workloads.make("advdiff1d_n128")[0]
+    p = api.make_problem(inst, krylov="poly")
+    plain = _lib.pxp_workspace_size([p])
+    tuned = _lib.pxp_tune_workspace_size([p], 4, 64)
+    assert tuned >= plain
+    # a larger slice range needs at least as much
+    assert _lib.pxp_tune_workspace_size([p], 4, 500) >= tuned
