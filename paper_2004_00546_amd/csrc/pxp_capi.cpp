@@ -676,20 +676,50 @@ bool contains(const std::vector<int>& v, int i) {
     return false;
 }
 
+// Launches of one batched 2D phase, one per row length: entries of `tab`
+// are ordered by nx, and blk0 counts from zero within each group.
+struct Group2D {
+    int first, count, blocks, nx;
+};
+
+std::vector<Group2D> group2d(std::vector<Band2D>& tab) {
+    std::vector<Group2D> g;
+    for (int j = 0; j < (int)tab.size(); ++j) {
+        const int nb = tab[j].items * (tab[j].ny / BAND_ROWS);
+        if (g.empty() || g.back().nx != tab[j].nx) g.push_back({j, 0, 0, tab[j].nx});
+        tab[j].blk0 = g.back().blocks;
+        g.back().blocks += nb;
+        ++g.back().count;
+    }
+    return g;
+}
+
 // Serial march of every instance: launch L advances each instance by up to
-// four steps; returns in `last` the buffer that holds each final state.
-pxp_status serial2d(std::vector<Band2D>& tab, Band2D* dtab, int nb_total, bool rev,
-                    hipStream_t s) {
-    int64_t lmax = 0;
-    for (const Band2D& d : tab) lmax = std::max(lmax, (d.n_t + 3) / 4);
+// four steps (entries ordered by nx).
+pxp_status serial2d(std::vector<Band2D>& tab, Band2D* dtab, bool rev, hipStream_t s) {
+    const std::vector<Group2D> groups = group2d(tab);
     HIPCHK(launch_upload(dtab, tab.data(), tab.size() * sizeof(Band2D), s));
-    for (int64_t L = 0; L < lmax; ++L) {
-        if (rev)
-            HIPCHK(launch_band2d_rev(dtab, (int)tab.size(), nb_total, (int)L, s));
-        else
-            HIPCHK(launch_band2d(dtab, (int)tab.size(), nb_total, 1, (int)L, s));
+    for (const Group2D& g : groups) {
+        int64_t lmax = 0;
+        for (int j = g.first; j < g.first + g.count; ++j)
+            lmax = std::max(lmax, (tab[j].n_t + 3) / 4);
+        for (int64_t L = 0; L < lmax; ++L) {
+            if (rev)
+                HIPCHK(launch_band2d_rev(dtab + g.first, g.count, g.blocks, g.nx, (int)L, s));
+            else
+                HIPCHK(launch_band2d(dtab + g.first, g.count, g.blocks, g.nx, 1, (int)L, s));
+        }
     }
     return PXP_OK;
+}
+
+// Instances ordered by row length (stable), for the per-nx band launches.
+std::vector<int> by_nx(const pxp_problem* pb, const std::vector<int>& idx) {
+    std::vector<int> o(idx.size());
+    for (size_t j = 0; j < o.size(); ++j) o[j] = (int)j;
+    std::stable_sort(o.begin(), o.end(),
+                     [&](int x, int y) { return pb[idx[x]].nx < pb[idx[y]].nx; });
+    return o;
 }
 
 const double* serial2d_result(const Band2D& d) {
@@ -706,11 +736,10 @@ pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, v
     if (idx.empty()) return PXP_OK;
     auto* dtab = reinterpret_cast<Band2D*>(static_cast<char*>(ws) + Ly.t2d);
     std::vector<Band2D> tab;
-    int blk = 0;
-    for (size_t j = 0; j < idx.size(); ++j) {
+    const std::vector<int> ord = by_nx(pb, idx);
+    for (int j : ord) {
         const pxp_problem& p = pb[idx[j]];
         Ctx c = make_ctx(p, ws, Ly, idx[j], s);
-        const int n = c.n(), nb = p.ny / BAND_ROWS;
         Band2D d{};
         d.F = F[j];
         d.nx = p.nx;
@@ -718,7 +747,6 @@ pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, v
         d.dt = c.dt();
         d.omega = p.omega;
         d.A = advdiff2d_sten(p);
-        d.blk0 = blk;
         if (method == PXP_METHOD_SERIAL) {
             d.y0 = init[j];
             d.buf[0] = c.at(c.L.sbuf0);
@@ -726,36 +754,35 @@ pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, v
             d.n_t = p.n_steps;
             d.items = 1;
         } else {
-            if (init[j]) {
-                // IC shift q~ = q - q0: the source gains A q0 (eq. linzero)
-                HIPCHK(launch_apply5(init[j], c.at(c.L.g0), p.nx, p.ny, d.A, s));
-                d.g0 = c.at(c.L.g0);
-            }
+            // the initial state is the first slice's initial data, so the
+            // superposition below needs no q0 term
+            d.y0 = init[j];
             d.out = c.at(c.L.slices);
             d.items = p.P;
             d.nsteps = (int)(p.n_steps / p.P);
             d.item_steps = p.n_steps / p.P;
-            (void)n;
         }
-        blk += d.items * nb;
         tab.push_back(d);
     }
     if (method == PXP_METHOD_SERIAL) {
         {
             ProfScope ps(PXP_K_SERIAL_DIRECT, s);
-            pxp_status st = serial2d(tab, dtab, blk, false, s);
+            pxp_status st = serial2d(tab, dtab, false, s);
             if (st != PXP_OK) return st;
         }
-        for (size_t j = 0; j < idx.size(); ++j)
-            HIPCHK(launch_add(nullptr, serial2d_result(tab[j]), qT[j],
-                              (int)grid_n(pb[idx[j]]), s));
+        for (size_t e = 0; e < ord.size(); ++e)
+            HIPCHK(launch_add(nullptr, serial2d_result(tab[e]), qT[ord[e]],
+                              (int)grid_n(pb[idx[ord[e]]]), s));
         return PXP_OK;
     }
-    // (1) the P inhomogeneous slices of every instance, one launch
+    // (1) the P inhomogeneous slices of every instance, one launch per row
+    // length
+    const std::vector<Group2D> groups = group2d(tab);
     HIPCHK(launch_upload(dtab, tab.data(), tab.size() * sizeof(Band2D), s));
     {
         ProfScope ps(PXP_K_SLICES, s);
-        HIPCHK(launch_band2d(dtab, (int)tab.size(), blk, 0, 0, s));
+        for (const Group2D& g : groups)
+            HIPCHK(launch_band2d(dtab + g.first, g.count, g.blocks, g.nx, 0, 0, s));
     }
     // (2) homogeneous pieces: classic (P-1 workgroups) or chain (one)
     std::vector<KrylovArgs> kt;
@@ -800,12 +827,12 @@ pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, v
         const int n = c.n();
         const double* sl = c.at(c.L.slices);
         if (p.P == 1)
-            HIPCHK(launch_recombine(init[j], sl, nullptr, 0, n, qT[j], c.st, s));
+            HIPCHK(launch_recombine(nullptr, sl, nullptr, 0, n, qT[j], c.st, s));
         else if (p.sched == PXP_SCHED_CLASSIC)
-            HIPCHK(launch_recombine(init[j], sl + (size_t)(p.P - 1) * n,
+            HIPCHK(launch_recombine(nullptr, sl + (size_t)(p.P - 1) * n,
                                     c.at(c.L.pieces), p.P - 1, n, qT[j], c.st, s));
         else
-            HIPCHK(launch_recombine(init[j], nullptr, c.at(c.L.chain), 1, n, qT[j], c.st,
+            HIPCHK(launch_recombine(nullptr, nullptr, c.at(c.L.chain), 1, n, qT[j], c.st,
                                     s));
     }
     return PXP_OK;
@@ -820,8 +847,8 @@ pxp_status adjoint_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, 
     if (method == PXP_METHOD_SERIAL) {
         auto* dtab = reinterpret_cast<Band2D*>(static_cast<char*>(ws) + Ly.t2d);
         std::vector<Band2D> tab;
-        int blk = 0;
-        for (size_t j = 0; j < idx.size(); ++j) {
+        const std::vector<int> ord = by_nx(pb, idx);
+        for (int j : ord) {
             const pxp_problem& p = pb[idx[j]];
             Ctx c = make_ctx(p, ws, Ly, idx[j], s);
             Band2D d{};
@@ -836,20 +863,18 @@ pxp_status adjoint_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, 
             d.omega = p.omega;
             d.A = transpose5(advdiff2d_sten(p));
             d.items = 1;
-            d.blk0 = blk;
-            blk += p.ny / BAND_ROWS;
             tab.push_back(d);
             if (Lam[j]) HIPCHK(launch_zero(Lam[j], (size_t)grid_n(p), s));
         }
         {
             ProfScope ps(PXP_K_SERIAL_REVERSE, s);
-            pxp_status st = serial2d(tab, dtab, blk, true, s);
+            pxp_status st = serial2d(tab, dtab, true, s);
             if (st != PXP_OK) return st;
         }
-        for (size_t j = 0; j < idx.size(); ++j)
-            if (lam0[j])
-                HIPCHK(launch_add(nullptr, serial2d_result(tab[j]), lam0[j],
-                                  (int)grid_n(pb[idx[j]]), s));
+        for (size_t e = 0; e < ord.size(); ++e)
+            if (lam0[ord[e]])
+                HIPCHK(launch_add(nullptr, serial2d_result(tab[e]), lam0[ord[e]],
+                                  (int)grid_n(pb[idx[ord[e]]]), s));
         return PXP_OK;
     }
     // one homogeneous piece per instance from q^dagger(T) over [T, 0]

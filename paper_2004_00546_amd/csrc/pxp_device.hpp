@@ -101,16 +101,33 @@ __device__ __forceinline__ void block_multi_sum(double (&part)[KMAX], int cnt,
 
 // ---- small dense matrices in LDS (n <= 64 rows) -----------------------
 
+// Visits the (row, col) pairs of an n x ncol index space, this thread's
+// share in the order o = threadIdx.x + i * blockDim.x, without a division
+// per element.
+template <class F>
+__device__ __forceinline__ void for_rc(int n, int ncol, F&& f) {
+    const int B = blockDim.x;
+    int r = threadIdx.x / ncol, c = threadIdx.x - r * ncol;
+    const int dr = B / ncol, dc = B - dr * ncol;
+    while (r < n) {
+        f(r, c);
+        c += dc;
+        r += dr;
+        if (c >= ncol) {
+            c -= ncol;
+            ++r;
+        }
+    }
+}
+
 // C = A * B (n x n, leading dimension ld).  C must not alias A or B.
 __device__ __forceinline__ void sm_matmul(double* C, const double* A, const double* B,
                                  int n, int ld) {
-    const int tot = n * n;
-    for (int o = threadIdx.x; o < tot; o += blockDim.x) {
-        const int r = o / n, c = o - r * n;
+    for_rc(n, n, [&](int r, int c) {
         double s = 0.0;
         for (int k = 0; k < n; ++k) s += A[r * ld + k] * B[k * ld + c];
         C[r * ld + c] = s;
-    }
+    });
     __syncthreads();
 }
 
@@ -118,13 +135,12 @@ __device__ __forceinline__ void sm_matmul(double* C, const double* A, const doub
 __device__ __forceinline__ void sm_comb(double* Y, int n, int ld, double a,
                                const double* X, double g, const double* Z,
                                double dI) {
-    for (int o = threadIdx.x; o < n * n; o += blockDim.x) {
-        const int r = o / n, c = o - r * n;
+    for_rc(n, n, [&](int r, int c) {
         double v = a * X[r * ld + c];
         if (Z) v += g * Z[r * ld + c];
         if (r == c) v += dI;
         Y[r * ld + c] = v;
-    }
+    });
     __syncthreads();
 }
 
@@ -176,11 +192,12 @@ __device__ __forceinline__ bool sm_gauss_jordan(double* Ab, int n, int ncol, int
         if (d == 0.0) { ok = false; break; }
         const double inv = 1.0 / d;
         // eliminate column k from every other row, then scale the pivot row
-        const int tot = n * ncol;
-        for (int o = threadIdx.x; o < tot; o += blockDim.x) {
-            const int r = o / ncol, c = o - r * ncol;
-            if (r != k && c > k) Ab[r * ld + c] -= Ab[r * ld + k] * inv * Ab[k * ld + c];
-        }
+        const int w = ncol - k - 1;
+        if (w > 0)
+            for_rc(n, w, [&](int r, int cc) {
+                const int c = k + 1 + cc;
+                if (r != k) Ab[r * ld + c] -= Ab[r * ld + k] * inv * Ab[k * ld + c];
+            });
         __syncthreads();
         for (int c = threadIdx.x; c < ncol; c += blockDim.x)
             if (c > k) Ab[k * ld + c] *= inv;
@@ -190,6 +207,110 @@ __device__ __forceinline__ bool sm_gauss_jordan(double* Ab, int n, int ncol, int
     }
     (void)red;
     return ok;
+}
+
+// Solves the complex upper-Hessenberg system (Mr + i Mi) x = (xr + i xi)
+// in place (n x n, leading dimension n; the right-hand side is overwritten
+// by the solution).  Gaussian elimination with partial pivoting: column j
+// has one entry below the diagonal, so step j only compares, swaps and
+// combines rows j and j+1 (columns j+1.. and the right-hand side; the pivot
+// goes to dr/di, so no thread writes what another may still be reading);
+// then back substitution, one column per step.  All threads take the same
+// pivot decisions from the same LDS values.  dr, di: n doubles of scratch.
+__device__ __forceinline__ void sm_hess_solve_c(double* Mr, double* Mi, double* xr,
+                                                double* xi, double* dr, double* di,
+                                                int n) {
+    const int t = threadIdx.x, B = blockDim.x;
+    for (int j = 0; j + 1 < n; ++j) {
+        const double ar = Mr[j * n + j], ai = Mi[j * n + j];
+        const double br = Mr[(j + 1) * n + j], bi = Mi[(j + 1) * n + j];
+        const bool swap = (br * br + bi * bi) > (ar * ar + ai * ai);
+        const double pr = swap ? br : ar, pi = swap ? bi : ai;
+        const double qr = swap ? ar : br, qi = swap ? ai : bi;
+        const double den = pr * pr + pi * pi;
+        const double lr = (qr * pr + qi * pi) / den, li = (qi * pr - qr * pi) / den;
+        if (t == 0) {
+            dr[j] = pr;
+            di[j] = pi;
+        }
+        for (int c = j + 1 + t; c <= n; c += B) {
+            // column n stands for the right-hand side
+            double* R0 = (c < n) ? Mr + j * n + c : xr + j;
+            double* I0 = (c < n) ? Mi + j * n + c : xi + j;
+            double* R1 = (c < n) ? Mr + (j + 1) * n + c : xr + j + 1;
+            double* I1 = (c < n) ? Mi + (j + 1) * n + c : xi + j + 1;
+            const double ur = swap ? *R1 : *R0, ui = swap ? *I1 : *I0;
+            const double vr = swap ? *R0 : *R1, vi = swap ? *I0 : *I1;
+            *R0 = ur;
+            *I0 = ui;
+            *R1 = vr - (lr * ur - li * ui);
+            *I1 = vi - (lr * ui + li * ur);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        dr[n - 1] = Mr[(n - 1) * n + n - 1];
+        di[n - 1] = Mi[(n - 1) * n + n - 1];
+    }
+    __syncthreads();
+    for (int i = n - 1; i >= 0; --i) {
+        const double ddr = dr[i], ddi = di[i];
+        const double den = ddr * ddr + ddi * ddi;
+        const double sr = xr[i], si = xi[i];
+        const double yr = (sr * ddr + si * ddi) / den, yi = (si * ddr - sr * ddi) / den;
+        for (int r = t; r < i; r += B) {
+            const double mr = Mr[r * n + i], mi = Mi[r * n + i];
+            xr[r] -= mr * yr - mi * yi;
+            xi[r] -= mr * yi + mi * yr;
+        }
+        __syncthreads();
+        if (t == 0) {
+            xr[i] = yr;
+            xi[i] = yi;
+        }
+    }
+    __syncthreads();
+}
+
+// X = H^{-1} for an n x n upper-Hessenberg H (leading dimension ldh, read
+// only).  U (n x n) and D (n) are scratch; X has leading dimension n.
+// Elimination of [H | I] with partial pivoting between neighbouring rows
+// (one barrier per column; the pivots go to D so no thread overwrites what
+// another may still read), then back substitution with one thread per
+// column of X.
+__device__ __forceinline__ void sm_hess_inverse(const double* H, int ldh, int n,
+                                                double* U, double* D, double* X) {
+    const int t = threadIdx.x, B = blockDim.x;
+    for_rc(n, n, [&](int r, int c) {
+        U[r * n + c] = H[r * ldh + c];
+        X[r * n + c] = (r == c) ? 1.0 : 0.0;
+    });
+    __syncthreads();
+    for (int j = 0; j + 1 < n; ++j) {
+        const double a = U[j * n + j], b = U[(j + 1) * n + j];
+        const bool swap = fabs(b) > fabs(a);
+        const double p = swap ? b : a, l = (swap ? a : b) / p;
+        if (t == 0) D[j] = p;
+        const int wu = n - j - 1;  // columns j+1.. of U, then the n of X
+        for (int c = t; c < wu + n; c += B) {
+            double* R0 = (c < wu) ? U + j * n + j + 1 + c : X + j * n + (c - wu);
+            double* R1 = (c < wu) ? U + (j + 1) * n + j + 1 + c : X + (j + 1) * n + (c - wu);
+            const double u = swap ? *R1 : *R0, v = swap ? *R0 : *R1;
+            *R0 = u;
+            *R1 = v - l * u;
+        }
+        __syncthreads();
+    }
+    if (t == 0) D[n - 1] = U[(n - 1) * n + n - 1];
+    __syncthreads();
+    for (int c = t; c < n; c += B) {
+        for (int i = n - 1; i >= 0; --i) {
+            double s = X[i * n + c];
+            for (int q = i + 1; q < n; ++q) s -= U[i * n + q] * X[q * n + c];
+            X[i * n + c] = s / D[i];
+        }
+    }
+    __syncthreads();
 }
 
 // E = exp(M) for an n x n matrix in LDS (M is overwritten).  Taylor
@@ -227,13 +348,12 @@ __device__ __forceinline__ int sm_expm(double* E, double* M, int n, int ld, doub
     for (int j = 3; j >= 0; --j) {
         sm_matmul(E, A4, T, n, ld);
         const int b = 4 * j;
-        for (int o = threadIdx.x; o < n * n; o += blockDim.x) {
-            const int r = o / n, c = o - r * n;
+        for_rc(n, n, [&](int r, int c) {
             const int ix = r * ld + c;
             double v = E[ix] + f[b + 1] * A[ix] + f[b + 2] * A2[ix] + f[b + 3] * A3[ix];
             if (r == c) v += f[b];
             T[ix] = v;
-        }
+        });
         __syncthreads();
     }
     double* src = T;
@@ -245,10 +365,7 @@ __device__ __forceinline__ int sm_expm(double* E, double* M, int n, int ld, doub
         dst = t;
     }
     if (src != E) {
-        for (int o = threadIdx.x; o < n * n; o += blockDim.x) {
-            const int r = o / n, c = o - r * n;
-            E[r * ld + c] = src[r * ld + c];
-        }
+        for_rc(n, n, [&](int r, int c) { E[r * ld + c] = src[r * ld + c]; });
         __syncthreads();
     }
     return s;

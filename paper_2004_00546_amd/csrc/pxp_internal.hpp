@@ -135,8 +135,9 @@ bool krylov_shape_pub(int n, int block_hint, int* B, int* pt);
 
 // One entry of a batched 2D RK4 march: `items` independent marches of one
 // instance (the slices, or the single serial march), each of nsteps steps of
-//   y' = A y + sin(omega t) F + g0,
-// item q starting at global step step0 + q * item_steps from y0 (null: zero).
+//   y' = A y + sin(omega t) F,
+// item q starting at global step step0 + q * item_steps, item 0 from y0
+// (null: zero) and the others from zero.
 // Workgroups blk0 .. blk0 + items * ny / 16 - 1 of the launch belong to the
 // entry.  Serial sweeps: launch number L of the sweep advances the state in
 // buf[L & 1] (y0 when L == 0) by min(4, n_t - 4L) steps into buf[(L+1) & 1];
@@ -145,7 +146,6 @@ bool krylov_shape_pub(int n, int block_hint, int* B, int* pt);
 struct Band2D {
     const double* y0;
     const double* F;
-    const double* g0;
     double* out;
     double* buf[2];
     double* Lam;
@@ -156,12 +156,13 @@ struct Band2D {
 };
 constexpr int BAND_ROWS = 16;  // interior rows per workgroup
 constexpr int BAND_MAX_STEPS = 4;
-// Forward: slices (serial == 0) or launch L of a serial sweep.
-hipError_t launch_band2d(const Band2D* tab, int count, int total_blocks, int serial,
-                         int L, hipStream_t s);
+// Forward: slices (serial == 0) or launch L of a serial sweep.  Every
+// entry of one launch has row length nx (64, 128 or 256).
+hipError_t launch_band2d(const Band2D* tab, int count, int total_blocks, int nx,
+                         int serial, int L, hipStream_t s);
 // Reverse launch L of the serial discrete-adjoint sweep (A holds A^T).
-hipError_t launch_band2d_rev(const Band2D* tab, int count, int total_blocks, int L,
-                             hipStream_t s);
+hipError_t launch_band2d_rev(const Band2D* tab, int count, int total_blocks, int nx,
+                             int L, hipStream_t s);
 // out = Op x for a five-point operator
 hipError_t launch_apply5(const double* x, double* out, int nx, int ny, Sten5 op,
                          hipStream_t s);

@@ -14,8 +14,13 @@
 //    substep only re-evaluates the small exponential;
 //  - shift-and-invert: K_m((I - gamma A)^{-1}, v), gamma = gamma_frac * tau,
 //    with A ~ (I - H_m^{-1}) / gamma on the space; the periodic tridiagonal
-//    solve is parallel cyclic reduction in LDS (n a power of two).  Error
-//    estimate: difference of the dimension m and m-1 approximations.
+//    solve is parallel cyclic reduction in LDS (uniform coefficients, n a
+//    power of two) or chunk elimination plus cyclic reduction of the chunk
+//    interfaces (the Burgers Jacobian).  From about m/2 on, every eighth
+//    dimension compares the approximation with the previous check's and
+//    stops once they differ by less than the tolerance; at full dimension
+//    the estimate is the difference of the dimension m and m-1
+//    approximations.
 //
 // Optional time integral of the piece against sin(a + b s):
 //   int_0^tau sin(a + b s) exp(s A) v ds ~ beta V_m Im(e^{ia} x),
@@ -52,6 +57,7 @@ struct Smem {
     double* red;   // num_waves * ldr (ldr = m+1 rounded up to 8)
     double* hcol;  // ldr + 8
     double* H;     // (m+1) x m, ld = m
+    double* yprev; // m: the previous shift-and-invert check's approximation
     double* big;   // vector buffers (2n) or small matrices
     // small-matrix region (inside big)
     double* Mt;    // m x m
@@ -82,7 +88,8 @@ struct Core {
         S.red = lds;
         S.hcol = S.red + 64;
         S.H = S.hcol + ldr + 8;
-        S.big = S.H + (size_t)(m + 1) * m;
+        S.yprev = S.H + (size_t)(m + 1) * m;
+        S.big = S.yprev + ldr;
         S.Mt = S.big;
         S.E = S.Mt + (size_t)m * m;
         S.W = S.E + (size_t)m * m;
@@ -94,17 +101,14 @@ struct Core {
 
     // Mt = scale * (I - H_k^{-1}) / gamma for the leading k x k block.
     __device__ __forceinline__ void si_image(int k, double gamma, double scale) {
-        const int ld = 2 * k;
-        for (int o = t; o < k * ld; o += B) {
-            const int r = o / ld, c = o - r * ld;
-            S.W[o] = (c < k) ? S.H[r * m + c] : ((c - k == r) ? 1.0 : 0.0);
-        }
-        __syncthreads();
-        sm_gauss_jordan(S.W, k, ld, ld, S.red, reinterpret_cast<int*>(S.hcol + ldr));
-        for (int o = t; o < k * k; o += B) {
-            const int r = o / k, c = o - r * k;
-            S.Mt[o] = scale * (((r == c) ? 1.0 : 0.0) - S.W[r * ld + k + c]) / gamma;
-        }
+        double* X = S.W;
+        double* U = X + (size_t)k * k;
+        double* piv = U + (size_t)k * k;
+        sm_hess_inverse(S.H, m, k, U, piv, X);
+        const double f = scale / gamma;
+        for_rc(k, k, [&](int r, int c) {
+            S.Mt[r * k + c] = f * (((r == c) ? 1.0 : 0.0) - X[r * k + c]);
+        });
         __syncthreads();
     }
 
@@ -113,10 +117,7 @@ struct Core {
         if (SI) {
             si_image(k, gamma, ts);
         } else {
-            for (int o = t; o < k * k; o += B) {
-                const int r = o / k, c = o - r * k;
-                S.Mt[o] = ts * S.H[r * m + c];
-            }
+            for_rc(k, k, [&](int r, int c) { S.Mt[r * k + c] = ts * S.H[r * m + c]; });
             __syncthreads();
         }
         sm_expm(S.E, S.Mt, k, k, S.W, S.red);
@@ -126,31 +127,49 @@ struct Core {
     }
 
     // vc = coefficients of int_0^ts sin(ia + ib s) exp(s Hop) e_1 ds, given
-    // vy = exp(ts Hop) e_1.
+    // vy = exp(ts Hop) e_1: Im(e^{i ia} x) with
+    //   (Hop + i ib I) x = e^{i ib ts} vy - e_1.
+    // Polynomial: Hop = H_k is upper Hessenberg.  Shift-and-invert:
+    // Hop = (I - H_k^{-1}) / gamma; multiplying by gamma H_k gives the
+    // Hessenberg system ((1 + i ib gamma) H_k - I) x = gamma H_k (rhs).
     __device__ __forceinline__ void small_integral(int k, double ts, double ia, double ib,
-                                   double gamma) {
-        if (SI) si_image(k, gamma, 1.0);  // Mt = Hop
-        const int n2 = 2 * k, ld = n2 + 1;
+                                                   double gamma) {
+        double* Mr = S.W;
+        double* Mi = Mr + (size_t)k * k;
+        double* xr = Mi + (size_t)k * k;
+        double* xi = xr + k;
+        double* dr = xi + k;
+        double* di = dr + k;
         const double cb = cos(ib * ts), sb = sin(ib * ts);
-        for (int o = t; o < n2 * ld; o += B) {
-            const int r = o / ld, c = o - r * ld;
-            const int rr = (r < k) ? r : r - k;
-            const int c2 = (c < k) ? c : c - k;
-            double v;
-            if (c == n2) {
-                v = (r < k) ? (cb * S.vy[rr] - (rr == 0 ? 1.0 : 0.0)) : sb * S.vy[rr];
-            } else if ((r < k) == (c < k)) {
-                v = SI ? S.Mt[rr * k + c2] : S.H[rr * m + c2];
+        for_rc(k, k, [&](int r, int c) {
+            const double h = S.H[r * m + c];
+            if (SI) {
+                Mr[r * k + c] = h - ((r == c) ? 1.0 : 0.0);
+                Mi[r * k + c] = ib * gamma * h;
             } else {
-                // upper-right block -b I, lower-left block +b I
-                v = (rr == c2) ? ((r < k) ? -ib : ib) : 0.0;
+                Mr[r * k + c] = h;
+                Mi[r * k + c] = (r == c) ? ib : 0.0;
             }
-            S.W[o] = v;
+        });
+        for (int r = t; r < k; r += B) {
+            if (SI) {
+                double sr = 0.0, si = 0.0;
+                for (int c = (r > 0 ? r - 1 : 0); c < k; ++c) {
+                    const double h = S.H[r * m + c];
+                    sr += h * (cb * S.vy[c] - ((c == 0) ? 1.0 : 0.0));
+                    si += h * (sb * S.vy[c]);
+                }
+                xr[r] = gamma * sr;
+                xi[r] = gamma * si;
+            } else {
+                xr[r] = cb * S.vy[r] - ((r == 0) ? 1.0 : 0.0);
+                xi[r] = sb * S.vy[r];
+            }
         }
         __syncthreads();
-        sm_gauss_jordan(S.W, n2, ld, ld, S.red, reinterpret_cast<int*>(S.hcol + ldr));
+        sm_hess_solve_c(Mr, Mi, xr, xi, dr, di, k);
         const double sa = sin(ia), ca = cos(ia);
-        for (int r = t; r < k; r += B) S.vc[r] = sa * S.W[r * ld + n2] + ca * S.W[(r + k) * ld + n2];
+        for (int r = t; r < k; r += B) S.vc[r] = sa * xr[r] + ca * xi[r];
         __syncthreads();
     }
 
@@ -176,21 +195,27 @@ struct Core {
             const double gamma = a.gamma_frac * tau;
             self().before_space(gamma);
             double beta;
-            bool bd;
-            const int me = self().arnoldi(gamma, beta, bd);
-            if (me == 0) return;
-            small_exp(me, tau, gamma, S.vy);
+            bool bd, conv = false;
             double est = 0.0;
-            if (iout) small_integral(me, tau, ia, ib, gamma);
-            if (!bd && me > 1) {
-                small_exp(me - 1, tau, gamma, S.vy2);
-                double s = 0.0;
-                for (int q = 0; q < me; ++q) {
-                    const double d = S.vy[q] - (q < me - 1 ? S.vy2[q] : 0.0);
-                    s += d * d;
+            const int me = self().arnoldi(gamma, beta, bd, tau, tol, &conv, &est);
+            if (me == 0) return;
+            if (!conv) {
+                // full dimension (or breakdown): estimate from dimensions m
+                // and m - 1
+                if (!bd && me > 1) {
+                    small_exp(me - 1, tau, gamma, S.vy2);
+                    small_exp(me, tau, gamma, S.vy);
+                    double s = 0.0;
+                    for (int q = 0; q < me; ++q) {
+                        const double d = S.vy[q] - (q < me - 1 ? S.vy2[q] : 0.0);
+                        s += d * d;
+                    }
+                    est = sqrt(s);  // relative to beta
+                } else {
+                    small_exp(me, tau, gamma, S.vy);
                 }
-                est = sqrt(s);  // relative to beta
             }
+            if (iout) small_integral(me, tau, ia, ib, gamma);
             self().combine(me, beta, iout);
             report(est, est > tol, 1, me);
             __syncthreads();
@@ -700,6 +725,27 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
                     break;
                 }
             }
+            const int k1 = (m / 8 > 1 ? m / 8 : 1) * 4;  // first check, about m/2
+            if (SI && conv && ts > 0.0 && k < m && k >= k1 && ((k - k1) % 8) == 0) {
+                // difference to the approximation of the previous check
+                // (dimension k - 8, kept in yprev): converged when below tol
+                small_exp(k, ts, gamma, S.vy);
+                double d2 = 0.0;
+                for (int q = 0; q < k; ++q) {
+                    const double d = S.vy[q] - ((k > k1 && q < k - 8) ? S.yprev[q] : 0.0);
+                    d2 += d * d;
+                }
+                const double est = sqrt(d2);
+                __syncthreads();
+                if (k > k1 && est <= tolb_rel) {
+                    *conv = true;
+                    if (est_out) *est_out = est;
+                    me = k;
+                    break;
+                }
+                for (int q = t; q < k; q += B) S.yprev[q] = S.vy[q];
+                __syncthreads();
+            }
             const double inv = 1.0 / nrm;
 #pragma unroll
             for (int u = 0; u < PT; ++u) z[u] *= inv;
@@ -1148,7 +1194,7 @@ bool krylov_shape(int n, int block_hint, int* B, int* pt) {
 size_t krylov1d_lds_bytes(int n, int m, int block, int si) {
     (void)si;
     const int ldr = ((m + 1 + 7) / 8) * 8;
-    const size_t d = 64 + ldr + 8 + (size_t)(m + 1) * m + big_doubles(n, m, block);
+    const size_t d = 64 + ldr + 8 + (size_t)(m + 1) * m + ldr + big_doubles(n, m, block);
     return d * sizeof(double);
 }
 
@@ -1156,7 +1202,7 @@ size_t krylov2d_lds_bytes(int m) {
     const int ldr = ((m + 1 + 7) / 8) * 8;
     const size_t part = (size_t)(m + 1) * (KRYLOV2D_BLOCK / 64);
     const size_t sm = 6 * (size_t)m * m + 5 * (size_t)m + 8;
-    const size_t d = 64 + ldr + 8 + (size_t)(m + 1) * m + (part > sm ? part : sm);
+    const size_t d = 64 + ldr + 8 + (size_t)(m + 1) * m + ldr + (part > sm ? part : sm);
     return d * sizeof(double);
 }
 

@@ -18,26 +18,64 @@ namespace pxp {
 namespace {
 
 constexpr int NT2 = 512;  // threads per band workgroup
-// region points per thread: (16 + 2*16 rows) * 256 columns / 512 threads
-constexpr int KPT = (BAND_ROWS + 4 * BAND_MAX_STEPS * 2) * 256 / NT2;
+// region points per thread for rows of NX points: (16 + 2*16 rows) * NX / NT2
+template <int NX>
+constexpr int kpt() {
+    return (BAND_ROWS + 4 * BAND_MAX_STEPS * 2) * NX / NT2;
+}
 
+// Band region of `rows` rows x NX columns; thread t owns column t % NX and
+// rows t / NX + q * (NT2 / NX), q < KPT.  In LDS, region row r sits at row
+// r + 1 with stride NX + 2: a zeroed pad row above and below, and the two
+// periodic neighbour columns stored beside each row, so the stencil reads
+// five fixed offsets from every point (the rows next to the pads are halo
+// rows, whose results are discarded).
+template <int NX>
 struct Region {
-    int nx, rows, np, lnx;
-    __device__ __forceinline__ int row(int p) const { return p >> lnx; }
-    __device__ __forceinline__ int col(int p) const { return p & (nx - 1); }
+    static constexpr int LD = NX + 2;
+    static constexpr int RSTEP = NT2 / NX;
+    int rows, col, r0;
+    __device__ __forceinline__ int row(int q) const { return r0 + q * RSTEP; }
+    __device__ __forceinline__ int idx(int q) const { return (row(q) + 1) * LD + col + 1; }
+    // store v at region point q, with its periodic copy when on an edge
+    __device__ __forceinline__ void put(double* X, int q, double v) const {
+        const int i = idx(q);
+        X[i] = v;
+        if (col == 0) X[i + NX] = v;
+        if (col == NX - 1) X[i - NX] = v;
+    }
 };
 
-// Five-point stencil at region point p from the stage input in LDS; rows
-// outside the region repeat the edge row (those points are discarded).
-__device__ __forceinline__ double sten(const double* X, const Region& R, int p,
-                                       const Sten5& A) {
-    const int r = R.row(p), c = R.col(p);
-    const int base = p - c;
-    const double xw = X[base + (c == 0 ? R.nx - 1 : c - 1)];
-    const double xe = X[base + (c == R.nx - 1 ? 0 : c + 1)];
-    const double xs = X[r == 0 ? p : p - R.nx];
-    const double xn = X[r == R.rows - 1 ? p : p + R.nx];
-    return A.c * X[p] + A.w * xw + A.e * xe + A.s * xs + A.n * xn;
+template <int NX>
+__device__ __forceinline__ Region<NX> make_region(int H) {
+    Region<NX> R;
+    R.rows = BAND_ROWS + 2 * H;
+    R.col = threadIdx.x % NX;
+    R.r0 = threadIdx.x / NX;
+    return R;
+}
+
+template <int NX>
+__device__ __forceinline__ void zero_pads(double* X, const Region<NX>& R) {
+    for (int c = threadIdx.x; c < Region<NX>::LD; c += NT2) {
+        X[c] = 0.0;
+        X[(R.rows + 1) * Region<NX>::LD + c] = 0.0;
+    }
+}
+
+// Five-point stencil at LDS index i.
+template <int NX>
+__device__ __forceinline__ double sten(const double* X, int i, const Sten5& A) {
+    constexpr int LD = Region<NX>::LD;
+    return A.c * X[i] + A.w * X[i - 1] + A.e * X[i + 1] + A.s * X[i - LD] + A.n * X[i + LD];
+}
+
+// global row of band row r (periodic in y)
+__device__ __forceinline__ int grow(int row0, int r, int ny) {
+    int g = row0 + r;
+    if (g < 0) g += ny;
+    if (g >= ny) g -= ny;
+    return g;
 }
 
 __device__ __forceinline__ int find_entry(const Band2D* tab, int count, int b) {
@@ -46,18 +84,15 @@ __device__ __forceinline__ int find_entry(const Band2D* tab, int count, int b) {
     return e;
 }
 
-__device__ __forceinline__ int ilog2(int v) {
-    int l = 0;
-    while ((1 << l) < v) ++l;
-    return l;
-}
-
+template <int NX>
 __global__ void __launch_bounds__(NT2)
 k_band2d_fwd(const Band2D* __restrict__ tab, int count, int serial, int L) {
     extern __shared__ double X[];
-    const int b = blockIdx.x, t = threadIdx.x;
-    const Band2D d = tab[find_entry(tab, count, b)];
-    const int nx = d.nx, ny = d.ny, nb = ny / BAND_ROWS;
+    constexpr int KPT = kpt<NX>();
+    const int b = blockIdx.x;
+    const Band2D& d = tab[find_entry(tab, count, b)];
+    constexpr int nx = NX;
+    const int ny = d.ny, nb = ny / BAND_ROWS;
     const int local = b - d.blk0;
     const int item = local / nb, band = local - item * nb;
     int ns;
@@ -76,23 +111,22 @@ k_band2d_fwd(const Band2D* __restrict__ tab, int count, int serial, int L) {
         if (item >= d.items) return;
         ns = d.nsteps;
         first = d.step0 + (int64_t)item * d.item_steps;
-        in = d.y0;
+        // the initial state belongs to the first slice, the others start
+        // from zero (eq. linInhomEqus)
+        in = (item == 0) ? d.y0 : nullptr;
         out = d.out + (size_t)item * nn;
     }
     const int H = 4 * ns;
-    Region R{nx, BAND_ROWS + 2 * H, (BAND_ROWS + 2 * H) * nx, ilog2(nx)};
+    const Region<NX> R = make_region<NX>(H);
     const int row0 = band * BAND_ROWS - H;
-    // global index of region point p
-    auto gidx = [&](int p) {
-        int gr = row0 + R.row(p);
-        gr = ((gr % ny) + ny) % ny;
-        return gr * nx + R.col(p);
-    };
-    double y[KPT], acc[KPT], Y[KPT];
+    zero_pads(X, R);
+    double y[KPT], acc[KPT], Y[KPT], f[KPT];
 #pragma unroll
     for (int q = 0; q < KPT; ++q) {
-        const int p = t + q * NT2;
-        y[q] = (p < R.np && in) ? in[gidx(p)] : 0.0;
+        const int r = R.row(q);
+        const int g = grow(row0, r, ny) * nx + R.col;
+        y[q] = (r < R.rows && in) ? in[g] : 0.0;
+        f[q] = (r < R.rows && d.F) ? d.F[g] : 0.0;
         acc[q] = 0.0;
         Y[q] = y[q];
     }
@@ -107,21 +141,14 @@ k_band2d_fwd(const Band2D* __restrict__ tab, int count, int serial, int L) {
             const double cy = (st == 2) ? dt : h2;
             __syncthreads();  // previous readers of X are done
 #pragma unroll
-            for (int q = 0; q < KPT; ++q) {
-                const int p = t + q * NT2;
-                if (p < R.np) X[p] = (st == 0) ? y[q] : Y[q];
-            }
+            for (int q = 0; q < KPT; ++q)
+                if (R.row(q) < R.rows) R.put(X, q, (st == 0) ? y[q] : Y[q]);
             __syncthreads();
 #pragma unroll
             for (int q = 0; q < KPT; ++q) {
-                const int p = t + q * NT2;
-                if (p >= R.np) continue;
-                double k = sten(X, R, p, A);
-                if (d.F || d.g0) {
-                    const int g = gidx(p);
-                    if (d.F) k += sv * d.F[g];
-                    if (d.g0) k += d.g0[g];
-                }
+                const int r = R.row(q);
+                if (r >= R.rows) continue;
+                const double k = sten<NX>(X, R.idx(q), A) + sv * f[q];
                 if (st < 3) {
                     acc[q] += cw * k;
                     Y[q] = y[q] + cy * k;
@@ -134,22 +161,23 @@ k_band2d_fwd(const Band2D* __restrict__ tab, int count, int serial, int L) {
     }
 #pragma unroll
     for (int q = 0; q < KPT; ++q) {
-        const int p = t + q * NT2;
-        if (p >= R.np) continue;
-        const int r = R.row(p);
-        if (r >= H && r < H + BAND_ROWS) out[gidx(p)] = y[q];
+        const int r = R.row(q);
+        if (r >= H && r < H + BAND_ROWS) out[grow(row0, r, ny) * nx + R.col] = y[q];
     }
 }
 
 // Exact discrete adjoint of the RK4 march, backwards over the steps of
 // launch L: per step, kbar_4 = dt/6 lam, Ybar_i = A^T kbar_i, kbar_{i-1} =
 // b_{i-1} dt lam + c_i dt Ybar_i, lam += sum_i Ybar_i, Lam += s(t_i) kbar_i.
+template <int NX>
 __global__ void __launch_bounds__(NT2)
 k_band2d_rev(const Band2D* __restrict__ tab, int count, int L) {
     extern __shared__ double X[];
-    const int b = blockIdx.x, t = threadIdx.x;
-    const Band2D d = tab[find_entry(tab, count, b)];
-    const int nx = d.nx, ny = d.ny;
+    constexpr int KPT = kpt<NX>();
+    const int b = blockIdx.x;
+    const Band2D& d = tab[find_entry(tab, count, b)];
+    constexpr int nx = NX;
+    const int ny = d.ny;
     const int band = b - d.blk0;
     const int64_t left = d.n_t - 4 * (int64_t)L;
     if (left <= 0) return;
@@ -158,18 +186,14 @@ k_band2d_rev(const Band2D* __restrict__ tab, int count, int L) {
     const double* in = (L == 0) ? d.y0 : d.buf[L & 1];
     double* out = d.buf[(L + 1) & 1];
     const int H = 4 * ns;
-    Region R{nx, BAND_ROWS + 2 * H, (BAND_ROWS + 2 * H) * nx, ilog2(nx)};
+    const Region<NX> R = make_region<NX>(H);
     const int row0 = band * BAND_ROWS - H;
-    auto gidx = [&](int p) {
-        int gr = row0 + R.row(p);
-        gr = ((gr % ny) + ny) % ny;
-        return gr * nx + R.col(p);
-    };
+    zero_pads(X, R);
     double lam[KPT], kb[KPT], nl[KPT], Lm[KPT];
 #pragma unroll
     for (int q = 0; q < KPT; ++q) {
-        const int p = t + q * NT2;
-        lam[q] = (p < R.np) ? in[gidx(p)] : 0.0;
+        const int r = R.row(q);
+        lam[q] = (r < R.rows) ? in[grow(row0, r, ny) * nx + R.col] : 0.0;
         Lm[q] = 0.0;
         nl[q] = 0.0;
         kb[q] = 0.0;
@@ -188,16 +212,14 @@ k_band2d_rev(const Band2D* __restrict__ tab, int count, int L) {
             const double cy = (st == 0) ? dt : d2;  // weight of Ybar in the next kbar
             __syncthreads();
 #pragma unroll
-            for (int q = 0; q < KPT; ++q) {
-                const int p = t + q * NT2;
-                if (p < R.np) X[p] = kb[q];
-            }
+            for (int q = 0; q < KPT; ++q)
+                if (R.row(q) < R.rows) R.put(X, q, kb[q]);
             __syncthreads();
 #pragma unroll
             for (int q = 0; q < KPT; ++q) {
-                const int p = t + q * NT2;
-                if (p >= R.np) continue;
-                const double yb = sten(X, R, p, A);
+                const int r = R.row(q);
+                if (r >= R.rows) continue;
+                const double yb = sten<NX>(X, R.idx(q), A);
                 Lm[q] += sv * kb[q];
                 if (st < 3) {
                     nl[q] += yb;
@@ -211,11 +233,9 @@ k_band2d_rev(const Band2D* __restrict__ tab, int count, int L) {
     }
 #pragma unroll
     for (int q = 0; q < KPT; ++q) {
-        const int p = t + q * NT2;
-        if (p >= R.np) continue;
-        const int r = R.row(p);
+        const int r = R.row(q);
         if (r >= H && r < H + BAND_ROWS) {
-            const int g = gidx(p);
+            const int g = grow(row0, r, ny) * nx + R.col;
             out[g] = lam[q];
             if (d.Lam) d.Lam[g] += Lm[q];
         }
@@ -235,31 +255,53 @@ __global__ void k_apply5(const double* __restrict__ x, double* __restrict__ out,
     out[i] = A.c * x[i] + A.w * xw + A.e * xe + A.s * xs + A.n * xn;
 }
 
-size_t band_lds(const Band2D* host_max_nx) {
-    (void)host_max_nx;
-    return (size_t)(BAND_ROWS + 8 * BAND_MAX_STEPS) * 256 * sizeof(double);
+size_t band_lds(int nx) {
+    return (size_t)(BAND_ROWS + 8 * BAND_MAX_STEPS + 2) * (nx + 2) * sizeof(double);
+}
+
+template <int NX>
+hipError_t band_fwd(const Band2D* tab, int count, int total_blocks, int serial, int L,
+                    hipStream_t s) {
+    const size_t lds = band_lds(NX);
+    (void)hipFuncSetAttribute((const void*)k_band2d_fwd<NX>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_band2d_fwd<NX><<<total_blocks, NT2, lds, s>>>(tab, count, serial, L);
+    return hipGetLastError();
+}
+
+template <int NX>
+hipError_t band_rev(const Band2D* tab, int count, int total_blocks, int L,
+                    hipStream_t s) {
+    const size_t lds = band_lds(NX);
+    (void)hipFuncSetAttribute((const void*)k_band2d_rev<NX>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_band2d_rev<NX><<<total_blocks, NT2, lds, s>>>(tab, count, L);
+    return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_band2d(const Band2D* tab, int count, int total_blocks, int serial,
-                         int L, hipStream_t s) {
+// Every entry of one launch has the same row length nx.
+hipError_t launch_band2d(const Band2D* tab, int count, int total_blocks, int nx,
+                         int serial, int L, hipStream_t s) {
     if (count <= 0 || total_blocks <= 0) return hipSuccess;
-    const size_t lds = band_lds(nullptr);
-    (void)hipFuncSetAttribute((const void*)k_band2d_fwd,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_band2d_fwd<<<total_blocks, NT2, lds, s>>>(tab, count, serial, L);
-    return hipGetLastError();
+    switch (nx) {
+        case 64: return band_fwd<64>(tab, count, total_blocks, serial, L, s);
+        case 128: return band_fwd<128>(tab, count, total_blocks, serial, L, s);
+        case 256: return band_fwd<256>(tab, count, total_blocks, serial, L, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
-hipError_t launch_band2d_rev(const Band2D* tab, int count, int total_blocks, int L,
-                             hipStream_t s) {
+hipError_t launch_band2d_rev(const Band2D* tab, int count, int total_blocks, int nx,
+                             int L, hipStream_t s) {
     if (count <= 0 || total_blocks <= 0) return hipSuccess;
-    const size_t lds = band_lds(nullptr);
-    (void)hipFuncSetAttribute((const void*)k_band2d_rev,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_band2d_rev<<<total_blocks, NT2, lds, s>>>(tab, count, L);
-    return hipGetLastError();
+    switch (nx) {
+        case 64: return band_rev<64>(tab, count, total_blocks, L, s);
+        case 128: return band_rev<128>(tab, count, total_blocks, L, s);
+        case 256: return band_rev<256>(tab, count, total_blocks, L, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_apply5(const double* x, double* out, int nx, int ny, Sten5 op,
