@@ -234,7 +234,7 @@ def main():
     else:
         args.no_cpu_baseline = True
 
-    roof = roofline(kern, insts, args, substeps, iters)
+    roof = roofline(kern, insts, args, substeps, iters, pxp.problems)
 
     gate = 1e-8 if args.prec == "fp64" else 1e-5
     ok = (err is not None and err["paraexp_grad"] <= gate and err["paraexp_qT"] <= gate
@@ -331,23 +331,27 @@ def time_graph(torch, r, steps):
     return (time.perf_counter() - t0) / steps
 
 
-def roofline(kern, insts, args, substeps, iters):
+def roofline(kern, insts, args, substeps, iters, problems):
     """Roofline object for the kernel class that takes the most time per step."""
     if not kern:
         return None
     top = max(kern, key=lambda k: kern[k]["per_step_ms"])
     inst = insts[0]
     n = inst["nx"] * inst.get("ny", 1)
-    P, m = inst["P"], inst["m"]
+    P, m = int(problems[0].P), int(problems[0].m)
     sec = kern[top]["avg_ms"] * 1e-3
-    if top == "krylov_direct" and args.sched == "classic" and len(insts) == 1:
-        byts = (P - 1) * krylov_space_bytes(n, m)
+    if top == "krylov_direct" and int(problems[0].sched) == 0 and len(insts) == 1:
+        # spaces may stop before dimension m: count the average dimension
+        # reached (Arnoldi iterations / spaces, all launches), rounded down
+        m_eff = min(m, int(iters / max(substeps, 1))) if substeps else m
+        byts = (P - 1) * krylov_space_bytes(n, m_eff)
         ach = byts / sec / 1e9
         return dict(kernel="k_krylov1d, direct pieces (classic, %d workgroups)" % (P - 1),
                     bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=ach / HBM_PEAK_GBS,
                     traffic=profiled_traffic("k_krylov1d_direct_classic"),
-                    algorithmic_bytes_per_launch=byts, avg_launch_ms=kern[top]["avg_ms"])
+                    algorithmic_bytes_per_launch=byts, krylov_dim=m_eff,
+                    avg_launch_ms=kern[top]["avg_ms"])
     if top == "slices" and len(insts) == 1:
         ach = rk4_slice_flops(n, inst["n_steps"]) / sec / 1e12
         return dict(kernel="k_rk4_lin1d (inhomogeneous slices)", bound="alu",
