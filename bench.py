@@ -40,12 +40,13 @@ def rk4_slice_flops(n, n_steps):
     return 64.0 * n * n_steps
 
 
-def krylov_space_bytes(n, m):
+def krylov_space_bytes(n, m, passes=2.0):
     """Algorithmic bytes of one Arnoldi space of dimension m on n points:
-    step j reads V_0..V_j four times (two Gram-Schmidt passes, each a dot
-    pass and an update pass) and writes V_{j+1}; the recombination reads m
-    vectors and writes one; the start vector is read and written once."""
-    vecs = sum(4 * (j + 1) + 1 for j in range(m)) + (m + 1) + 2
+    step j reads V_0..V_j twice per Gram-Schmidt pass (a dot pass and an
+    update pass; `passes` = average passes per step, 1 to 2) and writes
+    V_{j+1}; the recombination reads m vectors and writes one; the start
+    vector is read and written once."""
+    vecs = sum(2 * passes * (j + 1) + 1 for j in range(m)) + (m + 1) + 2
     return 8.0 * n * vecs
 
 
@@ -192,7 +193,7 @@ def main():
         ms, cnt = _lib.pxp_profile_read(k)
         if cnt:
             kern[k] = dict(avg_ms=ms / cnt, launches=cnt, per_step_ms=ms / args.steps)
-    substeps, iters = _lib.pxp_device_counters(pxp.ws)
+    substeps, iters, reorth = _lib.pxp_device_counters(pxp.ws)
     code, est = pxp.status()
     res_pxp = pxp.results()
     log("paraexp %.3f ms/step  kernels %s  status %d est %.1e"
@@ -234,7 +235,7 @@ def main():
     else:
         args.no_cpu_baseline = True
 
-    roof = roofline(kern, insts, args, substeps, iters, pxp.problems)
+    roof = roofline(kern, insts, args, substeps, iters, pxp.problems, reorth)
 
     gate = 1e-8 if args.prec == "fp64" else 1e-5
     ok = (err is not None and err["paraexp_grad"] <= gate and err["paraexp_qT"] <= gate
@@ -270,6 +271,7 @@ def main():
         "oracle_sample": sample,
         "krylov": {"spaces_per_step": substeps / max(1, args.steps),
                    "iters_per_step": iters / max(1, args.steps),
+                   "reorth_per_step": reorth / max(1, args.steps),
                    "max_est": est, "status": code},
         "kernels_ms": {k: v["avg_ms"] for k, v in kern.items()},
         "roofline": roof,
@@ -331,7 +333,7 @@ def time_graph(torch, r, steps):
     return (time.perf_counter() - t0) / steps
 
 
-def roofline(kern, insts, args, substeps, iters, problems):
+def roofline(kern, insts, args, substeps, iters, problems, reorth=0):
     """Roofline object for the kernel class that takes the most time per step."""
     if not kern:
         return None
@@ -344,13 +346,15 @@ def roofline(kern, insts, args, substeps, iters, problems):
         # spaces may stop before dimension m: count the average dimension
         # reached (Arnoldi iterations / spaces, all launches), rounded down
         m_eff = min(m, int(iters / max(substeps, 1))) if substeps else m
-        byts = (P - 1) * krylov_space_bytes(n, m_eff)
+        passes = 1.0 + reorth / iters if iters else 2.0
+        byts = (P - 1) * krylov_space_bytes(n, m_eff, passes)
         ach = byts / sec / 1e9
         return dict(kernel="k_krylov1d, direct pieces (classic, %d workgroups)" % (P - 1),
                     bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=ach / HBM_PEAK_GBS,
                     traffic=profiled_traffic("k_krylov1d_direct_classic"),
                     algorithmic_bytes_per_launch=byts, krylov_dim=m_eff,
+                    gram_schmidt_passes=passes,
                     avg_launch_ms=kern[top]["avg_ms"])
     if top == "slices" and len(insts) == 1:
         ach = rk4_slice_flops(n, inst["n_steps"]) / sec / 1e12
@@ -373,7 +377,8 @@ def roofline(kern, insts, args, substeps, iters, problems):
         it = iters / max(1, args.steps)
         mm = it / max(sp, 1.0)
         nbar = sum(x["nx"] * x.get("ny", 1) for x in insts) / len(insts)
-        byts = sp * krylov_space_bytes(nbar, max(1, int(round(mm))))
+        passes = 1.0 + reorth / iters if iters else 2.0
+        byts = sp * krylov_space_bytes(nbar, max(1, int(round(mm))), passes)
         launches = kern[top]["launches"] / args.steps
         ach = byts / launches / sec / 1e9
         return dict(kernel="k_krylov1d (%s)" % top, bound="hbm", achieved=ach,

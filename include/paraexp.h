@@ -190,10 +190,14 @@ pxp_status pxp_device_status(void* ws, size_t ws_bytes, void* stream,
                              double* max_est);
 
 /* Synchronises `stream` and reads the accumulated Krylov counters of the
- * workspace: accepted substeps and Arnoldi iterations over all pieces since
- * the last pxp_device_status call (host outputs, nullable). */
+ * workspace: accepted substeps, Arnoldi iterations, and Arnoldi iterations
+ * that took a second Gram-Schmidt pass (classical Gram-Schmidt reruns only
+ * when the first pass removed more than half of the vector's squared norm),
+ * over all pieces since the workspace was initialised (host outputs,
+ * nullable). */
 pxp_status pxp_device_counters(void* ws, size_t ws_bytes, void* stream,
-                               uint64_t* substeps, uint64_t* krylov_iters);
+                               uint64_t* substeps, uint64_t* krylov_iters,
+                               uint64_t* reorth_passes);
 
 /* Launch timing for benchmarks and profiling.  While enabled, every launch
  * of a kernel class is bracketed by two HIP events recorded on the launch

@@ -94,6 +94,7 @@ def load() -> ctypes.CDLL:
         "gradient": (st, [P, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "pxp_device_status": (st, [vp, sz, vp, ctypes.POINTER(ctypes.c_double)]),
         "pxp_device_counters": (st, [vp, sz, vp, ctypes.POINTER(ctypes.c_uint64),
+                                     ctypes.POINTER(ctypes.c_uint64),
                                      ctypes.POINTER(ctypes.c_uint64)]),
         "pxp_status_str": (ctypes.c_char_p, [st]),
         "pxp_assemble": (st, [P, i32, vp, vp, vp, vp, vp]),
@@ -193,11 +194,12 @@ def pxp_device_status(ws, stream=None):
 
 
 def pxp_device_counters(ws, stream=None):
-    a, b = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    """(substeps, Arnoldi iterations, second Gram-Schmidt passes)"""
+    a, b, c = ctypes.c_uint64(0), ctypes.c_uint64(0), ctypes.c_uint64(0)
     _check(load().pxp_device_counters(_ptr(ws), ws.numel(), _stream(stream),
-                                      ctypes.byref(a), ctypes.byref(b)),
+                                      ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
            "pxp_device_counters")
-    return a.value, b.value
+    return a.value, b.value, c.value
 
 
 def pxp_profile_enable(on: bool):

@@ -1274,7 +1274,8 @@ pxp_status pxp_device_status(void* ws, size_t ws_bytes, void* stream,
 }
 
 pxp_status pxp_device_counters(void* ws, size_t ws_bytes, void* stream,
-                               uint64_t* substeps, uint64_t* krylov_iters) {
+                               uint64_t* substeps, uint64_t* krylov_iters,
+                               uint64_t* reorth_passes) {
     if (!ws || ws_bytes < sizeof(DevStatus)) return PXP_EWORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (hipStreamSynchronize(s) != hipSuccess) return PXP_EHIP;
@@ -1283,6 +1284,7 @@ pxp_status pxp_device_counters(void* ws, size_t ws_bytes, void* stream,
         return PXP_EHIP;
     if (substeps) *substeps = h.substeps;
     if (krylov_iters) *krylov_iters = h.krylov_iters;
+    if (reorth_passes) *reorth_passes = h.reorth;
     return PXP_OK;
 }
 

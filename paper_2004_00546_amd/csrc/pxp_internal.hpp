@@ -26,6 +26,8 @@ struct DevStatus {
     unsigned long long max_est;  // bit pattern of the largest relative est.
     unsigned long long substeps; // accepted Krylov substeps (all pieces)
     unsigned long long krylov_iters;
+    unsigned long long reorth;   // Arnoldi steps that took a second
+                                 // Gram-Schmidt pass
 };
 constexpr unsigned int ST_NOCONV = 1u;
 constexpr unsigned int ST_NONFINITE = 2u;

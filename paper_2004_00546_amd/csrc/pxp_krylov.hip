@@ -81,6 +81,7 @@ struct Core {
     const KrylovArgs a;
     Smem S;
     int n, m, B, t, ldr;
+    unsigned nre = 0;  // second Gram-Schmidt passes since the last report
 
     __device__ Core(const KrylovArgs& a_, double* lds)
         : a(a_), n(a_.n), m(a_.m), B(blockDim.x), t(threadIdx.x) {
@@ -183,7 +184,9 @@ struct Core {
                 atomicMax(&a.status->max_est, (unsigned long long)__double_as_longlong(e));
             atomicAdd(&a.status->substeps, (unsigned long long)substeps);
             atomicAdd(&a.status->krylov_iters, (unsigned long long)iters);
+            atomicAdd(&a.status->reorth, (unsigned long long)nre);
         }
+        nre = 0;
     }
 
     // V_0 <- exp(tau Op) V_0; if iout, iout += int_0^tau sin(ia + ib s)
@@ -283,6 +286,7 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
     using Base::B;
     using Base::t;
     using Base::small_exp;
+    using Base::nre;
     // Points owned by thread t: R groups of VW consecutive points, group r
     // at (t + r*B)*VW, so every basis read is a coalesced 16-byte load.
     static constexpr int VW = (PT >= 2) ? 2 : 1;
@@ -696,16 +700,23 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
         int me = m;
         for (int j = 0; j < m; ++j) {
             apply(z, gamma);
-            // classical Gram-Schmidt, two passes
+            // classical Gram-Schmidt; the second pass runs only when the
+            // first removed more than half of |Op v_j|^2 (the DGKS
+            // criterion, eta = 1/sqrt(2))
+            double nrm2 = 0.0, col = 0.0;
             for (int pass = 0; pass < 2; ++pass) {
                 dots(z, j);
                 if (t <= j) S.H[t * m + j] += S.hcol[t];
                 subtract(z, j);
+                nrm2 = block_sum(sumsq(z), S.red);
+                double hh = 0.0;
+                for (int k = 0; k <= j; ++k) hh += S.H[k * m + j] * S.H[k * m + j];
+                // |Op v_j|^2 = sum_k h_kj^2 + nrm^2 (the Gram-Schmidt column)
+                col = hh + nrm2;
+                if (pass == 0 && !(nrm2 < hh)) break;
+                if (pass == 0) ++nre;
             }
-            const double nrm = sqrt(block_sum(sumsq(z), S.red));
-            // |Op v_j|^2 = sum_k h_kj^2 + nrm^2 (the Gram-Schmidt column)
-            double col = nrm * nrm;
-            for (int k = 0; k <= j; ++k) col += S.H[k * m + j] * S.H[k * m + j];
+            const double nrm = sqrt(nrm2);
             __syncthreads();
             if (t == 0) S.H[(j + 1) * m + j] = nrm;
             if (!(nrm > 1e-12 * sqrt(col))) {
@@ -901,6 +912,7 @@ struct Ctx2 : Core<Ctx2, false> {
     using Base::B;
     using Base::t;
     using Base::small_exp;
+    using Base::nre;
     double* V;
     int G, nx, ny;
 
@@ -1034,15 +1046,19 @@ struct Ctx2 : Core<Ctx2, false> {
             double* w = V + (size_t)(j + 1) * n;
             __syncthreads();  // V_j complete: the stencil reads neighbours
             apply(V + (size_t)j * n, w);
-            double ss = 0.0;
+            // classical Gram-Schmidt, second pass by the DGKS criterion
+            double nrm2 = 0.0, col = 0.0;
             for (int pass = 0; pass < 2; ++pass) {
                 dots(w, j);
                 if (t <= j) S.H[t * m + j] += S.hcol[t];
-                ss = subtract(w, j);
+                nrm2 = block_sum(subtract(w, j), S.red);
+                double hh = 0.0;
+                for (int k = 0; k <= j; ++k) hh += S.H[k * m + j] * S.H[k * m + j];
+                col = hh + nrm2;
+                if (pass == 0 && !(nrm2 < hh)) break;
+                if (pass == 0) ++nre;
             }
-            const double nrm = sqrt(block_sum(ss, S.red));
-            double col = nrm * nrm;
-            for (int k = 0; k <= j; ++k) col += S.H[k * m + j] * S.H[k * m + j];
+            const double nrm = sqrt(nrm2);
             __syncthreads();
             if (t == 0) S.H[(j + 1) * m + j] = nrm;
             if (!(nrm > 1e-12 * sqrt(col))) {
