@@ -101,6 +101,9 @@ def main():
                     help="threads per workgroup of the Krylov kernels (0 = default)")
     ap.add_argument("--graph", action="store_true",
                     help="also time replays of the gradient captured in a hipGraph")
+    ap.add_argument("--absorbed", action="store_true",
+                    help="adjoint in the absorbed form (batch of adjoint slices "
+                         "plus classic pieces; 1D linear problems)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick P, Krylov flavour, schedule and workgroup size with the "
                          "library's autotuner before timing")
@@ -151,13 +154,14 @@ def main():
 
     tol = args.tol if args.tol is not None else (1e-10 if args.prec == "fp64" else 1e-6)
     kw = dict(prec=args.prec, block=args.block, kblock=args.kblock)
+    pkw = dict(kw, absorbed=args.absorbed)
     tuned = None
     if args.autotune:
         lo, hi = (int(v) for v in args.p_range.split(","))
         t0 = time.perf_counter()
         probs, rep = api.autotune(insts, p_min=lo, p_max=hi,
                                   rtol=1e-9 if args.prec == "fp64" else 2e-6,
-                                  krylov=args.krylov, sched=args.sched, tol=tol, **kw)
+                                  krylov=args.krylov, sched=args.sched, tol=tol, **pkw)
         names = {v: k for k, v in _lib.KRYLOV.items()}
         tuned = {"seconds": time.perf_counter() - t0,
                  "P": sorted({int(p.P) for p in probs}),
@@ -169,7 +173,7 @@ def main():
         pxp = api.GradientRunner(insts, method="paraexp", problems=probs)
     else:
         pxp = api.GradientRunner(insts, method="paraexp", krylov=args.krylov,
-                                 sched=args.sched, tol=tol, **kw)
+                                 sched=args.sched, tol=tol, **pkw)
     ser = api.GradientRunner(insts, method="serial", krylov="auto", **kw)
 
     # timed Paraexp region, with per-kernel events on the library's stream
@@ -244,7 +248,8 @@ def main():
            "n_steps": n_steps, "slices": P, "krylov_m": m, "krylov": args.krylov,
            "schedule": args.sched, "precision": args.prec, "gate": gate,
            "controls": int(np.asarray(inst["basis"]).shape[0]),
-           "block": args.block, "kblock": args.kblock}
+           "block": args.block, "kblock": args.kblock,
+           "adjoint_form": "absorbed" if args.absorbed else "unabsorbed"}
     if B > 1:
         cfg.update(N=sorted({int(x["nx"]) * int(x.get("ny", 1)) for x in insts}),
                    n_steps=[min(int(x["n_steps"]) for x in insts),

@@ -83,6 +83,14 @@ enum { PXP_KRYLOV_POLY = 0, PXP_KRYLOV_SHIFT_INVERT = 1, PXP_KRYLOV_AUTO = 2 };
  * pieces exp((T - T_{p+1}) A) v_p (eq. hom); CHAIN = nested sum
  * w <- exp(dT A) w + v_p, one piece after the other. */
 enum { PXP_SCHED_CLASSIC = 0, PXP_SCHED_CHAIN = 1 };
+/* Problem flags.  ABSORBED_ADJOINT (1D linear problems): the Paraexp
+ * adjoint runs in the absorbed form of section 3.3 (eq. hybadjinhom with the
+ * final condition absorbed): lambda = lambda_T + q~, q~(T) = 0, with the P
+ * inhomogeneous adjoint slices q~' = A^T q~ + A^T lambda_T from zero (in
+ * reversed time) as one batch and the P-1 homogeneous pieces of their end
+ * states by Krylov, each with its share of Lambda.  Default (0): the
+ * unabsorbed form, one homogeneous piece from lambda_T (eq. adjhomfinal). */
+enum { PXP_FLAG_ABSORBED_ADJOINT = 1 };
 /* Method: PARAEXP = the time-parallel path; SERIAL = plain RK4 stepping of
  * the direct equation and its exact discrete adjoint (the comparison). */
 enum { PXP_METHOD_PARAEXP = 0, PXP_METHOD_SERIAL = 1 };
@@ -94,9 +102,9 @@ typedef struct {
                                         checkpoint interval (steps), threads
                                         per workgroup for the 1D marches
                                         (0 = library default)                 */
-    int32_t kblock, reserved;        /* threads per workgroup of the Krylov
+    int32_t kblock, flags;           /* threads per workgroup of the Krylov
                                         kernels (multiple of 64, <= 512;
-                                        0 = library default); reserved = 0    */
+                                        0 = library default); PXP_FLAG_*      */
     int64_t n_steps;                 /* RK4 steps; n_steps % P == 0            */
     double L, vx, vy, nu;            /* box [0,L)^d, velocity, viscosity       */
     double T, omega, beta;           /* horizon, s(t) = sin(omega t), weight   */

@@ -20,6 +20,7 @@ OP = {"advdiff1d": 0, "advdiff2d_upwind": 1, "burgers1d": 2}
 PREC = {"fp64": 0, "fp32_bulk": 1}
 CTRL = {"forcing": 0, "ic": 1}
 KRYLOV = {"poly": 0, "shift_invert": 1, "auto": 2}
+FLAG_ABSORBED_ADJOINT = 1
 SCHED = {"classic": 0, "chain": 1}
 METHOD = {"paraexp": 0, "serial": 1}
 
@@ -45,7 +46,7 @@ class pxp_problem(ctypes.Structure):
                 ("ny", ctypes.c_int32), ("P", ctypes.c_int32),
                 ("m", ctypes.c_int32), ("K", ctypes.c_int32),
                 ("ckpt_every", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("kblock", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("kblock", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("n_steps", ctypes.c_int64),
                 ("L", ctypes.c_double), ("vx", ctypes.c_double),
                 ("vy", ctypes.c_double), ("nu", ctypes.c_double),

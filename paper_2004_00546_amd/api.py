@@ -10,7 +10,7 @@ from . import _lib
 
 def make_problem(inst: dict, krylov: str = "shift_invert", sched: str = "classic",
                  tol: float = 1e-10, block: int = 0, kblock: int = 0,
-                 si_gamma: float = 0.2,
+                 si_gamma: float = 0.2, absorbed: bool = False,
                  P: int | None = None, m: int | None = None,
                  prec: str = "fp64") -> _lib.pxp_problem:
     p = _lib.pxp_problem()
@@ -27,6 +27,7 @@ def make_problem(inst: dict, krylov: str = "shift_invert", sched: str = "classic
     p.ckpt_every = int(inst.get("ckpt_every", 64))
     p.block = int(block)
     p.kblock = int(kblock)
+    p.flags = _lib.FLAG_ABSORBED_ADJOINT if absorbed else 0
     p.n_steps = int(inst["n_steps"])
     p.L = float(inst["L"])
     p.vx = float(inst.get("vx", 0.0))

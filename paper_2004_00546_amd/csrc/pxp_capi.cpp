@@ -31,7 +31,7 @@ struct Layout {
 // Per-instance buffers (offsets relative to the instance region).
 struct Inst {
     size_t F, g0, q0eff, slices, pieces, basis, qT, lamT, lam0, Lam, chain,
-        ckpt, seg, nodes, sbuf0, sbuf1, J, size;
+        ckpt, seg, nodes, sbuf0, sbuf1, aint, J, size;
 };
 
 int64_t grid_n(const pxp_problem& p) { return (int64_t)p.nx * (int64_t)p.ny; }
@@ -155,7 +155,8 @@ pxp_status validate(const pxp_problem& p) {
         return PXP_EINVAL;
     if (p.sched != PXP_SCHED_CLASSIC && p.sched != PXP_SCHED_CHAIN) return PXP_EINVAL;
     if (p.prec != PXP_FP64 && p.prec != PXP_FP32_BULK) return PXP_EINVAL;
-    if (p.reserved != 0 || p.kblock < 0 || p.block < 0) return PXP_EINVAL;
+    if ((p.flags & ~PXP_FLAG_ABSORBED_ADJOINT) || p.kblock < 0 || p.block < 0) return PXP_EINVAL;
+    if ((p.flags & PXP_FLAG_ABSORBED_ADJOINT) && p.op != PXP_OP_ADVDIFF1D) return PXP_EUNSUPPORTED;
     if (p.op == PXP_OP_ADVDIFF1D) {
         if (p.ny != 1) return PXP_EINVAL;
         if (p.m < 1 || p.m > M_MAX_1D) return PXP_EUNSUPPORTED;
@@ -221,10 +222,13 @@ Inst inst_layout(const pxp_problem& p) {
     L.chain = take(n * d);
     L.J = take(d);
     if (p.op == PXP_OP_ADVDIFF1D) {
+        const bool absorbed = (p.flags & PXP_FLAG_ABSORBED_ADJOINT) != 0;
         L.slices = take(P * n * d);
         L.pieces = take((P > 1 ? P - 1 : 1) * n * d);
-        const size_t npar = (p.sched == PXP_SCHED_CLASSIC && P > 1) ? P - 1 : 1;
+        const size_t npar = ((p.sched == PXP_SCHED_CLASSIC || absorbed) && P > 1) ? P - 1 : 1;
         L.basis = take(npar * (m + 1) * n * d);
+        // absorbed adjoint: the slices' and the pieces' integrals
+        if (absorbed) L.aint = take((2 * P - 1) * n * d);
     }
     if (p.op == PXP_OP_ADVDIFF2D_UPWIND) {
         L.slices = take(P * n * d);
@@ -418,6 +422,58 @@ pxp_status direct_lin1d(const Ctx& c, const double* q0, const double* F,
     return PXP_OK;
 }
 
+// Absorbed form of the adjoint (section 3.3, eq. hybadjinhom with the final
+// condition absorbed): lam = lamT + q~ with q~(T) = 0.  In tau = T - t,
+//   q~' = A^T q~ + A^T lamT,
+// cut into P slices marched from zero as one batch (slice p covers
+// tau in [p dT, (p+1) dT]); the end state w_p of slice p propagates
+// homogeneously over the remaining (P-1-p) dT (classic pieces).  Then
+//   lam(0) = lamT + w_{P-1} + sum_p exp((P-1-p) dT A^T) w_p,
+//   Lambda = (1 - cos omega T)/omega lamT + sum_p (slice integrals)
+//            + sum_p (piece integrals),
+// every integral of sin(omega (T - tau)) against its part of q~.
+pxp_status adjoint_lin1d_absorbed(const Ctx& c, const double* lamT, double* lam0,
+                                  double* Lam) {
+    const int n = c.n(), P = c.p.P;
+    const int64_t n_s = c.p.n_steps / P;
+    const Tri AT = transpose(advdiff_tri(c.p));
+    const double w = c.p.omega, T = c.p.T;
+    double* g = c.at(c.L.g0);
+    double* sl = c.at(c.L.slices);
+    double* aint = c.at(c.L.aint);
+    HIPCHK(launch_apply_tri(lamT, g, n, AT, c.s));
+    {
+        // (1) the P adjoint slices, one batch; their integrals, with the
+        // lamT term added to slice 0's
+        SliceIntegral si{Lam ? aint : nullptr, w * T, -w,
+                         (w != 0.0) ? (1.0 - std::cos(w * T)) / w : 0.0, lamT};
+        ProfScope ps(PXP_K_SLICES, c.s);
+        HIPCHK(launch_rk4_lin1d(nullptr, g, nullptr, sl, n, P, n_s, c.dt(), 0.0, AT,
+                                c.p.block, c.fp32(), c.s, si));
+    }
+    {
+        // (2) P-1 homogeneous pieces exp((P-1-p) dT A^T) w_p with integrals
+        KrylovArgs a = kargs(c, AT);
+        a.mode = KM_CLASSIC;
+        a.npieces = P - 1;
+        a.vin = sl;
+        a.yout = c.at(c.L.pieces);
+        a.iout = Lam ? aint + (size_t)P * n : nullptr;
+        a.tau = T / P;
+        a.ia = w;  // piece p: phase omega * tau_p
+        a.ib = -w;
+        ProfScope ps(PXP_K_KRYLOV_ADJOINT, c.s);
+        HIPCHK(launch_krylov1d(a, c.p.kblock, c.s));
+    }
+    // (3) superposition
+    if (lam0)
+        HIPCHK(launch_recombine(lamT, sl + (size_t)(P - 1) * n, c.at(c.L.pieces), P - 1, n,
+                                lam0, c.st, c.s));
+    if (Lam)
+        HIPCHK(launch_recombine(nullptr, nullptr, aint, 2 * P - 1, n, Lam, c.st, c.s));
+    return PXP_OK;
+}
+
 // Adjoint of one linear 1D instance from lamT: lam0 and/or Lambda.
 pxp_status adjoint_lin1d(const Ctx& c, const double* lamT, double* lam0,
                          double* Lam, int method) {
@@ -429,6 +485,8 @@ pxp_status adjoint_lin1d(const Ctx& c, const double* lamT, double* lam0,
                                     c.p.omega, AT, c.p.block, c.fp32(), c.s));
         return PXP_OK;
     }
+    if ((c.p.flags & PXP_FLAG_ABSORBED_ADJOINT) && c.p.P > 1)
+        return adjoint_lin1d_absorbed(c, lamT, lam0, Lam);
     // The terminal-cost adjoint is one homogeneous piece from q^dagger(T)
     // over [T, 0] (eq. adjhomfinal); in tau = T - t it reads
     // d lam / d tau = A^T lam, and Lambda = int_0^T sin(omega (T - tau))

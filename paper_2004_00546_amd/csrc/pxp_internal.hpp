@@ -36,12 +36,21 @@ constexpr unsigned int ST_NONFINITE = 2u;
 // fp32 != 0: stencil and RK arithmetic in FP32 with compensated (Kahan)
 // accumulation of the state and adjoint sums; inputs, outputs and
 // checkpoints stay FP64 (an FP32 compensated pair is exact in FP64).
+// Optional time integral of each slice's march: iout[p] = int over the
+// slice of sin(ia + ib t) y(t) dt (RK4 stages of the extra equation), plus
+// c0 * v0 for slice 0 when v0 is given.  iout null: none.
+struct SliceIntegral {
+    double* iout;
+    double ia, ib, c0;
+    const double* v0;
+};
 // Slices p = 0..P-1 of a linear 1D problem, each from zero (or from y0 when
 // given, P must then be 1) over n_s steps starting at global step p*n_s:
 //   y' = A y + sin(omega t) F + g0.
 hipError_t launch_rk4_lin1d(const double* F, const double* g0, const double* y0,
                             double* out, int n, int P, int64_t n_s, double dt,
-                            double omega, Tri A, int block, int fp32, hipStream_t s);
+                            double omega, Tri A, int block, int fp32, hipStream_t s,
+                            SliceIntegral si = SliceIntegral{nullptr, 0.0, 0.0, 0.0, nullptr});
 
 // Reverse sweep of the exact discrete adjoint of the linear RK4 march:
 // from lamT to lam0 and Lambda = sum s(t_stage) kbar_stage.
@@ -107,9 +116,11 @@ struct KrylovArgs {
     int npieces;         // classic: P-1 pieces; chain: P slices; single: 1
     const double* vin;   // classic/chain: slice end states [P][n]; single: [n]
     double* yout;        // classic: [P-1][n]; chain/single: [n]
-    double* iout;        // single: integral output [n] (nullable)
+    double* iout;        // single: integral output [n]; classic (1D):
+                         // [npieces][n], piece p integrating over its own
+                         // [0, tau_p] with phase ia * tau_p (nullable)
     double tau;          // single: time; chain: slice length; classic: slice
-                         // length dT (piece p uses (npieces - p) * dT)
+                         // length dT (piece p uses tau_p = (npieces - p) * dT)
     double ia, ib;       // integral weight sin(ia + ib * sigma)
     double tol;          // relative tolerance
     double gamma_frac;   // shift-and-invert shift = gamma_frac * time

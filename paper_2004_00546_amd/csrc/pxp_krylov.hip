@@ -807,14 +807,18 @@ __device__ __forceinline__ void dev_krylov1d(const KrylovArgs& a, int piece, dou
     // The current vector of the piece lives in V_0 (global memory); every
     // thread only reads and writes its own points of it.
     const double* vin = (a.mode == KM_CLASSIC) ? a.vin + (size_t)piece * n : a.vin;
+    // time integral: the single piece, or each classic piece into its own
+    // vector (phase a.ia per unit of the piece's time, see KrylovArgs)
+    double* iout = (a.mode == KM_SINGLE) ? a.iout
+                 : (a.mode == KM_CLASSIC && a.iout) ? a.iout + (size_t)piece * n : nullptr;
     {
         double x[PT];
         c.gload(vin, x);
         c.gstore(V, x);
-        if (a.mode == KM_SINGLE && a.iout) {
+        if (iout) {
 #pragma unroll
             for (int u = 0; u < PT; ++u) x[u] = 0.0;
-            c.gstore(a.iout, x);
+            c.gstore(iout, x);
         }
     }
     // classic: one exponential of (npieces - piece) slice lengths;
@@ -824,11 +828,11 @@ __device__ __forceinline__ void dev_krylov1d(const KrylovArgs& a, int piece, dou
     const int nexp = (a.mode == KM_CHAIN) ? a.npieces - 1
                    : (a.mode == KM_LTV) ? 2 * a.npieces : 1;
     const double tau = (a.mode == KM_CLASSIC) ? (double)(a.npieces - piece) * a.tau : a.tau;
-    double* iout = (a.mode == KM_SINGLE) ? a.iout : nullptr;
+    const double ia = (a.mode == KM_CLASSIC) ? a.ia * tau : a.ia;
     if (VAR && SI) c.aux = V + (size_t)(a.m + 1) * n;
     for (int q = 0; q < nexp; ++q) {
         if (VAR) c.Wcur = a.wop + (size_t)q * n;
-        c.expv(tau, a.ia, a.ib, iout);
+        c.expv(tau, ia, a.ib, iout);
         if (a.mode == KM_CHAIN) {
             double x[PT], w[PT];
             c.gload(a.vin + (size_t)(q + 1) * n, x);

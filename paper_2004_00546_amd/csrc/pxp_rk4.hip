@@ -106,7 +106,7 @@ template <int PT, typename R>
 __global__ void __launch_bounds__(max_block<PT>())
 k_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
             const double* __restrict__ y0, double* __restrict__ out, int n,
-            int64_t n_s, double dt, double omega, TriSplit A) {
+            int64_t n_s, double dt, double omega, TriSplit A, SliceIntegral si) {
     extern __shared__ double lds_d[];
     R* lds = reinterpret_cast<R*>(lds_d);
     const int t = threadIdx.x;
@@ -123,11 +123,25 @@ k_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
     int buf = 0;
     const int64_t step0 = (int64_t)p * n_s;
     const R h2 = (R)(0.5 * dt), h6 = (R)(dt / 6.0), h1 = (R)dt;
+    // optional time integral I = int sin(ia + ib t) y(t) dt over the slice,
+    // integrated as the extra equation I' = sin(ia + ib t) y with the same
+    // RK4 stages (fourth order)
+    double I[PT];
+#pragma unroll
+    for (int q = 0; q < PT; ++q) I[q] = 0.0;
     for (int64_t s = 0; s < n_s; ++s) {
         const double tn = (double)(step0 + s) * dt;
         const R s1 = (R)sin(omega * tn);
         const R s2 = (R)sin(omega * (tn + 0.5 * dt));
         const R s4 = (R)sin(omega * (tn + dt));
+        double w1 = 0.0, w2 = 0.0, w4 = 0.0;
+        if (si.iout) {
+            w1 = dt / 6.0 * sin(si.ia + si.ib * tn);
+            w2 = dt / 3.0 * sin(si.ia + si.ib * (tn + 0.5 * dt));
+            w4 = dt / 6.0 * sin(si.ia + si.ib * (tn + dt));
+#pragma unroll
+            for (int q = 0; q < PT; ++q) I[q] += w1 * hilo<R>(y[q], yc[q]);
+        }
         R l[1], r[1];
         {
             const R* arr[1] = {y};
@@ -140,6 +154,10 @@ k_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
             acc[q] = k[q];
             Y[q] = y[q] + h2 * k[q];
         }
+        if (si.iout) {
+#pragma unroll
+            for (int q = 0; q < PT; ++q) I[q] += w2 * ((double)y[q] - (double)yc[q] + (double)(h2 * k[q]));
+        }
         {
             const R* arr[1] = {Y};
             exch<PT, 1>(arr, lds, buf, l, r);
@@ -151,6 +169,10 @@ k_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
             acc[q] += (R)2 * k[q];
             Y[q] = y[q] + h2 * k[q];
         }
+        if (si.iout) {
+#pragma unroll
+            for (int q = 0; q < PT; ++q) I[q] += w2 * ((double)y[q] - (double)yc[q] + (double)(h2 * k[q]));
+        }
         {
             const R* arr[1] = {Y};
             exch<PT, 1>(arr, lds, buf, l, r);
@@ -161,6 +183,10 @@ k_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
             k[q] += s2 * f[q] + g[q];
             acc[q] += (R)2 * k[q];
             Y[q] = y[q] + h1 * k[q];
+        }
+        if (si.iout) {
+#pragma unroll
+            for (int q = 0; q < PT; ++q) I[q] += w4 * ((double)y[q] - (double)yc[q] + (double)(h1 * k[q]));
         }
         {
             const R* arr[1] = {Y};
@@ -176,6 +202,12 @@ k_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
     double* o = out + (size_t)p * n;
 #pragma unroll
     for (int q = 0; q < PT; ++q) o[base + q] = hilo<R>(y[q], yc[q]);
+    if (si.iout) {
+        double* io = si.iout + (size_t)p * n;
+#pragma unroll
+        for (int q = 0; q < PT; ++q)
+            io[base + q] = I[q] + ((p == 0 && si.v0) ? si.c0 * si.v0[base + q] : 0.0);
+    }
 }
 
 // Reverse sweep: y_{s+1} = y_s + dt sum_i b_i k_i with k_i = A Y_i + ...
@@ -700,13 +732,13 @@ bool march_shape(int n, int block_hint, int* block, int* pt) {
 hipError_t launch_rk4_lin1d(const double* F, const double* g0, const double* y0,
                             double* out, int n, int P, int64_t n_s, double dt,
                             double omega, Tri A, int block_hint, int fp32,
-                            hipStream_t s) {
+                            hipStream_t s, SliceIntegral si) {
     int block, pt;
     if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
     const size_t lds = sizeof(double) * 4 * block;
     const TriSplit sp = split(A);
     PXP_DISPATCH(fp32, pt, k_rk4_lin1d,
-                 <<<P, block, lds, s>>>(F, g0, y0, out, n, n_s, dt, omega, sp))
+                 <<<P, block, lds, s>>>(F, g0, y0, out, n, n_s, dt, omega, sp, si))
     return hipGetLastError();
 }
 

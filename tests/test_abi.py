@@ -165,3 +165,21 @@ def test_tune_workspace_covers_every_candidate():
     assert tuned >= plain
     # a larger slice range needs at least as much
     assert _lib.pxp_tune_workspace_size([p], 4, 500) >= tuned
+
+
+def test_problem_flags():
+    """Unknown flag bits are refused; the absorbed adjoint is for the 1D
+    linear problems and sizes extra workspace for its integrals."""
+    inst = workloads.make("advdiff1d_n128")[0]
+    plain = api.make_problem(inst, krylov="poly")
+    absorbed = api.make_problem(inst, krylov="poly", absorbed=True)
+    assert _lib.pxp_workspace_size([absorbed]) > _lib.pxp_workspace_size([plain])
+    bad = api.make_problem(inst, krylov="poly")
+    bad.flags = 2
+    with pytest.raises(_lib.PxpError) as e:
+        _lib.pxp_workspace_size([bad])
+    assert e.value.code == _lib.PXP_EINVAL
+    burg = api.make_problem(workloads.make("burgers1d_n2048")[0], krylov="poly", absorbed=True)
+    with pytest.raises(_lib.PxpError) as e:
+        _lib.pxp_workspace_size([burg])
+    assert e.value.code == _lib.PXP_EUNSUPPORTED

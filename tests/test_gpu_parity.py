@@ -433,3 +433,37 @@ def test_auto_flavour_ragged_equals_explicit_choice(torch):
         si = 0.5 * inst["T"] / inst["P"] * 4 * inst["nu"] / h**2 > 64
         one = run(inst, "paraexp", krylov="shift_invert" if si else "poly")
         assert np.array_equal(one["grad"], b["grad"]), (inst["nx"], si)
+
+
+# ---- absorbed adjoint: the batch of adjoint inhomogeneous slices ----------
+
+@pytest.mark.parametrize("wl,krylov,sched", [("advdiff1d_n128", "poly", "classic"),
+                                             ("advdiff1d_n128", "poly", "chain"),
+                                             ("advdiff1d_n4096", "shift_invert", "classic")])
+def test_absorbed_adjoint_matches_oracle(torch, orc, wl, krylov, sched):
+    """The absorbed form (adjoint slices from zero with source A^T lamT as one
+    batch, their end states propagated by classic pieces) against the oracle
+    and against the unabsorbed form (one homogeneous piece from lamT)."""
+    inst = workloads.make(wl)[0]
+    tol = 1e-9 if krylov == "shift_invert" else 1e-10
+    a = run(inst, "paraexp", krylov=krylov, sched=sched, tol=tol, absorbed=True)
+    b = run(inst, "paraexp", krylov=krylov, sched=sched, tol=tol)
+    want = orc.gradient(inst)
+    ea = rel(a["grad"], want["grad"])
+    say("absorbed %s %s %s: grad %.2e (unabsorbed %.2e), Lambda %.2e vs unabsorbed %.2e, status %d"
+        % (wl, krylov, sched, ea, rel(b["grad"], want["grad"]),
+           rel(a["lam"], want["Lambda"]), rel(a["lam"], b["lam"]), a["status"]))
+    assert a["status"] == 0
+    assert ea < FP64_GATE
+    assert rel(a["lam"], b["lam"]) < 1e-8
+
+
+def test_absorbed_adjoint_ic_control(torch, orc):
+    inst = small_advdiff(n=64, T=0.5, nt=500, P=5)
+    inst = dict(inst, control="ic")
+    a = run(inst, "paraexp", krylov="poly", absorbed=True)
+    want = orc.gradient(inst)
+    say("absorbed IC: lam0 %.2e grad %.2e" % (rel(a["lam"], want["lam0"]),
+                                              rel(a["grad"], want["grad"])))
+    assert rel(a["grad"], want["grad"]) < FP64_GATE
+    assert rel(a["lam"], want["lam0"]) < FP64_GATE
