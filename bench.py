@@ -90,7 +90,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="advdiff1d_n4096")
-    ap.add_argument("--krylov", default="auto", choices=["poly", "shift_invert", "auto"])
+    ap.add_argument("--krylov", default="auto", choices=["poly", "shift_invert", "auto", "taylor"])
     ap.add_argument("--sched", default="classic", choices=["classic", "chain"])
     ap.add_argument("--serial-steps", type=int, default=5)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32_bulk"])

@@ -77,8 +77,14 @@ enum { PXP_CTRL_FORCING = 0, PXP_CTRL_IC = 1 };
 /* Krylov flavour for the homogeneous exponentials. */
 /* AUTO: shift-and-invert when tau * rho > 64 (rho = 4 nu/h^2 + |vx|/h, tau
  * the horizon for the linear pieces or half a slice for the Burgers Magnus
- * factors) and the grid has the cyclic-reduction shape, else polynomial. */
-enum { PXP_KRYLOV_POLY = 0, PXP_KRYLOV_SHIFT_INVERT = 1, PXP_KRYLOV_AUTO = 2 };
+ * factors) and the grid has the cyclic-reduction shape, else TAYLOR. */
+/* TAYLOR: no Arnoldi process; exp(tau Op) v by the truncated Taylor series
+ * in substeps of at most theta/|Op| (theta from the remainder bound for 40
+ * terms at krylov_tol), terms added until two consecutive term norms fall
+ * below krylov_tol |v|; the time integral is accumulated term by term.  Its
+ * traffic is a few vectors per term and it needs no inner products. */
+enum { PXP_KRYLOV_POLY = 0, PXP_KRYLOV_SHIFT_INVERT = 1, PXP_KRYLOV_AUTO = 2,
+       PXP_KRYLOV_TAYLOR = 3 };
 /* Schedule of the direct homogeneous pieces: CLASSIC = P-1 independent
  * pieces exp((T - T_{p+1}) A) v_p (eq. hom); CHAIN = nested sum
  * w <- exp(dT A) w + v_p, one piece after the other. */

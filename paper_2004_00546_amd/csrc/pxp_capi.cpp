@@ -65,6 +65,9 @@ Sten5 advdiff2d_sten(const pxp_problem& p) {
     A.c = -p.vx / hx - p.vy / hy - 2.0 * p.nu / (hx * hx) - 2.0 * p.nu / (hy * hy);
     return A;
 }
+double sten_norm(const Sten5& A) {
+    return std::fabs(A.c) + std::fabs(A.w) + std::fabs(A.e) + std::fabs(A.s) + std::fabs(A.n);
+}
 Sten5 transpose5(Sten5 A) {
     Sten5 B = A;
     B.w = A.e;
@@ -112,12 +115,13 @@ bool rk4_stable_advdiff1d(const pxp_problem& p) {
     return true;
 }
 
-// Krylov flavour of a problem.  AUTO takes shift-and-invert where the
-// polynomial space would need many dimensions or substeps: when tau * rho,
+// Krylov flavour of a problem.  AUTO takes shift-and-invert where a
+// polynomial method would need many terms or substeps: when tau * rho,
 // rho = 4 nu / h^2 + |c| / h the spectral radius bound of the diffusion and
 // advection stencil and tau the longest exponential the call takes (the
 // horizon for the linear pieces, half a slice for the Magnus factors),
-// exceeds 64, and the grid allows the cyclic-reduction shape.
+// exceeds 64, and the grid allows the cyclic-reduction shape; otherwise the
+// Taylor flavour.
 bool use_si(const pxp_problem& p) {
     if (p.op == PXP_OP_ADVDIFF2D_UPWIND) return false;
     if (p.krylov == PXP_KRYLOV_SHIFT_INVERT) return true;
@@ -130,6 +134,12 @@ bool use_si(const pxp_problem& p) {
     if (!krylov_shape_pub(p.nx, p.kblock, &B, &pt)) return false;
     if (pt * B != p.nx || (B & (B - 1))) return false;
     return p.op == PXP_OP_BURGERS1D || (is_pow2(p.nx) && p.nx >= 64);
+}
+
+// Taylor flavour: named, or AUTO where shift-and-invert is not taken.
+bool use_taylor(const pxp_problem& p) {
+    if (p.krylov == PXP_KRYLOV_TAYLOR) return true;
+    return p.krylov == PXP_KRYLOV_AUTO && !use_si(p);
 }
 
 // The Krylov kernels' workgroup shape for this problem exists, fits in LDS,
@@ -151,7 +161,7 @@ pxp_status validate(const pxp_problem& p) {
     if (p.n_steps % p.P != 0) return PXP_EINVAL;
     if (p.ctrl != PXP_CTRL_FORCING && p.ctrl != PXP_CTRL_IC) return PXP_EINVAL;
     if (p.krylov != PXP_KRYLOV_POLY && p.krylov != PXP_KRYLOV_SHIFT_INVERT &&
-        p.krylov != PXP_KRYLOV_AUTO)
+        p.krylov != PXP_KRYLOV_AUTO && p.krylov != PXP_KRYLOV_TAYLOR)
         return PXP_EINVAL;
     if (p.sched != PXP_SCHED_CLASSIC && p.sched != PXP_SCHED_CHAIN) return PXP_EINVAL;
     if (p.prec != PXP_FP64 && p.prec != PXP_FP32_BULK) return PXP_EINVAL;
@@ -195,6 +205,8 @@ pxp_status validate(const pxp_problem& p) {
         if (p.prec != PXP_FP64) return PXP_EUNSUPPORTED;
         if (p.krylov == PXP_KRYLOV_SHIFT_INVERT) return PXP_EUNSUPPORTED;
         if (p.m < 1 || krylov2d_lds_bytes(p.m) > 160 * 1024) return PXP_EUNSUPPORTED;
+        // the Taylor flavour keeps four vectors in the basis region
+        if (use_taylor(p) && p.m < 3) return PXP_EUNSUPPORTED;
         if (!(p.krylov_tol > 0.0)) return PXP_EINVAL;
         if (!rk4_stable_advdiff2d(p)) return PXP_EUNSTABLE_DT;
         return PXP_OK;
@@ -347,8 +359,29 @@ struct Ctx {
     int fp32() const { return p.prec == PXP_FP32_BULK ? 1 : 0; }
 };
 
+// Largest scaled norm theta for which the Taylor remainder bound
+// theta^(d+1) e^theta / (d+1)! stays below tol (bisection in log form).
+double taylor_theta(int d, double tol) {
+    const double lt = std::log(tol), lf = std::lgamma((double)d + 2.0);
+    double lo = 1e-6, hi = 100.0;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if ((d + 1) * std::log(mid) + mid - lf <= lt)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+constexpr int TAYLOR_DEG = 40;
+
 KrylovArgs kargs(const Ctx& c, Tri op) {
     KrylovArgs a{};
+    a.taylor = use_taylor(c.p) ? 1 : 0;
+    a.tdeg = TAYLOR_DEG;
+    a.theta = taylor_theta(TAYLOR_DEG, c.p.krylov_tol);
+    a.anorm = std::fabs(op.lo) + std::fabs(op.d) + std::fabs(op.up);
     a.si = use_si(c.p) ? 1 : 0;
     a.n = c.n();
     a.m = c.p.m;
@@ -852,6 +885,7 @@ pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, v
         KrylovArgs a = kargs(c, Tri{0.0, 0.0, 0.0});
         a.si = 0;
         a.op5 = advdiff2d_sten(p);
+        a.anorm = sten_norm(a.op5);
         a.nx = p.nx;
         a.ny = p.ny;
         a.vin = c.at(c.L.slices);
@@ -945,6 +979,7 @@ pxp_status adjoint_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, 
         KrylovArgs a = kargs(c, Tri{0.0, 0.0, 0.0});
         a.si = 0;
         a.op5 = transpose5(advdiff2d_sten(p));
+        a.anorm = sten_norm(a.op5);
         a.nx = p.nx;
         a.ny = p.ny;
         a.mode = KM_SINGLE;

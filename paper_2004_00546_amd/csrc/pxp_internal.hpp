@@ -133,6 +133,13 @@ struct KrylovArgs {
     Sten5 op5;           // 2D: five-point operator
     int nx, ny;          // 2D: grid
     int blk0;            // batched launches: first workgroup of the entry
+    // Taylor flavour: exp(tau Op) v by the truncated Taylor series in
+    // substeps of at most theta / anorm time units, terms until two
+    // consecutive term norms are below tol |v| (at most tdeg terms); anorm
+    // is a bound of |Op| (0: computed in the kernel for the Burgers
+    // Jacobian)
+    int taylor, tdeg;
+    double anorm, theta;
     DevStatus* status;
 };
 hipError_t launch_krylov1d(const KrylovArgs& a, int block, hipStream_t s);

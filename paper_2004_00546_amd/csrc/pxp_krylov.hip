@@ -191,8 +191,32 @@ struct Core {
 
     // V_0 <- exp(tau Op) V_0; if iout, iout += int_0^tau sin(ia + ib s)
     // exp(s Op) V_0 ds.
+    // Weight of the k-th Taylor term (hOp)^k u / k! in the integral
+    // int_0^h sin(ph + ib s) exp(s Op) u ds:
+    //   J_k = h Im(e^{i ph} int_0^1 x^k e^{i ib h x} dx),
+    // the inner integral as the series sum_j (i ib h)^j / (j! (k + j + 1)).
+    __device__ __forceinline__ static double taylor_weight(int k, double h, double ph,
+                                                           double ib) {
+        const double beta = ib * h;
+        double re = 0.0, im = 0.0, tr = 1.0, ti = 0.0;
+        for (int j = 0; j < 60; ++j) {
+            const double c = 1.0 / (double)(k + j + 1);
+            re += tr * c;
+            im += ti * c;
+            const double nr = -ti * beta / (j + 1), ni = tr * beta / (j + 1);
+            tr = nr;
+            ti = ni;
+            if (fabs(tr) + fabs(ti) < 1e-18 * (fabs(re) + fabs(im))) break;
+        }
+        return h * (sin(ph) * re + cos(ph) * im);
+    }
+
     __device__ __forceinline__ void expv(double tau, double ia, double ib, double* iout) {
         if (!(tau > 0.0)) return;
+        if (!SI && a.taylor) {
+            self().expv_taylor(tau, ia, ib, iout);
+            return;
+        }
         const double tol = a.tol;
         if (SI) {
             const double gamma = a.gamma_frac * tau;
@@ -592,6 +616,93 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
                 const int i = gidx(r) + v;
                 z[r * VW + v] = X[(i / PT) * (PT + 1) + (i % PT)];
             }
+    }
+
+    // Taylor flavour (see KrylovArgs): V_0 <- exp(tau Op) V_0 in registers,
+    // iout += the time integral.  The Burgers Jacobian bounds its own norm
+    // (largest absolute row sum of J(W)^T).
+    __device__ __forceinline__ void expv_taylor(double tau, double ia, double ib,
+                                                double* iout) {
+        if constexpr (!SI) {
+            double u[PT];
+            gload(V, u);
+            double anorm = a.anorm;
+            if (VAR) {
+                double mx = 0.0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (!own(r)) continue;
+#pragma unroll
+                    for (int v = 0; v < VW; ++v) {
+                        const int i = gidx(r) + v;
+                        const double Wm = Wcur[i == 0 ? n - 1 : i - 1];
+                        const double Wp = Wcur[i == n - 1 ? 0 : i + 1];
+                        const double rs = 2.0 * a.nuh2 + fabs(a.nuh2 + a.inv2h * Wp) +
+                                          fabs(a.nuh2 - a.inv2h * Wm) +
+                                          fabs(a.inv2h * (Wp - Wm));
+                        mx = fmax(mx, rs);
+                    }
+                }
+                anorm = block_max(mx, S.red);
+            }
+            double nu = sqrt(block_sum(sumsq(u), S.red));
+            if (!(nu > 0.0)) return;
+            int ns = (int)ceil(tau * anorm / a.theta);
+            if (ns < 1) ns = 1;
+            const double h = tau / ns;
+            double I[PT];
+#pragma unroll
+            for (int q = 0; q < PT; ++q) I[q] = 0.0;
+            bool noconv = false;
+            double worst = 0.0;
+            unsigned terms = 0;
+            for (int sub = 0; sub < ns; ++sub) {
+                const double ph = ia + ib * (sub * h);
+                double tk[PT], sum[PT];
+                const double J0 = iout ? Base::taylor_weight(0, h, ph, ib) : 0.0;
+#pragma unroll
+                for (int q = 0; q < PT; ++q) {
+                    tk[q] = u[q];
+                    sum[q] = u[q];
+                    I[q] += J0 * u[q];
+                }
+                double prev = nu;
+                bool conv = false;
+                for (int k = 1; k <= a.tdeg; ++k) {
+                    apply(tk, 0.0);
+                    const double f = h / k;
+                    const double Jk = iout ? Base::taylor_weight(k, h, ph, ib) : 0.0;
+#pragma unroll
+                    for (int q = 0; q < PT; ++q) {
+                        tk[q] *= f;
+                        sum[q] += tk[q];
+                        I[q] += Jk * tk[q];
+                    }
+                    const double nt = sqrt(block_sum(sumsq(tk), S.red));
+                    ++terms;
+                    if (prev + nt <= a.tol * nu) {
+                        conv = true;
+                        worst = fmax(worst, (prev + nt) / nu);
+                        break;
+                    }
+                    prev = nt;
+                }
+                if (!conv) noconv = true;
+#pragma unroll
+                for (int q = 0; q < PT; ++q) u[q] = sum[q];
+                nu = sqrt(block_sum(sumsq(u), S.red));
+            }
+            gstore(V, u);
+            if (iout) {
+                double o[PT];
+                gload(iout, o);
+#pragma unroll
+                for (int q = 0; q < PT; ++q) o[q] += I[q];
+                gstore(iout, o);
+            }
+            this->report(worst, noconv, (unsigned)ns, terms);
+            __syncthreads();
+        }
     }
 
     // hcol[k] = <V_k, z> for k <= j, KD basis vectors at a time (8, or 4
@@ -1112,6 +1223,103 @@ struct Ctx2 : Core<Ctx2, false> {
                 st2(iout, g, o);
             }
         }
+    }
+
+    // One Taylor term: dst = f Op src; sum = (base ? base : sum) + dst;
+    // iout += (base ? J0 base : 0) + Jk dst.  Returns this thread's |dst|^2.
+    __device__ __forceinline__ double taylor_pass(const double* __restrict__ src,
+                                                  double* __restrict__ dst,
+                                                  double* __restrict__ sum,
+                                                  const double* __restrict__ base,
+                                                  double* __restrict__ iout, double f,
+                                                  double J0, double Jk) const {
+        const Sten5 o = a.op5;
+        double ss = 0.0;
+#pragma unroll 2
+        for (int r = 0; r < G; ++r) {
+            const int g = t + r * B, i = 2 * g;
+            const int row = i / nx, col = i - row * nx, rc = row * nx;
+            const int rs = (row == 0 ? ny - 1 : row - 1) * nx;
+            const int rn = (row == ny - 1 ? 0 : row + 1) * nx;
+            const double2 x = ld2(src, g);
+            const double xw = src[rc + (col == 0 ? nx - 1 : col - 1)];
+            const double xe = src[rc + (col + 2 == nx ? 0 : col + 2)];
+            const double2 xs = *reinterpret_cast<const double2*>(src + rs + col);
+            const double2 xn = *reinterpret_cast<const double2*>(src + rn + col);
+            double2 y;
+            y.x = f * (o.c * x.x + o.w * xw + o.e * x.y + o.s * xs.x + o.n * xn.x);
+            y.y = f * (o.c * x.y + o.w * x.x + o.e * xe + o.s * xs.y + o.n * xn.y);
+            st2(dst, g, y);
+            double2 sm = ld2(base ? base : sum, g);
+            if (iout) {
+                double2 io = ld2(iout, g);
+                if (base) {
+                    io.x += J0 * sm.x;
+                    io.y += J0 * sm.y;
+                }
+                io.x += Jk * y.x;
+                io.y += Jk * y.y;
+                st2(iout, g, io);
+            }
+            sm.x += y.x;
+            sm.y += y.y;
+            st2(sum, g, sm);
+            ss += y.x * y.x + y.y * y.y;
+        }
+        return ss;
+    }
+
+    // Taylor flavour (see KrylovArgs) on streamed vectors: the current
+    // vector and the running sum alternate between V_0 and V_1, the terms
+    // between V_2 and V_3.
+    __device__ __forceinline__ void expv_taylor(double tau, double ia, double ib,
+                                                double* iout) {
+        double* u = V;
+        double* sm = V + n;
+        double* tA = V + 2 * (size_t)n;
+        double* tB = V + 3 * (size_t)n;
+        double nu = sqrt(block_sum(sumsq(u), S.red));
+        if (!(nu > 0.0)) return;
+        int ns = (int)ceil(tau * a.anorm / a.theta);
+        if (ns < 1) ns = 1;
+        const double h = tau / ns;
+        bool noconv = false;
+        double worst = 0.0;
+        unsigned terms = 0;
+        for (int sub = 0; sub < ns; ++sub) {
+            const double ph = ia + ib * (sub * h);
+            const double J0 = iout ? this->taylor_weight(0, h, ph, ib) : 0.0;
+            const double J1 = iout ? this->taylor_weight(1, h, ph, ib) : 0.0;
+            __syncthreads();  // u complete: the stencil reads neighbours
+            double prev = sqrt(block_sum(taylor_pass(u, tA, sm, u, iout, h, J0, J1), S.red));
+            ++terms;
+            bool conv = false;
+            const double* src = tA;
+            double* dst = tB;
+            for (int k = 2; k <= a.tdeg; ++k) {
+                const double Jk = iout ? this->taylor_weight(k, h, ph, ib) : 0.0;
+                const double nt = sqrt(
+                    block_sum(taylor_pass(src, dst, sm, nullptr, iout, h / k, 0.0, Jk), S.red));
+                ++terms;
+                if (prev + nt <= a.tol * nu) {
+                    conv = true;
+                    worst = fmax(worst, (prev + nt) / nu);
+                    break;
+                }
+                prev = nt;
+                const double* tmp = src;
+                src = dst;
+                dst = const_cast<double*>(tmp);
+            }
+            if (!conv) noconv = true;
+            double* tmp = u;
+            u = sm;
+            sm = tmp;
+            nu = sqrt(block_sum(sumsq(u), S.red));
+        }
+        if (u != V) copy(u, V);
+        this->report(worst, noconv, (unsigned)ns, terms);
+        __syncthreads();
     }
 
     __device__ __forceinline__ void copy(const double* src, double* dst) const {

@@ -152,3 +152,58 @@ def test_workload_2d_sample_vs_oracle(torch, orc):
             inst["T"], inst["n_steps"], rel(b["qT"], want["qT"]), e))
         assert e < FP64_GATE
     assert code == 0
+
+
+# ---- Taylor flavour: exp(tau A) v by the scaled truncated Taylor series ----
+
+def test_adjoint_piece_2d_taylor_vs_fourier(torch):
+    inst = small2d(nx=64, ny=64, T=0.7, nt=64, P=16, m=40)
+    n = inst["nx"] * inst["ny"]
+    lamT = np.asarray(inst["u_tgt"])
+    p = api.make_problem(inst, krylov="taylor", tol=1e-12)
+    dev = torch.device("cuda:0")
+    f64 = dict(dtype=torch.float64, device=dev)
+    ws = torch.empty(_lib.pxp_workspace_size([p]), dtype=torch.uint8, device=dev)
+    _lib.pxp_workspace_init(ws)
+    lam0 = torch.zeros(n, **f64)
+    Lam = torch.zeros(n, **f64)
+    _lib.paraexp_adjoint([p], torch.tensor(lamT, **f64), lam0, Lam, ws)
+    code, est = _lib.pxp_device_status(ws)
+    lam_eig = fourier.eigenvalues(inst)
+    want0 = fourier.exp_action_T(inst, inst["T"], lamT, lam_eig)
+    mu = np.conj(lam_eig)
+    T, w = inst["T"], inst["omega"]
+    tr = (w * np.exp(mu * T) - mu * np.sin(w * T) - w * np.cos(w * T)) / (mu ** 2 + w ** 2)
+    wantL = fourier._ifft(inst, tr * fourier._fft(inst, lamT))
+    e0, eL = rel(lam0.cpu().numpy(), want0), rel(Lam.cpu().numpy(), wantL)
+    say("2d taylor adjoint piece: lam0 %.2e Lambda %.2e est %.1e" % (e0, eL, est))
+    assert code == 0
+    assert e0 < 1e-10 and eL < 1e-10
+
+
+@pytest.mark.parametrize("sched", ["chain", "classic"])
+def test_paraexp_2d_taylor_matches_oracle(torch, orc, sched):
+    inst = small2d(P=16)
+    got = run_flavour(inst, "taylor", sched=sched, tol=1e-11)
+    want = orc.gradient(inst)
+    e = rel(got["grad"], want["grad"])
+    say("2d taylor %s: grad %.2e status %d" % (sched, e, got["status"]))
+    assert got["status"] == 0 and e < FP64_GATE
+
+
+def test_workload_2d_taylor_sample(torch, orc):
+    full = workloads.make("advdiff2d_256")
+    inst = min(full, key=lambda x: x["n_steps"])
+    got = run_flavour(inst, "taylor", sched="chain")
+    want = orc.gradient(inst)
+    e = rel(got["grad"], want["grad"])
+    say("2d workload taylor chain: grad %.2e" % e)
+    assert got["status"] == 0 and e < FP64_GATE
+
+
+def run_flavour(inst, krylov, **kw):
+    r = api.GradientRunner([inst], method="paraexp", krylov=krylov, **kw)
+    r.run()
+    out = r.results()[0]
+    out["status"], out["est"] = r.status()
+    return out

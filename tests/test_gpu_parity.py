@@ -421,7 +421,7 @@ def test_ragged_burgers_shift_invert_batch(torch, orc):
 
 def test_auto_flavour_ragged_equals_explicit_choice(torch):
     """AUTO picks shift-and-invert per instance where half a slice times the
-    diffusion spectral radius exceeds 64, else the polynomial space; each
+    diffusion spectral radius exceeds 64, else the Taylor flavour; each
     batched result equals the run with that flavour named explicitly."""
     insts = ragged_burgers(seed=70)
     insts[2] = dict(insts[2], P=insts[2]["n_steps"] // 64)  # long macro steps
@@ -431,7 +431,7 @@ def test_auto_flavour_ragged_equals_explicit_choice(torch):
     for inst, b in zip(insts, r.results()):
         h = inst["L"] / inst["nx"]
         si = 0.5 * inst["T"] / inst["P"] * 4 * inst["nu"] / h**2 > 64
-        one = run(inst, "paraexp", krylov="shift_invert" if si else "poly")
+        one = run(inst, "paraexp", krylov="shift_invert" if si else "taylor")
         assert np.array_equal(one["grad"], b["grad"]), (inst["nx"], si)
 
 
@@ -467,3 +467,20 @@ def test_absorbed_adjoint_ic_control(torch, orc):
                                               rel(a["grad"], want["grad"])))
     assert rel(a["grad"], want["grad"]) < FP64_GATE
     assert rel(a["lam"], want["lam0"]) < FP64_GATE
+
+
+@pytest.mark.parametrize("case", ["advdiff1d_n128", "burgers_small"])
+def test_taylor_flavour_matches_oracle(torch, orc, case):
+    """The Taylor flavour (no Arnoldi process) on the register-resident 1D
+    pieces and on the Burgers Magnus factors (the Jacobian bounds its own
+    norm in the kernel)."""
+    if case == "burgers_small":
+        inst = small_burgers(n=512, T=0.3, nt=128, P=32, nu=0.01, seed=9, ckpt=16)
+    else:
+        inst = workloads.make(case)[0]
+    got = run(inst, "paraexp", krylov="taylor")
+    want = orc.gradient(inst)
+    e = rel(got["grad"], want["grad"])
+    say("taylor %s: grad %.2e status %d" % (case, e, got["status"]))
+    assert got["status"] == 0
+    assert e < FP64_GATE
