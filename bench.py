@@ -73,10 +73,18 @@ def m_is_full(inst):
     return True
 
 
-def time_runner(torch, r, steps, warmup):
-    for _ in range(warmup):
+def warm(torch, r, count, seconds):
+    """Untimed calls: at least `count`, and until `seconds` have passed."""
+    t0 = time.perf_counter()
+    k = 0
+    while k < count or time.perf_counter() - t0 < seconds:
         r.run()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        k += 1
+
+
+def time_runner(torch, r, steps, warmup, seconds=1.0):
+    warm(torch, r, warmup, seconds)
     t0 = time.perf_counter()
     for _ in range(steps):
         r.run()
@@ -89,6 +97,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup-seconds", type=float, default=2.0,
+                    help="keep warming up (untimed gradients) for at least this long, so "
+                         "the timed region runs at steady-state clocks")
     ap.add_argument("--workload", default="advdiff1d_n4096")
     ap.add_argument("--krylov", default="auto", choices=["poly", "shift_invert", "auto", "taylor"])
     ap.add_argument("--sched", default="classic", choices=["classic", "chain"])
@@ -177,9 +188,7 @@ def main():
     ser = api.GradientRunner(insts, method="serial", krylov="auto", **kw)
 
     # timed Paraexp region, with per-kernel events on the library's stream
-    for _ in range(args.warmup):
-        pxp.run()
-    torch.cuda.synchronize()
+    warm(torch, pxp, args.warmup, args.warmup_seconds)
     pxp.status()
     _lib.pxp_device_counters(pxp.ws)
     _lib.pxp_profile_enable(True)

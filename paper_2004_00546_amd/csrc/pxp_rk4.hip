@@ -102,11 +102,11 @@ __device__ __forceinline__ void tri_rhs(const R (&Y)[PT], R l, R r, R cs, R cdf,
     }
 }
 
-template <int PT, typename R>
-__global__ void __launch_bounds__(max_block<PT>())
-k_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
-            const double* __restrict__ y0, double* __restrict__ out, int n,
-            int64_t n_s, double dt, double omega, TriSplit A, SliceIntegral si) {
+template <int PT, typename R, bool INT>
+__device__ __forceinline__ void
+dev_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
+              const double* __restrict__ y0, double* __restrict__ out, int n,
+              int64_t n_s, double dt, double omega, TriSplit A, SliceIntegral si) {
     extern __shared__ double lds_d[];
     R* lds = reinterpret_cast<R*>(lds_d);
     const int t = threadIdx.x;
@@ -135,7 +135,7 @@ k_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
         const R s2 = (R)sin(omega * (tn + 0.5 * dt));
         const R s4 = (R)sin(omega * (tn + dt));
         double w1 = 0.0, w2 = 0.0, w4 = 0.0;
-        if (si.iout) {
+        if constexpr (INT) {
             w1 = dt / 6.0 * sin(si.ia + si.ib * tn);
             w2 = dt / 3.0 * sin(si.ia + si.ib * (tn + 0.5 * dt));
             w4 = dt / 6.0 * sin(si.ia + si.ib * (tn + dt));
@@ -154,7 +154,7 @@ k_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
             acc[q] = k[q];
             Y[q] = y[q] + h2 * k[q];
         }
-        if (si.iout) {
+        if constexpr (INT) {
 #pragma unroll
             for (int q = 0; q < PT; ++q) I[q] += w2 * ((double)y[q] - (double)yc[q] + (double)(h2 * k[q]));
         }
@@ -169,7 +169,7 @@ k_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
             acc[q] += (R)2 * k[q];
             Y[q] = y[q] + h2 * k[q];
         }
-        if (si.iout) {
+        if constexpr (INT) {
 #pragma unroll
             for (int q = 0; q < PT; ++q) I[q] += w2 * ((double)y[q] - (double)yc[q] + (double)(h2 * k[q]));
         }
@@ -184,7 +184,7 @@ k_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
             acc[q] += (R)2 * k[q];
             Y[q] = y[q] + h1 * k[q];
         }
-        if (si.iout) {
+        if constexpr (INT) {
 #pragma unroll
             for (int q = 0; q < PT; ++q) I[q] += w4 * ((double)y[q] - (double)yc[q] + (double)(h1 * k[q]));
         }
@@ -202,12 +202,29 @@ k_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
     double* o = out + (size_t)p * n;
 #pragma unroll
     for (int q = 0; q < PT; ++q) o[base + q] = hilo<R>(y[q], yc[q]);
-    if (si.iout) {
+    if constexpr (INT) {
         double* io = si.iout + (size_t)p * n;
 #pragma unroll
         for (int q = 0; q < PT; ++q)
             io[base + q] = I[q] + ((p == 0 && si.v0) ? si.c0 * si.v0[base + q] : 0.0);
     }
+}
+
+// The slice march without and with the slice integral (separate code, so
+// the plain march keeps its register budget).
+template <int PT, typename R>
+__global__ void __launch_bounds__(max_block<PT>())
+k_rk4_lin1d_plain(const double* __restrict__ F, const double* __restrict__ g0,
+                  const double* __restrict__ y0, double* __restrict__ out, int n,
+                  int64_t n_s, double dt, double omega, TriSplit A, SliceIntegral si) {
+    dev_rk4_lin1d<PT, R, false>(F, g0, y0, out, n, n_s, dt, omega, A, si);
+}
+template <int PT, typename R>
+__global__ void __launch_bounds__(max_block<PT>())
+k_rk4_lin1d_int(const double* __restrict__ F, const double* __restrict__ g0,
+                const double* __restrict__ y0, double* __restrict__ out, int n,
+                int64_t n_s, double dt, double omega, TriSplit A, SliceIntegral si) {
+    dev_rk4_lin1d<PT, R, true>(F, g0, y0, out, n, n_s, dt, omega, A, si);
 }
 
 // Reverse sweep: y_{s+1} = y_s + dt sum_i b_i k_i with k_i = A Y_i + ...
@@ -737,8 +754,13 @@ hipError_t launch_rk4_lin1d(const double* F, const double* g0, const double* y0,
     if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
     const size_t lds = sizeof(double) * 4 * block;
     const TriSplit sp = split(A);
-    PXP_DISPATCH(fp32, pt, k_rk4_lin1d,
-                 <<<P, block, lds, s>>>(F, g0, y0, out, n, n_s, dt, omega, sp, si))
+    if (si.iout) {
+        PXP_DISPATCH(fp32, pt, k_rk4_lin1d_int,
+                     <<<P, block, lds, s>>>(F, g0, y0, out, n, n_s, dt, omega, sp, si))
+    } else {
+        PXP_DISPATCH(fp32, pt, k_rk4_lin1d_plain,
+                     <<<P, block, lds, s>>>(F, g0, y0, out, n, n_s, dt, omega, sp, si))
+    }
     return hipGetLastError();
 }
 
