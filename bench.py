@@ -163,7 +163,7 @@ def main():
     log("workload %s: %d instance(s); first N=%d steps=%d P=%d m=%d; point-steps %.3g"
         % (args.workload, B, n, n_steps, P, m, sum(work)))
 
-    tol = args.tol if args.tol is not None else (1e-10 if args.prec == "fp64" else 1e-6)
+    tol = args.tol if args.tol is not None else (1e-9 if args.prec == "fp64" else 1e-6)
     kw = dict(prec=args.prec, block=args.block, kblock=args.kblock)
     pkw = dict(kw, absorbed=args.absorbed)
     tuned = None

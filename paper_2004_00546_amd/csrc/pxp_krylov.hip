@@ -16,11 +16,11 @@
 //    with A ~ (I - H_m^{-1}) / gamma on the space; the periodic tridiagonal
 //    solve is parallel cyclic reduction in LDS (uniform coefficients, n a
 //    power of two) or chunk elimination plus cyclic reduction of the chunk
-//    interfaces (the Burgers Jacobian).  From about m/2 on, every eighth
-//    dimension compares the approximation with the previous check's and
-//    stops once they differ by less than the tolerance; at full dimension
-//    the estimate is the difference of the dimension m and m-1
-//    approximations.
+//    interfaces (the Burgers Jacobian).  From about m/2 on, checks compare
+//    the approximation with the previous check's and extrapolate the
+//    error from the observed contraction; the process stops once that is
+//    below the tolerance, and the next check is placed where the
+//    contraction predicts convergence.
 //
 // Optional time integral of the piece against sin(a + b s):
 //   int_0^tau sin(a + b s) exp(s A) v ds ~ beta V_m Im(e^{ia} x),
@@ -34,6 +34,12 @@ namespace pxp {
 namespace {
 
 constexpr int M_MAX_1D = 48;
+
+// Gram-Schmidt: the second classical pass runs when the first removed all
+// but a fraction eta of the vector's norm, |w_1| < eta |w_0| (Daniel, Gragg,
+// Kaufman & Stewart's criterion), with eta = 0.1: the exponential's
+// approximation tolerates the orthogonality lost at milder cancellation.
+constexpr double DGKS_ETA2 = 0.01;  // eta^2
 
 __host__ __device__ inline size_t big_doubles(int n, int m, int block) {
     size_t vec = 2 * (size_t)n;
@@ -82,6 +88,12 @@ struct Core {
     Smem S;
     int n, m, B, t, ldr;
     unsigned nre = 0;  // second Gram-Schmidt passes since the last report
+    // Shift-and-invert early exit, state of the current Arnoldi process:
+    // dimension of the last check (0: none yet), the difference of that
+    // check's approximation to the one before it (negative: none) and the
+    // gap in dimensions between those two checks.
+    int si_kc = 0, si_gp = 0;
+    double si_dp = -1.0;
 
     __device__ Core(const KrylovArgs& a_, double* lds)
         : a(a_), n(a_.n), m(a_.m), B(blockDim.x), t(threadIdx.x) {
@@ -111,6 +123,29 @@ struct Core {
             S.Mt[r * k + c] = f * (((r == c) ? 1.0 : 0.0) - X[r * k + c]);
         });
         __syncthreads();
+    }
+
+    // |vy - yprev| over the first k coefficients (yprev holds the
+    // approximation of the last check, dimension si_kc, zero-extended).
+    __device__ __forceinline__ double si_diff(int k) const {
+        double d2 = 0.0;
+        for (int q = 0; q < k; ++q) {
+            const double d = S.vy[q] - (q < si_kc ? S.yprev[q] : 0.0);
+            d2 += d * d;
+        }
+        return sqrt(d2);
+    }
+
+    // Error of the dimension-k approximation.  d = |y_k - y_kc| (gap
+    // g = k - kc) measures the error of the older y_kc; with the previous
+    // difference dp over gap gp the per-dimension contraction is
+    // (d/dp)^(1/gp), and geometric convergence carries d over the g
+    // dimensions to k.  Without a previous difference d itself is returned
+    // (an over-estimate).
+    __device__ __forceinline__ static double si_extrapolate(double d, double dp, int g, int gp) {
+        if (!(dp > 0.0) || gp <= 0) return d;
+        const double r = fmin(1.0, d / dp);
+        return d * pow(r, (double)g / (double)gp);
     }
 
     // vec = exp(ts Hop) e_1 (leading k x k block); returns |vec[k-1]|.
@@ -227,9 +262,14 @@ struct Core {
             const int me = self().arnoldi(gamma, beta, bd, tau, tol, &conv, &est);
             if (me == 0) return;
             if (!conv) {
-                // full dimension (or breakdown): estimate from dimensions m
-                // and m - 1
-                if (!bd && me > 1) {
+                // full dimension: extrapolated from the checks when there
+                // were any, else the difference of dimensions m and m - 1;
+                // after a breakdown the space is exact
+                if (!bd && si_kc > 0 && si_kc < me) {
+                    small_exp(me, tau, gamma, S.vy);
+                    est = si_extrapolate(si_diff(me), si_dp, me - si_kc, si_gp);
+                    __syncthreads();
+                } else if (!bd && me > 1) {
                     small_exp(me - 1, tau, gamma, S.vy2);
                     small_exp(me, tau, gamma, S.vy);
                     double s = 0.0;
@@ -809,11 +849,14 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
         for (int u = 0; u < PT; ++u) z[u] *= ib;
         gstore(V, z);
         int me = m;
+        this->si_kc = 0;
+        this->si_gp = 0;
+        this->si_dp = -1.0;
+        int knext = (m / 8 > 1 ? m / 8 : 1) * 4;  // first check, about m/2
         for (int j = 0; j < m; ++j) {
             apply(z, gamma);
             // classical Gram-Schmidt; the second pass runs only when the
-            // first removed more than half of |Op v_j|^2 (the DGKS
-            // criterion, eta = 1/sqrt(2))
+            // first left less than eta^2 of |Op v_j|^2 (DGKS_ETA2)
             double nrm2 = 0.0, col = 0.0;
             for (int pass = 0; pass < 2; ++pass) {
                 dots(z, j);
@@ -824,7 +867,7 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
                 for (int k = 0; k <= j; ++k) hh += S.H[k * m + j] * S.H[k * m + j];
                 // |Op v_j|^2 = sum_k h_kj^2 + nrm^2 (the Gram-Schmidt column)
                 col = hh + nrm2;
-                if (pass == 0 && !(nrm2 < hh)) break;
+                if (pass == 0 && !(nrm2 < DGKS_ETA2 * col)) break;
                 if (pass == 0) ++nre;
             }
             const double nrm = sqrt(nrm2);
@@ -847,24 +890,38 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
                     break;
                 }
             }
-            const int k1 = (m / 8 > 1 ? m / 8 : 1) * 4;  // first check, about m/2
-            if (SI && conv && ts > 0.0 && k < m && k >= k1 && ((k - k1) % 8) == 0) {
-                // difference to the approximation of the previous check
-                // (dimension k - 8, kept in yprev): converged when below tol
+            if (SI && conv && ts > 0.0 && k < m && k == knext) {
+                // Compare with the previous check's approximation (yprev)
+                // and extrapolate the error to dimension k (si_extrapolate);
+                // converged when that is below tol.  The next check goes
+                // where the observed contraction predicts the tolerance,
+                // at least 4 dimensions on and at most at m - 4.
                 small_exp(k, ts, gamma, S.vy);
-                double d2 = 0.0;
-                for (int q = 0; q < k; ++q) {
-                    const double d = S.vy[q] - ((k > k1 && q < k - 8) ? S.yprev[q] : 0.0);
-                    d2 += d * d;
+                int step = 4;
+                if (this->si_kc > 0) {
+                    const double d = this->si_diff(k);
+                    const int g = k - this->si_kc;
+                    const double est = this->si_extrapolate(d, this->si_dp, g, this->si_gp);
+                    __syncthreads();
+                    if (est <= tolb_rel) {
+                        *conv = true;
+                        if (est_out) *est_out = est;
+                        me = k;
+                        break;
+                    }
+                    if (this->si_dp > 0.0 && d < this->si_dp && est > 0.0) {
+                        const double r4 = pow(d / this->si_dp, 4.0 / (double)this->si_gp);
+                        const double blocks = ceil(log(tolb_rel / est) / log(r4));
+                        if (blocks > 1.0) step = 4 * (int)fmin(blocks, (double)m);
+                    }
+                    this->si_dp = d;
+                    this->si_gp = g;
                 }
-                const double est = sqrt(d2);
-                __syncthreads();
-                if (k > k1 && est <= tolb_rel) {
-                    *conv = true;
-                    if (est_out) *est_out = est;
-                    me = k;
-                    break;
-                }
+                // the last check before the full dimension sits at most 4
+                // below it, so the final extrapolation spans few dimensions
+                knext = k + step < m - 4 ? k + step : m - 4;
+                if (knext < k + 4) knext = k + 4;
+                this->si_kc = k;
                 for (int q = t; q < k; q += B) S.yprev[q] = S.vy[q];
                 __syncthreads();
             }
@@ -1170,7 +1227,7 @@ struct Ctx2 : Core<Ctx2, false> {
                 double hh = 0.0;
                 for (int k = 0; k <= j; ++k) hh += S.H[k * m + j] * S.H[k * m + j];
                 col = hh + nrm2;
-                if (pass == 0 && !(nrm2 < hh)) break;
+                if (pass == 0 && !(nrm2 < DGKS_ETA2 * col)) break;
                 if (pass == 0) ++nre;
             }
             const double nrm = sqrt(nrm2);

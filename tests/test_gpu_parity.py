@@ -142,9 +142,9 @@ def test_krylov_full_dimension_is_exact(torch):
 def test_paraexp_workload_n128(torch, orc, krylov, sched):
     inst = workloads.make("advdiff1d_n128")[0]
     # per-piece estimate tolerance; m = 30 shift-and-invert spaces on this
-    # mildly stiff grid estimate about 2e-10 for the longest piece
+    # mildly stiff grid reach about 1e-9 on the longest piece
     got = run(inst, krylov=krylov, sched=sched,
-              tol=1e-9 if krylov == "shift_invert" else 1e-10)
+              tol=1e-8 if krylov == "shift_invert" else 1e-10)
     want = orc.gradient(inst)
     eq, eg = rel(got["qT"], want["qT"]), rel(got["grad"], want["grad"])
     say("n128 paraexp %s/%s: qT %.2e grad %.2e est %.1e st %d"
@@ -204,8 +204,10 @@ def test_paraexp_workload_n4096(torch, orc):
     inst = workloads.make("advdiff1d_n4096")[0]
     say("n4096: oracle (about 12 s)")
     want = orc.gradient(inst)
-    for krylov, sched in [("shift_invert", "classic"), ("poly", "chain")]:
-        got = run(inst, krylov=krylov, sched=sched)
+    # per-piece tolerances: the 40-dimensional shift-and-invert spaces of
+    # the longest pieces estimate about 1e-10
+    for krylov, sched, tol in [("shift_invert", "classic", 1e-9), ("poly", "chain", 1e-10)]:
+        got = run(inst, krylov=krylov, sched=sched, tol=tol)
         eq, eg = rel(got["qT"], want["qT"]), rel(got["grad"], want["grad"])
         say("n4096 %s/%s qT %.2e grad %.2e est %.1e st %d"
             % (krylov, sched, eq, eg, got["est"], got["status"]))
