@@ -35,6 +35,15 @@ namespace {
 
 constexpr int M_MAX_1D = 48;
 
+// Table of the uniform shift-and-invert solve (Ctx::ui_setup), in doubles:
+// Thomas pivots piv_l and ratios cp_l of a chunk's interior block, the
+// interior's responses g_l, h_l to the chunk's first point and to the next
+// chunk's first point (l < 32 each), the cyclic-reduction multipliers of
+// the chunk-interface system (two per level, at most 16 levels), then the
+// final 2 x 2 elimination and the row coefficients.
+constexpr int UT_PIV = 0, UT_CP = 32, UT_G = 64, UT_H = 96, UT_LVL = 128, UT_FIN = 160;
+constexpr int UT_DOUBLES = 168;
+
 // Gram-Schmidt: the second classical pass runs when the first removed all
 // but a fraction eta of the vector's norm, |w_1| < eta |w_0| (Daniel, Gragg,
 // Kaufman & Stewart's criterion), with eta = 0.1: the exponential's
@@ -64,6 +73,7 @@ struct Smem {
     double* hcol;  // ldr + 8
     double* H;     // (m+1) x m, ld = m
     double* yprev; // m: the previous shift-and-invert check's approximation
+    double* ut;    // UT_DOUBLES: factors of the uniform shift-and-invert solve
     double* big;   // vector buffers (2n) or small matrices
     // small-matrix region (inside big)
     double* Mt;    // m x m
@@ -102,7 +112,8 @@ struct Core {
         S.hcol = S.red + 64;
         S.H = S.hcol + ldr + 8;
         S.yprev = S.H + (size_t)(m + 1) * m;
-        S.big = S.yprev + ldr;
+        S.ut = S.yprev + ldr;
+        S.big = S.ut + UT_DOUBLES;
         S.Mt = S.big;
         S.E = S.Mt + (size_t)m * m;
         S.W = S.E + (size_t)m * m;
@@ -371,6 +382,131 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
 
     __device__ __forceinline__ void before_space(double gamma) {
         if (VAR && SI) si_setup(gamma);
+        if (!VAR && SI) ui_setup(gamma);
+    }
+
+    // Shift-and-invert solve with constant coefficients, rows
+    // lo x_{i-1} + dd x_i + up x_{i+1} of the periodic system (I - gamma A):
+    // thread k owns the chunk of PT consecutive points k*PT .. k*PT+PT-1.
+    // The chunk's interior 1..PT-1 is a tridiagonal block coupled only to
+    // the chunk's first point x_k and the next chunk's first point x_{k+1},
+    //   interior = y + g x_k + h x_{k+1},
+    // y the block's solve of the right-hand side (Thomas, in registers).
+    // Substituting into the chunks' first rows leaves a periodic system in
+    // the B values x_k whose rows are again uniform, solved by cyclic
+    // reduction with one value per thread.  Everything that depends only
+    // on gamma (pivots, g, h, the reduction's multipliers) is computed here
+    // once per Krylov space, by one thread, into the LDS table.
+    __device__ __attribute__((noinline)) void ui_setup(double gamma) {
+        if (t == 0) {
+            double* T = S.ut;
+            const double lo = -gamma * a.op.lo, dd = 1.0 - gamma * a.op.d, up = -gamma * a.op.up;
+            double ca = lo, cb = dd, cc = up;
+            if (PT > 1) {
+                // forward sweep: pivots, ratios, and the response to x_k
+                // (kept in the g slots until the backward sweep)
+                T[UT_PIV + 1] = 1.0 / dd;
+                T[UT_CP + 1] = up * T[UT_PIV + 1];
+                T[UT_G + 1] = -lo * T[UT_PIV + 1];
+                for (int l = 2; l < PT; ++l) {
+                    T[UT_PIV + l] = 1.0 / (dd - lo * T[UT_CP + l - 1]);
+                    T[UT_CP + l] = up * T[UT_PIV + l];
+                    T[UT_G + l] = -lo * T[UT_G + l - 1] * T[UT_PIV + l];
+                }
+                T[UT_H + PT - 1] = -up * T[UT_PIV + PT - 1];
+                for (int l = PT - 2; l >= 1; --l) {
+                    T[UT_G + l] -= T[UT_CP + l] * T[UT_G + l + 1];
+                    T[UT_H + l] = -T[UT_CP + l] * T[UT_H + l + 1];
+                }
+                ca = lo * T[UT_G + PT - 1];
+                cb = dd + lo * T[UT_H + PT - 1] + up * T[UT_G + 1];
+                cc = up * T[UT_H + 1];
+            }
+            int lvl = 0;
+            for (int sft = 1; 2 * sft < B; sft <<= 1, ++lvl) {
+                const double k1 = ca / cb, k2 = cc / cb;
+                T[UT_LVL + 2 * lvl] = k1;
+                T[UT_LVL + 2 * lvl + 1] = k2;
+                const double na = -ca * k1, nc = -cc * k2, nb = cb - cc * k1 - ca * k2;
+                ca = na;
+                cb = nb;
+                cc = nc;
+            }
+            // rows k and k + B/2 now couple only to each other
+            const double e = ca + cc;
+            T[UT_FIN] = cb;
+            T[UT_FIN + 1] = e;
+            T[UT_FIN + 2] = 1.0 / (cb * cb - e * e);
+            T[UT_FIN + 3] = lo;
+            T[UT_FIN + 4] = up;
+        }
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ void ui_solve(double (&z)[PT]) {
+        const int k = t, Bm = B - 1;
+        const double* T = S.ut;
+        double* X = S.big;          // chunk c at c * (PT + 1): one pad per chunk
+        double* Q = X + n + B;      // two buffers of B interface values
+        __syncthreads();            // previous users of `big` are done
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                const int i = gidx(r) + v;
+                X[(i / PT) * (PT + 1) + (i % PT)] = z[r * VW + v];
+            }
+        __syncthreads();
+        const double lo = T[UT_FIN + 3], up = T[UT_FIN + 4];
+        double rr[PT], y[PT];
+#pragma unroll
+        for (int l = 0; l < PT; ++l) rr[l] = X[k * (PT + 1) + l];
+        double rhs = rr[0];
+        if constexpr (PT > 1) {
+            y[1] = rr[1] * T[UT_PIV + 1];
+#pragma unroll
+            for (int l = 2; l < PT; ++l) y[l] = (rr[l] - lo * y[l - 1]) * T[UT_PIV + l];
+            // the previous chunk's last interior value: its forward sweep
+            // (the last point needs no back substitution)
+            const double* P = X + ((k - 1) & Bm) * (PT + 1);
+            double yp = P[1] * T[UT_PIV + 1];
+#pragma unroll
+            for (int l = 2; l < PT; ++l) yp = (P[l] - lo * yp) * T[UT_PIV + l];
+#pragma unroll
+            for (int l = PT - 2; l >= 1; --l) y[l] -= T[UT_CP + l] * y[l + 1];
+            rhs = rr[0] - lo * yp - up * y[1];
+        }
+        // cyclic reduction on the B interface values: level s removes the
+        // couplings to k - s and k + s using rows k - s and k + s
+        int buf = 0, lvl = 0;
+        for (int sft = 1; 2 * sft < B; sft <<= 1, ++lvl) {
+            double* Rb = Q + buf * B;
+            Rb[k] = rhs;
+            __syncthreads();
+            rhs = rhs - T[UT_LVL + 2 * lvl] * Rb[(k - sft) & Bm] -
+                  T[UT_LVL + 2 * lvl + 1] * Rb[(k + sft) & Bm];
+            buf ^= 1;
+        }
+        double* Rb = Q + buf * B;
+        Rb[k] = rhs;
+        __syncthreads();
+        const double cb = T[UT_FIN], e = T[UT_FIN + 1], idet = T[UT_FIN + 2];
+        const int kn = (k + 1) & Bm, hb = B >> 1;
+        const double xk = (cb * rhs - e * Rb[(k + hb) & Bm]) * idet;
+        // the next chunk's first point, from the same two reduced rows
+        const double xn = (cb * Rb[kn] - e * Rb[(kn + hb) & Bm]) * idet;
+        X[k * (PT + 1)] = xk;
+#pragma unroll
+        for (int l = 1; l < PT; ++l)
+            X[k * (PT + 1) + l] = y[l] + T[UT_G + l] * xk + T[UT_H + l] * xn;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                const int i = gidx(r) + v;
+                z[r * VW + v] = X[(i / PT) * (PT + 1) + (i % PT)];
+            }
     }
 
     // first point of group r, and whether the group lies inside the grid
@@ -406,6 +542,11 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
 
     // z <- Op z (polynomial) or (I - gamma Op)^{-1} z (shift-and-invert).
     __device__ __forceinline__ void apply(double (&z)[PT], double gamma) {
+        if constexpr (SI && !VAR) {
+            (void)gamma;
+            ui_solve(z);
+            return;
+        }
         double* b0 = S.big;
         __syncthreads();  // previous users of `big` are done
 #pragma unroll
@@ -458,39 +599,6 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
                     }
                 }
             }
-        } else {
-            // Periodic cyclic reduction on a x_{i-1} + b x_i + c x_{i+1} = d_i
-            // with uniform coefficients: level s eliminates x_{i-s}, x_{i+s}
-            // using equations i-s and i+s; after log2(n)-1 levels equation i
-            // couples only x_i and x_{i+n/2}.
-            double* src = b0;
-            double* dst = b0 + n;
-            double ca = -gamma * a.op.lo, cb = 1.0 - gamma * a.op.d, cc = -gamma * a.op.up;
-            const int mask = n - 1;
-            for (int s = 1; 2 * s < n; s <<= 1) {
-                const double k1 = ca / cb, k2 = cc / cb;
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-#pragma unroll
-                    for (int v = 0; v < VW; ++v) {
-                        const int i = gidx(r) + v;
-                        dst[i] = src[i] - k1 * src[(i - s) & mask] - k2 * src[(i + s) & mask];
-                    }
-                const double na = -ca * k1, nc = -cc * k2, nb = cb - cc * k1 - ca * k2;
-                ca = na; cb = nb; cc = nc;
-                __syncthreads();
-                double* tmp = src; src = dst; dst = tmp;
-            }
-            const double e = ca + cc;
-            const double idet = 1.0 / (cb * cb - e * e);
-            const int hn = n >> 1;
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int v = 0; v < VW; ++v) {
-                    const int i = gidx(r) + v;
-                    z[r * VW + v] = (cb * src[i] - e * src[(i + hn) & mask]) * idet;
-                }
         }
     }
 
@@ -1479,7 +1587,8 @@ bool krylov_shape(int n, int block_hint, int* B, int* pt) {
 size_t krylov1d_lds_bytes(int n, int m, int block, int si) {
     (void)si;
     const int ldr = ((m + 1 + 7) / 8) * 8;
-    const size_t d = 64 + ldr + 8 + (size_t)(m + 1) * m + ldr + big_doubles(n, m, block);
+    const size_t d = 64 + ldr + 8 + (size_t)(m + 1) * m + ldr + UT_DOUBLES +
+                     big_doubles(n, m, block);
     return d * sizeof(double);
 }
 
@@ -1487,7 +1596,8 @@ size_t krylov2d_lds_bytes(int m) {
     const int ldr = ((m + 1 + 7) / 8) * 8;
     const size_t part = (size_t)(m + 1) * (KRYLOV2D_BLOCK / 64);
     const size_t sm = 6 * (size_t)m * m + 5 * (size_t)m + 8;
-    const size_t d = 64 + ldr + 8 + (size_t)(m + 1) * m + ldr + (part > sm ? part : sm);
+    const size_t d = 64 + ldr + 8 + (size_t)(m + 1) * m + ldr + UT_DOUBLES +
+                     (part > sm ? part : sm);
     return d * sizeof(double);
 }
 
