@@ -121,13 +121,35 @@ __device__ __forceinline__ void for_rc(int n, int ncol, F&& f) {
 }
 
 // C = A * B (n x n, leading dimension ld).  C must not alias A or B.
+// FP64 matrix-core tiles: each wave takes 16 x 16 tiles of C in turn and
+// accumulates them over k in steps of 4 with v_mfma_f64_16x16x4f64 (lane l
+// supplies A[row0 + l%16][k + l/16] and B[k + l/16][col0 + l%16] and holds
+// C[row0 + 4j + l/16][col0 + l%16], j < 4).  Entries past n are read as
+// zero and not written.  Every operand is read from LDS once per tile
+// instead of once per output element.
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ void sm_matmul(double* C, const double* A, const double* B,
                                  int n, int ld) {
-    for_rc(n, n, [&](int r, int c) {
-        double s = 0.0;
-        for (int k = 0; k < n; ++k) s += A[r * ld + k] * B[k * ld + c];
-        C[r * ld + c] = s;
-    });
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int nt = (n + 15) >> 4;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int q = threadIdx.x >> 6; q < nt * nt; q += nw) {
+        const int r0 = (q / nt) * 16, c0 = (q % nt) * 16;
+        const int ra = r0 + li, cb = c0 + li;
+        mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < n; k0 += 4) {
+            const int kk = k0 + lk;
+            const double av = (ra < n && kk < n) ? A[ra * ld + kk] : 0.0;
+            const double bv = (kk < n && cb < n) ? B[kk * ld + cb] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = r0 + 4 * j + lk;
+            if (r < n && cb < n) C[r * ld + cb] = acc[j];
+        }
+    }
     __syncthreads();
 }
 
