@@ -91,6 +91,44 @@ __host__ __device__ inline TriSplit split(Tri a) {
     return s;
 }
 
+// The forcing sin(omega t) (and the integral weight sin(ia + ib t)) at the
+// three stage times t_s, t_s + dt/2, t_s + dt of a step is the same for
+// every point: a block of SINE_BLK steps is tabulated into LDS by the whole
+// workgroup, one sine per thread instead of three per thread per step.  Two
+// tables alternate between blocks: a table is rewritten two blocks after it
+// was read, with at least one barrier per step in between.  The values are
+// the very expressions the march would evaluate.
+constexpr int SINE_BLK = 64;
+constexpr int SINE_LDS_DOUBLES = 2 * SINE_BLK * 6;
+
+// Fill the table of block `blk` (steps blk*SINE_BLK .. of the march whose
+// step s starts at time (step0 + s) dt), NV = 3 (forcing) or 6 (forcing and
+// integral weights); ends with a barrier.
+template <int NV>
+__device__ __forceinline__ const double* sine_block(double* tabs, int64_t blk, int64_t n_s,
+                                                    int64_t step0, double dt, double omega,
+                                                    double ia, double ib) {
+    double* tab = tabs + (blk & 1) * SINE_BLK * 6;
+    for (int e = threadIdx.x; e < SINE_BLK * NV; e += blockDim.x) {
+        const int ls = e / NV, v = e - ls * NV;
+        const int64_t s = blk * SINE_BLK + ls;
+        if (s >= n_s) continue;
+        const double tn = (double)(step0 + s) * dt;
+        double val;
+        switch (v) {
+            case 0: val = sin(omega * tn); break;
+            case 1: val = sin(omega * (tn + 0.5 * dt)); break;
+            case 2: val = sin(omega * (tn + dt)); break;
+            case 3: val = sin(ia + ib * tn); break;
+            case 4: val = sin(ia + ib * (tn + 0.5 * dt)); break;
+            default: val = sin(ia + ib * (tn + dt)); break;
+        }
+        tab[ls * 6 + v] = val;
+    }
+    __syncthreads();
+    return tab;
+}
+
 template <int PT, typename R>
 __device__ __forceinline__ void tri_rhs(const R (&Y)[PT], R l, R r, R cs, R cdf,
                                         R cc, R (&k)[PT]) {
@@ -129,16 +167,20 @@ dev_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
     double I[PT];
 #pragma unroll
     for (int q = 0; q < PT; ++q) I[q] = 0.0;
+    double* tabs = lds_d + 4 * (size_t)blockDim.x;
+    const double* tab = nullptr;
     for (int64_t s = 0; s < n_s; ++s) {
-        const double tn = (double)(step0 + s) * dt;
-        const R s1 = (R)sin(omega * tn);
-        const R s2 = (R)sin(omega * (tn + 0.5 * dt));
-        const R s4 = (R)sin(omega * (tn + dt));
+        if (s % SINE_BLK == 0)
+            tab = sine_block<INT ? 6 : 3>(tabs, s / SINE_BLK, n_s, step0, dt, omega, si.ia, si.ib);
+        const double* sv = tab + (s % SINE_BLK) * 6;
+        const R s1 = (R)sv[0];
+        const R s2 = (R)sv[1];
+        const R s4 = (R)sv[2];
         double w1 = 0.0, w2 = 0.0, w4 = 0.0;
         if constexpr (INT) {
-            w1 = dt / 6.0 * sin(si.ia + si.ib * tn);
-            w2 = dt / 3.0 * sin(si.ia + si.ib * (tn + 0.5 * dt));
-            w4 = dt / 6.0 * sin(si.ia + si.ib * (tn + dt));
+            w1 = dt / 6.0 * sv[3];
+            w2 = dt / 3.0 * sv[4];
+            w4 = dt / 6.0 * sv[5];
 #pragma unroll
             for (int q = 0; q < PT; ++q) I[q] += w1 * hilo<R>(y[q], yc[q]);
         }
@@ -249,11 +291,15 @@ k_rk4_rev_lin1d(const double* __restrict__ lamT, double* __restrict__ lam0,
     }
     int buf = 0;
     const R d6 = (R)(dt / 6.0), d3 = (R)(dt / 3.0), d2 = (R)(0.5 * dt), d1 = (R)dt;
+    double* tabs = lds_d + 4 * (size_t)blockDim.x;
+    const double* tab = nullptr;
     for (int64_t s = n_t - 1; s >= 0; --s) {
-        const double tn = (double)s * dt;
-        const R s1 = (R)sin(omega * tn);
-        const R s2 = (R)sin(omega * (tn + 0.5 * dt));
-        const R s4 = (R)sin(omega * (tn + dt));
+        if (s == n_t - 1 || s % SINE_BLK == SINE_BLK - 1)
+            tab = sine_block<3>(tabs, s / SINE_BLK, n_t, 0, dt, omega, 0.0, 0.0);
+        const double* sv = tab + (s % SINE_BLK) * 6;
+        const R s1 = (R)sv[0];
+        const R s2 = (R)sv[1];
+        const R s4 = (R)sv[2];
         R l[1], r[1];
         // stage 4
 #pragma unroll
@@ -752,7 +798,7 @@ hipError_t launch_rk4_lin1d(const double* F, const double* g0, const double* y0,
                             hipStream_t s, SliceIntegral si) {
     int block, pt;
     if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
-    const size_t lds = sizeof(double) * 4 * block;
+    const size_t lds = sizeof(double) * (4 * block + SINE_LDS_DOUBLES);
     const TriSplit sp = split(A);
     if (si.iout) {
         PXP_DISPATCH(fp32, pt, k_rk4_lin1d_int,
@@ -770,7 +816,7 @@ hipError_t launch_rk4_rev_lin1d(const double* lamT, double* lam0,
                                 hipStream_t s) {
     int block, pt;
     if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
-    const size_t lds = sizeof(double) * 4 * block;
+    const size_t lds = sizeof(double) * (4 * block + SINE_LDS_DOUBLES);
     const TriSplit sp = split(AT);
     PXP_DISPATCH(fp32, pt, k_rk4_rev_lin1d,
                  <<<1, block, lds, s>>>(lamT, lam0, Lambda, n, n_t, dt, omega, sp))
