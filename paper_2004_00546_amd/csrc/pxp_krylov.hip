@@ -513,18 +513,23 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
     __device__ __forceinline__ int gidx(int r) const { return (t + r * B) * VW; }
     __device__ __forceinline__ bool own(int r) const { return gidx(r) < n; }
 
-    // x[r*VW + v] = src[gidx(r) + v] (global, 16-byte loads when VW == 2)
+    // x[r*VW + v] = src[gidx(r) + v] (global, 16-byte loads when VW == 2).
+    // Groups past the grid read point 0 and yield zero: the loads carry no
+    // branches, so a caller's loads of several vectors are all in flight
+    // together.
     __device__ __forceinline__ void gload(const double* __restrict__ src,
                                           double (&x)[PT]) const {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+            const bool o = own(r);
+            const int g = o ? gidx(r) : 0;
             if (VW == 2) {
-                double2 v = own(r) ? *reinterpret_cast<const double2*>(src + gidx(r))
-                                   : make_double2(0.0, 0.0);
-                x[2 * r] = v.x;
-                x[2 * r + 1] = v.y;
+                const double2 v = *reinterpret_cast<const double2*>(src + g);
+                x[2 * r] = o ? v.x : 0.0;
+                x[2 * r + 1] = o ? v.y : 0.0;
             } else {
-                x[r] = own(r) ? src[gidx(r)] : 0.0;
+                const double v = src[g];
+                x[r] = o ? v : 0.0;
             }
         }
     }
@@ -887,17 +892,18 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
         const int g = lane / GS;
         __syncthreads();
         for (int k0 = 0; k0 <= j; k0 += KD) {
+            // all KD vectors' loads are issued before the first is used;
+            // past V_j the index is clamped to j and the sum discarded
+            double x[KD][PT];
+#pragma unroll
+            for (int q = 0; q < KD; ++q) gload(V + (size_t)(k0 + q <= j ? k0 + q : j) * n, x[q]);
             double part[KD];
 #pragma unroll
             for (int q = 0; q < KD; ++q) {
                 double s = 0.0;
-                if (k0 + q <= j) {
-                    double x[PT];
-                    gload(V + (size_t)(k0 + q) * n, x);
 #pragma unroll
-                    for (int u = 0; u < PT; ++u) s += x[u] * z[u];
-                }
-                part[q] = s;
+                for (int u = 0; u < PT; ++u) s += x[q][u] * z[u];
+                part[q] = (k0 + q <= j) ? s : 0.0;
             }
             halve<KD, 32>(part, lane);
             double s = part[0];
@@ -914,16 +920,20 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
         __syncthreads();
     }
 
-    // z -= sum_{k<=j} hcol[k] V_k
+    // z -= sum_{k<=j} hcol[k] V_k, UK vectors' loads in flight at a time
+    // (past V_j the index is clamped and the coefficient is zero)
     __device__ __forceinline__ void subtract(double (&z)[PT], int j) {
         constexpr int UK = (PT >= 16) ? 2 : 4;
-#pragma unroll UK
-        for (int k = 0; k <= j; ++k) {
-            const double h = S.hcol[k];
-            double x[PT];
-            gload(V + (size_t)k * n, x);
+        for (int k0 = 0; k0 <= j; k0 += UK) {
+            double x[UK][PT];
 #pragma unroll
-            for (int u = 0; u < PT; ++u) z[u] -= h * x[u];
+            for (int q = 0; q < UK; ++q) gload(V + (size_t)(k0 + q <= j ? k0 + q : j) * n, x[q]);
+#pragma unroll
+            for (int q = 0; q < UK; ++q) {
+                const double h = (k0 + q <= j) ? S.hcol[k0 + q] : 0.0;
+#pragma unroll
+                for (int u = 0; u < PT; ++u) z[u] -= h * x[q][u];
+            }
         }
     }
 
