@@ -125,7 +125,12 @@ pxp_status pxp_workspace_size(const pxp_problem* pb, int32_t batch,
                               size_t* bytes);
 
 /* Zero the device status block at the start of a fresh workspace (enqueued
- * on `stream` as a kernel).  Call once after allocating `ws`. */
+ * on `stream` as a kernel).  Call once after allocating `ws`, outside any
+ * stream capture: on its first call on a device it also creates the
+ * library's side stream there (default priority, non-blocking) and two
+ * events, which the compute calls use to run independent launch groups of
+ * one phase concurrently (fork and join by events on the caller's stream).
+ * Without it the groups run one after the other on the caller's stream. */
 pxp_status pxp_workspace_init(void* ws, size_t ws_bytes, void* stream);
 
 /* Direct solve (section 3.1, eqs. linInhomEqus, hom, fullsol0):

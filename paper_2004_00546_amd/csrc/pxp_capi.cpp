@@ -8,6 +8,7 @@
 #include <complex>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/paraexp.h"
@@ -305,6 +306,41 @@ pxp_status check_all(const pxp_problem* pb, int batch) {
     do {                                        \
         if ((x) != hipSuccess) return PXP_EHIP; \
     } while (0)
+
+// ---- side stream: independent launch groups of one phase run concurrently --
+// One non-blocking stream (default priority) and two events per device,
+// created by pxp_workspace_init, outside any stream capture.  A call forks
+// onto the side stream with an event recorded on its own stream and joins
+// back with another; a stream capture records both as graph dependencies.
+// The enqueue of a fork/join is serialised by a mutex so that concurrent
+// host threads never interleave the event records and waits.
+struct SideStream {
+    hipStream_t st = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_side_mu;
+static SideStream g_side[MAX_DEVICES];
+
+static void side_init() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    SideStream& ss = g_side[dev];
+    if (ss.st) return;
+    hipStream_t st = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
+    if (hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
+        if (a) (void)hipEventDestroy(a);
+        (void)hipStreamDestroy(st);
+        return;
+    }
+    ss.st = st;
+    ss.fork = a;
+    ss.join = b;
+}
 
 // Optional launch timing: when enabled, every launch of a kernel class is
 // bracketed by two events recorded on the launch stream.  Host-side state,
@@ -742,11 +778,34 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
         HIPCHK(launch_burgers_batch(2, dtab, (int)tab.size(), q0, bb.fp32, s));
     }
     ProfScope ps(PXP_K_LTV_ADJOINT, s);
+    // the first group on the caller's stream, the others on the side stream
+    // (when it exists) so that the groups' chains run concurrently
+    int dev = 0;
+    SideStream side;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < MAX_DEVICES) {
+        std::lock_guard<std::mutex> copy(g_side_mu);
+        side = g_side[dev];
+    }
+    std::unique_lock<std::mutex> lock(g_side_mu, std::defer_lock);
+    const bool groups = !order.empty() && kB[order.front()] != kB[order.back()];
+    const bool forked = groups && side.st;
+    if (forked) {
+        // the side stream starts where the caller's stream is now: before
+        // the first group is enqueued
+        lock.lock();
+        HIPCHK(hipEventRecord(side.fork, s));
+        HIPCHK(hipStreamWaitEvent(side.st, side.fork, 0));
+    }
     for (size_t j0 = 0; j0 < order.size();) {
         size_t j1 = j0;
         while (j1 < order.size() && kB[order[j1]] == kB[order[j0]]) ++j1;
-        HIPCHK(launch_krylov_ltv_batch(kt + j0, kB[order[j0]], (int)(j1 - j0), lds, s));
+        const hipStream_t sg = (j0 > 0 && forked) ? side.st : s;
+        HIPCHK(launch_krylov_ltv_batch(kt + j0, kB[order[j0]], (int)(j1 - j0), lds, sg));
         j0 = j1;
+    }
+    if (forked) {
+        HIPCHK(hipEventRecord(side.join, side.st));
+        HIPCHK(hipStreamWaitEvent(s, side.join, 0));
     }
     return PXP_OK;
 }
@@ -1037,6 +1096,7 @@ pxp_status pxp_workspace_size(const pxp_problem* pb, int32_t batch,
 
 pxp_status pxp_workspace_init(void* ws, size_t ws_bytes, void* stream) {
     if (!ws || ws_bytes < sizeof(DevStatus)) return PXP_EWORKSPACE;
+    side_init();
     if (launch_zero(static_cast<double*>(ws), sizeof(DevStatus) / sizeof(double),
                     static_cast<hipStream_t>(stream)) != hipSuccess)
         return PXP_EHIP;

@@ -86,3 +86,38 @@ def test_graph_replay_equals_eager(torch, wl, krylov):
         # eager work between replays
         r.run()
         torch.cuda.synchronize()
+
+
+def test_graph_replay_two_launch_groups(torch):
+    """A ragged Burgers batch whose Magnus chains need two workgroup sizes
+    (N=8192 at 256 threads, N<=2048 at 512): the second launch group runs on
+    the library's side stream, forked and joined by events.  A captured
+    graph must replay the whole gradient exactly, with eager work between
+    the replays."""
+    full = workloads.make("burgers1d_ragged")
+    big = min((x for x in full if x["nx"] == 8192), key=lambda x: x["n_steps"])
+    small = min((x for x in full if x["nx"] <= 2048), key=lambda x: x["n_steps"])
+    r = api.GradientRunner([small, big], krylov="auto", tol=1e-9)
+    r.run()
+    eager = r.results()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        r.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        r.run()
+    for rep in range(3):
+        r.J.zero_()
+        r.grad.zero_()
+        r.qT.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for got, want in zip(r.results(), eager):
+            assert np.array_equal(got["grad"], want["grad"]), rep
+            assert np.array_equal(got["qT"], want["qT"]), rep
+        r.run()
+        torch.cuda.synchronize()
