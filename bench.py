@@ -68,11 +68,6 @@ def profiled_traffic(kernel_key):
     return None
 
 
-def m_is_full(inst):
-    # shift-and-invert spaces always run to the full dimension m
-    return True
-
-
 def warm(torch, r, count, seconds):
     """Untimed calls: at least `count`, and until `seconds` have passed."""
     t0 = time.perf_counter()
@@ -386,7 +381,8 @@ def roofline(kern, insts, args, substeps, iters, problems, reorth=0):
                     frac=ach / peak, traffic=None, avg_launch_ms=kern[top]["avg_ms"])
     if top in ("ltv_adjoint", "krylov_adjoint", "krylov_direct"):
         # bytes streamed by the Arnoldi steps actually taken (device counters):
-        # step j of a space reads j+1 basis vectors four times and writes one
+        # step j of a space reads j+1 basis vectors twice per Gram-Schmidt
+        # pass (passes from the device's second-pass counter) and writes one
         sp = substeps / max(1, args.steps)
         it = iters / max(1, args.steps)
         mm = it / max(sp, 1.0)
