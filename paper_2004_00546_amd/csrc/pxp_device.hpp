@@ -39,6 +39,32 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return s;
 }
 
+// Two sums over the block with a single barrier.  `red` is LDS scratch of
+// at least 80 doubles; the sums go to one of two slots (red + 16 and
+// red + 48, 32 doubles each, so at most 16 waves), and `slot` alternates
+// between calls: a call never overwrites the slot that a slower thread may
+// still be reading from the previous call, and neither slot overlaps the
+// first 16 doubles that block_sum uses.  Every thread gets both totals.
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* red, int& slot) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    double* r = red + 16 + 32 * slot;
+    if (lane_id() == 0) {
+        r[wave_id()] = a;
+        r[16 + wave_id()] = b;
+    }
+    __syncthreads();
+    double sa = 0.0, sb = 0.0;
+    const int nw = num_waves();
+    for (int w = 0; w < nw; ++w) {
+        sa += r[w];
+        sb += r[16 + w];
+    }
+    a = sa;
+    b = sb;
+    slot ^= 1;
+}
+
 __device__ __forceinline__ double block_max(double v, double* red) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));

@@ -69,7 +69,7 @@ __host__ __device__ constexpr int krylov_max_block(int pt) {
 }
 
 struct Smem {
-    double* red;   // num_waves * ldr (ldr = m+1 rounded up to 8)
+    double* red;   // 128: block reductions (block_sum, block_sum2)
     double* hcol;  // ldr + 8
     double* H;     // (m+1) x m, ld = m
     double* yprev; // m: the previous shift-and-invert check's approximation
@@ -109,7 +109,7 @@ struct Core {
         : a(a_), n(a_.n), m(a_.m), B(blockDim.x), t(threadIdx.x) {
         ldr = ((m + 1 + 7) / 8) * 8;
         S.red = lds;
-        S.hcol = S.red + 64;
+        S.hcol = S.red + 128;
         S.H = S.hcol + ldr + 8;
         S.yprev = S.H + (size_t)(m + 1) * m;
         S.ut = S.yprev + ldr;
@@ -819,26 +819,42 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
                     sum[q] = u[q];
                     I[q] += J0 * u[q];
                 }
+                // terms in pairs: both norms in one reduction.  The stop
+                // test of each term is the one of the single-term loop
+                // (two consecutive term norms below tol |u|); stopping at
+                // the first of a pair keeps its second term as well.
                 double prev = nu;
                 bool conv = false;
-                for (int k = 1; k <= a.tdeg; ++k) {
-                    apply(tk, 0.0);
-                    const double f = h / k;
-                    const double Jk = iout ? Base::taylor_weight(k, h, ph, ib) : 0.0;
+                int slot = 0;
+                for (int k = 1; k <= a.tdeg; k += 2) {
+                    const bool two = k + 1 <= a.tdeg;
+                    double s1, s2 = 0.0;
+                    for (int e = 0; e < (two ? 2 : 1); ++e) {
+                        apply(tk, 0.0);
+                        const double f = h / (k + e);
+                        const double Jk = iout ? Base::taylor_weight(k + e, h, ph, ib) : 0.0;
 #pragma unroll
-                    for (int q = 0; q < PT; ++q) {
-                        tk[q] *= f;
-                        sum[q] += tk[q];
-                        I[q] += Jk * tk[q];
+                        for (int q = 0; q < PT; ++q) {
+                            tk[q] *= f;
+                            sum[q] += tk[q];
+                            I[q] += Jk * tk[q];
+                        }
+                        (e == 0 ? s1 : s2) = sumsq(tk);
                     }
-                    const double nt = sqrt(block_sum(sumsq(tk), S.red));
-                    ++terms;
-                    if (prev + nt <= a.tol * nu) {
+                    block_sum2(s1, s2, S.red, slot);
+                    const double n1 = sqrt(s1), n2 = sqrt(s2);
+                    terms += two ? 2 : 1;
+                    if (prev + n1 <= a.tol * nu) {
                         conv = true;
-                        worst = fmax(worst, (prev + nt) / nu);
+                        worst = fmax(worst, (prev + n1) / nu);
                         break;
                     }
-                    prev = nt;
+                    if (two && n1 + n2 <= a.tol * nu) {
+                        conv = true;
+                        worst = fmax(worst, (n1 + n2) / nu);
+                        break;
+                    }
+                    prev = two ? n2 : n1;
                 }
                 if (!conv) noconv = true;
 #pragma unroll
@@ -1597,7 +1613,7 @@ bool krylov_shape(int n, int block_hint, int* B, int* pt) {
 size_t krylov1d_lds_bytes(int n, int m, int block, int si) {
     (void)si;
     const int ldr = ((m + 1 + 7) / 8) * 8;
-    const size_t d = 64 + ldr + 8 + (size_t)(m + 1) * m + ldr + UT_DOUBLES +
+    const size_t d = 128 + ldr + 8 + (size_t)(m + 1) * m + ldr + UT_DOUBLES +
                      big_doubles(n, m, block);
     return d * sizeof(double);
 }
@@ -1606,7 +1622,7 @@ size_t krylov2d_lds_bytes(int m) {
     const int ldr = ((m + 1 + 7) / 8) * 8;
     const size_t part = (size_t)(m + 1) * (KRYLOV2D_BLOCK / 64);
     const size_t sm = 6 * (size_t)m * m + 5 * (size_t)m + 8;
-    const size_t d = 64 + ldr + 8 + (size_t)(m + 1) * m + ldr + UT_DOUBLES +
+    const size_t d = 128 + ldr + 8 + (size_t)(m + 1) * m + ldr + UT_DOUBLES +
                      (part > sm ? part : sm);
     return d * sizeof(double);
 }
