@@ -75,6 +75,15 @@ enum { PXP_FP64 = 0, PXP_FP32_BULK = 1 };
  * (eq. initupdate). */
 enum { PXP_CTRL_FORCING = 0, PXP_CTRL_IC = 1 };
 /* Krylov flavour for the homogeneous exponentials. */
+/* POLY: Arnoldi on A; time substeps accepted by the a-posteriori estimate
+ * beta h_{k+1,k} |e_k^T exp(ts H_k) e_1| <= krylov_tol beta ts/tau, with an
+ * early exit every 4 dimensions from 8 on. */
+/* SHIFT_INVERT: Arnoldi on (I - gamma A)^{-1}, gamma = si_gamma times the
+ * exponential's time, one step over the whole time.  From about m/2 the
+ * approximation is compared with the previous check's; the error is
+ * extrapolated from the contraction of those differences and the space stops
+ * once it is below krylov_tol (relative to |v|).  Both Arnoldi flavours use
+ * classical Gram-Schmidt with a second pass only on tenfold cancellation. */
 /* AUTO: shift-and-invert when tau * rho > 64 (rho = 4 nu/h^2 + |vx|/h, tau
  * the horizon for the linear pieces or half a slice for the Burgers Magnus
  * factors) and the grid has the cyclic-reduction shape, else TAYLOR. */
@@ -211,7 +220,7 @@ pxp_status pxp_device_status(void* ws, size_t ws_bytes, void* stream,
 /* Synchronises `stream` and reads the accumulated Krylov counters of the
  * workspace: accepted substeps, Arnoldi iterations, and Arnoldi iterations
  * that took a second Gram-Schmidt pass (classical Gram-Schmidt reruns only
- * when the first pass removed more than half of the vector's squared norm),
+ * when the first pass left less than a tenth of the vector's norm),
  * over all pieces since the workspace was initialised (host outputs,
  * nullable). */
 pxp_status pxp_device_counters(void* ws, size_t ws_bytes, void* stream,
