@@ -50,6 +50,14 @@ constexpr int UT_DOUBLES = 168;
 // approximation tolerates the orthogonality lost at milder cancellation.
 constexpr double DGKS_ETA2 = 0.01;  // eta^2
 
+// Basis vectors per batch of the Gram-Schmidt sweeps: a batch holds at most
+// 32 doubles per thread in flight (sixteen 16-byte loads), so threads with
+// many points take fewer vectors at a time and stay within their registers.
+template <int PT>
+constexpr int sweep_batch(int cap) {
+    return (32 / PT) < 1 ? 1 : ((32 / PT) > cap ? cap : (32 / PT));
+}
+
 __host__ __device__ inline size_t big_doubles(int n, int m, int block) {
     size_t vec = 2 * (size_t)n;
     // variable-coefficient solve: padded chunks (n + B) and 8 B for the
@@ -874,8 +882,8 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
         }
     }
 
-    // hcol[k] = <V_k, z> for k <= j, KD basis vectors at a time (8, or 4
-    // when a thread owns 8 or more points).  The KD per-thread partial sums
+    // hcol[k] = <V_k, z> for k <= j, KD basis vectors at a time (at most
+    // 8, and at most 32 doubles per thread: sweep_batch).  The KD per-thread partial sums
     // are reduced inside the wave by recursive halving (log2 KD exchange
     // stages leave lane group g = lane / (64/KD) holding vector g, the
     // remaining stages sum within the group); one lane per group writes the
@@ -901,7 +909,7 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
     }
 
     __device__ __forceinline__ void dots(const double (&z)[PT], int j) {
-        constexpr int KD = (PT >= 8) ? 4 : 8;
+        constexpr int KD = sweep_batch<PT>(8);
         constexpr int GS = WAVE / KD;  // lanes per group after the exchanges
         double* P = S.big;
         const int nw = num_waves(), w = wave_id(), lane = lane_id();
@@ -939,7 +947,7 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
     // z -= sum_{k<=j} hcol[k] V_k, UK vectors' loads in flight at a time
     // (past V_j the index is clamped and the coefficient is zero)
     __device__ __forceinline__ void subtract(double (&z)[PT], int j) {
-        constexpr int UK = (PT >= 16) ? 2 : 4;
+        constexpr int UK = sweep_batch<PT>(4);
         for (int k0 = 0; k0 <= j; k0 += UK) {
             double x[UK][PT];
 #pragma unroll
