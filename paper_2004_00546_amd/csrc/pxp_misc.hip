@@ -16,9 +16,15 @@ __global__ void k_combine_basis(const double* __restrict__ a,
                                 double* __restrict__ out, int K, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double s = base ? base[i] : 0.0;
-    for (int k = 0; k < K; ++k) s += a[k] * basis[(size_t)k * n + i];
-    out[i] = s;
+    // four independent partial sums (fixed order) keep several loads in
+    // flight instead of one dependent chain
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = 0;
+    for (; k + 4 <= K; k += 4)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s[u] += a[k + u] * basis[(size_t)(k + u) * n + i];
+    for (; k < K; ++k) s[0] += a[k] * basis[(size_t)k * n + i];
+    out[i] = (base ? base[i] : 0.0) + ((s[0] + s[1]) + (s[2] + s[3]));
 }
 
 __global__ void k_apply_tri(const double* __restrict__ x, double* __restrict__ out,
@@ -69,9 +75,15 @@ __global__ void k_recombine(const double* __restrict__ q0,
                             double* __restrict__ out, DevStatus* st) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    int p = 0;
+    for (; p + 4 <= np; p += 4)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t[u] += Y[(size_t)(p + u) * n + i];
+    for (; p < np; ++p) t[0] += Y[(size_t)p * n + i];
     double s = q0 ? q0[i] : 0.0;
     if (vlast) s += vlast[i];
-    for (int p = 0; p < np; ++p) s += Y[(size_t)p * n + i];
+    s += (t[0] + t[1]) + (t[2] + t[3]);
     out[i] = s;
     if (st && !isfinite(s)) atomicOr(&st->flags, ST_NONFINITE);
 }
@@ -90,7 +102,7 @@ inline int blocks(int n, int b) { return (n + b - 1) / b; }
 hipError_t launch_combine_basis(const double* a, const double* basis,
                                 const double* base, double* out, int K, int n,
                                 hipStream_t s) {
-    k_combine_basis<<<blocks(n, 256), 256, 0, s>>>(a, basis, base, out, K, n);
+    k_combine_basis<<<blocks(n, 64), 64, 0, s>>>(a, basis, base, out, K, n);
     return hipGetLastError();
 }
 
@@ -117,7 +129,7 @@ hipError_t launch_grad(const double* basis, const double* v, const double* a,
 hipError_t launch_recombine(const double* q0, const double* vlast,
                             const double* Y, int np, int n, double* out,
                             DevStatus* st, hipStream_t s) {
-    k_recombine<<<blocks(n, 256), 256, 0, s>>>(q0, vlast, Y, np, n, out, st);
+    k_recombine<<<blocks(n, 64), 64, 0, s>>>(q0, vlast, Y, np, n, out, st);
     return hipGetLastError();
 }
 
