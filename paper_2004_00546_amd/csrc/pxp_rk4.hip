@@ -129,18 +129,23 @@ __device__ __forceinline__ const double* sine_block(double* tabs, int64_t blk, i
     return tab;
 }
 
-template <int PT, typename R>
+// CC = false: the operator has cc == 0 (central advection-diffusion, where
+// lo + d + up = 0 exactly), and the term, exactly zero, is not formed.
+template <int PT, typename R, bool CC = true>
 __device__ __forceinline__ void tri_rhs(const R (&Y)[PT], R l, R r, R cs, R cdf,
                                         R cc, R (&k)[PT]) {
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
         const R ym = (q == 0) ? l : Y[q - 1];
         const R yp = (q == PT - 1) ? r : Y[q + 1];
-        k[q] = cs * ((yp + ym) - (R)2 * Y[q]) + cdf * (yp - ym) + cc * Y[q];
+        if constexpr (CC)
+            k[q] = cs * ((yp + ym) - (R)2 * Y[q]) + cdf * (yp - ym) + cc * Y[q];
+        else
+            k[q] = cs * ((yp + ym) - (R)2 * Y[q]) + cdf * (yp - ym);
     }
 }
 
-template <int PT, typename R, bool INT>
+template <int PT, typename R, bool INT, bool CC = true>
 __device__ __forceinline__ void
 dev_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
               const double* __restrict__ y0, double* __restrict__ out, int n,
@@ -189,7 +194,7 @@ dev_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
             const R* arr[1] = {y};
             exch<PT, 1>(arr, lds, buf, l, r);
         }
-        tri_rhs<PT, R>(y, l[0], r[0], cs, cdf, cc, k);
+        tri_rhs<PT, R, CC>(y, l[0], r[0], cs, cdf, cc, k);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
             k[q] += s1 * f[q] + g[q];
@@ -204,7 +209,7 @@ dev_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
             const R* arr[1] = {Y};
             exch<PT, 1>(arr, lds, buf, l, r);
         }
-        tri_rhs<PT, R>(Y, l[0], r[0], cs, cdf, cc, k);
+        tri_rhs<PT, R, CC>(Y, l[0], r[0], cs, cdf, cc, k);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
             k[q] += s2 * f[q] + g[q];
@@ -219,7 +224,7 @@ dev_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
             const R* arr[1] = {Y};
             exch<PT, 1>(arr, lds, buf, l, r);
         }
-        tri_rhs<PT, R>(Y, l[0], r[0], cs, cdf, cc, k);
+        tri_rhs<PT, R, CC>(Y, l[0], r[0], cs, cdf, cc, k);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
             k[q] += s2 * f[q] + g[q];
@@ -234,7 +239,7 @@ dev_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
             const R* arr[1] = {Y};
             exch<PT, 1>(arr, lds, buf, l, r);
         }
-        tri_rhs<PT, R>(Y, l[0], r[0], cs, cdf, cc, k);
+        tri_rhs<PT, R, CC>(Y, l[0], r[0], cs, cdf, cc, k);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
             k[q] += s4 * f[q] + g[q];
@@ -268,15 +273,23 @@ k_rk4_lin1d_int(const double* __restrict__ F, const double* __restrict__ g0,
                 int64_t n_s, double dt, double omega, TriSplit A, SliceIntegral si) {
     dev_rk4_lin1d<PT, R, true>(F, g0, y0, out, n, n_s, dt, omega, A, si);
 }
+// plain march of an operator with cc == 0 (see tri_rhs)
+template <int PT, typename R>
+__global__ void __launch_bounds__(max_block<PT>())
+k_rk4_lin1d_nocc(const double* __restrict__ F, const double* __restrict__ g0,
+                 const double* __restrict__ y0, double* __restrict__ out, int n,
+                 int64_t n_s, double dt, double omega, TriSplit A, SliceIntegral si) {
+    dev_rk4_lin1d<PT, R, false, false>(F, g0, y0, out, n, n_s, dt, omega, A, si);
+}
 
 // Reverse sweep: y_{s+1} = y_s + dt sum_i b_i k_i with k_i = A Y_i + ...
 // gives kbar_i = dt b_i lam (+ the chain through later stages), Ybar_i =
 // A^T kbar_i, lam_s = lam_{s+1} + sum_i Ybar_i, Lambda += s(t_i) kbar_i.
-template <int PT, typename R>
-__global__ void __launch_bounds__(max_block<PT>())
-k_rk4_rev_lin1d(const double* __restrict__ lamT, double* __restrict__ lam0,
-                double* __restrict__ Lambda, int n, int64_t n_t, double dt,
-                double omega, TriSplit AT) {
+template <int PT, typename R, bool CC>
+__device__ __forceinline__ void
+dev_rk4_rev_lin1d(const double* __restrict__ lamT, double* __restrict__ lam0,
+                  double* __restrict__ Lambda, int n, int64_t n_t, double dt,
+                  double omega, TriSplit AT) {
     extern __shared__ double lds_d[];
     R* lds = reinterpret_cast<R*>(lds_d);
     const int t = threadIdx.x;
@@ -308,7 +321,7 @@ k_rk4_rev_lin1d(const double* __restrict__ lamT, double* __restrict__ lam0,
             const R* arr[1] = {kb};
             exch<PT, 1>(arr, lds, buf, l, r);
         }
-        tri_rhs<PT, R>(kb, l[0], r[0], cs, cdf, cc, Yb);
+        tri_rhs<PT, R, CC>(kb, l[0], r[0], cs, cdf, cc, Yb);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
             nl[q] = Yb[q];
@@ -320,7 +333,7 @@ k_rk4_rev_lin1d(const double* __restrict__ lamT, double* __restrict__ lam0,
             const R* arr[1] = {kb};
             exch<PT, 1>(arr, lds, buf, l, r);
         }
-        tri_rhs<PT, R>(kb, l[0], r[0], cs, cdf, cc, Yb);
+        tri_rhs<PT, R, CC>(kb, l[0], r[0], cs, cdf, cc, Yb);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
             nl[q] += Yb[q];
@@ -332,7 +345,7 @@ k_rk4_rev_lin1d(const double* __restrict__ lamT, double* __restrict__ lam0,
             const R* arr[1] = {kb};
             exch<PT, 1>(arr, lds, buf, l, r);
         }
-        tri_rhs<PT, R>(kb, l[0], r[0], cs, cdf, cc, Yb);
+        tri_rhs<PT, R, CC>(kb, l[0], r[0], cs, cdf, cc, Yb);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
             nl[q] += Yb[q];
@@ -344,7 +357,7 @@ k_rk4_rev_lin1d(const double* __restrict__ lamT, double* __restrict__ lam0,
             const R* arr[1] = {kb};
             exch<PT, 1>(arr, lds, buf, l, r);
         }
-        tri_rhs<PT, R>(kb, l[0], r[0], cs, cdf, cc, Yb);
+        tri_rhs<PT, R, CC>(kb, l[0], r[0], cs, cdf, cc, Yb);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
             kadd<R>(Lam[q], Lamc[q], s1 * kb[q]);
@@ -356,6 +369,21 @@ k_rk4_rev_lin1d(const double* __restrict__ lamT, double* __restrict__ lam0,
         if (lam0) lam0[base + q] = hilo<R>(lam[q], lamc[q]);
         if (Lambda) Lambda[base + q] = hilo<R>(Lam[q], Lamc[q]);
     }
+}
+
+template <int PT, typename R>
+__global__ void __launch_bounds__(max_block<PT>())
+k_rk4_rev_lin1d(const double* __restrict__ lamT, double* __restrict__ lam0,
+                double* __restrict__ Lambda, int n, int64_t n_t, double dt,
+                double omega, TriSplit AT) {
+    dev_rk4_rev_lin1d<PT, R, true>(lamT, lam0, Lambda, n, n_t, dt, omega, AT);
+}
+template <int PT, typename R>
+__global__ void __launch_bounds__(max_block<PT>())
+k_rk4_rev_lin1d_nocc(const double* __restrict__ lamT, double* __restrict__ lam0,
+                     double* __restrict__ Lambda, int n, int64_t n_t, double dt,
+                     double omega, TriSplit AT) {
+    dev_rk4_rev_lin1d<PT, R, false>(lamT, lam0, Lambda, n, n_t, dt, omega, AT);
 }
 
 // ---- Burgers: N(u)_i = -u_i (u_{i+1} - u_{i-1})/(2h) + nu lap(u)_i -------
@@ -803,6 +831,9 @@ hipError_t launch_rk4_lin1d(const double* F, const double* g0, const double* y0,
     if (si.iout) {
         PXP_DISPATCH(fp32, pt, k_rk4_lin1d_int,
                      <<<P, block, lds, s>>>(F, g0, y0, out, n, n_s, dt, omega, sp, si))
+    } else if (sp.cc == 0.0) {
+        PXP_DISPATCH(fp32, pt, k_rk4_lin1d_nocc,
+                     <<<P, block, lds, s>>>(F, g0, y0, out, n, n_s, dt, omega, sp, si))
     } else {
         PXP_DISPATCH(fp32, pt, k_rk4_lin1d_plain,
                      <<<P, block, lds, s>>>(F, g0, y0, out, n, n_s, dt, omega, sp, si))
@@ -818,8 +849,13 @@ hipError_t launch_rk4_rev_lin1d(const double* lamT, double* lam0,
     if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
     const size_t lds = sizeof(double) * (4 * block + SINE_LDS_DOUBLES);
     const TriSplit sp = split(AT);
-    PXP_DISPATCH(fp32, pt, k_rk4_rev_lin1d,
-                 <<<1, block, lds, s>>>(lamT, lam0, Lambda, n, n_t, dt, omega, sp))
+    if (sp.cc == 0.0) {
+        PXP_DISPATCH(fp32, pt, k_rk4_rev_lin1d_nocc,
+                     <<<1, block, lds, s>>>(lamT, lam0, Lambda, n, n_t, dt, omega, sp))
+    } else {
+        PXP_DISPATCH(fp32, pt, k_rk4_rev_lin1d,
+                     <<<1, block, lds, s>>>(lamT, lam0, Lambda, n, n_t, dt, omega, sp))
+    }
     return hipGetLastError();
 }
 
