@@ -61,9 +61,12 @@ class GradientRunner:
         self.ctrl = torch.tensor(np.concatenate(ctrl), **f64)
         self.basis = torch.tensor(np.concatenate(
             [np.asarray(inst["basis"], dtype=np.float64).ravel() for inst in self.instances]), **f64)
-        self.q0 = torch.tensor(np.concatenate(
+        q0 = np.concatenate(
             [np.asarray(inst.get("q0", np.zeros(inst["nx"] * inst.get("ny", 1))),
-                        dtype=np.float64) for inst in self.instances]), **f64)
+                        dtype=np.float64) for inst in self.instances])
+        # an all-zero base state is passed as null (the C ABI's zero), which
+        # lets the library drop the initial-state source term
+        self.q0 = torch.tensor(q0, **f64) if np.any(q0 != 0.0) else None
         self.u_tgt = torch.tensor(np.concatenate(
             [np.asarray(inst["u_tgt"], dtype=np.float64) for inst in self.instances]), **f64)
         ntot = self.u_tgt.numel()

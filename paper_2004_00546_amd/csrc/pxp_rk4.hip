@@ -145,7 +145,8 @@ __device__ __forceinline__ void tri_rhs(const R (&Y)[PT], R l, R r, R cs, R cdf,
     }
 }
 
-template <int PT, typename R, bool INT, bool CC = true>
+// G = false: no constant source (g0 is null), the term is not formed.
+template <int PT, typename R, bool INT, bool CC = true, bool G = true>
 __device__ __forceinline__ void
 dev_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
               const double* __restrict__ y0, double* __restrict__ out, int n,
@@ -160,7 +161,7 @@ dev_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
         f[q] = F ? (R)F[base + q] : (R)0;
-        g[q] = g0 ? (R)g0[base + q] : (R)0;
+        g[q] = (G && g0) ? (R)g0[base + q] : (R)0;
         split_hilo<R>(y0 ? y0[base + q] : 0.0, y[q], yc[q]);
     }
     int buf = 0;
@@ -197,7 +198,8 @@ dev_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
         tri_rhs<PT, R, CC>(y, l[0], r[0], cs, cdf, cc, k);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
-            k[q] += s1 * f[q] + g[q];
+            if constexpr (G) k[q] += s1 * f[q] + g[q];
+            else k[q] += s1 * f[q];
             acc[q] = k[q];
             Y[q] = y[q] + h2 * k[q];
         }
@@ -212,7 +214,8 @@ dev_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
         tri_rhs<PT, R, CC>(Y, l[0], r[0], cs, cdf, cc, k);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
-            k[q] += s2 * f[q] + g[q];
+            if constexpr (G) k[q] += s2 * f[q] + g[q];
+            else k[q] += s2 * f[q];
             acc[q] += (R)2 * k[q];
             Y[q] = y[q] + h2 * k[q];
         }
@@ -227,7 +230,8 @@ dev_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
         tri_rhs<PT, R, CC>(Y, l[0], r[0], cs, cdf, cc, k);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
-            k[q] += s2 * f[q] + g[q];
+            if constexpr (G) k[q] += s2 * f[q] + g[q];
+            else k[q] += s2 * f[q];
             acc[q] += (R)2 * k[q];
             Y[q] = y[q] + h1 * k[q];
         }
@@ -242,7 +246,8 @@ dev_rk4_lin1d(const double* __restrict__ F, const double* __restrict__ g0,
         tri_rhs<PT, R, CC>(Y, l[0], r[0], cs, cdf, cc, k);
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
-            k[q] += s4 * f[q] + g[q];
+            if constexpr (G) k[q] += s4 * f[q] + g[q];
+            else k[q] += s4 * f[q];
             kadd<R>(y[q], yc[q], h6 * (acc[q] + k[q]));
         }
     }
@@ -273,13 +278,21 @@ k_rk4_lin1d_int(const double* __restrict__ F, const double* __restrict__ g0,
                 int64_t n_s, double dt, double omega, TriSplit A, SliceIntegral si) {
     dev_rk4_lin1d<PT, R, true>(F, g0, y0, out, n, n_s, dt, omega, A, si);
 }
-// plain march of an operator with cc == 0 (see tri_rhs)
+// plain march of an operator with cc == 0 (see tri_rhs), with and without
+// the constant source
 template <int PT, typename R>
 __global__ void __launch_bounds__(max_block<PT>())
 k_rk4_lin1d_nocc(const double* __restrict__ F, const double* __restrict__ g0,
                  const double* __restrict__ y0, double* __restrict__ out, int n,
                  int64_t n_s, double dt, double omega, TriSplit A, SliceIntegral si) {
     dev_rk4_lin1d<PT, R, false, false>(F, g0, y0, out, n, n_s, dt, omega, A, si);
+}
+template <int PT, typename R>
+__global__ void __launch_bounds__(max_block<PT>())
+k_rk4_lin1d_nocc_nog(const double* __restrict__ F, const double* __restrict__ g0,
+                     const double* __restrict__ y0, double* __restrict__ out, int n,
+                     int64_t n_s, double dt, double omega, TriSplit A, SliceIntegral si) {
+    dev_rk4_lin1d<PT, R, false, false, false>(F, g0, y0, out, n, n_s, dt, omega, A, si);
 }
 
 // Reverse sweep: y_{s+1} = y_s + dt sum_i b_i k_i with k_i = A Y_i + ...
@@ -830,6 +843,9 @@ hipError_t launch_rk4_lin1d(const double* F, const double* g0, const double* y0,
     const TriSplit sp = split(A);
     if (si.iout) {
         PXP_DISPATCH(fp32, pt, k_rk4_lin1d_int,
+                     <<<P, block, lds, s>>>(F, g0, y0, out, n, n_s, dt, omega, sp, si))
+    } else if (sp.cc == 0.0 && !g0) {
+        PXP_DISPATCH(fp32, pt, k_rk4_lin1d_nocc_nog,
                      <<<P, block, lds, s>>>(F, g0, y0, out, n, n_s, dt, omega, sp, si))
     } else if (sp.cc == 0.0) {
         PXP_DISPATCH(fp32, pt, k_rk4_lin1d_nocc,
