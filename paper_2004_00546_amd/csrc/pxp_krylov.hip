@@ -1424,14 +1424,19 @@ struct Ctx2 : Core<Ctx2, false> {
         }
     }
 
-    // One Taylor term: dst = f Op src; sum = (base ? base : sum) + dst;
-    // iout += (base ? J0 base : 0) + Jk dst.  Returns this thread's |dst|^2.
-    __device__ __forceinline__ double taylor_pass(const double* __restrict__ src,
-                                                  double* __restrict__ dst,
-                                                  double* __restrict__ sum,
-                                                  const double* __restrict__ base,
-                                                  double* __restrict__ iout, double f,
-                                                  double J0, double Jk) const {
+    // One Taylor term with the running sum updated every other term:
+    // dst = f Op src; when acc, the sum takes both the previous term (src,
+    // read anyway for the stencil) and the new one, sum = (base or sum) +
+    // src + dst, and iout += Jb base + Js src + Jd dst (base: the substep's
+    // start vector, folded in at the substep's first update).  Without acc
+    // only dst is written.  Returns the local |dst|^2.
+    __device__ __forceinline__ double taylor_pass2(const double* __restrict__ src,
+                                                   double* __restrict__ dst,
+                                                   double* __restrict__ sum,
+                                                   const double* __restrict__ base,
+                                                   double* __restrict__ iout, double f,
+                                                   double Jb, double Js, double Jd,
+                                                   bool acc) const {
         const Sten5 o = a.op5;
         double ss = 0.0;
 #pragma unroll 2
@@ -1449,23 +1454,48 @@ struct Ctx2 : Core<Ctx2, false> {
             y.x = f * (o.c * x.x + o.w * xw + o.e * x.y + o.s * xs.x + o.n * xn.x);
             y.y = f * (o.c * x.y + o.w * x.x + o.e * xe + o.s * xs.y + o.n * xn.y);
             st2(dst, g, y);
-            double2 sm = ld2(base ? base : sum, g);
-            if (iout) {
-                double2 io = ld2(iout, g);
-                if (base) {
-                    io.x += J0 * sm.x;
-                    io.y += J0 * sm.y;
+            if (acc) {
+                const double2 b = ld2(base ? base : sum, g);
+                if (iout) {
+                    double2 io = ld2(iout, g);
+                    if (base) {
+                        io.x += Jb * b.x;
+                        io.y += Jb * b.y;
+                    }
+                    io.x += Js * x.x + Jd * y.x;
+                    io.y += Js * x.y + Jd * y.y;
+                    st2(iout, g, io);
                 }
-                io.x += Jk * y.x;
-                io.y += Jk * y.y;
-                st2(iout, g, io);
+                st2(sum, g, make_double2(b.x + x.x + y.x, b.y + x.y + y.y));
             }
-            sm.x += y.x;
-            sm.y += y.y;
-            st2(sum, g, sm);
             ss += y.x * y.x + y.y * y.y;
         }
         return ss;
+    }
+
+    // sum = (base or sum) + src and iout += Jb base + Js src: the last term
+    // of a substep when it is still pending.
+    __device__ __forceinline__ void taylor_flush(const double* __restrict__ src,
+                                                 double* __restrict__ sum,
+                                                 const double* __restrict__ base,
+                                                 double* __restrict__ iout, double Jb,
+                                                 double Js) const {
+        for (int r = 0; r < G; ++r) {
+            const int g = t + r * B;
+            const double2 x = ld2(src, g);
+            const double2 b = ld2(base ? base : sum, g);
+            if (iout) {
+                double2 io = ld2(iout, g);
+                if (base) {
+                    io.x += Jb * b.x;
+                    io.y += Jb * b.y;
+                }
+                io.x += Js * x.x;
+                io.y += Js * x.y;
+                st2(iout, g, io);
+            }
+            st2(sum, g, make_double2(b.x + x.x, b.y + x.y));
+        }
     }
 
     // Taylor flavour (see KrylovArgs) on streamed vectors: the current
@@ -1488,28 +1518,40 @@ struct Ctx2 : Core<Ctx2, false> {
         for (int sub = 0; sub < ns; ++sub) {
             const double ph = ia + ib * (sub * h);
             const double J0 = iout ? this->taylor_weight(0, h, ph, ib) : 0.0;
-            const double J1 = iout ? this->taylor_weight(1, h, ph, ib) : 0.0;
             __syncthreads();  // u complete: the stencil reads neighbours
-            double prev = sqrt(block_sum(taylor_pass(u, tA, sm, u, iout, h, J0, J1), S.red));
+            // term 1 from u; the sum (started from u) is updated every
+            // other term, so a term is pending after each odd one
+            double prev = sqrt(block_sum(
+                taylor_pass2(u, tA, sm, nullptr, nullptr, h, 0.0, 0.0, 0.0, false), S.red));
             ++terms;
-            bool conv = false;
+            bool conv = false, started = false;
+            double Jprev = iout ? this->taylor_weight(1, h, ph, ib) : 0.0;
             const double* src = tA;
             double* dst = tB;
-            for (int k = 2; k <= a.tdeg; ++k) {
+            int k = 2;
+            for (; k <= a.tdeg; ++k) {
                 const double Jk = iout ? this->taylor_weight(k, h, ph, ib) : 0.0;
-                const double nt = sqrt(
-                    block_sum(taylor_pass(src, dst, sm, nullptr, iout, h / k, 0.0, Jk), S.red));
+                const bool acc = (k % 2) == 0;
+                const double nt = sqrt(block_sum(
+                    taylor_pass2(src, dst, sm, started ? nullptr : u, iout, h / k, J0, Jprev, Jk,
+                                 acc), S.red));
+                if (acc) started = true;
                 ++terms;
+                Jprev = Jk;
+                const double* tmp = src;
+                src = dst;
+                dst = const_cast<double*>(tmp);
                 if (prev + nt <= a.tol * nu) {
                     conv = true;
                     worst = fmax(worst, (prev + nt) / nu);
                     break;
                 }
                 prev = nt;
-                const double* tmp = src;
-                src = dst;
-                dst = const_cast<double*>(tmp);
             }
+            // the last term (now in src) is pending after an odd term, and
+            // so is u when no update has run yet (term 1 only)
+            const int last = (k <= a.tdeg) ? k : a.tdeg;
+            if ((last % 2) == 1) taylor_flush(src, sm, started ? nullptr : u, iout, J0, Jprev);
             if (!conv) noconv = true;
             double* tmp = u;
             u = sm;
