@@ -132,11 +132,19 @@ k_band2d_fwd(const Band2D* __restrict__ tab, int count, int serial, int L) {
     }
     const Sten5 A = d.A;
     const double dt = d.dt, h2 = 0.5 * dt, h6 = dt / 6.0;
-    for (int s = 0; s < ns; ++s) {
+    // the forcing sines of the block's steps at the stage times t, t + dt/2,
+    // t + dt: one evaluation per value instead of one per thread and stage
+    __shared__ double sn[12];
+    if ((int)threadIdx.x < 3 * ns) {
+        const int s = threadIdx.x / 3, v = threadIdx.x - 3 * (threadIdx.x / 3);
         const double tn = (double)(first + s) * dt;
+        sn[threadIdx.x] = sin(d.omega * (tn + (v == 0 ? 0.0 : (v == 2 ? dt : h2))));
+    }
+    __syncthreads();
+    for (int s = 0; s < ns; ++s) {
 #pragma unroll 1
         for (int st = 0; st < 4; ++st) {
-            const double sv = sin(d.omega * (tn + (st == 0 ? 0.0 : (st == 3 ? dt : h2))));
+            const double sv = sn[3 * s + (st == 0 ? 0 : (st == 3 ? 2 : 1))];
             const double cw = (st == 0) ? 1.0 : 2.0;
             const double cy = (st == 2) ? dt : h2;
             __syncthreads();  // previous readers of X are done
@@ -200,14 +208,21 @@ k_band2d_rev(const Band2D* __restrict__ tab, int count, int L) {
     }
     const Sten5 A = d.A;
     const double dt = d.dt, d6 = dt / 6.0, d3 = dt / 3.0, d2 = 0.5 * dt;
-    for (int s = ns - 1; s >= 0; --s) {
+    // the forcing sines at the stage times, as in k_band2d_fwd
+    __shared__ double sn[12];
+    if ((int)threadIdx.x < 3 * ns) {
+        const int s = threadIdx.x / 3, v = threadIdx.x - 3 * (threadIdx.x / 3);
         const double tn = (double)(first + s) * dt;
+        sn[threadIdx.x] = sin(d.omega * (tn + (v == 0 ? 0.0 : (v == 2 ? dt : d2))));
+    }
+    __syncthreads();
+    for (int s = ns - 1; s >= 0; --s) {
 #pragma unroll
         for (int q = 0; q < KPT; ++q) kb[q] = d6 * lam[q];
         // stages 4, 3, 2, 1
 #pragma unroll 1
         for (int st = 0; st < 4; ++st) {
-            const double sv = sin(d.omega * (tn + (st == 0 ? dt : (st == 3 ? 0.0 : d2))));
+            const double sv = sn[3 * s + (st == 0 ? 2 : (st == 3 ? 0 : 1))];
             const double bl = (st == 2) ? d6 : d3;  // weight of lam in the next kbar
             const double cy = (st == 0) ? dt : d2;  // weight of Ybar in the next kbar
             __syncthreads();
