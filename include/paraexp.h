@@ -250,16 +250,19 @@ pxp_status pxp_profile_read(int32_t kernel_class, double* total_ms,
  * for each group the gradient of its longest instance is timed over
  * candidate settings and the fastest candidate whose gradient agrees with
  * the serial method's gradient (the exact discrete adjoint of the same RK4
- * march) to `rtol` (relative L2) is kept.  Candidates: slice counts P among
- * the divisors of n_steps in [p_min, p_max] (at most six, spread
- * geometrically; 0 = 8 and 256), polynomial or shift-and-invert Krylov,
- * classic or chain schedule (linear problems), 256 or 512 Krylov threads
- * (1D).  Candidates slower than four times the best so far in their warm-up
- * run are not timed further; `reps` timed runs each (0 = 2).  The other
- * instances of the group take the tuned krylov, sched and kblock, and the
- * slice count whose slices last about as long as the tuned ones; each is
- * checked against its own serial gradient and its slice count doubled (to
- * the next divisor of n_steps) until it passes, at most four times.  Arrays
+ * march) to `rtol` (relative L2) is kept.  Candidates: first the problem
+ * as given (so tuning never loses to the untuned settings), then slice
+ * counts P among the divisors of n_steps in [p_min, p_max] (at most six,
+ * spread geometrically; 0 = 8 and 256), polynomial, shift-and-invert or
+ * Taylor, classic or chain schedule (linear problems), 256 or 512 Krylov
+ * threads (1D).  Candidates slower than four times the best so far in their
+ * warm-up run are not timed further; `reps` timed runs each (0 = 2).  When
+ * the problem as given wins, every instance of the group keeps its own
+ * settings.  Otherwise the other instances of the group take the tuned
+ * krylov, sched and kblock, and the slice count whose slices last about as
+ * long as the tuned ones; each is checked against its own serial gradient
+ * and its slice count doubled (to the next divisor of n_steps) until it
+ * passes, at most four times.  Arrays
  * are packed as for pxp_gradient; ws must hold pxp_tune_workspace_size bytes
  * (256-byte aligned); report (host, nullable) receives one entry per
  * instance (rel_err = -1 when no setting passed: the instance then keeps

@@ -56,6 +56,13 @@ std::vector<int> p_candidates(const pxp_problem& p, int lo, int hi) {
 
 std::vector<pxp_problem> candidates(const pxp_problem& base, int lo, int hi) {
     std::vector<pxp_problem> out;
+    // the problem as given comes first, so tuning never picks settings
+    // slower than the untuned ones (e.g. AUTO, which chooses the flavour
+    // per instance)
+    {
+        size_t bytes = 0;
+        if (pxp_workspace_size(&base, 1, &bytes) == PXP_OK) out.push_back(base);
+    }
     const bool linear = base.op != PXP_OP_BURGERS1D;
     const bool twod = base.op == PXP_OP_ADVDIFF2D_UPWIND;
     for (int P : p_candidates(base, lo, hi))
@@ -247,6 +254,7 @@ pxp_status pxp_autotune(pxp_problem* pb, int32_t batch, const double* ctrl,
         }
         pxp_problem best = base;
         double best_ms = 1e300, best_err = 0.0;
+        bool best_is_base = false;
         int tried = 0;
         for (const pxp_problem& c : candidates(base, p_min, p_max)) {
             // the warm-up alone decides for candidates far slower than the
@@ -267,6 +275,7 @@ pxp_status pxp_autotune(pxp_problem* pb, int32_t batch, const double* ctrl,
                 best_ms = t.ms;
                 best = c;
                 best_err = err;
+                best_is_base = (tried == 1);
             }
         }
         if (st != PXP_OK) break;
@@ -281,11 +290,14 @@ pxp_status pxp_autotune(pxp_problem* pb, int32_t batch, const double* ctrl,
             double err_i = best_err;
             if (best_ms < 1e300) {
                 pxp_problem c = pb[i];
-                c.krylov = best.krylov;
-                c.sched = best.sched;
-                c.kblock = best.kblock;
-                c.P = (i == rep_i) ? best.P : map_P(pb[i], dur, p_min, p_max);
-                bool ok = (i == rep_i);
+                if (!best_is_base) {
+                    c.krylov = best.krylov;
+                    c.sched = best.sched;
+                    c.kblock = best.kblock;
+                    c.P = (i == rep_i) ? best.P : map_P(pb[i], dur, p_min, p_max);
+                }
+                // when the untuned settings won, every instance keeps its own
+                bool ok = (i == rep_i) || best_is_base;
                 if (!ok) {
                     Trial r = trial(pb[i], i, PXP_METHOD_SERIAL, 0);
                     if (r.st == PXP_EHIP) {
