@@ -209,6 +209,26 @@ def test_paraexp_slice_counts(torch, orc, P):
     assert rel(got["grad"], want["grad"]) < FP64_GATE
 
 
+@pytest.mark.parametrize("P,krylov,sched", [(500, "poly", "classic"),
+                                            (500, "poly", "chain"),
+                                            (250, "auto", "chain"),
+                                            (100, "taylor", "classic")])
+def test_paraexp_many_short_slices(torch, orc, P, krylov, sched):
+    """Degenerate partitions: one or two RK4 steps per slice, so nearly all of
+    the horizon is carried by the exponentials of the homogeneous pieces
+    (hundreds of them in one launch, or one chain of that length).  At two
+    steps per slice tau*rho is about 0.2 on this grid, so AUTO takes Taylor;
+    shift-and-invert is not meant for such short pieces (its inverse is
+    nearly the identity) and its estimate says so."""
+    inst = small_advdiff(n=128, T=0.5, nt=500, P=P)
+    got = run(inst, krylov=krylov, sched=sched, tol=1e-10)
+    want = orc.gradient(inst)
+    eq, eg = rel(got["qT"], want["qT"]), rel(got["grad"], want["grad"])
+    say("P=%d %s/%s qT %.2e grad %.2e st %d" % (P, krylov, sched, eq, eg, got["status"]))
+    assert got["status"] == 0
+    assert eq < FP64_GATE and eg < FP64_GATE
+
+
 def test_ragged_batch_equals_one_by_one(torch):
     insts = [small_advdiff(n=64, seed=3), small_advdiff(n=256, seed=4, P=5),
              small_advdiff(n=128, seed=5, P=2)]
