@@ -128,7 +128,7 @@ def main():
                          "for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the time slices are a "
+        print("bench.py runs on one GPU only (the time slices are a "
               "batch dimension inside each launch); --gpus %d is not supported"
               % args.gpus, file=sys.stderr)
         sys.exit(2)

@@ -1,0 +1,52 @@
+"""Host-side checks of bench.py that need no GPU: the one-GPU contract, the
+algorithmic-bytes formula of an Arnoldi space, and the rule that counter
+traffic is reported only for the kernel source it was measured on."""
+import hashlib
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+@pytest.mark.parametrize("m", [1, 2, 7, 40])
+@pytest.mark.parametrize("passes", [1.0, 1.5, 2.0])
+def test_krylov_space_bytes_closed_form(m, passes):
+    """Step j reads j+1 basis vectors twice per pass and writes one; the
+    recombination reads m and writes one; the start vector is read and
+    written: in total passes*m*(m+1) + 2m + 3 vectors of 8n bytes."""
+    n = 4096
+    want = 8.0 * n * (passes * m * (m + 1) + 2 * m + 3)
+    assert bench.krylov_space_bytes(n, m, passes) == pytest.approx(want, rel=1e-15)
+
+
+def _fake_tree(tmp_path, src_text, line_sha):
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "paper_2004_00546_amd" / "csrc").mkdir(parents=True)
+    (tmp_path / "paper_2004_00546_amd" / "csrc" / "pxp_krylov.hip").write_text(src_text)
+    (tmp_path / "profiles" / "advdiff1d_n4096_kernels.md").write_text(
+        "text\ntraffic k_direct bytes_per_launch=1234.5 source_sha256_prefix=%s\n" % line_sha)
+
+
+def test_profiled_traffic_only_for_the_profiled_source(tmp_path, monkeypatch):
+    src = "// kernel source\n"
+    sha = hashlib.sha256(src.encode()).hexdigest()[:16]
+    _fake_tree(tmp_path, src, sha)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.profiled_traffic("k_direct") == 1234.5
+    assert bench.profiled_traffic("k_other") is None
+    # the kernel changed after the counters were taken: no traffic figure
+    (tmp_path / "paper_2004_00546_amd" / "csrc" / "pxp_krylov.hip").write_text(src + "x")
+    assert bench.profiled_traffic("k_direct") is None
