@@ -910,6 +910,9 @@ hipError_t launch_rk4_burgers_reverse(const double* ckpt, const double* lamT,
                                       double nu, double L, int block_hint, int fp32,
                                       hipStream_t s) {
     int block, pt;
+    // Measured: at N = 2048 the reverse sweep ran 9% faster with 512
+    // threads of 4 points than with the march default of 256 threads of 8.
+    if (block_hint <= 0 && n == 4 * 512) block_hint = 512;
     if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
     const double h = L / n;
     BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
