@@ -810,6 +810,16 @@ bool pick_shape(int n, int block_hint, int* block, int* pt) {
     return false;
 }
 
+// One-workgroup marches (the serial comparison method) wait on a barrier per
+// RK4 stage.  Measured: at N = 4096 the linear forward march plus reverse
+// sweep took 105 ms with 512 threads of 8 points against 124 ms with 256 of
+// 16, and at N = 2048 the Burgers reverse sweep ran 9% faster with 512 of 4.
+// The Paraexp slice batch (many workgroups) keeps the 256-thread default.
+int serial_block_hint(int n, int block_hint) {
+    if (block_hint > 0) return block_hint;
+    return (n == 4 * 512 || n == 8 * 512) ? 512 : 0;
+}
+
 }  // namespace
 
 #define PXP_DISPATCH_PT(pt, KERNEL, R, ...)                                    \
@@ -838,7 +848,8 @@ hipError_t launch_rk4_lin1d(const double* F, const double* g0, const double* y0,
                             double omega, Tri A, int block_hint, int fp32,
                             hipStream_t s, SliceIntegral si) {
     int block, pt;
-    if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
+    if (!pick_shape(n, P == 1 ? serial_block_hint(n, block_hint) : block_hint, &block, &pt))
+        return hipErrorInvalidValue;
     const size_t lds = sizeof(double) * (4 * block + SINE_LDS_DOUBLES);
     const TriSplit sp = split(A);
     if (si.iout) {
@@ -862,7 +873,8 @@ hipError_t launch_rk4_rev_lin1d(const double* lamT, double* lam0,
                                 double omega, Tri AT, int block_hint, int fp32,
                                 hipStream_t s) {
     int block, pt;
-    if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
+    if (!pick_shape(n, serial_block_hint(n, block_hint), &block, &pt))
+        return hipErrorInvalidValue;
     const size_t lds = sizeof(double) * (4 * block + SINE_LDS_DOUBLES);
     const TriSplit sp = split(AT);
     if (sp.cc == 0.0) {
@@ -910,10 +922,8 @@ hipError_t launch_rk4_burgers_reverse(const double* ckpt, const double* lamT,
                                       double nu, double L, int block_hint, int fp32,
                                       hipStream_t s) {
     int block, pt;
-    // Measured: at N = 2048 the reverse sweep ran 9% faster with 512
-    // threads of 4 points than with the march default of 256 threads of 8.
-    if (block_hint <= 0 && n == 4 * 512) block_hint = 512;
-    if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
+    if (!pick_shape(n, serial_block_hint(n, block_hint), &block, &pt))
+        return hipErrorInvalidValue;
     const double h = L / n;
     BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
     const size_t lds = sizeof(double) * 8 * block;
