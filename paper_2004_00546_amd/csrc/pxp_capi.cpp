@@ -687,6 +687,8 @@ BurgersDesc burgers_desc(const pxp_problem& p, const Ctx& c) {
     const double h = p.L / p.nx;
     d.n = p.nx;
     d.pt = p.nx / 256;
+    const int pr = p.nx / 512;
+    d.pt_rev = (p.nx % 512 == 0 && (pr == 2 || pr == 4 || pr == 8 || pr == 16)) ? pr : 0;
     d.n_t = p.n_steps;
     d.c = p.ckpt_every;
     d.S = p.n_steps / p.P;
@@ -767,8 +769,12 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
     auto* dtab = reinterpret_cast<BurgersDesc*>(static_cast<char*>(ws) + Ly.btab);
     HIPCHK(launch_upload(dtab, tab.data(), tab.size() * sizeof(BurgersDesc), s));
     if (method == PXP_METHOD_SERIAL) {
+        // the sweep is barrier-latency bound: 512 threads with half the
+        // points each when every instance of the launch allows it
+        bool rev512 = true;
+        for (const BurgersDesc& d : tab) rev512 = rev512 && d.pt_rev != 0;
         ProfScope ps(PXP_K_SERIAL_REVERSE, s);
-        HIPCHK(launch_burgers_batch(1, dtab, (int)tab.size(), 0, bb.fp32, s));
+        HIPCHK(launch_burgers_batch(rev512 ? 3 : 1, dtab, (int)tab.size(), 0, bb.fp32, s));
         return PXP_OK;
     }
     auto* kt = reinterpret_cast<KrylovArgs*>(static_cast<char*>(ws) + Ly.ktab);

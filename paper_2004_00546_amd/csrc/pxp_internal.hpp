@@ -85,7 +85,9 @@ hipError_t launch_burgers_nodes(const double* ckpt, double* W, int n, int64_t n_
 // One descriptor per instance (device table in the workspace, written by
 // launch_upload).  Every instance uses 256 threads with pt = n / 256.
 struct BurgersDesc {
-    int n, pt, q0, pad;      // q0: prefix count of macro steps (nodes grid)
+    int n, pt, q0, pt_rev;   // q0: prefix count of macro steps (nodes grid);
+                             // pt_rev: points per thread of the 512-thread
+                             // reverse sweep (0: not available)
     int64_t n_t, c, S;
     double dt, inv2h, nuh2;
     const double* y0;
@@ -97,7 +99,8 @@ struct BurgersDesc {
     double* lam0;
 };
 // which: 0 direct march with checkpoints, 1 serial reverse sweep,
-// 2 Magnus node recompute (grid = total macro steps)
+// 2 Magnus node recompute (grid = total macro steps), 3 serial reverse sweep
+// at 512 threads (every descriptor's pt_rev set)
 hipError_t launch_burgers_batch(int which, const BurgersDesc* tab, int count,
                                 int total_blocks, int fp32, hipStream_t s);
 // Copy `bytes` (<= 3072) host bytes, passed by value as kernel arguments, to

@@ -757,6 +757,26 @@ __global__ void __launch_bounds__(256) k_burgers_reverse_batch(const BurgersDesc
                      d.c, d.dt, bc, lds_d)
 }
 
+// The serial reverse sweep at 512 threads per instance (every instance of
+// the launch has pt_rev points per thread, pt_rev * 512 = n).
+#define PXP_BATCH_SWITCH_REV(FN, R, ...)                                       \
+    switch (d.pt_rev) {                                                        \
+        case 2: FN<2, R>(__VA_ARGS__); break;                                  \
+        case 4: FN<4, R>(__VA_ARGS__); break;                                  \
+        case 8: FN<8, R>(__VA_ARGS__); break;                                  \
+        case 16: FN<16, R>(__VA_ARGS__); break;                                \
+        default: break;                                                        \
+    }
+
+template <typename R>
+__global__ void __launch_bounds__(512) k_burgers_reverse_batch512(const BurgersDesc* tab) {
+    extern __shared__ double lds_d[];
+    const BurgersDesc d = tab[blockIdx.x];
+    const BurgersC bc{d.inv2h, d.nuh2};
+    PXP_BATCH_SWITCH_REV(dev_burgers_reverse, R, d.ckpt, d.lamT, d.lam0, d.seg, d.n, d.n_t,
+                         d.c, d.dt, bc, lds_d)
+}
+
 // grid = sum of the instances' macro-step counts; the instance of a
 // workgroup is found by a scan of the table's prefix counts
 template <typename R>
@@ -943,6 +963,10 @@ hipError_t launch_burgers_batch(int which, const BurgersDesc* tab, int count,
     } else if (which == 1) {
         if (fp32) k_burgers_reverse_batch<float><<<grid, 256, lds, s>>>(tab);
         else k_burgers_reverse_batch<double><<<grid, 256, lds, s>>>(tab);
+    } else if (which == 3) {
+        const size_t lds512 = sizeof(double) * 8 * 512;
+        if (fp32) k_burgers_reverse_batch512<float><<<grid, 512, lds512, s>>>(tab);
+        else k_burgers_reverse_batch512<double><<<grid, 512, lds512, s>>>(tab);
     } else {
         if (fp32) k_burgers_nodes_batch<float><<<grid, 256, lds, s>>>(tab, count);
         else k_burgers_nodes_batch<double><<<grid, 256, lds, s>>>(tab, count);

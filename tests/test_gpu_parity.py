@@ -388,6 +388,31 @@ def test_ragged_burgers_batch_equals_one_by_one(torch, method):
         assert np.array_equal(one["grad"], b["grad"]), (inst["nx"], method)
 
 
+def test_ragged_burgers_serial_sweep_512(torch, orc):
+    """Every instance a multiple of 512 points (2, 4 and 8 per thread at 512
+    threads): the batched reverse sweep runs at 512 threads.  It must agree
+    with the one-by-one calls and, at the small size, with the oracle."""
+    insts = []
+    for i, (n, nu) in enumerate([(1024, 0.02), (2048, 0.02), (4096, 0.03), (1024, 0.01)]):
+        dt = 0.8 * workloads.burgers_dt_bound(n, nu)
+        nt = 64 * int(math.ceil(0.02 / (64 * dt)))
+        insts.append(small_burgers(n=n, T=0.02, nt=nt, P=nt // 16, nu=nu, seed=60 + i,
+                                   ckpt=16))
+    r = api.GradientRunner(insts, method="serial")
+    r.run()
+    code, _ = r.status()
+    assert code == 0
+    batch = r.results()
+    for inst, b in zip(insts, batch):
+        one = run(inst, "serial")
+        e = rel(b["grad"], one["grad"])
+        say("serial sweep 512 n=%d nt=%d: batch vs one %.2e" % (inst["nx"], inst["n_steps"], e))
+        assert np.array_equal(one["qT"], b["qT"])
+        assert e < 1e-13
+    want = orc.gradient(insts[0])
+    assert rel(batch[0]["grad"], want["grad"]) < 1e-11
+
+
 def test_ragged_burgers_batch_vs_oracle(torch, orc):
     insts = ragged_burgers(seed=40)
     r = api.GradientRunner(insts, method="paraexp", krylov="poly")
