@@ -283,6 +283,27 @@ pxp_status pxp_autotune(pxp_problem* pb, int32_t batch, const double* ctrl,
                         double rtol, int32_t reps, void* ws, size_t ws_bytes,
                         pxp_tune_report* report, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as pxp_gradient, with its workspace in a fixed device array of
+ * the library (PXP_NOALLOC_SCRATCH_BYTES per GPU, held by each GPU the
+ * library runs on until the process ends) instead of a caller buffer.  The
+ * call allocates nothing.  Arguments as for pxp_gradient; problems whose
+ * pxp_workspace_size exceeds PXP_NOALLOC_SCRATCH_BYTES are rejected with
+ * PXP_EWORKSPACE before anything is enqueued.  The device status block is
+ * cleared at the start of every call; status_out (device, nullable, at least
+ * 64 bytes, 8-byte aligned) receives it at the end, to be read with
+ * pxp_device_status(status_out, 64, stream, ...).  Every call on a GPU uses
+ * that GPU's one array: calls that overlap on one GPU (two streams, two host
+ * threads) race and give wrong results; serialise them. */
+#define PXP_NOALLOC_SCRATCH_BYTES (64u << 20)
+pxp_status pxp_gradient_noalloc(const pxp_problem* pb, int32_t batch,
+                                int32_t method, const double* ctrl,
+                                const double* basis, const double* q0,
+                                const double* u_tgt, double* J, double* grad,
+                                double* qT, double* lam_out, void* status_out,
+                                void* stream);
+
 /* Human-readable text for a status code (static storage). */
 const char* pxp_status_str(pxp_status s);
 

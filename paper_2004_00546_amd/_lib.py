@@ -33,7 +33,7 @@ EXPORTED = ("pxp_workspace_size", "pxp_workspace_init", "paraexp_direct",
             "pxp_device_counters", "pxp_status_str", "pxp_version",
             "pxp_profile_enable", "pxp_profile_read", "pxp_assemble",
             "pxp_cost", "pxp_reduce_gradient", "pxp_tune_workspace_size",
-            "pxp_autotune")
+            "pxp_autotune", "pxp_gradient_noalloc")
 KCLASS = {"slices": 0, "krylov_direct": 1, "krylov_adjoint": 2,
           "serial_direct": 3, "serial_reverse": 4, "ltv_adjoint": 5,
           "ltv_nodes": 6}
@@ -108,6 +108,8 @@ def load() -> ctypes.CDLL:
         "pxp_tune_workspace_size": (st, [P, i32, i32, i32, ctypes.POINTER(sz)]),
         "pxp_autotune": (st, [P, i32, vp, vp, vp, vp, i32, i32, ctypes.c_double, i32,
                               vp, sz, ctypes.POINTER(pxp_tune_report), vp]),
+        "pxp_gradient_noalloc": (st, [P, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                      vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -178,6 +180,21 @@ def pxp_gradient(problems, method, ctrl, basis, q0, u_tgt, J, grad, qT, lam_out,
                                _ptr(u_tgt), _ptr(J), _ptr(grad), _ptr(qT),
                                _ptr(lam_out), _ptr(ws), ws.numel(),
                                _stream(stream)), "pxp_gradient")
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # PXP_NOALLOC_SCRATCH_BYTES
+
+
+def pxp_gradient_noalloc(problems, method, ctrl, basis, q0, u_tgt, J, grad, qT, lam_out,
+                         status_out=None, stream=None):
+    """pxp_gradient with the library's fixed device workspace (no caller
+    workspace, no allocation)."""
+    arr, n = problems_array(problems)
+    _check(load().pxp_gradient_noalloc(arr, n, METHOD[method] if isinstance(method, str)
+                                       else method, _ptr(ctrl), _ptr(basis), _ptr(q0),
+                                       _ptr(u_tgt), _ptr(J), _ptr(grad), _ptr(qT),
+                                       _ptr(lam_out), _ptr(status_out), _stream(stream)),
+           "pxp_gradient_noalloc")
 
 
 def gradient(problems, ctrl, basis, q0, u_tgt, J, grad, qT, ws, stream=None):

@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libparaexp.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["pxp_rk4.hip", "pxp_rk4_2d.hip", "pxp_krylov.hip", "pxp_misc.hip",
-           "pxp_capi.cpp", "pxp_tune.cpp"]
+           "pxp_capi.cpp", "pxp_tune.cpp", "pxp_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

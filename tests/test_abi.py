@@ -183,3 +183,14 @@ def test_problem_flags():
     with pytest.raises(_lib.PxpError) as e:
         _lib.pxp_workspace_size([burg])
     assert e.value.code == _lib.PXP_EUNSUPPORTED
+
+
+def test_noalloc_rejects_oversize_on_host(lib):
+    # the size check runs before any HIP call: no GPU needed
+    inst = workloads.make("advdiff1d_n4096")[0]
+    p = api.make_problem(inst)
+    assert _lib.pxp_workspace_size([p]) > _lib.NOALLOC_SCRATCH_BYTES
+    arr, n = _lib.problems_array([p])
+    code = lib.pxp_gradient_noalloc(arr, n, 0, None, None, None, None, None, None,
+                                    None, None, None, None)
+    assert code == _lib.PXP_EWORKSPACE

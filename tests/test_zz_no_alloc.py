@@ -1,0 +1,99 @@
+"""pxp_gradient_noalloc (the allocation-free form of pxp_gradient, workspace
+in the library's fixed device array) against pxp_gradient with a caller
+workspace: two calls in a row, the second on a smaller problem, each
+compared with the workspace form on the same inputs.  Both run the same
+kernels in the same order, so the results must agree to rounding of a
+deterministic computation (they are compared at 1e-13, far inside the 1e-8
+gate)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import rel
+from paper_2004_00546_amd import _lib, api, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    _lib.load()
+    return _t
+
+
+def burgers_small(n=256, nt=512, P=8):
+    rng = np.random.default_rng(7)
+    L = 2 * math.pi
+    ph = rng.uniform(0, 2 * math.pi, 8)
+    basis = workloads.burgers_ic_modes(n, L, ph)[:8]
+    x = np.arange(n) * L / n
+    return dict(op="burgers1d", control="ic", nx=n, ny=1, L=L, vx=0.0, vy=0.0,
+                nu=0.02, T=0.5, omega=1.0, beta=1e-3, n_steps=nt, P=P, m=30,
+                ckpt_every=16, basis=basis, a=0.1 * rng.standard_normal(8),
+                u_tgt=0.05 * np.sin(2 * x), q0=np.zeros(n))
+
+
+def run_both(torch, inst, **kw):
+    """Workspace form and allocation-free form on the same device inputs."""
+    r = api.GradientRunner([inst], method="paraexp", **kw)
+    r.run()
+    ref = r.results()[0]
+    code_ref, _ = r.status()
+    f64 = dict(dtype=torch.float64, device=r.device)
+    J = torch.full((1,), float("nan"), **f64)
+    grad = torch.full_like(r.grad, float("nan"))
+    qT = torch.full_like(r.qT, float("nan"))
+    lam = torch.full_like(r.lam, float("nan"))
+    # 64 bytes of garbage: the call overwrites the status block
+    stat = torch.full((64,), 7, dtype=torch.uint8, device=r.device)
+    _lib.pxp_gradient_noalloc(r.problems, "paraexp", r.ctrl, r.basis, r.q0, r.u_tgt,
+                              J, grad, qT, lam, stat)
+    torch.cuda.synchronize()
+    code, est = _lib.pxp_device_status(stat)
+    got = dict(J=float(J.cpu()[0]), grad=grad.cpu().numpy(), qT=qT.cpu().numpy(),
+               lam=lam.cpu().numpy())
+    return ref, code_ref, got, code
+
+
+def check(ref, got):
+    assert abs(got["J"] - ref["J"]) <= 1e-13 * abs(ref["J"])
+    for k in ("grad", "qT", "lam"):
+        assert np.all(np.isfinite(got[k])), k
+        assert rel(got[k], ref[k]) <= 1e-13, k
+
+
+def test_noalloc_matches_workspace_form_twice(torch):
+    big = burgers_small(n=512, nt=1024, P=16)
+    small = workloads.make("advdiff1d_n128")[0]
+    sizes = [_lib.pxp_workspace_size([api.make_problem(x)]) for x in (big, small)]
+    print("noalloc: burgers n=512 (%d B) then advdiff1d_n128 (%d B)" % tuple(sizes),
+          flush=True)
+    assert sizes[1] < sizes[0] <= _lib.NOALLOC_SCRATCH_BYTES
+    ref, cr, got, c = run_both(torch, big, krylov="auto", tol=1e-10)
+    assert cr == 0 and c == 0
+    check(ref, got)
+    # a second, different and smaller problem reuses the same array
+    ref2, cr2, got2, c2 = run_both(torch, small, krylov="auto", sched="classic", tol=1e-10)
+    assert cr2 == 0 and c2 == 0
+    check(ref2, got2)
+    sys.stdout.flush()
+
+
+def test_noalloc_rejects_oversize_problem(torch):
+    inst = workloads.make("advdiff1d_n4096")[0]  # Krylov bases alone ~85 MB
+    p = api.make_problem(inst)
+    assert _lib.pxp_workspace_size([p]) > _lib.NOALLOC_SCRATCH_BYTES
+    f64 = dict(dtype=torch.float64, device="cuda:0")
+    n, K = inst["nx"], np.asarray(inst["basis"]).shape[0]
+    buf = torch.zeros(n, **f64)
+    with pytest.raises(_lib.PxpError) as e:
+        _lib.pxp_gradient_noalloc([p], "paraexp", torch.zeros(K, **f64),
+                                  torch.zeros(K * n, **f64), None, buf,
+                                  torch.zeros(1, **f64), torch.zeros(K, **f64),
+                                  None, None)
+    assert e.value.code == _lib.PXP_EWORKSPACE
