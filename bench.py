@@ -96,8 +96,9 @@ def main():
                     help="keep warming up (untimed gradients) for at least this long, so "
                          "the timed region runs at steady-state clocks")
     ap.add_argument("--workload", default="advdiff1d_n4096")
-    ap.add_argument("--krylov", default="auto", choices=["poly", "shift_invert", "auto", "taylor"])
-    ap.add_argument("--sched", default="classic", choices=["classic", "chain"])
+    ap.add_argument("--krylov", default="auto", choices=["poly", "shift_invert", "auto", "taylor", "uniform"])
+    ap.add_argument("--sched", default=None, choices=["classic", "chain", "tree"],
+                    help="schedule of the direct pieces (default: tree in 2D, classic in 1D)")
     ap.add_argument("--serial-steps", type=int, default=5)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32_bulk"])
     ap.add_argument("--tol", type=float, default=None)
@@ -158,6 +159,8 @@ def main():
     log("workload %s: %d instance(s); first N=%d steps=%d P=%d m=%d; point-steps %.3g"
         % (args.workload, B, n, n_steps, P, m, sum(work)))
 
+    if args.sched is None:
+        args.sched = "tree" if inst["op"] == "advdiff2d_upwind" else "classic"
     tol = args.tol if args.tol is not None else (1e-9 if args.prec == "fp64" else 1e-6)
     kw = dict(prec=args.prec, block=args.block, kblock=args.kblock)
     pkw = dict(kw, absorbed=args.absorbed)

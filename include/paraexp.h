@@ -84,20 +84,36 @@ enum { PXP_CTRL_FORCING = 0, PXP_CTRL_IC = 1 };
  * extrapolated from the contraction of those differences and the space stops
  * once it is below krylov_tol (relative to |v|).  Both Arnoldi flavours use
  * classical Gram-Schmidt with a second pass only on tenfold cancellation. */
-/* AUTO: shift-and-invert when tau * rho > 64 (rho = 4 nu/h^2 + |vx|/h, tau
- * the horizon for the linear pieces or half a slice for the Burgers Magnus
- * factors) and the grid has the cyclic-reduction shape, else TAYLOR. */
+/* AUTO: 1D: shift-and-invert when tau * rho > 64 (rho = 4 nu/h^2 + |vx|/h,
+ * tau the horizon for the linear pieces or half a slice for the Burgers
+ * Magnus factors) and the grid has the cyclic-reduction shape, else TAYLOR.
+ * 2D: UNIFORM, except for the CLASSIC schedule of the direct pieces, which
+ * takes TAYLOR. */
 /* TAYLOR: no Arnoldi process; exp(tau Op) v by the truncated Taylor series
  * in substeps of at most theta/|Op| (theta from the remainder bound for 40
  * terms at krylov_tol), terms added until two consecutive term norms fall
  * below krylov_tol |v|; the time integral is accumulated term by term.  Its
  * traffic is a few vectors per term and it needs no inner products. */
+/* UNIFORM (2D only): no Arnoldi process; exp(tau A) x by uniformisation,
+ * sum_k p_k N^k x with N = I + A/mu, mu = -A_ii the diagonal magnitude of
+ * the five-point operator (N is nonnegative with unit row and column sums
+ * for nonnegative velocities) and p_k the Poisson weights of mu tau.  The
+ * number of terms D is fixed before the launch as the smallest with Poisson
+ * tail P(X >= D) <= krylov_tol / 100, a bound of the truncation error in the
+ * max norm; it is the value reported as the estimate.  Each exponential is
+ * split over bands of grid rows, every band recomputing up to 16 halo rows
+ * per pass of 16 terms, so one exponential spreads over many workgroups.
+ * The adjoint's time integral uses the exact integral of every term's
+ * weight against the forcing modulation. */
 enum { PXP_KRYLOV_POLY = 0, PXP_KRYLOV_SHIFT_INVERT = 1, PXP_KRYLOV_AUTO = 2,
-       PXP_KRYLOV_TAYLOR = 3 };
+       PXP_KRYLOV_TAYLOR = 3, PXP_KRYLOV_UNIFORM = 4 };
 /* Schedule of the direct homogeneous pieces: CLASSIC = P-1 independent
  * pieces exp((T - T_{p+1}) A) v_p (eq. hom); CHAIN = nested sum
- * w <- exp(dT A) w + v_p, one piece after the other. */
-enum { PXP_SCHED_CLASSIC = 0, PXP_SCHED_CHAIN = 1 };
+ * w <- exp(dT A) w + v_p, one piece after the other; TREE (2D, UNIFORM) =
+ * the same sum combined pairwise: adjacent partial sums over slice ranges
+ * [a, b) and [b, c) give exp((T_c - T_b) A) w_ab + w_bc, all pairs of one
+ * level independent, log2(P) levels. */
+enum { PXP_SCHED_CLASSIC = 0, PXP_SCHED_CHAIN = 1, PXP_SCHED_TREE = 2 };
 /* Problem flags.  ABSORBED_ADJOINT (1D linear problems): the Paraexp
  * adjoint runs in the absorbed form of section 3.3 (eq. hybadjinhom with the
  * final condition absorbed): lambda = lambda_T + q~, q~(T) = 0, with the P

@@ -3,7 +3,8 @@
 ``ParaexpLoss.apply(a, problem)`` returns J(a) for one instance; its backward
 returns dJ/da.  Forward: ``pxp_assemble`` (controls -> forcing pattern or
 initial state), ``paraexp_direct`` (for Burgers the serial march that keeps
-its checkpoints in the problem's workspace, paper section 3.5),
+its checkpoints in a workspace of this forward's own, saved for its
+backward, paper section 3.5),
 ``pxp_cost`` (J and lambda_T).  Backward: ``paraexp_adjoint`` from lambda_T
 (Krylov pieces, or the Magnus chain for Burgers) and
 ``pxp_reduce_gradient`` (eqs. paramupdate, initupdate); the incoming
@@ -31,10 +32,19 @@ class Problem:
         self.q0 = torch.tensor(np.asarray(inst.get("q0", np.zeros(n)), dtype=np.float64), **f64)
         self.u_tgt = torch.tensor(np.asarray(inst["u_tgt"], dtype=np.float64), **f64)
         self.forcing = inst["control"] == "forcing"
-        nbytes = _lib.pxp_workspace_size([self.p])
-        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
-        _lib.pxp_workspace_init(self.ws)
+        self.nbytes = max(_lib.pxp_workspace_size([self.p]), 256)
+        self.ws = self.new_workspace()
         self.n = n
+        # the Burgers direct march leaves its checkpoints in the workspace
+        # for the adjoint: each forward then gets a workspace of its own,
+        # saved with the autograd context, so a second forward before the
+        # first backward cannot overwrite the trajectory that backward reads
+        self.ckpt_in_ws = inst["op"] == "burgers1d"
+
+    def new_workspace(self):
+        ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        _lib.pxp_workspace_init(ws)
+        return ws
 
 
 class ParaexpLoss(torch.autograd.Function):
@@ -50,11 +60,16 @@ class ParaexpLoss(torch.autograd.Function):
             _lib.pxp_assemble([prob.p], a, prob.basis, prob.q0, field)
             q0, F = field, None
         qT = torch.empty(prob.n, **f64)
-        _lib.paraexp_direct([prob.p], q0, F, qT, prob.ws)
+        ws = prob.new_workspace() if prob.ckpt_in_ws else prob.ws
+        _lib.paraexp_direct([prob.p], q0, F, qT, ws)
         J = torch.empty(1, **f64)
         lamT = torch.empty(prob.n, **f64)
         _lib.pxp_cost([prob.p], qT, prob.u_tgt, a, J, lamT)
+        code, _ = _lib.pxp_device_status(ws)
+        if code != _lib.PXP_OK:
+            raise _lib.PxpError(code, "paraexp_direct (device status)")
         ctx.prob = prob
+        ctx.ws = ws
         ctx.save_for_backward(a, lamT)
         return J[0]
 
@@ -64,11 +79,12 @@ class ParaexpLoss(torch.autograd.Function):
         prob = ctx.prob
         f64 = dict(dtype=torch.float64, device=prob.device)
         v = torch.empty(prob.n, **f64)
+        ws = ctx.ws
         if prob.forcing:
-            _lib.paraexp_adjoint([prob.p], lamT, None, v, prob.ws)
+            _lib.paraexp_adjoint([prob.p], lamT, None, v, ws)
         else:
-            _lib.paraexp_adjoint([prob.p], lamT, v, None, prob.ws)
-        code, _ = _lib.pxp_device_status(prob.ws)
+            _lib.paraexp_adjoint([prob.p], lamT, v, None, ws)
+        code, _ = _lib.pxp_device_status(ws)
         if code != _lib.PXP_OK:
             raise _lib.PxpError(code, "paraexp_adjoint (device status)")
         grad = torch.empty_like(a)

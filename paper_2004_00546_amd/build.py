@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libparaexp.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["pxp_rk4.hip", "pxp_rk4_2d.hip", "pxp_krylov.hip", "pxp_misc.hip",
+SOURCES = ["pxp_rk4.hip", "pxp_rk4_2d.hip", "pxp_expo2d.hip", "pxp_krylov.hip", "pxp_misc.hip",
            "pxp_capi.cpp", "pxp_tune.cpp", "pxp_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -32,8 +32,6 @@ def _compile(src: str) -> str:
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC, "--offload-arch=" + ARCH, *COMMON, "-c",
            os.path.join(CSRC, src), "-o", obj]
-    if src.endswith(".cpp"):
-        cmd = [HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, res.stdout, res.stderr))

@@ -25,6 +25,7 @@ inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
     size_t status;             // DevStatus
     size_t btab, ktab, t2d;    // batch tables: Burgers, Krylov, 2D marches
+    size_t ptab, pwt;          // uniformised exponentials: pass entries, weights
     std::vector<size_t> base;  // per-instance region offset
     size_t total;
 };
@@ -32,7 +33,7 @@ struct Layout {
 // Per-instance buffers (offsets relative to the instance region).
 struct Inst {
     size_t F, g0, q0eff, slices, pieces, basis, qT, lamT, lam0, Lam, chain,
-        ckpt, seg, nodes, sbuf0, sbuf1, aint, J, size;
+        ckpt, seg, nodes, sbuf0, sbuf1, aint, J, tbuf, wtab, ubuf, size;
 };
 
 int64_t grid_n(const pxp_problem& p) { return (int64_t)p.nx * (int64_t)p.ny; }
@@ -137,10 +138,24 @@ bool use_si(const pxp_problem& p) {
     return p.op == PXP_OP_BURGERS1D || (is_pow2(p.nx) && p.nx >= 64);
 }
 
-// Taylor flavour: named, or AUTO where shift-and-invert is not taken.
+// 2D exponentials by uniformisation: named, or AUTO for the adjoint piece and
+// for the chain and tree schedules of the direct pieces (the classic
+// schedule's independent long pieces stay with the Taylor flavour).
+bool uniform_direct(const pxp_problem& p) {
+    if (p.op != PXP_OP_ADVDIFF2D_UPWIND) return false;
+    if (p.krylov == PXP_KRYLOV_UNIFORM) return true;
+    return p.krylov == PXP_KRYLOV_AUTO && p.sched != PXP_SCHED_CLASSIC;
+}
+bool uniform_adjoint(const pxp_problem& p) {
+    if (p.op != PXP_OP_ADVDIFF2D_UPWIND) return false;
+    return p.krylov == PXP_KRYLOV_UNIFORM || p.krylov == PXP_KRYLOV_AUTO;
+}
+
+// Taylor flavour: named, or AUTO where neither shift-and-invert nor
+// uniformisation is taken.
 bool use_taylor(const pxp_problem& p) {
     if (p.krylov == PXP_KRYLOV_TAYLOR) return true;
-    return p.krylov == PXP_KRYLOV_AUTO && !use_si(p);
+    return p.krylov == PXP_KRYLOV_AUTO && !use_si(p) && !uniform_direct(p);
 }
 
 // The Krylov kernels' workgroup shape for this problem exists, fits in LDS,
@@ -162,9 +177,13 @@ pxp_status validate(const pxp_problem& p) {
     if (p.n_steps % p.P != 0) return PXP_EINVAL;
     if (p.ctrl != PXP_CTRL_FORCING && p.ctrl != PXP_CTRL_IC) return PXP_EINVAL;
     if (p.krylov != PXP_KRYLOV_POLY && p.krylov != PXP_KRYLOV_SHIFT_INVERT &&
-        p.krylov != PXP_KRYLOV_AUTO && p.krylov != PXP_KRYLOV_TAYLOR)
+        p.krylov != PXP_KRYLOV_AUTO && p.krylov != PXP_KRYLOV_TAYLOR &&
+        p.krylov != PXP_KRYLOV_UNIFORM)
         return PXP_EINVAL;
-    if (p.sched != PXP_SCHED_CLASSIC && p.sched != PXP_SCHED_CHAIN) return PXP_EINVAL;
+    if (p.sched != PXP_SCHED_CLASSIC && p.sched != PXP_SCHED_CHAIN && p.sched != PXP_SCHED_TREE)
+        return PXP_EINVAL;
+    if (p.krylov == PXP_KRYLOV_UNIFORM && p.op != PXP_OP_ADVDIFF2D_UPWIND) return PXP_EUNSUPPORTED;
+    if (p.sched == PXP_SCHED_TREE && !uniform_direct(p)) return PXP_EUNSUPPORTED;
     if (p.prec != PXP_FP64 && p.prec != PXP_FP32_BULK) return PXP_EINVAL;
     if ((p.flags & ~PXP_FLAG_ABSORBED_ADJOINT) || p.kblock < 0 || p.block < 0) return PXP_EINVAL;
     if ((p.flags & PXP_FLAG_ABSORBED_ADJOINT) && p.op != PXP_OP_ADVDIFF1D) return PXP_EUNSUPPORTED;
@@ -196,23 +215,87 @@ pxp_status validate(const pxp_problem& p) {
         return PXP_OK;
     }
     if (p.op == PXP_OP_ADVDIFF2D_UPWIND) {
-        // band marches: power-of-two rows of 64..256 points, whole bands of
-        // 16 rows (at most 4 steps per slice: checked per method); streamed
-        // Krylov: 2048-point multiples, polynomial flavour, FP64
+        // band marches and uniformised exponentials: power-of-two rows of
+        // 64..256 points, whole bands of 16 rows (at most 4 steps per slice:
+        // checked per method); streamed Krylov: 2048-point multiples,
+        // polynomial or Taylor flavour; FP64
         if (p.nx < 64 || p.nx > 256 || !is_pow2(p.nx)) return PXP_EUNSUPPORTED;
         if (p.ny < BAND_ROWS || p.ny % BAND_ROWS) return PXP_EUNSUPPORTED;
-        if (grid_n(p) % (2 * KRYLOV2D_BLOCK)) return PXP_EUNSUPPORTED;
         if (p.vx < 0.0 || p.vy < 0.0 || !std::isfinite(p.vy)) return PXP_EUNSUPPORTED;
         if (p.prec != PXP_FP64) return PXP_EUNSUPPORTED;
         if (p.krylov == PXP_KRYLOV_SHIFT_INVERT) return PXP_EUNSUPPORTED;
-        if (p.m < 1 || krylov2d_lds_bytes(p.m) > 160 * 1024) return PXP_EUNSUPPORTED;
-        // the Taylor flavour keeps four vectors in the basis region
-        if (use_taylor(p) && p.m < 3) return PXP_EUNSUPPORTED;
+        if (p.krylov == PXP_KRYLOV_UNIFORM && p.sched == PXP_SCHED_CLASSIC)
+            return PXP_EUNSUPPORTED;
+        if (!uniform_direct(p) || !uniform_adjoint(p)) {
+            if (grid_n(p) % (2 * KRYLOV2D_BLOCK)) return PXP_EUNSUPPORTED;
+            if (p.m < 1 || krylov2d_lds_bytes(p.m) > 160 * 1024) return PXP_EUNSUPPORTED;
+            // the Taylor flavour keeps four vectors in the basis region
+            if (use_taylor(p) && p.m < 3) return PXP_EUNSUPPORTED;
+        }
         if (!(p.krylov_tol > 0.0)) return PXP_EINVAL;
         if (!rk4_stable_advdiff2d(p)) return PXP_EUNSTABLE_DT;
         return PXP_OK;
     }
     return PXP_EINVAL;
+}
+
+// ---- uniformisation: terms, Poisson tails, plans ---------------------------
+
+// Smallest D with the Poisson tail P(X >= D) <= tol (X of mean lam); *est
+// receives that tail.  Weights in log form, tail summed from the far end.
+int pois_terms(double lam, double tol, double* est) {
+    if (!(lam > 0.0)) {
+        if (est) *est = 0.0;
+        return 1;
+    }
+    const int K = (int)(lam + 40.0 * std::sqrt(lam) + 80.0);
+    std::vector<long double> pk(K + 1);
+    const long double ll = std::log((long double)lam);
+    for (int k = 0; k <= K; ++k)
+        pk[k] = std::exp((long double)k * ll - (long double)lam - std::lgamma((long double)k + 1.0L));
+    long double tail = 0.0L;
+    int D = K + 1;
+    double e = 0.0;
+    for (int k = K; k >= 1; --k) {
+        tail += pk[k];  // P(X >= k)
+        if (tail > (long double)tol) break;
+        D = k;
+        e = (double)tail;
+    }
+    if (est) *est = e;
+    return D;
+}
+
+// Largest Poisson parameter of one uniformised adjoint exponential: its
+// integral weights start from e^{-lam}, which must stay a normal double.
+constexpr double POIS_LMAX = 600.0;
+
+double uniform_mu(const Sten5& A) { return -A.c; }
+Sten5 uniform_N(const Sten5& A, double mu) {
+    Sten5 N;
+    N.c = 1.0 + A.c / mu;
+    N.w = A.w / mu;
+    N.e = A.e / mu;
+    N.s = A.s / mu;
+    N.n = A.n / mu;
+    return N;
+}
+double uniform_tail_tol(const pxp_problem& p) { return 1e-2 * p.krylov_tol; }
+
+// The adjoint piece over [0, T] by uniformisation: nsub equal substeps of
+// Poisson parameter lam <= POIS_LMAX, D terms each.
+struct AdjPlan {
+    int nsub, D;
+    double h, lam, est;
+};
+AdjPlan adj_plan(const pxp_problem& p) {
+    AdjPlan a{};
+    const double mu = uniform_mu(advdiff2d_sten(p));
+    a.nsub = std::max(1, (int)std::ceil(mu * p.T / POIS_LMAX));
+    a.h = p.T / a.nsub;
+    a.lam = mu * a.h;
+    a.D = pois_terms(a.lam, uniform_tail_tol(p), &a.est);
+    return a;
 }
 
 Inst inst_layout(const pxp_problem& p) {
@@ -245,9 +328,22 @@ Inst inst_layout(const pxp_problem& p) {
     }
     if (p.op == PXP_OP_ADVDIFF2D_UPWIND) {
         L.slices = take(P * n * d);
+        const bool ud = uniform_direct(p), ua = uniform_adjoint(p);
         const bool classic = p.sched == PXP_SCHED_CLASSIC && P > 1;
-        L.pieces = take((classic ? P - 1 : 1) * n * d);
-        L.basis = take((classic ? P - 1 : 1) * (m + 1) * n * d);
+        // tree: the levels alternate between the slices and these (P+1)/2
+        // vectors; chain: two vectors in turn
+        const size_t half = (P + 1) / 2;
+        const size_t np = ud ? (p.sched == PXP_SCHED_TREE ? half : 2) : (classic ? P - 1 : 1);
+        L.pieces = take(np * n * d);
+        if (!ud || !ua) L.basis = take(((!ud && classic) ? P - 1 : 1) * (m + 1) * n * d);
+        // term vectors of multi-pass exponentials, two per job (the
+        // adjoint's single piece needs two)
+        L.tbuf = take(2 * (ud ? std::max(np, (size_t)1) : 1) * n * d);
+        if (ua) {
+            const AdjPlan ap = adj_plan(p);
+            L.wtab = take((size_t)ap.nsub * 2 * ap.D * d);
+            L.ubuf = take(3 * n * d);
+        }
         L.sbuf0 = take(n * d);
         L.sbuf1 = take(n * d);
     }
@@ -275,6 +371,15 @@ Layout layout(const pxp_problem* pb, int batch) {
     off += align_up((size_t)batch * sizeof(KrylovArgs));
     Ly.t2d = off;
     off += align_up((size_t)batch * sizeof(Band2D));
+    // at most four entries per instance in one pass launch (pairs of two
+    // lengths, a pass-through, or the adjoint's piece)
+    Ly.ptab = off;
+    off += align_up((size_t)batch * 4 * sizeof(PoisEntry));
+    size_t nw = 0;
+    for (int i = 0; i < batch; ++i)
+        if (uniform_adjoint(pb[i])) nw += (size_t)adj_plan(pb[i]).nsub;
+    Ly.pwt = off;
+    off += align_up(nw * sizeof(PoisWeights));
     for (int i = 0; i < batch; ++i) {
         Ly.base.push_back(off);
         off += inst_layout(pb[i]).size;
@@ -883,6 +988,206 @@ const double* serial2d_result(const Band2D& d) {
     return d.buf[L & 1];
 }
 
+// ---- uniformised exponentials: jobs, stages and pass launches ---------------
+
+// nvec independent exponentials of one instance with the same Poisson
+// parameter: out_v = sum_{k<D} w_k N^k x_v + partner_v and, for two-sum jobs,
+// out2_v = sum_k w2_k N^k x_v + out2_add_v.  Vectors are s* doubles apart.
+struct PJob {
+    const double* x = nullptr;
+    int64_t sx = 0;
+    const double* partner = nullptr;
+    int64_t sp = 0;
+    double* out = nullptr;
+    int64_t so = 0;
+    const double* wtab = nullptr;
+    double* acc2 = nullptr;
+    double* out2 = nullptr;
+    const double* out2_add = nullptr;
+    const double* wtab2 = nullptr;
+    double* tb[2] = {nullptr, nullptr};  // term vectors of later passes
+    int nvec = 1, D = 1, nx = 0, ny = 0;
+    double lam = 0.0, est = 0.0;
+    Sten5 N{};
+    DevStatus* st = nullptr;
+};
+
+int pois_passes(int D) { return (D + POIS_PASS_TERMS - 1) / POIS_PASS_TERMS; }
+
+// One stage: independent jobs (any instances), run pass by pass; every pass
+// is one launch per (row length, one or two sums).  Output rows per band:
+// 32 when that still gives a few workgroups per CU, else 16.
+pxp_status run_stage(const std::vector<PJob>& jobs, PoisEntry* dtab, hipStream_t s) {
+    if (jobs.empty()) return PXP_OK;
+    int maxp = 0;
+    size_t blocks32 = 0;
+    bool all32 = true;
+    for (const PJob& j : jobs) {
+        maxp = std::max(maxp, pois_passes(j.D));
+        blocks32 += (size_t)j.nvec * (size_t)(j.ny / 32);
+        all32 = all32 && (j.ny % 32 == 0);
+    }
+    const int rows = (all32 && blocks32 >= 1024) ? 32 : 16;
+    for (int pass = 0; pass < maxp; ++pass) {
+        for (int two = 0; two < 2; ++two)
+            for (int nx : {64, 128, 256}) {
+                std::vector<PoisEntry> tab;
+                int blk = 0;
+                for (const PJob& j : jobs) {
+                    if (j.nx != nx || (j.out2 != nullptr) != (two != 0)) continue;
+                    if (pois_passes(j.D) <= pass) continue;
+                    const int64_t n = (int64_t)j.nx * j.ny;
+                    PoisEntry e{};
+                    e.k0 = pass * POIS_PASS_TERMS;
+                    e.k1 = std::min(j.D, e.k0 + POIS_PASS_TERMS);
+                    e.final_pass = (e.k1 == j.D) ? 1 : 0;
+                    e.tin = pass == 0 ? j.x : j.tb[(pass - 1) & 1];
+                    e.s_tin = pass == 0 ? j.sx : n;
+                    e.tout = j.tb[pass & 1];
+                    e.s_tout = n;
+                    e.partner = j.partner;
+                    e.s_partner = j.sp;
+                    e.acc = j.out;
+                    e.out = j.out;
+                    e.s_acc = e.s_out = j.so;
+                    e.wtab = j.wtab;
+                    e.acc2 = j.acc2;
+                    e.out2 = j.out2;
+                    e.out2_add = j.out2_add;
+                    e.wtab2 = j.wtab2;
+                    e.lam = j.lam;
+                    e.est = j.est;
+                    e.N = j.N;
+                    e.nvec = j.nvec;
+                    e.nx = j.nx;
+                    e.ny = j.ny;
+                    e.rows = rows;
+                    e.blk0 = blk;
+                    e.status = j.st;
+                    blk += j.nvec * (j.ny / rows);
+                    tab.push_back(e);
+                }
+                if (tab.empty()) continue;
+                const size_t bytes = tab.size() * sizeof(PoisEntry);
+                for (size_t o = 0; o < bytes; o += 3072)
+                    HIPCHK(launch_upload(reinterpret_cast<char*>(dtab) + o,
+                                         reinterpret_cast<const char*>(tab.data()) + o,
+                                         std::min((size_t)3072, bytes - o), s));
+                HIPCHK(launch_pois2d(dtab, (int)tab.size(), blk, nx, two, s));
+            }
+    }
+    return PXP_OK;
+}
+
+// Tree schedule of one instance's direct pieces: the levels of pairwise
+// combinations, each a list of jobs.  Level l reads buf[(l-1)&1] (buf[0] =
+// slices) and writes buf[l&1]; the root goes to qT.
+void tree_levels(const pxp_problem& p, const Ctx& c, double* qT,
+                 std::vector<std::vector<PJob>>& levels) {
+    const int64_t n = c.n();
+    const Sten5 A = advdiff2d_sten(p);
+    const double mu = uniform_mu(A), dT = p.T / p.P, tol = uniform_tail_tol(p);
+    double* buf[2] = {c.at(c.L.slices), c.at(c.L.pieces)};
+    double* tb0 = c.at(c.L.tbuf);
+    double* tb1 = tb0 + (size_t)((p.P + 1) / 2) * n;
+    std::vector<int> size(p.P, 1);
+    int l = 0;
+    while (size.size() > 1) {
+        ++l;
+        const int cnt = (int)size.size(), pairs = cnt / 2;
+        const double* src = buf[(l - 1) & 1];
+        double* dst = buf[l & 1];
+        const bool root = (pairs + (cnt & 1)) == 1;
+        std::vector<PJob> lv;
+        int j = 0;
+        while (j < pairs) {
+            // a run of pairs whose right-hand ranges have the same length
+            int j1 = j + 1;
+            while (j1 < pairs && size[2 * j1 + 1] == size[2 * j + 1]) ++j1;
+            PJob b;
+            b.nvec = j1 - j;
+            b.x = src + (size_t)(2 * j) * n;
+            b.sx = 2 * n;
+            b.partner = src + (size_t)(2 * j + 1) * n;
+            b.sp = 2 * n;
+            b.out = root ? qT : dst + (size_t)j * n;
+            b.so = n;
+            b.tb[0] = tb0 + (size_t)j * n;
+            b.tb[1] = tb1 + (size_t)j * n;
+            b.lam = mu * dT * size[2 * j + 1];
+            b.D = pois_terms(b.lam, tol, &b.est);
+            b.nx = p.nx;
+            b.ny = p.ny;
+            b.N = uniform_N(A, mu);
+            b.st = c.st;
+            lv.push_back(b);
+            j = j1;
+        }
+        if (cnt & 1) {  // the last range has no partner: carried over as is
+            PJob b;
+            b.x = src + (size_t)(cnt - 1) * n;
+            b.out = dst + (size_t)pairs * n;
+            b.so = b.sx = n;
+            b.tb[0] = tb0;
+            b.tb[1] = tb1;
+            b.lam = 0.0;
+            b.D = 1;
+            b.nx = p.nx;
+            b.ny = p.ny;
+            b.N = uniform_N(A, mu);
+            b.st = c.st;
+            lv.push_back(b);
+        }
+        levels.push_back(lv);
+        std::vector<int> ns;
+        for (int q = 0; q < pairs; ++q) ns.push_back(size[2 * q] + size[2 * q + 1]);
+        if (cnt & 1) ns.push_back(size[cnt - 1]);
+        size.swap(ns);
+    }
+}
+
+// Chain schedule by uniformisation: w <- exp(dT A) w + v_{p+1}, p = 0..P-2.
+void chain_levels(const pxp_problem& p, const Ctx& c, double* qT,
+                  std::vector<std::vector<PJob>>& levels) {
+    const int64_t n = c.n();
+    const Sten5 A = advdiff2d_sten(p);
+    const double mu = uniform_mu(A), dT = p.T / p.P;
+    const double* sl = c.at(c.L.slices);
+    double* cb[2] = {c.at(c.L.pieces), c.at(c.L.pieces) + n};
+    double* tb0 = c.at(c.L.tbuf);
+    PJob b;
+    b.lam = mu * dT;
+    b.D = pois_terms(b.lam, uniform_tail_tol(p), &b.est);
+    b.nx = p.nx;
+    b.ny = p.ny;
+    b.N = uniform_N(A, mu);
+    b.st = c.st;
+    b.tb[0] = tb0;
+    b.tb[1] = tb0 + n;
+    b.sx = b.sp = b.so = n;
+    for (int q = 0; q + 1 < p.P; ++q) {
+        b.x = q == 0 ? sl : cb[(q - 1) & 1];
+        b.partner = sl + (size_t)(q + 1) * n;
+        b.out = (q + 2 == p.P) ? qT : cb[q & 1];
+        levels.push_back({b});
+    }
+}
+
+// Stages of every instance run together: stage l holds level l of each.
+pxp_status run_levels(const std::vector<std::vector<std::vector<PJob>>>& per, PoisEntry* dtab,
+                      hipStream_t s) {
+    size_t depth = 0;
+    for (const auto& v : per) depth = std::max(depth, v.size());
+    for (size_t l = 0; l < depth; ++l) {
+        std::vector<PJob> stage;
+        for (const auto& v : per)
+            if (l < v.size()) stage.insert(stage.end(), v[l].begin(), v[l].end());
+        pxp_status st = run_stage(stage, dtab, s);
+        if (st != PXP_OK) return st;
+    }
+    return PXP_OK;
+}
+
 // Direct solve of the 2D instances idx: init (nullable) and F (nullable)
 // per instance -> qT.
 pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, void* ws,
@@ -940,12 +1245,33 @@ pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, v
         for (const Group2D& g : groups)
             HIPCHK(launch_band2d(dtab + g.first, g.count, g.blocks, g.nx, 0, 0, s));
     }
-    // (2) homogeneous pieces: classic (P-1 workgroups) or chain (one)
+    // (2) homogeneous pieces.  Uniformised: tree or chain stages of pass
+    // launches over every instance; their last stage writes q(T).
+    {
+        std::vector<std::vector<std::vector<PJob>>> per;
+        for (size_t j = 0; j < idx.size(); ++j) {
+            const pxp_problem& p = pb[idx[j]];
+            if (!uniform_direct(p) || p.P == 1) continue;
+            Ctx c = make_ctx(p, ws, Ly, idx[j], s);
+            per.emplace_back();
+            if (p.sched == PXP_SCHED_TREE)
+                tree_levels(p, c, qT[j], per.back());
+            else
+                chain_levels(p, c, qT[j], per.back());
+        }
+        if (!per.empty()) {
+            auto* dp = reinterpret_cast<PoisEntry*>(static_cast<char*>(ws) + Ly.ptab);
+            ProfScope ps(PXP_K_KRYLOV_DIRECT, s);
+            pxp_status st = run_levels(per, dp, s);
+            if (st != PXP_OK) return st;
+        }
+    }
+    // Krylov pieces: classic (P-1 workgroups) or chain (one)
     std::vector<KrylovArgs> kt;
     int kblk = 0;
     for (size_t j = 0; j < idx.size(); ++j) {
         const pxp_problem& p = pb[idx[j]];
-        if (p.P == 1) continue;
+        if (p.P == 1 || uniform_direct(p)) continue;
         Ctx c = make_ctx(p, ws, Ly, idx[j], s);
         KrylovArgs a = kargs(c, Tri{0.0, 0.0, 0.0});
         a.si = 0;
@@ -985,6 +1311,8 @@ pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, v
         const double* sl = c.at(c.L.slices);
         if (p.P == 1)
             HIPCHK(launch_recombine(nullptr, sl, nullptr, 0, n, qT[j], c.st, s));
+        else if (uniform_direct(p))
+            continue;  // written by the last stage
         else if (p.sched == PXP_SCHED_CLASSIC)
             HIPCHK(launch_recombine(nullptr, sl + (size_t)(p.P - 1) * n,
                                     c.at(c.L.pieces), p.P - 1, n, qT[j], c.st, s));
@@ -1035,11 +1363,88 @@ pxp_status adjoint_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, 
         return PXP_OK;
     }
     // one homogeneous piece per instance from q^dagger(T) over [T, 0]
-    // (eq. adjhomfinal), with Lambda formed in the Krylov space
+    // (eq. adjhomfinal).  Uniformised: substeps of at most POIS_LMAX, the
+    // time integral Lambda by the exact integral weights of every term.
+    {
+        std::vector<std::vector<std::vector<PJob>>> per;
+        std::vector<PoisWeights> wt;
+        for (size_t j = 0; j < idx.size(); ++j) {
+            const pxp_problem& p = pb[idx[j]];
+            if (!uniform_adjoint(p) || (!lam0[j] && !Lam[j])) continue;
+            Ctx c = make_ctx(p, ws, Ly, idx[j], s);
+            const int64_t n = c.n();
+            const AdjPlan ap = adj_plan(p);
+            const Sten5 AT = transpose5(advdiff2d_sten(p));
+            const double mu = uniform_mu(AT);
+            double* wbase = c.at(c.L.wtab);
+            double* ub = c.at(c.L.ubuf);
+            per.emplace_back();
+            for (int q = 0; q < ap.nsub; ++q) {
+                double* w = wbase + (size_t)q * 2 * ap.D;
+                if (Lam[j]) {
+                    PoisWeights pw{};
+                    pw.w = w;
+                    pw.wi = w + ap.D;
+                    pw.D = ap.D;
+                    pw.lam = ap.lam;
+                    pw.mu = mu;
+                    pw.omega = p.omega;
+                    pw.phi = p.omega * (p.T - q * ap.h);
+                    pw.scale = 1.0 / mu;
+                    wt.push_back(pw);
+                }
+                PJob b;
+                b.lam = ap.lam;
+                b.D = ap.D;
+                b.est = ap.est;
+                b.nx = p.nx;
+                b.ny = p.ny;
+                b.N = uniform_N(AT, mu);
+                b.st = c.st;
+                b.tb[0] = c.at(c.L.tbuf);
+                b.tb[1] = b.tb[0] + n;
+                b.sx = b.sp = b.so = n;
+                b.x = q == 0 ? lamT[j] : ub + (size_t)((q - 1) & 1) * n;
+                const bool last = q + 1 == ap.nsub;
+                if (ap.nsub == 1 && !lam0[j]) {
+                    // Lambda only: one sum with the integral weights
+                    b.out = Lam[j];
+                    b.wtab = w;
+                } else {
+                    b.out = (last && lam0[j]) ? lam0[j] : ub + (size_t)(q & 1) * n;
+                    if (Lam[j]) {
+                        b.wtab2 = w;
+                        b.out2 = Lam[j];
+                        // the second sum of later substeps builds beside
+                        // Lambda and is added to it at the end
+                        b.acc2 = q == 0 ? Lam[j] : ub + 2 * (size_t)n;
+                        b.out2_add = q == 0 ? nullptr : Lam[j];
+                    }
+                }
+                per.back().push_back({b});
+            }
+        }
+        if (!per.empty()) {
+            ProfScope ps(PXP_K_KRYLOV_ADJOINT, s);
+            if (!wt.empty()) {
+                auto* dw = reinterpret_cast<PoisWeights*>(static_cast<char*>(ws) + Ly.pwt);
+                const size_t bytes = wt.size() * sizeof(PoisWeights);
+                for (size_t o = 0; o < bytes; o += 3072)
+                    HIPCHK(launch_upload(reinterpret_cast<char*>(dw) + o,
+                                         reinterpret_cast<const char*>(wt.data()) + o,
+                                         std::min((size_t)3072, bytes - o), s));
+                HIPCHK(launch_pois_weights(dw, (int)wt.size(), s));
+            }
+            auto* dp = reinterpret_cast<PoisEntry*>(static_cast<char*>(ws) + Ly.ptab);
+            pxp_status st = run_levels(per, dp, s);
+            if (st != PXP_OK) return st;
+        }
+    }
     std::vector<KrylovArgs> kt;
     for (size_t j = 0; j < idx.size(); ++j) {
         const pxp_problem& p = pb[idx[j]];
         if (!lam0[j] && !Lam[j]) continue;
+        if (uniform_adjoint(p)) continue;
         Ctx c = make_ctx(p, ws, Ly, idx[j], s);
         KrylovArgs a = kargs(c, Tri{0.0, 0.0, 0.0});
         a.si = 0;
@@ -1302,9 +1707,10 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
     st = direct_2d_batch(pb, idx2, ws, Ly, i2, f2, o2, method, s);
     if (st != PXP_OK) return st;
     // (a5) cost and adjoint final condition
+    auto* dst = reinterpret_cast<DevStatus*>(static_cast<char*>(ws) + Ly.status);
     for (int i = 0; i < batch; ++i)
         HIPCHK(launch_cost(ip[i].qT, ip[i].tgt, ip[i].a, ip[i].n, ip[i].K, pb[i].beta,
-                           ip[i].lamT, J + i, s));
+                           ip[i].lamT, J + i, s, dst));
     // (a6-a8) adjoint
     std::vector<const double*> l2;
     std::vector<double*> z2, L2;
@@ -1336,7 +1742,7 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
         const bool forcing = (pb[i].ctrl == PXP_CTRL_FORCING);
         const double* v = forcing ? ip[i].Lam : ip[i].lam0;
         HIPCHK(launch_grad(ip[i].G, v, ip[i].a, ip[i].K, ip[i].n, pb[i].beta,
-                           grad + ip[i].koff, s));
+                           grad + ip[i].koff, s, dst));
         if (lam_out) HIPCHK(launch_add(nullptr, v, lam_out + ip[i].off, ip[i].n, s));
     }
     return PXP_OK;

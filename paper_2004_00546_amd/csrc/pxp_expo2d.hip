@@ -1,0 +1,273 @@
+// Exponential actions of the 2D five-point operator by uniformisation, split
+// over row bands (the homogeneous solves of paper section 3.1, eqs. hom and
+// adjHomNormal, for the 2D problem of section 4.2).
+//
+// With mu >= -A.c and nonnegative off-diagonal coefficients (upwind
+// advection with nonnegative velocities and the five-point Laplacian, and
+// the transposes of both), N = I + A / mu is a nonnegative matrix whose rows
+// and columns sum to one, and
+//     exp(tau A) x = sum_k p_k N^k x,   p_k = e^{-lam} lam^k / k!,  lam = mu tau.
+// Every term N^k x is bounded by |x| in the max norm and the weights are
+// positive with unit sum, so the series has no cancellation, and the part
+// left out after D terms is bounded a priori by the Poisson tail P(X >= D).
+// The number of terms is therefore fixed before the launch, and a band of
+// output rows can compute its part of D terms from its own rows plus D halo
+// rows on each side, recomputed redundantly: no workgroup waits for another.
+//
+// Workgroup layout: 8 waves; wave w holds region rows 8w .. 8w+7 (64 rows),
+// lane l columns l*CPL .. l*CPL+CPL-1 of each (CPL = NX/64), so a wave row is
+// a whole grid row and the periodic x neighbours are the next and previous
+// lanes (wrapping).  The y neighbours are in the same lane's registers except
+// at the wave's first and last rows, which are exchanged through LDS once per
+// term.  Output rows are region rows off .. off+R-1 (R = 16 or 32 rows per
+// band, off = (64 - R) / 2); a pass of d stencil applications needs d <= off
+// halo rows, and rows further out are garbage that never reaches the output.
+//
+// A pass covers terms k0 .. k1-1 of one or two weighted sums of the same
+// terms: the first (weights p_k, or a table) for exp(tau A) x, the second (a
+// table) for a time integral of the exponential (the adjoint's Lambda).
+#include "pxp_internal.hpp"
+#include "pxp_device.hpp"
+
+namespace pxp {
+namespace {
+
+constexpr int PW = 8;          // waves per workgroup
+constexpr int PNT = PW * WAVE;  // threads per workgroup
+constexpr int PRW = 8;          // region rows per wave
+constexpr int PROWS = PW * PRW;  // region rows
+
+static_assert(POIS_PASS_TERMS <= 16, "a pass needs at most 16 halo rows");
+
+// Poisson weight e^{-lam} lam^k / k! in log form (no underflow of e^{-lam}
+// for large lam; terms far below the peak flush to zero harmlessly).
+__device__ __forceinline__ double pois_pmf(double lam, int k) {
+    if (lam <= 0.0) return k == 0 ? 1.0 : 0.0;
+    return exp((double)k * log(lam) - lam - lgamma((double)k + 1.0));
+}
+
+__device__ __forceinline__ int pois_entry(const PoisEntry* tab, int count, int b) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].blk0 <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int NX, bool TWO>
+__global__ void __launch_bounds__(PNT) k_pois2d(const PoisEntry* __restrict__ tab, int count) {
+    constexpr int CPL = NX / WAVE;
+    __shared__ double xch[2][PW][2][NX];
+    __shared__ double wt[POIS_PASS_TERMS], wt2[POIS_PASS_TERMS];
+    const PoisEntry& E = tab[pois_entry(tab, count, blockIdx.x)];
+    const int ny = E.ny, R = E.rows, nb = ny / R;
+    const int local = blockIdx.x - E.blk0;
+    const int vec = local / nb, band = local - vec * nb;
+    const int off = (PROWS - R) / 2;
+    const int nterm = E.k1 - E.k0;
+    const int napp = E.final_pass ? nterm - 1 : nterm;
+    const int t = threadIdx.x, w = wave_id(), l = lane_id();
+    if (t < nterm) {
+        const int k = E.k0 + t;
+        wt[t] = E.wtab ? E.wtab[k] : pois_pmf(E.lam, k);
+        if (TWO) wt2[t] = E.wtab2[k];
+    }
+    // region row r <-> grid row band*R - off + r (periodic)
+    const int gr0 = band * R - off + w * PRW;
+    const int cbase = l * CPL;
+    const size_t vof = (size_t)vec;
+    const double* tin = E.tin + vof * E.s_tin;
+    double tv[PRW][CPL], acc[PRW][CPL], acc2[TWO ? PRW : 1][CPL];
+#pragma unroll
+    for (int i = 0; i < PRW; ++i) {
+        const int r = w * PRW + i;
+        int g = (gr0 + i) % ny;
+        if (g < 0) g += ny;
+        const bool need = r >= off - napp && r < off + R + napp;
+        const bool outrow = r >= off && r < off + R;
+        const size_t o = (size_t)g * NX + cbase;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            tv[i][c] = need ? tin[o + c] : 0.0;
+            acc[i][c] = (outrow && E.k0 > 0) ? E.acc[vof * E.s_acc + o + c] : 0.0;
+            if (TWO) acc2[i][c] = (outrow && E.k0 > 0) ? E.acc2[vof * E.s_acc + o + c] : 0.0;
+        }
+    }
+    const Sten5 N = E.N;
+    __syncthreads();  // weights visible
+    for (int j = 0; j < nterm; ++j) {
+        const double pj = wt[j];
+        const double qj = TWO ? wt2[j] : 0.0;
+#pragma unroll
+        for (int i = 0; i < PRW; ++i)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                acc[i][c] += pj * tv[i][c];
+                if (TWO) acc2[i][c] += qj * tv[i][c];
+            }
+        if (j >= napp) break;
+        // tv <- N tv: first and last rows through LDS (two slots, so one
+        // barrier per term: a slot is rewritten only after every wave has
+        // passed the barrier that follows its last read)
+        const int sl = j & 1;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            xch[sl][w][0][cbase + c] = tv[0][c];
+            xch[sl][w][1][cbase + c] = tv[PRW - 1][c];
+        }
+        __syncthreads();
+        double prev[CPL], nxt_edge[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            prev[c] = (w > 0) ? xch[sl][w - 1][1][cbase + c] : 0.0;
+            nxt_edge[c] = (w < PW - 1) ? xch[sl][w + 1][0][cbase + c] : 0.0;
+        }
+        const int lw = (l + WAVE - 1) & (WAVE - 1), le = (l + 1) & (WAVE - 1);
+#pragma unroll
+        for (int i = 0; i < PRW; ++i) {
+            double cur[CPL];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) cur[c] = tv[i][c];
+            const double wv = __shfl(cur[CPL - 1], lw, WAVE);
+            const double ev = __shfl(cur[0], le, WAVE);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const double xw = (c > 0) ? cur[c - 1] : wv;
+                const double xe = (c < CPL - 1) ? cur[c + 1] : ev;
+                const double xn = (i < PRW - 1) ? tv[i + 1][c] : nxt_edge[c];
+                tv[i][c] = N.c * cur[c] + N.w * xw + N.e * xe + N.s * prev[c] + N.n * xn;
+                prev[c] = cur[c];
+            }
+        }
+    }
+    // write back: output rows only
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < PRW; ++i) {
+        const int r = w * PRW + i;
+        if (r < off || r >= off + R) continue;
+        int g = (gr0 + i) % ny;
+        if (g < 0) g += ny;
+        const size_t o = (size_t)g * NX + cbase;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            if (E.final_pass) {
+                if (E.out) {
+                    const double v = acc[i][c] + (E.partner ? E.partner[vof * E.s_partner + o + c] : 0.0);
+                    E.out[vof * E.s_out + o + c] = v;
+                    bad |= !isfinite(v);
+                }
+                if (TWO) {
+                    const double v = acc2[i][c] + (E.out2_add ? E.out2_add[vof * E.s_out + o + c] : 0.0);
+                    E.out2[vof * E.s_out + o + c] = v;
+                    bad |= !isfinite(v);
+                }
+            } else {
+                E.tout[vof * E.s_tout + o + c] = tv[i][c];
+                E.acc[vof * E.s_acc + o + c] = acc[i][c];
+                if (TWO) E.acc2[vof * E.s_acc + o + c] = acc2[i][c];
+            }
+        }
+    }
+    if (E.final_pass && E.status) {
+        if (__any(bad) && l == 0) atomicOr(&E.status->flags, ST_NONFINITE);
+        if (local == 0 && t == 0)
+            atomicMax(&E.status->max_est, (unsigned long long)__double_as_longlong(E.est));
+    }
+}
+
+// Weights of the time integral int_0^h sin(phi - omega s) exp(s A) x ds of
+// one uniformised exponential (lam = mu h), in the form sum_k w_k N^k x:
+//   w_k = scale * Im( e^{i phi} alpha^{-(k+1)} R_k ),  alpha = 1 + i omega / mu,
+//   R_k = sum_{j > k} e^{-alpha lam} (alpha lam)^j / j!,  scale = 1 / mu,
+// which is int_0^lam of e^{-u} u^k / k! against the modulation, written with
+// the regularised incomplete gamma function of complex argument alpha lam.
+// R_k is summed from the far tail down (no cancellation).  One workgroup per
+// table, one thread.
+__global__ void k_pois_weights(const PoisWeights* __restrict__ tab) {
+    const PoisWeights& P = tab[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    const int D = P.D;
+    const double beta = P.omega / P.mu;
+    const double zr = P.lam, zi = P.lam * beta;  // z = alpha lam
+    // E_j by the forward recurrence from E_0 = e^{-z}, up to J well past D
+    const int J = D + 64 + (int)(8.0 * sqrt(P.lam));
+    double er = exp(-zr) * cos(zi), ei = -exp(-zr) * sin(zi);
+    // first pass: walk to J keeping nothing but the final value is not enough
+    // for a backward sum, so store E_j into the output table where j < D and
+    // accumulate the tail beyond D on the way
+    double tr = 0.0, ti = 0.0;  // sum_{j >= D} E_j
+    for (int j = 0; j <= J; ++j) {
+        if (j > 0) {
+            const double nr = (er * zr - ei * zi) / j, ni = (er * zi + ei * zr) / j;
+            er = nr;
+            ei = ni;
+        }
+        if (j < D) {
+            P.w[j] = er;
+            P.wi[j] = ei;
+        } else {
+            tr += er;
+            ti += ei;
+        }
+    }
+    // R_k = sum_{j > k} E_j, downwards from k = D-1; alpha^{-(k+1)} upwards
+    // is replaced by its value at D-1 carried down by multiplying with alpha
+    const double an = 1.0 + beta * beta;
+    // alpha^{-D} by repeated multiplication with 1/alpha
+    double pr = 1.0, pi = 0.0;
+    const double ir = 1.0 / an, ii = -beta / an;  // 1 / alpha
+    for (int k = 0; k < D; ++k) {
+        const double nr = pr * ir - pi * ii, ni = pr * ii + pi * ir;
+        pr = nr;
+        pi = ni;
+    }
+    const double cph = cos(P.phi), sph = sin(P.phi);
+    double Rr = tr, Ri = ti;  // R_{D-1}
+    for (int k = D - 1; k >= 0; --k) {
+        // c_k = scale Im(e^{i phi} alpha^{-(k+1)} R_k); here p = alpha^{-(k+1)}
+        const double ar = pr * Rr - pi * Ri, ai = pr * Ri + pi * Rr;
+        const double Ej_r = P.w[k], Ej_i = P.wi[k];
+        P.w[k] = P.scale * (sph * ar + cph * ai);
+        // R_{k-1} = R_k + E_k; alpha^{-k} = alpha^{-(k+1)} * alpha
+        Rr += Ej_r;
+        Ri += Ej_i;
+        const double nr = pr * 1.0 - pi * beta, ni = pr * beta + pi * 1.0;
+        pr = nr;
+        pi = ni;
+    }
+}
+
+template <int NX, bool TWO>
+hipError_t pois_launch(const PoisEntry* tab, int count, int blocks, hipStream_t s) {
+    k_pois2d<NX, TWO><<<blocks, PNT, 0, s>>>(tab, count);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_pois2d(const PoisEntry* tab, int count, int total_blocks, int nx, int two,
+                         hipStream_t s) {
+    if (count <= 0 || total_blocks <= 0) return hipSuccess;
+    switch (nx) {
+        case 64: return two ? pois_launch<64, true>(tab, count, total_blocks, s)
+                            : pois_launch<64, false>(tab, count, total_blocks, s);
+        case 128: return two ? pois_launch<128, true>(tab, count, total_blocks, s)
+                             : pois_launch<128, false>(tab, count, total_blocks, s);
+        case 256: return two ? pois_launch<256, true>(tab, count, total_blocks, s)
+                             : pois_launch<256, false>(tab, count, total_blocks, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pois_weights(const PoisWeights* tab, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    k_pois_weights<<<count, 64, 0, s>>>(tab);
+    return hipGetLastError();
+}
+
+}  // namespace pxp

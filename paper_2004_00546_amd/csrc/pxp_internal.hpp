@@ -198,6 +198,49 @@ hipError_t launch_krylov2d(const KrylovArgs* tab, int count, int total_blocks,
 size_t krylov2d_lds_bytes(int m);
 constexpr int KRYLOV2D_BLOCK = 1024;
 
+// ---- 2D exponential actions by uniformisation -------------------------------
+// exp(tau A) x = sum_k p_k N^k x with N = I + A / mu (mu >= -A.c, off-diagonal
+// coefficients >= 0, so N is nonnegative with unit row and column sums) and
+// p_k the Poisson weights of lam = mu tau.  One entry of a pass launch covers
+// `nvec` vectors (stride s_* doubles apart) of one row length; workgroups
+// blk0 .. blk0 + nvec * ny / rows - 1 of the launch belong to it.  A pass
+// covers terms k0 .. k1-1 (at most POIS_PASS_TERMS): the first pass starts
+// the sums from zero, later ones read them from acc / acc2; a non-final pass
+// writes N^{k1} x to tout and the sums back in place, the final one writes
+// out = sum + partner and out2 = sum2 + out2_add.
+constexpr int POIS_PASS_TERMS = 16;
+struct PoisEntry {
+    const double* tin;       // N^{k0} x (the input vector x when k0 == 0)
+    double* tout;            // N^{k1} x (non-final pass)
+    const double* partner;   // added to the final first sum (nullable)
+    double* acc;             // first sum between passes
+    double* out;             // final first sum (nullable: not wanted)
+    const double* wtab;      // weights of the first sum (null: Poisson of lam)
+    double* acc2;            // second sum between passes (two-sum launches)
+    double* out2;            // final second sum
+    const double* out2_add;  // added to the final second sum (nullable)
+    const double* wtab2;     // weights of the second sum
+    int64_t s_tin, s_tout, s_partner, s_acc, s_out;
+    double lam;              // Poisson parameter mu * tau
+    double est;              // a priori truncation bound (reported)
+    Sten5 N;                 // I + A / mu
+    int k0, k1, final_pass, nvec;
+    int nx, ny, rows, blk0;  // rows: output rows per band (16 or 32)
+    DevStatus* status;
+};
+hipError_t launch_pois2d(const PoisEntry* tab, int count, int total_blocks, int nx, int two,
+                         hipStream_t s);
+// Weight table of the time integral int_0^h sin(phi - omega s) exp(s A) x ds
+// of one uniformised exponential: w[k], k < D, so that the integral is
+// sum_k w_k N^k x (lam = mu h); wi is scratch of D doubles.
+struct PoisWeights {
+    double* w;
+    double* wi;
+    int D, pad;
+    double lam, mu, omega, phi, scale;
+};
+hipError_t launch_pois_weights(const PoisWeights* tab, int count, hipStream_t s);
+
 // ---- small kernels ---------------------------------------------------------
 // out[i] = base[i] (or 0) + sum_k a[k] basis[k*n + i]
 hipError_t launch_combine_basis(const double* a, const double* basis,
@@ -206,13 +249,16 @@ hipError_t launch_combine_basis(const double* a, const double* basis,
 // out = Op x (tridiagonal, periodic)
 hipError_t launch_apply_tri(const double* x, double* out, int n, Tri op,
                             hipStream_t s);
-// lamT = qT - tgt;  J = 1/2 |lamT|^2 + beta |a|^2 (one workgroup)
+// lamT = qT - tgt;  J = 1/2 |lamT|^2 + beta |a|^2 (one workgroup); a
+// non-finite J sets ST_NONFINITE in st (nullable)
 hipError_t launch_cost(const double* qT, const double* tgt, const double* a,
                        int n, int K, double beta, double* lamT, double* J,
-                       hipStream_t s);
-// grad[k] = <basis_k, v> + 2 beta a[k] (one workgroup per k)
+                       hipStream_t s, DevStatus* st = nullptr);
+// grad[k] = <basis_k, v> + 2 beta a[k] (one workgroup per k); a non-finite
+// component sets ST_NONFINITE in st (nullable)
 hipError_t launch_grad(const double* basis, const double* v, const double* a,
-                       int K, int n, double beta, double* grad, hipStream_t s);
+                       int K, int n, double beta, double* grad, hipStream_t s,
+                       DevStatus* st = nullptr);
 // out = q0 (or 0) + vlast + sum_{p<np} Y[p]   (checks finiteness)
 hipError_t launch_recombine(const double* q0, const double* vlast,
                             const double* Y, int np, int n, double* out,

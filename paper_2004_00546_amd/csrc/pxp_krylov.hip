@@ -228,6 +228,12 @@ struct Core {
         __syncthreads();
     }
 
+    // A NaN or infinite norm of a start vector ends the exponential early
+    // (nothing to propagate); it is recorded here so the caller learns of it.
+    __device__ __forceinline__ void flag_nonfinite(double x) {
+        if (t == 0 && a.status && !isfinite(x)) atomicOr(&a.status->flags, ST_NONFINITE);
+    }
+
     __device__ __forceinline__ void report(double est_rel, bool noconv, unsigned substeps,
                            unsigned iters) {
         if (t == 0 && a.status) {
@@ -807,7 +813,10 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
                 anorm = block_max(mx, S.red);
             }
             double nu = sqrt(block_sum(sumsq(u), S.red));
-            if (!(nu > 0.0)) return;
+            if (!(nu > 0.0)) {
+                this->flag_nonfinite(nu);
+                return;
+            }
             int ns = (int)ceil(tau * anorm / a.theta);
             if (ns < 1) ns = 1;
             const double h = tau / ns;
@@ -983,6 +992,7 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
         bd = false;
         for (int o = t; o < (m + 1) * m; o += B) S.H[o] = 0.0;
         if (!(beta > 0.0)) {
+            this->flag_nonfinite(beta);
             __syncthreads();
             return 0;
         }
@@ -1351,6 +1361,7 @@ struct Ctx2 : Core<Ctx2, false> {
         bd = false;
         for (int o = t; o < (m + 1) * m; o += B) S.H[o] = 0.0;
         if (!(beta > 0.0)) {
+            this->flag_nonfinite(beta);
             __syncthreads();
             return 0;
         }
@@ -1508,7 +1519,10 @@ struct Ctx2 : Core<Ctx2, false> {
         double* tA = V + 2 * (size_t)n;
         double* tB = V + 3 * (size_t)n;
         double nu = sqrt(block_sum(sumsq(u), S.red));
-        if (!(nu > 0.0)) return;
+        if (!(nu > 0.0)) {
+            this->flag_nonfinite(nu);
+            return;
+        }
         int ns = (int)ceil(tau * a.anorm / a.theta);
         if (ns < 1) ns = 1;
         const double h = tau / ns;

@@ -40,7 +40,7 @@ __global__ void k_apply_tri(const double* __restrict__ x, double* __restrict__ o
 __global__ void __launch_bounds__(256)
 k_cost(const double* __restrict__ qT, const double* __restrict__ tgt,
        const double* __restrict__ a, int n, int K, double beta,
-       double* __restrict__ lamT, double* __restrict__ J) {
+       double* __restrict__ lamT, double* __restrict__ J, DevStatus* st) {
     __shared__ double red[8];
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -52,21 +52,28 @@ k_cost(const double* __restrict__ qT, const double* __restrict__ tgt,
     for (int k = threadIdx.x; k < K; k += blockDim.x) r += a[k] * a[k];
     s = block_sum(s, red);
     r = block_sum(r, red);
-    if (threadIdx.x == 0) *J = 0.5 * s + beta * r;
+    if (threadIdx.x == 0) {
+        *J = 0.5 * s + beta * r;
+        // every method's q(T) passes through here
+        if (st && !isfinite(s + r)) atomicOr(&st->flags, ST_NONFINITE);
+    }
 }
 
 // One workgroup per control k: grad[k] = <basis_k, v> + 2 beta a[k].
 __global__ void __launch_bounds__(256)
 k_grad(const double* __restrict__ basis, const double* __restrict__ v,
        const double* __restrict__ a, int n, double beta,
-       double* __restrict__ grad) {
+       double* __restrict__ grad, DevStatus* st) {
     __shared__ double red[8];
     const int k = blockIdx.x;
     const double* b = basis + (size_t)k * n;
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) s += b[i] * v[i];
     s = block_sum(s, red);
-    if (threadIdx.x == 0) grad[k] = s + 2.0 * beta * a[k];
+    if (threadIdx.x == 0) {
+        grad[k] = s + 2.0 * beta * a[k];
+        if (st && !isfinite(grad[k])) atomicOr(&st->flags, ST_NONFINITE);
+    }
 }
 
 __global__ void k_recombine(const double* __restrict__ q0,
@@ -114,15 +121,16 @@ hipError_t launch_apply_tri(const double* x, double* out, int n, Tri op,
 
 hipError_t launch_cost(const double* qT, const double* tgt, const double* a,
                        int n, int K, double beta, double* lamT, double* J,
-                       hipStream_t s) {
-    k_cost<<<1, 256, 0, s>>>(qT, tgt, a, n, K, beta, lamT, J);
+                       hipStream_t s, DevStatus* st) {
+    k_cost<<<1, 256, 0, s>>>(qT, tgt, a, n, K, beta, lamT, J, st);
     return hipGetLastError();
 }
 
 hipError_t launch_grad(const double* basis, const double* v, const double* a,
-                       int K, int n, double beta, double* grad, hipStream_t s) {
+                       int K, int n, double beta, double* grad, hipStream_t s,
+                       DevStatus* st) {
     if (K <= 0) return hipSuccess;
-    k_grad<<<K, 256, 0, s>>>(basis, v, a, n, beta, grad);
+    k_grad<<<K, 256, 0, s>>>(basis, v, a, n, beta, grad, st);
     return hipGetLastError();
 }
 

@@ -27,3 +27,13 @@ def orc():
     import oracle
     oracle.build()
     return oracle
+
+
+def rel_max(x, ref):
+    """Largest pointwise error relative to the largest |ref|: catches a
+    localised error that a relative L2 norm over many points would dilute."""
+    import numpy as np
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = np.max(np.abs(ref)) if ref.size else 0.0
+    return float(np.max(np.abs(x - ref)) / (den if den > 0 else 1.0)) if ref.size else 0.0

@@ -121,3 +121,24 @@ def test_graph_replay_two_launch_groups(torch):
             assert np.array_equal(got["qT"], want["qT"]), rep
         r.run()
         torch.cuda.synchronize()
+
+
+def test_autograd_two_forwards_then_backward(torch, orc):
+    """Two Burgers forwards at different controls, then one backward through
+    both: each backward must read its own forward's checkpoints."""
+    from paper_2004_00546_amd.autograd import Problem, paraexp_loss
+    base = workloads.make("burgers1d_n2048")[0]
+    inst = workloads.scaled(base, n_steps=1024, T=0.25, P=16)
+    prob = Problem(inst, krylov="auto", tol=1e-10)
+    a1 = torch.tensor(inst["a"], dtype=torch.float64, device="cuda:0", requires_grad=True)
+    a2v = np.asarray(inst["a"]) * -1.5 + 0.01
+    a2 = torch.tensor(a2v, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    J1 = paraexp_loss(a1, prob)
+    J2 = paraexp_loss(a2, prob)
+    (J1 + 2.0 * J2).backward()
+    w1 = orc.gradient(inst)
+    w2 = orc.gradient(dict(inst, a=a2v))
+    e1 = rel(a1.grad.cpu().numpy(), w1["grad"])
+    e2 = rel(a2.grad.cpu().numpy() / 2.0, w2["grad"])
+    print("two forwards: grad errors %.2e %.2e" % (e1, e2), flush=True)
+    assert e1 < 1e-8 and e2 < 1e-8

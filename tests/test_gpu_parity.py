@@ -567,3 +567,55 @@ def test_taylor_flavour_matches_oracle(torch, orc, case):
     say("taylor %s: grad %.2e status %d" % (case, e, got["status"]))
     assert got["status"] == 0
     assert e < FP64_GATE
+
+
+# ---- non-finite inputs reach the device status ------------------------------
+
+@pytest.mark.parametrize("case", ["advdiff_paraexp", "advdiff_serial", "burgers_paraexp",
+                                  "burgers_serial"])
+def test_nan_input_sets_nonfinite_status(torch, case):
+    """A NaN in the initial state must come back as PXP_ENONFINITE (not a
+    silent NaN gradient with PXP_OK) on every path."""
+    if case.startswith("advdiff"):
+        inst = small_advdiff(n=128, T=0.25, nt=250, P=5)
+        q0 = np.zeros(inst["nx"])
+        q0[17] = np.nan
+        inst = dict(inst, q0=q0)
+    else:
+        inst = small_burgers()
+        inst = dict(inst, q0=np.zeros(inst["nx"]))
+        inst["q0"][5] = np.nan
+    method = "serial" if case.endswith("serial") else "paraexp"
+    say("nan input: %s" % case)
+    r = api.GradientRunner([inst], method=method, krylov="auto", tol=1e-10)
+    r.run()
+    code, _ = r.status()
+    assert code == _lib.PXP_ENONFINITE, (case, code)
+    # the status is cleared by the read: a clean run reports OK again
+    r2 = api.GradientRunner([dict(inst, q0=np.zeros(inst["nx"]))], method=method,
+                            krylov="auto", tol=1e-10)
+    r2.run()
+    assert r2.status()[0] == _lib.PXP_OK
+
+
+# ---- the one-call boundary entry point ----------------------------------------
+
+@pytest.mark.parametrize("wl", ["advdiff1d_n128", "advdiff1d_n4096"])
+def test_gradient_entry_point_matches_oracle(torch, orc, wl):
+    """gradient() (include/paraexp.h) called through ctypes on the workload as
+    stated, compared with the oracle at the FP64 gate."""
+    inst = workloads.make(wl)[0]
+    r = api.GradientRunner([inst], method="paraexp", krylov="auto", tol=1e-9)
+    say("gradient() on %s" % wl)
+    _lib.gradient(r.problems, r.ctrl, r.basis, r.q0, r.u_tgt, r.J, r.grad, r.qT, r.ws)
+    got = r.results()[0]
+    code, est = r.status()
+    want = orc.gradient(inst)
+    eg, eq = rel(got["grad"], want["grad"]), rel(got["qT"], want["qT"])
+    say("  grad %.2e  qT %.2e  J %.2e  status %d" % (eg, eq, abs(got["J"] - want["J"]) /
+                                                     abs(want["J"]), code))
+    assert code == 0
+    assert eg <= FP64_GATE and eq <= FP64_GATE
+    assert abs(got["J"] - want["J"]) <= FP64_GATE * abs(want["J"])
+    # no single component far off either (max-abs relative to the largest)
+    assert np.max(np.abs(got["grad"] - want["grad"])) <= FP64_GATE * np.max(np.abs(want["grad"]))
