@@ -8,7 +8,9 @@
 #include <complex>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/paraexp.h"
@@ -26,6 +28,7 @@ struct Layout {
     size_t status;             // DevStatus
     size_t btab, ktab, t2d;    // batch tables: Burgers, Krylov, 2D marches
     size_t ptab, pwt;          // uniformised exponentials: pass entries, weights
+    size_t rtab, rpart;        // batched cost/gradient: descriptors, partial sums
     std::vector<size_t> base;  // per-instance region offset
     size_t total;
 };
@@ -151,6 +154,29 @@ bool uniform_adjoint(const pxp_problem& p) {
     return p.krylov == PXP_KRYLOV_UNIFORM || p.krylov == PXP_KRYLOV_AUTO;
 }
 
+// The RK4 stability checks above visit every Fourier mode of the grid
+// (65536 for a 256 x 256 grid): their results are remembered per operator,
+// grid, horizon and step count, so repeated calls on the same problem pay
+// for the check once.  The cache is process-wide and bounded.
+using StabKey = std::tuple<int, int, int, double, double, double, double, double, int64_t>;
+std::mutex g_stab_mu;
+std::map<StabKey, bool> g_stab;
+
+bool rk4_stable_cached(const pxp_problem& p) {
+    const StabKey k{p.op, p.nx, p.ny, p.L, p.vx, p.vy, p.nu, p.T, p.n_steps};
+    {
+        std::lock_guard<std::mutex> lock(g_stab_mu);
+        auto it = g_stab.find(k);
+        if (it != g_stab.end()) return it->second;
+    }
+    const bool ok = p.op == PXP_OP_ADVDIFF2D_UPWIND ? rk4_stable_advdiff2d(p)
+                                                    : rk4_stable_advdiff1d(p);
+    std::lock_guard<std::mutex> lock(g_stab_mu);
+    if (g_stab.size() >= 4096) g_stab.clear();
+    g_stab[k] = ok;
+    return ok;
+}
+
 // Taylor flavour: named, or AUTO where neither shift-and-invert nor
 // uniformisation is taken.
 bool use_taylor(const pxp_problem& p) {
@@ -197,7 +223,7 @@ pxp_status validate(const pxp_problem& p) {
         if (use_si(p) && (!is_pow2(p.nx) || p.nx < 64)) return PXP_EUNSUPPORTED;
         if (!(p.krylov_tol > 0.0)) return PXP_EINVAL;
         if (!krylov_fits(p, use_si(p))) return PXP_EUNSUPPORTED;
-        if (!rk4_stable_advdiff1d(p)) return PXP_EUNSTABLE_DT;
+        if (!rk4_stable_cached(p)) return PXP_EUNSTABLE_DT;
         return PXP_OK;
     }
     if (p.op == PXP_OP_BURGERS1D) {
@@ -233,7 +259,7 @@ pxp_status validate(const pxp_problem& p) {
             if (use_taylor(p) && p.m < 3) return PXP_EUNSUPPORTED;
         }
         if (!(p.krylov_tol > 0.0)) return PXP_EINVAL;
-        if (!rk4_stable_advdiff2d(p)) return PXP_EUNSTABLE_DT;
+        if (!rk4_stable_cached(p)) return PXP_EUNSTABLE_DT;
         return PXP_OK;
     }
     return PXP_EINVAL;
@@ -243,7 +269,33 @@ pxp_status validate(const pxp_problem& p) {
 
 // Smallest D with the Poisson tail P(X >= D) <= tol (X of mean lam); *est
 // receives that tail.  Weights in log form, tail summed from the far end.
+int pois_terms_uncached(double lam, double tol, double* est);
+
+// pois_terms is called for every job of every call; its result depends on
+// (lam, tol) only and is remembered (process-wide, bounded).
+std::mutex g_pois_mu;
+std::map<std::pair<double, double>, std::pair<int, double>> g_pois;
+
 int pois_terms(double lam, double tol, double* est) {
+    const std::pair<double, double> k{lam, tol};
+    {
+        std::lock_guard<std::mutex> lock(g_pois_mu);
+        auto it = g_pois.find(k);
+        if (it != g_pois.end()) {
+            if (est) *est = it->second.second;
+            return it->second.first;
+        }
+    }
+    double e = 0.0;
+    const int D = pois_terms_uncached(lam, tol, &e);
+    std::lock_guard<std::mutex> lock(g_pois_mu);
+    if (g_pois.size() >= 4096) g_pois.clear();
+    g_pois[k] = {D, e};
+    if (est) *est = e;
+    return D;
+}
+
+int pois_terms_uncached(double lam, double tol, double* est) {
     if (!(lam > 0.0)) {
         if (est) *est = 0.0;
         return 1;
@@ -380,6 +432,13 @@ Layout layout(const pxp_problem* pb, int batch) {
         if (uniform_adjoint(pb[i])) nw += (size_t)adj_plan(pb[i]).nsub;
     Ly.pwt = off;
     off += align_up(nw * sizeof(PoisWeights));
+    Ly.rtab = off;
+    off += align_up((size_t)batch * sizeof(RedDesc));
+    size_t np = 0;
+    for (int i = 0; i < batch; ++i)
+        np += (size_t)(pb[i].K + 1) * (size_t)((grid_n(pb[i]) + RED_CHUNK - 1) / RED_CHUNK);
+    Ly.rpart = off;
+    off += align_up(np * sizeof(double));
     for (int i = 0; i < batch; ++i) {
         Ly.base.push_back(off);
         off += inst_layout(pb[i]).size;
@@ -943,10 +1002,25 @@ struct Group2D {
     int first, count, blocks, nx;
 };
 
+// Output rows per band workgroup for a launch: 32 when every grid allows
+// it and the launch still has a few workgroups per CU, else 16 (more,
+// shorter workgroups for the latency-bound serial marches).
+void band_rows(std::vector<Band2D>& tab) {
+    size_t blocks32 = 0;
+    bool all32 = true;
+    for (const Band2D& d : tab) {
+        blocks32 += (size_t)d.items * (size_t)(d.ny / 32);
+        all32 = all32 && d.ny % 32 == 0;
+    }
+    const int rows = (all32 && blocks32 >= 1024) ? 32 : BAND_ROWS;
+    for (Band2D& d : tab) d.rows = rows;
+}
+
 std::vector<Group2D> group2d(std::vector<Band2D>& tab) {
+    band_rows(tab);
     std::vector<Group2D> g;
     for (int j = 0; j < (int)tab.size(); ++j) {
-        const int nb = tab[j].items * (tab[j].ny / BAND_ROWS);
+        const int nb = tab[j].items * (tab[j].ny / tab[j].rows);
         if (g.empty() || g.back().nx != tab[j].nx) g.push_back({j, 0, 0, tab[j].nx});
         tab[j].blk0 = g.back().blocks;
         g.back().blocks += nb;
@@ -1528,6 +1602,14 @@ static pxp_status direct_impl(const pxp_problem* pb, int32_t batch,
     if (st != PXP_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     size_t off = 0;
+    // the 2D kernels move whole rows with 16-byte accesses
+    for (int i = 0; i < batch; ++i) {
+        if (pb[i].op == PXP_OP_ADVDIFF2D_UPWIND &&
+            (!aligned16(q0, off) || !aligned16(F, off) || !aligned16(qT, off)))
+            return PXP_EINVAL;
+        off += (size_t)grid_n(pb[i]);
+    }
+    off = 0;
     const std::vector<int> idx2 = batch2d(pb, batch);
     std::vector<const double*> i2, f2;
     std::vector<double*> o2;
@@ -1640,6 +1722,10 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
             const pxp_problem& p = pb[i];
             const int n = (int)grid_n(p), K = p.K;
             if (K > 0 && (!ctrl || !basis)) return PXP_EINVAL;
+            // the 2D kernels move whole rows with 16-byte accesses
+            if (p.op == PXP_OP_ADVDIFF2D_UPWIND &&
+                (!aligned16(q0, off) || !aligned16(qT, off) || !aligned16(u_tgt, off)))
+                return PXP_EINVAL;
             Ctx c = make_ctx(p, ws, Ly, i, s);
             IP& x = ip[i];
             x.a = ctrl ? ctrl + koff : nullptr;
@@ -1706,11 +1792,41 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
     }
     st = direct_2d_batch(pb, idx2, ws, Ly, i2, f2, o2, method, s);
     if (st != PXP_OK) return st;
-    // (a5) cost and adjoint final condition
+    // (a5) cost and adjoint final condition, every instance in two launches
     auto* dst = reinterpret_cast<DevStatus*>(static_cast<char*>(ws) + Ly.status);
-    for (int i = 0; i < batch; ++i)
-        HIPCHK(launch_cost(ip[i].qT, ip[i].tgt, ip[i].a, ip[i].n, ip[i].K, pb[i].beta,
-                           ip[i].lamT, J + i, s, dst));
+    std::vector<RedDesc> rd(batch);
+    int bcost = 0, bgrad = 0;
+    {
+        int64_t po = 0;
+        for (int i = 0; i < batch; ++i) {
+            RedDesc& d = rd[i];
+            const bool forcing = (pb[i].ctrl == PXP_CTRL_FORCING);
+            d.qT = ip[i].qT;
+            d.tgt = ip[i].tgt;
+            d.lamT = ip[i].lamT;
+            d.a = ip[i].a;
+            d.J = J + i;
+            d.basis = ip[i].G;
+            d.v = forcing ? ip[i].Lam : ip[i].lam0;
+            d.grad = grad + ip[i].koff;
+            d.beta = pb[i].beta;
+            d.st = dst;
+            d.n = ip[i].n;
+            d.K = ip[i].K;
+            d.chunks = (d.n + RED_CHUNK - 1) / RED_CHUNK;
+            d.blk0_cost = bcost;
+            d.blk0_grad = bgrad;
+            d.part0 = po;
+            d.gpart0 = po + d.chunks;
+            po += (int64_t)(d.K + 1) * d.chunks;
+            bcost += d.chunks;
+            bgrad += d.K * d.chunks;
+        }
+    }
+    auto* drd = reinterpret_cast<RedDesc*>(static_cast<char*>(ws) + Ly.rtab);
+    double* rpart = reinterpret_cast<double*>(static_cast<char*>(ws) + Ly.rpart);
+    HIPCHK(launch_upload(drd, rd.data(), rd.size() * sizeof(RedDesc), s));
+    HIPCHK(launch_cost_batch(drd, batch, bcost, rpart, s));
     // (a6-a8) adjoint
     std::vector<const double*> l2;
     std::vector<double*> z2, L2;
@@ -1737,14 +1853,11 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
     }
     st = adjoint_2d_batch(pb, idx2, ws, Ly, l2, z2, L2, method, s);
     if (st != PXP_OK) return st;
-    // (a9) gradient
-    for (int i = 0; i < batch; ++i) {
-        const bool forcing = (pb[i].ctrl == PXP_CTRL_FORCING);
-        const double* v = forcing ? ip[i].Lam : ip[i].lam0;
-        HIPCHK(launch_grad(ip[i].G, v, ip[i].a, ip[i].K, ip[i].n, pb[i].beta,
-                           grad + ip[i].koff, s, dst));
-        if (lam_out) HIPCHK(launch_add(nullptr, v, lam_out + ip[i].off, ip[i].n, s));
-    }
+    // (a9) gradient, every instance in two launches
+    HIPCHK(launch_grad_batch(drd, batch, bgrad, rpart, s));
+    if (lam_out)
+        for (int i = 0; i < batch; ++i)
+            HIPCHK(launch_add(nullptr, rd[i].v, lam_out + ip[i].off, ip[i].n, s));
     return PXP_OK;
 }
 

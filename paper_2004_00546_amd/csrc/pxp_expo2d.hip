@@ -14,28 +14,22 @@
 // output rows can compute its part of D terms from its own rows plus D halo
 // rows on each side, recomputed redundantly: no workgroup waits for another.
 //
-// Workgroup layout: 8 waves; wave w holds region rows 8w .. 8w+7 (64 rows),
-// lane l columns l*CPL .. l*CPL+CPL-1 of each (CPL = NX/64), so a wave row is
-// a whole grid row and the periodic x neighbours are the next and previous
-// lanes (wrapping).  The y neighbours are in the same lane's registers except
-// at the wave's first and last rows, which are exchanged through LDS once per
-// term.  Output rows are region rows off .. off+R-1 (R = 16 or 32 rows per
-// band, off = (64 - R) / 2); a pass of d stencil applications needs d <= off
-// halo rows, and rows further out are garbage that never reaches the output.
+// Workgroup layout: the row bands of pxp_band.hpp (8 waves of 8 rows, whole
+// grid rows per wave row, edge rows through LDS once per term).  Output rows
+// are region rows off .. off+R-1 (R = 16 or 32 rows per band, off =
+// (64 - R) / 2); a pass of d stencil applications needs d <= off halo rows,
+// and rows further out never reach the output.  N has a zero diagonal
+// (mu = -A.c), so a term costs four multiply-adds per point.
 //
 // A pass covers terms k0 .. k1-1 of one or two weighted sums of the same
 // terms: the first (weights p_k, or a table) for exp(tau A) x, the second (a
 // table) for a time integral of the exponential (the adjoint's Lambda).
 #include "pxp_internal.hpp"
 #include "pxp_device.hpp"
+#include "pxp_band.hpp"
 
 namespace pxp {
 namespace {
-
-constexpr int PW = 8;          // waves per workgroup
-constexpr int PNT = PW * WAVE;  // threads per workgroup
-constexpr int PRW = 8;          // region rows per wave
-constexpr int PROWS = PW * PRW;  // region rows
 
 static_assert(POIS_PASS_TERMS <= 16, "a pass needs at most 16 halo rows");
 
@@ -59,76 +53,71 @@ __device__ __forceinline__ int pois_entry(const PoisEntry* tab, int count, int b
 }
 
 template <int NX, bool TWO>
-__global__ void __launch_bounds__(PNT) k_pois2d(const PoisEntry* __restrict__ tab, int count) {
+__global__ void __launch_bounds__(BNT) k_pois2d(const PoisEntry* __restrict__ tab, int count) {
     constexpr int CPL = NX / WAVE;
-    __shared__ double xch[2][PW][2][NX];
+    __shared__ double xch[BW][2][NX];
     __shared__ double wt[POIS_PASS_TERMS], wt2[POIS_PASS_TERMS];
     const PoisEntry& E = tab[pois_entry(tab, count, blockIdx.x)];
     const int ny = E.ny, R = E.rows, nb = ny / R;
     const int local = blockIdx.x - E.blk0;
     const int vec = local / nb, band = local - vec * nb;
-    const int off = (PROWS - R) / 2;
+    const int off = (BROWS - R) / 2;
     const int nterm = E.k1 - E.k0;
     const int napp = E.final_pass ? nterm - 1 : nterm;
-    const int t = threadIdx.x, w = wave_id(), l = lane_id();
+    const int t = threadIdx.x, w = wave_id(), l = lane_id(), cb = l * CPL;
     if (t < nterm) {
         const int k = E.k0 + t;
         wt[t] = E.wtab ? E.wtab[k] : pois_pmf(E.lam, k);
         if (TWO) wt2[t] = E.wtab2[k];
     }
-    // region row r <-> grid row band*R - off + r (periodic)
-    const int gr0 = band * R - off + w * PRW;
-    const int cbase = l * CPL;
+    // region row r <-> grid row band*R - off + r (periodic); every region
+    // row is a grid row, so the loads are in bounds and issued together, and
+    // rows beyond the pass's halo never reach the output
+    int g[BRW];
+    wave_rows(band_grow(band * R - off + w * BRW, 0, ny), ny, g);
     const size_t vof = (size_t)vec;
     const double* tin = E.tin + vof * E.s_tin;
-    double tv[PRW][CPL], acc[PRW][CPL], acc2[TWO ? PRW : 1][CPL];
+    double tv[BRW][CPL], acc[BRW][CPL], acc2[TWO ? BRW : 1][CPL];
 #pragma unroll
-    for (int i = 0; i < PRW; ++i) {
-        const int r = w * PRW + i;
-        int g = (gr0 + i) % ny;
-        if (g < 0) g += ny;
-        const bool need = r >= off - napp && r < off + R + napp;
-        const bool outrow = r >= off && r < off + R;
-        const size_t o = (size_t)g * NX + cbase;
+    for (int i = 0; i < BRW; ++i) row_load<CPL>(tin + (size_t)g[i] * NX + cb, tv[i]);
+    const bool cont = E.k0 > 0;
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            tv[i][c] = need ? tin[o + c] : 0.0;
-            acc[i][c] = (outrow && E.k0 > 0) ? E.acc[vof * E.s_acc + o + c] : 0.0;
-            if (TWO) acc2[i][c] = (outrow && E.k0 > 0) ? E.acc2[vof * E.s_acc + o + c] : 0.0;
+    for (int i = 0; i < BRW; ++i) {
+        const int r = w * BRW + i;
+        const bool orow = r >= off && r < off + R;
+        if (cont && orow) {
+            row_load<CPL>(E.acc + vof * E.s_acc + (size_t)g[i] * NX + cb, acc[i]);
+            if (TWO) row_load<CPL>(E.acc2 + vof * E.s_acc + (size_t)g[i] * NX + cb, acc2[i]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                acc[i][c] = 0.0;
+                if (TWO) acc2[i][c] = 0.0;
+            }
         }
     }
-    const Sten5 N = E.N;
+    // N = I + A/mu has a zero diagonal for mu = -A.c
+    const double Nw = E.N.w, Ne = E.N.e, Ns = E.N.s, Nn = E.N.n;
+    const int lw = (l + WAVE - 1) & (WAVE - 1), le = (l + 1) & (WAVE - 1);
     __syncthreads();  // weights visible
     for (int j = 0; j < nterm; ++j) {
         const double pj = wt[j];
         const double qj = TWO ? wt2[j] : 0.0;
 #pragma unroll
-        for (int i = 0; i < PRW; ++i)
+        for (int i = 0; i < BRW; ++i)
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 acc[i][c] += pj * tv[i][c];
                 if (TWO) acc2[i][c] += qj * tv[i][c];
             }
         if (j >= napp) break;
-        // tv <- N tv: first and last rows through LDS (two slots, so one
-        // barrier per term: a slot is rewritten only after every wave has
-        // passed the barrier that follows its last read)
-        const int sl = j & 1;
+        // tv <- N tv; waves whose rows are no longer needed skip it
+        double prev[CPL], dn[CPL];
+        exchange_edges<NX, CPL>(xch, tv, w, cb, prev, dn);
+        const int keep = napp - 1 - j;
+        if (w * BRW + BRW <= off - keep || w * BRW >= off + R + keep) continue;
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            xch[sl][w][0][cbase + c] = tv[0][c];
-            xch[sl][w][1][cbase + c] = tv[PRW - 1][c];
-        }
-        __syncthreads();
-        double prev[CPL], nxt_edge[CPL];
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            prev[c] = (w > 0) ? xch[sl][w - 1][1][cbase + c] : 0.0;
-            nxt_edge[c] = (w < PW - 1) ? xch[sl][w + 1][0][cbase + c] : 0.0;
-        }
-        const int lw = (l + WAVE - 1) & (WAVE - 1), le = (l + 1) & (WAVE - 1);
-#pragma unroll
-        for (int i = 0; i < PRW; ++i) {
+        for (int i = 0; i < BRW; ++i) {
             double cur[CPL];
 #pragma unroll
             for (int c = 0; c < CPL; ++c) cur[c] = tv[i][c];
@@ -138,39 +127,53 @@ __global__ void __launch_bounds__(PNT) k_pois2d(const PoisEntry* __restrict__ ta
             for (int c = 0; c < CPL; ++c) {
                 const double xw = (c > 0) ? cur[c - 1] : wv;
                 const double xe = (c < CPL - 1) ? cur[c + 1] : ev;
-                const double xn = (i < PRW - 1) ? tv[i + 1][c] : nxt_edge[c];
-                tv[i][c] = N.c * cur[c] + N.w * xw + N.e * xe + N.s * prev[c] + N.n * xn;
+                const double xn = (i < BRW - 1) ? tv[i + 1][c] : dn[c];
+                tv[i][c] = Nw * xw + Ne * xe + Ns * prev[c] + Nn * xn;
                 prev[c] = cur[c];
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
     // write back: output rows only
     bool bad = false;
 #pragma unroll
-    for (int i = 0; i < PRW; ++i) {
-        const int r = w * PRW + i;
+    for (int i = 0; i < BRW; ++i) {
+        const int r = w * BRW + i;
         if (r < off || r >= off + R) continue;
-        int g = (gr0 + i) % ny;
-        if (g < 0) g += ny;
-        const size_t o = (size_t)g * NX + cbase;
+        const size_t o = (size_t)g[i] * NX + cb;
+        if (E.final_pass) {
+            if (E.out) {
+                double v[CPL];
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            if (E.final_pass) {
-                if (E.out) {
-                    const double v = acc[i][c] + (E.partner ? E.partner[vof * E.s_partner + o + c] : 0.0);
-                    E.out[vof * E.s_out + o + c] = v;
-                    bad |= !isfinite(v);
+                for (int c = 0; c < CPL; ++c) v[c] = acc[i][c];
+                if (E.partner) {
+                    double q[CPL];
+                    row_load<CPL>(E.partner + vof * E.s_partner + o, q);
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) v[c] += q[c];
                 }
-                if (TWO) {
-                    const double v = acc2[i][c] + (E.out2_add ? E.out2_add[vof * E.s_out + o + c] : 0.0);
-                    E.out2[vof * E.s_out + o + c] = v;
-                    bad |= !isfinite(v);
-                }
-            } else {
-                E.tout[vof * E.s_tout + o + c] = tv[i][c];
-                E.acc[vof * E.s_acc + o + c] = acc[i][c];
-                if (TWO) E.acc2[vof * E.s_acc + o + c] = acc2[i][c];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) bad |= !isfinite(v[c]);
+                row_store<CPL>(E.out + vof * E.s_out + o, v);
             }
+            if (TWO) {
+                double v[CPL];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) v[c] = acc2[i][c];
+                if (E.out2_add) {
+                    double q[CPL];
+                    row_load<CPL>(E.out2_add + vof * E.s_out + o, q);
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) v[c] += q[c];
+                }
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) bad |= !isfinite(v[c]);
+                row_store<CPL>(E.out2 + vof * E.s_out + o, v);
+            }
+        } else {
+            row_store<CPL>(E.tout + vof * E.s_tout + o, tv[i]);
+            row_store<CPL>(E.acc + vof * E.s_acc + o, acc[i]);
+            if (TWO) row_store<CPL>(E.acc2 + vof * E.s_acc + o, acc2[i]);
         }
     }
     if (E.final_pass && E.status) {
@@ -244,7 +247,7 @@ __global__ void k_pois_weights(const PoisWeights* __restrict__ tab) {
 
 template <int NX, bool TWO>
 hipError_t pois_launch(const PoisEntry* tab, int count, int blocks, hipStream_t s) {
-    k_pois2d<NX, TWO><<<blocks, PNT, 0, s>>>(tab, count);
+    k_pois2d<NX, TWO><<<blocks, BNT, 0, s>>>(tab, count);
     return hipGetLastError();
 }
 

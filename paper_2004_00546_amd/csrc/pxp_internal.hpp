@@ -176,8 +176,9 @@ struct Band2D {
     double dt, omega;
     Sten5 A;
     int nx, ny, nsteps, items, blk0;
+    int rows;  // output rows per workgroup: 16 or 32 (a divisor of ny)
 };
-constexpr int BAND_ROWS = 16;  // interior rows per workgroup
+constexpr int BAND_ROWS = 16;  // smallest band: ny must be a multiple
 constexpr int BAND_MAX_STEPS = 4;
 // Forward: slices (serial == 0) or launch L of a serial sweep.  Every
 // entry of one launch has row length nx (64, 128 or 256).
@@ -259,6 +260,31 @@ hipError_t launch_cost(const double* qT, const double* tgt, const double* a,
 hipError_t launch_grad(const double* basis, const double* v, const double* a,
                        int K, int n, double beta, double* grad, hipStream_t s,
                        DevStatus* st = nullptr);
+// Batched cost and gradient reductions over every instance of a call, in
+// two deterministic phases: blocks of RED_CHUNK points write partial sums,
+// then one block per instance adds them in chunk order.
+//   cost: lamT = qT - tgt, J = 1/2 |lamT|^2 + beta |a|^2
+//   grad: grad_k = <basis_k, v> + 2 beta a_k
+// Non-finite J or gradient components set ST_NONFINITE in st (nullable).
+constexpr int RED_CHUNK = 8192;
+struct RedDesc {
+    const double* qT;
+    const double* tgt;
+    double* lamT;
+    const double* a;
+    double* J;
+    const double* basis;
+    const double* v;
+    double* grad;
+    double beta;
+    DevStatus* st;
+    int n, K, chunks, blk0_cost, blk0_grad, pad;
+    int64_t part0, gpart0;  // this instance's partials in the cost / gradient areas
+};
+hipError_t launch_cost_batch(const RedDesc* tab, int count, int blocks_cost, double* part,
+                             hipStream_t s);
+hipError_t launch_grad_batch(const RedDesc* tab, int count, int blocks_grad, double* part,
+                             hipStream_t s);
 // out = q0 (or 0) + vlast + sum_{p<np} Y[p]   (checks finiteness)
 hipError_t launch_recombine(const double* q0, const double* vlast,
                             const double* Y, int np, int n, double* out,

@@ -104,7 +104,118 @@ __global__ void k_add(const double* __restrict__ a, const double* __restrict__ b
 
 inline int blocks(int n, int b) { return (n + b - 1) / b; }
 
+__device__ __forceinline__ int red_entry(const RedDesc* tab, int count, int b, bool grad) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((grad ? tab[mid].blk0_grad : tab[mid].blk0_cost) <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Batched cost, phase 1: block (instance, chunk) forms lamT = qT - tgt on
+// its chunk of RED_CHUNK points and the partial sum of lamT^2.
+__global__ void __launch_bounds__(256)
+k_cost_part(const RedDesc* __restrict__ tab, int count, double* __restrict__ part) {
+    __shared__ double red[8];
+    const RedDesc& d = tab[red_entry(tab, count, blockIdx.x, false)];
+    const int c = blockIdx.x - d.blk0_cost;
+    const int i0 = c * RED_CHUNK, i1 = min(d.n, i0 + RED_CHUNK);
+    double s0 = 0.0, s1 = 0.0;
+    int i = i0 + threadIdx.x;
+    for (; i + 256 < i1; i += 512) {
+        const double a = d.qT[i] - d.tgt[i], b = d.qT[i + 256] - d.tgt[i + 256];
+        if (d.lamT) {
+            d.lamT[i] = a;
+            d.lamT[i + 256] = b;
+        }
+        s0 += a * a;
+        s1 += b * b;
+    }
+    if (i < i1) {
+        const double a = d.qT[i] - d.tgt[i];
+        if (d.lamT) d.lamT[i] = a;
+        s0 += a * a;
+    }
+    const double s = block_sum(s0 + s1, red);
+    if (threadIdx.x == 0) part[d.part0 + c] = s;
+}
+
+// Batched cost, phase 2: one block per instance, partials in chunk order.
+__global__ void __launch_bounds__(64)
+k_cost_fin(const RedDesc* __restrict__ tab, const double* __restrict__ part) {
+    const RedDesc& d = tab[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    double s = 0.0, r = 0.0;
+    for (int c = 0; c < d.chunks; ++c) s += part[d.part0 + c];
+    for (int k = 0; k < d.K; ++k) r += d.a[k] * d.a[k];
+    *d.J = 0.5 * s + d.beta * r;
+    // every method's q(T) passes through here
+    if (d.st && !isfinite(s + r)) atomicOr(&d.st->flags, ST_NONFINITE);
+}
+
+// Batched gradient, phase 1: block (instance, k, chunk) forms the partial
+// <basis_k, v> over its chunk.
+__global__ void __launch_bounds__(256)
+k_grad_part(const RedDesc* __restrict__ tab, int count, double* __restrict__ part) {
+    __shared__ double red[8];
+    const RedDesc& d = tab[red_entry(tab, count, blockIdx.x, true)];
+    const int local = blockIdx.x - d.blk0_grad;
+    const int k = local / d.chunks, c = local - k * d.chunks;
+    const double* b = d.basis + (size_t)k * d.n;
+    const int i0 = c * RED_CHUNK, i1 = min(d.n, i0 + RED_CHUNK);
+    double s0 = 0.0, s1 = 0.0;
+    int i = i0 + threadIdx.x;
+    for (; i + 256 < i1; i += 512) {
+        s0 += b[i] * d.v[i];
+        s1 += b[i + 256] * d.v[i + 256];
+    }
+    if (i < i1) s0 += b[i] * d.v[i];
+    const double s = block_sum(s0 + s1, red);
+    if (threadIdx.x == 0) part[d.gpart0 + (size_t)k * d.chunks + c] = s;
+}
+
+// Batched gradient, phase 2: grad_k = sum of the partials + 2 beta a_k.
+__global__ void __launch_bounds__(256)
+k_grad_fin(const RedDesc* __restrict__ tab, const double* __restrict__ part) {
+    const RedDesc& d = tab[blockIdx.x];
+    bool bad = false;
+    for (int k = threadIdx.x; k < d.K; k += blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < d.chunks; ++c) s += part[d.gpart0 + (size_t)k * d.chunks + c];
+        const double g = s + 2.0 * d.beta * d.a[k];
+        d.grad[k] = g;
+        bad |= !isfinite(g);
+    }
+    if (d.st && bad) atomicOr(&d.st->flags, ST_NONFINITE);
+}
+
 }  // namespace
+
+hipError_t launch_cost_batch(const RedDesc* tab, int count, int blocks_cost, double* part,
+                             hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    k_cost_part<<<blocks_cost, 256, 0, s>>>(tab, count, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_cost_fin<<<count, 64, 0, s>>>(tab, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_batch(const RedDesc* tab, int count, int blocks_grad, double* part,
+                             hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    if (blocks_grad > 0) {
+        k_grad_part<<<blocks_grad, 256, 0, s>>>(tab, count, part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    k_grad_fin<<<count, 256, 0, s>>>(tab, part);
+    return hipGetLastError();
+}
 
 hipError_t launch_combine_basis(const double* a, const double* basis,
                                 const double* base, double* out, int K, int n,

@@ -4,102 +4,134 @@
 //     instances and slices of a call in one launch;
 //   - the serial comparison march and its exact discrete adjoint.
 //
-// Workgroup layout: one workgroup advances BAND_ROWS full grid rows of one
-// march by up to BAND_MAX_STEPS steps.  Rows are periodic in x, so the band
-// only needs a halo in y: every stage application of the stencil consumes
-// one halo row on each side, so a band of nsteps steps loads 4*nsteps extra
-// rows above and below, recomputes them redundantly, and writes back only
-// its own rows.  The stage input lives in LDS (neighbour reads), the state
-// and the stage accumulators in registers.
+// Workgroup layout: one workgroup advances a band of grid rows of one march
+// by up to BAND_MAX_STEPS steps.  Rows are periodic in x, so the band only
+// needs a halo in y: every stage application of the stencil consumes one
+// halo row on each side, so a band of nsteps steps loads 4*nsteps extra rows
+// above and below, recomputes them redundantly, and writes back only its own
+// rows.  State, stage input and stage accumulator live in registers.
 #include "pxp_internal.hpp"
 #include "pxp_device.hpp"
+#include "pxp_band.hpp"
 
 namespace pxp {
 namespace {
 
-constexpr int NT2 = 512;  // threads per band workgroup
-// region points per thread for rows of NX points: (16 + 2*16 rows) * NX / NT2
-template <int NX>
-constexpr int kpt() {
-    return (BAND_ROWS + 4 * BAND_MAX_STEPS * 2) * NX / NT2;
-}
+// Band layout (shared with the uniformised exponentials): 8 waves, wave w
+// holds region rows 8w .. 8w+7 of a 64-row region, lane l columns
+// l*CPL .. l*CPL+CPL-1 (CPL = NX/64), so a wave row is a whole periodic grid
+// row: x neighbours are the adjacent lanes (wrapping), y neighbours the same
+// lane's registers except at the wave's first and last rows, which go
+// through LDS once per stage.  Output rows are region rows off .. off+R-1
+// (R = d.rows, 16 or 32; off = (64 - R) / 2); every stage application
+// consumes one halo row on each side, and at most 16 are needed (four steps
+// of four stages).  Waves whose rows are no longer needed skip the
+// arithmetic.  The forcing pattern of the needed rows is staged in LDS once
+// per launch (it enters every stage); the four stages are unrolled, each
+// with its own update, and the forcing sines of the launch are evaluated by
+// one lane each and broadcast.
+// One classical RK4 step of y' = A y + s(t) F with constant A is, exactly
+// (up to rounding), the polynomial step
+//   y_{n+1} = R(Z) y_n + phi(Z) F,   Z = dt A,
+//   R(Z) = 1 + Z + Z^2/2 + Z^3/6 + Z^4/24,
+//   phi(Z) = dt/6 [s1 (1 + Z + Z^2/2 + Z^3/4) + s2 (4 + 2Z + Z^2/2) + s4],
+// s1, s2, s4 the forcing modulation at t_n, t_n + dt/2, t_n + dt: expand the
+// four stages with y = 0 and with F = 0.  The marches evaluate it by Horner
+// in Z (four stencil applications per step, as the stages), keeping two
+// arrays in registers instead of three; the forcing pattern comes from LDS.
+// Its exact discrete adjoint is lambda_n = R(Z^T) lambda_{n+1} with the
+// forcing gradient phi(Z^T) lambda_{n+1}, formed from the powers
+// (Z^T)^j lambda_{n+1}, j <= 4.
 
-// Band region of `rows` rows x NX columns; thread t owns column t % NX and
-// rows t / NX + q * (NT2 / NX), q < KPT.  In LDS, region row r sits at row
-// r + 1 with stride NX + 2: a zeroed pad row above and below, and the two
-// periodic neighbour columns stored beside each row, so the stencil reads
-// five fixed offsets from every point (the rows next to the pads are halo
-// rows, whose results are discarded).
-template <int NX>
-struct Region {
-    static constexpr int LD = NX + 2;
-    static constexpr int RSTEP = NT2 / NX;
-    int rows, col, r0;
-    __device__ __forceinline__ int row(int q) const { return r0 + q * RSTEP; }
-    __device__ __forceinline__ int idx(int q) const { return (row(q) + 1) * LD + col + 1; }
-    // store v at region point q, with its periodic copy when on an edge
-    __device__ __forceinline__ void put(double* X, int q, double v) const {
-        const int i = idx(q);
-        X[i] = v;
-        if (col == 0) X[i + NX] = v;
-        if (col == NX - 1) X[i - NX] = v;
+// One Horner level of the forward step: v = rj y + fj F + Z v, with
+// (rj, fj) = (1/6, f3), (1/2, f2), (1, f1), (1, f0) for the levels in turn.
+template <int NX, int CPL, bool FORCED>
+__device__ __forceinline__ void fwd_level(const double (&y)[BRW][CPL], double (&v)[BRW][CPL],
+                                          const double (*fl)[NX], double (*xch)[2][NX],
+                                          const Sten5& A, double rj, double fj, double dt,
+                                          int w, int l, int cb, bool active) {
+    double prev[CPL], dn[CPL];
+    exchange_edges<NX, CPL>(xch, v, w, cb, prev, dn);
+    if (!active) return;
+    const int lw = (l + WAVE - 1) & (WAVE - 1), le = (l + 1) & (WAVE - 1);
+#pragma unroll
+    for (int i = 0; i < BRW; ++i) {
+        double cur[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) cur[c] = v[i][c];
+        const double wv = __shfl(cur[CPL - 1], lw, WAVE);
+        const double ev = __shfl(cur[0], le, WAVE);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const double xw = (c > 0) ? cur[c - 1] : wv;
+            const double xe = (c < CPL - 1) ? cur[c + 1] : ev;
+            const double xn = (i < BRW - 1) ? v[i + 1][c] : dn[c];
+            const double av = A.c * cur[c] + A.w * xw + A.e * xe + A.s * prev[c] + A.n * xn;
+            double r = rj * y[i][c] + dt * av;
+            if (FORCED) r += fj * fl[w * BRW + i][cb + c];
+            v[i][c] = r;
+            prev[c] = cur[c];
+        }
+        // one row at a time: the scheduler would otherwise hoist later rows'
+        // LDS reads and shuffles and push the register use past 256
+        __builtin_amdgcn_sched_barrier(0);
     }
-};
-
-template <int NX>
-__device__ __forceinline__ Region<NX> make_region(int H) {
-    Region<NX> R;
-    R.rows = BAND_ROWS + 2 * H;
-    R.col = threadIdx.x % NX;
-    R.r0 = threadIdx.x / NX;
-    return R;
 }
 
-template <int NX>
-__device__ __forceinline__ void zero_pads(double* X, const Region<NX>& R) {
-    for (int c = threadIdx.x; c < Region<NX>::LD; c += NT2) {
-        X[c] = 0.0;
-        X[(R.rows + 1) * Region<NX>::LD + c] = 0.0;
+// rows of the wave still needed after stencil application `app` of H
+__device__ __forceinline__ bool wave_active(int w, int off, int R, int H, int app) {
+    const int keep = H - 1 - app;
+    return !(w * BRW + BRW <= off - keep || w * BRW >= off + R + keep);
+}
+
+template <int NX, bool FORCED>
+__device__ __forceinline__ void fwd_march(double (&y)[BRW][NX / WAVE], const Band2D& d,
+                                          const double (*fl)[NX], double (*xch)[2][NX], int ns,
+                                          double snv, int w, int l, int cb, int off, int R) {
+    constexpr int CPL = NX / WAVE;
+    const Sten5 A = d.A;
+    const double dt = d.dt, h6 = dt / 6.0;
+    const int H = 4 * ns;
+    double v[BRW][CPL];
+    for (int s = 0; s < ns; ++s) {
+        // modulation at t_n, t_n + dt/2, t_n + dt (lanes 3s .. 3s+2)
+        const double s1 = __shfl(snv, 3 * s, WAVE), s2 = __shfl(snv, 3 * s + 1, WAVE),
+                     s4 = __shfl(snv, 3 * s + 2, WAVE);
+        const double f0 = h6 * (s1 + 4.0 * s2 + s4), f1 = h6 * (s1 + 2.0 * s2),
+                     f2 = h6 * 0.5 * (s1 + s2), f3 = h6 * 0.25 * s1;
+#pragma unroll
+        for (int i = 0; i < BRW; ++i)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) v[i][c] = y[i][c] * (1.0 / 24.0);
+#pragma unroll 1
+        for (int j = 0; j < 4; ++j) {
+            const double rj = (j == 0) ? 1.0 / 6.0 : ((j == 1) ? 0.5 : 1.0);
+            const double fj = (j == 0) ? f3 : ((j == 1) ? f2 : ((j == 2) ? f1 : f0));
+            fwd_level<NX, CPL, FORCED>(y, v, fl, xch, A, rj, fj, dt, w, l, cb,
+                                       wave_active(w, off, R, H, 4 * s + j));
+        }
+#pragma unroll
+        for (int i = 0; i < BRW; ++i)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) y[i][c] = v[i][c];
     }
 }
 
-// Five-point stencil at LDS index i.
 template <int NX>
-__device__ __forceinline__ double sten(const double* X, int i, const Sten5& A) {
-    constexpr int LD = Region<NX>::LD;
-    return A.c * X[i] + A.w * X[i - 1] + A.e * X[i + 1] + A.s * X[i - LD] + A.n * X[i + LD];
-}
-
-// global row of band row r (periodic in y)
-__device__ __forceinline__ int grow(int row0, int r, int ny) {
-    int g = row0 + r;
-    if (g < 0) g += ny;
-    if (g >= ny) g -= ny;
-    return g;
-}
-
-__device__ __forceinline__ int find_entry(const Band2D* tab, int count, int b) {
-    int e = 0;
-    while (e + 1 < count && tab[e + 1].blk0 <= b) ++e;
-    return e;
-}
-
-template <int NX>
-__global__ void __launch_bounds__(NT2)
+__global__ void __launch_bounds__(BNT)
 k_band2d_fwd(const Band2D* __restrict__ tab, int count, int serial, int L) {
-    extern __shared__ double X[];
-    constexpr int KPT = kpt<NX>();
-    const int b = blockIdx.x;
-    const Band2D& d = tab[find_entry(tab, count, b)];
-    constexpr int nx = NX;
-    const int ny = d.ny, nb = ny / BAND_ROWS;
-    const int local = b - d.blk0;
+    constexpr int CPL = NX / WAVE;
+    __shared__ double xch[BW][2][NX];
+    __shared__ double fl[BROWS][NX];
+    const Band2D& d = tab[find_entry(tab, count, blockIdx.x)];
+    const int ny = d.ny, R = d.rows, nb = ny / R, off = (BROWS - R) / 2;
+    const int local = blockIdx.x - d.blk0;
     const int item = local / nb, band = local - item * nb;
     int ns;
     int64_t first;
     const double* in;
     double* out;
-    const size_t nn = (size_t)nx * ny;
+    const size_t nn = (size_t)NX * ny;
     if (serial) {
         const int64_t left = d.n_t - 4 * (int64_t)L;
         if (left <= 0) return;
@@ -117,76 +149,137 @@ k_band2d_fwd(const Band2D* __restrict__ tab, int count, int serial, int L) {
         out = d.out + (size_t)item * nn;
     }
     const int H = 4 * ns;
-    const Region<NX> R = make_region<NX>(H);
-    const int row0 = band * BAND_ROWS - H;
-    zero_pads(X, R);
-    double y[KPT], acc[KPT], Y[KPT], f[KPT];
-#pragma unroll
-    for (int q = 0; q < KPT; ++q) {
-        const int r = R.row(q);
-        const int g = grow(row0, r, ny) * nx + R.col;
-        y[q] = (r < R.rows && in) ? in[g] : 0.0;
-        f[q] = (r < R.rows && d.F) ? d.F[g] : 0.0;
-        acc[q] = 0.0;
-        Y[q] = y[q];
+    const int w = wave_id(), l = lane_id(), cb = l * CPL;
+    const int base = band * R - off + w * BRW;
+    const double dt = d.dt;
+    // lane j < 3 ns: the forcing modulation at stage time j of the launch
+    double snv = 0.0;
+    if (l < 3 * ns) {
+        const int st = l / 3, v = l - 3 * (l / 3);
+        const double tn = (double)(first + st) * dt;
+        snv = sin(d.omega * (tn + (v == 0 ? 0.0 : (v == 2 ? dt : 0.5 * dt))));
     }
-    const Sten5 A = d.A;
-    const double dt = d.dt, h2 = 0.5 * dt, h6 = dt / 6.0;
-    // the forcing sines of the block's steps at the stage times t, t + dt/2,
-    // t + dt: one evaluation per value instead of one per thread and stage
-    __shared__ double sn[12];
-    if ((int)threadIdx.x < 3 * ns) {
-        const int s = threadIdx.x / 3, v = threadIdx.x - 3 * (threadIdx.x / 3);
-        const double tn = (double)(first + s) * dt;
-        sn[threadIdx.x] = sin(d.omega * (tn + (v == 0 ? 0.0 : (v == 2 ? dt : h2))));
+    // every region row is a grid row, so all loads are in bounds and issued
+    // together; rows beyond the halo the launch needs never reach the output
+    int g[BRW];
+    wave_rows(band_grow(base, 0, ny), ny, g);
+    double y[BRW][CPL];
+    if (in) {
+#pragma unroll
+        for (int i = 0; i < BRW; ++i) row_load<CPL>(in + (size_t)g[i] * NX + cb, y[i]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < BRW; ++i)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) y[i][c] = 0.0;
     }
-    __syncthreads();
-    for (int s = 0; s < ns; ++s) {
-#pragma unroll 1
-        for (int st = 0; st < 4; ++st) {
-            const double sv = sn[3 * s + (st == 0 ? 0 : (st == 3 ? 2 : 1))];
-            const double cw = (st == 0) ? 1.0 : 2.0;
-            const double cy = (st == 2) ? dt : h2;
-            __syncthreads();  // previous readers of X are done
+    if (d.F) {
+        double f[BRW][CPL];
 #pragma unroll
-            for (int q = 0; q < KPT; ++q)
-                if (R.row(q) < R.rows) R.put(X, q, (st == 0) ? y[q] : Y[q]);
-            __syncthreads();
+        for (int i = 0; i < BRW; ++i) row_load<CPL>(d.F + (size_t)g[i] * NX + cb, f[i]);
 #pragma unroll
-            for (int q = 0; q < KPT; ++q) {
-                const int r = R.row(q);
-                if (r >= R.rows) continue;
-                const double k = sten<NX>(X, R.idx(q), A) + sv * f[q];
-                if (st < 3) {
-                    acc[q] += cw * k;
-                    Y[q] = y[q] + cy * k;
-                } else {
-                    y[q] += h6 * (acc[q] + k);
-                    acc[q] = 0.0;
-                }
-            }
+        for (int i = 0; i < BRW; ++i) row_store<CPL>(&fl[w * BRW + i][cb], f[i]);
+        fwd_march<NX, true>(y, d, fl, xch, ns, snv, w, l, cb, off, R);
+    } else {
+        fwd_march<NX, false>(y, d, fl, xch, ns, snv, w, l, cb, off, R);
+    }
+    (void)H;
+#pragma unroll
+    for (int i = 0; i < BRW; ++i) {
+        const int r = w * BRW + i;
+        if (r >= off && r < off + R) row_store<CPL>(out + (size_t)g[i] * NX + cb, y[i]);
+    }
+}
+
+// One power of the reverse step: w <- Z^T w, lam_n += rj w and (output
+// rows) Lambda += fj w, with (rj, fj) = (1, f1), (1/2, f2), (1/6, f3),
+// (1/24, 0) for the powers 1..4.
+template <int NX, int CPL, bool TRACK>
+__device__ __forceinline__ void rev_power(double (&w_)[BRW][CPL], double (&ln)[BRW][CPL],
+                                          double (*lm)[NX], double (*xch)[2][NX],
+                                          const Sten5& A, double rj, double fj, double dt,
+                                          int w, int l, int cb, int off, int R, bool active) {
+    double prev[CPL], dn[CPL];
+    exchange_edges<NX, CPL>(xch, w_, w, cb, prev, dn);
+    if (!active) return;
+    const int lw = (l + WAVE - 1) & (WAVE - 1), le = (l + 1) & (WAVE - 1);
+#pragma unroll
+    for (int i = 0; i < BRW; ++i) {
+        const int r = w * BRW + i;
+        double cur[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) cur[c] = w_[i][c];
+        const double wv = __shfl(cur[CPL - 1], lw, WAVE);
+        const double ev = __shfl(cur[0], le, WAVE);
+        const bool orow = TRACK && r >= off && r < off + R;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const double xw = (c > 0) ? cur[c - 1] : wv;
+            const double xe = (c < CPL - 1) ? cur[c + 1] : ev;
+            const double xn = (i < BRW - 1) ? w_[i + 1][c] : dn[c];
+            const double z =
+                dt * (A.c * cur[c] + A.w * xw + A.e * xe + A.s * prev[c] + A.n * xn);
+            ln[i][c] += rj * z;
+            if (orow) lm[r - off][cb + c] += fj * z;
+            w_[i][c] = z;
+            prev[c] = cur[c];
         }
-    }
-#pragma unroll
-    for (int q = 0; q < KPT; ++q) {
-        const int r = R.row(q);
-        if (r >= H && r < H + BAND_ROWS) out[grow(row0, r, ny) * nx + R.col] = y[q];
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
 // Exact discrete adjoint of the RK4 march, backwards over the steps of
-// launch L: per step, kbar_4 = dt/6 lam, Ybar_i = A^T kbar_i, kbar_{i-1} =
-// b_{i-1} dt lam + c_i dt Ybar_i, lam += sum_i Ybar_i, Lam += s(t_i) kbar_i.
+// launch L: lam_n = R(Z^T) lam_{n+1}, Lambda += phi(Z^T) lam_{n+1}.  The
+// Lambda increments of the launch build in LDS for the output rows.
+template <int NX, bool TRACK>
+__device__ __forceinline__ void rev_march(double (&lam)[BRW][NX / WAVE], const Band2D& d,
+                                          double (*lm)[NX], double (*xch)[2][NX], int ns,
+                                          double snv, int w, int l, int cb, int off, int R) {
+    constexpr int CPL = NX / WAVE;
+    const Sten5 A = d.A;
+    const double dt = d.dt, h6 = dt / 6.0;
+    const int H = 4 * ns;
+    double ln[BRW][CPL];
+    int a = 0;
+    for (int s = ns - 1; s >= 0; --s, a += 4) {
+        const double s1 = __shfl(snv, 3 * s, WAVE), s2 = __shfl(snv, 3 * s + 1, WAVE),
+                     s4 = __shfl(snv, 3 * s + 2, WAVE);
+        const double f0 = h6 * (s1 + 4.0 * s2 + s4), f1 = h6 * (s1 + 2.0 * s2),
+                     f2 = h6 * 0.5 * (s1 + s2), f3 = h6 * 0.25 * s1;
+        // power 0: lam_n starts as lam_{n+1}, Lambda takes f0 lam_{n+1}
+#pragma unroll
+        for (int i = 0; i < BRW; ++i) {
+            const int r = w * BRW + i;
+            const bool orow = TRACK && r >= off && r < off + R;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                ln[i][c] = lam[i][c];
+                if (orow) lm[r - off][cb + c] += f0 * lam[i][c];
+            }
+        }
+#pragma unroll 1
+        for (int j = 1; j <= 4; ++j) {
+            const double rj = (j == 1) ? 1.0 : ((j == 2) ? 0.5 : ((j == 3) ? 1.0 / 6.0 : 1.0 / 24.0));
+            const double fj = (j == 1) ? f1 : ((j == 2) ? f2 : ((j == 3) ? f3 : 0.0));
+            rev_power<NX, CPL, TRACK>(lam, ln, lm, xch, A, rj, fj, dt, w, l, cb, off, R,
+                                      wave_active(w, off, R, H, a + j - 1));
+        }
+#pragma unroll
+        for (int i = 0; i < BRW; ++i)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) lam[i][c] = ln[i][c];
+    }
+}
+
 template <int NX>
-__global__ void __launch_bounds__(NT2)
+__global__ void __launch_bounds__(BNT)
 k_band2d_rev(const Band2D* __restrict__ tab, int count, int L) {
-    extern __shared__ double X[];
-    constexpr int KPT = kpt<NX>();
-    const int b = blockIdx.x;
-    const Band2D& d = tab[find_entry(tab, count, b)];
-    constexpr int nx = NX;
-    const int ny = d.ny;
-    const int band = b - d.blk0;
+    constexpr int CPL = NX / WAVE;
+    __shared__ double xch[BW][2][NX];
+    __shared__ double lm[32][NX];
+    const Band2D& d = tab[find_entry(tab, count, blockIdx.x)];
+    const int ny = d.ny, R = d.rows, off = (BROWS - R) / 2;
+    const int band = blockIdx.x - d.blk0;
     const int64_t left = d.n_t - 4 * (int64_t)L;
     if (left <= 0) return;
     const int ns = left < 4 ? (int)left : 4;
@@ -194,65 +287,42 @@ k_band2d_rev(const Band2D* __restrict__ tab, int count, int L) {
     const double* in = (L == 0) ? d.y0 : d.buf[L & 1];
     double* out = d.buf[(L + 1) & 1];
     const int H = 4 * ns;
-    const Region<NX> R = make_region<NX>(H);
-    const int row0 = band * BAND_ROWS - H;
-    zero_pads(X, R);
-    double lam[KPT], kb[KPT], nl[KPT], Lm[KPT];
-#pragma unroll
-    for (int q = 0; q < KPT; ++q) {
-        const int r = R.row(q);
-        lam[q] = (r < R.rows) ? in[grow(row0, r, ny) * nx + R.col] : 0.0;
-        Lm[q] = 0.0;
-        nl[q] = 0.0;
-        kb[q] = 0.0;
+    const int t = threadIdx.x, w = wave_id(), l = lane_id(), cb = l * CPL;
+    const int base = band * R - off + w * BRW;
+    const double dt = d.dt;
+    double snv = 0.0;
+    if (l < 3 * ns) {
+        const int st = l / 3, v = l - 3 * (l / 3);
+        const double tn = (double)(first + st) * dt;
+        snv = sin(d.omega * (tn + (v == 0 ? 0.0 : (v == 2 ? dt : 0.5 * dt))));
     }
-    const Sten5 A = d.A;
-    const double dt = d.dt, d6 = dt / 6.0, d3 = dt / 3.0, d2 = 0.5 * dt;
-    // the forcing sines at the stage times, as in k_band2d_fwd
-    __shared__ double sn[12];
-    if ((int)threadIdx.x < 3 * ns) {
-        const int s = threadIdx.x / 3, v = threadIdx.x - 3 * (threadIdx.x / 3);
-        const double tn = (double)(first + s) * dt;
-        sn[threadIdx.x] = sin(d.omega * (tn + (v == 0 ? 0.0 : (v == 2 ? dt : d2))));
-    }
-    __syncthreads();
-    for (int s = ns - 1; s >= 0; --s) {
+    const bool track = d.Lam != nullptr;
+    if (track)
+        for (int q = t; q < R * NX; q += BNT) lm[q / NX][q % NX] = 0.0;
+    int g[BRW];
+    wave_rows(band_grow(base, 0, ny), ny, g);
+    double lam[BRW][CPL];
 #pragma unroll
-        for (int q = 0; q < KPT; ++q) kb[q] = d6 * lam[q];
-        // stages 4, 3, 2, 1
-#pragma unroll 1
-        for (int st = 0; st < 4; ++st) {
-            const double sv = sn[3 * s + (st == 0 ? 2 : (st == 3 ? 0 : 1))];
-            const double bl = (st == 2) ? d6 : d3;  // weight of lam in the next kbar
-            const double cy = (st == 0) ? dt : d2;  // weight of Ybar in the next kbar
-            __syncthreads();
+    for (int i = 0; i < BRW; ++i) row_load<CPL>(in + (size_t)g[i] * NX + cb, lam[i]);
+    (void)H;
+    __syncthreads();  // the Lambda buffer is cleared
+    if (track)
+        rev_march<NX, true>(lam, d, lm, xch, ns, snv, w, l, cb, off, R);
+    else
+        rev_march<NX, false>(lam, d, lm, xch, ns, snv, w, l, cb, off, R);
 #pragma unroll
-            for (int q = 0; q < KPT; ++q)
-                if (R.row(q) < R.rows) R.put(X, q, kb[q]);
-            __syncthreads();
+    for (int i = 0; i < BRW; ++i) {
+        const int r = w * BRW + i;
+        if (r < off || r >= off + R) continue;
+        const size_t o = (size_t)g[i] * NX + cb;
+        row_store<CPL>(out + o, lam[i]);
+        if (track) {
+            double L[CPL], m[CPL];
+            row_load<CPL>(d.Lam + o, L);
+            row_load<CPL>(&lm[r - off][cb], m);
 #pragma unroll
-            for (int q = 0; q < KPT; ++q) {
-                const int r = R.row(q);
-                if (r >= R.rows) continue;
-                const double yb = sten<NX>(X, R.idx(q), A);
-                Lm[q] += sv * kb[q];
-                if (st < 3) {
-                    nl[q] += yb;
-                    kb[q] = bl * lam[q] + cy * yb;
-                } else {
-                    lam[q] += nl[q] + yb;
-                    nl[q] = 0.0;
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < KPT; ++q) {
-        const int r = R.row(q);
-        if (r >= H && r < H + BAND_ROWS) {
-            const int g = grow(row0, r, ny) * nx + R.col;
-            out[g] = lam[q];
-            if (d.Lam) d.Lam[g] += Lm[q];
+            for (int c = 0; c < CPL; ++c) L[c] += m[c];
+            row_store<CPL>(d.Lam + o, L);
         }
     }
 }
@@ -270,27 +340,17 @@ __global__ void k_apply5(const double* __restrict__ x, double* __restrict__ out,
     out[i] = A.c * x[i] + A.w * xw + A.e * xe + A.s * xs + A.n * xn;
 }
 
-size_t band_lds(int nx) {
-    return (size_t)(BAND_ROWS + 8 * BAND_MAX_STEPS + 2) * (nx + 2) * sizeof(double);
-}
-
 template <int NX>
 hipError_t band_fwd(const Band2D* tab, int count, int total_blocks, int serial, int L,
                     hipStream_t s) {
-    const size_t lds = band_lds(NX);
-    (void)hipFuncSetAttribute((const void*)k_band2d_fwd<NX>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_band2d_fwd<NX><<<total_blocks, NT2, lds, s>>>(tab, count, serial, L);
+    k_band2d_fwd<NX><<<total_blocks, BNT, 0, s>>>(tab, count, serial, L);
     return hipGetLastError();
 }
 
 template <int NX>
 hipError_t band_rev(const Band2D* tab, int count, int total_blocks, int L,
                     hipStream_t s) {
-    const size_t lds = band_lds(NX);
-    (void)hipFuncSetAttribute((const void*)k_band2d_rev<NX>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_band2d_rev<NX><<<total_blocks, NT2, lds, s>>>(tab, count, L);
+    k_band2d_rev<NX><<<total_blocks, BNT, 0, s>>>(tab, count, L);
     return hipGetLastError();
 }
 
