@@ -2,16 +2,21 @@
 RK4 stepping, at the FP64 accuracy gate (rel err <= 1e-8 against the CPU
 oracle).
 
-Workload (default): 1D periodic advection-diffusion, N = 4096, T = 4,
-dt = 1e-4 (40 000 RK4 steps), 64 time slices, Krylov dimension 40,
-64 forcing amplitudes; one full direct-adjoint gradient per step.
+Workload (default): 16 independent instances of the 2D periodic upwind
+advection-diffusion problem on 256 x 256 grids, horizons T uniform in
+[0.5, 2] (256 to 1024 RK4 steps), 256 time slices, 8 forcing blob
+amplitudes each; one step = one full direct-adjoint gradient of every
+instance; value = 16 / seconds per step.  A secondary measurement on the
+1D N = 4096 problem (40 000 steps, 64 slices) rides in the same JSON line.
 
 Prints one JSON line (see --help for options).
 """
 from __future__ import annotations
 
 import argparse
+import functools
 import json
+import math
 import os
 import sys
 import time
@@ -22,9 +27,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "gradient evals/s, Paraexp vs serial stepping on 1 GPU at rel err ≤1e-8"
+DEFAULT_WORKLOAD = "advdiff2d_256"
+SECONDARY_WORKLOAD = "advdiff1d_n4096"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+# flops per grid point and stencil application (multiply-add = 2 flops):
+# 2D RK4 step as its polynomial, Horner level: 5-point stencil (5 FMA) +
+# r_j y + f_j F (2 FMA)
+RK2D_FLOPS = 14.0
+# 2D uniformised exponential, one term: 4-point N (4 FMA) + weighted sum (1)
+POIS_FLOPS = 10.0
 
 
 def log(*a):
@@ -33,11 +46,6 @@ def log(*a):
 
 def rel(x, ref):
     return float(np.linalg.norm(np.asarray(x) - ref) / np.linalg.norm(ref))
-
-
-def rk4_slice_flops(n, n_steps):
-    # per point and stage: stencil 9, source 3, accumulation 2, stage state 2
-    return 64.0 * n * n_steps
 
 
 def krylov_space_bytes(n, m, passes=2.0):
@@ -50,12 +58,52 @@ def krylov_space_bytes(n, m, passes=2.0):
     return 8.0 * n * vecs
 
 
-def profiled_traffic(kernel_key):
-    """HBM bytes per launch from the committed counter summary, only while
-    the Krylov kernel source is the one that was profiled."""
+@functools.lru_cache(maxsize=None)
+def pois_terms(lam, tol):
+    """Terms of a uniformised exponential: the smallest D with the Poisson
+    tail P(X >= D) <= tol (the library's rule)."""
+    if lam <= 0.0:
+        return 1
+    K = int(lam + 40.0 * math.sqrt(lam) + 80.0)
+    logp = [k * math.log(lam) - lam - math.lgamma(k + 1.0) for k in range(K + 1)]
+    tail, D = 0.0, K + 1
+    for k in range(K, 0, -1):
+        tail += math.exp(logp[k])
+        if tail > tol:
+            break
+        D = k
+    return D
+
+
+def tree_jobs(P):
+    """(left-range length of each pair) for the pairwise tree of P slices:
+    a list per level of the right-hand range sizes of its pairs."""
+    size = [1] * P
+    levels = []
+    while len(size) > 1:
+        pairs = len(size) // 2
+        levels.append([size[2 * j + 1] for j in range(pairs)])
+        ns = [size[2 * j] + size[2 * j + 1] for j in range(pairs)]
+        if len(size) % 2:
+            ns.append(size[-1])
+        size = ns
+    return levels
+
+
+def sten2d_mu(inst):
+    """Diagonal magnitude of the 2D upwind five-point operator."""
+    hx, hy = inst["L"] / inst["nx"], inst["L"] / inst["ny"]
+    nu = inst["nu"]
+    return (inst["vx"] / hx + inst["vy"] / hy + 2 * nu / hx ** 2 + 2 * nu / hy ** 2)
+
+
+def profiled_traffic(kernel_key, prof_name="advdiff1d_n4096_kernels.md",
+                     src_name="pxp_krylov.hip"):
+    """HBM bytes per launch from a committed counter summary, only while the
+    kernel source is the one that was profiled."""
     import hashlib
-    prof = os.path.join(ROOT, "profiles", "advdiff1d_n4096_kernels.md")
-    src = os.path.join(ROOT, "paper_2004_00546_amd", "csrc", "pxp_krylov.hip")
+    prof = os.path.join(ROOT, "profiles", prof_name)
+    src = os.path.join(ROOT, "paper_2004_00546_amd", "csrc", src_name)
     try:
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
         for line in open(prof):
@@ -66,6 +114,22 @@ def profiled_traffic(kernel_key):
     except OSError:
         pass
     return None
+
+
+def host_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return dict(nproc=os.cpu_count(), usable_cpus=usable, cpu_model=model)
 
 
 def warm(torch, r, count, seconds):
@@ -87,6 +151,281 @@ def time_runner(torch, r, steps, warmup, seconds=1.0):
     return (time.perf_counter() - t0) / steps
 
 
+def time_graph(torch, r, steps):
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        r.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        r.run()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def oracle_sample(insts, work, budget):
+    """Instances the oracle checks: all of a single-instance workload; for a
+    batch, the longest one, the cheapest of each grid size, then the
+    cheapest others while the point-step budget lasts."""
+    if len(insts) == 1:
+        return [0]
+    order = sorted(range(len(insts)), key=lambda i: work[i])
+    pick, seen, used = [order[-1]], set(), work[order[-1]]
+    for i in order:
+        nn = int(insts[i]["nx"]) * int(insts[i].get("ny", 1))
+        if nn not in seen:
+            seen.add(nn)
+            if i not in pick:
+                pick.append(i)
+                used += work[i]
+    for i in order:
+        if i not in pick and used + work[i] <= budget:
+            pick.append(i)
+            used += work[i]
+    return sorted(pick)
+
+
+def run_oracle(insts, sample, threads):
+    """Oracle gradients of the sampled instances, `threads` at a time (the
+    oracle is a C library called through ctypes, which releases the GIL).
+    Returns (results by index, wall seconds, summed per-instance seconds)."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    oracle.build()
+
+    def one(i):
+        t0 = time.perf_counter()
+        out = oracle.gradient(insts[i])
+        return i, out, time.perf_counter() - t0
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        res = list(ex.map(one, sample))
+    wall = time.perf_counter() - t0
+    return {i: o for i, o, _ in res}, wall, {i: dt for i, _, dt in res}
+
+
+# ---- roofline models of the kernel classes ------------------------------------
+
+def class_models(insts, problems, args, counters):
+    """Per kernel class: (bound, algorithmic quantity per class launch, unit
+    word, description).  counters: {cls: (substeps, iters, reorth)} per step
+    of the direct (0) and adjoint (1) exponentials."""
+    out = {}
+    two_d = all(x["op"] == "advdiff2d_upwind" for x in insts)
+    one_lin = all(x["op"] == "advdiff1d" for x in insts)
+    tol = problems[0].krylov_tol * 1e-2
+    if two_d:
+        n = [x["nx"] * x["ny"] for x in insts]
+        flops = sum(x["n_steps"] * 4 * nn * RK2D_FLOPS for x, nn in zip(insts, n))
+        out["slices"] = ("alu", flops, "flop",
+                         "k_band2d_fwd: every slice of every instance, 4 stencil "
+                         "applications per RK4 step at %g flop per point" % RK2D_FLOPS)
+        sched = {0: "classic", 1: "chain", 2: "tree"}[int(problems[0].sched)]
+        if sched == "tree":
+            byts = sum(3 * (int(p.P) - 1) * 8 * nn for p, nn in zip(problems, n))
+            terms = 0
+            for x, p, nn in zip(insts, problems, n):
+                mu, dT = sten2d_mu(x), x["T"] / int(p.P)
+                for lv in tree_jobs(int(p.P)):
+                    terms += sum(pois_terms(mu * dT * r, tol) for r in lv) * nn
+            out["krylov_direct"] = (
+                "hbm", byts, "B",
+                "k_pois2d, tree of uniformised exponentials: every pair reads its two "
+                "partial sums and writes one (3 vectors per pair, P-1 pairs per "
+                "instance); %.3g term-points (%.3g flop) beside it" %
+                (terms, terms * POIS_FLOPS))
+        lam = [sten2d_mu(x) * x["T"] for x in insts]
+        adj_terms = sum(pois_terms(min(l, 600.0), tol) * math.ceil(l / 600.0) * nn
+                        for l, nn in zip(lam, n))
+        out["krylov_adjoint"] = (
+            "alu", adj_terms * (POIS_FLOPS + 2.0), "flop",
+            "k_pois2d, the adjoint piece with its time integral: terms x points x "
+            "%g flop" % (POIS_FLOPS + 2.0))
+    if one_lin and len(insts) == 1 and counters.get(0):
+        inst, p = insts[0], problems[0]
+        n = inst["nx"]
+        sub, it, re = counters[0]
+        if int(p.sched) == 0 and sub:
+            m_eff = min(int(p.m), int(it / sub))
+            passes = 1.0 + re / it if it else 2.0
+            byts = (int(p.P) - 1) * krylov_space_bytes(n, m_eff, passes)
+            out["krylov_direct"] = (
+                "hbm", byts, "B",
+                "k_krylov1d, direct pieces (classic, %d workgroups): P-1 Arnoldi spaces "
+                "at the measured mean dimension %d and %.3f Gram-Schmidt passes per "
+                "step" % (int(p.P) - 1, m_eff, passes))
+    return out
+
+
+def roofline(kern, models, steps, traffic=None):
+    objs = {}
+    for k, (bound, q, word, desc) in models.items():
+        if k not in kern:
+            continue
+        per_launch = kern[k]["launches"] / steps
+        sec = kern[k]["avg_ms"] * 1e-3
+        q_launch = q / per_launch
+        if bound == "hbm":
+            ach, peak, unit = q_launch / sec / 1e9, HBM_PEAK_GBS, "GB/s"
+        else:
+            ach, peak, unit = q_launch / sec / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
+        objs[k] = dict(kernel=desc, bound=bound, achieved=ach, peak=peak, unit=unit,
+                       frac=ach / peak, traffic=(traffic or {}).get(k),
+                       algorithmic_per_launch=q_launch, algorithmic_unit=word,
+                       avg_launch_ms=kern[k]["avg_ms"])
+    if not kern:
+        return None, objs
+    top = max(kern, key=lambda k: kern[k]["per_step_ms"])
+    main = objs.get(top, dict(kernel=top, bound=None, achieved=None, peak=None, unit=None,
+                              frac=None, traffic=None, avg_launch_ms=kern[top]["avg_ms"]))
+    return main, objs
+
+
+# ---- one workload ---------------------------------------------------------------
+
+def measure(args, name, torch, _lib, api, workloads, steps, serial_steps, with_oracle,
+            cpu_baseline):
+    insts = workloads.make(name)
+    if args.instances > 0 and name == args.workload:
+        insts = insts[:args.instances]
+    inst = insts[0]
+    B = len(insts)
+    n = inst["nx"] * inst.get("ny", 1)
+    work = [int(x["nx"]) * int(x.get("ny", 1)) * int(x["n_steps"]) for x in insts]
+    log("workload %s: %d instance(s); first N=%d steps=%d P=%d; point-steps %.3g"
+        % (name, B, n, inst["n_steps"], inst["P"], sum(work)))
+    sched = args.sched or ("tree" if inst["op"] == "advdiff2d_upwind" else "classic")
+    tol = args.tol if args.tol is not None else (1e-9 if args.prec == "fp64" else 1e-6)
+    kw = dict(prec=args.prec, block=args.block, kblock=args.kblock)
+    pkw = dict(kw, absorbed=args.absorbed)
+    tuned = None
+    if args.autotune and name == args.workload:
+        lo, hi = (int(v) for v in args.p_range.split(","))
+        t0 = time.perf_counter()
+        probs, rep = api.autotune(insts, p_min=lo, p_max=hi,
+                                  rtol=1e-9 if args.prec == "fp64" else 5e-6,
+                                  krylov=args.krylov, sched=sched, tol=tol, **pkw)
+        names = {v: k for k, v in _lib.KRYLOV.items()}
+        tuned = {"seconds": time.perf_counter() - t0,
+                 "P": sorted({int(p.P) for p in probs}),
+                 "krylov": sorted({names[int(p.krylov)] for p in probs}),
+                 "sched": sorted({{0: "classic", 1: "chain", 2: "tree"}[int(p.sched)]
+                                  for p in probs}),
+                 "kblock": sorted({int(p.kblock) for p in probs}),
+                 "groups": len({r["group"] for r in rep})}
+        log("autotune", tuned, rep[:4])
+        pxp = api.GradientRunner(insts, method="paraexp", problems=probs)
+    else:
+        pxp = api.GradientRunner(insts, method="paraexp", krylov=args.krylov, sched=sched,
+                                 tol=tol, **pkw)
+    ser = api.GradientRunner(insts, method="serial", krylov="auto", **kw)
+
+    # timed Paraexp region, with per-kernel events on the library's stream
+    warm(torch, pxp, args.warmup, args.warmup_seconds)
+    pxp.status()
+    _lib.pxp_last_report(pxp.problems, pxp.ws)
+    c0 = {c: _lib.pxp_device_counters_class(pxp.ws, c) for c in (0, 1)}
+    _lib.pxp_profile_enable(True)
+    for k in _lib.KCLASS:
+        _lib.pxp_profile_read(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pxp.run()
+    torch.cuda.synchronize()
+    t_pxp = (time.perf_counter() - t0) / steps
+    _lib.pxp_profile_enable(False)
+    kern = {}
+    for k in _lib.KCLASS:
+        ms, cnt = _lib.pxp_profile_read(k)
+        if cnt:
+            kern[k] = dict(avg_ms=ms / cnt, launches=cnt, per_step_ms=ms / steps)
+    c1 = {c: _lib.pxp_device_counters_class(pxp.ws, c) for c in (0, 1)}
+    counters = {c: tuple((b - a) / steps for a, b in zip(c0[c], c1[c])) for c in (0, 1)}
+    code, est = pxp.status()
+    report = _lib.pxp_last_report(pxp.problems, pxp.ws)
+    res_pxp = pxp.results()
+    log("paraexp %.3f ms/step  kernels %s  status %d est %.1e" % (t_pxp * 1e3, kern, code, est))
+
+    t_graph = None
+    if args.graph and name == args.workload:
+        t_graph = time_graph(torch, pxp, steps)
+        log("paraexp, hipGraph replay %.3f ms/step" % (t_graph * 1e3))
+
+    t_ser = time_runner(torch, ser, serial_steps, 1)
+    res_ser = ser.results()
+    log("serial %.3f ms/step" % (t_ser * 1e3))
+
+    # accuracy against the oracle on a bounded sample of the instances, run
+    # instance-parallel; the same runs time the CPU baseline
+    sample = oracle_sample(insts, work, args.oracle_budget)
+    err, orc = None, None
+    if with_oracle:
+        hi = host_info()
+        threads = max(1, min(len(sample), hi["usable_cpus"] or 1, args.oracle_threads))
+        refs, wall, per = run_oracle(insts, sample, threads)
+        err = dict(paraexp_grad=0.0, paraexp_grad_maxabs=0.0, paraexp_adjoint=0.0,
+                   paraexp_qT=0.0, serial_grad=0.0, serial_qT=0.0)
+        for i in sample:
+            ref = refs[i]
+            lam_key = "Lambda" if insts[i]["control"] == "forcing" else "lam0"
+            g = res_pxp[i]["grad"]
+            e = dict(paraexp_grad=rel(g, ref["grad"]),
+                     paraexp_grad_maxabs=float(np.max(np.abs(g - ref["grad"])) /
+                                               np.max(np.abs(ref["grad"]))),
+                     paraexp_adjoint=rel(res_pxp[i]["lam"], ref[lam_key]),
+                     paraexp_qT=rel(res_pxp[i]["qT"], ref["qT"]),
+                     serial_grad=rel(res_ser[i]["grad"], ref["grad"]),
+                     serial_qT=rel(res_ser[i]["qT"], ref["qT"]))
+            err = {k: max(err[k], v) for k, v in e.items()}
+        w_s = sum(work[i] for i in sample)
+        orc = dict(wall=wall, cpu=sum(per.values()), threads=threads, point_steps=w_s,
+                   host=hi)
+        log("rel errors (max over %d sampled instance(s))" % len(sample), err,
+            "oracle %.2f s wall on %d thread(s), %.2f s summed" % (wall, threads, orc["cpu"]))
+
+    models = class_models(insts, pxp.problems, args, counters)
+    traffic = {}
+    if inst["op"] == "advdiff2d_upwind":
+        tr = profiled_traffic("k_pois2d_tree", "advdiff2d_256_kernels.md", "pxp_expo2d.hip")
+        if tr is not None:
+            traffic["krylov_direct"] = tr
+    elif name == SECONDARY_WORKLOAD:
+        tr = profiled_traffic("k_krylov1d_direct_classic")
+        if tr is not None:
+            traffic["krylov_direct"] = tr
+    roof, roof_all = roofline(kern, models, steps, traffic)
+
+    gate = 1e-8 if args.prec == "fp64" else 1e-5
+    ok = (err is not None and err["paraexp_grad"] <= gate and err["paraexp_qT"] <= gate
+          and code == 0)
+    out = dict(name=name, B=B, P=sorted({int(p.P) for p in pxp.problems}), t_pxp=t_pxp, t_ser=t_ser, t_graph=t_graph, ok=ok, gate=gate,
+               err=err, sample=sample, kern=kern, counters=counters, est=est, code=code,
+               roof=roof, roof_all=roof_all, tuned=tuned, report=report, sched=sched,
+               insts=insts, work=work, orc=orc)
+    return out
+
+
+def summary_report(report):
+    """Per-instance report condensed to ranges."""
+    if not report:
+        return None
+    keys = ("substeps", "iterations")
+    return dict(krylov_direct=sorted({str(r["krylov_direct"]) for r in report}),
+                krylov_adjoint=sorted({str(r["krylov_adjoint"]) for r in report}),
+                P=sorted({r["P"] for r in report}),
+                **{k: [min(r[k] for r in report), max(r[k] for r in report)] for k in keys},
+                max_est=max(r["max_est"] for r in report))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,17 +434,18 @@ def main():
     ap.add_argument("--warmup-seconds", type=float, default=2.0,
                     help="keep warming up (untimed gradients) for at least this long, so "
                          "the timed region runs at steady-state clocks")
-    ap.add_argument("--workload", default="advdiff1d_n4096")
-    ap.add_argument("--krylov", default="auto", choices=["poly", "shift_invert", "auto", "taylor", "uniform"])
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
+    ap.add_argument("--krylov", default="auto",
+                    choices=["poly", "shift_invert", "auto", "taylor", "uniform"])
     ap.add_argument("--sched", default=None, choices=["classic", "chain", "tree"],
                     help="schedule of the direct pieces (default: tree in 2D, classic in 1D)")
     ap.add_argument("--serial-steps", type=int, default=5)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32_bulk"])
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--block", type=int, default=0,
-                    help="threads per workgroup of the RK4 marches (0 = default)")
+                    help="threads per workgroup of the 1D RK4 marches (0 = default)")
     ap.add_argument("--kblock", type=int, default=0,
-                    help="threads per workgroup of the Krylov kernels (0 = default)")
+                    help="threads per workgroup of the 1D Krylov kernels (0 = default)")
     ap.add_argument("--graph", action="store_true",
                     help="also time replays of the gradient captured in a hipGraph")
     ap.add_argument("--absorbed", action="store_true",
@@ -120,6 +460,10 @@ def main():
                     help="use only the first K instances of a batch workload (0 = all)")
     ap.add_argument("--oracle-budget", type=float, default=2.5e8,
                     help="point-steps of the oracle accuracy sample for batch workloads")
+    ap.add_argument("--oracle-threads", type=int, default=16,
+                    help="oracle instances run at once (at most the usable host cores)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the secondary 1D N=4096 measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true",
                     help="skip the CPU accuracy check (profiler runs only; "
@@ -149,256 +493,79 @@ def main():
         print(json.dumps({"copy_calibration_bytes_per_launch": nbytes,
                           "launches": 5}), flush=True)
         return
-    insts = workloads.make(args.workload)
-    if args.instances > 0:
-        insts = insts[:args.instances]
+
+    m = measure(args, args.workload, torch, _lib, api, workloads, args.steps,
+                args.serial_steps, not args.no_oracle, not args.no_cpu_baseline)
+    insts, B = m["insts"], m["B"]
     inst = insts[0]
-    B = len(insts)
-    n, n_steps, P, m = inst["nx"] * inst.get("ny", 1), inst["n_steps"], inst["P"], inst["m"]
-    work = [int(x["nx"]) * int(x.get("ny", 1)) * int(x["n_steps"]) for x in insts]
-    log("workload %s: %d instance(s); first N=%d steps=%d P=%d m=%d; point-steps %.3g"
-        % (args.workload, B, n, n_steps, P, m, sum(work)))
-
-    if args.sched is None:
-        args.sched = "tree" if inst["op"] == "advdiff2d_upwind" else "classic"
-    tol = args.tol if args.tol is not None else (1e-9 if args.prec == "fp64" else 1e-6)
-    kw = dict(prec=args.prec, block=args.block, kblock=args.kblock)
-    pkw = dict(kw, absorbed=args.absorbed)
-    tuned = None
-    if args.autotune:
-        lo, hi = (int(v) for v in args.p_range.split(","))
-        t0 = time.perf_counter()
-        probs, rep = api.autotune(insts, p_min=lo, p_max=hi,
-                                  rtol=1e-9 if args.prec == "fp64" else 5e-6,
-                                  krylov=args.krylov, sched=args.sched, tol=tol, **pkw)
-        names = {v: k for k, v in _lib.KRYLOV.items()}
-        tuned = {"seconds": time.perf_counter() - t0,
-                 "P": sorted({int(p.P) for p in probs}),
-                 "krylov": sorted({names[int(p.krylov)] for p in probs}),
-                 "sched": sorted({"classic" if p.sched == 0 else "chain" for p in probs}),
-                 "kblock": sorted({int(p.kblock) for p in probs}),
-                 "groups": len({r["group"] for r in rep})}
-        log("autotune", tuned, rep[:4])
-        pxp = api.GradientRunner(insts, method="paraexp", problems=probs)
-    else:
-        pxp = api.GradientRunner(insts, method="paraexp", krylov=args.krylov,
-                                 sched=args.sched, tol=tol, **pkw)
-    ser = api.GradientRunner(insts, method="serial", krylov="auto", **kw)
-
-    # timed Paraexp region, with per-kernel events on the library's stream
-    warm(torch, pxp, args.warmup, args.warmup_seconds)
-    pxp.status()
-    _lib.pxp_device_counters(pxp.ws)
-    _lib.pxp_profile_enable(True)
-    for k in _lib.KCLASS:
-        _lib.pxp_profile_read(k)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        pxp.run()
-    torch.cuda.synchronize()
-    t_pxp = (time.perf_counter() - t0) / args.steps
-    _lib.pxp_profile_enable(False)
-    kern = {}
-    for k in _lib.KCLASS:
-        ms, cnt = _lib.pxp_profile_read(k)
-        if cnt:
-            kern[k] = dict(avg_ms=ms / cnt, launches=cnt, per_step_ms=ms / args.steps)
-    substeps, iters, reorth = _lib.pxp_device_counters(pxp.ws)
-    code, est = pxp.status()
-    res_pxp = pxp.results()
-    log("paraexp %.3f ms/step  kernels %s  status %d est %.1e"
-        % (t_pxp * 1e3, kern, code, est))
-
-    t_graph = None
-    if args.graph:
-        t_graph = time_graph(torch, pxp, args.steps)
-        log("paraexp, hipGraph replay %.3f ms/step" % (t_graph * 1e3))
-
-    t_ser = time_runner(torch, ser, args.serial_steps, 1)
-    res_ser = ser.results()
-    log("serial %.3f ms/step" % (t_ser * 1e3))
-
-    # accuracy against the oracle on a bounded sample of the instances (all
-    # of them for single-instance workloads); the same runs time the CPU
-    # baseline
-    sample = oracle_sample(insts, work, args.oracle_budget)
-    err = None
-    t_orc = float("nan")
-    if not args.no_oracle:
-        import oracle
-        oracle.build()
-        err = dict(paraexp_grad=0.0, paraexp_adjoint=0.0, paraexp_qT=0.0,
-                   serial_grad=0.0, serial_qT=0.0)
-        t0 = time.perf_counter()
-        for i in sample:
-            ref = oracle.gradient(insts[i])
-            lam_key = "Lambda" if insts[i]["control"] == "forcing" else "lam0"
-            e = dict(paraexp_grad=rel(res_pxp[i]["grad"], ref["grad"]),
-                     paraexp_adjoint=rel(res_pxp[i]["lam"], ref[lam_key]),
-                     paraexp_qT=rel(res_pxp[i]["qT"], ref["qT"]),
-                     serial_grad=rel(res_ser[i]["grad"], ref["grad"]),
-                     serial_qT=rel(res_ser[i]["qT"], ref["qT"]))
-            err = {k: max(err[k], v) for k, v in e.items()}
-        t_orc = time.perf_counter() - t0
-        log("rel errors (max over %d sampled instance(s))" % len(sample), err,
-            "oracle %.2f s" % t_orc)
-    else:
-        args.no_cpu_baseline = True
-
-    roof = roofline(kern, insts, args, substeps, iters, pxp.problems, reorth)
-
-    gate = 1e-8 if args.prec == "fp64" else 1e-5
-    ok = (err is not None and err["paraexp_grad"] <= gate and err["paraexp_qT"] <= gate
-          and code == 0)
-    cfg = {"workload": args.workload, "instances": B, "N": n, "T": inst["T"],
-           "n_steps": n_steps, "slices": P, "krylov_m": m, "krylov": args.krylov,
-           "schedule": args.sched, "precision": args.prec, "gate": gate,
-           "controls": int(np.asarray(inst["basis"]).shape[0]),
-           "block": args.block, "kblock": args.kblock,
-           "adjoint_form": "absorbed" if args.absorbed else "unabsorbed"}
-    if B > 1:
-        cfg.update(N=sorted({int(x["nx"]) * int(x.get("ny", 1)) for x in insts}),
-                   n_steps=[min(int(x["n_steps"]) for x in insts),
-                            max(int(x["n_steps"]) for x in insts)],
-                   T=[min(x["T"] for x in insts), max(x["T"] for x in insts)],
-                   point_steps=sum(work))
+    cfg = {"workload": args.workload, "instances": B,
+           "N": sorted({int(x["nx"]) * int(x.get("ny", 1)) for x in insts}),
+           "grid": sorted({"%dx%d" % (x["nx"], x.get("ny", 1)) for x in insts}),
+           "T": [min(x["T"] for x in insts), max(x["T"] for x in insts)],
+           "n_steps": [min(int(x["n_steps"]) for x in insts),
+                       max(int(x["n_steps"]) for x in insts)],
+           "slices": m["P"],
+           "krylov": args.krylov, "schedule": m["sched"], "precision": args.prec,
+           "gate": m["gate"], "controls": int(np.asarray(inst["basis"]).shape[0]),
+           "adjoint_form": "absorbed" if args.absorbed else "unabsorbed",
+           "point_steps": sum(m["work"])}
+    if m["tuned"] is not None:
+        cfg["autotune"] = m["tuned"]
     line = {
         "metric": METRIC,
-        "value": (B / t_pxp) if ok else 0.0,
+        "value": (B / m["t_pxp"]) if m["ok"] else 0.0,
         "unit": "gradient evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": t_pxp * 1e3,
+        "ms_per_step": m["t_pxp"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.prec == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": cfg,
-        "serial_gpu": {"value": B / t_ser, "ms_per_step": t_ser * 1e3},
-        "speedup_vs_serial": t_ser / t_pxp,
-        "rel_err_vs_oracle": err,
-        "oracle_sample": sample,
-        "krylov": {"spaces_per_step": substeps / max(1, args.steps),
-                   "iters_per_step": iters / max(1, args.steps),
-                   "reorth_per_step": reorth / max(1, args.steps),
-                   "max_est": est, "status": code},
-        "kernels_ms": {k: v["avg_ms"] for k, v in kern.items()},
-        "roofline": roof,
+        "serial_gpu": {"value": B / m["t_ser"], "ms_per_step": m["t_ser"] * 1e3},
+        "speedup_vs_serial": m["t_ser"] / m["t_pxp"],
+        "rel_err_vs_oracle": m["err"],
+        "oracle_sample": m["sample"],
+        "krylov_counters_per_step": {"direct": m["counters"][0], "adjoint": m["counters"][1],
+                                     "fields": ["substeps", "iterations or terms",
+                                                "second Gram-Schmidt passes"],
+                                     "max_est": m["est"], "status": m["code"]},
+        "instance_report": summary_report(m["report"]),
+        "kernels_ms": {k: v["avg_ms"] for k, v in m["kern"].items()},
+        "roofline": m["roof"],
+        "roofline_classes": m["roof_all"],
     }
-    if t_graph is not None:
-        line["graph"] = {"value": B / t_graph, "ms_per_step": t_graph * 1e3}
-    if tuned is not None:
-        line["config"]["autotune"] = tuned
-    if not args.no_cpu_baseline:
-        w_s = sum(work[i] for i in sample)
-        t_all = t_orc * sum(work) / w_s
+    if m["t_graph"] is not None:
+        line["graph"] = {"value": B / m["t_graph"], "ms_per_step": m["t_graph"] * 1e3}
+    if m["orc"] is not None and not args.no_cpu_baseline:
+        o = m["orc"]
+        work = m["work"]
+        # the whole batch at the sample's measured rates
+        t_par = o["wall"] * sum(work) / o["point_steps"]
+        t_one = o["cpu"] * sum(work) / o["point_steps"]
         line["cpu_baseline"] = {
-            "value": B / t_all, "unit": "gradient evals/s", "cores": 1, "kind": "oracle",
-            "sample": ("one full gradient of the workload (serial FP64 RK4 + exact "
-                       "discrete adjoint)" if B == 1 else
-                       "full gradients of instances %s (%.3g of %.3g point-steps, %.1f s), "
-                       "scaled by point-steps to the %d-instance batch"
-                       % (sample, w_s, sum(work), t_orc, B))}
+            "value": B / t_par, "unit": "gradient evals/s", "cores": o["threads"],
+            "kind": "oracle",
+            "single_core_value": B / t_one,
+            "host": o["host"],
+            "sample": ("full gradients (serial FP64 RK4 + exact discrete adjoint) of "
+                       "instances %s, %.3g of %.3g point-steps, run %d at a time: %.1f s "
+                       "wall, %.1f s summed over instances; scaled by point-steps to the "
+                       "%d-instance batch" % (m["sample"], o["point_steps"], sum(work),
+                                              o["threads"], o["wall"], o["cpu"], B))}
+    if not args.no_secondary and args.workload == DEFAULT_WORKLOAD:
+        s = measure(args, SECONDARY_WORKLOAD, torch, _lib, api, workloads,
+                    max(5, args.steps // 2), 2, not args.no_oracle, False)
+        line["secondary"] = {
+            "workload": SECONDARY_WORKLOAD, "value": (s["B"] / s["t_pxp"]) if s["ok"] else 0.0,
+            "ms_per_step": s["t_pxp"] * 1e3, "serial_ms_per_step": s["t_ser"] * 1e3,
+            "speedup_vs_serial": s["t_ser"] / s["t_pxp"], "rel_err_vs_oracle": s["err"],
+            "kernels_ms": {k: v["avg_ms"] for k, v in s["kern"].items()},
+            "roofline": s["roof"], "instance_report": summary_report(s["report"])}
     print(json.dumps(line), flush=True)
-
-
-def oracle_sample(insts, work, budget):
-    """Instances the oracle checks: all of a single-instance workload; for a
-    batch, the cheapest instance of each grid size, then the cheapest others
-    while the point-step budget lasts."""
-    if len(insts) == 1:
-        return [0]
-    order = sorted(range(len(insts)), key=lambda i: work[i])
-    pick, seen, used = [], set(), 0
-    for i in order:
-        nn = int(insts[i]["nx"]) * int(insts[i].get("ny", 1))
-        if nn not in seen:
-            pick.append(i)
-            seen.add(nn)
-            used += work[i]
-    for i in order:
-        if i not in pick and used + work[i] <= budget:
-            pick.append(i)
-            used += work[i]
-    return sorted(pick)
-
-
-def time_graph(torch, r, steps):
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
-        r.run()
-    torch.cuda.current_stream().wait_stream(s)
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        r.run()
-    g.replay()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        g.replay()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
-
-
-def roofline(kern, insts, args, substeps, iters, problems, reorth=0):
-    """Roofline object for the kernel class that takes the most time per step."""
-    if not kern:
-        return None
-    top = max(kern, key=lambda k: kern[k]["per_step_ms"])
-    inst = insts[0]
-    n = inst["nx"] * inst.get("ny", 1)
-    P, m = int(problems[0].P), int(problems[0].m)
-    sec = kern[top]["avg_ms"] * 1e-3
-    if top == "krylov_direct" and int(problems[0].sched) == 0 and len(insts) == 1:
-        # spaces may stop before dimension m: count the average dimension
-        # reached (Arnoldi iterations / spaces, all launches), rounded down
-        m_eff = min(m, int(iters / max(substeps, 1))) if substeps else m
-        passes = 1.0 + reorth / iters if iters else 2.0
-        byts = (P - 1) * krylov_space_bytes(n, m_eff, passes)
-        ach = byts / sec / 1e9
-        return dict(kernel="k_krylov1d, direct pieces (classic, %d workgroups)" % (P - 1),
-                    bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=ach / HBM_PEAK_GBS,
-                    traffic=profiled_traffic("k_krylov1d_direct_classic"),
-                    algorithmic_bytes_per_launch=byts, krylov_dim=m_eff,
-                    gram_schmidt_passes=passes,
-                    avg_launch_ms=kern[top]["avg_ms"])
-    if top == "slices" and len(insts) == 1:
-        ach = rk4_slice_flops(n, inst["n_steps"]) / sec / 1e12
-        return dict(kernel="k_rk4_lin1d (inhomogeneous slices)", bound="alu",
-                    achieved=ach, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=ach / FP64_PEAK_TFLOPS, traffic=None, avg_launch_ms=kern[top]["avg_ms"])
-    if top == "serial_direct" and all(x["op"] == "burgers1d" for x in insts):
-        # one launch marches every instance; 48 flop per point and step
-        per_step = kern[top]["launches"] / args.steps
-        fl = sum(48.0 * x["nx"] * x["n_steps"] for x in insts) / per_step
-        peak = FP64_PEAK_TFLOPS if args.prec == "fp64" else FP32_PEAK_TFLOPS
-        ach = fl / sec / 1e12
-        return dict(kernel="k_burgers_direct_batch (serial Burgers RK4 marches)",
-                    bound="alu", achieved=ach, peak=peak, unit="TFLOP/s",
-                    frac=ach / peak, traffic=None, avg_launch_ms=kern[top]["avg_ms"])
-    if top in ("ltv_adjoint", "krylov_adjoint", "krylov_direct"):
-        # bytes streamed by the Arnoldi steps actually taken (device counters):
-        # step j of a space reads j+1 basis vectors twice per Gram-Schmidt
-        # pass (passes from the device's second-pass counter) and writes one
-        sp = substeps / max(1, args.steps)
-        it = iters / max(1, args.steps)
-        mm = it / max(sp, 1.0)
-        nbar = sum(x["nx"] * x.get("ny", 1) for x in insts) / len(insts)
-        passes = 1.0 + reorth / iters if iters else 2.0
-        byts = sp * krylov_space_bytes(nbar, max(1, int(round(mm))), passes)
-        launches = kern[top]["launches"] / args.steps
-        ach = byts / launches / sec / 1e9
-        return dict(kernel="k_krylov1d (%s)" % top, bound="hbm", achieved=ach,
-                    peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=None,
-                    avg_launch_ms=kern[top]["avg_ms"])
-    return dict(kernel=top, bound=None, achieved=None, peak=None, unit=None, frac=None,
-                traffic=None, avg_launch_ms=kern[top]["avg_ms"])
 
 
 if __name__ == "__main__":

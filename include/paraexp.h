@@ -149,8 +149,8 @@ typedef struct {
 pxp_status pxp_workspace_size(const pxp_problem* pb, int32_t batch,
                               size_t* bytes);
 
-/* Zero the device status block at the start of a fresh workspace (enqueued
- * on `stream` as a kernel).  Call once after allocating `ws`, outside any
+/* Zero a fresh workspace (status block, per-instance statistics and the
+ * rest; enqueued on `stream` as a kernel).  Call once after allocating `ws`, outside any
  * stream capture: on its first call on a device it also creates the
  * library's side stream there (default priority, non-blocking) and two
  * events, which the compute calls use to run independent launch groups of
@@ -174,13 +174,19 @@ pxp_status paraexp_direct(const pxp_problem* pb, int32_t batch,
  * adjhomfinal) from the final condition lamT (= dJ/dq(T)).  lamT, lam0
  * and Lambda must be 16-byte aligned at every instance offset (PXP_EINVAL
  * otherwise):
+ *   jI_src  [sum (n_steps+1) n]  source of an integral cost term J_I =
+ *           int_0^T j(q, t) dt (section 2, eq. adjEquation: the adjoint's
+ *           source -dj/dq at the RK4 step times), nullable; a terminal cost
+ *           passes NULL.  Not implemented: non-null returns PXP_EUNSUPPORTED
+ *           before anything is enqueued.
  *   lam0    [sum n]  output q^dagger(0) (nullable)
  *   Lambda  [sum n]  output int_0^T sin(omega t) q^dagger(t) dt (nullable)
- * Burgers instances need the checkpoints of the preceding paraexp_direct
- * call in the same workspace. */
+ * Burgers instances read the checkpoints that the preceding paraexp_direct
+ * call left in the same workspace (the workspace holds them, not a caller
+ * array: a second direct call on that workspace replaces them). */
 pxp_status paraexp_adjoint(const pxp_problem* pb, int32_t batch,
-                           const double* lamT, double* lam0, double* Lambda,
-                           void* ws, size_t ws_bytes, void* stream);
+                           const double* lamT, const double* jI_src, double* lam0,
+                           double* Lambda, void* ws, size_t ws_bytes, void* stream);
 
 /* Full direct-adjoint loop (section 2): control -> J and dJ/da.
  *   ctrl   [sum K]      control amplitudes a
@@ -227,7 +233,7 @@ pxp_status pxp_reduce_gradient(const pxp_problem* pb, int32_t batch,
                                const double* ctrl, double* grad, void* stream);
 
 /* Synchronises `stream` and returns the device-side status recorded in the
- * workspace by the last calls (PXP_OK, PXP_EKRYLOV_NOCONV, PXP_ENONFINITE);
+ * workspace (its first 64 bytes) by the last calls (PXP_OK, PXP_EKRYLOV_NOCONV, PXP_ENONFINITE);
  * `max_est` (host, nullable) receives the largest relative Krylov error
  * estimate seen.  Clears the recorded status. */
 pxp_status pxp_device_status(void* ws, size_t ws_bytes, void* stream,
@@ -242,6 +248,34 @@ pxp_status pxp_device_status(void* ws, size_t ws_bytes, void* stream,
 pxp_status pxp_device_counters(void* ws, size_t ws_bytes, void* stream,
                                uint64_t* substeps, uint64_t* krylov_iters,
                                uint64_t* reorth_passes);
+
+/* The same counters for one class of exponentials: cls = 0 the direct
+ * pieces (eq. hom), cls = 1 the adjoint pieces (eqs. adjHomNormal,
+ * adjhomfinal, the absorbed adjoint's pieces and the time-varying Magnus
+ * chains).  For the Taylor flavour the iteration counter holds Taylor terms.
+ * The uniformised 2D exponentials fix their terms before the launch and do
+ * not count.  PXP_EINVAL for another cls. */
+pxp_status pxp_device_counters_class(void* ws, size_t ws_bytes, void* stream, int32_t cls,
+                                     uint64_t* substeps, uint64_t* krylov_iters,
+                                     uint64_t* reorth_passes);
+
+/* Per-instance report of the exponentials since the workspace was
+ * initialised or last reported on (host output `out`, one entry per
+ * instance of the same batch and workspace as the compute calls).
+ * Synchronises `stream`, then clears the statistics.  P and the schedule are
+ * the problem's (sched -1: the direct march is serial, Burgers); the flavours
+ * are the ones that ran, AUTO resolved (-1: no exponential).  substeps counts
+ * Krylov substeps (uniformised exponentials: one per exponential);
+ * iterations counts Arnoldi steps or series terms; max_est is the largest
+ * error estimate, relative to |v| (Krylov: a posteriori; uniformisation: the
+ * a priori Poisson tail). */
+typedef struct {
+    int32_t P, sched, krylov_direct, krylov_adjoint;
+    uint64_t substeps, iterations;
+    double max_est, pad;
+} pxp_report;
+pxp_status pxp_last_report(const pxp_problem* pb, int32_t batch, void* ws, size_t ws_bytes,
+                           void* stream, pxp_report* out);
 
 /* Launch timing for benchmarks and profiling.  While enabled, every launch
  * of a kernel class is bracketed by two HIP events recorded on the launch

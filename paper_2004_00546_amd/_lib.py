@@ -33,7 +33,8 @@ EXPORTED = ("pxp_workspace_size", "pxp_workspace_init", "paraexp_direct",
             "pxp_device_counters", "pxp_status_str", "pxp_version",
             "pxp_profile_enable", "pxp_profile_read", "pxp_assemble",
             "pxp_cost", "pxp_reduce_gradient", "pxp_tune_workspace_size",
-            "pxp_autotune", "pxp_gradient_noalloc")
+            "pxp_autotune", "pxp_gradient_noalloc", "pxp_device_counters_class",
+            "pxp_last_report")
 KCLASS = {"slices": 0, "krylov_direct": 1, "krylov_adjoint": 2,
           "serial_direct": 3, "serial_reverse": 4, "ltv_adjoint": 5,
           "ltv_nodes": 6}
@@ -63,6 +64,13 @@ class pxp_tune_report(ctypes.Structure):
                 ("rel_err", ctypes.c_double)]
 
 
+class pxp_report(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int32), ("sched", ctypes.c_int32),
+                ("krylov_direct", ctypes.c_int32), ("krylov_adjoint", ctypes.c_int32),
+                ("substeps", ctypes.c_uint64), ("iterations", ctypes.c_uint64),
+                ("max_est", ctypes.c_double), ("pad", ctypes.c_double)]
+
+
 class PxpError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
@@ -89,7 +97,7 @@ def load() -> ctypes.CDLL:
         "pxp_workspace_size": (st, [P, i32, ctypes.POINTER(sz)]),
         "pxp_workspace_init": (st, [vp, sz, vp]),
         "paraexp_direct": (st, [P, i32, vp, vp, vp, vp, sz, vp]),
-        "paraexp_adjoint": (st, [P, i32, vp, vp, vp, vp, sz, vp]),
+        "paraexp_adjoint": (st, [P, i32, vp, vp, vp, vp, vp, sz, vp]),
         "pxp_gradient": (st, [P, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                               sz, vp]),
         "gradient": (st, [P, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
@@ -110,6 +118,10 @@ def load() -> ctypes.CDLL:
                               vp, sz, ctypes.POINTER(pxp_tune_report), vp]),
         "pxp_gradient_noalloc": (st, [P, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                       vp]),
+        "pxp_last_report": (st, [P, i32, vp, sz, vp, ctypes.POINTER(pxp_report)]),
+        "pxp_device_counters_class": (st, [vp, sz, vp, i32, ctypes.POINTER(ctypes.c_uint64),
+                                           ctypes.POINTER(ctypes.c_uint64),
+                                           ctypes.POINTER(ctypes.c_uint64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -165,10 +177,10 @@ def paraexp_direct(problems, q0, F, qT, ws, stream=None):
                                  ws.numel(), _stream(stream)), "paraexp_direct")
 
 
-def paraexp_adjoint(problems, lamT, lam0, Lambda, ws, stream=None):
+def paraexp_adjoint(problems, lamT, lam0, Lambda, ws, stream=None, jI_src=None):
     arr, n = problems_array(problems)
-    _check(load().paraexp_adjoint(arr, n, _ptr(lamT), _ptr(lam0), _ptr(Lambda),
-                                  _ptr(ws), ws.numel(), _stream(stream)),
+    _check(load().paraexp_adjoint(arr, n, _ptr(lamT), _ptr(jI_src), _ptr(lam0),
+                                  _ptr(Lambda), _ptr(ws), ws.numel(), _stream(stream)),
            "paraexp_adjoint")
 
 
@@ -218,6 +230,34 @@ def pxp_device_counters(ws, stream=None):
                                       ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
            "pxp_device_counters")
     return a.value, b.value, c.value
+
+
+def pxp_device_counters_class(ws, cls, stream=None):
+    """(substeps, iterations or Taylor terms, second Gram-Schmidt passes) of
+    the direct (cls 0) or adjoint (cls 1) exponentials"""
+    a, b, c = ctypes.c_uint64(0), ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _check(load().pxp_device_counters_class(_ptr(ws), ws.numel(), _stream(stream), cls,
+                                            ctypes.byref(a), ctypes.byref(b),
+                                            ctypes.byref(c)),
+           "pxp_device_counters_class")
+    return a.value, b.value, c.value
+
+
+def pxp_last_report(problems, ws, stream=None):
+    """Per-instance statistics since the last report (dicts); clears them."""
+    arr, n = problems_array(problems)
+    rep = (pxp_report * n)()
+    _check(load().pxp_last_report(arr, n, _ptr(ws), ws.numel(), _stream(stream), rep),
+           "pxp_last_report")
+    names = {v: k for k, v in KRYLOV.items()}
+    out = []
+    for r in rep:
+        d = dict((f, getattr(r, f)) for f, _ in pxp_report._fields_ if f != "pad")
+        d["krylov_direct"] = names.get(d["krylov_direct"], None)
+        d["krylov_adjoint"] = names.get(d["krylov_adjoint"], None)
+        d["sched"] = {0: "classic", 1: "chain", 2: "tree"}.get(d["sched"], None)
+        out.append(d)
+    return out
 
 
 def pxp_profile_enable(on: bool):

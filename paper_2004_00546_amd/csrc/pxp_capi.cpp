@@ -29,6 +29,7 @@ struct Layout {
     size_t btab, ktab, t2d;    // batch tables: Burgers, Krylov, 2D marches
     size_t ptab, pwt;          // uniformised exponentials: pass entries, weights
     size_t rtab, rpart;        // batched cost/gradient: descriptors, partial sums
+    size_t irep;               // per-instance statistics
     std::vector<size_t> base;  // per-instance region offset
     size_t total;
 };
@@ -439,6 +440,8 @@ Layout layout(const pxp_problem* pb, int batch) {
         np += (size_t)(pb[i].K + 1) * (size_t)((grid_n(pb[i]) + RED_CHUNK - 1) / RED_CHUNK);
     Ly.rpart = off;
     off += align_up(np * sizeof(double));
+    Ly.irep = off;
+    off += align_up((size_t)batch * sizeof(InstStat));
     for (int i = 0; i < batch; ++i) {
         Ly.base.push_back(off);
         off += inst_layout(pb[i]).size;
@@ -553,6 +556,7 @@ struct Ctx {
     Inst L;
     DevStatus* st;
     hipStream_t s;
+    InstStat* irep;
     double* at(size_t off) const { return reinterpret_cast<double*>(base + off); }
     int n() const { return (int)grid_n(p); }
     double dt() const { return p.T / (double)p.n_steps; }
@@ -590,6 +594,7 @@ KrylovArgs kargs(const Ctx& c, Tri op) {
     a.op = op;
     a.basis = c.at(c.L.basis);
     a.status = c.st;
+    a.irep = c.irep;
     a.fp32 = c.fp32();
     return a;
 }
@@ -688,6 +693,7 @@ pxp_status adjoint_lin1d_absorbed(const Ctx& c, const double* lamT, double* lam0
         // (2) P-1 homogeneous pieces exp((P-1-p) dT A^T) w_p with integrals
         KrylovArgs a = kargs(c, AT);
         a.mode = KM_CLASSIC;
+        a.adj = 1;
         a.npieces = P - 1;
         a.vin = sl;
         a.yout = c.at(c.L.pieces);
@@ -843,7 +849,8 @@ Ctx make_ctx(const pxp_problem& p, void* ws, const Layout& Ly, int i,
              hipStream_t s) {
     char* w = static_cast<char*>(ws);
     return Ctx{p, w + Ly.base[i], inst_layout(p),
-               reinterpret_cast<DevStatus*>(w + Ly.status), s};
+               reinterpret_cast<DevStatus*>(w + Ly.status), s,
+               reinterpret_cast<InstStat*>(w + Ly.irep) + i};
 }
 
 BurgersDesc burgers_desc(const pxp_problem& p, const Ctx& c) {
@@ -1084,6 +1091,7 @@ struct PJob {
     double lam = 0.0, est = 0.0;
     Sten5 N{};
     DevStatus* st = nullptr;
+    InstStat* irep = nullptr;
 };
 
 int pois_passes(int D) { return (D + POIS_PASS_TERMS - 1) / POIS_PASS_TERMS; }
@@ -1138,6 +1146,7 @@ pxp_status run_stage(const std::vector<PJob>& jobs, PoisEntry* dtab, hipStream_t
                     e.rows = rows;
                     e.blk0 = blk;
                     e.status = j.st;
+                    e.irep = j.irep;
                     blk += j.nvec * (j.ny / rows);
                     tab.push_back(e);
                 }
@@ -1194,6 +1203,7 @@ void tree_levels(const pxp_problem& p, const Ctx& c, double* qT,
             b.ny = p.ny;
             b.N = uniform_N(A, mu);
             b.st = c.st;
+            b.irep = c.irep;
             lv.push_back(b);
             j = j1;
         }
@@ -1210,6 +1220,7 @@ void tree_levels(const pxp_problem& p, const Ctx& c, double* qT,
             b.ny = p.ny;
             b.N = uniform_N(A, mu);
             b.st = c.st;
+            b.irep = c.irep;
             lv.push_back(b);
         }
         levels.push_back(lv);
@@ -1236,6 +1247,7 @@ void chain_levels(const pxp_problem& p, const Ctx& c, double* qT,
     b.ny = p.ny;
     b.N = uniform_N(A, mu);
     b.st = c.st;
+    b.irep = c.irep;
     b.tb[0] = tb0;
     b.tb[1] = tb0 + n;
     b.sx = b.sp = b.so = n;
@@ -1475,6 +1487,7 @@ pxp_status adjoint_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, 
                 b.ny = p.ny;
                 b.N = uniform_N(AT, mu);
                 b.st = c.st;
+                b.irep = c.irep;
                 b.tb[0] = c.at(c.L.tbuf);
                 b.tb[1] = b.tb[0] + n;
                 b.sx = b.sp = b.so = n;
@@ -1582,8 +1595,58 @@ pxp_status pxp_workspace_size(const pxp_problem* pb, int32_t batch,
 pxp_status pxp_workspace_init(void* ws, size_t ws_bytes, void* stream) {
     if (!ws || ws_bytes < sizeof(DevStatus)) return PXP_EWORKSPACE;
     side_init();
-    if (launch_zero(static_cast<double*>(ws), sizeof(DevStatus) / sizeof(double),
+    // the whole workspace starts at zero: the status block and the
+    // per-instance statistics accumulate from there
+    if (launch_zero(static_cast<double*>(ws), ws_bytes / sizeof(double),
                     static_cast<hipStream_t>(stream)) != hipSuccess)
+        return PXP_EHIP;
+    return PXP_OK;
+}
+
+// Flavour of the direct and of the adjoint exponentials as they run.
+int flavour_direct(const pxp_problem& p) {
+    if (p.op == PXP_OP_BURGERS1D) return -1;  // the direct march is serial
+    if (uniform_direct(p)) return PXP_KRYLOV_UNIFORM;
+    if (use_si(p)) return PXP_KRYLOV_SHIFT_INVERT;
+    return use_taylor(p) ? PXP_KRYLOV_TAYLOR : PXP_KRYLOV_POLY;
+}
+int flavour_adjoint(const pxp_problem& p) {
+    if (uniform_adjoint(p)) return PXP_KRYLOV_UNIFORM;
+    if (use_si(p)) return PXP_KRYLOV_SHIFT_INVERT;
+    return use_taylor(p) ? PXP_KRYLOV_TAYLOR : PXP_KRYLOV_POLY;
+}
+
+pxp_status pxp_last_report(const pxp_problem* pb, int32_t batch, void* ws, size_t ws_bytes,
+                           void* stream, pxp_report* out) {
+    pxp_status st = check_all(pb, batch);
+    if (st != PXP_OK) return st;
+    if (batch == 0) return PXP_OK;
+    if (!out) return PXP_EINVAL;
+    Layout Ly;
+    st = ws_check(pb, batch, ws, ws_bytes, &Ly);
+    if (st != PXP_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipStreamSynchronize(s) != hipSuccess) return PXP_EHIP;
+    std::vector<InstStat> h(batch);
+    char* w = static_cast<char*>(ws);
+    if (hipMemcpy(h.data(), w + Ly.irep, batch * sizeof(InstStat), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return PXP_EHIP;
+    for (int i = 0; i < batch; ++i) {
+        const pxp_problem& p = pb[i];
+        pxp_report& r = out[i];
+        r.P = p.P;
+        r.sched = (p.op == PXP_OP_BURGERS1D) ? -1 : p.sched;
+        r.krylov_direct = flavour_direct(p);
+        r.krylov_adjoint = flavour_adjoint(p);
+        r.substeps = h[i].substeps;
+        r.iterations = h[i].iters;
+        std::memcpy(&r.max_est, &h[i].max_est, sizeof(double));
+        r.pad = 0.0;
+    }
+    if (launch_zero(reinterpret_cast<double*>(w + Ly.irep),
+                    batch * sizeof(InstStat) / sizeof(double), s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
         return PXP_EHIP;
     return PXP_OK;
 }
@@ -1685,8 +1748,11 @@ static pxp_status adjoint_impl(const pxp_problem* pb, int32_t batch,
 }
 
 pxp_status paraexp_adjoint(const pxp_problem* pb, int32_t batch,
-                           const double* lamT, double* lam0, double* Lambda,
-                           void* ws, size_t ws_bytes, void* stream) {
+                           const double* lamT, const double* jI_src, double* lam0,
+                           double* Lambda, void* ws, size_t ws_bytes, void* stream) {
+    // the integral-cost source needs the direct trajectory inside the slices
+    // (adjoint slices from corrected boundary states): not available
+    if (jI_src) return PXP_EUNSUPPORTED;
     return adjoint_impl(pb, batch, lamT, lam0, Lambda, ws, ws_bytes, stream,
                         PXP_METHOD_PARAEXP);
 }
@@ -1960,9 +2026,25 @@ pxp_status pxp_device_counters(void* ws, size_t ws_bytes, void* stream,
     DevStatus h{};
     if (hipMemcpy(&h, ws, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
         return PXP_EHIP;
-    if (substeps) *substeps = h.substeps;
-    if (krylov_iters) *krylov_iters = h.krylov_iters;
-    if (reorth_passes) *reorth_passes = h.reorth;
+    if (substeps) *substeps = h.substeps[0] + h.substeps[1];
+    if (krylov_iters) *krylov_iters = h.krylov_iters[0] + h.krylov_iters[1];
+    if (reorth_passes) *reorth_passes = h.reorth[0] + h.reorth[1];
+    return PXP_OK;
+}
+
+pxp_status pxp_device_counters_class(void* ws, size_t ws_bytes, void* stream, int32_t cls,
+                                     uint64_t* substeps, uint64_t* krylov_iters,
+                                     uint64_t* reorth_passes) {
+    if (cls != 0 && cls != 1) return PXP_EINVAL;
+    if (!ws || ws_bytes < sizeof(DevStatus)) return PXP_EWORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipStreamSynchronize(s) != hipSuccess) return PXP_EHIP;
+    DevStatus h{};
+    if (hipMemcpy(&h, ws, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+        return PXP_EHIP;
+    if (substeps) *substeps = h.substeps[cls];
+    if (krylov_iters) *krylov_iters = h.krylov_iters[cls];
+    if (reorth_passes) *reorth_passes = h.reorth[cls];
     return PXP_OK;
 }
 

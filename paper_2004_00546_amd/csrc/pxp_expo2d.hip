@@ -178,8 +178,16 @@ __global__ void __launch_bounds__(BNT) k_pois2d(const PoisEntry* __restrict__ ta
     }
     if (E.final_pass && E.status) {
         if (__any(bad) && l == 0) atomicOr(&E.status->flags, ST_NONFINITE);
-        if (local == 0 && t == 0)
-            atomicMax(&E.status->max_est, (unsigned long long)__double_as_longlong(E.est));
+        if (local == 0 && t == 0) {
+            const unsigned long long eb = (unsigned long long)__double_as_longlong(E.est);
+            atomicMax(&E.status->max_est, eb);
+            if (E.irep) {
+                // one exponential per vector of the entry, k1 terms each
+                atomicAdd(&E.irep->substeps, (unsigned long long)E.nvec);
+                atomicAdd(&E.irep->iters, (unsigned long long)E.nvec * (unsigned long long)E.k1);
+                atomicMax(&E.irep->max_est, eb);
+            }
+        }
     }
 }
 

@@ -24,10 +24,18 @@ struct DevStatus {
                                  // bit 1: non-finite value met
     unsigned int pad;
     unsigned long long max_est;  // bit pattern of the largest relative est.
-    unsigned long long substeps; // accepted Krylov substeps (all pieces)
-    unsigned long long krylov_iters;
-    unsigned long long reorth;   // Arnoldi steps that took a second
-                                 // Gram-Schmidt pass
+    // per class: [0] direct pieces, [1] adjoint pieces
+    unsigned long long substeps[2];      // accepted Krylov substeps
+    unsigned long long krylov_iters[2];  // Arnoldi steps (Taylor: terms)
+    unsigned long long reorth[2];        // Arnoldi steps that took a second
+                                         // Gram-Schmidt pass
+};
+static_assert(sizeof(DevStatus) == 64, "status block layout");
+// Per-instance statistics beside the status block: Krylov substeps and
+// iterations (Arnoldi steps, or series terms) and the largest error estimate
+// (bit pattern) of one instance's exponentials since the last read.
+struct InstStat {
+    unsigned long long substeps, iters, max_est, pad;
 };
 constexpr unsigned int ST_NOCONV = 1u;
 constexpr unsigned int ST_NONFINITE = 2u;
@@ -144,6 +152,9 @@ struct KrylovArgs {
     int taylor, tdeg;
     double anorm, theta;
     DevStatus* status;
+    int adj;             // counters of the adjoint class (absorbed pieces;
+                         // KM_SINGLE and KM_LTV count there anyway)
+    InstStat* irep;      // this instance's statistics (nullable)
 };
 hipError_t launch_krylov1d(const KrylovArgs& a, int block, hipStream_t s);
 // Batched time-varying chains: workgroup i runs tab[i] (KM_LTV, polynomial),
@@ -228,6 +239,7 @@ struct PoisEntry {
     int k0, k1, final_pass, nvec;
     int nx, ny, rows, blk0;  // rows: output rows per band (16 or 32)
     DevStatus* status;
+    InstStat* irep;          // the instance's statistics (nullable)
 };
 hipError_t launch_pois2d(const PoisEntry* tab, int count, int total_blocks, int nx, int two,
                          hipStream_t s);

@@ -242,9 +242,16 @@ struct Core {
             const double e = fabs(est_rel);
             if (e == e)
                 atomicMax(&a.status->max_est, (unsigned long long)__double_as_longlong(e));
-            atomicAdd(&a.status->substeps, (unsigned long long)substeps);
-            atomicAdd(&a.status->krylov_iters, (unsigned long long)iters);
-            atomicAdd(&a.status->reorth, (unsigned long long)nre);
+            const int cls = (a.adj || a.mode == KM_SINGLE || a.mode == KM_LTV) ? 1 : 0;
+            atomicAdd(&a.status->substeps[cls], (unsigned long long)substeps);
+            atomicAdd(&a.status->krylov_iters[cls], (unsigned long long)iters);
+            atomicAdd(&a.status->reorth[cls], (unsigned long long)nre);
+            if (a.irep) {
+                atomicAdd(&a.irep->substeps, (unsigned long long)substeps);
+                atomicAdd(&a.irep->iters, (unsigned long long)iters);
+                if (e == e)
+                    atomicMax(&a.irep->max_est, (unsigned long long)__double_as_longlong(e));
+            }
         }
         nre = 0;
     }

@@ -194,3 +194,18 @@ def test_noalloc_rejects_oversize_on_host(lib):
     code = lib.pxp_gradient_noalloc(arr, n, 0, None, None, None, None, None, None,
                                     None, None, None, None)
     assert code == _lib.PXP_EWORKSPACE
+
+
+def test_adjoint_rejects_integral_cost_source_on_host(lib):
+    """The J_I source argument exists at the boundary but is not implemented:
+    a non-null source is refused before any HIP call."""
+    inst = workloads.make("advdiff1d_n128")[0]
+    p = api.make_problem(inst)
+    arr, n = _lib.problems_array([p])
+    fake = ctypes.c_void_p(4096)  # never dereferenced: refused first
+    code = lib.paraexp_adjoint(arr, n, fake, fake, None, None, fake, 1 << 30, None)
+    assert code == _lib.PXP_EUNSUPPORTED
+
+
+def test_report_struct_layout():
+    assert ctypes.sizeof(_lib.pxp_report) == 4 * 4 + 2 * 8 + 2 * 8

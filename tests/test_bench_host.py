@@ -2,6 +2,7 @@
 algorithmic-bytes formula of an Arnoldi space, and the rule that counter
 traffic is reported only for the kernel source it was measured on."""
 import hashlib
+import math
 import os
 import subprocess
 import sys
@@ -50,3 +51,26 @@ def test_profiled_traffic_only_for_the_profiled_source(tmp_path, monkeypatch):
     # the kernel changed after the counters were taken: no traffic figure
     (tmp_path / "paper_2004_00546_amd" / "csrc" / "pxp_krylov.hip").write_text(src + "x")
     assert bench.profiled_traffic("k_direct") is None
+
+
+def test_tree_jobs_counts_pairs():
+    """A pairwise tree over P slices has P - 1 pairs; ceil(log2 P) levels;
+    the right-hand ranges of level l are 2^(l-1) slices (power of two P)."""
+    for P in (1, 2, 6, 13, 64, 256):
+        lv = bench.tree_jobs(P)
+        assert sum(len(x) for x in lv) == max(P - 1, 0)
+        assert len(lv) == (0 if P == 1 else math.ceil(math.log2(P)))
+    lv = bench.tree_jobs(256)
+    assert all(set(x) == {2 ** l} for l, x in enumerate(lv))
+
+
+def test_pois_terms_tail_rule():
+    """The smallest D whose Poisson tail is below tol: the tail at D is below,
+    the tail at D - 1 above (checked against a direct sum)."""
+    for lam in (0.13, 0.53, 8.5, 68.0, 136.0):
+        for tol in (1e-10, 1e-12):
+            D = bench.pois_terms(lam, tol)
+            pk = [math.exp(k * math.log(lam) - lam - math.lgamma(k + 1)) for k in range(D + 200)]
+            tail = lambda d: sum(pk[d:])  # noqa: E731
+            assert tail(D) <= tol * (1 + 1e-9)
+            assert tail(D - 1) > tol

@@ -619,3 +619,46 @@ def test_gradient_entry_point_matches_oracle(torch, orc, wl):
     assert abs(got["J"] - want["J"]) <= FP64_GATE * abs(want["J"])
     # no single component far off either (max-abs relative to the largest)
     assert np.max(np.abs(got["grad"] - want["grad"])) <= FP64_GATE * np.max(np.abs(want["grad"]))
+
+
+# ---- per-instance report and per-class counters ---------------------------------
+
+def test_last_report_per_instance(torch):
+    """A mixed batch (1D linear, Burgers, 2D) reports each instance's resolved
+    flavours, its own substeps and iterations, and an estimate within the
+    tolerance; reading clears the statistics."""
+    import test_gpu_2d_uniform as u2
+    insts = [small_advdiff(n=128, T=0.25, nt=250, P=5), small_burgers(),
+             u2.small2d(P=16)]
+    probs = [api.make_problem(x, krylov="auto", sched=sc, tol=1e-10)
+             for x, sc in zip(insts, ("classic", "classic", "tree"))]
+    r = api.GradientRunner(insts, method="paraexp", problems=probs)
+    r.run()
+    assert r.status()[0] == 0
+    rep = _lib.pxp_last_report(r.problems, r.ws)
+    say("report", rep)
+    a, b, c = rep
+    assert a["P"] == 5 and a["sched"] == "classic" and a["krylov_direct"] == "taylor"
+    assert a["substeps"] >= 5 and a["iterations"] > 0 and 0.0 <= a["max_est"] <= 1e-10
+    assert b["krylov_direct"] is None and b["sched"] is None
+    assert b["krylov_adjoint"] in ("taylor", "shift_invert") and b["substeps"] > 0
+    assert c["krylov_direct"] == "uniform" and c["krylov_adjoint"] == "uniform"
+    assert c["sched"] == "tree" and c["substeps"] >= 16 and c["iterations"] > 0
+    assert 0.0 < c["max_est"] <= 1e-12
+    again = _lib.pxp_last_report(r.problems, r.ws)
+    assert all(x["substeps"] == 0 and x["iterations"] == 0 for x in again)
+
+
+def test_counters_by_class(torch):
+    """Direct pieces and the adjoint piece count separately: P-1 classic
+    pieces of at least one substep each, one adjoint exponential."""
+    inst = small_advdiff(n=128, T=0.25, nt=250, P=5)
+    r = api.GradientRunner([inst], method="paraexp", krylov="poly", sched="classic", tol=1e-10)
+    _lib.pxp_device_counters(r.ws)
+    r.run()
+    d = _lib.pxp_device_counters_class(r.ws, 0)
+    j = _lib.pxp_device_counters_class(r.ws, 1)
+    tot = _lib.pxp_device_counters(r.ws)
+    say("counters direct %s adjoint %s total %s" % (d, j, tot))
+    assert d[0] >= 4 and j[0] >= 1
+    assert tot == tuple(x + y for x, y in zip(d, j))
