@@ -662,3 +662,59 @@ def test_counters_by_class(torch):
     say("counters direct %s adjoint %s total %s" % (d, j, tot))
     assert d[0] >= 4 and j[0] >= 1
     assert tot == tuple(x + y for x, y in zip(d, j))
+
+
+def test_ragged_workload_full_autotuned_graph_vs_oracle(torch, orc):
+    """The 64-instance ragged Burgers workload as stated: full horizons, FP32
+    bulk, slice counts autotuned within 32..256, the whole gradient captured
+    in a hipGraph and replayed (bit-equal to the eager call); the oracle
+    checks the cheapest instance of every grid size, N = 1024, 2048, 4096
+    and 8192, at the FP32-bulk gate."""
+    import time
+    from concurrent.futures import ThreadPoolExecutor
+    full = workloads.make("burgers1d_ragged")
+    t0 = time.perf_counter()
+    probs, rep = api.autotune(full, p_min=32, p_max=256, rtol=5e-6, krylov="auto",
+                              prec="fp32_bulk", tol=1e-6)
+    say("ragged autotune %.1f s: P %s" % (time.perf_counter() - t0,
+                                           sorted({int(p.P) for p in probs})))
+    assert all(32 <= int(p.P) <= 256 and x["n_steps"] % int(p.P) == 0
+               for p, x in zip(probs, full))
+    r = api.GradientRunner(full, method="paraexp", problems=probs)
+    r.run()
+    assert r.status()[0] == 0
+    eager = [dict(grad=b["grad"].copy(), qT=b["qT"].copy()) for b in r.results()]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        r.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        r.run()
+    for rep_i in range(2):
+        r.grad.zero_()
+        r.qT.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(eager, r.results()):
+            assert np.array_equal(a["grad"], b["grad"]), rep_i
+            assert np.array_equal(a["qT"], b["qT"]), rep_i
+    assert r.status()[0] == 0
+    res = r.results()
+    cost = [x["nx"] * x["n_steps"] for x in full]
+    picks = {}
+    for i, x in enumerate(full):
+        if x["nx"] not in picks or cost[i] < cost[picks[x["nx"]]]:
+            picks[x["nx"]] = i
+    assert sorted(picks) == [1024, 2048, 4096, 8192]
+    say("oracle on instances %s" % sorted(picks.values()))
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        refs = dict(zip(picks.values(), ex.map(lambda i: orc.gradient(full[i]), picks.values())))
+    for i, want in refs.items():
+        eg, eq = rel(res[i]["grad"], want["grad"]), rel(res[i]["qT"], want["qT"])
+        say("  N=%d steps=%d P=%d: qT %.2e grad %.2e" % (full[i]["nx"], full[i]["n_steps"],
+                                                       int(probs[i].P), eq, eg))
+        assert eg < FP32_GATE and eq < FP32_GATE
