@@ -360,9 +360,11 @@ def measure(args, name, torch, _lib, api, workloads, steps, serial_steps, with_o
         t_graph = time_graph(torch, pxp, steps)
         log("paraexp, hipGraph replay %.3f ms/step" % (t_graph * 1e3))
 
-    t_ser = time_runner(torch, ser, serial_steps, 1)
-    res_ser = ser.results()
-    log("serial %.3f ms/step" % (t_ser * 1e3))
+    t_ser, res_ser = None, None
+    if serial_steps > 0:
+        t_ser = time_runner(torch, ser, serial_steps, 1)
+        res_ser = ser.results()
+        log("serial %.3f ms/step" % (t_ser * 1e3))
 
     # accuracy against the oracle on a bounded sample of the instances, run
     # instance-parallel; the same runs time the CPU baseline
@@ -383,8 +385,8 @@ def measure(args, name, torch, _lib, api, workloads, steps, serial_steps, with_o
                                                np.max(np.abs(ref["grad"]))),
                      paraexp_adjoint=rel(res_pxp[i]["lam"], ref[lam_key]),
                      paraexp_qT=rel(res_pxp[i]["qT"], ref["qT"]),
-                     serial_grad=rel(res_ser[i]["grad"], ref["grad"]),
-                     serial_qT=rel(res_ser[i]["qT"], ref["qT"]))
+                     serial_grad=rel(res_ser[i]["grad"], ref["grad"]) if res_ser else 0.0,
+                     serial_qT=rel(res_ser[i]["qT"], ref["qT"]) if res_ser else 0.0)
             err = {k: max(err[k], v) for k, v in e.items()}
         w_s = sum(work[i] for i in sample)
         orc = dict(wall=wall, cpu=sum(per.values()), threads=threads, point_steps=w_s,
@@ -439,7 +441,8 @@ def main():
                     choices=["poly", "shift_invert", "auto", "taylor", "uniform"])
     ap.add_argument("--sched", default=None, choices=["classic", "chain", "tree"],
                     help="schedule of the direct pieces (default: tree in 2D, classic in 1D)")
-    ap.add_argument("--serial-steps", type=int, default=5)
+    ap.add_argument("--serial-steps", type=int, default=5,
+                    help="timed serial-method gradients (0: none, for profiler runs)")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32_bulk"])
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--block", type=int, default=0,
@@ -525,8 +528,9 @@ def main():
         "dtype": "f64" if args.prec == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": cfg,
-        "serial_gpu": {"value": B / m["t_ser"], "ms_per_step": m["t_ser"] * 1e3},
-        "speedup_vs_serial": m["t_ser"] / m["t_pxp"],
+        "serial_gpu": ({"value": B / m["t_ser"], "ms_per_step": m["t_ser"] * 1e3}
+                       if m["t_ser"] else None),
+        "speedup_vs_serial": m["t_ser"] / m["t_pxp"] if m["t_ser"] else None,
         "rel_err_vs_oracle": m["err"],
         "oracle_sample": m["sample"],
         "krylov_counters_per_step": {"direct": m["counters"][0], "adjoint": m["counters"][1],

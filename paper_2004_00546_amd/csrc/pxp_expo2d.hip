@@ -67,7 +67,15 @@ __global__ void __launch_bounds__(BNT) k_pois2d(const PoisEntry* __restrict__ ta
     const int t = threadIdx.x, w = wave_id(), l = lane_id(), cb = l * CPL;
     if (t < nterm) {
         const int k = E.k0 + t;
-        wt[t] = E.wtab ? E.wtab[k] : pois_pmf(E.lam, k);
+        if (E.wtab) {
+            wt[t] = E.wtab[k];
+        } else {
+            // p_k = p_{k0} lam^(k-k0) k0! / k!: one log-form weight per
+            // pass, then a short product (k - k0 < 16)
+            double pk = pois_pmf(E.lam, E.k0);
+            for (int q = E.k0 + 1; q <= k; ++q) pk *= E.lam / q;
+            wt[t] = pk;
+        }
         if (TWO) wt2[t] = E.wtab2[k];
     }
     // region row r <-> grid row band*R - off + r (periodic); every region
@@ -78,22 +86,50 @@ __global__ void __launch_bounds__(BNT) k_pois2d(const PoisEntry* __restrict__ ta
     const size_t vof = (size_t)vec;
     const double* tin = E.tin + vof * E.s_tin;
     double tv[BRW][CPL], acc[BRW][CPL], acc2[TWO ? BRW : 1][CPL];
+    // rows of the term vector this pass needs (the halo of its napp
+    // applications); a wave row is uniform, so the skip is a uniform branch
 #pragma unroll
-    for (int i = 0; i < BRW; ++i) row_load<CPL>(tin + (size_t)g[i] * NX + cb, tv[i]);
+    for (int i = 0; i < BRW; ++i) {
+        const int r = w * BRW + i;
+        if (r >= off - napp && r < off + R + napp) {
+            row_load<CPL>(tin + (size_t)g[i] * NX + cb, tv[i]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) tv[i][c] = 0.0;
+        }
+    }
+    // the sums start from the previous pass's (or zero) plus, in the final
+    // pass, the vectors added to them: those loads then overlap the term
+    // loads instead of trailing the arithmetic
     const bool cont = E.k0 > 0;
+    const double* add1 = E.final_pass ? E.partner : nullptr;
+    const double* add2 = (TWO && E.final_pass) ? E.out2_add : nullptr;
 #pragma unroll
     for (int i = 0; i < BRW; ++i) {
         const int r = w * BRW + i;
         const bool orow = r >= off && r < off + R;
-        if (cont && orow) {
-            row_load<CPL>(E.acc + vof * E.s_acc + (size_t)g[i] * NX + cb, acc[i]);
-            if (TWO) row_load<CPL>(E.acc2 + vof * E.s_acc + (size_t)g[i] * NX + cb, acc2[i]);
-        } else {
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                acc[i][c] = 0.0;
-                if (TWO) acc2[i][c] = 0.0;
-            }
+        for (int c = 0; c < CPL; ++c) {
+            acc[i][c] = 0.0;
+            if (TWO) acc2[i][c] = 0.0;
+        }
+        if (!orow) continue;
+        const size_t o = (size_t)g[i] * NX + cb;
+        if (cont) {
+            row_load<CPL>(E.acc + vof * E.s_acc + o, acc[i]);
+            if (TWO) row_load<CPL>(E.acc2 + vof * E.s_acc + o, acc2[i]);
+        }
+        if (add1) {
+            double q[CPL];
+            row_load<CPL>(add1 + vof * E.s_partner + o, q);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) acc[i][c] += q[c];
+        }
+        if (add2) {
+            double q[CPL];
+            row_load<CPL>(add2 + vof * E.s_out + o, q);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) acc2[i][c] += q[c];
         }
     }
     // N = I + A/mu has a zero diagonal for mu = -A.c
@@ -143,32 +179,14 @@ __global__ void __launch_bounds__(BNT) k_pois2d(const PoisEntry* __restrict__ ta
         const size_t o = (size_t)g[i] * NX + cb;
         if (E.final_pass) {
             if (E.out) {
-                double v[CPL];
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) v[c] = acc[i][c];
-                if (E.partner) {
-                    double q[CPL];
-                    row_load<CPL>(E.partner + vof * E.s_partner + o, q);
-#pragma unroll
-                    for (int c = 0; c < CPL; ++c) v[c] += q[c];
-                }
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) bad |= !isfinite(v[c]);
-                row_store<CPL>(E.out + vof * E.s_out + o, v);
+                for (int c = 0; c < CPL; ++c) bad |= !isfinite(acc[i][c]);
+                row_store<CPL>(E.out + vof * E.s_out + o, acc[i]);
             }
             if (TWO) {
-                double v[CPL];
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) v[c] = acc2[i][c];
-                if (E.out2_add) {
-                    double q[CPL];
-                    row_load<CPL>(E.out2_add + vof * E.s_out + o, q);
-#pragma unroll
-                    for (int c = 0; c < CPL; ++c) v[c] += q[c];
-                }
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) bad |= !isfinite(v[c]);
-                row_store<CPL>(E.out2 + vof * E.s_out + o, v);
+                for (int c = 0; c < CPL; ++c) bad |= !isfinite(acc2[i][c]);
+                row_store<CPL>(E.out2 + vof * E.s_out + o, acc2[i]);
             }
         } else {
             row_store<CPL>(E.tout + vof * E.s_tout + o, tv[i]);
