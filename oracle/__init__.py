@@ -64,6 +64,8 @@ def _load():
         lib.orc_gradient.argtypes = [pp, ctypes.c_int, ctypes.c_int, dp, dp, dp,
                                      dp, dp, dp, dp, dp, dp]
         lib.orc_gradient.restype = ctypes.c_int
+        lib.orc_gradient_icost.argtypes = lib.orc_gradient.argtypes
+        lib.orc_gradient_icost.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -138,7 +140,9 @@ def adjoint(inst: dict, traj, F, lamT):
 
 
 def gradient(inst: dict, a=None) -> dict:
-    """One direct-adjoint loop: q(T), J, dJ/da, lambda_0 and Lambda."""
+    """One direct-adjoint loop: q(T), J, dJ/da, lambda_0 and Lambda.  An
+    instance with cost "integral" takes the integral cost of section 4.2
+    (trapezoidal rule over the step states), else the terminal cost."""
     basis = _f64(inst["basis"])
     a = _f64(inst["a"] if a is None else a)
     K = basis.shape[0]
@@ -151,7 +155,9 @@ def gradient(inst: dict, a=None) -> dict:
     lam0 = np.empty(n)
     Lam = np.empty(n)
     p = _prob(inst)
-    rc = _load().orc_gradient(ctypes.byref(p), CONTROLS[inst["control"]], K,
+    fn = (_load().orc_gradient_icost if inst.get("cost", "terminal") == "integral"
+          else _load().orc_gradient)
+    rc = fn(ctypes.byref(p), CONTROLS[inst["control"]], K,
                               _ptr(basis), _ptr(a), _ptr(q0), _ptr(tgt),
                               _ptr(qT), _ptr(J), _ptr(g), _ptr(lam0), _ptr(Lam))
     if rc:
@@ -160,7 +166,8 @@ def gradient(inst: dict, a=None) -> dict:
 
 
 def cost(inst: dict, a) -> float:
-    """J(a) from the direct march alone (for finite differences)."""
+    """J(a) from the direct march alone (for finite differences); the
+    integral cost sums the trapezoidal weights over the stored states."""
     basis = _f64(inst["basis"])
     a = _f64(a)
     n = size(inst)
@@ -170,6 +177,14 @@ def cost(inst: dict, a) -> float:
     else:
         F = None
         q0 = q0 + a @ basis
+    if inst.get("cost", "terminal") == "integral":
+        _, tr = direct(inst, q0, F, traj=True)
+        nt = int(inst["n_steps"])
+        d = tr - np.asarray(inst["u_tgt"])[None, :]
+        s = np.einsum("ij,ij->i", d, d)
+        w = np.full(nt + 1, 1.0 / nt)
+        w[0] = w[-1] = 0.5 / nt
+        return float(w @ s) + float(inst["beta"]) * float(a @ a)
     qT = direct(inst, q0, F)
     d = qT - inst["u_tgt"]
     return 0.5 * float(d @ d) + float(inst["beta"]) * float(a @ a)

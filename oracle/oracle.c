@@ -13,11 +13,18 @@
  *            dt = T / n_steps (the time integrator the paper's inhomogeneous
  *            solves use, section 4.2, here without step adaptation);
  *   cost     J = 1/2 ||q(T) - q_tgt||^2 + beta ||a||^2, with the unweighted
- *            discrete inner product [a, b] = a^H b (section 2);
+ *            discrete inner product [a, b] = a^H b (section 2); or the
+ *            integral cost of section 4.2, J = 1/T int_0^T ||q - q_tgt||^2 dt
+ *            + beta ||a||^2, with the time integral taken by the trapezoidal
+ *            rule over the RK4 step states (orc_gradient_icost);
  *   adjoint  the exact discrete adjoint of the RK4 march (the adjoint of the
  *            discretised direct map, section 2: the adjoint operator of a
  *            discrete problem is its transpose), started from the final
  *            condition lambda_T = dJ/dq(T) = q(T) - q_tgt (eq. adjFinalTime);
+ *            for the integral cost every step state q_n is a cost argument,
+ *            so the reverse sweep adds dJ/dq_n after each step and starts
+ *            from dJ/dq_{n_t} (the discrete form of the source -dJ_I/dq of
+ *            eq. adjEquation);
  *   gradient forcing amplitudes:  dJ/da_k = <G_k, Lambda> + 2 beta a_k,
  *            Lambda = sum over steps/stages of s(t_stage) * kbar_stage, the
  *            discrete counterpart of int_0^T s(t) lambda(t) dt
@@ -300,5 +307,132 @@ int orc_gradient(const orc_problem* p, int control, int K,
 done:
     free(traj); free(F); free(init); free(fin); free(lamT); free(lam0);
     free(Lam);
+    return rc;
+}
+
+/*
+ * Integral cost (section 4.2, eq. cost):
+ *   J = sum_{n=0}^{n_t} w_n ||q_n - q_tgt||^2 + beta ||a||^2,
+ *   w_n = dt c_n / T, c_0 = c_{n_t} = 1/2, c_n = 1 otherwise
+ * (the trapezoidal rule for 1/T int_0^T ||q - q_tgt||^2 dt on the RK4 step
+ * states).  Every q_n enters J, so the exact discrete adjoint is the reverse
+ * sweep of orc_adjoint with dJ/dq_n = 2 w_n (q_n - q_tgt) added to the
+ * adjoint after the step that produces lambda_n, starting from
+ * lambda_{n_t} = dJ/dq_{n_t}.  Written out here rather than folded into
+ * orc_adjoint so that the terminal-cost path stays as it is.
+ */
+static double icost_weight(const orc_problem* p, long s)
+{
+    double dt = p->T / (double)p->n_steps;
+    double c = (s == 0 || s == p->n_steps) ? 0.5 : 1.0;
+    return dt * c / p->T;
+}
+
+static int orc_adjoint_icost(const orc_problem* p, const double* traj, const double* F,
+                             const double* q_tgt, double* lam0, double* Lambda)
+{
+    long n = orc_n(p);
+    double dt = p->T / (double)p->n_steps;
+    double* lam = malloc(n * sizeof(double));
+    double* Y = malloc(4 * n * sizeof(double));
+    double* k = malloc(4 * n * sizeof(double));
+    double* kb = malloc(4 * n * sizeof(double));
+    double* Yb = malloc(n * sizeof(double));
+    double* nl = malloc(n * sizeof(double));
+    if (!lam || !Y || !k || !kb || !Yb || !nl) {
+        free(lam); free(Y); free(k); free(kb); free(Yb); free(nl); return 1;
+    }
+    {
+        double w = icost_weight(p, p->n_steps);
+        const double* qn = traj + p->n_steps * n;
+        for (long i = 0; i < n; ++i) lam[i] = 2.0 * w * (qn[i] - q_tgt[i]);
+    }
+    if (Lambda) for (long i = 0; i < n; ++i) Lambda[i] = 0.0;
+    double c[4] = {0.0, 0.5, 0.5, 1.0};
+    double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    int linear = (p->op != 2);
+    for (long s = p->n_steps - 1; s >= 0; --s) {
+        double t = s * dt;
+        if (!linear) rk4_stages(p, traj + s * n, t, F, Y, k);
+        for (int st = 0; st < 4; ++st)
+            for (long i = 0; i < n; ++i) kb[st * n + i] = dt * b[st] * lam[i];
+        for (long i = 0; i < n; ++i) nl[i] = lam[i];
+        for (int st = 3; st >= 0; --st) {
+            orc_rhs_adjoint(p, Y + st * n, kb + st * n, Yb);
+            for (long i = 0; i < n; ++i) nl[i] += Yb[i];
+            if (st > 0) {
+                double a = (st == 3) ? dt : 0.5 * dt;
+                for (long i = 0; i < n; ++i) kb[(st - 1) * n + i] += a * Yb[i];
+            }
+        }
+        if (Lambda) {
+            for (int st = 0; st < 4; ++st) {
+                double sv = sin(p->omega * (t + c[st] * dt));
+                for (long i = 0; i < n; ++i) Lambda[i] += sv * kb[st * n + i];
+            }
+        }
+        /* q_s is a cost argument too: add dJ/dq_s */
+        double w = icost_weight(p, s);
+        const double* qs = traj + s * n;
+        for (long i = 0; i < n; ++i) lam[i] = nl[i] + 2.0 * w * (qs[i] - q_tgt[i]);
+    }
+    memcpy(lam0, lam, n * sizeof(double));
+    free(lam); free(Y); free(k); free(kb); free(Yb); free(nl);
+    return 0;
+}
+
+/* One direct-adjoint loop with the integral cost; arguments as for
+ * orc_gradient. */
+int orc_gradient_icost(const orc_problem* p, int control, int K,
+                       const double* basis, const double* a, const double* q0,
+                       const double* q_tgt, double* qT, double* J, double* grad,
+                       double* lam0_out, double* Lambda_out)
+{
+    long n = orc_n(p);
+    double* traj = malloc((p->n_steps + 1) * n * sizeof(double));
+    double* F = calloc(n, sizeof(double));
+    double* init = malloc(n * sizeof(double));
+    double* fin = malloc(n * sizeof(double));
+    double* lam0 = malloc(n * sizeof(double));
+    double* Lam = malloc(n * sizeof(double));
+    int rc = 1;
+    if (!traj || !F || !init || !fin || !lam0 || !Lam) goto done;
+    for (long i = 0; i < n; ++i) init[i] = q0 ? q0[i] : 0.0;
+    if (control == 0) {
+        for (int kk = 0; kk < K; ++kk)
+            for (long i = 0; i < n; ++i) F[i] += a[kk] * basis[kk * n + i];
+    } else {
+        for (int kk = 0; kk < K; ++kk)
+            for (long i = 0; i < n; ++i) init[i] += a[kk] * basis[kk * n + i];
+    }
+    const double* Fp = (control == 0) ? F : NULL;
+    if (orc_direct(p, init, Fp, fin, traj)) goto done;
+    double ji = 0.0, jr = 0.0;
+    for (long s = 0; s <= p->n_steps; ++s) {
+        double w = icost_weight(p, s), acc = 0.0;
+        const double* qs = traj + s * n;
+        for (long i = 0; i < n; ++i) {
+            double d = qs[i] - q_tgt[i];
+            acc += d * d;
+        }
+        ji += w * acc;
+    }
+    for (int kk = 0; kk < K; ++kk) jr += p->beta * a[kk] * a[kk];
+    *J = ji + jr;
+    if (orc_adjoint_icost(p, traj, Fp, q_tgt, lam0, Lam)) goto done;
+    if (grad) {
+        for (int kk = 0; kk < K; ++kk) {
+            const double* v = (control == 0) ? Lam : lam0;
+            double g = 0.0;
+            for (long i = 0; i < n; ++i) g += basis[kk * n + i] * v[i];
+            grad[kk] = g + 2.0 * p->beta * a[kk];
+        }
+    }
+    if (qT) memcpy(qT, fin, n * sizeof(double));
+    if (lam0_out) memcpy(lam0_out, lam0, n * sizeof(double));
+    if (Lambda_out) memcpy(Lambda_out, Lam, n * sizeof(double));
+    rc = 0;
+done:
+    free(traj); free(F); free(init); free(fin); free(lam0); free(Lam);
     return rc;
 }

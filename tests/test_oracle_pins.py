@@ -236,3 +236,85 @@ def test_burgers_discrete_adjoint_dot_product(orc):
     eps = 1e-5
     dqT = (orc.direct(inst, u0 + eps * dq0) - orc.direct(inst, u0 - eps * dq0)) / (2 * eps)
     assert abs(lamT @ dqT - lam0 @ dq0) < 1e-8 * abs(lam0 @ dq0)
+
+
+# ---- integral cost (section 4.2, eq. cost) --------------------------------
+
+def icost_closed_form(inst, a=None):
+    """J and dJ/da of the integral cost for a circulant operator, forcing
+    control, zero initial state, mode by mode: the step states are
+    q_n = t_n(lambda) F per mode (t_n the RK4 transfer factor up to step n),
+    J = sum_n w_n ||q_n - q_tgt||^2 + beta |a|^2 with the trapezoidal weights
+    w_n = c_n / n_t, and dJ/da_k = sum_n 2 w_n [t_n G_k, q_n - q_tgt] +
+    2 beta a_k (Parseval: [u, v] = Re(sum_k conj(u_k) v_k) / N).  No adjoint
+    sweep is involved."""
+    a = inst["a"] if a is None else a
+    G = np.asarray(inst["basis"])
+    F = a @ G
+    lam = fourier.eigenvalues(inst)
+    nt = int(inst["n_steps"])
+    dt = inst["T"] / nt
+    w_om = inst.get("omega", 1.0)
+    z = dt * lam
+    R = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    p1 = 1 + z + z ** 2 / 2 + z ** 3 / 4
+    p2 = 4 + 2 * z + z ** 2 / 2
+    Fh = fourier._fft(inst, F)
+    Gh = np.stack([fourier._fft(inst, G[k]) for k in range(G.shape[0])])
+    th = fourier._fft(inst, inst["u_tgt"])
+    Nn = Fh.size
+    tr = np.zeros_like(lam)
+    J = 0.0
+    g = np.zeros(G.shape[0])
+    for n in range(nt + 1):
+        wn = (0.5 if n in (0, nt) else 1.0) / nt
+        rh = tr * Fh - th
+        J += wn * float(np.sum(np.abs(rh) ** 2)) / Nn
+        for k in range(G.shape[0]):
+            g[k] += 2 * wn * float(np.real(np.sum(np.conj(tr * Gh[k]) * rh))) / Nn
+        if n < nt:
+            t = n * dt
+            s1, s2, s4 = (np.sin(w_om * t), np.sin(w_om * (t + dt / 2)),
+                          np.sin(w_om * (t + dt)))
+            tr = R * tr + dt / 6 * (s1 * p1 + s2 * p2 + s4)
+    J += inst["beta"] * float(a @ a)
+    g += 2 * inst["beta"] * a
+    return J, g
+
+
+@pytest.mark.parametrize("maker", [small_advdiff, small_2d])
+def test_integral_cost_closed_form(orc, maker):
+    inst = dict(maker(), cost="integral")
+    out = orc.gradient(inst)
+    J, g = icost_closed_form(inst)
+    assert abs(out["J"] - J) < 1e-12 * abs(J)
+    assert rel(out["grad"], g) < 1e-11
+
+
+@pytest.mark.parametrize("control", ["forcing", "ic"])
+@pytest.mark.parametrize("maker", [small_advdiff, small_2d])
+def test_integral_cost_central_difference_is_exact(orc, maker, control):
+    """The integral cost is quadratic in a for the linear problems: central
+    differences of the oracle's own direct march match the adjoint gradient
+    to rounding, for forcing and for initial-condition controls."""
+    inst = dict(maker(), cost="integral", control=control)
+    if control == "ic":
+        inst["basis"] = np.asarray(inst["basis"]) * 0.5
+    out = orc.gradient(inst)
+    a = np.asarray(inst["a"])
+    rng = np.random.default_rng(11)
+    for _ in range(4):
+        d = rng.standard_normal(a.size)
+        d /= np.linalg.norm(d)
+        eps = 1e-2 * np.linalg.norm(a)
+        fd = (orc.cost(inst, a + eps * d) - orc.cost(inst, a - eps * d)) / (2 * eps)
+        assert abs(fd - out["grad"] @ d) < 1e-9 * (abs(fd) + np.linalg.norm(out["grad"]))
+
+
+def test_integral_cost_differs_from_terminal(orc):
+    """The two costs are different functionals (a swapped flag would pass
+    the gradient tests of one with the other's data)."""
+    inst = small_advdiff()
+    jt = orc.gradient(inst)["J"]
+    ji = orc.gradient(dict(inst, cost="integral"))["J"]
+    assert abs(jt - ji) > 1e-3 * abs(jt)
