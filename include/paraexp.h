@@ -121,7 +121,26 @@ enum { PXP_SCHED_CLASSIC = 0, PXP_SCHED_CHAIN = 1, PXP_SCHED_TREE = 2 };
  * reversed time) as one batch and the P-1 homogeneous pieces of their end
  * states by Krylov, each with its share of Lambda.  Default (0): the
  * unabsorbed form, one homogeneous piece from lambda_T (eq. adjhomfinal). */
-enum { PXP_FLAG_ABSORBED_ADJOINT = 1 };
+enum { PXP_FLAG_ABSORBED_ADJOINT = 1, PXP_FLAG_INTEGRAL_COST = 2 };
+/* INTEGRAL_COST (2D problems, UNIFORM or AUTO exponentials, TREE schedule):
+ * pxp_gradient minimises the integral cost of section 4.2 (eq. cost),
+ *   J = 1/T int_0^T |q(t) - u_tgt|^2 dt + beta |a|^2,
+ * the time integral taken by the trapezoidal rule over the RK4 step states
+ * (weights dt/T inside, dt/(2T) at both ends).  Every step state is then an
+ * argument of J, so the adjoint is driven by the sources dJ/dq_n after each
+ * step (eq. adjEquation) instead of a final condition.  The Paraexp path:
+ * the slices as usual, the tree of their homogeneous pieces kept level by
+ * level and walked back down for the corrected state at every slice start,
+ * one more batched march of every slice from its corrected start that writes
+ * the sources (the dense direct trajectory) and the cost, the adjoint slices
+ * with those sources as one batch (the genuinely inhomogeneous adjoint of
+ * eq. adjInhom), and the tree of their homogeneous pieces, each carrying its
+ * exact share of Lambda.  The workspace then holds (n_steps + 1) n sources
+ * per instance.  The largest adjoint piece, mu T_left with T_left the
+ * horizon of the tree's left half, must stay within 4096 (PXP_EUNSUPPORTED
+ * otherwise; mu = -diagonal of A).  The paraexp_direct and paraexp_adjoint
+ * calls on their own ignore the flag, except that paraexp_adjoint accepts
+ * jI_src only for problems that carry it; pxp_cost refuses it. */
 /* Method: PARAEXP = the time-parallel path; SERIAL = plain RK4 stepping of
  * the direct equation and its exact discrete adjoint (the comparison). */
 enum { PXP_METHOD_PARAEXP = 0, PXP_METHOD_SERIAL = 1 };
@@ -174,11 +193,15 @@ pxp_status paraexp_direct(const pxp_problem* pb, int32_t batch,
  * adjhomfinal) from the final condition lamT (= dJ/dq(T)).  lamT, lam0
  * and Lambda must be 16-byte aligned at every instance offset (PXP_EINVAL
  * otherwise):
- *   jI_src  [sum (n_steps+1) n]  source of an integral cost term J_I =
- *           int_0^T j(q, t) dt (section 2, eq. adjEquation: the adjoint's
- *           source -dj/dq at the RK4 step times), nullable; a terminal cost
- *           passes NULL.  Not implemented: non-null returns PXP_EUNSUPPORTED
- *           before anything is enqueued.
+ *   jI_src  [sum (n_steps+1) n]  sources of an integral cost term J_I =
+ *           int_0^T j(q, t) dt (section 2, eq. adjEquation), nullable: row n
+ *           of instance i (at sum_{j<i} (n_steps_j + 1) n_j + n n_i) holds
+ *           dJ_I/dq_n of the discrete cost, added to the adjoint after the
+ *           reverse step that produces lambda_n (row n_steps: added to lamT).
+ *           Non-null requires every instance to be 2D with
+ *           PXP_FLAG_INTEGRAL_COST (PXP_EUNSUPPORTED otherwise, before
+ *           anything is enqueued); lamT may then be NULL (no terminal
+ *           cost).  16-byte aligned rows.
  *   lam0    [sum n]  output q^dagger(0) (nullable)
  *   Lambda  [sum n]  output int_0^T sin(omega t) q^dagger(t) dt (nullable)
  * Burgers instances read the checkpoints that the preceding paraexp_direct
@@ -194,6 +217,7 @@ pxp_status paraexp_adjoint(const pxp_problem* pb, int32_t batch,
  *                       instance i at koff_i*n_i + k*n_i
  *   q0     [sum n]      base initial state (nullable = zero)
  *   u_tgt  [sum n]      target state of J = 1/2 |q(T) - u_tgt|^2 + beta |a|^2
+ *                       (PXP_FLAG_INTEGRAL_COST: of the integral cost)
  *   J      [batch]      output cost
  *   grad   [sum K]      output dJ/da
  *   qT     [sum n]      output q(T) (nullable)
@@ -217,7 +241,9 @@ pxp_status gradient(const pxp_problem* pb, int32_t batch, const double* ctrl,
  *   pxp_assemble         out = base + sum_k ctrl_k basis_k per instance
  *                        (forcing pattern or initial state; base nullable)
  *   pxp_cost             J_i = 1/2 |qT - u_tgt|^2 + beta |ctrl|^2 and
- *                        lamT = qT - u_tgt (eq. adjFinalTime; lamT nullable)
+ *                        lamT = qT - u_tgt (eq. adjFinalTime; lamT nullable);
+ *                        terminal cost only (PXP_EUNSUPPORTED for
+ *                        PXP_FLAG_INTEGRAL_COST problems)
  *   pxp_reduce_gradient  grad_k = <basis_k, v> + 2 beta ctrl_k with v the
  *                        adjoint integral Lambda (forcing, eq. paramupdate)
  *                        or lambda_0 (initial condition, eq. initupdate)
@@ -289,7 +315,10 @@ enum {
     PXP_K_SERIAL_DIRECT = 3,   /* serial RK4 march                          */
     PXP_K_SERIAL_REVERSE = 4,  /* serial reverse (discrete adjoint) sweep   */
     PXP_K_LTV_ADJOINT = 5,     /* time-varying adjoint Magnus chain         */
-    PXP_K_LTV_NODES = 6        /* per-slice recompute of the Magnus states  */
+    PXP_K_LTV_NODES = 6,       /* per-slice recompute of the Magnus states  */
+    PXP_K_SOURCES = 7,         /* integral cost: march of every slice from its
+                                  corrected start writing the step sources   */
+    PXP_K_ADJ_SLICES = 8       /* integral cost: adjoint slices with sources */
 };
 pxp_status pxp_profile_enable(int32_t on);
 pxp_status pxp_profile_read(int32_t kernel_class, double* total_ms,

@@ -21,6 +21,7 @@ PREC = {"fp64": 0, "fp32_bulk": 1}
 CTRL = {"forcing": 0, "ic": 1}
 KRYLOV = {"poly": 0, "shift_invert": 1, "auto": 2, "taylor": 3, "uniform": 4}
 FLAG_ABSORBED_ADJOINT = 1
+FLAG_INTEGRAL_COST = 2
 SCHED = {"classic": 0, "chain": 1, "tree": 2}
 METHOD = {"paraexp": 0, "serial": 1}
 
@@ -37,7 +38,7 @@ EXPORTED = ("pxp_workspace_size", "pxp_workspace_init", "paraexp_direct",
             "pxp_last_report")
 KCLASS = {"slices": 0, "krylov_direct": 1, "krylov_adjoint": 2,
           "serial_direct": 3, "serial_reverse": 4, "ltv_adjoint": 5,
-          "ltv_nodes": 6}
+          "ltv_nodes": 6, "sources": 7, "adj_slices": 8}
 
 
 class pxp_problem(ctypes.Structure):

@@ -28,6 +28,9 @@ def make_problem(inst: dict, krylov: str = "shift_invert", sched: str = "classic
     p.block = int(block)
     p.kblock = int(kblock)
     p.flags = _lib.FLAG_ABSORBED_ADJOINT if absorbed else 0
+    # the integral cost of section 4.2 (eq. cost) instead of the terminal one
+    if inst.get("cost", "terminal") == "integral":
+        p.flags |= _lib.FLAG_INTEGRAL_COST
     p.n_steps = int(inst["n_steps"])
     p.L = float(inst["L"])
     p.vx = float(inst.get("vx", 0.0))

@@ -37,7 +37,12 @@ struct Layout {
 // Per-instance buffers (offsets relative to the instance region).
 struct Inst {
     size_t F, g0, q0eff, slices, pieces, basis, qT, lamT, lam0, Lam, chain,
-        ckpt, seg, nodes, sbuf0, sbuf1, aint, J, tbuf, wtab, ubuf, size;
+        ckpt, seg, nodes, sbuf0, sbuf1, aint, J, tbuf, wtab, ubuf;
+    // integral cost: step sources, kept tree levels, corrected slice-start
+    // states, Lambda shares (slices then tree pairs), cost partials, weight
+    // tables of the adjoint tree
+    size_t gsrc, lev, ebuf, islot, cpart, iwtab;
+    size_t size;
 };
 
 int64_t grid_n(const pxp_problem& p) { return (int64_t)p.nx * (int64_t)p.ny; }
@@ -212,7 +217,9 @@ pxp_status validate(const pxp_problem& p) {
     if (p.krylov == PXP_KRYLOV_UNIFORM && p.op != PXP_OP_ADVDIFF2D_UPWIND) return PXP_EUNSUPPORTED;
     if (p.sched == PXP_SCHED_TREE && !uniform_direct(p)) return PXP_EUNSUPPORTED;
     if (p.prec != PXP_FP64 && p.prec != PXP_FP32_BULK) return PXP_EINVAL;
-    if ((p.flags & ~PXP_FLAG_ABSORBED_ADJOINT) || p.kblock < 0 || p.block < 0) return PXP_EINVAL;
+    if ((p.flags & ~(PXP_FLAG_ABSORBED_ADJOINT | PXP_FLAG_INTEGRAL_COST)) || p.kblock < 0 ||
+        p.block < 0)
+        return PXP_EINVAL;
     if ((p.flags & PXP_FLAG_ABSORBED_ADJOINT) && p.op != PXP_OP_ADVDIFF1D) return PXP_EUNSUPPORTED;
     if (p.op == PXP_OP_ADVDIFF1D) {
         if (p.ny != 1) return PXP_EINVAL;
@@ -319,9 +326,14 @@ int pois_terms_uncached(double lam, double tol, double* est) {
     return D;
 }
 
-// Largest Poisson parameter of one uniformised adjoint exponential: its
-// integral weights start from e^{-lam}, which must stay a normal double.
+// Largest Poisson parameter of one uniformised adjoint exponential of the
+// terminal-cost piece, split into substeps beyond (its integral weights are
+// formed by a recurrence from e^{-lam} up to this size).
 constexpr double POIS_LMAX = 600.0;
+// Largest Poisson parameter of one piece of the integral-cost adjoint tree
+// (weights in log form beyond POIS_LMAX; their table is formed by one thread
+// in time proportional to lam).
+constexpr double POIS_LMAX_TREE = 4096.0;
 
 double uniform_mu(const Sten5& A) { return -A.c; }
 Sten5 uniform_N(const Sten5& A, double mu) {
@@ -349,6 +361,73 @@ AdjPlan adj_plan(const pxp_problem& p) {
     a.lam = mu * a.h;
     a.D = pois_terms(a.lam, uniform_tail_tol(p), &a.est);
     return a;
+}
+
+// ---- the pairwise tree over the slice ranges --------------------------------
+
+// Level 0 holds the P slices; level l pairs ranges 2j and 2j+1 of level l-1
+// (an odd last range is carried up alone); the last level holds the root.
+// Every range of a level but its last spans 2^l slices, so the pairs of a
+// level have at most two shapes.
+struct TNode {
+    int start, size;  // slice range [start, start + size)
+};
+using TShape = std::vector<std::vector<TNode>>;
+
+TShape tree_shape(int P) {
+    TShape lv(1);
+    for (int q = 0; q < P; ++q) lv[0].push_back({q, 1});
+    while (lv.back().size() > 1) {
+        std::vector<TNode> nx;
+        {
+            const std::vector<TNode>& c = lv.back();
+            const size_t pairs = c.size() / 2;
+            for (size_t j = 0; j < pairs; ++j)
+                nx.push_back({c[2 * j].start, c[2 * j].size + c[2 * j + 1].size});
+            if (c.size() & 1) nx.push_back(c.back());
+        }
+        lv.push_back(nx);
+    }
+    return lv;
+}
+
+// vectors of levels 1 .. depth kept one after the other
+size_t tree_kept_vectors(const TShape& sh) {
+    size_t v = 0;
+    for (size_t l = 1; l < sh.size(); ++l) v += sh[l].size();
+    return v;
+}
+
+bool icost(const pxp_problem& p) { return (p.flags & PXP_FLAG_INTEGRAL_COST) != 0; }
+
+// Largest Poisson parameter of the integral-cost adjoint tree: the pair at
+// the root, whose left half spans the most slices.
+double icost_max_lam(const pxp_problem& p) {
+    if (p.P < 2) return 0.0;
+    const TShape sh = tree_shape(p.P);
+    const int left = sh[sh.size() - 2][0].size;
+    return uniform_mu(transpose5(advdiff2d_sten(p))) * (p.T / p.P) * left;
+}
+
+// Weight tables of the adjoint tree: at most two pair shapes per level, two
+// tables of D doubles each, D at most that of the largest piece.
+size_t icost_wtab_doubles(const pxp_problem& p) {
+    if (p.P < 2) return 1;
+    const size_t depth = tree_shape(p.P).size() - 1;
+    const int D = pois_terms(icost_max_lam(p), uniform_tail_tol(p), nullptr);
+    return 2 * depth * 2 * (size_t)D;
+}
+size_t icost_wtab_count(const pxp_problem& p) {
+    return p.P < 2 ? 0 : 2 * (tree_shape(p.P).size() - 1);
+}
+
+pxp_status validate_icost(const pxp_problem& p) {
+    if (!icost(p)) return PXP_OK;
+    if (p.op != PXP_OP_ADVDIFF2D_UPWIND) return PXP_EUNSUPPORTED;
+    if (!uniform_direct(p) || !uniform_adjoint(p) || p.sched != PXP_SCHED_TREE)
+        return PXP_EUNSUPPORTED;
+    if (icost_max_lam(p) > POIS_LMAX_TREE) return PXP_EUNSUPPORTED;
+    return PXP_OK;
 }
 
 Inst inst_layout(const pxp_problem& p) {
@@ -399,6 +478,14 @@ Inst inst_layout(const pxp_problem& p) {
         }
         L.sbuf0 = take(n * d);
         L.sbuf1 = take(n * d);
+        if (icost(p)) {
+            L.gsrc = take(((size_t)p.n_steps + 1) * n * d);
+            L.lev = take(std::max(tree_kept_vectors(tree_shape(p.P)), (size_t)1) * n * d);
+            L.ebuf = take((P > 1 ? P - 1 : 1) * n * d);
+            L.islot = take((2 * P - 1) * n * d);
+            L.cpart = take(P * (size_t)(p.ny / BAND_ROWS) * d);
+            L.iwtab = take(icost_wtab_doubles(p) * d);
+        }
     }
     if (p.op == PXP_OP_BURGERS1D) {
         const size_t c = (size_t)p.ckpt_every;
@@ -427,10 +514,12 @@ Layout layout(const pxp_problem* pb, int batch) {
     // at most four entries per instance in one pass launch (pairs of two
     // lengths, a pass-through, or the adjoint's piece)
     Ly.ptab = off;
-    off += align_up((size_t)batch * 4 * sizeof(PoisEntry));
+    off += align_up((size_t)batch * 8 * sizeof(PoisEntry));
     size_t nw = 0;
-    for (int i = 0; i < batch; ++i)
+    for (int i = 0; i < batch; ++i) {
         if (uniform_adjoint(pb[i])) nw += (size_t)adj_plan(pb[i]).nsub;
+        if (icost(pb[i])) nw += icost_wtab_count(pb[i]);
+    }
     Ly.pwt = off;
     off += align_up(nw * sizeof(PoisWeights));
     Ly.rtab = off;
@@ -464,6 +553,7 @@ pxp_status check_all(const pxp_problem* pb, int batch) {
     if (batch < 0 || (batch > 0 && !pb)) return PXP_EINVAL;
     for (int i = 0; i < batch; ++i) {
         pxp_status s = validate(pb[i]);
+        if (s == PXP_OK) s = validate_icost(pb[i]);
         if (s != PXP_OK) return s;
     }
     return PXP_OK;
@@ -1038,7 +1128,8 @@ std::vector<Group2D> group2d(std::vector<Band2D>& tab) {
 
 // Serial march of every instance: launch L advances each instance by up to
 // four steps (entries ordered by nx).
-pxp_status serial2d(std::vector<Band2D>& tab, Band2D* dtab, bool rev, hipStream_t s) {
+// src: the integral-cost marches (sources written forward, added in reverse).
+pxp_status serial2d(std::vector<Band2D>& tab, Band2D* dtab, bool rev, bool src, hipStream_t s) {
     const std::vector<Group2D> groups = group2d(tab);
     HIPCHK(launch_upload(dtab, tab.data(), tab.size() * sizeof(Band2D), s));
     for (const Group2D& g : groups) {
@@ -1046,10 +1137,15 @@ pxp_status serial2d(std::vector<Band2D>& tab, Band2D* dtab, bool rev, hipStream_
         for (int j = g.first; j < g.first + g.count; ++j)
             lmax = std::max(lmax, (tab[j].n_t + 3) / 4);
         for (int64_t L = 0; L < lmax; ++L) {
-            if (rev)
-                HIPCHK(launch_band2d_rev(dtab + g.first, g.count, g.blocks, g.nx, (int)L, s));
+            const Band2D* t = dtab + g.first;
+            if (src && rev)
+                HIPCHK(launch_band2d_rsrc(t, g.count, g.blocks, g.nx, 1, (int)L, s));
+            else if (src)
+                HIPCHK(launch_band2d_src(t, g.count, g.blocks, g.nx, 1, (int)L, s));
+            else if (rev)
+                HIPCHK(launch_band2d_rev(t, g.count, g.blocks, g.nx, (int)L, s));
             else
-                HIPCHK(launch_band2d(dtab + g.first, g.count, g.blocks, g.nx, 1, (int)L, s));
+                HIPCHK(launch_band2d(t, g.count, g.blocks, g.nx, 1, (int)L, s));
         }
     }
     return PXP_OK;
@@ -1086,6 +1182,8 @@ struct PJob {
     double* out2 = nullptr;
     const double* out2_add = nullptr;
     const double* wtab2 = nullptr;
+    const double* wtab2i = nullptr;  // phase form of the second sum's weights
+    double ph0 = 0.0, dph = 0.0;
     double* tb[2] = {nullptr, nullptr};  // term vectors of later passes
     int nvec = 1, D = 1, nx = 0, ny = 0;
     double lam = 0.0, est = 0.0;
@@ -1137,6 +1235,9 @@ pxp_status run_stage(const std::vector<PJob>& jobs, PoisEntry* dtab, hipStream_t
                     e.out2 = j.out2;
                     e.out2_add = j.out2_add;
                     e.wtab2 = j.wtab2;
+                    e.wtab2i = j.wtab2i;
+                    e.ph0 = j.ph0;
+                    e.dph = j.dph;
                     e.lam = j.lam;
                     e.est = j.est;
                     e.N = j.N;
@@ -1163,41 +1264,40 @@ pxp_status run_stage(const std::vector<PJob>& jobs, PoisEntry* dtab, hipStream_t
 }
 
 // Tree schedule of one instance's direct pieces: the levels of pairwise
-// combinations, each a list of jobs.  Level l reads buf[(l-1)&1] (buf[0] =
-// slices) and writes buf[l&1]; the root goes to qT.
-void tree_levels(const pxp_problem& p, const Ctx& c, double* qT,
-                 std::vector<std::vector<PJob>>& levels) {
+// combinations, each a list of jobs.  Level l reads bufs[l-1] (bufs[0] =
+// slices) and writes bufs[l]; the root goes to qT.  A pair of ranges
+// [a, b), [b, c) gives exp((T_c - T_b) A) w_ab + w_bc.
+void tree_up_levels(const pxp_problem& p, const Ctx& c, const TShape& sh,
+                    const std::vector<double*>& bufs, double* qT,
+                    std::vector<std::vector<PJob>>& levels) {
     const int64_t n = c.n();
     const Sten5 A = advdiff2d_sten(p);
     const double mu = uniform_mu(A), dT = p.T / p.P, tol = uniform_tail_tol(p);
-    double* buf[2] = {c.at(c.L.slices), c.at(c.L.pieces)};
     double* tb0 = c.at(c.L.tbuf);
     double* tb1 = tb0 + (size_t)((p.P + 1) / 2) * n;
-    std::vector<int> size(p.P, 1);
-    int l = 0;
-    while (size.size() > 1) {
-        ++l;
-        const int cnt = (int)size.size(), pairs = cnt / 2;
-        const double* src = buf[(l - 1) & 1];
-        double* dst = buf[l & 1];
-        const bool root = (pairs + (cnt & 1)) == 1;
+    const size_t depth = sh.size() - 1;
+    for (size_t l = 1; l <= depth; ++l) {
+        const std::vector<TNode>& ch = sh[l - 1];
+        const int cnt = (int)ch.size(), pairs = cnt / 2;
+        const double* src = bufs[l - 1];
+        double* dst = l == depth ? qT : bufs[l];
         std::vector<PJob> lv;
         int j = 0;
         while (j < pairs) {
             // a run of pairs whose right-hand ranges have the same length
             int j1 = j + 1;
-            while (j1 < pairs && size[2 * j1 + 1] == size[2 * j + 1]) ++j1;
+            while (j1 < pairs && ch[2 * j1 + 1].size == ch[2 * j + 1].size) ++j1;
             PJob b;
             b.nvec = j1 - j;
             b.x = src + (size_t)(2 * j) * n;
             b.sx = 2 * n;
             b.partner = src + (size_t)(2 * j + 1) * n;
             b.sp = 2 * n;
-            b.out = root ? qT : dst + (size_t)j * n;
+            b.out = dst + (size_t)j * n;
             b.so = n;
             b.tb[0] = tb0 + (size_t)j * n;
             b.tb[1] = tb1 + (size_t)j * n;
-            b.lam = mu * dT * size[2 * j + 1];
+            b.lam = mu * dT * ch[2 * j + 1].size;
             b.D = pois_terms(b.lam, tol, &b.est);
             b.nx = p.nx;
             b.ny = p.ny;
@@ -1224,10 +1324,177 @@ void tree_levels(const pxp_problem& p, const Ctx& c, double* qT,
             lv.push_back(b);
         }
         levels.push_back(lv);
-        std::vector<int> ns;
-        for (int q = 0; q < pairs; ++q) ns.push_back(size[2 * q] + size[2 * q + 1]);
-        if (cnt & 1) ns.push_back(size[cnt - 1]);
-        size.swap(ns);
+    }
+}
+
+// The tree with its levels alternating between the slices and the pieces
+// buffer ((P+1)/2 vectors).
+void tree_levels(const pxp_problem& p, const Ctx& c, double* qT,
+                 std::vector<std::vector<PJob>>& levels) {
+    const TShape sh = tree_shape(p.P);
+    std::vector<double*> bufs;
+    for (size_t l = 0; l < sh.size(); ++l)
+        bufs.push_back((l & 1) ? c.at(c.L.pieces) : c.at(c.L.slices));
+    tree_up_levels(p, c, sh, bufs, qT, levels);
+}
+
+// Buffers of the kept levels (integral cost): level 0 the slices, level l
+// >= 1 one after the other in the lev region.
+std::vector<double*> kept_bufs(const Ctx& c, const TShape& sh) {
+    const int64_t n = c.n();
+    std::vector<double*> bufs{c.at(c.L.slices)};
+    size_t v = 0;
+    for (size_t l = 1; l < sh.size(); ++l) {
+        bufs.push_back(c.at(c.L.lev) + v * n);
+        v += sh[l].size();
+    }
+    return bufs;
+}
+
+// Corrected slice-start states q(T_m), m = 1..P-1, into ebuf slot m-1, from
+// the kept up-sweep levels, top down: a pair of ranges [s, m), [m, e) gives
+// q(T_m) = exp((T_m - T_s) A) q(T_s) + w_sm (w_sm: the left range's sum,
+// which for s = 0 already holds the initial state and is q(T_m) itself).
+void tree_down_levels(const pxp_problem& p, const Ctx& c, const TShape& sh,
+                      const std::vector<double*>& bufs,
+                      std::vector<std::vector<PJob>>& levels) {
+    const int64_t n = c.n();
+    const Sten5 A = advdiff2d_sten(p);
+    const double mu = uniform_mu(A), dT = p.T / p.P, tol = uniform_tail_tol(p);
+    double* E = c.at(c.L.ebuf);
+    double* tb0 = c.at(c.L.tbuf);
+    double* tb1 = tb0 + (size_t)((p.P + 1) / 2) * n;
+    for (size_t l = sh.size() - 1; l >= 1; --l) {
+        const std::vector<TNode>& ch = sh[l - 1];
+        const int pairs = (int)ch.size() / 2;
+        const double* left = bufs[l - 1];
+        std::vector<PJob> lv;
+        int j = 0;
+        while (j < pairs) {
+            const int s0 = ch[2 * j].start, Ls = ch[2 * j].size, Rs = ch[2 * j + 1].size;
+            PJob b;
+            b.nx = p.nx;
+            b.ny = p.ny;
+            b.N = uniform_N(A, mu);
+            b.st = c.st;
+            b.irep = c.irep;
+            b.tb[0] = tb0 + (size_t)j * n;
+            b.tb[1] = tb1 + (size_t)j * n;
+            if (s0 == 0) {  // the leftmost pair: a copy
+                b.x = left + (size_t)(2 * j) * n;
+                b.out = E + (size_t)(Ls - 1) * n;
+                b.sx = b.so = n;
+                b.lam = 0.0;
+                b.D = 1;
+                lv.push_back(b);
+                ++j;
+                continue;
+            }
+            int j1 = j + 1;
+            while (j1 < pairs && ch[2 * j1].size == Ls && ch[2 * j1 + 1].size == Rs) ++j1;
+            b.nvec = j1 - j;
+            b.x = E + (size_t)(s0 - 1) * n;
+            b.sx = (int64_t)(Ls + Rs) * n;
+            b.partner = left + (size_t)(2 * j) * n;
+            b.sp = 2 * n;
+            b.out = E + (size_t)(s0 + Ls - 1) * n;
+            b.so = (int64_t)(Ls + Rs) * n;
+            b.lam = mu * dT * Ls;
+            b.D = pois_terms(b.lam, tol, &b.est);
+            lv.push_back(b);
+            j = j1;
+        }
+        levels.push_back(lv);
+    }
+}
+
+// Tree of the integral-cost adjoint pieces over the adjoint slices' end
+// states (bufs[0]): a pair of ranges [s, m), [m, e) gives the adjoint at
+// T_s, exp((T_m - T_s) A^T) u_me + u_sm, and (integral) its share of
+// Lambda, int_{T_s}^{T_m} sin(omega t) exp((T_m - t) A^T) u_me dt, into the
+// next islot slot (slots 0..P-1 hold the slices' own shares).  The root goes
+// to root_out.  Weight tables (phase form) are appended to wt from wbase.
+void adj_tree_levels(const pxp_problem& p, const Ctx& c, const TShape& sh,
+                     const std::vector<double*>& bufs, double* root_out, bool integral,
+                     std::vector<PoisWeights>& wt, std::vector<std::vector<PJob>>& levels) {
+    const int64_t n = c.n();
+    const Sten5 AT = transpose5(advdiff2d_sten(p));
+    const double mu = uniform_mu(AT), dT = p.T / p.P, tol = uniform_tail_tol(p);
+    double* tb0 = c.at(c.L.tbuf);
+    double* tb1 = tb0 + (size_t)((p.P + 1) / 2) * n;
+    double* islot = c.at(c.L.islot);
+    double* wbase = c.at(c.L.iwtab);
+    size_t wofs = 0;
+    int slot = p.P;
+    const size_t depth = sh.size() - 1;
+    for (size_t l = 1; l <= depth; ++l) {
+        const std::vector<TNode>& ch = sh[l - 1];
+        const int cnt = (int)ch.size(), pairs = cnt / 2;
+        const double* src = bufs[l - 1];
+        double* dst = l == depth ? root_out : bufs[l];
+        std::vector<PJob> lv;
+        int j = 0;
+        while (j < pairs) {
+            const int Ls = ch[2 * j].size, Rs = ch[2 * j + 1].size;
+            int j1 = j + 1;
+            while (j1 < pairs && ch[2 * j1].size == Ls && ch[2 * j1 + 1].size == Rs) ++j1;
+            PJob b;
+            b.nvec = j1 - j;
+            b.x = src + (size_t)(2 * j + 1) * n;
+            b.sx = 2 * n;
+            b.partner = src + (size_t)(2 * j) * n;
+            b.sp = 2 * n;
+            b.out = dst + (size_t)j * n;
+            b.so = n;
+            b.tb[0] = tb0 + (size_t)j * n;
+            b.tb[1] = tb1 + (size_t)j * n;
+            b.lam = mu * dT * Ls;
+            b.D = pois_terms(b.lam, tol, &b.est);
+            b.nx = p.nx;
+            b.ny = p.ny;
+            b.N = uniform_N(AT, mu);
+            b.st = c.st;
+            b.irep = c.irep;
+            if (integral) {
+                PoisWeights pw{};
+                pw.w = wbase + wofs;
+                pw.wi = pw.w + b.D;
+                pw.D = b.D;
+                pw.split = 1;
+                pw.lam = b.lam;
+                pw.mu = mu;
+                pw.omega = p.omega;
+                pw.scale = 1.0 / mu;
+                wofs += 2 * (size_t)b.D;
+                wt.push_back(pw);
+                b.wtab2 = pw.w;
+                b.wtab2i = pw.wi;
+                b.ph0 = p.omega * dT * (ch[2 * j].start + Ls);
+                b.dph = p.omega * dT * (Ls + Rs);
+                b.out2 = islot + (size_t)slot * n;
+                b.acc2 = b.out2;
+                slot += b.nvec;
+            }
+            lv.push_back(b);
+            j = j1;
+        }
+        if (cnt & 1) {
+            PJob b;
+            b.x = src + (size_t)(cnt - 1) * n;
+            b.out = dst + (size_t)pairs * n;
+            b.so = b.sx = n;
+            b.tb[0] = tb0;
+            b.tb[1] = tb1;
+            b.lam = 0.0;
+            b.D = 1;
+            b.nx = p.nx;
+            b.ny = p.ny;
+            b.N = uniform_N(AT, mu);
+            b.st = c.st;
+            b.irep = c.irep;
+            lv.push_back(b);
+        }
+        levels.push_back(lv);
     }
 }
 
@@ -1275,15 +1542,67 @@ pxp_status run_levels(const std::vector<std::vector<std::vector<PJob>>>& per, Po
 }
 
 // Direct solve of the 2D instances idx: init (nullable) and F (nullable)
-// per instance -> qT.
+// per instance -> qT.  tgt (nullable; per instance, nullable): for the
+// integral-cost instances, also the step sources and the cost partials
+// (nparts[j] receives their count).
 pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, void* ws,
                            const Layout& Ly, const std::vector<const double*>& init,
                            const std::vector<const double*>& F,
-                           const std::vector<double*>& qT, int method, hipStream_t s) {
+                           const std::vector<double*>& qT, int method, hipStream_t s,
+                           const std::vector<const double*>* tgt = nullptr,
+                           std::vector<int>* nparts = nullptr) {
     if (idx.empty()) return PXP_OK;
     auto* dtab = reinterpret_cast<Band2D*>(static_cast<char*>(ws) + Ly.t2d);
-    std::vector<Band2D> tab;
     const std::vector<int> ord = by_nx(pb, idx);
+    auto with_src = [&](int j) { return tgt && (*tgt)[j] && icost(pb[idx[j]]); };
+    auto src_fields = [&](Band2D& d, const Ctx& c, int j) {
+        d.g = c.at(c.L.gsrc);
+        d.tgt = (*tgt)[j];
+        d.cpart = c.at(c.L.cpart);
+        d.gw = 2.0 * c.dt() / c.p.T;
+        d.n_t = c.p.n_steps;
+    };
+    if (method == PXP_METHOD_SERIAL) {
+        // plain instances, then the integral-cost ones (their march also
+        // writes the sources)
+        for (int pass = 0; pass < 2; ++pass) {
+            std::vector<Band2D> tab;
+            std::vector<int> who;
+            for (int j : ord) {
+                if (with_src(j) != (pass == 1)) continue;
+                const pxp_problem& p = pb[idx[j]];
+                Ctx c = make_ctx(p, ws, Ly, idx[j], s);
+                Band2D d{};
+                d.F = F[j];
+                d.nx = p.nx;
+                d.ny = p.ny;
+                d.dt = c.dt();
+                d.omega = p.omega;
+                d.A = advdiff2d_sten(p);
+                d.y0 = init[j];
+                d.buf[0] = c.at(c.L.sbuf0);
+                d.buf[1] = c.at(c.L.sbuf1);
+                d.n_t = p.n_steps;
+                d.items = 1;
+                if (pass == 1) src_fields(d, c, j);
+                tab.push_back(d);
+                who.push_back(j);
+            }
+            if (tab.empty()) continue;
+            {
+                ProfScope ps(PXP_K_SERIAL_DIRECT, s);
+                pxp_status st = serial2d(tab, dtab, false, pass == 1, s);
+                if (st != PXP_OK) return st;
+            }
+            for (size_t e = 0; e < who.size(); ++e) {
+                HIPCHK(launch_add(nullptr, serial2d_result(tab[e]), qT[who[e]],
+                                  (int)grid_n(pb[idx[who[e]]]), s));
+                if (pass == 1 && nparts) (*nparts)[who[e]] = tab[e].ny / tab[e].rows;
+            }
+        }
+        return PXP_OK;
+    }
+    std::vector<Band2D> tab;
     for (int j : ord) {
         const pxp_problem& p = pb[idx[j]];
         Ctx c = make_ctx(p, ws, Ly, idx[j], s);
@@ -1294,33 +1613,14 @@ pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, v
         d.dt = c.dt();
         d.omega = p.omega;
         d.A = advdiff2d_sten(p);
-        if (method == PXP_METHOD_SERIAL) {
-            d.y0 = init[j];
-            d.buf[0] = c.at(c.L.sbuf0);
-            d.buf[1] = c.at(c.L.sbuf1);
-            d.n_t = p.n_steps;
-            d.items = 1;
-        } else {
-            // the initial state is the first slice's initial data, so the
-            // superposition below needs no q0 term
-            d.y0 = init[j];
-            d.out = c.at(c.L.slices);
-            d.items = p.P;
-            d.nsteps = (int)(p.n_steps / p.P);
-            d.item_steps = p.n_steps / p.P;
-        }
+        // the initial state is the first slice's initial data, so the
+        // superposition below needs no q0 term
+        d.y0 = init[j];
+        d.out = c.at(c.L.slices);
+        d.items = p.P;
+        d.nsteps = (int)(p.n_steps / p.P);
+        d.item_steps = p.n_steps / p.P;
         tab.push_back(d);
-    }
-    if (method == PXP_METHOD_SERIAL) {
-        {
-            ProfScope ps(PXP_K_SERIAL_DIRECT, s);
-            pxp_status st = serial2d(tab, dtab, false, s);
-            if (st != PXP_OK) return st;
-        }
-        for (size_t e = 0; e < ord.size(); ++e)
-            HIPCHK(launch_add(nullptr, serial2d_result(tab[e]), qT[ord[e]],
-                              (int)grid_n(pb[idx[ord[e]]]), s));
-        return PXP_OK;
     }
     // (1) the P inhomogeneous slices of every instance, one launch per row
     // length
@@ -1340,16 +1640,60 @@ pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, v
             if (!uniform_direct(p) || p.P == 1) continue;
             Ctx c = make_ctx(p, ws, Ly, idx[j], s);
             per.emplace_back();
-            if (p.sched == PXP_SCHED_TREE)
+            if (with_src((int)j)) {
+                // integral cost: the levels kept, then walked back down for
+                // the corrected state at every slice start
+                const TShape sh = tree_shape(p.P);
+                const std::vector<double*> bufs = kept_bufs(c, sh);
+                tree_up_levels(p, c, sh, bufs, qT[j], per.back());
+                tree_down_levels(p, c, sh, bufs, per.back());
+            } else if (p.sched == PXP_SCHED_TREE) {
                 tree_levels(p, c, qT[j], per.back());
-            else
+            } else {
                 chain_levels(p, c, qT[j], per.back());
+            }
         }
         if (!per.empty()) {
             auto* dp = reinterpret_cast<PoisEntry*>(static_cast<char*>(ws) + Ly.ptab);
             ProfScope ps(PXP_K_KRYLOV_DIRECT, s);
             pxp_status st = run_levels(per, dp, s);
             if (st != PXP_OK) return st;
+        }
+    }
+    // integral cost: every slice again from its corrected start, writing the
+    // sources of its steps and the cost partials
+    {
+        std::vector<Band2D> st;
+        std::vector<int> who;
+        for (int j : ord) {
+            if (!with_src(j)) continue;
+            const pxp_problem& p = pb[idx[j]];
+            Ctx c = make_ctx(p, ws, Ly, idx[j], s);
+            Band2D d{};
+            d.F = F[j];
+            d.nx = p.nx;
+            d.ny = p.ny;
+            d.dt = c.dt();
+            d.omega = p.omega;
+            d.A = advdiff2d_sten(p);
+            d.y0 = init[j];
+            d.ys = c.at(c.L.ebuf);
+            d.items = p.P;
+            d.nsteps = (int)(p.n_steps / p.P);
+            d.item_steps = p.n_steps / p.P;
+            src_fields(d, c, j);
+            st.push_back(d);
+            who.push_back(j);
+        }
+        if (!st.empty()) {
+            const std::vector<Group2D> sg = group2d(st);
+            HIPCHK(launch_upload(dtab, st.data(), st.size() * sizeof(Band2D), s));
+            ProfScope ps(PXP_K_SOURCES, s);
+            for (const Group2D& g : sg)
+                HIPCHK(launch_band2d_src(dtab + g.first, g.count, g.blocks, g.nx, 0, 0, s));
+            if (nparts)
+                for (size_t e = 0; e < who.size(); ++e)
+                    (*nparts)[who[e]] = st[e].items * (st[e].ny / st[e].rows);
         }
     }
     // Krylov pieces: classic (P-1 workgroups) or chain (one)
@@ -1409,44 +1753,125 @@ pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, v
     return PXP_OK;
 }
 
-// Adjoint of the 2D instances idx from lamT: lam0 and/or Lambda.
+// Adjoint of the 2D instances idx from lamT: lam0 and/or Lambda.  src
+// (nullable; per instance, nullable): the step sources of an integral cost
+// ([n_steps + 1][n], added after each reverse step; lamT may then be null).
 pxp_status adjoint_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, void* ws,
                             const Layout& Ly, const std::vector<const double*>& lamT,
                             const std::vector<double*>& lam0,
-                            const std::vector<double*>& Lam, int method, hipStream_t s) {
+                            const std::vector<double*>& Lam, int method, hipStream_t s,
+                            const std::vector<const double*>* src = nullptr) {
     if (idx.empty()) return PXP_OK;
+    auto has_src = [&](int j) { return src && (*src)[j] != nullptr; };
+    auto* dtab = reinterpret_cast<Band2D*>(static_cast<char*>(ws) + Ly.t2d);
+    const std::vector<int> ord = by_nx(pb, idx);
     if (method == PXP_METHOD_SERIAL) {
-        auto* dtab = reinterpret_cast<Band2D*>(static_cast<char*>(ws) + Ly.t2d);
-        std::vector<Band2D> tab;
-        const std::vector<int> ord = by_nx(pb, idx);
+        for (int pass = 0; pass < 2; ++pass) {
+            std::vector<Band2D> tab;
+            std::vector<int> who;
+            for (int j : ord) {
+                if (has_src(j) != (pass == 1)) continue;
+                const pxp_problem& p = pb[idx[j]];
+                Ctx c = make_ctx(p, ws, Ly, idx[j], s);
+                Band2D d{};
+                d.y0 = lamT[j];
+                d.buf[0] = c.at(c.L.sbuf0);
+                d.buf[1] = c.at(c.L.sbuf1);
+                d.Lam = Lam[j];
+                d.n_t = p.n_steps;
+                d.nx = p.nx;
+                d.ny = p.ny;
+                d.dt = c.dt();
+                d.omega = p.omega;
+                d.A = transpose5(advdiff2d_sten(p));
+                d.items = 1;
+                if (pass == 1) d.g = const_cast<double*>((*src)[j]);
+                tab.push_back(d);
+                who.push_back(j);
+                if (Lam[j]) HIPCHK(launch_zero(Lam[j], (size_t)grid_n(p), s));
+            }
+            if (tab.empty()) continue;
+            {
+                ProfScope ps(PXP_K_SERIAL_REVERSE, s);
+                pxp_status st = serial2d(tab, dtab, true, pass == 1, s);
+                if (st != PXP_OK) return st;
+            }
+            for (size_t e = 0; e < who.size(); ++e)
+                if (lam0[who[e]])
+                    HIPCHK(launch_add(nullptr, serial2d_result(tab[e]), lam0[who[e]],
+                                      (int)grid_n(pb[idx[who[e]]]), s));
+        }
+        return PXP_OK;
+    }
+    // integral cost: the adjoint slices with their sources (zero data at
+    // each slice end; the last slice from lamT), one batch, then the tree of
+    // their homogeneous pieces with their shares of Lambda, and Lambda as the
+    // sum of all shares
+    {
+        std::vector<Band2D> at;
         for (int j : ord) {
+            if (!has_src(j) || (!lam0[j] && !Lam[j])) continue;
             const pxp_problem& p = pb[idx[j]];
             Ctx c = make_ctx(p, ws, Ly, idx[j], s);
             Band2D d{};
             d.y0 = lamT[j];
-            d.buf[0] = c.at(c.L.sbuf0);
-            d.buf[1] = c.at(c.L.sbuf1);
-            d.Lam = Lam[j];
+            d.g = const_cast<double*>((*src)[j]);
+            d.out = c.at(c.L.slices);
+            d.Lam = Lam[j] ? c.at(c.L.islot) : nullptr;
+            d.items = p.P;
+            d.nsteps = (int)(p.n_steps / p.P);
+            d.item_steps = p.n_steps / p.P;
             d.n_t = p.n_steps;
             d.nx = p.nx;
             d.ny = p.ny;
             d.dt = c.dt();
             d.omega = p.omega;
             d.A = transpose5(advdiff2d_sten(p));
-            d.items = 1;
-            tab.push_back(d);
-            if (Lam[j]) HIPCHK(launch_zero(Lam[j], (size_t)grid_n(p), s));
+            at.push_back(d);
         }
-        {
-            ProfScope ps(PXP_K_SERIAL_REVERSE, s);
-            pxp_status st = serial2d(tab, dtab, true, s);
+        if (!at.empty()) {
+            const std::vector<Group2D> ag = group2d(at);
+            HIPCHK(launch_upload(dtab, at.data(), at.size() * sizeof(Band2D), s));
+            ProfScope ps(PXP_K_ADJ_SLICES, s);
+            for (const Group2D& g : ag)
+                HIPCHK(launch_band2d_rsrc(dtab + g.first, g.count, g.blocks, g.nx, 0, 0, s));
+        }
+        std::vector<std::vector<std::vector<PJob>>> per;
+        std::vector<PoisWeights> wt;
+        for (size_t j = 0; j < idx.size(); ++j) {
+            const pxp_problem& p = pb[idx[j]];
+            if (!has_src((int)j) || (!lam0[j] && !Lam[j]) || p.P < 2) continue;
+            Ctx c = make_ctx(p, ws, Ly, idx[j], s);
+            const TShape sh = tree_shape(p.P);
+            per.emplace_back();
+            adj_tree_levels(p, c, sh, kept_bufs(c, sh), lam0[j] ? lam0[j] : c.at(c.L.lam0),
+                            Lam[j] != nullptr, wt, per.back());
+        }
+        if (!per.empty()) {
+            ProfScope ps(PXP_K_KRYLOV_ADJOINT, s);
+            if (!wt.empty()) {
+                auto* dw = reinterpret_cast<PoisWeights*>(static_cast<char*>(ws) + Ly.pwt);
+                const size_t bytes = wt.size() * sizeof(PoisWeights);
+                for (size_t o = 0; o < bytes; o += 3072)
+                    HIPCHK(launch_upload(reinterpret_cast<char*>(dw) + o,
+                                         reinterpret_cast<const char*>(wt.data()) + o,
+                                         std::min((size_t)3072, bytes - o), s));
+                HIPCHK(launch_pois_weights(dw, (int)wt.size(), s));
+            }
+            auto* dp = reinterpret_cast<PoisEntry*>(static_cast<char*>(ws) + Ly.ptab);
+            pxp_status st = run_levels(per, dp, s);
             if (st != PXP_OK) return st;
         }
-        for (size_t e = 0; e < ord.size(); ++e)
-            if (lam0[ord[e]])
-                HIPCHK(launch_add(nullptr, serial2d_result(tab[e]), lam0[ord[e]],
-                                  (int)grid_n(pb[idx[ord[e]]]), s));
-        return PXP_OK;
+        for (size_t j = 0; j < idx.size(); ++j) {
+            const pxp_problem& p = pb[idx[j]];
+            if (!has_src((int)j) || (!lam0[j] && !Lam[j])) continue;
+            Ctx c = make_ctx(p, ws, Ly, idx[j], s);
+            if (p.P == 1 && lam0[j])
+                HIPCHK(launch_add(nullptr, c.at(c.L.slices), lam0[j], c.n(), s));
+            if (Lam[j])
+                HIPCHK(launch_recombine(nullptr, nullptr, c.at(c.L.islot), 2 * p.P - 1, c.n(),
+                                        Lam[j], c.st, s));
+        }
     }
     // one homogeneous piece per instance from q^dagger(T) over [T, 0]
     // (eq. adjhomfinal).  Uniformised: substeps of at most POIS_LMAX, the
@@ -1456,7 +1881,7 @@ pxp_status adjoint_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, 
         std::vector<PoisWeights> wt;
         for (size_t j = 0; j < idx.size(); ++j) {
             const pxp_problem& p = pb[idx[j]];
-            if (!uniform_adjoint(p) || (!lam0[j] && !Lam[j])) continue;
+            if (!uniform_adjoint(p) || (!lam0[j] && !Lam[j]) || has_src((int)j)) continue;
             Ctx c = make_ctx(p, ws, Ly, idx[j], s);
             const int64_t n = c.n();
             const AdjPlan ap = adj_plan(p);
@@ -1705,32 +2130,43 @@ pxp_status paraexp_direct(const pxp_problem* pb, int32_t batch,
 }
 
 static pxp_status adjoint_impl(const pxp_problem* pb, int32_t batch,
-                               const double* lamT, double* lam0, double* Lambda,
-                               void* ws, size_t ws_bytes, void* stream,
+                               const double* lamT, const double* jI_src, double* lam0,
+                               double* Lambda, void* ws, size_t ws_bytes, void* stream,
                                int method) {
     pxp_status st = check_all(pb, batch);
     if (st != PXP_OK) return st;
+    // step sources: the integral-cost path of the 2D problems only (its
+    // workspace holds the adjoint slices' buffers)
+    if (jI_src)
+        for (int i = 0; i < batch; ++i)
+            if (pb[i].op != PXP_OP_ADVDIFF2D_UPWIND || !icost(pb[i])) return PXP_EUNSUPPORTED;
     if (batch == 0) return PXP_OK;
-    if (!lamT) return PXP_EINVAL;
+    if (!lamT && !jI_src) return PXP_EINVAL;
     Layout Ly;
     st = ws_check(pb, batch, ws, ws_bytes, &Ly);
     if (st != PXP_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     size_t off = 0;
+    size_t goff = 0;
     for (int i = 0; i < batch; ++i) {
         if (!aligned16(lamT, off) || !aligned16(lam0, off) || !aligned16(Lambda, off))
             return PXP_EINVAL;
+        if (jI_src && !aligned16(jI_src, goff)) return PXP_EINVAL;
         off += (size_t)grid_n(pb[i]);
+        goff += ((size_t)pb[i].n_steps + 1) * (size_t)grid_n(pb[i]);
     }
     off = 0;
+    goff = 0;
     const std::vector<int> idx2 = batch2d(pb, batch);
-    std::vector<const double*> l2;
+    std::vector<const double*> l2, g2;
     std::vector<double*> z2, L2;
     for (int i = 0; i < batch; ++i) {
         const pxp_problem& p = pb[i];
         Ctx c = make_ctx(p, ws, Ly, i, s);
         if (p.op == PXP_OP_ADVDIFF2D_UPWIND) {
-            l2.push_back(lamT + off);
+            g2.push_back(jI_src ? jI_src + goff : nullptr);
+            goff += ((size_t)p.n_steps + 1) * (size_t)grid_n(p);
+            l2.push_back(lamT ? lamT + off : nullptr);
             z2.push_back(lam0 ? lam0 + off : nullptr);
             L2.push_back(Lambda ? Lambda + off : nullptr);
         } else if (p.op == PXP_OP_ADVDIFF1D) {
@@ -1744,16 +2180,13 @@ static pxp_status adjoint_impl(const pxp_problem* pb, int32_t batch,
         if (st != PXP_OK) return st;
         off += (size_t)grid_n(p);
     }
-    return adjoint_2d_batch(pb, idx2, ws, Ly, l2, z2, L2, method, s);
+    return adjoint_2d_batch(pb, idx2, ws, Ly, l2, z2, L2, method, s, &g2);
 }
 
 pxp_status paraexp_adjoint(const pxp_problem* pb, int32_t batch,
                            const double* lamT, const double* jI_src, double* lam0,
                            double* Lambda, void* ws, size_t ws_bytes, void* stream) {
-    // the integral-cost source needs the direct trajectory inside the slices
-    // (adjoint slices from corrected boundary states): not available
-    if (jI_src) return PXP_EUNSUPPORTED;
-    return adjoint_impl(pb, batch, lamT, lam0, Lambda, ws, ws_bytes, stream,
+    return adjoint_impl(pb, batch, lamT, jI_src, lam0, Lambda, ws, ws_bytes, stream,
                         PXP_METHOD_PARAEXP);
 }
 
@@ -1856,9 +2289,15 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
         st = burgers_batch_direct(pb, bb, ws, Ly, binit, bqT, s);
         if (st != PXP_OK) return st;
     }
-    st = direct_2d_batch(pb, idx2, ws, Ly, i2, f2, o2, method, s);
+    // integral-cost instances: their targets, for the step sources
+    std::vector<const double*> t2(idx2.size(), nullptr);
+    std::vector<int> np2(idx2.size(), 0);
+    for (size_t j = 0; j < idx2.size(); ++j)
+        if (icost(pb[idx2[j]])) t2[j] = ip[idx2[j]].tgt;
+    st = direct_2d_batch(pb, idx2, ws, Ly, i2, f2, o2, method, s, &t2, &np2);
     if (st != PXP_OK) return st;
     // (a5) cost and adjoint final condition, every instance in two launches
+    // (integral cost: the partials of the source march; no final condition)
     auto* dst = reinterpret_cast<DevStatus*>(static_cast<char*>(ws) + Ly.status);
     std::vector<RedDesc> rd(batch);
     int bcost = 0, bgrad = 0;
@@ -1885,7 +2324,17 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
             d.part0 = po;
             d.gpart0 = po + d.chunks;
             po += (int64_t)(d.K + 1) * d.chunks;
-            bcost += d.chunks;
+            if (icost(pb[i])) {
+                int np = 0;
+                for (size_t j = 0; j < idx2.size(); ++j)
+                    if (idx2[j] == i) np = np2[j];
+                Ctx c = make_ctx(pb[i], ws, Ly, i, s);
+                d.ipart = c.at(c.L.cpart);
+                d.ichunks = np;
+                d.lamT = nullptr;
+            } else {
+                bcost += d.chunks;
+            }
             bgrad += d.K * d.chunks;
         }
     }
@@ -1894,13 +2343,15 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
     HIPCHK(launch_upload(drd, rd.data(), rd.size() * sizeof(RedDesc), s));
     HIPCHK(launch_cost_batch(drd, batch, bcost, rpart, s));
     // (a6-a8) adjoint
-    std::vector<const double*> l2;
+    std::vector<const double*> l2, g2;
     std::vector<double*> z2, L2;
     for (int i = 0; i < batch; ++i) {
         const pxp_problem& p = pb[i];
         const bool forcing = (p.ctrl == PXP_CTRL_FORCING);
         if (p.op == PXP_OP_ADVDIFF2D_UPWIND) {
-            l2.push_back(ip[i].lamT);
+            Ctx c = make_ctx(p, ws, Ly, i, s);
+            l2.push_back(icost(p) ? nullptr : ip[i].lamT);
+            g2.push_back(icost(p) ? c.at(c.L.gsrc) : nullptr);
             z2.push_back(forcing ? nullptr : ip[i].lam0);
             L2.push_back(forcing ? ip[i].Lam : nullptr);
             continue;
@@ -1917,7 +2368,7 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
         st = burgers_batch_adjoint(pb, bb, ws, Ly, blamT, blam0, method, s);
         if (st != PXP_OK) return st;
     }
-    st = adjoint_2d_batch(pb, idx2, ws, Ly, l2, z2, L2, method, s);
+    st = adjoint_2d_batch(pb, idx2, ws, Ly, l2, z2, L2, method, s, &g2);
     if (st != PXP_OK) return st;
     // (a9) gradient, every instance in two launches
     HIPCHK(launch_grad_batch(drd, batch, bgrad, rpart, s));
@@ -1961,6 +2412,9 @@ pxp_status pxp_cost(const pxp_problem* pb, int32_t batch, const double* qT,
                     double* lamT, void* stream) {
     pxp_status st = check_all(pb, batch);
     if (st != PXP_OK) return st;
+    // the integral cost needs the trajectory: pxp_gradient forms it
+    for (int i = 0; i < batch; ++i)
+        if (icost(pb[i])) return PXP_EUNSUPPORTED;
     if (batch > 0 && (!qT || !u_tgt || !J)) return PXP_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     size_t off = 0, koff = 0;

@@ -76,7 +76,14 @@ __global__ void __launch_bounds__(BNT) k_pois2d(const PoisEntry* __restrict__ ta
             for (int q = E.k0 + 1; q <= k; ++q) pk *= E.lam / q;
             wt[t] = pk;
         }
-        if (TWO) wt2[t] = E.wtab2[k];
+        if (TWO) {
+            if (E.wtab2i) {
+                const double ph = E.ph0 + (double)vec * E.dph;
+                wt2[t] = sin(ph) * E.wtab2[k] + cos(ph) * E.wtab2i[k];
+            } else {
+                wt2[t] = E.wtab2[k];
+            }
+        }
     }
     // region row r <-> grid row band*R - off + r (periodic); every region
     // row is a grid row, so the loads are in bounds and issued together, and
@@ -226,12 +233,21 @@ __global__ void k_pois_weights(const PoisWeights* __restrict__ tab) {
     // E_j by the forward recurrence from E_0 = e^{-z}, up to J well past D
     const int J = D + 64 + (int)(8.0 * sqrt(P.lam));
     double er = exp(-zr) * cos(zi), ei = -exp(-zr) * sin(zi);
-    // first pass: walk to J keeping nothing but the final value is not enough
-    // for a backward sum, so store E_j into the output table where j < D and
-    // accumulate the tail beyond D on the way
+    // E_j = e^{-z} z^j / j!: by the recurrence E_j = E_{j-1} z / j from E_0
+    // while e^{-lam} is a normal double; beyond, each E_j on its own in log
+    // form, |E_j| = exp(j log|z| - lam - lgamma(j+1)), arg E_j = j arg z -
+    // Im z (terms far from the peak flush to zero harmlessly).  E_j, j < D,
+    // go into the output table; the tail beyond D is summed on the way.
+    const bool logform = P.lam > 600.0;
+    const double lz = 0.5 * log(zr * zr + zi * zi), az = atan2(zi, zr);
     double tr = 0.0, ti = 0.0;  // sum_{j >= D} E_j
     for (int j = 0; j <= J; ++j) {
-        if (j > 0) {
+        if (logform) {
+            const double m = exp((double)j * lz - zr - lgamma((double)j + 1.0));
+            const double ph = (double)j * az - zi;
+            er = m * cos(ph);
+            ei = m * sin(ph);
+        } else if (j > 0) {
             const double nr = (er * zr - ei * zi) / j, ni = (er * zi + ei * zr) / j;
             er = nr;
             ei = ni;
@@ -261,7 +277,12 @@ __global__ void k_pois_weights(const PoisWeights* __restrict__ tab) {
         // c_k = scale Im(e^{i phi} alpha^{-(k+1)} R_k); here p = alpha^{-(k+1)}
         const double ar = pr * Rr - pi * Ri, ai = pr * Ri + pi * Rr;
         const double Ej_r = P.w[k], Ej_i = P.wi[k];
-        P.w[k] = P.scale * (sph * ar + cph * ai);
+        if (P.split) {
+            P.w[k] = P.scale * ar;
+            P.wi[k] = P.scale * ai;
+        } else {
+            P.w[k] = P.scale * (sph * ar + cph * ai);
+        }
         // R_{k-1} = R_k + E_k; alpha^{-k} = alpha^{-(k+1)} * alpha
         Rr += Ej_r;
         Ri += Ej_i;

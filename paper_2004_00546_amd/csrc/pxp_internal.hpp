@@ -183,6 +183,16 @@ struct Band2D {
     double* out;
     double* buf[2];
     double* Lam;
+    // integral cost J = 1/T int |q - tgt|^2 dt (trapezoidal over the step
+    // states): the source marches write g_n = dJ/dq_n = gw c_n (q_n - tgt),
+    // c_n = 1/2 at both ends, 1 inside, into g ([n_t + 1][n]) and one cost
+    // partial per (item, band) into cpart; the reverse source marches add
+    // g_n after each step.  Forward items p >= 1 start from ys + (p-1) n.
+    double* g;
+    const double* tgt;
+    const double* ys;
+    double* cpart;
+    double gw;
     int64_t step0, item_steps, n_t;
     double dt, omega;
     Sten5 A;
@@ -198,6 +208,18 @@ hipError_t launch_band2d(const Band2D* tab, int count, int total_blocks, int nx,
 // Reverse launch L of the serial discrete-adjoint sweep (A holds A^T).
 hipError_t launch_band2d_rev(const Band2D* tab, int count, int total_blocks, int nx,
                              int L, hipStream_t s);
+// Integral-cost marches.  Forward: the step sources g_n and the cost
+// partials of every step of the slices (serial == 0: item p from y0 (p = 0)
+// or ys, the corrected slice-start states) or of launch L of the serial
+// march (which also advances buf as launch_band2d does).  Reverse: the
+// discrete adjoint with the sources added after each step, from zero (the
+// last item: from y0 + g_{n_t}) over each slice, writing the slice's end
+// state to out + p n and its share of Lambda to Lam + p n (serial == 0), or
+// launch L of the serial sweep (Lambda accumulated).
+hipError_t launch_band2d_src(const Band2D* tab, int count, int total_blocks, int nx,
+                             int serial, int L, hipStream_t s);
+hipError_t launch_band2d_rsrc(const Band2D* tab, int count, int total_blocks, int nx,
+                              int serial, int L, hipStream_t s);
 // out = Op x for a five-point operator
 hipError_t launch_apply5(const double* x, double* out, int nx, int ny, Sten5 op,
                          hipStream_t s);
@@ -232,6 +254,11 @@ struct PoisEntry {
     double* out2;            // final second sum
     const double* out2_add;  // added to the final second sum (nullable)
     const double* wtab2;     // weights of the second sum
+    // phase form of the second sum's weights (nullable): vector v of the
+    // entry weighs term k by sin(ph_v) wtab2[k] + cos(ph_v) wtab2i[k],
+    // ph_v = ph0 + v dph (integrals of pieces that start at different times)
+    const double* wtab2i;
+    double ph0, dph;
     int64_t s_tin, s_tout, s_partner, s_acc, s_out;
     double lam;              // Poisson parameter mu * tau
     double est;              // a priori truncation bound (reported)
@@ -245,11 +272,13 @@ hipError_t launch_pois2d(const PoisEntry* tab, int count, int total_blocks, int 
                          hipStream_t s);
 // Weight table of the time integral int_0^h sin(phi - omega s) exp(s A) x ds
 // of one uniformised exponential: w[k], k < D, so that the integral is
-// sum_k w_k N^k x (lam = mu h); wi is scratch of D doubles.
+// sum_k w_k N^k x (lam = mu h); wi is scratch of D doubles.  split != 0:
+// the phase is left open, w and wi receive the two tables whose combination
+// sin(phi) w + cos(phi) wi gives the weights for any phi.
 struct PoisWeights {
     double* w;
     double* wi;
-    int D, pad;
+    int D, split;
     double lam, mu, omega, phi, scale;
 };
 hipError_t launch_pois_weights(const PoisWeights* tab, int count, hipStream_t s);
@@ -290,7 +319,11 @@ struct RedDesc {
     double* grad;
     double beta;
     DevStatus* st;
-    int n, K, chunks, blk0_cost, blk0_grad, pad;
+    // integral cost (nullable): J = sum of ipart[0..ichunks) + beta |a|^2,
+    // the partials written by the source march; the instance then has no
+    // terminal-cost blocks
+    const double* ipart;
+    int n, K, chunks, blk0_cost, blk0_grad, ichunks;
     int64_t part0, gpart0;  // this instance's partials in the cost / gradient areas
 };
 hipError_t launch_cost_batch(const RedDesc* tab, int count, int blocks_cost, double* part,

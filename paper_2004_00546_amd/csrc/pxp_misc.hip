@@ -150,9 +150,14 @@ k_cost_fin(const RedDesc* __restrict__ tab, const double* __restrict__ part) {
     const RedDesc& d = tab[blockIdx.x];
     if (threadIdx.x != 0) return;
     double s = 0.0, r = 0.0;
-    for (int c = 0; c < d.chunks; ++c) s += part[d.part0 + c];
+    if (d.ipart) {
+        for (int c = 0; c < d.ichunks; ++c) s += d.ipart[c];
+    } else {
+        for (int c = 0; c < d.chunks; ++c) s += part[d.part0 + c];
+        s *= 0.5;
+    }
     for (int k = 0; k < d.K; ++k) r += d.a[k] * d.a[k];
-    *d.J = 0.5 * s + d.beta * r;
+    *d.J = s + d.beta * r;
     // every method's q(T) passes through here
     if (d.st && !isfinite(s + r)) atomicOr(&d.st->flags, ST_NONFINITE);
 }
@@ -198,9 +203,11 @@ k_grad_fin(const RedDesc* __restrict__ tab, const double* __restrict__ part) {
 hipError_t launch_cost_batch(const RedDesc* tab, int count, int blocks_cost, double* part,
                              hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    k_cost_part<<<blocks_cost, 256, 0, s>>>(tab, count, part);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (blocks_cost > 0) {
+        k_cost_part<<<blocks_cost, 256, 0, s>>>(tab, count, part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     k_cost_fin<<<count, 64, 0, s>>>(tab, part);
     return hipGetLastError();
 }

@@ -14,6 +14,14 @@ the five workloads below are concrete instances of that family:
 * ``burgers1d_n2048`` 1D viscous Burgers, N=2048, T=2, 128 slices, IC control
 * ``advdiff2d_256``   2D upwind advection-diffusion 256^2, 16 instances
 * ``burgers1d_ragged`` 64 Burgers instances of uneven N, nu and T
+* ``advdiff2d_icost`` the integral-cost experiment of section 4.2 (eq. cost):
+  2D forced advection-diffusion 128^2, a = 1, omega = 1, T = 10, four
+  diffusivities D in {0.01, 0.02, 0.05, 0.1}, forcing control on the
+  patterns {1, sin x sin y}; the paper recovers f_true = sin x sin y from
+  the guess f = 1 against the observed trajectory q_true(t).  The problem is
+  linear with zero initial state, so q_f(t) - q_true(t) = q_{f - f_true}(t):
+  the instances hold the difference amplitudes a = (1, -1) and a zero
+  target, which gives the same cost and gradient.
 
 Every instance is a plain dict of numbers and float64 numpy arrays.  Random
 draws come from ``numpy.random.default_rng([1000 + cfg, instance])`` in the
@@ -31,7 +39,7 @@ TWO_PI = 2.0 * math.pi
 RK4_REAL_LIMIT = 2.785
 
 WORKLOADS = ("advdiff1d_n128", "advdiff1d_n4096", "burgers1d_n2048",
-             "advdiff2d_256", "burgers1d_ragged")
+             "advdiff2d_256", "burgers1d_ragged", "advdiff2d_icost")
 CFG_INDEX = {name: i + 1 for i, name in enumerate(WORKLOADS)}
 
 
@@ -183,6 +191,23 @@ def make(name: str) -> list[dict]:
             n_steps = 256 * int(math.ceil(T / (256 * dt)))
             out.append(_burgers_instance(cfg, i, n, nu, T, n_steps, 64, 32,
                                          30, rng))
+        return out
+    if name == "advdiff2d_icost":
+        out = []
+        nx = ny = 128
+        L = TWO_PI
+        x = np.arange(nx) * (L / nx)
+        y = np.arange(ny) * (L / ny)
+        patterns = np.stack([np.ones((ny, nx)),
+                             np.sin(x[None, :]) * np.sin(y[:, None])])
+        for i, D in enumerate((0.01, 0.02, 0.05, 0.1)):
+            rng = _rng(cfg, i)  # draws: FD directions only
+            out.append(dict(op="advdiff2d_upwind", control="forcing", cost="integral",
+                            nx=nx, ny=ny, L=L, vx=1.0, vy=1.0, nu=D, T=10.0,
+                            omega=1.0, beta=0.0, n_steps=2048, P=512, m=50,
+                            basis=patterns.reshape(2, nx * ny).copy(),
+                            a=np.array([1.0, -1.0]), u_tgt=np.zeros(nx * ny),
+                            q0=np.zeros(nx * ny), fd_dirs=_fd_dirs(rng, 2)))
         return out
     raise KeyError(name)
 

@@ -175,10 +175,16 @@ def test_problem_flags():
     absorbed = api.make_problem(inst, krylov="poly", absorbed=True)
     assert _lib.pxp_workspace_size([absorbed]) > _lib.pxp_workspace_size([plain])
     bad = api.make_problem(inst, krylov="poly")
-    bad.flags = 2
+    bad.flags = 4
     with pytest.raises(_lib.PxpError) as e:
         _lib.pxp_workspace_size([bad])
     assert e.value.code == _lib.PXP_EINVAL
+    # the integral cost is a 2D path
+    ic1d = api.make_problem(dict(inst, cost="integral"), krylov="poly")
+    assert ic1d.flags == _lib.FLAG_INTEGRAL_COST
+    with pytest.raises(_lib.PxpError) as e:
+        _lib.pxp_workspace_size([ic1d])
+    assert e.value.code == _lib.PXP_EUNSUPPORTED
     burg = api.make_problem(workloads.make("burgers1d_n2048")[0], krylov="poly", absorbed=True)
     with pytest.raises(_lib.PxpError) as e:
         _lib.pxp_workspace_size([burg])
@@ -197,8 +203,9 @@ def test_noalloc_rejects_oversize_on_host(lib):
 
 
 def test_adjoint_rejects_integral_cost_source_on_host(lib):
-    """The J_I source argument exists at the boundary but is not implemented:
-    a non-null source is refused before any HIP call."""
+    """Step sources are taken only by 2D problems that carry the integral-cost
+    flag (their workspace holds the adjoint slices' buffers): a 1D problem
+    with a non-null source is refused before any HIP call."""
     inst = workloads.make("advdiff1d_n128")[0]
     p = api.make_problem(inst)
     arr, n = _lib.problems_array([p])
@@ -209,3 +216,53 @@ def test_adjoint_rejects_integral_cost_source_on_host(lib):
 
 def test_report_struct_layout():
     assert ctypes.sizeof(_lib.pxp_report) == 4 * 4 + 2 * 8 + 2 * 8
+
+
+def _icost2d(**kw):
+    import math
+    base = dict(op="advdiff2d_upwind", control="forcing", cost="integral", nx=64, ny=32,
+                L=2 * math.pi, vx=1.0, vy=1.0, nu=0.02, T=0.5, n_steps=64, P=16, m=30,
+                basis=np.zeros((2, 64 * 32)))
+    base.update(kw)
+    return base
+
+
+def test_integral_cost_rules_on_host(lib):
+    """The integral cost runs on the uniformised tree schedule of the 2D
+    problems; the largest adjoint piece is bounded; its workspace holds the
+    (n_steps + 1) n step sources; pxp_cost (terminal cost only) refuses it
+    before any HIP call."""
+    ok = api.make_problem(_icost2d(), krylov="uniform", sched="tree")
+    plain = api.make_problem(dict(_icost2d(), cost="terminal"), krylov="uniform", sched="tree")
+    n = 64 * 32
+    grow = _lib.pxp_workspace_size([ok]) - _lib.pxp_workspace_size([plain])
+    assert grow >= (64 + 1) * n * 8 + (2 * 16 - 1) * n * 8
+    assert _lib.pxp_workspace_size([api.make_problem(_icost2d(), krylov="auto",
+                                                     sched="tree")]) > 0
+    for kw, code in [(dict(krylov="uniform", sched="chain"), _lib.PXP_EUNSUPPORTED),
+                     (dict(krylov="poly", sched="chain"), _lib.PXP_EUNSUPPORTED),
+                     (dict(krylov="taylor", sched="classic"), _lib.PXP_EUNSUPPORTED)]:
+        with pytest.raises(_lib.PxpError) as e:
+            _lib.pxp_workspace_size([api.make_problem(_icost2d(), **kw)])
+        assert e.value.code == code, kw
+    # mu T/2 beyond the bound of one adjoint piece: T = 500 on a grid where
+    # mu is about 20 (the step of the accepted case keeps RK4 stable)
+    long = api.make_problem(_icost2d(T=500.0, n_steps=65536, P=16384), krylov="uniform",
+                            sched="tree")
+    with pytest.raises(_lib.PxpError) as e:
+        _lib.pxp_workspace_size([long])
+    assert e.value.code == _lib.PXP_EUNSUPPORTED
+    arr, nb = _lib.problems_array([ok])
+    fake = ctypes.c_void_p(4096)  # never dereferenced: refused first
+    assert lib.pxp_cost(arr, nb, fake, fake, fake, fake, None, None) == _lib.PXP_EUNSUPPORTED
+
+
+def test_integral_cost_workload_accepted(lib):
+    """The section 4.2 stand-in: four diffusivities on 128^2, T = 10, 2048
+    steps in 512 slices; every instance passes the host checks (RK4
+    stability, tree bound)."""
+    insts = workloads.make("advdiff2d_icost")
+    assert [i["nu"] for i in insts] == [0.01, 0.02, 0.05, 0.1]
+    probs = [api.make_problem(i, krylov="uniform", sched="tree", tol=1e-9) for i in insts]
+    assert all(p.flags == _lib.FLAG_INTEGRAL_COST for p in probs)
+    assert _lib.pxp_workspace_size(probs) > 4 * 2049 * 128 * 128 * 8
