@@ -90,6 +90,21 @@ def tree_jobs(P):
     return levels
 
 
+def tree_pairs(P):
+    """(left, right) range lengths of every pair, per level, of the pairwise
+    tree of P slices (an odd last range carried up alone)."""
+    size = [1] * P
+    levels = []
+    while len(size) > 1:
+        pairs = len(size) // 2
+        levels.append([(size[2 * j], size[2 * j + 1]) for j in range(pairs)])
+        ns = [size[2 * j] + size[2 * j + 1] for j in range(pairs)]
+        if len(size) % 2:
+            ns.append(size[-1])
+        size = ns
+    return levels
+
+
 def sten2d_mu(inst):
     """Diagonal magnitude of the 2D upwind five-point operator."""
     hx, hy = inst["L"] / inst["nx"], inst["L"] / inst["ny"]
@@ -242,13 +257,53 @@ def class_models(insts, problems, args, counters):
                 "partial sums and writes one (3 vectors per pair, P-1 pairs per "
                 "instance); %.3g term-points (%.3g flop) beside it" %
                 (terms, terms * POIS_FLOPS))
-        lam = [sten2d_mu(x) * x["T"] for x in insts]
-        adj_terms = sum(pois_terms(min(l, 600.0), tol) * math.ceil(l / 600.0) * nn
-                        for l, nn in zip(lam, n))
-        out["krylov_adjoint"] = (
-            "alu", adj_terms * (POIS_FLOPS + 2.0), "flop",
-            "k_pois2d, the adjoint piece with its time integral: terms x points x "
-            "%g flop" % (POIS_FLOPS + 2.0))
+        icost = all(x.get("cost") == "integral" for x in insts)
+        if icost and sched == "tree":
+            # integral cost: the tree is walked back down (each pair with a
+            # start state reads it and the left sum and writes the state at
+            # its middle; the leftmost pairs copy), the sources are written
+            # by a second march of every slice and read by the adjoint slices,
+            # whose pieces combine pairwise with two sums (state and Lambda
+            # share, the halves' shares added)
+            dn, st, rs, adj, adj_terms = 0.0, 0.0, 0.0, 0.0, 0.0
+            for x, p, nn in zip(insts, problems, n):
+                P, nt = int(p.P), int(x["n_steps"])
+                mu, dT = sten2d_mu(x), x["T"] / P
+                for lv in tree_pairs(P):
+                    for j, (ls, rs_) in enumerate(lv):
+                        first = j == 0
+                        dn += (2 if first else 3) * 8 * nn
+                        adj += 6 * 8 * nn
+                        adj_terms += pois_terms(mu * dT * ls, tol) * nn
+                st += (nt + 1) * 8 * nn + (P - 1) * 8 * nn
+                rs += (nt + 1) * 8 * nn + 2 * P * 8 * nn
+            bd, bq, wd, dd = out["krylov_direct"]
+            out["krylov_direct"] = (bd, bq + dn, wd,
+                                    dd + "; plus the walk back down for the slice-start "
+                                    "states (3 vectors per pair, 2 for the leftmost)")
+            out["sources"] = (
+                "hbm", st, "B",
+                "k_band2d_src: every slice again from its corrected start state "
+                "(read once), writing the n_t + 1 step sources dJ/dq_n; %.3g flop of "
+                "RK4 beside it" % flops)
+            out["adj_slices"] = (
+                "hbm", rs, "B",
+                "k_band2d_rsrc: the adjoint slices read every step source once and "
+                "write each slice's end state and Lambda share")
+            out["krylov_adjoint"] = (
+                "hbm", adj, "B",
+                "k_pois2d, adjoint tree of the integral cost: every pair reads its "
+                "halves' states and Lambda shares and writes its state and share (6 "
+                "vectors per pair; the root's share is Lambda); %.3g term-points "
+                "beside it" % adj_terms)
+        else:
+            lam = [sten2d_mu(x) * x["T"] for x in insts]
+            adj_terms = sum(pois_terms(min(l, 600.0), tol) * math.ceil(l / 600.0) * nn
+                            for l, nn in zip(lam, n))
+            out["krylov_adjoint"] = (
+                "alu", adj_terms * (POIS_FLOPS + 2.0), "flop",
+                "k_pois2d, the adjoint piece with its time integral: terms x points x "
+                "%g flop" % (POIS_FLOPS + 2.0))
     if one_lin and len(insts) == 1 and counters.get(0):
         inst, p = insts[0], problems[0]
         n = inst["nx"]
@@ -326,7 +381,9 @@ def measure(args, name, torch, _lib, api, workloads, steps, serial_steps, with_o
     else:
         pxp = api.GradientRunner(insts, method="paraexp", krylov=args.krylov, sched=sched,
                                  tol=tol, **pkw)
-    ser = api.GradientRunner(insts, method="serial", krylov="auto", **kw)
+    # (the integral cost is validated on the tree schedule also for the
+    # serial method, which uses neither)
+    ser = api.GradientRunner(insts, method="serial", krylov=args.krylov, sched=sched, **kw)
 
     # timed Paraexp region, with per-kernel events on the library's stream
     warm(torch, pxp, args.warmup, args.warmup_seconds)

@@ -28,6 +28,7 @@ struct Layout {
     size_t status;             // DevStatus
     size_t btab, ktab, t2d;    // batch tables: Burgers, Krylov, 2D marches
     size_t ptab, pwt;          // uniformised exponentials: pass entries, weights
+    size_t ptab_entries;       // capacity of the pass-entry table
     size_t rtab, rpart;        // batched cost/gradient: descriptors, partial sums
     size_t irep;               // per-instance statistics
     std::vector<size_t> base;  // per-instance region offset
@@ -514,7 +515,8 @@ Layout layout(const pxp_problem* pb, int batch) {
     // at most four entries per instance in one pass launch (pairs of two
     // lengths, a pass-through, or the adjoint's piece)
     Ly.ptab = off;
-    off += align_up((size_t)batch * 8 * sizeof(PoisEntry));
+    Ly.ptab_entries = (size_t)batch * 8;
+    off += align_up(Ly.ptab_entries * sizeof(PoisEntry));
     size_t nw = 0;
     for (int i = 0; i < batch; ++i) {
         if (uniform_adjoint(pb[i])) nw += (size_t)adj_plan(pb[i]).nsub;
@@ -1181,6 +1183,8 @@ struct PJob {
     double* acc2 = nullptr;
     double* out2 = nullptr;
     const double* out2_add = nullptr;
+    const double* out2_add2 = nullptr;
+    int64_t sa = 0;  // stride of the added vectors
     const double* wtab2 = nullptr;
     const double* wtab2i = nullptr;  // phase form of the second sum's weights
     double ph0 = 0.0, dph = 0.0;
@@ -1195,10 +1199,18 @@ struct PJob {
 int pois_passes(int D) { return (D + POIS_PASS_TERMS - 1) / POIS_PASS_TERMS; }
 
 // One stage: independent jobs (any instances), run pass by pass; every pass
-// is one launch per (row length, one or two sums).  Output rows per band:
-// 32 when that still gives a few workgroups per CU, else 16.
-pxp_status run_stage(const std::vector<PJob>& jobs, PoisEntry* dtab, hipStream_t s) {
+// is one launch per (row length, one or two sums).  Each such group's table
+// is uploaded once per stage, its entries ordered by falling term count, so
+// the entries still running at a pass are a prefix of the table and the
+// kernel derives the pass's terms and term vectors from the pass index.
+// Output rows per band: 32 when that still gives a few workgroups per CU,
+// else 16.
+pxp_status run_stage(const std::vector<PJob>& jobs, PoisEntry* dtab, size_t cap,
+                     hipStream_t s) {
     if (jobs.empty()) return PXP_OK;
+    // at most a few jobs per instance and stage (two pair shapes, a carried
+    // range, a copy); the table holds eight per instance
+    if (jobs.size() > cap) return PXP_EWORKSPACE;
     int maxp = 0;
     size_t blocks32 = 0;
     bool all32 = true;
@@ -1208,58 +1220,79 @@ pxp_status run_stage(const std::vector<PJob>& jobs, PoisEntry* dtab, hipStream_t
         all32 = all32 && (j.ny % 32 == 0);
     }
     const int rows = (all32 && blocks32 >= 1024) ? 32 : 16;
-    for (int pass = 0; pass < maxp; ++pass) {
-        for (int two = 0; two < 2; ++two)
-            for (int nx : {64, 128, 256}) {
-                std::vector<PoisEntry> tab;
-                int blk = 0;
-                for (const PJob& j : jobs) {
-                    if (j.nx != nx || (j.out2 != nullptr) != (two != 0)) continue;
-                    if (pois_passes(j.D) <= pass) continue;
-                    const int64_t n = (int64_t)j.nx * j.ny;
-                    PoisEntry e{};
-                    e.k0 = pass * POIS_PASS_TERMS;
-                    e.k1 = std::min(j.D, e.k0 + POIS_PASS_TERMS);
-                    e.final_pass = (e.k1 == j.D) ? 1 : 0;
-                    e.tin = pass == 0 ? j.x : j.tb[(pass - 1) & 1];
-                    e.s_tin = pass == 0 ? j.sx : n;
-                    e.tout = j.tb[pass & 1];
-                    e.s_tout = n;
-                    e.partner = j.partner;
-                    e.s_partner = j.sp;
-                    e.acc = j.out;
-                    e.out = j.out;
-                    e.s_acc = e.s_out = j.so;
-                    e.wtab = j.wtab;
-                    e.acc2 = j.acc2;
-                    e.out2 = j.out2;
-                    e.out2_add = j.out2_add;
-                    e.wtab2 = j.wtab2;
-                    e.wtab2i = j.wtab2i;
-                    e.ph0 = j.ph0;
-                    e.dph = j.dph;
-                    e.lam = j.lam;
-                    e.est = j.est;
-                    e.N = j.N;
-                    e.nvec = j.nvec;
-                    e.nx = j.nx;
-                    e.ny = j.ny;
-                    e.rows = rows;
-                    e.blk0 = blk;
-                    e.status = j.st;
-                    e.irep = j.irep;
-                    blk += j.nvec * (j.ny / rows);
-                    tab.push_back(e);
-                }
-                if (tab.empty()) continue;
-                const size_t bytes = tab.size() * sizeof(PoisEntry);
-                for (size_t o = 0; o < bytes; o += 3072)
-                    HIPCHK(launch_upload(reinterpret_cast<char*>(dtab) + o,
-                                         reinterpret_cast<const char*>(tab.data()) + o,
-                                         std::min((size_t)3072, bytes - o), s));
-                HIPCHK(launch_pois2d(dtab, (int)tab.size(), blk, nx, two, s));
+    struct Group {
+        int nx, two;
+        PoisEntry* dev;
+        std::vector<PoisEntry> tab;
+        std::vector<int> passes;  // per entry
+    };
+    std::vector<Group> groups;
+    size_t used = 0;
+    for (int two = 0; two < 2; ++two)
+        for (int nx : {64, 128, 256}) {
+            Group g{nx, two, dtab + used, {}, {}};
+            std::vector<const PJob*> js;
+            for (const PJob& j : jobs)
+                if (j.nx == nx && (j.out2 != nullptr) == (two != 0)) js.push_back(&j);
+            if (js.empty()) continue;
+            std::stable_sort(js.begin(), js.end(), [](const PJob* x, const PJob* y) {
+                return pois_passes(x->D) > pois_passes(y->D);
+            });
+            int blk = 0;
+            for (const PJob* jp : js) {
+                const PJob& j = *jp;
+                PoisEntry e{};
+                e.x = j.x;
+                e.sx = j.sx;
+                e.tb[0] = j.tb[0];
+                e.tb[1] = j.tb[1];
+                e.partner = j.partner;
+                e.s_partner = j.sp;
+                e.acc = j.out;
+                e.out = j.out;
+                e.s_acc = e.s_out = j.so;
+                e.wtab = j.wtab;
+                e.acc2 = j.acc2;
+                e.out2 = j.out2;
+                e.out2_add = j.out2_add;
+                e.out2_add2 = j.out2_add2;
+                e.s_add = j.sa;
+                e.wtab2 = j.wtab2;
+                e.wtab2i = j.wtab2i;
+                e.ph0 = j.ph0;
+                e.dph = j.dph;
+                e.lam = j.lam;
+                e.est = j.est;
+                e.N = j.N;
+                e.D = j.D;
+                e.nvec = j.nvec;
+                e.nx = j.nx;
+                e.ny = j.ny;
+                e.rows = rows;
+                e.blk0 = blk;
+                e.status = j.st;
+                e.irep = j.irep;
+                blk += j.nvec * (j.ny / rows);
+                g.tab.push_back(e);
+                g.passes.push_back(pois_passes(j.D));
             }
-    }
+            used += g.tab.size();
+            const size_t bytes = g.tab.size() * sizeof(PoisEntry);
+            for (size_t o = 0; o < bytes; o += 3072)
+                HIPCHK(launch_upload(reinterpret_cast<char*>(g.dev) + o,
+                                     reinterpret_cast<const char*>(g.tab.data()) + o,
+                                     std::min((size_t)3072, bytes - o), s));
+            groups.push_back(std::move(g));
+        }
+    for (int pass = 0; pass < maxp; ++pass)
+        for (const Group& g : groups) {
+            int cnt = 0;
+            while (cnt < (int)g.tab.size() && g.passes[cnt] > pass) ++cnt;
+            if (cnt == 0) continue;
+            const PoisEntry& last = g.tab[cnt - 1];
+            const int blocks = last.blk0 + last.nvec * (last.ny / rows);
+            HIPCHK(launch_pois2d(g.dev, cnt, blocks, g.nx, g.two, pass, s));
+        }
     return PXP_OK;
 }
 
@@ -1410,12 +1443,14 @@ void tree_down_levels(const pxp_problem& p, const Ctx& c, const TShape& sh,
 
 // Tree of the integral-cost adjoint pieces over the adjoint slices' end
 // states (bufs[0]): a pair of ranges [s, m), [m, e) gives the adjoint at
-// T_s, exp((T_m - T_s) A^T) u_me + u_sm, and (integral) its share of
-// Lambda, int_{T_s}^{T_m} sin(omega t) exp((T_m - t) A^T) u_me dt, into the
-// next islot slot (slots 0..P-1 hold the slices' own shares).  The root goes
-// to root_out.  Weight tables (phase form) are appended to wt from wbase.
+// T_s, exp((T_m - T_s) A^T) u_me + u_sm, and (Lam_out non-null) its share of
+// Lambda, int_{T_s}^{T_m} sin(omega t) exp((T_m - t) A^T) u_me dt plus the
+// shares of both halves (the slices' own shares in islot slots 0..P-1 at
+// level 0; later levels' shares in the slots after them; a carried range
+// keeps its share).  The root's state goes to root_out, its share (Lambda)
+// to Lam_out.  Weight tables (phase form) are appended to wt.
 void adj_tree_levels(const pxp_problem& p, const Ctx& c, const TShape& sh,
-                     const std::vector<double*>& bufs, double* root_out, bool integral,
+                     const std::vector<double*>& bufs, double* root_out, double* Lam_out,
                      std::vector<PoisWeights>& wt, std::vector<std::vector<PJob>>& levels) {
     const int64_t n = c.n();
     const Sten5 AT = transpose5(advdiff2d_sten(p));
@@ -1425,19 +1460,27 @@ void adj_tree_levels(const pxp_problem& p, const Ctx& c, const TShape& sh,
     double* islot = c.at(c.L.islot);
     double* wbase = c.at(c.L.iwtab);
     size_t wofs = 0;
-    int slot = p.P;
+    size_t slot = (size_t)p.P;
+    std::vector<double*> share;  // shares of the ranges of the level below
+    for (int q = 0; q < p.P; ++q) share.push_back(islot + (size_t)q * n);
     const size_t depth = sh.size() - 1;
     for (size_t l = 1; l <= depth; ++l) {
         const std::vector<TNode>& ch = sh[l - 1];
         const int cnt = (int)ch.size(), pairs = cnt / 2;
         const double* src = bufs[l - 1];
         double* dst = l == depth ? root_out : bufs[l];
+        double* shl = l == depth ? Lam_out : islot + slot * n;
+        std::vector<double*> nshare;
         std::vector<PJob> lv;
         int j = 0;
         while (j < pairs) {
             const int Ls = ch[2 * j].size, Rs = ch[2 * j + 1].size;
+            // a run: equal shapes, and (shares) halves' shares 2n apart
             int j1 = j + 1;
-            while (j1 < pairs && ch[2 * j1].size == Ls && ch[2 * j1 + 1].size == Rs) ++j1;
+            while (j1 < pairs && ch[2 * j1].size == Ls && ch[2 * j1 + 1].size == Rs &&
+                   (!Lam_out || (share[2 * j1] == share[2 * j] + 2 * (j1 - j) * n &&
+                                 share[2 * j1 + 1] == share[2 * j + 1] + 2 * (j1 - j) * n)))
+                ++j1;
             PJob b;
             b.nvec = j1 - j;
             b.x = src + (size_t)(2 * j + 1) * n;
@@ -1455,7 +1498,7 @@ void adj_tree_levels(const pxp_problem& p, const Ctx& c, const TShape& sh,
             b.N = uniform_N(AT, mu);
             b.st = c.st;
             b.irep = c.irep;
-            if (integral) {
+            if (Lam_out) {
                 PoisWeights pw{};
                 pw.w = wbase + wofs;
                 pw.wi = pw.w + b.D;
@@ -1471,14 +1514,17 @@ void adj_tree_levels(const pxp_problem& p, const Ctx& c, const TShape& sh,
                 b.wtab2i = pw.wi;
                 b.ph0 = p.omega * dT * (ch[2 * j].start + Ls);
                 b.dph = p.omega * dT * (Ls + Rs);
-                b.out2 = islot + (size_t)slot * n;
+                b.out2 = shl + (size_t)j * n;
                 b.acc2 = b.out2;
-                slot += b.nvec;
+                b.out2_add = share[2 * j];
+                b.out2_add2 = share[2 * j + 1];
+                b.sa = 2 * n;
+                for (int v = j; v < j1; ++v) nshare.push_back(shl + (size_t)v * n);
             }
             lv.push_back(b);
             j = j1;
         }
-        if (cnt & 1) {
+        if (cnt & 1) {  // carried: the state is copied, the share kept
             PJob b;
             b.x = src + (size_t)(cnt - 1) * n;
             b.out = dst + (size_t)pairs * n;
@@ -1493,7 +1539,10 @@ void adj_tree_levels(const pxp_problem& p, const Ctx& c, const TShape& sh,
             b.st = c.st;
             b.irep = c.irep;
             lv.push_back(b);
+            if (Lam_out) nshare.push_back(share[cnt - 1]);
         }
+        slot += (size_t)pairs;
+        share.swap(nshare);
         levels.push_back(lv);
     }
 }
@@ -1528,14 +1577,14 @@ void chain_levels(const pxp_problem& p, const Ctx& c, double* qT,
 
 // Stages of every instance run together: stage l holds level l of each.
 pxp_status run_levels(const std::vector<std::vector<std::vector<PJob>>>& per, PoisEntry* dtab,
-                      hipStream_t s) {
+                      size_t cap, hipStream_t s) {
     size_t depth = 0;
     for (const auto& v : per) depth = std::max(depth, v.size());
     for (size_t l = 0; l < depth; ++l) {
         std::vector<PJob> stage;
         for (const auto& v : per)
             if (l < v.size()) stage.insert(stage.end(), v[l].begin(), v[l].end());
-        pxp_status st = run_stage(stage, dtab, s);
+        pxp_status st = run_stage(stage, dtab, cap, s);
         if (st != PXP_OK) return st;
     }
     return PXP_OK;
@@ -1656,7 +1705,7 @@ pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, v
         if (!per.empty()) {
             auto* dp = reinterpret_cast<PoisEntry*>(static_cast<char*>(ws) + Ly.ptab);
             ProfScope ps(PXP_K_KRYLOV_DIRECT, s);
-            pxp_status st = run_levels(per, dp, s);
+            pxp_status st = run_levels(per, dp, Ly.ptab_entries, s);
             if (st != PXP_OK) return st;
         }
     }
@@ -1805,8 +1854,8 @@ pxp_status adjoint_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, 
     }
     // integral cost: the adjoint slices with their sources (zero data at
     // each slice end; the last slice from lamT), one batch, then the tree of
-    // their homogeneous pieces with their shares of Lambda, and Lambda as the
-    // sum of all shares
+    // their homogeneous pieces, each pair adding its share of Lambda to its
+    // halves' shares up to the root
     {
         std::vector<Band2D> at;
         for (int j : ord) {
@@ -1817,7 +1866,8 @@ pxp_status adjoint_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, 
             d.y0 = lamT[j];
             d.g = const_cast<double*>((*src)[j]);
             d.out = c.at(c.L.slices);
-            d.Lam = Lam[j] ? c.at(c.L.islot) : nullptr;
+            // each slice's share of Lambda (a single slice: Lambda itself)
+            d.Lam = Lam[j] ? (p.P == 1 ? Lam[j] : c.at(c.L.islot)) : nullptr;
             d.items = p.P;
             d.nsteps = (int)(p.n_steps / p.P);
             d.item_steps = p.n_steps / p.P;
@@ -1845,7 +1895,7 @@ pxp_status adjoint_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, 
             const TShape sh = tree_shape(p.P);
             per.emplace_back();
             adj_tree_levels(p, c, sh, kept_bufs(c, sh), lam0[j] ? lam0[j] : c.at(c.L.lam0),
-                            Lam[j] != nullptr, wt, per.back());
+                            Lam[j], wt, per.back());
         }
         if (!per.empty()) {
             ProfScope ps(PXP_K_KRYLOV_ADJOINT, s);
@@ -1859,7 +1909,7 @@ pxp_status adjoint_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, 
                 HIPCHK(launch_pois_weights(dw, (int)wt.size(), s));
             }
             auto* dp = reinterpret_cast<PoisEntry*>(static_cast<char*>(ws) + Ly.ptab);
-            pxp_status st = run_levels(per, dp, s);
+            pxp_status st = run_levels(per, dp, Ly.ptab_entries, s);
             if (st != PXP_OK) return st;
         }
         for (size_t j = 0; j < idx.size(); ++j) {
@@ -1868,9 +1918,6 @@ pxp_status adjoint_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, 
             Ctx c = make_ctx(p, ws, Ly, idx[j], s);
             if (p.P == 1 && lam0[j])
                 HIPCHK(launch_add(nullptr, c.at(c.L.slices), lam0[j], c.n(), s));
-            if (Lam[j])
-                HIPCHK(launch_recombine(nullptr, nullptr, c.at(c.L.islot), 2 * p.P - 1, c.n(),
-                                        Lam[j], c.st, s));
         }
     }
     // one homogeneous piece per instance from q^dagger(T) over [T, 0]
@@ -1948,7 +1995,7 @@ pxp_status adjoint_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, 
                 HIPCHK(launch_pois_weights(dw, (int)wt.size(), s));
             }
             auto* dp = reinterpret_cast<PoisEntry*>(static_cast<char*>(ws) + Ly.ptab);
-            pxp_status st = run_levels(per, dp, s);
+            pxp_status st = run_levels(per, dp, Ly.ptab_entries, s);
             if (st != PXP_OK) return st;
         }
     }

@@ -53,7 +53,8 @@ __device__ __forceinline__ int pois_entry(const PoisEntry* tab, int count, int b
 }
 
 template <int NX, bool TWO>
-__global__ void __launch_bounds__(BNT) k_pois2d(const PoisEntry* __restrict__ tab, int count) {
+__global__ void __launch_bounds__(BNT)
+k_pois2d(const PoisEntry* __restrict__ tab, int count, int pass) {
     constexpr int CPL = NX / WAVE;
     __shared__ double xch[BW][2][NX];
     __shared__ double wt[POIS_PASS_TERMS], wt2[POIS_PASS_TERMS];
@@ -62,18 +63,21 @@ __global__ void __launch_bounds__(BNT) k_pois2d(const PoisEntry* __restrict__ ta
     const int local = blockIdx.x - E.blk0;
     const int vec = local / nb, band = local - vec * nb;
     const int off = (BROWS - R) / 2;
-    const int nterm = E.k1 - E.k0;
-    const int napp = E.final_pass ? nterm - 1 : nterm;
+    const int k0 = pass * POIS_PASS_TERMS, k1 = min(E.D, k0 + POIS_PASS_TERMS);
+    const bool final_pass = k1 == E.D;
+    const int nterm = k1 - k0;
+    const int napp = final_pass ? nterm - 1 : nterm;
+    const size_t nn = (size_t)NX * ny;
     const int t = threadIdx.x, w = wave_id(), l = lane_id(), cb = l * CPL;
     if (t < nterm) {
-        const int k = E.k0 + t;
+        const int k = k0 + t;
         if (E.wtab) {
             wt[t] = E.wtab[k];
         } else {
             // p_k = p_{k0} lam^(k-k0) k0! / k!: one log-form weight per
             // pass, then a short product (k - k0 < 16)
-            double pk = pois_pmf(E.lam, E.k0);
-            for (int q = E.k0 + 1; q <= k; ++q) pk *= E.lam / q;
+            double pk = pois_pmf(E.lam, k0);
+            for (int q = k0 + 1; q <= k; ++q) pk *= E.lam / q;
             wt[t] = pk;
         }
         if (TWO) {
@@ -91,7 +95,8 @@ __global__ void __launch_bounds__(BNT) k_pois2d(const PoisEntry* __restrict__ ta
     int g[BRW];
     wave_rows(band_grow(band * R - off + w * BRW, 0, ny), ny, g);
     const size_t vof = (size_t)vec;
-    const double* tin = E.tin + vof * E.s_tin;
+    // pass 0 reads the input vectors, later passes the previous pass's terms
+    const double* tin = pass == 0 ? E.x + vof * E.sx : E.tb[(pass - 1) & 1] + vof * nn;
     double tv[BRW][CPL], acc[BRW][CPL], acc2[TWO ? BRW : 1][CPL];
     // rows of the term vector this pass needs (the halo of its napp
     // applications); a wave row is uniform, so the skip is a uniform branch
@@ -108,9 +113,10 @@ __global__ void __launch_bounds__(BNT) k_pois2d(const PoisEntry* __restrict__ ta
     // the sums start from the previous pass's (or zero) plus, in the final
     // pass, the vectors added to them: those loads then overlap the term
     // loads instead of trailing the arithmetic
-    const bool cont = E.k0 > 0;
-    const double* add1 = E.final_pass ? E.partner : nullptr;
-    const double* add2 = (TWO && E.final_pass) ? E.out2_add : nullptr;
+    const bool cont = k0 > 0;
+    const double* add1 = final_pass ? E.partner : nullptr;
+    const double* add2 = (TWO && final_pass) ? E.out2_add : nullptr;
+    const double* add3 = (TWO && final_pass) ? E.out2_add2 : nullptr;
 #pragma unroll
     for (int i = 0; i < BRW; ++i) {
         const int r = w * BRW + i;
@@ -134,7 +140,13 @@ __global__ void __launch_bounds__(BNT) k_pois2d(const PoisEntry* __restrict__ ta
         }
         if (add2) {
             double q[CPL];
-            row_load<CPL>(add2 + vof * E.s_out + o, q);
+            row_load<CPL>(add2 + vof * E.s_add + o, q);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) acc2[i][c] += q[c];
+        }
+        if (add3) {
+            double q[CPL];
+            row_load<CPL>(add3 + vof * E.s_add + o, q);
 #pragma unroll
             for (int c = 0; c < CPL; ++c) acc2[i][c] += q[c];
         }
@@ -184,7 +196,7 @@ __global__ void __launch_bounds__(BNT) k_pois2d(const PoisEntry* __restrict__ ta
         const int r = w * BRW + i;
         if (r < off || r >= off + R) continue;
         const size_t o = (size_t)g[i] * NX + cb;
-        if (E.final_pass) {
+        if (final_pass) {
             if (E.out) {
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) bad |= !isfinite(acc[i][c]);
@@ -196,12 +208,12 @@ __global__ void __launch_bounds__(BNT) k_pois2d(const PoisEntry* __restrict__ ta
                 row_store<CPL>(E.out2 + vof * E.s_out + o, acc2[i]);
             }
         } else {
-            row_store<CPL>(E.tout + vof * E.s_tout + o, tv[i]);
+            row_store<CPL>(E.tb[pass & 1] + vof * nn + o, tv[i]);
             row_store<CPL>(E.acc + vof * E.s_acc + o, acc[i]);
             if (TWO) row_store<CPL>(E.acc2 + vof * E.s_acc + o, acc2[i]);
         }
     }
-    if (E.final_pass && E.status) {
+    if (final_pass && E.status) {
         if (__any(bad) && l == 0) atomicOr(&E.status->flags, ST_NONFINITE);
         if (local == 0 && t == 0) {
             const unsigned long long eb = (unsigned long long)__double_as_longlong(E.est);
@@ -209,7 +221,7 @@ __global__ void __launch_bounds__(BNT) k_pois2d(const PoisEntry* __restrict__ ta
             if (E.irep) {
                 // one exponential per vector of the entry, k1 terms each
                 atomicAdd(&E.irep->substeps, (unsigned long long)E.nvec);
-                atomicAdd(&E.irep->iters, (unsigned long long)E.nvec * (unsigned long long)E.k1);
+                atomicAdd(&E.irep->iters, (unsigned long long)E.nvec * (unsigned long long)k1);
                 atomicMax(&E.irep->max_est, eb);
             }
         }
@@ -234,30 +246,56 @@ __global__ void k_pois_weights(const PoisWeights* __restrict__ tab) {
     const int J = D + 64 + (int)(8.0 * sqrt(P.lam));
     double er = exp(-zr) * cos(zi), ei = -exp(-zr) * sin(zi);
     // E_j = e^{-z} z^j / j!: by the recurrence E_j = E_{j-1} z / j from E_0
-    // while e^{-lam} is a normal double; beyond, each E_j on its own in log
-    // form, |E_j| = exp(j log|z| - lam - lgamma(j+1)), arg E_j = j arg z -
-    // Im z (terms far from the peak flush to zero harmlessly).  E_j, j < D,
-    // go into the output table; the tail beyond D is summed on the way.
-    const bool logform = P.lam > 600.0;
-    const double lz = 0.5 * log(zr * zr + zi * zi), az = atan2(zi, zr);
+    // while e^{-lam} is a normal double.  Beyond, e^{-lam} underflows: E_j is
+    // formed in log form at the peak j0 = floor|z|, |E_j0| = exp(j0 log|z| -
+    // lam - lgamma(j0+1)), arg E_j0 = j0 arg z - Im z, and the same
+    // recurrence runs from there both ways (down: E_{j-1} = E_j j / z), the
+    // magnitudes falling away from the peak (terms far from it flush to zero
+    // harmlessly).  E_j, j < D, go into the output table; the tail beyond D
+    // is summed on the way.
     double tr = 0.0, ti = 0.0;  // sum_{j >= D} E_j
-    for (int j = 0; j <= J; ++j) {
-        if (logform) {
-            const double m = exp((double)j * lz - zr - lgamma((double)j + 1.0));
-            const double ph = (double)j * az - zi;
-            er = m * cos(ph);
-            ei = m * sin(ph);
-        } else if (j > 0) {
+    auto put = [&](int j, double a, double b) {
+        if (j < D) {
+            P.w[j] = a;
+            P.wi[j] = b;
+        } else {
+            tr += a;
+            ti += b;
+        }
+    };
+    if (P.lam <= 600.0) {
+        for (int j = 0; j <= J; ++j) {
+            if (j > 0) {
+                const double nr = (er * zr - ei * zi) / j, ni = (er * zi + ei * zr) / j;
+                er = nr;
+                ei = ni;
+            }
+            put(j, er, ei);
+        }
+    } else {
+        const double az2 = zr * zr + zi * zi;
+        const int j0 = min(J, (int)floor(sqrt(az2)));
+        const double m0 = exp((double)j0 * 0.5 * log(az2) - zr - lgamma((double)j0 + 1.0));
+        const double ph0 = (double)j0 * atan2(zi, zr) - zi;
+        const double e0r = m0 * cos(ph0), e0i = m0 * sin(ph0);
+        // down to 0: E_{j-1} = E_j j conj(z) / |z|^2
+        er = e0r;
+        ei = e0i;
+        put(j0, er, ei);
+        for (int j = j0; j > 0; --j) {
+            const double f = (double)j / az2;
+            const double nr = (er * zr + ei * zi) * f, ni = (ei * zr - er * zi) * f;
+            er = nr;
+            ei = ni;
+            put(j - 1, er, ei);
+        }
+        er = e0r;
+        ei = e0i;
+        for (int j = j0 + 1; j <= J; ++j) {
             const double nr = (er * zr - ei * zi) / j, ni = (er * zi + ei * zr) / j;
             er = nr;
             ei = ni;
-        }
-        if (j < D) {
-            P.w[j] = er;
-            P.wi[j] = ei;
-        } else {
-            tr += er;
-            ti += ei;
+            put(j, er, ei);
         }
     }
     // R_k = sum_{j > k} E_j, downwards from k = D-1; alpha^{-(k+1)} upwards
@@ -293,23 +331,23 @@ __global__ void k_pois_weights(const PoisWeights* __restrict__ tab) {
 }
 
 template <int NX, bool TWO>
-hipError_t pois_launch(const PoisEntry* tab, int count, int blocks, hipStream_t s) {
-    k_pois2d<NX, TWO><<<blocks, BNT, 0, s>>>(tab, count);
+hipError_t pois_launch(const PoisEntry* tab, int count, int blocks, int pass, hipStream_t s) {
+    k_pois2d<NX, TWO><<<blocks, BNT, 0, s>>>(tab, count, pass);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_pois2d(const PoisEntry* tab, int count, int total_blocks, int nx, int two,
-                         hipStream_t s) {
+                         int pass, hipStream_t s) {
     if (count <= 0 || total_blocks <= 0) return hipSuccess;
     switch (nx) {
-        case 64: return two ? pois_launch<64, true>(tab, count, total_blocks, s)
-                            : pois_launch<64, false>(tab, count, total_blocks, s);
-        case 128: return two ? pois_launch<128, true>(tab, count, total_blocks, s)
-                             : pois_launch<128, false>(tab, count, total_blocks, s);
-        case 256: return two ? pois_launch<256, true>(tab, count, total_blocks, s)
-                             : pois_launch<256, false>(tab, count, total_blocks, s);
+        case 64: return two ? pois_launch<64, true>(tab, count, total_blocks, pass, s)
+                            : pois_launch<64, false>(tab, count, total_blocks, pass, s);
+        case 128: return two ? pois_launch<128, true>(tab, count, total_blocks, pass, s)
+                             : pois_launch<128, false>(tab, count, total_blocks, pass, s);
+        case 256: return two ? pois_launch<256, true>(tab, count, total_blocks, pass, s)
+                             : pois_launch<256, false>(tab, count, total_blocks, pass, s);
         default: return hipErrorInvalidValue;
     }
 }

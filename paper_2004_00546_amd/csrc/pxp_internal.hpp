@@ -244,8 +244,8 @@ constexpr int KRYLOV2D_BLOCK = 1024;
 // out = sum + partner and out2 = sum2 + out2_add.
 constexpr int POIS_PASS_TERMS = 16;
 struct PoisEntry {
-    const double* tin;       // N^{k0} x (the input vector x when k0 == 0)
-    double* tout;            // N^{k1} x (non-final pass)
+    const double* x;         // input vectors (vector v at x + v sx)
+    double* tb[2];           // term vectors N^k x between passes (+ v n)
     const double* partner;   // added to the final first sum (nullable)
     double* acc;             // first sum between passes
     double* out;             // final first sum (nullable: not wanted)
@@ -253,23 +253,28 @@ struct PoisEntry {
     double* acc2;            // second sum between passes (two-sum launches)
     double* out2;            // final second sum
     const double* out2_add;  // added to the final second sum (nullable)
+    const double* out2_add2; // a second vector added to it (nullable)
+    int64_t s_add;           // vector stride of both added vectors
     const double* wtab2;     // weights of the second sum
     // phase form of the second sum's weights (nullable): vector v of the
     // entry weighs term k by sin(ph_v) wtab2[k] + cos(ph_v) wtab2i[k],
     // ph_v = ph0 + v dph (integrals of pieces that start at different times)
     const double* wtab2i;
     double ph0, dph;
-    int64_t s_tin, s_tout, s_partner, s_acc, s_out;
+    int64_t sx, s_partner, s_acc, s_out;
     double lam;              // Poisson parameter mu * tau
     double est;              // a priori truncation bound (reported)
     Sten5 N;                 // I + A / mu
-    int k0, k1, final_pass, nvec;
+    int D, nvec;             // terms; vectors of the entry
     int nx, ny, rows, blk0;  // rows: output rows per band (16 or 32)
     DevStatus* status;
     InstStat* irep;          // the instance's statistics (nullable)
 };
+// Pass `pass` (terms 16 pass .. 16 pass + 15) of the first `count` entries
+// of a table (the entries still running: a table lists its entries by
+// falling term count, blk0 their prefix sums).
 hipError_t launch_pois2d(const PoisEntry* tab, int count, int total_blocks, int nx, int two,
-                         hipStream_t s);
+                         int pass, hipStream_t s);
 // Weight table of the time integral int_0^h sin(phi - omega s) exp(s A) x ds
 // of one uniformised exponential: w[k], k < D, so that the integral is
 // sum_k w_k N^k x (lam = mu h); wi is scratch of D doubles.  split != 0:

@@ -144,18 +144,21 @@ k_cost_part(const RedDesc* __restrict__ tab, int count, double* __restrict__ par
     if (threadIdx.x == 0) part[d.part0 + c] = s;
 }
 
-// Batched cost, phase 2: one block per instance, partials in chunk order.
+// Batched cost, phase 2: one wave per instance; lane l sums partials l,
+// l+64, ... in order, then the lanes combine in a fixed pattern.
 __global__ void __launch_bounds__(64)
 k_cost_fin(const RedDesc* __restrict__ tab, const double* __restrict__ part) {
     const RedDesc& d = tab[blockIdx.x];
-    if (threadIdx.x != 0) return;
+    const int l = threadIdx.x;
     double s = 0.0, r = 0.0;
     if (d.ipart) {
-        for (int c = 0; c < d.ichunks; ++c) s += d.ipart[c];
+        for (int c = l; c < d.ichunks; c += WAVE) s += d.ipart[c];
+        s = wave_sum(s);
     } else {
-        for (int c = 0; c < d.chunks; ++c) s += part[d.part0 + c];
-        s *= 0.5;
+        for (int c = l; c < d.chunks; c += WAVE) s += part[d.part0 + c];
+        s = 0.5 * wave_sum(s);
     }
+    if (l != 0) return;
     for (int k = 0; k < d.K; ++k) r += d.a[k] * d.a[k];
     *d.J = s + d.beta * r;
     // every method's q(T) passes through here
