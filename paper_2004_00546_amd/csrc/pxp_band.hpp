@@ -2,8 +2,8 @@
 // uniformised exponentials): 8 waves, wave w holds region rows 8w .. 8w+7
 // of a 64-row region, lane l columns l*CPL .. l*CPL+CPL-1 (CPL = NX/64), so a
 // wave row is a whole periodic grid row: x neighbours are the adjacent lanes
-// (wrapping), y neighbours the same lane's registers except at the wave's
-// first and last rows, which go through LDS.
+// (wrapping; wave-wide DPP rotates), y neighbours the same lane's registers
+// except at the wave's first and last rows, which go through LDS.
 #pragma once
 #include "pxp_internal.hpp"
 #include "pxp_device.hpp"
@@ -43,6 +43,26 @@ __device__ __forceinline__ void wave_rows(int g0, int ny, int (&g)[BRW]) {
         g[i] = r >= ny ? r - ny : r;
     }
 }
+
+// x neighbours of a lane's edge columns across the wave (the row is periodic
+// and spans the wave): wave-wide DPP rotates, two 32-bit moves per double,
+// every lane active.  wave_ror:1 hands lane l the value of lane l-1 (lane 0:
+// lane 63), wave_rol:1 that of lane l+1 (lane 63: lane 0).
+__device__ __forceinline__ double dpp_rot(double v, bool from_west) {
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+    int rlo, rhi;
+    if (from_west) {
+        rlo = __builtin_amdgcn_update_dpp(0, lo, 0x13C, 0xF, 0xF, false);
+        rhi = __builtin_amdgcn_update_dpp(0, hi, 0x13C, 0xF, 0xF, false);
+    } else {
+        rlo = __builtin_amdgcn_update_dpp(0, lo, 0x134, 0xF, 0xF, false);
+        rhi = __builtin_amdgcn_update_dpp(0, hi, 0x134, 0xF, 0xF, false);
+    }
+    return __longlong_as_double((long long)(unsigned)rlo | ((long long)rhi << 32));
+}
+__device__ __forceinline__ double from_west(double v) { return dpp_rot(v, true); }
+__device__ __forceinline__ double from_east(double v) { return dpp_rot(v, false); }
 
 // CPL consecutive doubles of one grid row (16-byte loads and stores where
 // CPL is even).

@@ -153,7 +153,6 @@ k_pois2d(const PoisEntry* __restrict__ tab, int count, int pass) {
     }
     // N = I + A/mu has a zero diagonal for mu = -A.c
     const double Nw = E.N.w, Ne = E.N.e, Ns = E.N.s, Nn = E.N.n;
-    const int lw = (l + WAVE - 1) & (WAVE - 1), le = (l + 1) & (WAVE - 1);
     __syncthreads();  // weights visible
     for (int j = 0; j < nterm; ++j) {
         const double pj = wt[j];
@@ -176,8 +175,8 @@ k_pois2d(const PoisEntry* __restrict__ tab, int count, int pass) {
             double cur[CPL];
 #pragma unroll
             for (int c = 0; c < CPL; ++c) cur[c] = tv[i][c];
-            const double wv = __shfl(cur[CPL - 1], lw, WAVE);
-            const double ev = __shfl(cur[0], le, WAVE);
+            const double wv = from_west(cur[CPL - 1]);
+            const double ev = from_east(cur[0]);
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 const double xw = (c > 0) ? cur[c - 1] : wv;

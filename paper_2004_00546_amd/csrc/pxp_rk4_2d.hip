@@ -53,14 +53,13 @@ __device__ __forceinline__ void fwd_level(const double (&y)[BRW][CPL], double (&
     double prev[CPL], dn[CPL];
     exchange_edges<NX, CPL>(xch, v, w, cb, prev, dn);
     if (!active) return;
-    const int lw = (l + WAVE - 1) & (WAVE - 1), le = (l + 1) & (WAVE - 1);
 #pragma unroll
     for (int i = 0; i < BRW; ++i) {
         double cur[CPL];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) cur[c] = v[i][c];
-        const double wv = __shfl(cur[CPL - 1], lw, WAVE);
-        const double ev = __shfl(cur[0], le, WAVE);
+        const double wv = from_west(cur[CPL - 1]);
+        const double ev = from_east(cur[0]);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             const double xw = (c > 0) ? cur[c - 1] : wv;
@@ -208,15 +207,14 @@ __device__ __forceinline__ void rev_power(double (&w_)[BRW][CPL], double (&ln)[B
     double prev[CPL], dn[CPL];
     exchange_edges<NX, CPL>(xch, w_, w, cb, prev, dn);
     if (!active) return;
-    const int lw = (l + WAVE - 1) & (WAVE - 1), le = (l + 1) & (WAVE - 1);
 #pragma unroll
     for (int i = 0; i < BRW; ++i) {
         const int r = w * BRW + i;
         double cur[CPL];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) cur[c] = w_[i][c];
-        const double wv = __shfl(cur[CPL - 1], lw, WAVE);
-        const double ev = __shfl(cur[0], le, WAVE);
+        const double wv = from_west(cur[CPL - 1]);
+        const double ev = from_east(cur[0]);
         const bool orow = TRACK && r >= off && r < off + R;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
