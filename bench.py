@@ -454,7 +454,7 @@ def measure(args, name, torch, _lib, api, workloads, steps, serial_steps, with_o
     models = class_models(insts, pxp.problems, args, counters)
     traffic = {}
     if inst["op"] == "advdiff2d_upwind":
-        tr = profiled_traffic("k_pois2d_tree", "advdiff2d_256_kernels.md", "pxp_expo2d.hip")
+        tr = profiled_traffic("k_pois2d_tree", "%s_kernels.md" % name, "pxp_expo2d.hip")
         if tr is not None:
             traffic["krylov_direct"] = tr
     elif name == SECONDARY_WORKLOAD:
