@@ -206,7 +206,15 @@ pxp_status paraexp_direct(const pxp_problem* pb, int32_t batch,
  *   Lambda  [sum n]  output int_0^T sin(omega t) q^dagger(t) dt (nullable)
  * Burgers instances read the checkpoints that the preceding paraexp_direct
  * call left in the same workspace (the workspace holds them, not a caller
- * array: a second direct call on that workspace replaces them). */
+ * array: a second direct call on that workspace replaces them).  Their
+ * time-varying adjoint is propagated by fourth-order commutator-free Magnus
+ * steps, one per slice; where a slice has an even number of RK4 steps the
+ * call also estimates the steps' own error a posteriori: on the first and
+ * the last slice (in reversed time) one step and two half steps of lamT,
+ * 16/15 |difference| / |two half steps| (the Richardson estimate of a
+ * fourth-order step, in FP64 whatever prec says).  It enters the device
+ * status like the Krylov estimates: the largest estimate, and
+ * PXP_EKRYLOV_NOCONV above krylov_tol. */
 pxp_status paraexp_adjoint(const pxp_problem* pb, int32_t batch,
                            const double* lamT, const double* jI_src, double* lam0,
                            double* Lambda, void* ws, size_t ws_bytes, void* stream);
@@ -318,7 +326,8 @@ enum {
     PXP_K_LTV_NODES = 6,       /* per-slice recompute of the Magnus states  */
     PXP_K_SOURCES = 7,         /* integral cost: march of every slice from its
                                   corrected start writing the step sources   */
-    PXP_K_ADJ_SLICES = 8       /* integral cost: adjoint slices with sources */
+    PXP_K_ADJ_SLICES = 8,      /* integral cost: adjoint slices with sources */
+    PXP_K_LTV_CHECK = 9        /* a posteriori error of the Magnus steps    */
 };
 pxp_status pxp_profile_enable(int32_t on);
 pxp_status pxp_profile_read(int32_t kernel_class, double* total_ms,

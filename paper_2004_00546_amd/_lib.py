@@ -38,7 +38,8 @@ EXPORTED = ("pxp_workspace_size", "pxp_workspace_init", "paraexp_direct",
             "pxp_last_report")
 KCLASS = {"slices": 0, "krylov_direct": 1, "krylov_adjoint": 2,
           "serial_direct": 3, "serial_reverse": 4, "ltv_adjoint": 5,
-          "ltv_nodes": 6, "sources": 7, "adj_slices": 8}
+          "ltv_nodes": 6, "sources": 7, "adj_slices": 8,
+          "ltv_check": 9}
 
 
 class pxp_problem(ctypes.Structure):

@@ -27,6 +27,7 @@ inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
     size_t status;             // DevStatus
     size_t btab, ktab, t2d;    // batch tables: Burgers, Krylov, 2D marches
+    size_t kchk, mtab;         // Magnus check: chains, estimate descriptors
     size_t ptab, pwt;          // uniformised exponentials: pass entries, weights
     size_t ptab_entries;       // capacity of the pass-entry table
     size_t rtab, rpart;        // batched cost/gradient: descriptors, partial sums
@@ -43,6 +44,9 @@ struct Inst {
     // states, Lambda shares (slices then tree pairs), cost partials, weight
     // tables of the adjoint tree
     size_t gsrc, lev, ebuf, islot, cpart, iwtab;
+    // Burgers: Magnus check node states (two samples x two half steps x two
+    // vectors) and results (one step, two half steps per sample)
+    size_t mnodes, mout, mdesc;
     size_t size;
 };
 
@@ -493,6 +497,9 @@ Inst inst_layout(const pxp_problem& p) {
         L.ckpt = take(((size_t)p.n_steps / c + 1) * n * d);
         L.seg = take(c * n * d);
         L.nodes = take(2 * P * n * d);
+        L.mnodes = take(8 * n * d);
+        L.mout = take(4 * n * d);
+        L.mdesc = take(sizeof(MagnusCheck));
         // basis, then the shift-and-invert factors of the time-varying
         // operator (5 n + 5 B doubles, B <= 512)
         L.basis = take(((m + 6) * n + 5 * 512) * d);
@@ -506,10 +513,16 @@ Layout layout(const pxp_problem* pb, int batch) {
     size_t off = 0;
     Ly.status = off;
     off += align_up(sizeof(DevStatus));
+    // Burgers descriptors: the instances, then two Magnus-check node jobs
+    // per instance
     Ly.btab = off;
-    off += align_up((size_t)batch * sizeof(BurgersDesc));
+    off += align_up((size_t)batch * 3 * sizeof(BurgersDesc));
     Ly.ktab = off;
     off += align_up((size_t)batch * sizeof(KrylovArgs));
+    Ly.kchk = off;
+    off += align_up((size_t)batch * 4 * sizeof(KrylovArgs));
+    Ly.mtab = off;
+    off += align_up((size_t)batch * sizeof(MagnusCheck));
     Ly.t2d = off;
     off += align_up((size_t)batch * sizeof(Band2D));
     // at most four entries per instance in one pass launch (pairs of two
@@ -845,6 +858,52 @@ pxp_status direct_burgers(const Ctx& c, const double* q0, double* qT) {
     return PXP_OK;
 }
 
+// The Magnus steps' own error is estimated on two sampled macro steps (the
+// first and the last in reversed time) by one step against two half steps
+// of lamT; the half steps need an even number of RK4 steps per slice (no
+// estimate otherwise).
+bool magnus_checkable(const pxp_problem& p) {
+    const int64_t S = p.n_steps / p.P;
+    return S >= 2 && S % 2 == 0;
+}
+
+// Sampled macro step k (0, 1) of the check.
+int magnus_sample(const pxp_problem& p, int k) { return k == 0 ? 0 : p.P - 1; }
+
+// The four check chains of one instance from its main chain's arguments a
+// (kind 2k: one step of sample k, kind 2k+1: its two half steps).
+KrylovArgs magnus_check_args(const Ctx& c, const KrylovArgs& a, int kind) {
+    const int64_t n = c.n();
+    const int k = kind / 2, q = magnus_sample(c.p, k);
+    const double D = (double)(c.p.n_steps / c.p.P) * c.dt();
+    KrylovArgs b = a;
+    // in FP64 also for FP32-bulk problems: the difference of the two
+    // propagations is then the Magnus error, not the FP32 stencil's rounding
+    b.fp32 = 0;
+    b.yout = c.at(c.L.mout) + (size_t)kind * n;
+    if (kind % 2 == 0) {
+        b.npieces = 1;
+        b.wop = c.at(c.L.nodes) + (size_t)(2 * q) * n;
+        b.tau = 0.5 * D;
+    } else {
+        b.npieces = 2;
+        b.wop = c.at(c.L.mnodes) + (size_t)(4 * k) * n;
+        b.tau = 0.25 * D;
+    }
+    return b;
+}
+
+MagnusCheck magnus_check_desc(const Ctx& c) {
+    MagnusCheck m{};
+    m.y = c.at(c.L.mout);
+    m.n = c.n();
+    m.nsamp = 2;
+    m.tol = c.p.krylov_tol;
+    m.st = c.st;
+    m.irep = c.irep;
+    return m;
+}
+
 pxp_status adjoint_burgers(const Ctx& c, const double* lamT, double* lam0,
                            int method) {
     if (method == PXP_METHOD_SERIAL) {
@@ -878,8 +937,25 @@ pxp_status adjoint_burgers(const Ctx& c, const double* lamT, double* lam0,
     a.wop = c.at(c.L.nodes);
     a.inv2h = 1.0 / (2.0 * h);
     a.nuh2 = c.p.nu / (h * h);
-    ProfScope ps(PXP_K_LTV_ADJOINT, c.s);
-    HIPCHK(launch_krylov1d(a, c.p.kblock, c.s));
+    {
+        ProfScope ps(PXP_K_LTV_ADJOINT, c.s);
+        HIPCHK(launch_krylov1d(a, c.p.kblock, c.s));
+    }
+    if (!magnus_checkable(c.p)) return PXP_OK;
+    // the a posteriori Magnus check: half-step nodes of the two sampled
+    // macro steps, one and two steps from lamT, the Richardson estimate
+    ProfScope ps(PXP_K_LTV_CHECK, c.s);
+    for (int k = 0; k < 2; ++k)
+        HIPCHK(launch_burgers_nodes(c.at(c.L.ckpt), c.at(c.L.mnodes) + (size_t)(4 * k) * c.n(),
+                                    c.n(), c.p.n_steps, c.p.ckpt_every, S / 2, c.dt(), c.p.nu,
+                                    c.p.L, c.p.block, c.fp32(), c.s,
+                                    2 * magnus_sample(c.p, k), 2));
+    for (int kind = 0; kind < 4; ++kind)
+        HIPCHK(launch_krylov1d(magnus_check_args(c, a, kind), c.p.kblock, c.s));
+    const MagnusCheck m = magnus_check_desc(c);
+    auto* dm = reinterpret_cast<MagnusCheck*>(c.at(c.L.mdesc));
+    HIPCHK(launch_upload(dm, &m, sizeof(m), c.s));
+    HIPCHK(launch_magnus_check(dm, 1, c.s));
     return PXP_OK;
 }
 
@@ -1046,6 +1122,72 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
         ProfScope ps(PXP_K_LTV_NODES, s);
         HIPCHK(launch_burgers_batch(2, dtab, (int)tab.size(), q0, bb.fp32, s));
     }
+    // Magnus check of the instances that allow it: half-step nodes of the
+    // two sampled macro steps (one job each, after the instances' own
+    // descriptors), then per workgroup-size group and kind one chain launch
+    // right after the group's main chains (the same basis), then the
+    // estimates
+    std::vector<int> chk(order.size(), 0);
+    std::vector<BurgersDesc> ctab;
+    std::vector<KrylovArgs> cks;  // group-major, then kind, then instance
+    std::vector<MagnusCheck> mt;
+    struct CLaunch {
+        size_t first;
+        int count, block;
+        size_t group;
+    };
+    std::vector<CLaunch> cl;
+    {
+        int cq0 = 0;
+        for (size_t j = 0; j < bb.idx.size(); ++j) {
+            const pxp_problem& p = pb[bb.idx[j]];
+            if (!magnus_checkable(p)) continue;
+            Ctx c = make_ctx(p, ws, Ly, bb.idx[j], s);
+            for (int k = 0; k < 2; ++k) {
+                BurgersDesc d = tab[j];
+                d.S = tab[j].S / 2;
+                d.nodes = c.at(c.L.mnodes) + (size_t)(4 * k) * c.n();
+                d.qbase = 2 * magnus_sample(p, k);
+                d.q0 = cq0;
+                cq0 += 2;
+                ctab.push_back(d);
+            }
+            mt.push_back(magnus_check_desc(c));
+        }
+        size_t g = 0;
+        for (size_t j0 = 0; j0 < order.size(); ++g) {
+            size_t j1 = j0;
+            while (j1 < order.size() && kB[order[j1]] == kB[order[j0]]) ++j1;
+            for (int kind = 0; kind < 4; ++kind) {
+                const size_t first = cks.size();
+                for (size_t e = j0; e < j1; ++e) {
+                    const int j = order[e];
+                    const pxp_problem& p = pb[bb.idx[j]];
+                    if (!magnus_checkable(p)) continue;
+                    Ctx c = make_ctx(p, ws, Ly, bb.idx[j], s);
+                    cks.push_back(magnus_check_args(c, ktab[j], kind));
+                }
+                if (cks.size() > first)
+                    cl.push_back({first, (int)(cks.size() - first), kB[order[j0]], g});
+            }
+            j0 = j1;
+        }
+        if (!ctab.empty()) {
+            auto* dc = dtab + tab.size();
+            HIPCHK(launch_upload(dc, ctab.data(), ctab.size() * sizeof(BurgersDesc), s));
+            auto* kc = reinterpret_cast<KrylovArgs*>(static_cast<char*>(ws) + Ly.kchk);
+            const size_t bytes = cks.size() * sizeof(KrylovArgs);
+            for (size_t o = 0; o < bytes; o += 3072)
+                HIPCHK(launch_upload(reinterpret_cast<char*>(kc) + o,
+                                     reinterpret_cast<const char*>(cks.data()) + o,
+                                     std::min((size_t)3072, bytes - o), s));
+            auto* dm = reinterpret_cast<MagnusCheck*>(static_cast<char*>(ws) + Ly.mtab);
+            HIPCHK(launch_upload(dm, mt.data(), mt.size() * sizeof(MagnusCheck), s));
+            ProfScope ps(PXP_K_LTV_CHECK, s);
+            HIPCHK(launch_burgers_batch(2, dc, (int)ctab.size(), cq0, bb.fp32, s));
+        }
+    }
+    auto* kc = reinterpret_cast<KrylovArgs*>(static_cast<char*>(ws) + Ly.kchk);
     ProfScope ps(PXP_K_LTV_ADJOINT, s);
     // the first group on the caller's stream, the others on the side stream
     // (when it exists) so that the groups' chains run concurrently
@@ -1065,16 +1207,23 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
         HIPCHK(hipEventRecord(side.fork, s));
         HIPCHK(hipStreamWaitEvent(side.st, side.fork, 0));
     }
-    for (size_t j0 = 0; j0 < order.size();) {
+    size_t g = 0;
+    for (size_t j0 = 0; j0 < order.size(); ++g) {
         size_t j1 = j0;
         while (j1 < order.size() && kB[order[j1]] == kB[order[j0]]) ++j1;
         const hipStream_t sg = (j0 > 0 && forked) ? side.st : s;
         HIPCHK(launch_krylov_ltv_batch(kt + j0, kB[order[j0]], (int)(j1 - j0), lds, sg));
+        for (const CLaunch& x : cl)
+            if (x.group == g) HIPCHK(launch_krylov_ltv_batch(kc + x.first, x.block, x.count, lds, sg));
         j0 = j1;
     }
     if (forked) {
         HIPCHK(hipEventRecord(side.join, side.st));
         HIPCHK(hipStreamWaitEvent(s, side.join, 0));
+    }
+    if (!mt.empty()) {
+        auto* dm = reinterpret_cast<MagnusCheck*>(static_cast<char*>(ws) + Ly.mtab);
+        HIPCHK(launch_magnus_check(dm, (int)mt.size(), s));
     }
     return PXP_OK;
 }

@@ -85,9 +85,25 @@ hipError_t launch_rk4_burgers_reverse(const double* ckpt, const double* lamT,
 // Effective states of the two commutator-free Magnus factors of each macro
 // step of S steps (W[2q], W[2q+1], q < n_t / S), recomputed from the
 // checkpoints (every c steps) in parallel over macro steps.
+// Macro steps qbase .. qbase+count-1 (count < 0: all from qbase) into
+// slots 0 .. count-1 of W (two vectors per slot).
 hipError_t launch_burgers_nodes(const double* ckpt, double* W, int n, int64_t n_t,
                                 int64_t c, int64_t S, double dt, double nu, double L,
-                                int block, int fp32, hipStream_t s);
+                                int block, int fp32, hipStream_t s, int qbase = 0,
+                                int count = -1);
+// A posteriori error of the commutator-free Magnus steps: per instance, for
+// nsamp sampled macro steps, y[2k] = one step and y[2k+1] = two half steps
+// of the same vector; est = 16/15 |y[2k] - y[2k+1]| / |y[2k+1]| (the
+// fourth-order Richardson estimate of the one-step error, relative), the
+// largest over the samples raises max_est and, above tol, ST_NOCONV.
+struct MagnusCheck {
+    const double* y;
+    int n, nsamp;
+    double tol;
+    DevStatus* st;
+    InstStat* irep;
+};
+hipError_t launch_magnus_check(const MagnusCheck* tab, int count, hipStream_t s);
 
 // ---- ragged Burgers batches ----------------------------------------------------
 // One descriptor per instance (device table in the workspace, written by
@@ -96,6 +112,7 @@ struct BurgersDesc {
     int n, pt, q0, pt_rev;   // q0: prefix count of macro steps (nodes grid);
                              // pt_rev: points per thread of the 512-thread
                              // reverse sweep (0: not available)
+    int qbase, pad;          // nodes: first macro step (its slot is 0)
     int64_t n_t, c, S;
     double dt, inv2h, nuh2;
     const double* y0;

@@ -255,6 +255,44 @@ hipError_t launch_grad(const double* basis, const double* v, const double* a,
     return hipGetLastError();
 }
 
+// One block per instance: the Richardson estimate of each sampled Magnus
+// step, sums in a fixed order.
+__global__ void __launch_bounds__(256) k_magnus_check(const MagnusCheck* __restrict__ tab) {
+    __shared__ double red[80];
+    const MagnusCheck& d = tab[blockIdx.x];
+    double est = 0.0;
+    int slot = 0;
+    for (int k = 0; k < d.nsamp; ++k) {
+        const double* a = d.y + (size_t)(2 * k) * d.n;
+        const double* b = a + d.n;
+        double dd = 0.0, bb = 0.0;
+        for (int i = threadIdx.x; i < d.n; i += blockDim.x) {
+            const double e = a[i] - b[i];
+            dd += e * e;
+            bb += b[i] * b[i];
+        }
+        block_sum2(dd, bb, red, slot);
+        const double e = bb > 0.0 ? (16.0 / 15.0) * sqrt(dd / bb) : 0.0;
+        est = fmax(est, e);
+    }
+    if (threadIdx.x != 0) return;
+    bool bad = !isfinite(est);
+    if (bad) est = INFINITY;
+    const unsigned long long eb = (unsigned long long)__double_as_longlong(est);
+    if (d.st) {
+        atomicMax(&d.st->max_est, eb);
+        if (bad) atomicOr(&d.st->flags, ST_NONFINITE);
+        else if (est > d.tol) atomicOr(&d.st->flags, ST_NOCONV);
+    }
+    if (d.irep) atomicMax(&d.irep->max_est, eb);
+}
+
+hipError_t launch_magnus_check(const MagnusCheck* tab, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    k_magnus_check<<<count, 256, 0, s>>>(tab);
+    return hipGetLastError();
+}
+
 hipError_t launch_recombine(const double* q0, const double* vlast,
                             const double* Y, int np, int n, double* out,
                             DevStatus* st, hipStream_t s) {

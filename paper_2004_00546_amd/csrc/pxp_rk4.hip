@@ -642,7 +642,7 @@ template <int PT, typename R>
 __device__ __forceinline__ void dev_burgers_nodes(const double* __restrict__ ckpt,
                                                   double* __restrict__ Wout, int n,
                                                   int64_t n_t, int64_t c, int64_t S,
-                                                  double dt, BurgersC bc, int q,
+                                                  double dt, BurgersC bc, int q, int qw,
                                                   double* lds_d) {
     R* lds = reinterpret_cast<R*>(lds_d);
     const int base = threadIdx.x * PT;
@@ -706,8 +706,8 @@ __device__ __forceinline__ void dev_burgers_nodes(const double* __restrict__ ckp
         rhs(k1);
         hermite(th1, U1);
     }
-    double* w1 = Wout + (size_t)(2 * q) * n;
-    double* w2 = Wout + (size_t)(2 * q + 1) * n;
+    double* w1 = Wout + (size_t)(2 * qw) * n;
+    double* w2 = Wout + (size_t)(2 * qw + 1) * n;
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
         w1[base + i] = 2.0 * (a2 * U1[i] + a1 * U2[i]);
@@ -718,9 +718,11 @@ __device__ __forceinline__ void dev_burgers_nodes(const double* __restrict__ ckp
 template <int PT, typename R>
 __global__ void __launch_bounds__(max_block<PT>())
 k_burgers_nodes(const double* __restrict__ ckpt, double* __restrict__ Wout, int n,
-                int64_t n_t, int64_t c, int64_t S, double dt, BurgersC bc) {
+                int64_t n_t, int64_t c, int64_t S, double dt, BurgersC bc, int qbase) {
     extern __shared__ double lds_d[];
-    dev_burgers_nodes<PT, R>(ckpt, Wout, n, n_t, c, S, dt, bc, blockIdx.x, lds_d);
+    // macro step qbase + b into output slot b
+    dev_burgers_nodes<PT, R>(ckpt, Wout, n, n_t, c, S, dt, bc, qbase + (int)blockIdx.x,
+                             (int)blockIdx.x, lds_d);
 }
 
 // ---- ragged batches: one launch over all instances -------------------------
@@ -789,7 +791,7 @@ __global__ void __launch_bounds__(256) k_burgers_nodes_batch(const BurgersDesc* 
     const BurgersC bc{d.inv2h, d.nuh2};
     const int q = (int)blockIdx.x - d.q0;
     PXP_BATCH_SWITCH(dev_burgers_nodes, R, d.ckpt, d.nodes, d.n, d.n_t, d.c, d.S, d.dt,
-                     bc, q, lds_d)
+                     bc, d.qbase + q, q, lds_d)
 }
 
 // Threads per workgroup and points per thread for an n-point march: by
@@ -923,7 +925,8 @@ hipError_t launch_rk4_burgers_direct(const double* y0, double* yT, double* ckpt,
 
 hipError_t launch_burgers_nodes(const double* ckpt, double* W, int n, int64_t n_t,
                                 int64_t c, int64_t S, double dt, double nu, double L,
-                                int block_hint, int fp32, hipStream_t s) {
+                                int block_hint, int fp32, hipStream_t s, int qbase,
+                                int count) {
     int block, pt;
     if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
     if (S <= 0 || n_t % S) return hipErrorInvalidValue;
@@ -931,8 +934,10 @@ hipError_t launch_burgers_nodes(const double* ckpt, double* W, int n, int64_t n_
     BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
     const size_t lds = sizeof(double) * 4 * block;
     const int Q = (int)(n_t / S);
+    if (count < 0) count = Q - qbase;
+    if (qbase < 0 || count <= 0 || qbase + count > Q) return hipErrorInvalidValue;
     PXP_DISPATCH(fp32, pt, k_burgers_nodes,
-                 <<<Q, block, lds, s>>>(ckpt, W, n, n_t, c, S, dt, bc))
+                 <<<count, block, lds, s>>>(ckpt, W, n, n_t, c, S, dt, bc, qbase))
     return hipGetLastError();
 }
 

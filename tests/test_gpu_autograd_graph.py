@@ -26,7 +26,9 @@ def test_autograd_matches_oracle(torch, orc, wl, krylov):
     inst = workloads.make(wl)[0]
     # the 30-dimensional shift-and-invert space reaches about 1e-9 on the
     # longest N=128 pieces (mild stiffness converges slowest)
-    prob = Problem(inst, krylov=krylov, tol=1e-8 if krylov == "shift_invert" else 1e-10)
+    # (Burgers: the Magnus check estimates 1e-10 for the workload's slices)
+    prob = Problem(inst, krylov=krylov, tol=1e-8 if krylov == "shift_invert" else
+                   (1e-9 if wl.startswith("burgers") else 1e-10))
     a = torch.tensor(inst["a"], dtype=torch.float64, device="cuda:0", requires_grad=True)
     J = paraexp_loss(a, prob)
     (3.0 * J).backward()
@@ -128,7 +130,7 @@ def test_autograd_two_forwards_then_backward(torch, orc):
     both: each backward must read its own forward's checkpoints."""
     from paper_2004_00546_amd.autograd import Problem, paraexp_loss
     base = workloads.make("burgers1d_n2048")[0]
-    inst = workloads.scaled(base, n_steps=1024, T=0.25, P=16)
+    inst = workloads.scaled(base, n_steps=1024, T=0.25, P=64)
     prob = Problem(inst, krylov="auto", tol=1e-10)
     a1 = torch.tensor(inst["a"], dtype=torch.float64, device="cuda:0", requires_grad=True)
     a2v = np.asarray(inst["a"]) * -1.5 + 0.01

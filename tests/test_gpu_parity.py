@@ -300,11 +300,13 @@ def test_burgers_serial_matches_oracle_to_rounding(torch, orc, ckpt):
 
 
 # The Magnus macro step is one slice; its fourth-order error needs slices of
-# at most 64 RK4 steps here (P = 4, i.e. 256 steps, measures 9e-7).
+# at most 64 RK4 steps here (P = 4, i.e. 256 steps, measures 9e-7).  The
+# a posteriori Magnus check estimates up to 1.3e-8 at P = 16 (the adjoint's
+# actual error 3.8e-9): the piece tolerance 1e-7 lets every P pass it.
 @pytest.mark.parametrize("P", [16, 32, 64])
 def test_burgers_paraexp_small(torch, orc, P):
     inst = small_burgers(P=P)
-    got = run(inst, "paraexp", krylov="poly")
+    got = run(inst, "paraexp", krylov="poly", tol=1e-7)
     want = orc.gradient(inst)
     el, eg = rel(got["lam"], want["lam0"]), rel(got["grad"], want["grad"])
     say("burgers paraexp P=%d: lam0 %.2e grad %.2e st %d est %.1e" % (P, el, eg, got["status"], got["est"]))
@@ -313,10 +315,51 @@ def test_burgers_paraexp_small(torch, orc, P):
     assert el < FP64_GATE and eg < FP64_GATE
 
 
+def test_magnus_check_flags_long_slices(torch, orc):
+    """The a posteriori Magnus check: one macro step against two half steps
+    of lambda_T on the first and the last slice, the fourth-order Richardson
+    estimate of the step's relative error.  At a 1e-9 piece tolerance,
+    slices of 256 and 64 RK4 steps are flagged as not converged and the
+    estimate follows the adjoint's actual error (within a factor 10); slices
+    of 16 steps pass."""
+    inst = small_burgers()
+    want = orc.gradient(inst)
+    for P, flagged in [(4, True), (16, True), (64, False)]:
+        got = run(dict(inst, P=P), "paraexp", krylov="poly", tol=1e-9)
+        e = rel(got["lam"], want["lam0"])
+        say("magnus check P=%d: adjoint error %.2e estimate %.2e status %d"
+            % (P, e, got["est"], got["status"]))
+        assert (got["status"] == _lib.PXP_EKRYLOV_NOCONV) == flagged
+        if flagged:
+            assert 0.1 * e <= got["est"] <= 10.0 * e
+
+
+def test_magnus_check_batched_per_instance(torch, orc):
+    """The same check on the batched Burgers path: each instance's report
+    carries its own estimate, within a factor 20 of its adjoint's actual
+    error where the Magnus error dominates, and the batch status is
+    flagged at a 1e-9 tolerance."""
+    insts = ragged_burgers(seed=40)
+    r = api.GradientRunner(insts, method="paraexp", krylov="poly", tol=1e-9)
+    _lib.pxp_last_report(r.problems, r.ws)
+    r.run()
+    res = r.results()
+    rep = _lib.pxp_last_report(r.problems, r.ws)
+    code, _ = r.status()
+    assert code == _lib.PXP_EKRYLOV_NOCONV
+    for inst, b, x in zip(insts, res, rep):
+        e = rel(b["lam"], orc.gradient(inst)["lam0"])
+        say("batched magnus check n=%d P=%d: adjoint error %.2e estimate %.2e"
+            % (inst["nx"], inst["P"], e, x["max_est"]))
+        if e > 1e-9:
+            assert e / 20.0 <= x["max_est"] <= 20.0 * e
+
+
 def test_burgers_workload_n2048(torch, orc):
     inst = workloads.make("burgers1d_n2048")[0]
     want = orc.gradient(inst)
-    got = run(inst, "paraexp", krylov="poly")
+    # the Magnus check estimates 1e-10 here (adjoint error 2e-10)
+    got = run(inst, "paraexp", krylov="poly", tol=1e-9)
     el, eg = rel(got["lam"], want["lam0"]), rel(got["grad"], want["grad"])
     say("burgers n2048 paraexp: lam0 %.2e grad %.2e st %d est %.1e" % (el, eg, got["status"], got["est"]))
     assert got["status"] == 0
@@ -377,13 +420,14 @@ def ragged_burgers(seed=21):
 @pytest.mark.parametrize("method", ["paraexp", "serial"])
 def test_ragged_burgers_batch_equals_one_by_one(torch, method):
     insts = ragged_burgers()
-    r = api.GradientRunner(insts, method=method, krylov="poly")
+    # slices of four RK4 steps: Magnus estimates up to about 1e-8
+    r = api.GradientRunner(insts, method=method, krylov="poly", tol=1e-7)
     r.run()
     code, _ = r.status()
     assert code == 0
     batch = r.results()
     for inst, b in zip(insts, batch):
-        one = run(inst, method, krylov="poly")
+        one = run(inst, method, krylov="poly", tol=1e-7)
         assert np.array_equal(one["qT"], b["qT"])
         assert np.array_equal(one["grad"], b["grad"]), (inst["nx"], method)
 
@@ -483,14 +527,14 @@ def test_ragged_burgers_shift_invert_batch(torch, orc):
     the same Magnus factors); against the oracle with macro steps of two RK4
     steps, so that the Magnus error stays far below the gate."""
     insts = ragged_burgers(seed=60)
-    r = api.GradientRunner(insts, method="paraexp", krylov="shift_invert")
+    r = api.GradientRunner(insts, method="paraexp", krylov="shift_invert", tol=1e-7)
     r.run()
     code, _ = r.status()
     assert code == 0
     for inst, b in zip(insts, r.results()):
-        one = run(inst, "paraexp", krylov="shift_invert")
+        one = run(inst, "paraexp", krylov="shift_invert", tol=1e-7)
         assert np.array_equal(one["grad"], b["grad"]), inst["nx"]
-        poly = run(inst, "paraexp", krylov="poly")
+        poly = run(inst, "paraexp", krylov="poly", tol=1e-7)
         d = rel(b["grad"], poly["grad"])
         fine = dict(inst, P=inst["n_steps"] // 2)
         sif = run(fine, "paraexp", krylov="shift_invert")
@@ -508,13 +552,15 @@ def test_auto_flavour_ragged_equals_explicit_choice(torch):
     batched result equals the run with that flavour named explicitly."""
     insts = ragged_burgers(seed=70)
     insts[2] = dict(insts[2], P=insts[2]["n_steps"] // 64)  # long macro steps
-    r = api.GradientRunner(insts, method="paraexp", krylov="auto")
+    # (long macro steps: a loose piece tolerance keeps the Magnus check
+    # quiet; the test is about the flavour choice)
+    r = api.GradientRunner(insts, method="paraexp", krylov="auto", tol=1e-5)
     r.run()
     assert r.status()[0] == 0
     for inst, b in zip(insts, r.results()):
         h = inst["L"] / inst["nx"]
         si = 0.5 * inst["T"] / inst["P"] * 4 * inst["nu"] / h**2 > 64
-        one = run(inst, "paraexp", krylov="shift_invert" if si else "taylor")
+        one = run(inst, "paraexp", krylov="shift_invert" if si else "taylor", tol=1e-5)
         assert np.array_equal(one["grad"], b["grad"]), (inst["nx"], si)
 
 
@@ -561,10 +607,13 @@ def test_taylor_flavour_matches_oracle(torch, orc, case):
         inst = small_burgers(n=512, T=0.3, nt=128, P=32, nu=0.01, seed=9, ckpt=16)
     else:
         inst = workloads.make(case)[0]
-    got = run(inst, "paraexp", krylov="taylor")
+    # Burgers: the Magnus check estimates a little above 1e-10 for these
+    # slices (gradient error 9e-11), so the piece tolerance is 1e-9 there
+    got = run(inst, "paraexp", krylov="taylor",
+              tol=1e-9 if case == "burgers_small" else 1e-10)
     want = orc.gradient(inst)
     e = rel(got["grad"], want["grad"])
-    say("taylor %s: grad %.2e status %d" % (case, e, got["status"]))
+    say("taylor %s: grad %.2e status %d est %.1e" % (case, e, got["status"], got["est"]))
     assert got["status"] == 0
     assert e < FP64_GATE
 
@@ -593,7 +642,7 @@ def test_nan_input_sets_nonfinite_status(torch, case):
     assert code == _lib.PXP_ENONFINITE, (case, code)
     # the status is cleared by the read: a clean run reports OK again
     r2 = api.GradientRunner([dict(inst, q0=np.zeros(inst["nx"]))], method=method,
-                            krylov="auto", tol=1e-10)
+                            krylov="auto", tol=1e-7)
     r2.run()
     assert r2.status()[0] == _lib.PXP_OK
 
@@ -628,7 +677,7 @@ def test_last_report_per_instance(torch):
     flavours, its own substeps and iterations, and an estimate within the
     tolerance; reading clears the statistics."""
     import test_gpu_2d_uniform as u2
-    insts = [small_advdiff(n=128, T=0.25, nt=250, P=5), small_burgers(),
+    insts = [small_advdiff(n=128, T=0.25, nt=250, P=5), small_burgers(P=128),
              u2.small2d(P=16)]
     probs = [api.make_problem(x, krylov="auto", sched=sc, tol=1e-10)
              for x, sc in zip(insts, ("classic", "classic", "tree"))]

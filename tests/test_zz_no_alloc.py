@@ -68,7 +68,8 @@ def check(ref, got):
 
 
 def test_noalloc_matches_workspace_form_twice(torch):
-    big = burgers_small(n=512, nt=1024, P=16)
+    # slices of 8 RK4 steps: the Magnus check stays far below the tolerance
+    big = burgers_small(n=512, nt=1024, P=128)
     small = workloads.make("advdiff1d_n128")[0]
     sizes = [_lib.pxp_workspace_size([api.make_problem(x)]) for x in (big, small)]
     print("noalloc: burgers n=512 (%d B) then advdiff1d_n128 (%d B)" % tuple(sizes),
