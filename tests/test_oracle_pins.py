@@ -318,3 +318,26 @@ def test_integral_cost_differs_from_terminal(orc):
     jt = orc.gradient(inst)["J"]
     ji = orc.gradient(dict(inst, cost="integral"))["J"]
     assert abs(jt - ji) > 1e-3 * abs(jt)
+
+
+def test_burgers_integral_cost_central_difference(orc):
+    """Burgers with the integral cost: the reverse sweep through the
+    nonlinear steps' Jacobians with the step sources matches central
+    differences of the oracle's own march (fourth order in eps: a 5-point
+    stencil), and the sources make it differ from the terminal-cost
+    gradient."""
+    inst = dict(small_burgers(), cost="integral")
+    out = orc.gradient(inst)
+    a = np.asarray(inst["a"])
+    rng = np.random.default_rng(13)
+    for _ in range(4):
+        d = rng.standard_normal(a.size)
+        d /= np.linalg.norm(d)
+        eps = 1e-3
+        f = [orc.cost(inst, a + k * eps * d) for k in (-2, -1, 1, 2)]
+        fd = (f[0] - 8 * f[1] + 8 * f[2] - f[3]) / (12 * eps)
+        assert abs(fd - out["grad"] @ d) < 1e-9 * (abs(fd) + np.linalg.norm(out["grad"]))
+    term = orc.gradient(dict(inst, cost="terminal"))
+    assert rel(term["grad"], out["grad"]) > 1e-2
+    # lambda_0 of the integral cost includes dJ/dq_0 = 2 w_0 (q_0 - q_tgt)
+    assert np.all(np.isfinite(out["lam0"]))
