@@ -351,6 +351,11 @@ def measure(args, name, torch, _lib, api, workloads, steps, serial_steps, with_o
     insts = workloads.make(name)
     if args.instances > 0 and name == args.workload:
         insts = insts[:args.instances]
+    if name == args.workload:
+        for key, v in (("hyb_slices", args.hyb_slices), ("hyb_k", args.hyb_k),
+                       ("hyb_group", args.hyb_group)):
+            if v is not None:
+                insts = [dict(x, **{key: v}) for x in insts]
     inst = insts[0]
     B = len(insts)
     n = inst["nx"] * inst.get("ny", 1)
@@ -473,6 +478,53 @@ def measure(args, name, torch, _lib, api, workloads, steps, serial_steps, with_o
     return out
 
 
+def hyb_bounds(inst):
+    """Adjoint slice bounds of the hybrid scheme (the library's rule: eq.
+    nonEquiP rounded to multiples of lcm(macro step, checkpoint interval))."""
+    nt, P, c = int(inst["n_steps"]), int(inst["P"]), int(inst["ckpt_every"])
+    S = nt // P
+    L = S // math.gcd(S, c) * c
+    U = nt // L
+    N = min(int(inst.get("hyb_slices", 0)) or P, U)
+    k = float(inst.get("hyb_k", 0.0))
+    r = k / (k + 1.0)
+    b = [0]
+    for i in range(1, N):
+        f = (1 - r ** i) / (1 - r ** N) if k > 0 else i / N
+        a = int(round(f * U)) * L
+        if b[-1] < a < nt:
+            b.append(a)
+    b.append(nt)
+    return b
+
+
+def hybrid_model(inst, kern, t_ser):
+    """The hybrid scheme's times against eq. hybridSpeedup: tau_I (march,
+    per RK4 step), tau_I^dagger (adjoint slices, per step of one slice: the
+    batches run their slices concurrently), the chain (tau_H^dagger T_H) and
+    the check; predicted T_L = n_t tau_I + (last slice) tau_I^dagger +
+    chain; the ceiling (tau_I + tau_I^dagger) / (tau_I + tau_H^dagger)."""
+    nt = int(inst["n_steps"])
+    b = hyb_bounds(inst)
+    G = int(inst.get("hyb_group", 0)) or 4
+    d = kern.get("serial_direct", {}).get("per_step_ms")
+    a = kern.get("adj_slices", {}).get("per_step_ms")
+    ch = kern.get("ltv_adjoint", {}).get("per_step_ms", 0.0)
+    ck = kern.get("ltv_check", {}).get("per_step_ms", 0.0)
+    if not d or not a:
+        return None
+    tau_i = d / nt
+    tau_a = a * G / nt  # equal slices: each batch runs G slices at once
+    pred = nt * tau_i + (b[-1] - b[-2]) * tau_a + ch + ck
+    serial_model = nt * (tau_i + tau_a)
+    return {"slices": len(b) - 1, "group": G, "k": float(inst.get("hyb_k", 0.0)),
+            "tau_I_us_per_step": tau_i * 1e3, "tau_I_adj_us_per_step": tau_a * 1e3,
+            "k_measured": tau_a / tau_i, "chain_ms": ch, "check_ms": ck,
+            "predicted_ms": pred,
+            "predicted_speedup_vs_serial": (t_ser * 1e3 / pred) if t_ser else None,
+            "ceiling_speedup": serial_model / (nt * tau_i + ch)}
+
+
 def summary_report(report):
     """Per-instance report condensed to ranges."""
     if not report:
@@ -516,6 +568,12 @@ def main():
                          "library's autotuner before timing")
     ap.add_argument("--p-range", default="8,256",
                     help="slice counts the autotuner may choose (lo,hi)")
+    ap.add_argument("--hyb-slices", type=int, default=None,
+                    help="Burgers integral cost: adjoint slices of the hybrid scheme")
+    ap.add_argument("--hyb-k", type=float, default=None,
+                    help="Burgers integral cost: k of eq. nonEquiP (0 = equal slices)")
+    ap.add_argument("--hyb-group", type=int, default=None,
+                    help="Burgers integral cost: adjoint slices per launch")
     ap.add_argument("--instances", type=int, default=0,
                     help="use only the first K instances of a batch workload (0 = all)")
     ap.add_argument("--oracle-budget", type=float, default=2.5e8,
@@ -571,6 +629,12 @@ def main():
            "point_steps": sum(m["work"])}
     if m["tuned"] is not None:
         cfg["autotune"] = m["tuned"]
+    if inst.get("cost") == "integral":
+        cfg["cost"] = "integral"
+        if inst["op"] == "burgers1d":
+            cfg["hybrid"] = {"adjoint_slices": int(inst.get("hyb_slices", 0)) or int(inst["P"]),
+                             "k": float(inst.get("hyb_k", 0.0)),
+                             "group": int(inst.get("hyb_group", 0)) or 4}
     line = {
         "metric": METRIC,
         "value": (B / m["t_pxp"]) if m["ok"] else 0.0,
@@ -601,6 +665,8 @@ def main():
     }
     if m["t_graph"] is not None:
         line["graph"] = {"value": B / m["t_graph"], "ms_per_step": m["t_graph"] * 1e3}
+    if inst["op"] == "burgers1d" and inst.get("cost") == "integral" and B == 1:
+        line["hybrid_model"] = hybrid_model(inst, m["kern"], m["t_ser"])
     if m["orc"] is not None and not args.no_cpu_baseline:
         o = m["orc"]
         work = m["work"]

@@ -122,7 +122,8 @@ enum { PXP_SCHED_CLASSIC = 0, PXP_SCHED_CHAIN = 1, PXP_SCHED_TREE = 2 };
  * states by Krylov, each with its share of Lambda.  Default (0): the
  * unabsorbed form, one homogeneous piece from lambda_T (eq. adjhomfinal). */
 enum { PXP_FLAG_ABSORBED_ADJOINT = 1, PXP_FLAG_INTEGRAL_COST = 2 };
-/* INTEGRAL_COST (2D problems, UNIFORM or AUTO exponentials, TREE schedule):
+/* INTEGRAL_COST (2D problems with UNIFORM or AUTO exponentials and the TREE
+ * schedule; Burgers problems in FP64):
  * pxp_gradient minimises the integral cost of section 4.2 (eq. cost),
  *   J = 1/T int_0^T |q(t) - u_tgt|^2 dt + beta |a|^2,
  * the time integral taken by the trapezoidal rule over the RK4 step states
@@ -138,9 +139,20 @@ enum { PXP_FLAG_ABSORBED_ADJOINT = 1, PXP_FLAG_INTEGRAL_COST = 2 };
  * exact share of Lambda.  The workspace then holds (n_steps + 1) n sources
  * per instance.  The largest adjoint piece, mu T_left with T_left the
  * horizon of the tree's left half, must stay within 4096 (PXP_EUNSUPPORTED
- * otherwise; mu = -diagonal of A).  The paraexp_direct and paraexp_adjoint
- * calls on their own ignore the flag, except that paraexp_adjoint accepts
- * jI_src only for problems that carry it; pxp_cost refuses it. */
+ * otherwise; mu = -diagonal of A).
+ * Burgers (section 3.3, the hybrid serial-direct-parallel-adjoint scheme of
+ * algorithm 3): the serial direct march writes the step sources; it runs as
+ * one launch per adjoint slice, and every hyb_group slices the adjoint
+ * slices of the march so far (the exact discrete adjoint of each slice from
+ * zero with its sources, eq. hybadjinhom) start on the library's side stream
+ * while the march goes on.  The slice bounds follow eq. nonEquiP with
+ * k = hyb_k, rounded to multiples of lcm(n_steps/P, ckpt_every) steps; the
+ * P Magnus steps of the time-varying adjoint chain then start from
+ * dJ/dq(T) and add each slice's end state where it starts (eq.
+ * fullAdjSolHyb as a nested sum).
+ * The paraexp_direct and paraexp_adjoint calls on their own ignore the
+ * flag, except that paraexp_adjoint accepts jI_src only for 2D problems
+ * that carry it; pxp_cost refuses it. */
 /* Method: PARAEXP = the time-parallel path; SERIAL = plain RK4 stepping of
  * the direct equation and its exact discrete adjoint (the comparison). */
 enum { PXP_METHOD_PARAEXP = 0, PXP_METHOD_SERIAL = 1 };
@@ -161,6 +173,12 @@ typedef struct {
     double krylov_tol;               /* relative a-posteriori tolerance        */
     double si_gamma;                 /* shift-and-invert shift as a fraction of
                                         the exponential's time (0 = 0.2)      */
+    int32_t hyb_slices;              /* integral cost, Burgers: adjoint slices
+                                        of the hybrid scheme (0 = P)          */
+    int32_t hyb_group;               /* slices per adjoint launch (0 = 4)      */
+    double hyb_k;                    /* their partition (eq. nonEquiP): adjoint
+                                        over direct time per unit of time
+                                        (0 = equal slices)                    */
 } pxp_problem;
 
 /* Bytes of device workspace the calls below need for this batch.

@@ -55,7 +55,9 @@ class pxp_problem(ctypes.Structure):
                 ("vy", ctypes.c_double), ("nu", ctypes.c_double),
                 ("T", ctypes.c_double), ("omega", ctypes.c_double),
                 ("beta", ctypes.c_double), ("krylov_tol", ctypes.c_double),
-                ("si_gamma", ctypes.c_double)]
+                ("si_gamma", ctypes.c_double),
+                ("hyb_slices", ctypes.c_int32), ("hyb_group", ctypes.c_int32),
+                ("hyb_k", ctypes.c_double)]
 
 
 class pxp_tune_report(ctypes.Structure):

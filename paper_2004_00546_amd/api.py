@@ -41,6 +41,11 @@ def make_problem(inst: dict, krylov: str = "shift_invert", sched: str = "classic
     p.beta = float(inst.get("beta", 0.0))
     p.krylov_tol = float(tol)
     p.si_gamma = float(si_gamma)
+    # hybrid scheme of the Burgers integral cost: adjoint slices and their
+    # partition (eq. nonEquiP)
+    p.hyb_slices = int(inst.get("hyb_slices", 0))
+    p.hyb_group = int(inst.get("hyb_group", 0))
+    p.hyb_k = float(inst.get("hyb_k", 0.0))
     return p
 
 

@@ -44,6 +44,8 @@ struct Inst {
     // states, Lambda shares (slices then tree pairs), cost partials, weight
     // tables of the adjoint tree
     size_t gsrc, lev, ebuf, islot, cpart, iwtab;
+    // Burgers integral cost: hybrid scheme buffers
+    size_t hstate, hmu, hseg, hbnd, haddq;
     // Burgers: Magnus check node states (two samples x two half steps x two
     // vectors) and results (one step, two half steps per sample)
     size_t mnodes, mout, mdesc;
@@ -426,8 +428,40 @@ size_t icost_wtab_count(const pxp_problem& p) {
     return p.P < 2 ? 0 : 2 * (tree_shape(p.P).size() - 1);
 }
 
+// Adjoint slices of the hybrid scheme for the Burgers integral cost
+// (section 3.3): bounds T_n = T (1 - r^n) / (1 - r^N), r = k / (k + 1)
+// (eq. nonEquiP; k = 0: equal slices), in steps rounded to multiples of
+// L = lcm(S, c) (S = n_steps / P the Magnus macro step, c the checkpoint
+// interval: the slices start on checkpoints, the chain adds their end states
+// between macro steps); bounds that coincide after rounding merge.  Returns
+// 0 = a_0 < a_1 < ... < a_N = n_steps.
+int64_t gcd64(int64_t a, int64_t b) { return b == 0 ? a : gcd64(b, a % b); }
+std::vector<int64_t> hyb_bounds(const pxp_problem& p) {
+    const int64_t S = p.n_steps / p.P, c = p.ckpt_every;
+    const int64_t L = S / gcd64(S, c) * c, U = p.n_steps / L;
+    const int64_t N = std::min<int64_t>(p.hyb_slices > 0 ? p.hyb_slices : p.P, U);
+    const double r = p.hyb_k / (p.hyb_k + 1.0);
+    std::vector<int64_t> b{0};
+    for (int64_t i = 1; i < N; ++i) {
+        const double f = p.hyb_k > 0.0 ? (1.0 - std::pow(r, (double)i)) / (1.0 - std::pow(r, (double)N))
+                                        : (double)i / (double)N;
+        const int64_t a = std::llround(f * (double)U) * L;
+        if (a > b.back() && a < p.n_steps) b.push_back(a);
+    }
+    b.push_back(p.n_steps);
+    return b;
+}
+int hyb_group(const pxp_problem& p) { return p.hyb_group > 0 ? p.hyb_group : 4; }
+
 pxp_status validate_icost(const pxp_problem& p) {
+    if (p.hyb_slices < 0 || p.hyb_group < 0 || !(p.hyb_k >= 0.0) || !std::isfinite(p.hyb_k))
+        return PXP_EINVAL;
     if (!icost(p)) return PXP_OK;
+    if (p.op == PXP_OP_BURGERS1D) {
+        // the serial march's state passes between launches as FP64
+        if (p.prec != PXP_FP64) return PXP_EUNSUPPORTED;
+        return PXP_OK;
+    }
     if (p.op != PXP_OP_ADVDIFF2D_UPWIND) return PXP_EUNSUPPORTED;
     if (!uniform_direct(p) || !uniform_adjoint(p) || p.sched != PXP_SCHED_TREE)
         return PXP_EUNSUPPORTED;
@@ -500,6 +534,19 @@ Inst inst_layout(const pxp_problem& p) {
         L.mnodes = take(8 * n * d);
         L.mout = take(4 * n * d);
         L.mdesc = take(sizeof(MagnusCheck));
+        if (icost(p)) {
+            // the march's running state, the hybrid adjoint slices' end
+            // states and segment scratch, cost partials, and the slice
+            // bounds and chain additions (device tables); the step sources
+            // are formed from the states the reverse sweeps recompute
+            const size_t ns = hyb_bounds(p).size() - 1;
+            L.hstate = take(n * d);
+            L.hmu = take(ns * n * d);
+            L.hseg = take(ns * c * n * d);
+            L.cpart = take(std::max(ns, (size_t)1) * d);
+            L.hbnd = take((ns + 1) * sizeof(int64_t));
+            L.haddq = take(ns * sizeof(int));
+        }
         // basis, then the shift-and-invert factors of the time-varying
         // operator (5 n + 5 B doubles, B <= 512)
         L.basis = take(((m + 6) * n + 5 * 512) * d);
@@ -880,6 +927,10 @@ KrylovArgs magnus_check_args(const Ctx& c, const KrylovArgs& a, int kind) {
     // in FP64 also for FP32-bulk problems: the difference of the two
     // propagations is then the Magnus error, not the FP32 stencil's rounding
     b.fp32 = 0;
+    // the check propagates the start vector alone
+    b.vadd = nullptr;
+    b.addq = nullptr;
+    b.nadd = 0;
     b.yout = c.at(c.L.mout) + (size_t)kind * n;
     if (kind % 2 == 0) {
         b.npieces = 1;
@@ -905,7 +956,8 @@ MagnusCheck magnus_check_desc(const Ctx& c) {
 }
 
 pxp_status adjoint_burgers(const Ctx& c, const double* lamT, double* lam0,
-                           int method) {
+                           int method, const double* vadd = nullptr,
+                           const int* addq = nullptr, int nadd = 0) {
     if (method == PXP_METHOD_SERIAL) {
         ProfScope ps(PXP_K_SERIAL_REVERSE, c.s);
         HIPCHK(launch_rk4_burgers_reverse(c.at(c.L.ckpt), lamT, lam0, c.at(c.L.seg),
@@ -937,6 +989,9 @@ pxp_status adjoint_burgers(const Ctx& c, const double* lamT, double* lam0,
     a.wop = c.at(c.L.nodes);
     a.inv2h = 1.0 / (2.0 * h);
     a.nuh2 = c.p.nu / (h * h);
+    a.vadd = vadd;
+    a.addq = addq;
+    a.nadd = nadd;
     {
         ProfScope ps(PXP_K_LTV_ADJOINT, c.s);
         HIPCHK(launch_krylov1d(a, c.p.kblock, c.s));
@@ -959,10 +1014,123 @@ pxp_status adjoint_burgers(const Ctx& c, const double* lamT, double* lam0,
     return PXP_OK;
 }
 
+// Integral cost, Burgers: the serial march forms one cost partial per
+// launch (the step sources come later, from the recomputed states).  Paraexp: the hybrid scheme of section 3.3
+// (algorithm 3) -- one march launch per adjoint slice on the caller's
+// stream; after every hyb_group slices the library's side stream (when it
+// exists; else the caller's) waits for the march and runs those slices'
+// adjoint batch.  *nparts receives the number of cost partials.
+pxp_status direct_burgers_icost(const Ctx& c, const double* q0, const double* tgt,
+                                double* qT, int method, int* nparts) {
+    const int64_t n_t = c.p.n_steps;
+    const int n = c.n();
+    BurgersRange rg{};
+    rg.tgt = tgt;
+    rg.gw = 2.0 * c.dt() / c.p.T;
+    if (method == PXP_METHOD_SERIAL) {
+        rg.s0 = 0;
+        rg.s1 = n_t;
+        rg.cpart = c.at(c.L.cpart);
+        ProfScope ps(PXP_K_SERIAL_DIRECT, c.s);
+        HIPCHK(launch_rk4_burgers_direct(q0, qT, c.at(c.L.ckpt), n, n_t, c.p.ckpt_every,
+                                         c.dt(), c.p.nu, c.p.L, c.p.block, 0, c.s, &rg));
+        *nparts = 1;
+        return PXP_OK;
+    }
+    const std::vector<int64_t> b = hyb_bounds(c.p);
+    const int ns = (int)b.size() - 1;
+    const int64_t S = n_t / c.p.P;
+    // the chain adds slice ns-1-k's end state after macro step addq[k]
+    // (reversed time), where it reaches the slice's start
+    std::vector<int> addq(ns);
+    for (int k = 0; k < ns; ++k) addq[k] = (int)((n_t - b[ns - 1 - k]) / S) - 1;
+    auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+        for (size_t o = 0; o < bytes; o += 3072) {
+            hipError_t e = launch_upload(static_cast<char*>(dst) + o,
+                                         static_cast<const char*>(src) + o,
+                                         std::min((size_t)3072, bytes - o), c.s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    auto* dbnd = reinterpret_cast<int64_t*>(c.at(c.L.hbnd));
+    HIPCHK(up(dbnd, b.data(), b.size() * sizeof(int64_t)));
+    HIPCHK(up(c.at(c.L.haddq), addq.data(), addq.size() * sizeof(int)));
+    int dev = 0;
+    SideStream side;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < MAX_DEVICES) {
+        std::lock_guard<std::mutex> copy(g_side_mu);
+        side = g_side[dev];
+    }
+    std::unique_lock<std::mutex> lock(g_side_mu, std::defer_lock);
+    const bool forked = side.st != nullptr;
+    if (forked) lock.lock();
+    const int G = hyb_group(c.p);
+    double* st = c.at(c.L.hstate);
+    for (int sl = 0; sl < ns; ++sl) {
+        rg.s0 = b[sl];
+        rg.s1 = b[sl + 1];
+        rg.cpart = c.at(c.L.cpart) + sl;
+        const double* in = sl == 0 ? q0 : st;
+        double* out = sl == ns - 1 ? qT : st;
+        {
+            ProfScope ps(PXP_K_SERIAL_DIRECT, c.s);
+            HIPCHK(launch_rk4_burgers_direct(in, out, c.at(c.L.ckpt), n, n_t, c.p.ckpt_every,
+                                             c.dt(), c.p.nu, c.p.L, c.p.block, 0, c.s, &rg));
+        }
+        if ((sl + 1) % G != 0 && sl != ns - 1) continue;
+        const int g0 = (sl / G) * G;
+        hipStream_t sg = c.s;
+        if (forked) {
+            HIPCHK(hipEventRecord(side.fork, c.s));
+            HIPCHK(hipStreamWaitEvent(side.st, side.fork, 0));
+            sg = side.st;
+        }
+        ProfScope ps(PXP_K_ADJ_SLICES, sg);
+        HIPCHK(launch_burgers_adj_slices(c.at(c.L.ckpt), tgt, rg.gw, c.at(c.L.hseg),
+                                         c.at(c.L.hmu), dbnd, g0, sl + 1 - g0, n, n_t,
+                                         c.p.ckpt_every, c.dt(), c.p.nu, c.p.L, c.p.block, sg));
+    }
+    if (forked) {
+        HIPCHK(hipEventRecord(side.join, side.st));
+        HIPCHK(hipStreamWaitEvent(c.s, side.join, 0));
+    }
+    *nparts = ns;
+    return PXP_OK;
+}
+
+// Its adjoint: serial, the discrete adjoint with the sources from
+// dJ/dq(T); Paraexp, the Magnus chain from dJ/dq(T) = gw / 2 (q(T) - tgt)
+// adding the hybrid slices' end states.
+pxp_status adjoint_burgers_icost(const Ctx& c, const double* qT, const double* tgt,
+                                 double* lam0, int method) {
+    const int64_t n_t = c.p.n_steps;
+    const int n = c.n();
+    const double gw = 2.0 * c.dt() / c.p.T;
+    if (method == PXP_METHOD_SERIAL) {
+        BurgersRange rg{};
+        rg.s0 = 0;
+        rg.s1 = n_t;
+        rg.tgt = tgt;
+        rg.gw = gw;
+        rg.src_start = 1;
+        ProfScope ps(PXP_K_SERIAL_REVERSE, c.s);
+        HIPCHK(launch_rk4_burgers_reverse(c.at(c.L.ckpt), nullptr, lam0, c.at(c.L.seg), n,
+                                          n_t, c.p.ckpt_every, c.dt(), c.p.nu, c.p.L,
+                                          c.p.block, 0, c.s, &rg));
+        return PXP_OK;
+    }
+    const int ns = (int)hyb_bounds(c.p).size() - 1;
+    double* gT = c.at(c.L.lamT);
+    HIPCHK(launch_scaled_diff(qT, tgt, 0.5 * gw, gT, n, c.s));
+    return adjoint_burgers(c, gT, lam0, method, c.at(c.L.hmu),
+                           reinterpret_cast<const int*>(c.at(c.L.haddq)), ns);
+}
+
 // Burgers instances that the ragged batch kernels take: 256 threads with a
 // supported number of points per thread.
 bool burgers_batchable(const pxp_problem& p) {
-    if (p.op != PXP_OP_BURGERS1D || p.nx % 256) return false;
+    if (p.op != PXP_OP_BURGERS1D || p.nx % 256 || icost(p)) return false;
     const int pt = p.nx / 256;
     return pt == 1 || pt == 2 || pt == 4 || pt == 8 || pt == 16 || pt == 32;
 }
@@ -2444,6 +2612,7 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
         }
     }
     const BurgersBatch bb = burgers_batch(pb, batch);
+    std::vector<int> npart(batch, 0);  // integral cost: cost partials per instance
     // (a1) controls -> forcing pattern or initial state
     for (int i = 0; i < batch; ++i) {
         const pxp_problem& p = pb[i];
@@ -2477,8 +2646,12 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
             continue;
         }
         Ctx c = make_ctx(p, ws, Ly, i, s);
-        st = (p.op == PXP_OP_ADVDIFF1D) ? direct_lin1d(c, ip[i].init, ip[i].F, ip[i].qT, method)
-                                        : direct_burgers(c, ip[i].init, ip[i].qT);
+        if (p.op == PXP_OP_BURGERS1D && icost(p))
+            st = direct_burgers_icost(c, ip[i].init, ip[i].tgt, ip[i].qT, method, &npart[i]);
+        else
+            st = (p.op == PXP_OP_ADVDIFF1D)
+                     ? direct_lin1d(c, ip[i].init, ip[i].F, ip[i].qT, method)
+                     : direct_burgers(c, ip[i].init, ip[i].qT);
         if (st != PXP_OK) return st;
     }
     if (bb.on) {
@@ -2492,6 +2665,7 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
         if (icost(pb[idx2[j]])) t2[j] = ip[idx2[j]].tgt;
     st = direct_2d_batch(pb, idx2, ws, Ly, i2, f2, o2, method, s, &t2, &np2);
     if (st != PXP_OK) return st;
+    for (size_t j = 0; j < idx2.size(); ++j) npart[idx2[j]] = np2[j];
     // (a5) cost and adjoint final condition, every instance in two launches
     // (integral cost: the partials of the source march; no final condition)
     auto* dst = reinterpret_cast<DevStatus*>(static_cast<char*>(ws) + Ly.status);
@@ -2521,12 +2695,9 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
             d.gpart0 = po + d.chunks;
             po += (int64_t)(d.K + 1) * d.chunks;
             if (icost(pb[i])) {
-                int np = 0;
-                for (size_t j = 0; j < idx2.size(); ++j)
-                    if (idx2[j] == i) np = np2[j];
                 Ctx c = make_ctx(pb[i], ws, Ly, i, s);
                 d.ipart = c.at(c.L.cpart);
-                d.ichunks = np;
+                d.ichunks = npart[i];
                 d.lamT = nullptr;
             } else {
                 bcost += d.chunks;
@@ -2554,10 +2725,13 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
         }
         if (bb.on && in_batch(bb, i)) continue;
         Ctx c = make_ctx(p, ws, Ly, i, s);
-        st = (p.op == PXP_OP_ADVDIFF1D)
-                 ? adjoint_lin1d(c, ip[i].lamT, forcing ? nullptr : ip[i].lam0,
-                                 forcing ? ip[i].Lam : nullptr, method)
-                 : adjoint_burgers(c, ip[i].lamT, ip[i].lam0, method);
+        if (p.op == PXP_OP_BURGERS1D && icost(p))
+            st = adjoint_burgers_icost(c, ip[i].qT, ip[i].tgt, ip[i].lam0, method);
+        else
+            st = (p.op == PXP_OP_ADVDIFF1D)
+                     ? adjoint_lin1d(c, ip[i].lamT, forcing ? nullptr : ip[i].lam0,
+                                     forcing ? ip[i].Lam : nullptr, method)
+                     : adjoint_burgers(c, ip[i].lamT, ip[i].lam0, method);
         if (st != PXP_OK) return st;
     }
     if (bb.on) {

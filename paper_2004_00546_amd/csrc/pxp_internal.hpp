@@ -69,10 +69,39 @@ hipError_t launch_rk4_rev_lin1d(const double* lamT, double* lam0,
 
 // Burgers 1D direct march with checkpoints every c steps (ckpt[k] = state at
 // step k*c, k = 0..n_t/c).
+// Step range and integral-cost terms of a Burgers march (the cost of
+// section 4.2 on the problem of section 4.3): steps [s0, s1) of n_t, the
+// states at step s0 in / at s1 out.  With tgt set, the step sources are
+// g_s = gw c_s (q_s - tgt), c_s = 1/2 at both ends and 1 inside.  Forward:
+// the workgroup's share of J, sum over s0 <= s < s1 (and s = n_t when
+// s1 = n_t) of w_s |q_s - tgt|^2 (w_s = gw c_s / 2), into *cpart.  Reverse:
+// g_s added after the step that produces lambda_s, formed from the step
+// states the sweep recomputes from the checkpoints (g_{s1} added to the
+// start vector when src_start, from the checkpoint at s1).  Ranges of the
+// reverse sweep start and end on checkpoints.
+struct BurgersRange {
+    int64_t s0, s1;
+    const double* tgt;
+    double gw;
+    double* cpart;
+    int src_start, pad;
+};
+// out = a (x - y) on n points
+hipError_t launch_scaled_diff(const double* x, const double* y, double a, double* out, int n,
+                              hipStream_t s);
 hipError_t launch_rk4_burgers_direct(const double* y0, double* yT, double* ckpt,
                                      int n, int64_t n_t, int64_t c, double dt,
                                      double nu, double L, int block, int fp32,
-                                     hipStream_t s);
+                                     hipStream_t s, const BurgersRange* rg = nullptr);
+// The adjoint slices of the hybrid scheme (section 3.3, eq. hybadjinhom with
+// the step sources of target tgt and weight gw): workgroup b runs slice
+// s = s_first + b, steps [bounds[s], bounds[s+1]) backwards from zero,
+// recomputing the states from the checkpoints (its own segment scratch
+// seg + s c n), and writes the slice's end state to mu + s n.
+hipError_t launch_burgers_adj_slices(const double* ckpt, const double* tgt, double gw,
+                                     double* seg, double* mu, const int64_t* bounds,
+                                     int s_first, int count, int n, int64_t n_t, int64_t c,
+                                     double dt, double nu, double L, int block, hipStream_t s);
 
 // Burgers reverse sweep, serial, over segments between checkpoints: each
 // segment's step states are recomputed into `seg` (c x n) first.
@@ -80,7 +109,7 @@ hipError_t launch_rk4_burgers_reverse(const double* ckpt, const double* lamT,
                                       double* lam0, double* seg, int n,
                                       int64_t n_t, int64_t c, double dt,
                                       double nu, double L, int block, int fp32,
-                                      hipStream_t s);
+                                      hipStream_t s, const BurgersRange* rg = nullptr);
 
 // Effective states of the two commutator-free Magnus factors of each macro
 // step of S steps (W[2q], W[2q+1], q < n_t / S), recomputed from the
@@ -157,6 +186,11 @@ struct KrylovArgs {
     int pt;              // batched launches: points per thread
     const double* wop;   // KM_LTV: effective states [2*npieces][n]
     double inv2h, nuh2;  // KM_LTV: 1/(2h), nu/h^2
+    // KM_LTV: vectors added to the chain (nullable): after macro step
+    // addq[k] (increasing), vadd + (nadd - 1 - k) n
+    const double* vadd;
+    const int* addq;
+    int nadd;
     double* basis;       // [gridDim][m+1][n] workspace
     Sten5 op5;           // 2D: five-point operator
     int nx, ny;          // 2D: grid

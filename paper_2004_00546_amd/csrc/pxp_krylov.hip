@@ -1157,6 +1157,7 @@ __device__ __forceinline__ void dev_krylov1d(const KrylovArgs& a, int piece, dou
     const double tau = (a.mode == KM_CLASSIC) ? (double)(a.npieces - piece) * a.tau : a.tau;
     const double ia = (a.mode == KM_CLASSIC) ? a.ia * tau : a.ia;
     if (VAR && SI) c.aux = V + (size_t)(a.m + 1) * n;
+    int nextadd = 0;
     for (int q = 0; q < nexp; ++q) {
         if (VAR) c.Wcur = a.wop + (size_t)q * n;
         c.expv(tau, ia, a.ib, iout);
@@ -1167,6 +1168,17 @@ __device__ __forceinline__ void dev_krylov1d(const KrylovArgs& a, int piece, dou
 #pragma unroll
             for (int u = 0; u < PT; ++u) w[u] += x[u];
             c.gstore(V, w);
+        }
+        // time-varying chain: after a macro step (two factors) that ends on
+        // an adjoint slice start, add that slice's end state
+        if (VAR && a.vadd && (q & 1) && nextadd < a.nadd && a.addq[nextadd] == (q >> 1)) {
+            double x[PT], w[PT];
+            c.gload(a.vadd + (size_t)(a.nadd - 1 - nextadd) * n, x);
+            c.gload(V, w);
+#pragma unroll
+            for (int u = 0; u < PT; ++u) w[u] += x[u];
+            c.gstore(V, w);
+            ++nextadd;
         }
     }
     double* y = (a.mode == KM_CLASSIC) ? a.yout + (size_t)piece * n : a.yout;

@@ -293,6 +293,18 @@ hipError_t launch_magnus_check(const MagnusCheck* tab, int count, hipStream_t s)
     return hipGetLastError();
 }
 
+__global__ void k_scaled_diff(const double* __restrict__ x, const double* __restrict__ y,
+                              double a, double* __restrict__ out, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a * (x[i] - y[i]);
+}
+
+hipError_t launch_scaled_diff(const double* x, const double* y, double a, double* out, int n,
+                              hipStream_t s) {
+    k_scaled_diff<<<blocks(n, 256), 256, 0, s>>>(x, y, a, out, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_recombine(const double* q0, const double* vlast,
                             const double* Y, int np, int n, double* out,
                             DevStatus* st, hipStream_t s) {

@@ -461,24 +461,46 @@ __device__ __forceinline__ void burgers_step(R (&y)[PT], R (&yc)[PT], R dt,
     for (int q = 0; q < PT; ++q) kadd<R>(y[q], yc[q], (dt / (R)6) * (acc[q] + k[q]));
 }
 
+// The march over steps [rg.s0, rg.s1) from y0 (the state at s0) to yT
+// (in place allowed: every thread reads its own points before it writes
+// them), checkpoints every c steps, and the integral-cost share of J where
+// rg.tgt is set.
 template <int PT, typename R>
-__device__ __forceinline__ void dev_burgers_direct(const double* __restrict__ y0,
-                                                   double* __restrict__ yT,
+__device__ __forceinline__ void dev_burgers_direct(const double* y0,
+                                                   double* yT,
                                                    double* __restrict__ ckpt, int n,
                                                    int64_t n_t, int64_t c, double dt,
-                                                   BurgersC bc, double* lds_d) {
+                                                   BurgersC bc, double* lds_d,
+                                                   const BurgersRange& rg) {
     R* lds = reinterpret_cast<R*>(lds_d);
     const int base = threadIdx.x * PT;
     const R inv2h = (R)bc.inv2h, nuh2 = (R)bc.nuh2, rdt = (R)dt;
     R y[PT], yc[PT];
 #pragma unroll
     for (int q = 0; q < PT; ++q) split_hilo<R>(y0[base + q], y[q], yc[q]);
-    if (ckpt) {
+    if (ckpt && rg.s0 == 0) {
 #pragma unroll
         for (int q = 0; q < PT; ++q) ckpt[base + q] = hilo<R>(y[q], yc[q]);
     }
+    // the share of J: sum w_s (q_s - tgt)^2, w_s = gw c_s / 2
+    double js = 0.0, tg[PT];
+    if (rg.tgt) {
+#pragma unroll
+        for (int q = 0; q < PT; ++q) tg[q] = rg.tgt[base + q];
+    }
+    auto emit = [&](int64_t st) {
+        const double cs = rg.gw * ((st == 0 || st == n_t) ? 0.5 : 1.0);
+        double e = 0.0;
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            const double d = hilo<R>(y[q], yc[q]) - tg[q];
+            e += d * d;
+        }
+        js += 0.5 * cs * e;
+    };
     int buf = 0;
-    for (int64_t s = 0; s < n_t; ++s) {
+    for (int64_t s = rg.s0; s < rg.s1; ++s) {
+        if (rg.tgt) emit(s);
         burgers_step<PT, 1, R>(y, yc, rdt, inv2h, nuh2, lds, buf);
         if (ckpt && ((s + 1) % c) == 0) {
             double* o = ckpt + (size_t)((s + 1) / c) * n;
@@ -486,17 +508,24 @@ __device__ __forceinline__ void dev_burgers_direct(const double* __restrict__ y0
             for (int q = 0; q < PT; ++q) o[base + q] = hilo<R>(y[q], yc[q]);
         }
     }
+    if (rg.tgt && rg.s1 == n_t) emit(n_t);
 #pragma unroll
     for (int q = 0; q < PT; ++q) yT[base + q] = hilo<R>(y[q], yc[q]);
+    if (rg.cpart) {
+        // the march is done with the LDS exchange buffers (block_sum
+        // begins with a barrier)
+        const double t = block_sum(js, lds_d);
+        if (threadIdx.x == 0) *rg.cpart = t;
+    }
 }
 
 template <int PT, typename R>
 __global__ void __launch_bounds__(max_block<PT>())
-k_rk4_burgers_direct(const double* __restrict__ y0, double* __restrict__ yT,
+k_rk4_burgers_direct(const double* y0, double* yT,
                      double* __restrict__ ckpt, int n, int64_t n_t, int64_t c,
-                     double dt, BurgersC bc) {
+                     double dt, BurgersC bc, BurgersRange rg) {
     extern __shared__ double lds_d[];
-    dev_burgers_direct<PT, R>(y0, yT, ckpt, n, n_t, c, dt, bc, lds_d);
+    dev_burgers_direct<PT, R>(y0, yT, ckpt, n, n_t, c, dt, bc, lds_d, rg);
 }
 
 // (J(U)^T v)_i = ((U v)_{i+1} - (U v)_{i-1})/(2h) - (U_{i+1} - U_{i-1}) v_i/(2h)
@@ -525,22 +554,37 @@ __device__ __forceinline__ void burgers_jt(const R (&U)[PT], R Ul, R Ur,
     }
 }
 
+// The exact discrete adjoint over steps [rg.s0, rg.s1) (multiples of c)
+// from lamT (nullable: zero) at s1, with the step sources where rg.tgt is
+// set; lambda at s0 to lam0.
 template <int PT, typename R>
 __device__ __forceinline__ void dev_burgers_reverse(const double* __restrict__ ckpt,
                                                     const double* __restrict__ lamT,
                                                     double* __restrict__ lam0,
                                                     double* __restrict__ seg, int n,
                                                     int64_t n_t, int64_t c, double dt,
-                                                    BurgersC bc, double* lds_d) {
+                                                    BurgersC bc, double* lds_d,
+                                                    const BurgersRange& rg) {
     R* lds = reinterpret_cast<R*>(lds_d);
     const int base = threadIdx.x * PT;
     const R inv2h = (R)bc.inv2h, nuh2 = (R)bc.nuh2, rdt = (R)dt;
     R lam[PT], lamc[PT];
 #pragma unroll
-    for (int q = 0; q < PT; ++q) split_hilo<R>(lamT[base + q], lam[q], lamc[q]);
+    for (int q = 0; q < PT; ++q) split_hilo<R>(lamT ? lamT[base + q] : 0.0, lam[q], lamc[q]);
+    // step sources g_s = gw c_s (q_s - tgt) from the states at hand
+    double tg[PT];
+    if (rg.tgt) {
+#pragma unroll
+        for (int q = 0; q < PT; ++q) tg[q] = rg.tgt[base + q];
+    }
+    auto source = [&](const double* ys, int64_t st) {
+        const double cs = rg.gw * ((st == 0 || st == n_t) ? 0.5 : 1.0);
+#pragma unroll
+        for (int q = 0; q < PT; ++q) kadd<R>(lam[q], lamc[q], (R)(cs * (ys[base + q] - tg[q])));
+    };
+    if (rg.tgt && rg.src_start) source(ckpt + (size_t)(rg.s1 / c) * n, rg.s1);
     int buf = 0;
-    const int64_t nseg = n_t / c;
-    for (int64_t g = nseg - 1; g >= 0; --g) {
+    for (int64_t g = rg.s1 / c - 1; g >= rg.s0 / c; --g) {
         // recompute the segment's step states from its checkpoint (stored
         // exactly as FP64 values of the compensated pairs)
         R y[PT], yc[PT];
@@ -614,6 +658,7 @@ __device__ __forceinline__ void dev_burgers_reverse(const double* __restrict__ c
             burgers_jt<PT, R>(Y1, Ul[0], Ur[0], kb, inv2h, nuh2, lds, buf, Yb);
 #pragma unroll
             for (int q = 0; q < PT; ++q) kadd<R>(lam[q], lamc[q], nl[q] + Yb[q]);
+            if (rg.tgt) source(ys, g * c + q2);
         }
     }
 #pragma unroll
@@ -625,9 +670,27 @@ __global__ void __launch_bounds__(max_block<PT>())
 k_rk4_burgers_reverse(const double* __restrict__ ckpt,
                       const double* __restrict__ lamT, double* __restrict__ lam0,
                       double* __restrict__ seg, int n, int64_t n_t, int64_t c,
-                      double dt, BurgersC bc) {
+                      double dt, BurgersC bc, BurgersRange rg) {
     extern __shared__ double lds_d[];
-    dev_burgers_reverse<PT, R>(ckpt, lamT, lam0, seg, n, n_t, c, dt, bc, lds_d);
+    dev_burgers_reverse<PT, R>(ckpt, lamT, lam0, seg, n, n_t, c, dt, bc, lds_d, rg);
+}
+
+// Hybrid adjoint slices: workgroup b runs slice s_first + b from zero.
+template <int PT, typename R>
+__global__ void __launch_bounds__(max_block<PT>())
+k_burgers_adj_slices(const double* __restrict__ ckpt, const double* __restrict__ tgt,
+                     double gw, double* __restrict__ seg, double* __restrict__ mu,
+                     const int64_t* __restrict__ bounds, int s_first, int n, int64_t n_t,
+                     int64_t c, double dt, BurgersC bc) {
+    extern __shared__ double lds_d[];
+    const int sl = s_first + (int)blockIdx.x;
+    BurgersRange rg{};
+    rg.s0 = bounds[sl];
+    rg.s1 = bounds[sl + 1];
+    rg.tgt = tgt;
+    rg.gw = gw;
+    dev_burgers_reverse<PT, R>(ckpt, nullptr, mu + (size_t)sl * n,
+                               seg + (size_t)sl * (size_t)c * n, n, n_t, c, dt, bc, lds_d, rg);
 }
 
 // Per-macro-step recompute for the time-varying adjoint (one workgroup per
@@ -746,8 +809,9 @@ __global__ void __launch_bounds__(256) k_burgers_direct_batch(const BurgersDesc*
     extern __shared__ double lds_d[];
     const BurgersDesc d = tab[blockIdx.x];
     const BurgersC bc{d.inv2h, d.nuh2};
+    const BurgersRange rg{0, d.n_t, nullptr, 0.0, nullptr, 0, 0};
     PXP_BATCH_SWITCH(dev_burgers_direct, R, d.y0, d.yT, d.ckpt, d.n, d.n_t, d.c, d.dt,
-                     bc, lds_d)
+                     bc, lds_d, rg)
 }
 
 template <typename R>
@@ -755,8 +819,9 @@ __global__ void __launch_bounds__(256) k_burgers_reverse_batch(const BurgersDesc
     extern __shared__ double lds_d[];
     const BurgersDesc d = tab[blockIdx.x];
     const BurgersC bc{d.inv2h, d.nuh2};
+    const BurgersRange rg{0, d.n_t, nullptr, 0.0, nullptr, 0, 0};
     PXP_BATCH_SWITCH(dev_burgers_reverse, R, d.ckpt, d.lamT, d.lam0, d.seg, d.n, d.n_t,
-                     d.c, d.dt, bc, lds_d)
+                     d.c, d.dt, bc, lds_d, rg)
 }
 
 // The serial reverse sweep at 512 threads per instance (every instance of
@@ -775,8 +840,9 @@ __global__ void __launch_bounds__(512) k_burgers_reverse_batch512(const BurgersD
     extern __shared__ double lds_d[];
     const BurgersDesc d = tab[blockIdx.x];
     const BurgersC bc{d.inv2h, d.nuh2};
+    const BurgersRange rg{0, d.n_t, nullptr, 0.0, nullptr, 0, 0};
     PXP_BATCH_SWITCH_REV(dev_burgers_reverse, R, d.ckpt, d.lamT, d.lam0, d.seg, d.n, d.n_t,
-                         d.c, d.dt, bc, lds_d)
+                         d.c, d.dt, bc, lds_d, rg)
 }
 
 // grid = sum of the instances' macro-step counts; the instance of a
@@ -912,14 +978,17 @@ hipError_t launch_rk4_rev_lin1d(const double* lamT, double* lam0,
 hipError_t launch_rk4_burgers_direct(const double* y0, double* yT, double* ckpt,
                                      int n, int64_t n_t, int64_t c, double dt,
                                      double nu, double L, int block_hint, int fp32,
-                                     hipStream_t s) {
+                                     hipStream_t s, const BurgersRange* rgp) {
     int block, pt;
     if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
     const double h = L / n;
     BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
     const size_t lds = sizeof(double) * 4 * block;
+    BurgersRange rg{0, n_t, nullptr, 0.0, nullptr, 0, 0};
+    if (rgp) rg = *rgp;
+    if (rg.s0 < 0 || rg.s1 > n_t || rg.s0 >= rg.s1) return hipErrorInvalidValue;
     PXP_DISPATCH(fp32, pt, k_rk4_burgers_direct,
-                 <<<1, block, lds, s>>>(y0, yT, ckpt, n, n_t, c, dt, bc))
+                 <<<1, block, lds, s>>>(y0, yT, ckpt, n, n_t, c, dt, bc, rg))
     return hipGetLastError();
 }
 
@@ -945,15 +1014,37 @@ hipError_t launch_rk4_burgers_reverse(const double* ckpt, const double* lamT,
                                       double* lam0, double* seg, int n,
                                       int64_t n_t, int64_t c, double dt,
                                       double nu, double L, int block_hint, int fp32,
-                                      hipStream_t s) {
+                                      hipStream_t s, const BurgersRange* rgp) {
     int block, pt;
     if (!pick_shape(n, serial_block_hint(n, block_hint), &block, &pt))
         return hipErrorInvalidValue;
     const double h = L / n;
     BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
     const size_t lds = sizeof(double) * 8 * block;
+    BurgersRange rg{0, n_t, nullptr, 0.0, nullptr, 0, 0};
+    if (rgp) rg = *rgp;
+    if (rg.s0 < 0 || rg.s1 > n_t || rg.s0 >= rg.s1 || rg.s0 % c || rg.s1 % c)
+        return hipErrorInvalidValue;
     PXP_DISPATCH(fp32, pt, k_rk4_burgers_reverse,
-                 <<<1, block, lds, s>>>(ckpt, lamT, lam0, seg, n, n_t, c, dt, bc))
+                 <<<1, block, lds, s>>>(ckpt, lamT, lam0, seg, n, n_t, c, dt, bc, rg))
+    return hipGetLastError();
+}
+
+hipError_t launch_burgers_adj_slices(const double* ckpt, const double* tgt, double gw,
+                                     double* seg, double* mu, const int64_t* bounds,
+                                     int s_first, int count, int n, int64_t n_t, int64_t c,
+                                     double dt, double nu, double L, int block_hint,
+                                     hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    int block, pt;
+    if (!pick_shape(n, serial_block_hint(n, block_hint), &block, &pt))
+        return hipErrorInvalidValue;
+    const double h = L / n;
+    BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
+    const size_t lds = sizeof(double) * 8 * block;
+    PXP_DISPATCH_PT(pt, k_burgers_adj_slices, double,
+                    <<<count, block, lds, s>>>(ckpt, tgt, gw, seg, mu, bounds, s_first, n,
+                                               n_t, c, dt, bc))
     return hipGetLastError();
 }
 

@@ -22,6 +22,9 @@ the five workloads below are concrete instances of that family:
   linear with zero initial state, so q_f(t) - q_true(t) = q_{f - f_true}(t):
   the instances hold the difference amplitudes a = (1, -1) and a zero
   target, which gives the same cost and gradient.
+* ``burgers1d_icost`` the N=2048 Burgers instance above with the integral
+  cost (the hybrid serial-direct-parallel-adjoint scheme of section 3.3):
+  128 Magnus steps and 128 equal adjoint slices, four per launch.
 
 Every instance is a plain dict of numbers and float64 numpy arrays.  Random
 draws come from ``numpy.random.default_rng([1000 + cfg, instance])`` in the
@@ -39,7 +42,7 @@ TWO_PI = 2.0 * math.pi
 RK4_REAL_LIMIT = 2.785
 
 WORKLOADS = ("advdiff1d_n128", "advdiff1d_n4096", "burgers1d_n2048",
-             "advdiff2d_256", "burgers1d_ragged", "advdiff2d_icost")
+             "advdiff2d_256", "burgers1d_ragged", "advdiff2d_icost", "burgers1d_icost")
 CFG_INDEX = {name: i + 1 for i, name in enumerate(WORKLOADS)}
 
 
@@ -192,6 +195,9 @@ def make(name: str) -> list[dict]:
             out.append(_burgers_instance(cfg, i, n, nu, T, n_steps, 64, 32,
                                          30, rng))
         return out
+    if name == "burgers1d_icost":
+        inst = make("burgers1d_n2048")[0]
+        return [dict(inst, cost="integral", hyb_slices=128, hyb_k=0.0, hyb_group=4)]
     if name == "advdiff2d_icost":
         out = []
         nx = ny = 128

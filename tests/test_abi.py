@@ -49,8 +49,8 @@ def test_version_and_status_strings(lib):
 
 
 def test_struct_layout_matches_header():
-    # 12 int32, 1 int64, 9 doubles
-    assert ctypes.sizeof(_lib.pxp_problem) == 14 * 4 + 8 + 9 * 8
+    # 14 int32, 1 int64, 9 doubles, then 2 int32 and a double
+    assert ctypes.sizeof(_lib.pxp_problem) == 14 * 4 + 8 + 9 * 8 + 2 * 4 + 8
 
 
 def _size_status(probs):

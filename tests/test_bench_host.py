@@ -74,3 +74,22 @@ def test_pois_terms_tail_rule():
             tail = lambda d: sum(pk[d:])  # noqa: E731
             assert tail(D) <= tol * (1 + 1e-9)
             assert tail(D - 1) > tol
+
+
+def test_hybrid_bounds_follow_eq_nonequip():
+    """The hybrid scheme's adjoint slices (the library's rule, restated for
+    the bench model): equal slices for k = 0; for k > 0 the lengths shrink
+    toward T by about k / (k + 1) per slice (eq. paritionRatio), on the grid
+    of lcm(macro step, checkpoint interval)."""
+    import bench
+    from paper_2004_00546_amd import workloads
+    inst = workloads.make("burgers1d_icost")[0]
+    b = bench.hyb_bounds(inst)
+    assert b[0] == 0 and b[-1] == inst["n_steps"] and len(b) == 129
+    assert len(set(b[i + 1] - b[i] for i in range(len(b) - 1))) == 1
+    b = bench.hyb_bounds(dict(inst, hyb_slices=16, hyb_k=2.0))
+    L = 64
+    assert all(x % L == 0 for x in b) and b == sorted(set(b))
+    d = [b[i + 1] - b[i] for i in range(len(b) - 1)]
+    for i in range(3):
+        assert abs(d[i + 1] / d[i] - 2.0 / 3.0) < 0.1

@@ -264,3 +264,119 @@ def test_icost_graph_replay(torch):
             assert a["J"] == b["J"], rep
             assert np.array_equal(a["lam"], b["lam"]), rep
     assert r.status()[0] == 0
+
+
+# ---- Burgers: the hybrid serial-direct-parallel-adjoint scheme (section 3.3) --
+
+def small_burgers_icost(n=256, T=0.5, nt=1024, P=64, nu=0.02, K=8, seed=7, ckpt=16, **hyb):
+    rng = np.random.default_rng(seed)
+    phases = rng.uniform(0, 2 * math.pi, K)
+    x = np.arange(n) * (2 * math.pi / n)
+    inst = dict(op="burgers1d", control="ic", cost="integral", nx=n, ny=1, L=2 * math.pi,
+                vx=0.0, vy=0.0, nu=nu, T=T, omega=1.0, beta=1e-3, n_steps=nt, P=P, m=30,
+                ckpt_every=ckpt,
+                basis=workloads.burgers_ic_modes(n, 2 * math.pi, phases),
+                a=0.3 * rng.standard_normal(K) / np.arange(1, K + 1),
+                u_tgt=0.1 * np.sin(2 * x + 0.3), q0=np.zeros(n))
+    inst.update(hyb)
+    return inst
+
+
+def run_b(insts, method="paraexp", tol=1e-9, krylov="poly"):
+    r = api.GradientRunner(insts, method=method, krylov=krylov, tol=tol)
+    r.run()
+    res = r.results()
+    code, est = r.status()
+    return res, code, r
+
+
+def test_burgers_icost_serial_matches_oracle(torch, orc):
+    """The serial march writes the step sources; the discrete adjoint adds
+    them after every reverse step, from dJ/dq(T): the oracle's arithmetic."""
+    inst = small_burgers_icost()
+    res, code, _ = run_b([inst], method="serial")
+    got, want = res[0], orc.gradient(inst)
+    eJ = abs(got["J"] - want["J"]) / abs(want["J"])
+    say("burgers icost serial: J %.2e lam0 %.2e grad %.2e" % (
+        eJ, rel(got["lam"], want["lam0"]), rel(got["grad"], want["grad"])))
+    assert code == 0
+    assert eJ < SERIAL_GATE
+    assert rel(got["qT"], want["qT"]) < SERIAL_GATE
+    assert rel(got["lam"], want["lam0"]) < SERIAL_GATE
+    assert rel(got["grad"], want["grad"]) < SERIAL_GATE
+
+
+@pytest.mark.parametrize("hyb", [dict(), dict(hyb_group=1), dict(hyb_slices=16, hyb_k=2.0),
+                                 dict(hyb_slices=7, hyb_k=1.0, hyb_group=3)])
+def test_burgers_icost_hybrid_matches_oracle(torch, orc, hyb):
+    """The hybrid scheme: march launches per adjoint slice, the adjoint
+    slices with their sources on the side stream as the march passes them,
+    then the Magnus chain from dJ/dq(T) adding each slice's end state.
+    Equal slices (one per macro step), one slice per adjoint launch, and the
+    partition of eq. nonEquiP with k = 2 and k = 1 (slices shrinking toward
+    T, rounded to the macro-step grid)."""
+    inst = small_burgers_icost(**hyb)
+    res, code, _ = run_b([inst])
+    got, want = res[0], orc.gradient(inst)
+    eJ = abs(got["J"] - want["J"]) / abs(want["J"])
+    el, eg = rel(got["lam"], want["lam0"]), rel(got["grad"], want["grad"])
+    say("burgers icost hybrid %s: J %.2e qT %.2e lam0 %.2e grad %.2e" % (
+        hyb, eJ, rel(got["qT"], want["qT"]), el, eg))
+    assert code == 0
+    # the direct is the serial march, split into launches: rounding only
+    assert rel(got["qT"], want["qT"]) < 1e-12 and eJ < 1e-12
+    assert el < FP64_GATE and eg < FP64_GATE
+
+
+def test_burgers_icost_hybrid_graph_replay(torch):
+    """The hybrid scheme's fork and join of the side stream captured in a
+    hipGraph: three replays, with eager work in between, equal the eager
+    result bit for bit."""
+    insts = [small_burgers_icost(hyb_slices=16, hyb_k=2.0)]
+    r = api.GradientRunner(insts, method="paraexp", krylov="poly", tol=1e-9)
+    r.run()
+    ref = r.results()[0]
+    ref = dict(grad=ref["grad"].copy(), J=ref["J"], lam=ref["lam"].copy())
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        r.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        r.run()
+    for rep in range(3):
+        r.grad.zero_()
+        r.J.zero_()
+        r.lam.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        b = r.results()[0]
+        assert np.array_equal(ref["grad"], b["grad"]), rep
+        assert ref["J"] == b["J"], rep
+        assert np.array_equal(ref["lam"], b["lam"]), rep
+        r.run()
+        torch.cuda.synchronize()
+    assert r.status()[0] == 0
+
+
+def test_burgers_icost_workload_vs_oracle(torch, orc):
+    """The N = 2048 Burgers workload (T = 2, 8192 steps, 128 Magnus steps,
+    checkpoints every 64) with the integral cost: hybrid scheme with 128
+    equal adjoint slices and with 32 slices of eq. nonEquiP (k = 2.5); the
+    serial method beside it."""
+    base = workloads.make("burgers1d_n2048")[0]
+    inst = dict(base, cost="integral")
+    say("burgers icost n2048: oracle (about 20 s)")
+    want = orc.gradient(inst)
+    for hyb in (dict(), dict(hyb_slices=32, hyb_k=2.5)):
+        res, code, _ = run_b([dict(inst, **hyb)])
+        got = res[0]
+        el, eg = rel(got["lam"], want["lam0"]), rel(got["grad"], want["grad"])
+        say("  hybrid %s: lam0 %.2e grad %.2e status %d" % (hyb, el, eg, code))
+        assert code == 0
+        assert el < FP64_GATE and eg < FP64_GATE
+    res, code, _ = run_b([inst], method="serial")
+    assert rel(res[0]["grad"], want["grad"]) < SERIAL_GATE
