@@ -266,3 +266,20 @@ def test_integral_cost_workload_accepted(lib):
     probs = [api.make_problem(i, krylov="uniform", sched="tree", tol=1e-9) for i in insts]
     assert all(p.flags == _lib.FLAG_INTEGRAL_COST for p in probs)
     assert _lib.pxp_workspace_size(probs) > 4 * 2049 * 128 * 128 * 8
+
+
+def test_burgers_integral_cost_rules_on_host(lib):
+    """The Burgers integral cost (hybrid scheme) is FP64 only; the hybrid
+    fields must be non-negative; the workspace grows by the adjoint slices'
+    end states and segment scratch."""
+    inst = dict(workloads.make("burgers1d_n2048")[0], cost="integral")
+    ok = api.make_problem(inst, krylov="poly")
+    plain = api.make_problem(dict(inst, cost="terminal"), krylov="poly")
+    assert _lib.pxp_workspace_size([ok]) > _lib.pxp_workspace_size([plain])
+    with pytest.raises(_lib.PxpError) as e:
+        _lib.pxp_workspace_size([api.make_problem(inst, krylov="poly", prec="fp32_bulk")])
+    assert e.value.code == _lib.PXP_EUNSUPPORTED
+    for bad in (dict(hyb_slices=-1), dict(hyb_group=-2), dict(hyb_k=-0.5)):
+        with pytest.raises(_lib.PxpError) as e:
+            _lib.pxp_workspace_size([api.make_problem(dict(inst, **bad), krylov="poly")])
+        assert e.value.code == _lib.PXP_EINVAL, bad
