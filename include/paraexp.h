@@ -121,7 +121,23 @@ enum { PXP_SCHED_CLASSIC = 0, PXP_SCHED_CHAIN = 1, PXP_SCHED_TREE = 2 };
  * reversed time) as one batch and the P-1 homogeneous pieces of their end
  * states by Krylov, each with its share of Lambda.  Default (0): the
  * unabsorbed form, one homogeneous piece from lambda_T (eq. adjhomfinal). */
-enum { PXP_FLAG_ABSORBED_ADJOINT = 1, PXP_FLAG_INTEGRAL_COST = 2 };
+enum { PXP_FLAG_ABSORBED_ADJOINT = 1, PXP_FLAG_INTEGRAL_COST = 2, PXP_FLAG_NL_PARAEXP = 4 };
+/* NL_PARAEXP (Burgers, FP64, terminal cost): the Paraexp direct solves the
+ * nonlinear equation by the iteration of section 3.2 (eqs. nlIter,
+ * nonlinTrans, Jacobians, nlHomIter, fullsolIter) instead of the serial
+ * march: with A = nu lap and N(y) = -y Dy, iterate i+1 on each of the P
+ * slices is the linear problem y' = (A + J_p) y + N(O) - J_p O, J_p the
+ * Jacobian of N at the slice's time-averaged state of iterate i (J is
+ * linear in the state, so this is the slice-averaged Jacobian), O the
+ * previous iterate's RK4 stage states; the slices from zero as one batch,
+ * the chain of exp((T_{p+1} - T_p)(A + J_p)) with each slice's end state
+ * added for the corrected slice starts, and every slice again from its
+ * corrected start for the new stage states.  The first iterate is q0 at
+ * all times; nl_iters iterations run (no host synchronisation); the last
+ * iteration's relative change of q(T) is reported as the estimate and
+ * raises PXP_EKRYLOV_NOCONV above nl_tol.  The checkpoints for the adjoint
+ * come from the last iterate.  The workspace then holds 8 n_steps n stage
+ * states. */
 /* INTEGRAL_COST (2D problems with UNIFORM or AUTO exponentials and the TREE
  * schedule; Burgers problems in FP64):
  * pxp_gradient minimises the integral cost of section 4.2 (eq. cost),
@@ -179,6 +195,9 @@ typedef struct {
     double hyb_k;                    /* their partition (eq. nonEquiP): adjoint
                                         over direct time per unit of time
                                         (0 = equal slices)                    */
+    int32_t nl_iters, nl_pad;        /* NL_PARAEXP: iterations (0 = 8)         */
+    double nl_tol;                   /* NL_PARAEXP: tolerance of the last
+                                        iteration's change (0 = krylov_tol)   */
 } pxp_problem;
 
 /* Bytes of device workspace the calls below need for this batch.
@@ -345,7 +364,8 @@ enum {
     PXP_K_SOURCES = 7,         /* integral cost: march of every slice from its
                                   corrected start writing the step sources   */
     PXP_K_ADJ_SLICES = 8,      /* integral cost: adjoint slices with sources */
-    PXP_K_LTV_CHECK = 9        /* a posteriori error of the Magnus steps    */
+    PXP_K_LTV_CHECK = 9,       /* a posteriori error of the Magnus steps    */
+    PXP_K_NL_ITER = 10         /* iterations of the nonlinear Paraexp direct */
 };
 pxp_status pxp_profile_enable(int32_t on);
 pxp_status pxp_profile_read(int32_t kernel_class, double* total_ms,

@@ -22,6 +22,7 @@ CTRL = {"forcing": 0, "ic": 1}
 KRYLOV = {"poly": 0, "shift_invert": 1, "auto": 2, "taylor": 3, "uniform": 4}
 FLAG_ABSORBED_ADJOINT = 1
 FLAG_INTEGRAL_COST = 2
+FLAG_NL_PARAEXP = 4
 SCHED = {"classic": 0, "chain": 1, "tree": 2}
 METHOD = {"paraexp": 0, "serial": 1}
 
@@ -39,7 +40,7 @@ EXPORTED = ("pxp_workspace_size", "pxp_workspace_init", "paraexp_direct",
 KCLASS = {"slices": 0, "krylov_direct": 1, "krylov_adjoint": 2,
           "serial_direct": 3, "serial_reverse": 4, "ltv_adjoint": 5,
           "ltv_nodes": 6, "sources": 7, "adj_slices": 8,
-          "ltv_check": 9}
+          "ltv_check": 9, "nl_iter": 10}
 
 
 class pxp_problem(ctypes.Structure):
@@ -57,7 +58,9 @@ class pxp_problem(ctypes.Structure):
                 ("beta", ctypes.c_double), ("krylov_tol", ctypes.c_double),
                 ("si_gamma", ctypes.c_double),
                 ("hyb_slices", ctypes.c_int32), ("hyb_group", ctypes.c_int32),
-                ("hyb_k", ctypes.c_double)]
+                ("hyb_k", ctypes.c_double),
+                ("nl_iters", ctypes.c_int32), ("nl_pad", ctypes.c_int32),
+                ("nl_tol", ctypes.c_double)]
 
 
 class pxp_tune_report(ctypes.Structure):

@@ -46,6 +46,11 @@ def make_problem(inst: dict, krylov: str = "shift_invert", sched: str = "classic
     p.hyb_slices = int(inst.get("hyb_slices", 0))
     p.hyb_group = int(inst.get("hyb_group", 0))
     p.hyb_k = float(inst.get("hyb_k", 0.0))
+    # the iterative nonlinear Paraexp of section 3.2 for the Burgers direct
+    if inst.get("nl_paraexp", False):
+        p.flags |= _lib.FLAG_NL_PARAEXP
+    p.nl_iters = int(inst.get("nl_iters", 0))
+    p.nl_tol = float(inst.get("nl_tol", 0.0))
     return p
 
 

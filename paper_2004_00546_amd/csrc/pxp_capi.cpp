@@ -46,6 +46,8 @@ struct Inst {
     size_t gsrc, lev, ebuf, islot, cpart, iwtab;
     // Burgers integral cost: hybrid scheme buffers
     size_t hstate, hmu, hseg, hbnd, haddq;
+    // Burgers nonlinear Paraexp iteration
+    size_t nst[2], nW, nv, nE, nq, naddq, ndesc;
     // Burgers: Magnus check node states (two samples x two half steps x two
     // vectors) and results (one step, two half steps per sample)
     size_t mnodes, mout, mdesc;
@@ -224,8 +226,9 @@ pxp_status validate(const pxp_problem& p) {
     if (p.krylov == PXP_KRYLOV_UNIFORM && p.op != PXP_OP_ADVDIFF2D_UPWIND) return PXP_EUNSUPPORTED;
     if (p.sched == PXP_SCHED_TREE && !uniform_direct(p)) return PXP_EUNSUPPORTED;
     if (p.prec != PXP_FP64 && p.prec != PXP_FP32_BULK) return PXP_EINVAL;
-    if ((p.flags & ~(PXP_FLAG_ABSORBED_ADJOINT | PXP_FLAG_INTEGRAL_COST)) || p.kblock < 0 ||
-        p.block < 0)
+    if ((p.flags & ~(PXP_FLAG_ABSORBED_ADJOINT | PXP_FLAG_INTEGRAL_COST |
+                     PXP_FLAG_NL_PARAEXP)) ||
+        p.kblock < 0 || p.block < 0)
         return PXP_EINVAL;
     if ((p.flags & PXP_FLAG_ABSORBED_ADJOINT) && p.op != PXP_OP_ADVDIFF1D) return PXP_EUNSUPPORTED;
     if (p.op == PXP_OP_ADVDIFF1D) {
@@ -406,6 +409,8 @@ size_t tree_kept_vectors(const TShape& sh) {
 }
 
 bool icost(const pxp_problem& p) { return (p.flags & PXP_FLAG_INTEGRAL_COST) != 0; }
+bool nlpx(const pxp_problem& p) { return (p.flags & PXP_FLAG_NL_PARAEXP) != 0; }
+int nl_iters(const pxp_problem& p) { return p.nl_iters > 0 ? p.nl_iters : 8; }
 
 // Largest Poisson parameter of the integral-cost adjoint tree: the pair at
 // the root, whose left half spans the most slices.
@@ -456,6 +461,12 @@ int hyb_group(const pxp_problem& p) { return p.hyb_group > 0 ? p.hyb_group : 4; 
 pxp_status validate_icost(const pxp_problem& p) {
     if (p.hyb_slices < 0 || p.hyb_group < 0 || !(p.hyb_k >= 0.0) || !std::isfinite(p.hyb_k))
         return PXP_EINVAL;
+    if (p.nl_iters < 0 || !(p.nl_tol >= 0.0) || !std::isfinite(p.nl_tol)) return PXP_EINVAL;
+    if (nlpx(p)) {
+        // the iteration of section 3.2: Burgers, FP64, terminal cost, at
+        // least four steps (the march's stage layout)
+        if (p.op != PXP_OP_BURGERS1D || p.prec != PXP_FP64 || icost(p)) return PXP_EUNSUPPORTED;
+    }
     if (!icost(p)) return PXP_OK;
     if (p.op == PXP_OP_BURGERS1D) {
         // the serial march's state passes between launches as FP64
@@ -534,6 +545,19 @@ Inst inst_layout(const pxp_problem& p) {
         L.mnodes = take(8 * n * d);
         L.mout = take(4 * n * d);
         L.mdesc = take(sizeof(MagnusCheck));
+        if (nlpx(p)) {
+            // two generations of stage states, the slices' averaged states,
+            // their end states, the corrected slice starts, the
+            // previous q(T), the chain's addition table, the change check
+            L.nst[0] = take(4 * (size_t)p.n_steps * n * d);
+            L.nst[1] = take(4 * (size_t)p.n_steps * n * d);
+            L.nW = take(P * n * d);
+            L.nv = take(P * n * d);
+            L.nE = take(P * n * d);
+            L.nq = take(2 * n * d);
+            L.naddq = take(P * sizeof(int));
+            L.ndesc = take(sizeof(MagnusCheck));
+        }
         if (icost(p)) {
             // the march's running state, the hybrid adjoint slices' end
             // states and segment scratch, cost partials, and the slice
@@ -897,7 +921,10 @@ pxp_status adjoint_lin1d(const Ctx& c, const double* lamT, double* lam0,
     return PXP_OK;
 }
 
-pxp_status direct_burgers(const Ctx& c, const double* q0, double* qT) {
+pxp_status direct_burgers_nl(const Ctx& c, const double* q0, double* qT);
+
+pxp_status direct_burgers(const Ctx& c, const double* q0, double* qT, int method) {
+    if (nlpx(c.p) && method == PXP_METHOD_PARAEXP) return direct_burgers_nl(c, q0, qT);
     ProfScope ps(PXP_K_SERIAL_DIRECT, c.s);
     HIPCHK(launch_rk4_burgers_direct(q0, qT, c.at(c.L.ckpt), c.n(), c.p.n_steps,
                                      c.p.ckpt_every, c.dt(), c.p.nu, c.p.L,
@@ -950,6 +977,7 @@ MagnusCheck magnus_check_desc(const Ctx& c) {
     m.n = c.n();
     m.nsamp = 2;
     m.tol = c.p.krylov_tol;
+    m.scale = 16.0 / 15.0;
     m.st = c.st;
     m.irep = c.irep;
     return m;
@@ -1011,6 +1039,82 @@ pxp_status adjoint_burgers(const Ctx& c, const double* lamT, double* lam0,
     auto* dm = reinterpret_cast<MagnusCheck*>(c.at(c.L.mdesc));
     HIPCHK(launch_upload(dm, &m, sizeof(m), c.s));
     HIPCHK(launch_magnus_check(dm, 1, c.s));
+    return PXP_OK;
+}
+
+// The iterative nonlinear Paraexp direct for Burgers (section 3.2): the
+// first iterate q0 at every stage; per iteration the slice averages, the
+// zero-start slices, the chain of the slices' linearised exponentials with
+// their end states added (the corrected slice starts kept), and every slice
+// again from its corrected start for the new stage states.  The last
+// iteration's change of q(T) is the estimate; the checkpoints come from the
+// last iterate.
+pxp_status direct_burgers_nl(const Ctx& c, const double* q0, double* qT) {
+    const pxp_problem& p = c.p;
+    const int n = c.n(), P = p.P;
+    const int64_t n_t = p.n_steps, S = n_t / P;
+    const double h = p.L / p.nx;
+    double* st[2] = {c.at(c.L.nst[0]), c.at(c.L.nst[1])};
+    double* qprev = c.at(c.L.nq);
+    std::vector<int> addq(P);
+    for (int k = 0; k < P; ++k) addq[k] = k;
+    auto* daddq = reinterpret_cast<int*>(c.at(c.L.naddq));
+    HIPCHK(launch_upload(daddq, addq.data(), std::min(addq.size() * sizeof(int), (size_t)3072),
+                         c.s));
+    for (size_t o = 3072; o < addq.size() * sizeof(int); o += 3072)
+        HIPCHK(launch_upload(reinterpret_cast<char*>(daddq) + o,
+                             reinterpret_cast<const char*>(addq.data()) + o,
+                             std::min((size_t)3072, addq.size() * sizeof(int) - o), c.s));
+    HIPCHK(launch_nl_fill(q0, st[0], n, 4 * n_t, c.s));
+    // the chain of the linearised slice exponentials: the operator is
+    // constant over a slice, so a macro step is the single factor
+    // exp((T_{p+1} - T_p)(A + J_p))
+    KrylovArgs a = kargs(c, Tri{0.0, 0.0, 0.0});
+    a.mode = KM_LTV;
+    a.ltv_one = 1;
+    a.npieces = P;
+    a.vin = q0;
+    a.yout = nullptr;  // q(T) comes from the last slice's march
+    a.tau = (double)S * c.dt();
+    a.wop = c.at(c.L.nW);
+    a.inv2h = 1.0 / (2.0 * h);
+    a.nuh2 = p.nu / (h * h);
+    a.vadd = c.at(c.L.nv);
+    a.addq = daddq;
+    a.nadd = P;
+    a.ltv_fwd = 1;
+    a.vsnap = c.at(c.L.nE);
+    a.adj = 0;
+    const int K = nl_iters(p);
+    for (int it = 0; it < K; ++it) {
+        const double* so = st[it & 1];
+        double* sn = st[(it + 1) & 1];
+        ProfScope ps(PXP_K_NL_ITER, c.s);
+        // q(T) before the last iteration, for its change
+        if (it == K - 1) HIPCHK(launch_add(nullptr, it == 0 ? q0 : qT, qprev, n, c.s));
+        HIPCHK(launch_nl_slice_mean(so, it == 0 ? q0 : qT, c.at(c.L.nW), n, S, P, c.s));
+        // every slice from zero (slice 0 too: the chain carries q0)
+        HIPCHK(launch_burgers_nl_march(so, nullptr, c.at(c.L.nv), nullptr, nullptr, nullptr,
+                                       c.at(c.L.nW), n, S, P, c.dt(), p.nu, p.L, p.block, c.s));
+        HIPCHK(launch_krylov1d(a, p.kblock, c.s));
+        HIPCHK(launch_burgers_nl_march(so, sn, nullptr, c.at(c.L.nE), q0, qT, c.at(c.L.nW), n,
+                                       S, P, c.dt(), p.nu, p.L, p.block, c.s));
+    }
+    // the change of q(T) in the last iteration (q(T) of the previous one is
+    // in qprev; with one iteration, against q0)
+    MagnusCheck m{};
+    m.y = qprev;  // pair: previous, then (copied) current
+    m.n = n;
+    m.nsamp = 1;
+    m.tol = p.nl_tol > 0.0 ? p.nl_tol : p.krylov_tol;
+    m.scale = 1.0;
+    m.st = c.st;
+    m.irep = c.irep;
+    HIPCHK(launch_add(nullptr, qT, qprev + n, n, c.s));
+    auto* dm = reinterpret_cast<MagnusCheck*>(c.at(c.L.ndesc));
+    HIPCHK(launch_upload(dm, &m, sizeof(m), c.s));
+    HIPCHK(launch_magnus_check(dm, 1, c.s));
+    HIPCHK(launch_nl_ckpt(st[K & 1], qT, c.at(c.L.ckpt), n, n_t, p.ckpt_every, c.s));
     return PXP_OK;
 }
 
@@ -1130,7 +1234,7 @@ pxp_status adjoint_burgers_icost(const Ctx& c, const double* qT, const double* t
 // Burgers instances that the ragged batch kernels take: 256 threads with a
 // supported number of points per thread.
 bool burgers_batchable(const pxp_problem& p) {
-    if (p.op != PXP_OP_BURGERS1D || p.nx % 256 || icost(p)) return false;
+    if (p.op != PXP_OP_BURGERS1D || p.nx % 256 || icost(p) || nlpx(p)) return false;
     const int pt = p.nx / 256;
     return pt == 1 || pt == 2 || pt == 4 || pt == 8 || pt == 16 || pt == 32;
 }
@@ -2478,7 +2582,7 @@ static pxp_status direct_impl(const pxp_problem* pb, int32_t batch,
             st = direct_lin1d(c, q0i, Fi, qT + off, method);
         } else {
             if (!q0i) return PXP_EINVAL;
-            st = direct_burgers(c, q0i, qT + off);
+            st = direct_burgers(c, q0i, qT + off, method);
         }
         if (st != PXP_OK) return st;
         off += (size_t)grid_n(p);
@@ -2651,7 +2755,7 @@ pxp_status pxp_gradient(const pxp_problem* pb, int32_t batch, int32_t method,
         else
             st = (p.op == PXP_OP_ADVDIFF1D)
                      ? direct_lin1d(c, ip[i].init, ip[i].F, ip[i].qT, method)
-                     : direct_burgers(c, ip[i].init, ip[i].qT);
+                     : direct_burgers(c, ip[i].init, ip[i].qT, method);
         if (st != PXP_OK) return st;
     }
     if (bb.on) {

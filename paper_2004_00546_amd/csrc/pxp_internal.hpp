@@ -86,6 +86,23 @@ struct BurgersRange {
     double* cpart;
     int src_start, pad;
 };
+// Iterative nonlinear Paraexp for Burgers (section 3.2): one workgroup per
+// slice p of P (S steps each), the linearised march of iterate i+1 with
+// the previous stage states st_old ([n_t][4][n]) as sources, from q0
+// (p = 0), E + (p-1) n or zero; writes st_new (nullable), the end states
+// reversed (vend + (P-1-p) n, nullable) and q(T) (last slice, nullable).
+hipError_t launch_burgers_nl_march(const double* st_old, double* st_new, double* vend,
+                                   const double* E, const double* q0, double* qT,
+                                   const double* W, int n, int64_t S, int P, double dt,
+                                   double nu, double L, int block, hipStream_t s);
+// W[2p] = W[2p+1] = mean of slice p's step states
+hipError_t launch_nl_slice_mean(const double* st, const double* qlast, double* W, int n,
+                                int64_t S, int P, hipStream_t s);
+// every stage state of nst = 4 n_t stages = q0
+hipError_t launch_nl_fill(const double* q0, double* st, int n, int64_t nst, hipStream_t s);
+// checkpoints every c steps from the step states, q(T) at n_t
+hipError_t launch_nl_ckpt(const double* st, const double* qT, double* ckpt, int n,
+                          int64_t n_t, int64_t c, hipStream_t s);
 // out = a (x - y) on n points
 hipError_t launch_scaled_diff(const double* x, const double* y, double a, double* out, int n,
                               hipStream_t s);
@@ -129,6 +146,7 @@ struct MagnusCheck {
     const double* y;
     int n, nsamp;
     double tol;
+    double scale;  // 16/15 (Richardson, fourth order); 1: a plain relative change
     DevStatus* st;
     InstStat* irep;
 };
@@ -191,6 +209,14 @@ struct KrylovArgs {
     const double* vadd;
     const int* addq;
     int nadd;
+    // KM_LTV: the operator J(W) itself instead of J(W)^T (the nonlinear
+    // direct iteration), and (nullable) the chain's vector after its k-th
+    // addition into vsnap + k n
+    int ltv_fwd;
+    double* vsnap;
+    // KM_LTV: one factor exp(tau J(W_k)) per macro step k (wop [npieces][n],
+    // additions after macro step addq[k]) instead of two half-step factors
+    int ltv_one;
     double* basis;       // [gridDim][m+1][n] workspace
     Sten5 op5;           // 2D: five-point operator
     int nx, ny;          // 2D: grid

@@ -390,7 +390,8 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
     double* V;
     Tsplit op;
     const double* Wcur = nullptr;  // VAR: state W of the operator J(W)^T
-    // VAR && SI: factors of (I - gamma J(W)^T) for the current W, in global
+    // VAR && SI: factors of (I - gamma J(W)^T), or of (I - gamma J(W)) with
+    // ltv_fwd, for the current W, in global
     // memory after the basis: lo, piv, cp, g, h ([l][chunk], 5n doubles),
     // then the interface rows RA, RB, RC and lo, up at the chunk starts (5B)
     double* aux = nullptr;
@@ -595,7 +596,12 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
                     const int im = i == 0 ? n - 1 : i - 1, ip = i == n - 1 ? 0 : i + 1;
                     const double xm = b0[im], xp = b0[ip], x0 = b0[i];
                     const double Wm = Wcur[im], Wp = Wcur[ip];
-                    if (a.fp32) {
+                    if (a.ltv_fwd) {
+                        // (J(W) x)_i = nu lap(x)_i - W_i (x_{i+1} - x_{i-1})/(2h)
+                        //             - x_i (W_{i+1} - W_{i-1})/(2h)
+                        z[r * VW + v] = a.nuh2 * ((xp + xm) - 2.0 * x0)
+                                        - a.inv2h * (Wcur[i] * (xp - xm) + x0 * (Wp - Wm));
+                    } else if (a.fp32) {
                         const float fxm = (float)xm, fxp = (float)xp, fx0 = (float)x0;
                         const float fWm = (float)Wm, fWp = (float)Wp;
                         z[r * VW + v] = (double)((float)a.nuh2 * ((fxp + fxm) - 2.0f * fx0)
@@ -631,12 +637,19 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
     // Row i of (I - gamma J(W)^T): lo x_{i-1} + d x_i + up x_{i+1}, with
     // (J(W)^T x)_i = (W_{i+1} x_{i+1} - W_{i-1} x_{i-1})/(2h)
     //               - (W_{i+1} - W_{i-1}) x_i/(2h) + nu (x_{i+1} - 2x_i + x_{i-1})/h^2.
+    // With ltv_fwd, row i of (I - gamma J(W)) from
+    // (J(W) x)_i = nu lap(x)_i - W_i (x_{i+1} - x_{i-1})/(2h) - (W_{i+1} - W_{i-1}) x_i/(2h).
     __device__ __forceinline__ void var_row(int i, double gamma, double& lo, double& d,
                                             double& up) const {
         const int im = i == 0 ? n - 1 : i - 1, ip = i == n - 1 ? 0 : i + 1;
         const double Wm = Wcur[im], Wp = Wcur[ip];
-        lo = -gamma * (a.nuh2 - a.inv2h * Wm);
-        up = -gamma * (a.nuh2 + a.inv2h * Wp);
+        if (a.ltv_fwd) {
+            lo = -gamma * (a.nuh2 + a.inv2h * Wcur[i]);
+            up = -gamma * (a.nuh2 - a.inv2h * Wcur[i]);
+        } else {
+            lo = -gamma * (a.nuh2 - a.inv2h * Wm);
+            up = -gamma * (a.nuh2 + a.inv2h * Wp);
+        }
         d = 1.0 + gamma * (2.0 * a.nuh2 + a.inv2h * (Wp - Wm));
     }
 
@@ -811,9 +824,14 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
                         const int i = gidx(r) + v;
                         const double Wm = Wcur[i == 0 ? n - 1 : i - 1];
                         const double Wp = Wcur[i == n - 1 ? 0 : i + 1];
-                        const double rs = 2.0 * a.nuh2 + fabs(a.nuh2 + a.inv2h * Wp) +
-                                          fabs(a.nuh2 - a.inv2h * Wm) +
-                                          fabs(a.inv2h * (Wp - Wm));
+                        // absolute row sum of J(W)^T (or of J(W))
+                        const double rs =
+                            a.ltv_fwd ? 2.0 * a.nuh2 + fabs(a.nuh2 - a.inv2h * Wcur[i]) +
+                                            fabs(a.nuh2 + a.inv2h * Wcur[i]) +
+                                            fabs(a.inv2h * (Wp - Wm))
+                                      : 2.0 * a.nuh2 + fabs(a.nuh2 + a.inv2h * Wp) +
+                                            fabs(a.nuh2 - a.inv2h * Wm) +
+                                            fabs(a.inv2h * (Wp - Wm));
                         mx = fmax(mx, rs);
                     }
                 }
@@ -1153,7 +1171,7 @@ __device__ __forceinline__ void dev_krylov1d(const KrylovArgs& a, int piece, dou
     // slice end state after each; single: one exponential with integral.
     // ltv: 2 * npieces exponentials, each with its own operator state.
     const int nexp = (a.mode == KM_CHAIN) ? a.npieces - 1
-                   : (a.mode == KM_LTV) ? 2 * a.npieces : 1;
+                   : (a.mode == KM_LTV) ? (a.ltv_one ? a.npieces : 2 * a.npieces) : 1;
     const double tau = (a.mode == KM_CLASSIC) ? (double)(a.npieces - piece) * a.tau : a.tau;
     const double ia = (a.mode == KM_CLASSIC) ? a.ia * tau : a.ia;
     if (VAR && SI) c.aux = V + (size_t)(a.m + 1) * n;
@@ -1169,15 +1187,18 @@ __device__ __forceinline__ void dev_krylov1d(const KrylovArgs& a, int piece, dou
             for (int u = 0; u < PT; ++u) w[u] += x[u];
             c.gstore(V, w);
         }
-        // time-varying chain: after a macro step (two factors) that ends on
-        // an adjoint slice start, add that slice's end state
-        if (VAR && a.vadd && (q & 1) && nextadd < a.nadd && a.addq[nextadd] == (q >> 1)) {
+        // time-varying chain: after a macro step (two factors, or one) that
+        // ends on a slice start, add that slice's end state
+        const bool mend = a.ltv_one || (q & 1);
+        const int mstep = a.ltv_one ? q : (q >> 1);
+        if (VAR && a.vadd && mend && nextadd < a.nadd && a.addq[nextadd] == mstep) {
             double x[PT], w[PT];
             c.gload(a.vadd + (size_t)(a.nadd - 1 - nextadd) * n, x);
             c.gload(V, w);
 #pragma unroll
             for (int u = 0; u < PT; ++u) w[u] += x[u];
             c.gstore(V, w);
+            if (a.vsnap) c.gstore(a.vsnap + (size_t)nextadd * n, w);
             ++nextadd;
         }
     }

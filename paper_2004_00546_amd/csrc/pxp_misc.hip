@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(256) k_magnus_check(const MagnusCheck* __restr
             bb += b[i] * b[i];
         }
         block_sum2(dd, bb, red, slot);
-        const double e = bb > 0.0 ? (16.0 / 15.0) * sqrt(dd / bb) : 0.0;
+        const double e = bb > 0.0 ? d.scale * sqrt(dd / bb) : 0.0;
         est = fmax(est, e);
     }
     if (threadIdx.x != 0) return;

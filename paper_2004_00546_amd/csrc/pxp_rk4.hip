@@ -788,6 +788,153 @@ k_burgers_nodes(const double* __restrict__ ckpt, double* __restrict__ Wout, int 
                              (int)blockIdx.x, lds_d);
 }
 
+// ---- Burgers: the iterative nonlinear Paraexp (section 3.2) ----------------
+// Burgers as y' = A y + N(y), A = nu lap (linear), N(y) = -y Dy.  Iterate
+// i+1 on slice p solves the linear problem (eq. nonlinTrans)
+//   y' = (A + J_p) y + N(O) - J_p O,   J_p = J(ubar_p) = -ubar_p D - diag(D ubar_p)
+// (J is linear in the state, so the slice-averaged Jacobian of eq.
+// Jacobians is the Jacobian at the slice-averaged state), where O are the
+// previous iterate's RK4 stage states: at the fixed point every stage's
+// source is N at that stage's own state, the nonlinear RK4 stage.  The
+// right-hand side of a stage with state Y and previous stage state O:
+//   F = nu lap Y - ubar (DY - DO) - (D ubar)(Y - O) - O DO.
+
+// Stage states st[(s * 4 + k) * n], k = 0..3 (Y1 = the step state).
+template <int PT>
+__device__ __forceinline__ void nl_rhs(const double (&Y)[PT], const double (&O)[PT],
+                                       double yl, double yr, double ol, double orr,
+                                       const double (&ub)[PT], const double (&dub)[PT],
+                                       double inv2h, double nuh2, double (&F)[PT]) {
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+        const double ym = (q == 0) ? yl : Y[q - 1], yp = (q == PT - 1) ? yr : Y[q + 1];
+        const double om = (q == 0) ? ol : O[q - 1], op = (q == PT - 1) ? orr : O[q + 1];
+        const double dy = (yp - ym) * inv2h, dO = (op - om) * inv2h;
+        F[q] = nuh2 * ((yp + ym) - 2.0 * Y[q]) - ub[q] * (dy - dO) - dub[q] * (Y[q] - O[q]) -
+               O[q] * dO;
+    }
+}
+
+// Slice p (one workgroup) of iterate i+1: RK4 over steps [p S, (p+1) S)
+// from q0 (p = 0, when q0 is set), E + (p-1) n (p > 0, the corrected
+// start, when E is set) or zero, with the stage sources of the previous stages st_old; writes the
+// new stage states (st_new, nullable), the end state reversed for the
+// chain (vend + (P-1-p) n, nullable) and, for the last slice, q(T) (qT,
+// nullable).
+template <int PT>
+__device__ __forceinline__ void dev_burgers_nl_march(
+    const double* __restrict__ st_old, double* __restrict__ st_new, double* __restrict__ vend,
+    const double* __restrict__ E, const double* __restrict__ q0, double* __restrict__ qT,
+    const double* __restrict__ W, int n, int64_t S, int P, double dt, BurgersC bc,
+    double* lds_d) {
+    const int p = blockIdx.x;
+    const int base = threadIdx.x * PT;
+    double* lds = lds_d;
+    int buf = 0;
+    const double inv2h = bc.inv2h, nuh2 = bc.nuh2;
+    // the slice's averaged state and its central difference
+    double ub[PT], dub[PT];
+    {
+        const double* w = W + (size_t)p * n;
+#pragma unroll
+        for (int q = 0; q < PT; ++q) ub[q] = w[base + q];
+        double l[1], r[1];
+        const double* arr[1] = {ub};
+        exch<PT, 1, 2>(arr, lds, buf, l, r);
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            const double um = (q == 0) ? l[0] : ub[q - 1], up = (q == PT - 1) ? r[0] : ub[q + 1];
+            dub[q] = (up - um) * inv2h;
+        }
+    }
+    double y[PT];
+    const double* y0 = (p == 0) ? q0 : (E ? E + (size_t)(p - 1) * n : nullptr);
+#pragma unroll
+    for (int q = 0; q < PT; ++q) y[q] = y0 ? y0[base + q] : 0.0;
+    const int64_t a = (int64_t)p * S;
+    for (int64_t s = a; s < a + S; ++s) {
+        double Y[PT], O[PT], F[PT], acc[PT];
+        const double cf[4] = {0.0, 0.5, 0.5, 1.0};
+#pragma unroll 1
+        for (int k = 0; k < 4; ++k) {
+            // stage state from the previous stage's slope
+#pragma unroll
+            for (int q = 0; q < PT; ++q) Y[q] = (k == 0) ? y[q] : y[q] + cf[k] * dt * F[q];
+            const double* o = st_old + (size_t)(s * 4 + k) * n;
+#pragma unroll
+            for (int q = 0; q < PT; ++q) O[q] = o[base + q];
+            if (st_new) {
+                double* w = st_new + (size_t)(s * 4 + k) * n;
+#pragma unroll
+                for (int q = 0; q < PT; ++q) w[base + q] = Y[q];
+            }
+            double l[2], r[2];
+            const double* arr[2] = {Y, O};
+            exch<PT, 2, 2>(arr, lds, buf, l, r);
+            nl_rhs<PT>(Y, O, l[0], r[0], l[1], r[1], ub, dub, inv2h, nuh2, F);
+#pragma unroll
+            for (int q = 0; q < PT; ++q) acc[q] = (k == 0) ? F[q] : acc[q] + ((k == 3) ? 1.0 : 2.0) * F[q];
+        }
+#pragma unroll
+        for (int q = 0; q < PT; ++q) y[q] += (dt / 6.0) * acc[q];
+    }
+    if (vend) {
+        double* v = vend + (size_t)(P - 1 - p) * n;
+#pragma unroll
+        for (int q = 0; q < PT; ++q) v[base + q] = y[q];
+    }
+    if (qT && p == P - 1) {
+#pragma unroll
+        for (int q = 0; q < PT; ++q) qT[base + q] = y[q];
+    }
+}
+
+template <int PT, typename R>
+__global__ void __launch_bounds__(max_block<PT>())
+k_burgers_nl_march(const double* __restrict__ st_old, double* __restrict__ st_new,
+                   double* __restrict__ vend, const double* __restrict__ E,
+                   const double* __restrict__ q0, double* __restrict__ qT,
+                   const double* __restrict__ W, int n, int64_t S, int P, double dt,
+                   BurgersC bc) {
+    extern __shared__ double lds_d[];
+    dev_burgers_nl_march<PT>(st_old, st_new, vend, E, q0, qT, W, n, S, P, dt, bc, lds_d);
+}
+
+// ubar_p = time average of the previous iterate over slice p by the
+// trapezoidal rule on the step grid: the step states pS .. (p+1)S (stage 0
+// of each step; the last slice ends on that iterate's q(T), qlast); grid
+// (n / 256, P).
+__global__ void k_nl_slice_mean(const double* __restrict__ st, const double* __restrict__ qlast,
+                                double* __restrict__ W, int n, int64_t S, int P) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = blockIdx.y;
+    if (i >= n) return;
+    const int64_t s0 = (int64_t)p * S, s1 = s0 + S;
+    double a = 0.5 * st[(size_t)(s0 * 4) * n + i];
+    for (int64_t s = s0 + 1; s < s1; ++s) a += st[(size_t)(s * 4) * n + i];
+    a += 0.5 * ((p == P - 1) ? qlast[i] : st[(size_t)(s1 * 4) * n + i]);
+    W[(size_t)p * n + i] = a / (double)S;
+}
+
+// The first guess: every stage state of every step equals q0.
+__global__ void k_nl_fill(const double* __restrict__ q0, double* __restrict__ st, int n,
+                          int64_t nst) {
+    const size_t tot = (size_t)nst * n;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < tot;
+         k += (size_t)gridDim.x * blockDim.x)
+        st[k] = q0[k % n];
+}
+
+// Checkpoints of the final iterate: the step states every c steps, and q(T).
+__global__ void k_nl_ckpt(const double* __restrict__ st, const double* __restrict__ qT,
+                          double* __restrict__ ckpt, int n, int64_t n_t, int64_t c) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = blockIdx.y;
+    if (i >= n) return;
+    const int64_t s = j * c;
+    ckpt[(size_t)j * n + i] = (s == n_t) ? qT[i] : st[(size_t)(s * 4) * n + i];
+}
+
 // ---- ragged batches: one launch over all instances -------------------------
 // Every workgroup reads its instance from the descriptor table and runs the
 // march for that instance's points per thread (256 threads per workgroup,
@@ -1027,6 +1174,39 @@ hipError_t launch_rk4_burgers_reverse(const double* ckpt, const double* lamT,
         return hipErrorInvalidValue;
     PXP_DISPATCH(fp32, pt, k_rk4_burgers_reverse,
                  <<<1, block, lds, s>>>(ckpt, lamT, lam0, seg, n, n_t, c, dt, bc, rg))
+    return hipGetLastError();
+}
+
+hipError_t launch_burgers_nl_march(const double* st_old, double* st_new, double* vend,
+                                   const double* E, const double* q0, double* qT,
+                                   const double* W, int n, int64_t S, int P, double dt,
+                                   double nu, double L, int block_hint, hipStream_t s) {
+    int block, pt;
+    if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
+    const double h = L / n;
+    BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
+    const size_t lds = sizeof(double) * 8 * block;
+    PXP_DISPATCH_PT(pt, k_burgers_nl_march, double,
+                    <<<P, block, lds, s>>>(st_old, st_new, vend, E, q0, qT, W, n, S, P, dt, bc))
+    return hipGetLastError();
+}
+
+hipError_t launch_nl_slice_mean(const double* st, const double* qlast, double* W, int n,
+                                int64_t S, int P, hipStream_t s) {
+    dim3 g((unsigned)((n + 255) / 256), (unsigned)P);
+    k_nl_slice_mean<<<g, 256, 0, s>>>(st, qlast, W, n, S, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_nl_fill(const double* q0, double* st, int n, int64_t nst, hipStream_t s) {
+    k_nl_fill<<<1024, 256, 0, s>>>(q0, st, n, nst);
+    return hipGetLastError();
+}
+
+hipError_t launch_nl_ckpt(const double* st, const double* qT, double* ckpt, int n,
+                          int64_t n_t, int64_t c, hipStream_t s) {
+    dim3 g((unsigned)((n + 255) / 256), (unsigned)(n_t / c + 1));
+    k_nl_ckpt<<<g, 256, 0, s>>>(st, qT, ckpt, n, n_t, c);
     return hipGetLastError();
 }
 

@@ -49,8 +49,8 @@ def test_version_and_status_strings(lib):
 
 
 def test_struct_layout_matches_header():
-    # 14 int32, 1 int64, 9 doubles, then 2 int32 and a double
-    assert ctypes.sizeof(_lib.pxp_problem) == 14 * 4 + 8 + 9 * 8 + 2 * 4 + 8
+    # 14 int32, 1 int64, 9 doubles, then twice 2 int32 and a double
+    assert ctypes.sizeof(_lib.pxp_problem) == 14 * 4 + 8 + 9 * 8 + 2 * (2 * 4 + 8)
 
 
 def _size_status(probs):
@@ -175,7 +175,7 @@ def test_problem_flags():
     absorbed = api.make_problem(inst, krylov="poly", absorbed=True)
     assert _lib.pxp_workspace_size([absorbed]) > _lib.pxp_workspace_size([plain])
     bad = api.make_problem(inst, krylov="poly")
-    bad.flags = 4
+    bad.flags = 8
     with pytest.raises(_lib.PxpError) as e:
         _lib.pxp_workspace_size([bad])
     assert e.value.code == _lib.PXP_EINVAL
@@ -283,3 +283,31 @@ def test_burgers_integral_cost_rules_on_host(lib):
         with pytest.raises(_lib.PxpError) as e:
             _lib.pxp_workspace_size([api.make_problem(dict(inst, **bad), krylov="poly")])
         assert e.value.code == _lib.PXP_EINVAL, bad
+
+
+def test_nl_paraexp_rules_on_host(lib):
+    """The iterative nonlinear direct (section 3.2) is a Burgers FP64 path
+    with the terminal cost; its workspace holds two generations of stage
+    states (8 n_steps n doubles) and the slices' states; negative iteration
+    counts and tolerances are refused."""
+    base = workloads.make("burgers1d_n2048")[0]
+    inst = dict(base, nl_paraexp=True)
+    ok = api.make_problem(inst, krylov="auto")
+    assert ok.flags == _lib.FLAG_NL_PARAEXP
+    plain = api.make_problem(base, krylov="auto")
+    n, nt = 2048, 8192
+    assert _lib.pxp_workspace_size([ok]) - _lib.pxp_workspace_size([plain]) >= 8 * nt * n * 8
+    for bad, code in [(dict(prec="fp32_bulk"), _lib.PXP_EUNSUPPORTED)]:
+        with pytest.raises(_lib.PxpError) as e:
+            _lib.pxp_workspace_size([api.make_problem(inst, krylov="auto", **bad)])
+        assert e.value.code == code, bad
+    for bad, code in [(dict(cost="integral"), _lib.PXP_EUNSUPPORTED),
+                      (dict(nl_iters=-1), _lib.PXP_EINVAL),
+                      (dict(nl_tol=-1.0), _lib.PXP_EINVAL)]:
+        with pytest.raises(_lib.PxpError) as e:
+            _lib.pxp_workspace_size([api.make_problem(dict(inst, **bad), krylov="auto")])
+        assert e.value.code == code, bad
+    lin = dict(workloads.make("advdiff1d_n128")[0], nl_paraexp=True)
+    with pytest.raises(_lib.PxpError) as e:
+        _lib.pxp_workspace_size([api.make_problem(lin, krylov="poly")])
+    assert e.value.code == _lib.PXP_EUNSUPPORTED
