@@ -166,6 +166,24 @@ def time_runner(torch, r, steps, warmup, seconds=1.0):
     return (time.perf_counter() - t0) / steps
 
 
+def profile_classes(torch, _lib, r, steps):
+    """Per-class kernel time (ms per call) over `steps` calls of r, from the
+    library's events."""
+    _lib.pxp_profile_enable(True)
+    for k in _lib.KCLASS:
+        _lib.pxp_profile_read(k)
+    for _ in range(steps):
+        r.run()
+    torch.cuda.synchronize()
+    _lib.pxp_profile_enable(False)
+    out = {}
+    for k in _lib.KCLASS:
+        ms, cnt = _lib.pxp_profile_read(k)
+        if cnt:
+            out[k] = ms / steps
+    return out
+
+
 def time_graph(torch, r, steps):
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -353,7 +371,8 @@ def measure(args, name, torch, _lib, api, workloads, steps, serial_steps, with_o
         insts = insts[:args.instances]
     if name == args.workload:
         for key, v in (("hyb_slices", args.hyb_slices), ("hyb_k", args.hyb_k),
-                       ("hyb_group", args.hyb_group)):
+                       ("hyb_group", args.hyb_group), ("nl_iters", args.nl_iters),
+                       ("nl_tol", args.nl_tol), ("P", args.slices)):
             if v is not None:
                 insts = [dict(x, **{key: v}) for x in insts]
     inst = insts[0]
@@ -422,11 +441,12 @@ def measure(args, name, torch, _lib, api, workloads, steps, serial_steps, with_o
         t_graph = time_graph(torch, pxp, steps)
         log("paraexp, hipGraph replay %.3f ms/step" % (t_graph * 1e3))
 
-    t_ser, res_ser = None, None
+    t_ser, res_ser, kern_ser = None, None, {}
     if serial_steps > 0:
         t_ser = time_runner(torch, ser, serial_steps, 1)
         res_ser = ser.results()
-        log("serial %.3f ms/step" % (t_ser * 1e3))
+        kern_ser = profile_classes(torch, _lib, ser, serial_steps)
+        log("serial %.3f ms/step  kernels %s" % (t_ser * 1e3, kern_ser))
 
     # accuracy against the oracle on a bounded sample of the instances, run
     # instance-parallel; the same runs time the CPU baseline
@@ -471,7 +491,8 @@ def measure(args, name, torch, _lib, api, workloads, steps, serial_steps, with_o
     gate = 1e-8 if args.prec == "fp64" else 1e-5
     ok = (err is not None and err["paraexp_grad"] <= gate and err["paraexp_qT"] <= gate
           and code == 0)
-    out = dict(name=name, B=B, P=sorted({int(p.P) for p in pxp.problems}), t_pxp=t_pxp, t_ser=t_ser, t_graph=t_graph, ok=ok, gate=gate,
+    out = dict(name=name, B=B, P=sorted({int(p.P) for p in pxp.problems}), t_pxp=t_pxp,
+               t_ser=t_ser, t_graph=t_graph, ok=ok, gate=gate, kern_ser=kern_ser, steps=steps,
                err=err, sample=sample, kern=kern, counters=counters, est=est, code=code,
                roof=roof, roof_all=roof_all, tuned=tuned, report=report, sched=sched,
                insts=insts, work=work, orc=orc)
@@ -525,6 +546,56 @@ def hybrid_model(inst, kern, t_ser):
             "ceiling_speedup": serial_model / (nt * tau_i + ch)}
 
 
+def nl_model(inst, kern, kern_ser, t_pxp, t_ser, report, steps):
+    """The iterative nonlinear direct's times against eq. nonLinSpeedup,
+    per RK4 step of one slice or of the horizon: tau_I (the slices' Jacobians
+    and the slices from zero, S steps per iteration), tau_H (the chain of
+    slice exponentials, n_t - S steps of time per iteration), tau_F (the
+    slices marched again from their corrected starts and the change check,
+    S steps: the iterate at the stage points, a step the paper's sum
+    formulation does not have), tau_D^S and tau_A^S (serial march and
+    serial discrete adjoint, per step).  Predicted T_L = K (S tau_I +
+    (n_t - S) tau_H + S tau_F) + the parallel adjoint as measured; the
+    speedup condition of eq. speedupCond and the ceiling (N -> infinity)
+    follow from eq. nonLinSpeedup with the adjoint's parallel cost split the
+    same way (tau_I^dagger: the Magnus node states over a slice, tau_H^dagger:
+    the Magnus chain per step)."""
+    nt, P = int(inst["n_steps"]), int(inst["P"])
+    S = nt // P
+    if not report or not t_ser:
+        return None
+    K = sum(r["nl_iterations"] for r in report) / steps
+    if K <= 0:
+        return None
+    sl = kern.get("slices", {}).get("per_step_ms", 0.0) / K
+    ch = kern.get("krylov_direct", {}).get("per_step_ms", 0.0) / K
+    fm = kern.get("nl_iter", {}).get("per_step_ms", 0.0) / K
+    adj = sum(kern.get(k, {}).get("per_step_ms", 0.0)
+              for k in ("ltv_adjoint", "ltv_nodes", "ltv_check", "serial_reverse"))
+    tau_i, tau_h, tau_f = sl / S, ch / (nt - S), fm / S
+    tau_ds = kern_ser.get("serial_direct", 0.0) / nt
+    tau_as = kern_ser.get("serial_reverse", 0.0) / nt
+    tau_ia = kern.get("ltv_nodes", {}).get("per_step_ms", 0.0) / S
+    tau_ha = kern.get("ltv_adjoint", {}).get("per_step_ms", 0.0) / (nt - S)
+    pred = K * (S * tau_i + (nt - S) * tau_h + S * tau_f) + adj
+    # s > 1 iff N (tau_D^S + tau_A^S - K tau_H - tau_H^dagger)
+    #           > K (tau_I + tau_F - tau_H) + tau_I^dagger - tau_H^dagger
+    den = tau_ds + tau_as - K * tau_h - tau_ha
+    num = K * (tau_i + tau_f - tau_h) + tau_ia - tau_ha
+    return {"iterations": K, "slices": P,
+            "per_iteration_ms": {"jacobians_and_slices": sl, "chain": ch,
+                                 "iterate_and_change": fm},
+            "adjoint_ms": adj, "serial_direct_ms": kern_ser.get("serial_direct"),
+            "serial_adjoint_ms": kern_ser.get("serial_reverse"),
+            "tau_us_per_step": {"I": tau_i * 1e3, "H": tau_h * 1e3, "F": tau_f * 1e3,
+                                "D_serial": tau_ds * 1e3, "A_serial": tau_as * 1e3,
+                                "I_adj": tau_ia * 1e3, "H_adj": tau_ha * 1e3},
+            "predicted_ms": pred, "measured_ms": t_pxp * 1e3,
+            "speedup_vs_serial": t_ser / t_pxp,
+            "min_slices_for_speedup": (num / den) if den > 0 else None,
+            "ceiling_speedup": (tau_ds + tau_as) / (K * tau_h + tau_ha)}
+
+
 def summary_report(report):
     """Per-instance report condensed to ranges."""
     if not report:
@@ -574,6 +645,12 @@ def main():
                     help="Burgers integral cost: k of eq. nonEquiP (0 = equal slices)")
     ap.add_argument("--hyb-group", type=int, default=None,
                     help="Burgers integral cost: adjoint slices per launch")
+    ap.add_argument("--nl-iters", type=int, default=None,
+                    help="iterative nonlinear direct: most iterations")
+    ap.add_argument("--nl-tol", type=float, default=None,
+                    help="iterative nonlinear direct: change of q(T) that ends it")
+    ap.add_argument("--slices", type=int, default=None,
+                    help="override the workload's slice count P")
     ap.add_argument("--instances", type=int, default=0,
                     help="use only the first K instances of a batch workload (0 = all)")
     ap.add_argument("--oracle-budget", type=float, default=2.5e8,
@@ -667,6 +744,11 @@ def main():
         line["graph"] = {"value": B / m["t_graph"], "ms_per_step": m["t_graph"] * 1e3}
     if inst["op"] == "burgers1d" and inst.get("cost") == "integral" and B == 1:
         line["hybrid_model"] = hybrid_model(inst, m["kern"], m["t_ser"])
+    if inst.get("nl_paraexp") and B == 1:
+        cfg["direct"] = "iterative nonlinear Paraexp (at most %d iterations)" % int(
+            inst.get("nl_iters", 8))
+        line["nl_model"] = nl_model(inst, m["kern"], m["kern_ser"], m["t_pxp"], m["t_ser"],
+                                    m["report"], m["steps"])
     if m["orc"] is not None and not args.no_cpu_baseline:
         o = m["orc"]
         work = m["work"]

@@ -127,13 +127,17 @@ enum { PXP_FLAG_ABSORBED_ADJOINT = 1, PXP_FLAG_INTEGRAL_COST = 2, PXP_FLAG_NL_PA
  * nonlinTrans, Jacobians, nlHomIter, fullsolIter) instead of the serial
  * march: with A = nu lap and N(y) = -y Dy, iterate i+1 on each of the P
  * slices is the linear problem y' = (A + J_p) y + N(O) - J_p O, J_p the
- * Jacobian of N at the slice's time-averaged state of iterate i (J is
- * linear in the state, so this is the slice-averaged Jacobian), O the
- * previous iterate's RK4 stage states; the slices from zero as one batch,
- * the chain of exp((T_{p+1} - T_p)(A + J_p)) with each slice's end state
- * added for the corrected slice starts, and every slice again from its
- * corrected start for the new stage states.  The first iterate is q0 at
- * all times; nl_iters iterations run (no host synchronisation); the last
+ * Jacobian of N at the time average of iterate i over the slice (the
+ * trapezoidal rule on the step grid; J is linear in the state, so this is
+ * the slice-averaged Jacobian), O the previous iterate's RK4 stage states;
+ * the slices from zero as one batch, the chain of one exponential
+ * exp((T_{p+1} - T_p)(A + J_p)) per slice (the krylov flavour as for the
+ * adjoint's factors) with each slice's end state added for the corrected
+ * slice starts, and every slice again from its corrected start for the new
+ * stage states.  The first iterate is q0 at all times; after every
+ * iteration the relative change of q(T), and once it is within nl_tol the
+ * remaining launches of the call return at once (at most nl_iters
+ * iterations; no host synchronisation); the last
  * iteration's relative change of q(T) is reported as the estimate and
  * raises PXP_EKRYLOV_NOCONV above nl_tol.  The checkpoints for the adjoint
  * come from the last iterate.  The workspace then holds 8 n_steps n stage
@@ -195,9 +199,10 @@ typedef struct {
     double hyb_k;                    /* their partition (eq. nonEquiP): adjoint
                                         over direct time per unit of time
                                         (0 = equal slices)                    */
-    int32_t nl_iters, nl_pad;        /* NL_PARAEXP: iterations (0 = 8)         */
-    double nl_tol;                   /* NL_PARAEXP: tolerance of the last
-                                        iteration's change (0 = krylov_tol)   */
+    int32_t nl_iters, nl_pad;        /* NL_PARAEXP: most iterations (0 = 8)    */
+    double nl_tol;                   /* NL_PARAEXP: relative change of q(T)
+                                        that ends the iteration
+                                        (0 = krylov_tol)                      */
 } pxp_problem;
 
 /* Bytes of device workspace the calls below need for this batch.
@@ -339,11 +344,13 @@ pxp_status pxp_device_counters_class(void* ws, size_t ws_bytes, void* stream, in
  * Krylov substeps (uniformised exponentials: one per exponential);
  * iterations counts Arnoldi steps or series terms; max_est is the largest
  * error estimate, relative to |v| (Krylov: a posteriori; uniformisation: the
- * a priori Poisson tail). */
+ * a priori Poisson tail); nl_iterations counts the iterations of the
+ * nonlinear Paraexp direct that ran (NL_PARAEXP; 0 otherwise). */
 typedef struct {
     int32_t P, sched, krylov_direct, krylov_adjoint;
     uint64_t substeps, iterations;
-    double max_est, pad;
+    double max_est;
+    int32_t nl_iterations, pad;
 } pxp_report;
 pxp_status pxp_last_report(const pxp_problem* pb, int32_t batch, void* ws, size_t ws_bytes,
                            void* stream, pxp_report* out);

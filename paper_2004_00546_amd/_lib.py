@@ -75,7 +75,8 @@ class pxp_report(ctypes.Structure):
     _fields_ = [("P", ctypes.c_int32), ("sched", ctypes.c_int32),
                 ("krylov_direct", ctypes.c_int32), ("krylov_adjoint", ctypes.c_int32),
                 ("substeps", ctypes.c_uint64), ("iterations", ctypes.c_uint64),
-                ("max_est", ctypes.c_double), ("pad", ctypes.c_double)]
+                ("max_est", ctypes.c_double), ("nl_iterations", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class PxpError(RuntimeError):

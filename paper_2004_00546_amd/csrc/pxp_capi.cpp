@@ -554,9 +554,9 @@ Inst inst_layout(const pxp_problem& p) {
             L.nW = take(P * n * d);
             L.nv = take(P * n * d);
             L.nE = take(P * n * d);
-            L.nq = take(2 * n * d);
+            L.nq = take(n * d);
             L.naddq = take(P * sizeof(int));
-            L.ndesc = take(sizeof(MagnusCheck));
+            L.ndesc = take(sizeof(NlState));
         }
         if (icost(p)) {
             // the march's running state, the hybrid adjoint slices' end
@@ -1046,26 +1046,26 @@ pxp_status adjoint_burgers(const Ctx& c, const double* lamT, double* lam0,
 // first iterate q0 at every stage; per iteration the slice averages, the
 // zero-start slices, the chain of the slices' linearised exponentials with
 // their end states added (the corrected slice starts kept), and every slice
-// again from its corrected start for the new stage states.  The last
-// iteration's change of q(T) is the estimate; the checkpoints come from the
-// last iterate.
+// again from its corrected start for the new stage states, and the change
+// of q(T), which ends the iteration once within tolerance.  The last
+// change is the estimate; the checkpoints come from the last iterate.
 pxp_status direct_burgers_nl(const Ctx& c, const double* q0, double* qT) {
     const pxp_problem& p = c.p;
     const int n = c.n(), P = p.P;
     const int64_t n_t = p.n_steps, S = n_t / P;
     const double h = p.L / p.nx;
+    const double tol = p.nl_tol > 0.0 ? p.nl_tol : p.krylov_tol;
     double* st[2] = {c.at(c.L.nst[0]), c.at(c.L.nst[1])};
     double* qprev = c.at(c.L.nq);
+    auto* ns = reinterpret_cast<NlState*>(c.at(c.L.ndesc));
     std::vector<int> addq(P);
     for (int k = 0; k < P; ++k) addq[k] = k;
     auto* daddq = reinterpret_cast<int*>(c.at(c.L.naddq));
-    HIPCHK(launch_upload(daddq, addq.data(), std::min(addq.size() * sizeof(int), (size_t)3072),
-                         c.s));
-    for (size_t o = 3072; o < addq.size() * sizeof(int); o += 3072)
+    for (size_t o = 0; o < addq.size() * sizeof(int); o += 3072)
         HIPCHK(launch_upload(reinterpret_cast<char*>(daddq) + o,
                              reinterpret_cast<const char*>(addq.data()) + o,
                              std::min((size_t)3072, addq.size() * sizeof(int) - o), c.s));
-    HIPCHK(launch_nl_fill(q0, st[0], n, 4 * n_t, c.s));
+    HIPCHK(launch_nl_fill(q0, st[0], qprev, ns, n, 4 * n_t, c.s));
     // the chain of the linearised slice exponentials: the operator is
     // constant over a slice, so a macro step is the single factor
     // exp((T_{p+1} - T_p)(A + J_p))
@@ -1085,36 +1085,37 @@ pxp_status direct_burgers_nl(const Ctx& c, const double* q0, double* qT) {
     a.ltv_fwd = 1;
     a.vsnap = c.at(c.L.nE);
     a.adj = 0;
+    a.skip = &ns->done;
+    // up to nl_iters iterations; once an iteration's change of q(T) is
+    // within tol the remaining launches return at once (algorithm 2's
+    // while loop without a host synchronisation)
     const int K = nl_iters(p);
     for (int it = 0; it < K; ++it) {
         const double* so = st[it & 1];
         double* sn = st[(it + 1) & 1];
-        ProfScope ps(PXP_K_NL_ITER, c.s);
-        // q(T) before the last iteration, for its change
-        if (it == K - 1) HIPCHK(launch_add(nullptr, it == 0 ? q0 : qT, qprev, n, c.s));
-        HIPCHK(launch_nl_slice_mean(so, it == 0 ? q0 : qT, c.at(c.L.nW), n, S, P, c.s));
-        // every slice from zero (slice 0 too: the chain carries q0)
-        HIPCHK(launch_burgers_nl_march(so, nullptr, c.at(c.L.nv), nullptr, nullptr, nullptr,
-                                       c.at(c.L.nW), n, S, P, c.dt(), p.nu, p.L, p.block, c.s));
-        HIPCHK(launch_krylov1d(a, p.kblock, c.s));
-        HIPCHK(launch_burgers_nl_march(so, sn, nullptr, c.at(c.L.nE), q0, qT, c.at(c.L.nW), n,
-                                       S, P, c.dt(), p.nu, p.L, p.block, c.s));
+        {
+            // the slices' Jacobians and the slices from zero (every slice,
+            // slice 0 too: the chain carries q0)
+            ProfScope ps(PXP_K_SLICES, c.s);
+            HIPCHK(launch_nl_slice_mean(so, it == 0 ? q0 : qT, c.at(c.L.nW), n, S, P, ns, c.s));
+            HIPCHK(launch_burgers_nl_march(so, nullptr, c.at(c.L.nv), nullptr, nullptr, nullptr,
+                                           c.at(c.L.nW), n, S, P, c.dt(), p.nu, p.L, p.block,
+                                           ns, c.s));
+        }
+        {
+            ProfScope ps(PXP_K_KRYLOV_DIRECT, c.s);
+            HIPCHK(launch_krylov1d(a, p.kblock, c.s));
+        }
+        {
+            // the new iterate at the stage points, and its change
+            ProfScope ps(PXP_K_NL_ITER, c.s);
+            HIPCHK(launch_burgers_nl_march(so, sn, nullptr, c.at(c.L.nE), q0, qT, c.at(c.L.nW),
+                                           n, S, P, c.dt(), p.nu, p.L, p.block, ns, c.s));
+            HIPCHK(launch_nl_change(qT, qprev, n, tol, ns, (it + 1) & 1, c.irep, c.s));
+        }
     }
-    // the change of q(T) in the last iteration (q(T) of the previous one is
-    // in qprev; with one iteration, against q0)
-    MagnusCheck m{};
-    m.y = qprev;  // pair: previous, then (copied) current
-    m.n = n;
-    m.nsamp = 1;
-    m.tol = p.nl_tol > 0.0 ? p.nl_tol : p.krylov_tol;
-    m.scale = 1.0;
-    m.st = c.st;
-    m.irep = c.irep;
-    HIPCHK(launch_add(nullptr, qT, qprev + n, n, c.s));
-    auto* dm = reinterpret_cast<MagnusCheck*>(c.at(c.L.ndesc));
-    HIPCHK(launch_upload(dm, &m, sizeof(m), c.s));
-    HIPCHK(launch_magnus_check(dm, 1, c.s));
-    HIPCHK(launch_nl_ckpt(st[K & 1], qT, c.at(c.L.ckpt), n, n_t, p.ckpt_every, c.s));
+    HIPCHK(launch_nl_final(ns, tol, c.st, c.irep, c.s));
+    HIPCHK(launch_nl_ckpt(st[0], st[1], ns, qT, c.at(c.L.ckpt), n, n_t, p.ckpt_every, c.s));
     return PXP_OK;
 }
 
@@ -2535,7 +2536,8 @@ pxp_status pxp_last_report(const pxp_problem* pb, int32_t batch, void* ws, size_
         r.substeps = h[i].substeps;
         r.iterations = h[i].iters;
         std::memcpy(&r.max_est, &h[i].max_est, sizeof(double));
-        r.pad = 0.0;
+        r.nl_iterations = (int32_t)h[i].nl_iters;
+        r.pad = 0;
     }
     if (launch_zero(reinterpret_cast<double*>(w + Ly.irep),
                     batch * sizeof(InstStat) / sizeof(double), s) != hipSuccess ||

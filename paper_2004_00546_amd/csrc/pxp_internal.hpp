@@ -33,9 +33,10 @@ struct DevStatus {
 static_assert(sizeof(DevStatus) == 64, "status block layout");
 // Per-instance statistics beside the status block: Krylov substeps and
 // iterations (Arnoldi steps, or series terms) and the largest error estimate
-// (bit pattern) of one instance's exponentials since the last read.
+// (bit pattern) of one instance's exponentials, and the iterations of the
+// nonlinear Paraexp direct that ran, since the last read.
 struct InstStat {
-    unsigned long long substeps, iters, max_est, pad;
+    unsigned long long substeps, iters, max_est, nl_iters;
 };
 constexpr unsigned int ST_NOCONV = 1u;
 constexpr unsigned int ST_NONFINITE = 2u;
@@ -86,23 +87,43 @@ struct BurgersRange {
     double* cpart;
     int src_start, pad;
 };
-// Iterative nonlinear Paraexp for Burgers (section 3.2): one workgroup per
-// slice p of P (S steps each), the linearised march of iterate i+1 with
-// the previous stage states st_old ([n_t][4][n]) as sources, from q0
-// (p = 0), E + (p-1) n or zero; writes st_new (nullable), the end states
-// reversed (vend + (P-1-p) n, nullable) and q(T) (last slice, nullable).
+// Iterative nonlinear Paraexp for Burgers (section 3.2).  Device state of
+// one call's iteration (in the workspace): done = an iteration's change of
+// q(T) was within the tolerance, after which every launch of the call that
+// takes the state returns at once; last = the stage-state generation that
+// holds the last iterate; change = the last iteration's relative change.
+struct NlState {
+    int done, last;
+    double change;
+};
+// One workgroup per slice p of P (S steps each): the linearised march of
+// iterate i+1 with the previous stage states st_old ([n_t][4][n]) as
+// sources and J at W + p n, from q0 (p = 0, when set), E + (p-1) n (p > 0,
+// when set) or zero; writes st_new (nullable), the end states reversed
+// (vend + (P-1-p) n, nullable) and q(T) (last slice, nullable).
 hipError_t launch_burgers_nl_march(const double* st_old, double* st_new, double* vend,
                                    const double* E, const double* q0, double* qT,
                                    const double* W, int n, int64_t S, int P, double dt,
-                                   double nu, double L, int block, hipStream_t s);
-// W[2p] = W[2p+1] = mean of slice p's step states
+                                   double nu, double L, int block, const NlState* ns,
+                                   hipStream_t s);
+// W + p n = trapezoidal time average of slice p's step states (the last
+// slice ends on qlast)
 hipError_t launch_nl_slice_mean(const double* st, const double* qlast, double* W, int n,
-                                int64_t S, int P, hipStream_t s);
-// every stage state of nst = 4 n_t stages = q0
-hipError_t launch_nl_fill(const double* q0, double* st, int n, int64_t nst, hipStream_t s);
-// checkpoints every c steps from the step states, q(T) at n_t
-hipError_t launch_nl_ckpt(const double* st, const double* qT, double* ckpt, int n,
-                          int64_t n_t, int64_t c, hipStream_t s);
+                                int64_t S, int P, const NlState* ns, hipStream_t s);
+// every stage state of nst = 4 n_t stages = q0, qprev = q0, the state reset
+hipError_t launch_nl_fill(const double* q0, double* st, double* qprev, NlState* ns, int n,
+                          int64_t nst, hipStream_t s);
+// the change |qT - qprev| / |qT| of an iteration that wrote generation gen:
+// sets done when within tol, then qprev = qT (skipped once done)
+hipError_t launch_nl_change(const double* qT, double* qprev, int n, double tol, NlState* ns,
+                            int gen, InstStat* irep, hipStream_t s);
+// the last change into the status block (estimate; NOCONV above tol)
+hipError_t launch_nl_final(const NlState* ns, double tol, DevStatus* st, InstStat* irep,
+                           hipStream_t s);
+// checkpoints every c steps from the last iterate's step states, q(T) at n_t
+hipError_t launch_nl_ckpt(const double* st0, const double* st1, const NlState* ns,
+                          const double* qT, double* ckpt, int n, int64_t n_t, int64_t c,
+                          hipStream_t s);
 // out = a (x - y) on n points
 hipError_t launch_scaled_diff(const double* x, const double* y, double a, double* out, int n,
                               hipStream_t s);
@@ -217,6 +238,8 @@ struct KrylovArgs {
     // KM_LTV: one factor exp(tau J(W_k)) per macro step k (wop [npieces][n],
     // additions after macro step addq[k]) instead of two half-step factors
     int ltv_one;
+    // nullable: the launch returns at once when *skip is set
+    const int* skip;
     double* basis;       // [gridDim][m+1][n] workspace
     Sten5 op5;           // 2D: five-point operator
     int nx, ny;          // 2D: grid

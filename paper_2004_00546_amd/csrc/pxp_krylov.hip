@@ -1146,6 +1146,7 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
 
 template <int PT, bool SI, bool VAR>
 __device__ __forceinline__ void dev_krylov1d(const KrylovArgs& a, int piece, double* lds) {
+    if (a.skip && *a.skip) return;  // the same value for the whole workgroup
     const int n = a.n;
     double* V = a.basis + (size_t)piece * (a.m + 1) * n;
     Ctx<PT, SI, VAR> c(a, lds, V);

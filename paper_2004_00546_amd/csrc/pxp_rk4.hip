@@ -826,7 +826,8 @@ __device__ __forceinline__ void dev_burgers_nl_march(
     const double* __restrict__ st_old, double* __restrict__ st_new, double* __restrict__ vend,
     const double* __restrict__ E, const double* __restrict__ q0, double* __restrict__ qT,
     const double* __restrict__ W, int n, int64_t S, int P, double dt, BurgersC bc,
-    double* lds_d) {
+    const NlState* __restrict__ ns, double* lds_d) {
+    if (ns && ns->done) return;
     const int p = blockIdx.x;
     const int base = threadIdx.x * PT;
     double* lds = lds_d;
@@ -895,9 +896,9 @@ k_burgers_nl_march(const double* __restrict__ st_old, double* __restrict__ st_ne
                    double* __restrict__ vend, const double* __restrict__ E,
                    const double* __restrict__ q0, double* __restrict__ qT,
                    const double* __restrict__ W, int n, int64_t S, int P, double dt,
-                   BurgersC bc) {
+                   BurgersC bc, const NlState* __restrict__ ns) {
     extern __shared__ double lds_d[];
-    dev_burgers_nl_march<PT>(st_old, st_new, vend, E, q0, qT, W, n, S, P, dt, bc, lds_d);
+    dev_burgers_nl_march<PT>(st_old, st_new, vend, E, q0, qT, W, n, S, P, dt, bc, ns, lds_d);
 }
 
 // ubar_p = time average of the previous iterate over slice p by the
@@ -905,10 +906,11 @@ k_burgers_nl_march(const double* __restrict__ st_old, double* __restrict__ st_ne
 // of each step; the last slice ends on that iterate's q(T), qlast); grid
 // (n / 256, P).
 __global__ void k_nl_slice_mean(const double* __restrict__ st, const double* __restrict__ qlast,
-                                double* __restrict__ W, int n, int64_t S, int P) {
+                                double* __restrict__ W, int n, int64_t S, int P,
+                                const NlState* __restrict__ ns) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int p = blockIdx.y;
-    if (i >= n) return;
+    if (i >= n || ns->done) return;
     const int64_t s0 = (int64_t)p * S, s1 = s0 + S;
     double a = 0.5 * st[(size_t)(s0 * 4) * n + i];
     for (int64_t s = s0 + 1; s < s1; ++s) a += st[(size_t)(s * 4) * n + i];
@@ -916,21 +918,74 @@ __global__ void k_nl_slice_mean(const double* __restrict__ st, const double* __r
     W[(size_t)p * n + i] = a / (double)S;
 }
 
-// The first guess: every stage state of every step equals q0.
-__global__ void k_nl_fill(const double* __restrict__ q0, double* __restrict__ st, int n,
+// The first guess: every stage state of every step equals q0; the change
+// check's previous q(T) is q0; the iteration state is reset.
+__global__ void k_nl_fill(const double* __restrict__ q0, double* __restrict__ st,
+                          double* __restrict__ qprev, NlState* __restrict__ ns, int n,
                           int64_t nst) {
     const size_t tot = (size_t)nst * n;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < tot;
-         k += (size_t)gridDim.x * blockDim.x)
-        st[k] = q0[k % n];
+    const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = i0; k < tot; k += stride) st[k] = q0[k % n];
+    for (size_t k = i0; k < (size_t)n; k += stride) qprev[k] = q0[k];
+    if (i0 == 0) {
+        ns->done = 0;
+        ns->last = 0;
+        ns->change = INFINITY;
+    }
+}
+
+// One workgroup: the relative change of q(T) in the iteration that wrote
+// stage-state generation gen; within tol it stops the iteration.  Every
+// thread reads done before the reduction's barrier, thread 0 writes it
+// after; qprev takes the new q(T) for the next iteration's change.
+__global__ void __launch_bounds__(256) k_nl_change(const double* __restrict__ qT,
+                                                   double* __restrict__ qprev, int n,
+                                                   double tol, NlState* __restrict__ ns,
+                                                   int gen, InstStat* irep) {
+    __shared__ double red[80];
+    if (ns->done) return;
+    double dd = 0.0, qq = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double e = qT[i] - qprev[i];
+        dd += e * e;
+        qq += qT[i] * qT[i];
+    }
+    int slot = 0;
+    block_sum2(dd, qq, red, slot);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) qprev[i] = qT[i];
+    if (threadIdx.x == 0) {
+        double c = qq > 0.0 ? sqrt(dd / qq) : (dd > 0.0 ? INFINITY : 0.0);
+        if (!isfinite(c)) c = INFINITY;
+        ns->change = c;
+        ns->last = gen;
+        ns->done = (c <= tol) ? 1 : 0;
+        if (irep) atomicAdd(&irep->nl_iters, 1ull);
+    }
+}
+
+__global__ void k_nl_final(const NlState* __restrict__ ns, double tol, DevStatus* st,
+                           InstStat* irep) {
+    if (threadIdx.x != 0) return;
+    const double est = ns->change;
+    const bool bad = !isfinite(est);
+    const unsigned long long eb = (unsigned long long)__double_as_longlong(bad ? INFINITY : est);
+    if (st) {
+        atomicMax(&st->max_est, eb);
+        if (bad) atomicOr(&st->flags, ST_NONFINITE);
+        else if (est > tol) atomicOr(&st->flags, ST_NOCONV);
+    }
+    if (irep) atomicMax(&irep->max_est, eb);
 }
 
 // Checkpoints of the final iterate: the step states every c steps, and q(T).
-__global__ void k_nl_ckpt(const double* __restrict__ st, const double* __restrict__ qT,
+__global__ void k_nl_ckpt(const double* __restrict__ st0, const double* __restrict__ st1,
+                          const NlState* __restrict__ ns, const double* __restrict__ qT,
                           double* __restrict__ ckpt, int n, int64_t n_t, int64_t c) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t j = blockIdx.y;
     if (i >= n) return;
+    const double* st = ns->last ? st1 : st0;
     const int64_t s = j * c;
     ckpt[(size_t)j * n + i] = (s == n_t) ? qT[i] : st[(size_t)(s * 4) * n + i];
 }
@@ -1180,33 +1235,49 @@ hipError_t launch_rk4_burgers_reverse(const double* ckpt, const double* lamT,
 hipError_t launch_burgers_nl_march(const double* st_old, double* st_new, double* vend,
                                    const double* E, const double* q0, double* qT,
                                    const double* W, int n, int64_t S, int P, double dt,
-                                   double nu, double L, int block_hint, hipStream_t s) {
+                                   double nu, double L, int block_hint, const NlState* ns,
+                                   hipStream_t s) {
     int block, pt;
     if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
     const double h = L / n;
     BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
     const size_t lds = sizeof(double) * 8 * block;
     PXP_DISPATCH_PT(pt, k_burgers_nl_march, double,
-                    <<<P, block, lds, s>>>(st_old, st_new, vend, E, q0, qT, W, n, S, P, dt, bc))
+                    <<<P, block, lds, s>>>(st_old, st_new, vend, E, q0, qT, W, n, S, P, dt, bc,
+                                           ns))
     return hipGetLastError();
 }
 
 hipError_t launch_nl_slice_mean(const double* st, const double* qlast, double* W, int n,
-                                int64_t S, int P, hipStream_t s) {
+                                int64_t S, int P, const NlState* ns, hipStream_t s) {
     dim3 g((unsigned)((n + 255) / 256), (unsigned)P);
-    k_nl_slice_mean<<<g, 256, 0, s>>>(st, qlast, W, n, S, P);
+    k_nl_slice_mean<<<g, 256, 0, s>>>(st, qlast, W, n, S, P, ns);
     return hipGetLastError();
 }
 
-hipError_t launch_nl_fill(const double* q0, double* st, int n, int64_t nst, hipStream_t s) {
-    k_nl_fill<<<1024, 256, 0, s>>>(q0, st, n, nst);
+hipError_t launch_nl_fill(const double* q0, double* st, double* qprev, NlState* ns, int n,
+                          int64_t nst, hipStream_t s) {
+    k_nl_fill<<<1024, 256, 0, s>>>(q0, st, qprev, ns, n, nst);
     return hipGetLastError();
 }
 
-hipError_t launch_nl_ckpt(const double* st, const double* qT, double* ckpt, int n,
-                          int64_t n_t, int64_t c, hipStream_t s) {
+hipError_t launch_nl_change(const double* qT, double* qprev, int n, double tol, NlState* ns,
+                            int gen, InstStat* irep, hipStream_t s) {
+    k_nl_change<<<1, 256, 0, s>>>(qT, qprev, n, tol, ns, gen, irep);
+    return hipGetLastError();
+}
+
+hipError_t launch_nl_final(const NlState* ns, double tol, DevStatus* st, InstStat* irep,
+                           hipStream_t s) {
+    k_nl_final<<<1, 64, 0, s>>>(ns, tol, st, irep);
+    return hipGetLastError();
+}
+
+hipError_t launch_nl_ckpt(const double* st0, const double* st1, const NlState* ns,
+                          const double* qT, double* ckpt, int n, int64_t n_t, int64_t c,
+                          hipStream_t s) {
     dim3 g((unsigned)((n + 255) / 256), (unsigned)(n_t / c + 1));
-    k_nl_ckpt<<<g, 256, 0, s>>>(st, qT, ckpt, n, n_t, c);
+    k_nl_ckpt<<<g, 256, 0, s>>>(st0, st1, ns, qT, ckpt, n, n_t, c);
     return hipGetLastError();
 }
 

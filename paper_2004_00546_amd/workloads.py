@@ -25,6 +25,9 @@ the five workloads below are concrete instances of that family:
 * ``burgers1d_icost`` the N=2048 Burgers instance above with the integral
   cost (the hybrid serial-direct-parallel-adjoint scheme of section 3.3):
   128 Magnus steps and 128 equal adjoint slices, four per launch.
+* ``burgers1d_nl``    the N=2048 Burgers instance above with the direct
+  solved by the iterative nonlinear Paraexp of section 3.2 (128 slices, at
+  most 8 iterations, ended by the change of q(T)).
 
 Every instance is a plain dict of numbers and float64 numpy arrays.  Random
 draws come from ``numpy.random.default_rng([1000 + cfg, instance])`` in the
@@ -42,7 +45,8 @@ TWO_PI = 2.0 * math.pi
 RK4_REAL_LIMIT = 2.785
 
 WORKLOADS = ("advdiff1d_n128", "advdiff1d_n4096", "burgers1d_n2048",
-             "advdiff2d_256", "burgers1d_ragged", "advdiff2d_icost", "burgers1d_icost")
+             "advdiff2d_256", "burgers1d_ragged", "advdiff2d_icost", "burgers1d_icost",
+             "burgers1d_nl")
 CFG_INDEX = {name: i + 1 for i, name in enumerate(WORKLOADS)}
 
 
@@ -195,6 +199,9 @@ def make(name: str) -> list[dict]:
             out.append(_burgers_instance(cfg, i, n, nu, T, n_steps, 64, 32,
                                          30, rng))
         return out
+    if name == "burgers1d_nl":
+        inst = make("burgers1d_n2048")[0]
+        return [dict(inst, nl_paraexp=True, nl_iters=8)]
     if name == "burgers1d_icost":
         inst = make("burgers1d_n2048")[0]
         return [dict(inst, cost="integral", hyb_slices=128, hyb_k=0.0, hyb_group=4)]

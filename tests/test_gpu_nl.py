@@ -6,7 +6,8 @@ oracle's serial march.
     iterates, and the reported change of q(T) against the oracle's;
   - the fixed point: q(T) against the serial RK4 march, the gradient
     against the exact discrete adjoint, one slice and several;
-  - too few iterations flagged PXP_EKRYLOV_NOCONV;
+  - too few iterations flagged PXP_EKRYLOV_NOCONV; the iteration ending
+    once its change is within tolerance;
   - the N = 2048 Burgers workload;
   - a batch mixing an iterated instance with a plain one;
   - hipGraph replays.
@@ -60,10 +61,13 @@ def burgers(n=256, T=0.5, nt=1024, P=16, nu=0.02, K=8, seed=7, ckpt=64, **kw):
     return inst
 
 
-def run(insts, tol):
+def run(insts, tol, report=False):
     r = api.GradientRunner(insts, method="paraexp", krylov="auto", tol=tol)
     r.run()
-    return r.results(), r.status()
+    out = (r.results(), r.status())
+    if report:
+        out += (_lib.pxp_last_report(r.problems, r.ws),)
+    return out
 
 
 def test_nl_iterates_match_oracle(torch):
@@ -72,7 +76,8 @@ def test_nl_iterates_match_oracle(torch):
     say("nl iterates: oracle, 3 iterations (about 3 s)")
     want = onl.nl_paraexp_direct(inst, 3)
     for K in (1, 2, 3):
-        res, (code, est) = run([dict(inst, nl_iters=K)], 1e-12)
+        res, (code, est), rep = run([dict(inst, nl_iters=K)], 1e-12, report=True)
+        assert rep[0]["nl_iterations"] == K
         e = rel(res[0]["qT"], want["qT_iters"][K - 1])
         ec = abs(est - want["change"][K - 1]) / want["change"][K - 1]
         say("  K=%d: qT %.2e, change %.3e (oracle %.3e), status %d" % (
@@ -123,6 +128,25 @@ def test_nl_too_few_iterations_flagged(torch):
     assert np.all(np.isfinite(res[0]["qT"]))
     res, (code, est) = run([burgers(P=64, nl_iters=6)], 1e-9)
     assert code == 0 and est < 1e-9
+
+
+def test_nl_stops_within_tolerance(torch):
+    """Algorithm 2's while loop: once an iteration's change of q(T) is
+    within nl_tol, the call's remaining iterations do nothing; a cap far
+    above the iterations needed gives the same bits as a cap just above."""
+    res6, (c6, e6), rep6 = run([burgers(P=64, nl_iters=6, nl_tol=1e-9)], 1e-9, report=True)
+    res30, (c30, e30), rep30 = run([burgers(P=64, nl_iters=30, nl_tol=1e-9)], 1e-9,
+                                   report=True)
+    k = rep30[0]["nl_iterations"]
+    say("nl stop: %d iterations (cap 30), %d (cap 6), est %.2e" % (
+        k, rep6[0]["nl_iterations"], e30))
+    assert c6 == 0 and c30 == 0
+    assert 3 <= k <= 6 and rep6[0]["nl_iterations"] == k
+    for key in ("qT", "grad", "lam"):
+        assert np.array_equal(res6[0][key], res30[0][key]), key
+    # a tolerance no change meets runs every iteration and is flagged
+    _, (c, _), rep = run([burgers(P=64, nl_iters=4, nl_tol=1e-300)], 1e-9, report=True)
+    assert rep[0]["nl_iterations"] == 4 and c == _lib.PXP_EKRYLOV_NOCONV
 
 
 def test_nl_mixed_batch(torch, orc):
