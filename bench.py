@@ -618,7 +618,7 @@ def main():
                          "the timed region runs at steady-state clocks")
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--krylov", default="auto",
-                    choices=["poly", "shift_invert", "auto", "taylor", "uniform"])
+                    choices=["poly", "shift_invert", "auto", "taylor", "uniform", "chebyshev"])
     ap.add_argument("--sched", default=None, choices=["classic", "chain", "tree"],
                     help="schedule of the direct pieces (default: tree in 2D, classic in 1D)")
     ap.add_argument("--serial-steps", type=int, default=5,

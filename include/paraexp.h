@@ -86,9 +86,9 @@ enum { PXP_CTRL_FORCING = 0, PXP_CTRL_IC = 1 };
  * classical Gram-Schmidt with a second pass only on tenfold cancellation. */
 /* AUTO: 1D: shift-and-invert when tau * rho > 64 (rho = 4 nu/h^2 + |vx|/h,
  * tau the horizon for the linear pieces or half a slice for the Burgers
- * Magnus factors) and the grid has the cyclic-reduction shape, else TAYLOR.
- * 2D: UNIFORM, except for the CLASSIC schedule of the direct pieces, which
- * takes TAYLOR. */
+ * Magnus factors) and the grid has the cyclic-reduction shape, else TAYLOR
+ * (linear problems) or CHEBYSHEV (Burgers).  2D: UNIFORM, except for the
+ * CLASSIC schedule of the direct pieces, which takes TAYLOR. */
 /* TAYLOR: no Arnoldi process; exp(tau Op) v by the truncated Taylor series
  * in substeps of at most theta/|Op| (theta from the remainder bound for 40
  * terms at krylov_tol), terms added until two consecutive term norms fall
@@ -105,8 +105,18 @@ enum { PXP_CTRL_FORCING = 0, PXP_CTRL_IC = 1 };
  * per pass of 16 terms, so one exponential spreads over many workgroups.
  * The adjoint's time integral uses the exact integral of every term's
  * weight against the forcing modulation. */
+/* CHEBYSHEV (Burgers only): no Arnoldi process; each exponential of the
+ * time-varying chains, exp(tau J) v, by the Chebyshev series of exp on the
+ * real interval of the Gershgorin bounds of tau J's real parts (the focal
+ * interval of section 4.1's ReLPM; Chebyshev basis, coefficients the scaled
+ * modified Bessel functions of the half-width), taken in substeps where
+ * the half-width exceeds what the kernel's coefficient table holds.  Terms
+ * are added up to the a priori degree of the coefficients' decay and then
+ * until two consecutive term norms are below krylov_tol |v|, which is the
+ * reported estimate.  About a fifth of the Taylor flavour's stencil
+ * applications for the diffusion-dominated Burgers Jacobian. */
 enum { PXP_KRYLOV_POLY = 0, PXP_KRYLOV_SHIFT_INVERT = 1, PXP_KRYLOV_AUTO = 2,
-       PXP_KRYLOV_TAYLOR = 3, PXP_KRYLOV_UNIFORM = 4 };
+       PXP_KRYLOV_TAYLOR = 3, PXP_KRYLOV_UNIFORM = 4, PXP_KRYLOV_CHEBYSHEV = 5 };
 /* Schedule of the direct homogeneous pieces: CLASSIC = P-1 independent
  * pieces exp((T - T_{p+1}) A) v_p (eq. hom); CHAIN = nested sum
  * w <- exp(dT A) w + v_p, one piece after the other; TREE (2D, UNIFORM) =
@@ -339,7 +349,8 @@ pxp_status pxp_device_counters_class(void* ws, size_t ws_bytes, void* stream, in
  * initialised or last reported on (host output `out`, one entry per
  * instance of the same batch and workspace as the compute calls).
  * Synchronises `stream`, then clears the statistics.  P and the schedule are
- * the problem's (sched -1: the direct march is serial, Burgers); the flavours
+ * the problem's (sched -1: the direct march is serial, Burgers without
+ * NL_PARAEXP, whose chain reports CHAIN); the flavours
  * are the ones that ran, AUTO resolved (-1: no exponential).  substeps counts
  * Krylov substeps (uniformised exponentials: one per exponential);
  * iterations counts Arnoldi steps or series terms; max_est is the largest

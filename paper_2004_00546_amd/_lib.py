@@ -19,7 +19,8 @@ PXP_EUNSTABLE_DT, PXP_EKRYLOV_NOCONV, PXP_ENONFINITE, PXP_EHIP = 4, 5, 6, 7
 OP = {"advdiff1d": 0, "advdiff2d_upwind": 1, "burgers1d": 2}
 PREC = {"fp64": 0, "fp32_bulk": 1}
 CTRL = {"forcing": 0, "ic": 1}
-KRYLOV = {"poly": 0, "shift_invert": 1, "auto": 2, "taylor": 3, "uniform": 4}
+KRYLOV = {"poly": 0, "shift_invert": 1, "auto": 2, "taylor": 3, "uniform": 4,
+          "chebyshev": 5}
 FLAG_ABSORBED_ADJOINT = 1
 FLAG_INTEGRAL_COST = 2
 FLAG_NL_PARAEXP = 4

@@ -196,7 +196,15 @@ bool rk4_stable_cached(const pxp_problem& p) {
 // uniformisation is taken.
 bool use_taylor(const pxp_problem& p) {
     if (p.krylov == PXP_KRYLOV_TAYLOR) return true;
-    return p.krylov == PXP_KRYLOV_AUTO && !use_si(p) && !uniform_direct(p);
+    return p.krylov == PXP_KRYLOV_AUTO && !use_si(p) && !uniform_direct(p) &&
+           p.op != PXP_OP_BURGERS1D;
+}
+
+// Chebyshev flavour: the time-varying Burgers chains, named or AUTO where
+// shift-and-invert is not taken.
+bool use_cheb(const pxp_problem& p) {
+    if (p.op != PXP_OP_BURGERS1D) return false;
+    return p.krylov == PXP_KRYLOV_CHEBYSHEV || (p.krylov == PXP_KRYLOV_AUTO && !use_si(p));
 }
 
 // The Krylov kernels' workgroup shape for this problem exists, fits in LDS,
@@ -219,11 +227,12 @@ pxp_status validate(const pxp_problem& p) {
     if (p.ctrl != PXP_CTRL_FORCING && p.ctrl != PXP_CTRL_IC) return PXP_EINVAL;
     if (p.krylov != PXP_KRYLOV_POLY && p.krylov != PXP_KRYLOV_SHIFT_INVERT &&
         p.krylov != PXP_KRYLOV_AUTO && p.krylov != PXP_KRYLOV_TAYLOR &&
-        p.krylov != PXP_KRYLOV_UNIFORM)
+        p.krylov != PXP_KRYLOV_UNIFORM && p.krylov != PXP_KRYLOV_CHEBYSHEV)
         return PXP_EINVAL;
     if (p.sched != PXP_SCHED_CLASSIC && p.sched != PXP_SCHED_CHAIN && p.sched != PXP_SCHED_TREE)
         return PXP_EINVAL;
     if (p.krylov == PXP_KRYLOV_UNIFORM && p.op != PXP_OP_ADVDIFF2D_UPWIND) return PXP_EUNSUPPORTED;
+    if (p.krylov == PXP_KRYLOV_CHEBYSHEV && p.op != PXP_OP_BURGERS1D) return PXP_EUNSUPPORTED;
     if (p.sched == PXP_SCHED_TREE && !uniform_direct(p)) return PXP_EUNSUPPORTED;
     if (p.prec != PXP_FP64 && p.prec != PXP_FP32_BULK) return PXP_EINVAL;
     if ((p.flags & ~(PXP_FLAG_ABSORBED_ADJOINT | PXP_FLAG_INTEGRAL_COST |
@@ -759,6 +768,7 @@ constexpr int TAYLOR_DEG = 40;
 KrylovArgs kargs(const Ctx& c, Tri op) {
     KrylovArgs a{};
     a.taylor = use_taylor(c.p) ? 1 : 0;
+    a.cheb = use_cheb(c.p) ? 1 : 0;
     a.tdeg = TAYLOR_DEG;
     a.theta = taylor_theta(TAYLOR_DEG, c.p.krylov_tol);
     a.anorm = std::fabs(op.lo) + std::fabs(op.d) + std::fabs(op.up);
@@ -2499,14 +2509,17 @@ pxp_status pxp_workspace_init(void* ws, size_t ws_bytes, void* stream) {
 
 // Flavour of the direct and of the adjoint exponentials as they run.
 int flavour_direct(const pxp_problem& p) {
-    if (p.op == PXP_OP_BURGERS1D) return -1;  // the direct march is serial
+    // Burgers: the direct march is serial, except in the nonlinear iteration
+    if (p.op == PXP_OP_BURGERS1D && !nlpx(p)) return -1;
     if (uniform_direct(p)) return PXP_KRYLOV_UNIFORM;
     if (use_si(p)) return PXP_KRYLOV_SHIFT_INVERT;
+    if (use_cheb(p)) return PXP_KRYLOV_CHEBYSHEV;
     return use_taylor(p) ? PXP_KRYLOV_TAYLOR : PXP_KRYLOV_POLY;
 }
 int flavour_adjoint(const pxp_problem& p) {
     if (uniform_adjoint(p)) return PXP_KRYLOV_UNIFORM;
     if (use_si(p)) return PXP_KRYLOV_SHIFT_INVERT;
+    if (use_cheb(p)) return PXP_KRYLOV_CHEBYSHEV;
     return use_taylor(p) ? PXP_KRYLOV_TAYLOR : PXP_KRYLOV_POLY;
 }
 
@@ -2530,7 +2543,7 @@ pxp_status pxp_last_report(const pxp_problem* pb, int32_t batch, void* ws, size_
         const pxp_problem& p = pb[i];
         pxp_report& r = out[i];
         r.P = p.P;
-        r.sched = (p.op == PXP_OP_BURGERS1D) ? -1 : p.sched;
+        r.sched = (p.op == PXP_OP_BURGERS1D) ? (nlpx(p) ? PXP_SCHED_CHAIN : -1) : p.sched;
         r.krylov_direct = flavour_direct(p);
         r.krylov_adjoint = flavour_adjoint(p);
         r.substeps = h[i].substeps;

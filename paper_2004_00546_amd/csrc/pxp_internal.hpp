@@ -251,6 +251,10 @@ struct KrylovArgs {
     // Jacobian)
     int taylor, tdeg;
     double anorm, theta;
+    // Chebyshev flavour (time-varying Burgers chains without a time
+    // integral): exp(tau Op) v by the Chebyshev series on the Gershgorin
+    // interval of the real parts, computed in the kernel
+    int cheb;
     DevStatus* status;
     int adj;             // counters of the adjoint class (absorbed pieces;
                          // KM_SINGLE and KM_LTV count there anyway)

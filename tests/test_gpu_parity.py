@@ -548,7 +548,7 @@ def test_ragged_burgers_shift_invert_batch(torch, orc):
 
 def test_auto_flavour_ragged_equals_explicit_choice(torch):
     """AUTO picks shift-and-invert per instance where half a slice times the
-    diffusion spectral radius exceeds 64, else the Taylor flavour; each
+    diffusion spectral radius exceeds 64, else the Chebyshev flavour; each
     batched result equals the run with that flavour named explicitly."""
     insts = ragged_burgers(seed=70)
     insts[2] = dict(insts[2], P=insts[2]["n_steps"] // 64)  # long macro steps
@@ -560,7 +560,7 @@ def test_auto_flavour_ragged_equals_explicit_choice(torch):
     for inst, b in zip(insts, r.results()):
         h = inst["L"] / inst["nx"]
         si = 0.5 * inst["T"] / inst["P"] * 4 * inst["nu"] / h**2 > 64
-        one = run(inst, "paraexp", krylov="shift_invert" if si else "taylor", tol=1e-5)
+        one = run(inst, "paraexp", krylov="shift_invert" if si else "chebyshev", tol=1e-5)
         assert np.array_equal(one["grad"], b["grad"]), (inst["nx"], si)
 
 
@@ -616,6 +616,42 @@ def test_taylor_flavour_matches_oracle(torch, orc, case):
     say("taylor %s: grad %.2e status %d est %.1e" % (case, e, got["status"], got["est"]))
     assert got["status"] == 0
     assert e < FP64_GATE
+
+
+@pytest.mark.parametrize("n,nu,P", [(256, 0.02, 16), (512, 0.01, 32), (2048, 0.005, 128)])
+def test_chebyshev_flavour_matches_oracle_and_taylor(torch, orc, n, nu, P):
+    """The Chebyshev flavour of the Burgers Magnus factors (series on the
+    Gershgorin interval, coefficients from the Bessel recurrence in the
+    kernel): against the oracle, against the Taylor flavour (both are
+    within the piece tolerance of the same factors), and with fewer stencil
+    applications where the interval is wide.  The N = 2048 case has
+    half-widths of about 8 per factor (no substeps); the coarse cases cover
+    small intervals, where both flavours need about as many terms."""
+    if n == 2048:
+        inst = workloads.make("burgers1d_n2048")[0]
+    else:
+        inst = small_burgers(n=n, T=0.3, nt=256, P=P, nu=nu, seed=9, ckpt=16)
+    want = orc.gradient(inst)
+    res = {}
+    for kr in ("chebyshev", "taylor"):
+        r = api.GradientRunner([inst], method="paraexp", krylov=kr, tol=1e-10)
+        _lib.pxp_last_report(r.problems, r.ws)
+        r.run()
+        out = r.results()[0]
+        code, est = r.status()
+        rep = _lib.pxp_last_report(r.problems, r.ws)[0]
+        res[kr] = (out, code, est, rep)
+        say("%s n=%d: grad %.2e lam0 %.2e status %d est %.1e terms %d" % (
+            kr, n, rel(out["grad"], want["grad"]), rel(out["lam"], want["lam0"]), code, est,
+            rep["iterations"]))
+    ch, ta = res["chebyshev"], res["taylor"]
+    assert ch[3]["krylov_adjoint"] == "chebyshev"
+    assert rel(ch[0]["grad"], want["grad"]) < FP64_GATE
+    assert rel(ch[0]["lam"], want["lam0"]) < FP64_GATE
+    assert rel(ch[0]["lam"], ta[0]["lam"]) < 1e-9
+    assert ch[1] == ta[1]
+    if n == 2048:
+        assert ch[3]["iterations"] < ta[3]["iterations"]
 
 
 # ---- non-finite inputs reach the device status ------------------------------
