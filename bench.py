@@ -372,7 +372,8 @@ def measure(args, name, torch, _lib, api, workloads, steps, serial_steps, with_o
     if name == args.workload:
         for key, v in (("hyb_slices", args.hyb_slices), ("hyb_k", args.hyb_k),
                        ("hyb_group", args.hyb_group), ("nl_iters", args.nl_iters),
-                       ("nl_tol", args.nl_tol), ("P", args.slices)):
+                       ("nl_tol", args.nl_tol), ("nl_slices", args.nl_slices),
+                       ("P", args.slices)):
             if v is not None:
                 insts = [dict(x, **{key: v}) for x in insts]
     inst = insts[0]
@@ -560,8 +561,9 @@ def nl_model(inst, kern, kern_ser, t_pxp, t_ser, report, steps):
     follow from eq. nonLinSpeedup with the adjoint's parallel cost split the
     same way (tau_I^dagger: the Magnus node states over a slice, tau_H^dagger:
     the Magnus chain per step)."""
-    nt, P = int(inst["n_steps"]), int(inst["P"])
-    S = nt // P
+    nt, Pa = int(inst["n_steps"]), int(inst["P"])
+    P = int(inst.get("nl_slices", 0)) or Pa  # the iteration's slices
+    S, Sa = nt // P, nt // Pa  # ... and the adjoint's Magnus steps
     if not report or not t_ser:
         return None
     K = sum(r["nl_iterations"] for r in report) / steps
@@ -575,14 +577,14 @@ def nl_model(inst, kern, kern_ser, t_pxp, t_ser, report, steps):
     tau_i, tau_h, tau_f = sl / S, ch / (nt - S), fm / S
     tau_ds = kern_ser.get("serial_direct", 0.0) / nt
     tau_as = kern_ser.get("serial_reverse", 0.0) / nt
-    tau_ia = kern.get("ltv_nodes", {}).get("per_step_ms", 0.0) / S
-    tau_ha = kern.get("ltv_adjoint", {}).get("per_step_ms", 0.0) / (nt - S)
+    tau_ia = kern.get("ltv_nodes", {}).get("per_step_ms", 0.0) / Sa
+    tau_ha = kern.get("ltv_adjoint", {}).get("per_step_ms", 0.0) / (nt - Sa)
     pred = K * (S * tau_i + (nt - S) * tau_h + S * tau_f) + adj
     # s > 1 iff N (tau_D^S + tau_A^S - K tau_H - tau_H^dagger)
     #           > K (tau_I + tau_F - tau_H) + tau_I^dagger - tau_H^dagger
     den = tau_ds + tau_as - K * tau_h - tau_ha
     num = K * (tau_i + tau_f - tau_h) + tau_ia - tau_ha
-    return {"iterations": K, "slices": P,
+    return {"iterations": K, "slices": P, "adjoint_slices": Pa,
             "per_iteration_ms": {"jacobians_and_slices": sl, "chain": ch,
                                  "iterate_and_change": fm},
             "adjoint_ms": adj, "serial_direct_ms": kern_ser.get("serial_direct"),
@@ -649,6 +651,8 @@ def main():
                     help="iterative nonlinear direct: most iterations")
     ap.add_argument("--nl-tol", type=float, default=None,
                     help="iterative nonlinear direct: change of q(T) that ends it")
+    ap.add_argument("--nl-slices", type=int, default=None,
+                    help="iterative nonlinear direct: slices of the iteration")
     ap.add_argument("--slices", type=int, default=None,
                     help="override the workload's slice count P")
     ap.add_argument("--instances", type=int, default=0,

@@ -209,7 +209,10 @@ typedef struct {
     double hyb_k;                    /* their partition (eq. nonEquiP): adjoint
                                         over direct time per unit of time
                                         (0 = equal slices)                    */
-    int32_t nl_iters, nl_pad;        /* NL_PARAEXP: most iterations (0 = 8)    */
+    int32_t nl_iters;                /* NL_PARAEXP: most iterations (0 = 8)    */
+    int32_t nl_slices;               /* NL_PARAEXP: slices of the iteration
+                                        (0 = P; must divide n_steps); the
+                                        adjoint's Magnus steps stay P        */
     double nl_tol;                   /* NL_PARAEXP: relative change of q(T)
                                         that ends the iteration
                                         (0 = krylov_tol)                      */

@@ -60,7 +60,7 @@ class pxp_problem(ctypes.Structure):
                 ("si_gamma", ctypes.c_double),
                 ("hyb_slices", ctypes.c_int32), ("hyb_group", ctypes.c_int32),
                 ("hyb_k", ctypes.c_double),
-                ("nl_iters", ctypes.c_int32), ("nl_pad", ctypes.c_int32),
+                ("nl_iters", ctypes.c_int32), ("nl_slices", ctypes.c_int32),
                 ("nl_tol", ctypes.c_double)]
 
 

@@ -50,6 +50,7 @@ def make_problem(inst: dict, krylov: str = "shift_invert", sched: str = "classic
     if inst.get("nl_paraexp", False):
         p.flags |= _lib.FLAG_NL_PARAEXP
     p.nl_iters = int(inst.get("nl_iters", 0))
+    p.nl_slices = int(inst.get("nl_slices", 0))
     p.nl_tol = float(inst.get("nl_tol", 0.0))
     return p
 

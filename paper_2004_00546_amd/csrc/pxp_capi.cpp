@@ -420,6 +420,7 @@ size_t tree_kept_vectors(const TShape& sh) {
 bool icost(const pxp_problem& p) { return (p.flags & PXP_FLAG_INTEGRAL_COST) != 0; }
 bool nlpx(const pxp_problem& p) { return (p.flags & PXP_FLAG_NL_PARAEXP) != 0; }
 int nl_iters(const pxp_problem& p) { return p.nl_iters > 0 ? p.nl_iters : 8; }
+int nl_slices(const pxp_problem& p) { return p.nl_slices > 0 ? p.nl_slices : p.P; }
 
 // Largest Poisson parameter of the integral-cost adjoint tree: the pair at
 // the root, whose left half spans the most slices.
@@ -470,7 +471,9 @@ int hyb_group(const pxp_problem& p) { return p.hyb_group > 0 ? p.hyb_group : 4; 
 pxp_status validate_icost(const pxp_problem& p) {
     if (p.hyb_slices < 0 || p.hyb_group < 0 || !(p.hyb_k >= 0.0) || !std::isfinite(p.hyb_k))
         return PXP_EINVAL;
-    if (p.nl_iters < 0 || !(p.nl_tol >= 0.0) || !std::isfinite(p.nl_tol)) return PXP_EINVAL;
+    if (p.nl_iters < 0 || p.nl_slices < 0 || !(p.nl_tol >= 0.0) || !std::isfinite(p.nl_tol))
+        return PXP_EINVAL;
+    if (p.n_steps % nl_slices(p)) return PXP_EINVAL;
     if (nlpx(p)) {
         // the iteration of section 3.2: Burgers, FP64, terminal cost, at
         // least four steps (the march's stage layout)
@@ -560,11 +563,12 @@ Inst inst_layout(const pxp_problem& p) {
             // previous q(T), the chain's addition table, the change check
             L.nst[0] = take(4 * (size_t)p.n_steps * n * d);
             L.nst[1] = take(4 * (size_t)p.n_steps * n * d);
-            L.nW = take(P * n * d);
-            L.nv = take(P * n * d);
-            L.nE = take(P * n * d);
+            const size_t Pn = (size_t)nl_slices(p);
+            L.nW = take(Pn * n * d);
+            L.nv = take(Pn * n * d);
+            L.nE = take(Pn * n * d);
             L.nq = take(n * d);
-            L.naddq = take(P * sizeof(int));
+            L.naddq = take(Pn * sizeof(int));
             L.ndesc = take(sizeof(NlState));
         }
         if (icost(p)) {
@@ -1061,7 +1065,7 @@ pxp_status adjoint_burgers(const Ctx& c, const double* lamT, double* lam0,
 // change is the estimate; the checkpoints come from the last iterate.
 pxp_status direct_burgers_nl(const Ctx& c, const double* q0, double* qT) {
     const pxp_problem& p = c.p;
-    const int n = c.n(), P = p.P;
+    const int n = c.n(), P = nl_slices(p);
     const int64_t n_t = p.n_steps, S = n_t / P;
     const double h = p.L / p.nx;
     const double tol = p.nl_tol > 0.0 ? p.nl_tol : p.krylov_tol;

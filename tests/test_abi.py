@@ -303,6 +303,8 @@ def test_nl_paraexp_rules_on_host(lib):
         assert e.value.code == code, bad
     for bad, code in [(dict(cost="integral"), _lib.PXP_EUNSUPPORTED),
                       (dict(nl_iters=-1), _lib.PXP_EINVAL),
+                      (dict(nl_slices=-2), _lib.PXP_EINVAL),
+                      (dict(nl_slices=3), _lib.PXP_EINVAL),
                       (dict(nl_tol=-1.0), _lib.PXP_EINVAL)]:
         with pytest.raises(_lib.PxpError) as e:
             _lib.pxp_workspace_size([api.make_problem(dict(inst, **bad), krylov="auto")])

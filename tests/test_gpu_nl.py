@@ -119,6 +119,25 @@ def test_nl_fixed_point_matches_serial(torch, orc, P):
         assert code == 0
 
 
+def test_nl_own_slice_count(torch, orc):
+    """The iteration's slices (nl_slices) apart from the adjoint's Magnus
+    steps (P): the iterates follow the oracle's iteration on nl_slices
+    slices, and the gradient the serial loop's."""
+    from oracle import nonlinear as onl
+    inst = burgers(P=64, nl_slices=8)
+    want = onl.nl_paraexp_direct(inst, 2, P=8)
+    res, (code, est), rep = run([dict(inst, nl_iters=2)], 1e-12, report=True)
+    e = rel(res[0]["qT"], want["qT_iters"][1])
+    assert rep[0]["nl_iterations"] == 2
+    full = orc.gradient(inst)
+    res, (code, est) = run([dict(inst, nl_iters=8)], 1e-9)
+    eq, eg = rel(res[0]["qT"], full["qT"]), rel(res[0]["grad"], full["grad"])
+    say("nl 8 slices, 64 Magnus steps: iterate 2 %.2e; qT %.2e grad %.2e status %d" % (
+        e, eq, eg, code))
+    assert e < ITER_GATE
+    assert code == 0 and eq < FP64_GATE and eg < FP64_GATE
+
+
 def test_nl_one_slice_is_the_serial_march(torch, orc):
     """P = 1: no slice start comes from an exponential, so the fixed point
     is the serial march to rounding."""
