@@ -1355,6 +1355,7 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
     std::vector<BurgersDesc> tab;
     std::vector<KrylovArgs> ktab;
     std::vector<int> kB;
+    std::vector<char> kcheb;  // the Chebyshev flavour's own chain kernel
     int q0 = 0;
     size_t lds = 0;
     for (size_t j = 0; j < bb.idx.size(); ++j) {
@@ -1378,18 +1379,24 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
         a.inv2h = d.inv2h;
         a.nuh2 = d.nuh2;
         int B = 0, pt = 0;
-        krylov_shape_pub(p.nx, p.kblock, &B, &pt);  // validated
+        const bool ch = a.cheb && !a.si && cheb_chain_shape_pub(p.nx, &B, &pt);
+        if (!ch) {
+            krylov_shape_pub(p.nx, p.kblock, &B, &pt);  // validated
+            const size_t l = krylov1d_lds_bytes(p.nx, p.m, B, 0);
+            if (l > lds) lds = l;
+        }
         a.pt = pt;
         ktab.push_back(a);
         kB.push_back(B);
-        const size_t l = krylov1d_lds_bytes(p.nx, p.m, B, 0);
-        if (l > lds) lds = l;
+        kcheb.push_back(ch ? 1 : 0);
     }
-    // one launch per workgroup size, instances of a size contiguous
+    // one launch per kernel and workgroup size, the instances of one
+    // contiguous
+    auto key = [&](int j) { return (kcheb[j] ? 1024 : 0) + kB[j]; };
     std::vector<int> order(ktab.size());
     for (size_t j = 0; j < order.size(); ++j) order[j] = (int)j;
     std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return kB[x] < kB[y]; });
+                     [&](int x, int y) { return key(x) < key(y); });
     std::vector<KrylovArgs> ksorted;
     for (int j : order) ksorted.push_back(ktab[j]);
     auto* dtab = reinterpret_cast<BurgersDesc*>(static_cast<char*>(ws) + Ly.btab);
@@ -1422,6 +1429,7 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
         size_t first;
         int count, block;
         size_t group;
+        bool cheb;
     };
     std::vector<CLaunch> cl;
     {
@@ -1444,7 +1452,7 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
         size_t g = 0;
         for (size_t j0 = 0; j0 < order.size(); ++g) {
             size_t j1 = j0;
-            while (j1 < order.size() && kB[order[j1]] == kB[order[j0]]) ++j1;
+            while (j1 < order.size() && key(order[j1]) == key(order[j0])) ++j1;
             for (int kind = 0; kind < 4; ++kind) {
                 const size_t first = cks.size();
                 for (size_t e = j0; e < j1; ++e) {
@@ -1455,7 +1463,8 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
                     cks.push_back(magnus_check_args(c, ktab[j], kind));
                 }
                 if (cks.size() > first)
-                    cl.push_back({first, (int)(cks.size() - first), kB[order[j0]], g});
+                    cl.push_back({first, (int)(cks.size() - first), kB[order[j0]], g,
+                                  kcheb[order[j0]] != 0});
             }
             j0 = j1;
         }
@@ -1485,7 +1494,7 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
         side = g_side[dev];
     }
     std::unique_lock<std::mutex> lock(g_side_mu, std::defer_lock);
-    const bool groups = !order.empty() && kB[order.front()] != kB[order.back()];
+    const bool groups = !order.empty() && key(order.front()) != key(order.back());
     const bool forked = groups && side.st;
     if (forked) {
         // the side stream starts where the caller's stream is now: before
@@ -1497,11 +1506,19 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
     size_t g = 0;
     for (size_t j0 = 0; j0 < order.size(); ++g) {
         size_t j1 = j0;
-        while (j1 < order.size() && kB[order[j1]] == kB[order[j0]]) ++j1;
+        while (j1 < order.size() && key(order[j1]) == key(order[j0])) ++j1;
         const hipStream_t sg = (j0 > 0 && forked) ? side.st : s;
-        HIPCHK(launch_krylov_ltv_batch(kt + j0, kB[order[j0]], (int)(j1 - j0), lds, sg));
-        for (const CLaunch& x : cl)
-            if (x.group == g) HIPCHK(launch_krylov_ltv_batch(kc + x.first, x.block, x.count, lds, sg));
+        if (kcheb[order[j0]])
+            HIPCHK(launch_cheb_chain_batch(kt + j0, kB[order[j0]], (int)(j1 - j0), sg));
+        else
+            HIPCHK(launch_krylov_ltv_batch(kt + j0, kB[order[j0]], (int)(j1 - j0), lds, sg));
+        for (const CLaunch& x : cl) {
+            if (x.group != g) continue;
+            if (x.cheb)
+                HIPCHK(launch_cheb_chain_batch(kc + x.first, x.block, x.count, sg));
+            else
+                HIPCHK(launch_krylov_ltv_batch(kc + x.first, x.block, x.count, lds, sg));
+        }
         j0 = j1;
     }
     if (forked) {

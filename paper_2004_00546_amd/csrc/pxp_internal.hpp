@@ -266,6 +266,12 @@ hipError_t launch_krylov1d(const KrylovArgs& a, int block, hipStream_t s);
 // lds = the largest krylov1d_lds_bytes of the batch.
 hipError_t launch_krylov_ltv_batch(const KrylovArgs* tab, int block, int count,
                                    size_t lds, hipStream_t s);
+// The Chebyshev flavour's own chain kernel: the grids it covers in whole
+// chunks (B threads of pt points, B pt = n), and a ragged batch of such
+// chains (entries with a.pt set, all of workgroup size block).
+bool cheb_chain_shape_pub(int n, int* B, int* pt);
+hipError_t launch_cheb_chain_batch(const KrylovArgs* tab, int block, int count,
+                                   hipStream_t s);
 size_t krylov1d_lds_bytes(int n, int m, int block, int si);
 bool krylov_shape_pub(int n, int block_hint, int* B, int* pt);
 

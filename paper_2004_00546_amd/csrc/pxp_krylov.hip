@@ -1449,6 +1449,273 @@ __global__ void __launch_bounds__(krylov_max_block(PT)) k_krylov1d(KrylovArgs a)
     dev_krylov1d<PT, SI, VAR>(a, blockIdx.x, lds);
 }
 
+// ---- the Chebyshev flavour's own chain kernel -----------------------------
+// A time-varying chain (KM_LTV with the Chebyshev flavour) in one
+// workgroup whose B threads cover the grid in whole chunks (B PT = n):
+// thread t keeps points t PT .. t PT + PT - 1 of the chain vector in
+// registers from the start vector to the result, each factor's operator
+// state W beside it (its two halo values loaded once per factor), and each
+// series term exchanges only the chunk edges through LDS (two slots in
+// turn, one barrier per term).  The series is the one of Ctx::expv_cheb.
+// LDS: 128 doubles for reductions, 4 B for the edges, the coefficients.
+constexpr int CHEB_CHAIN_LDS = 128 + 4 * 512 + CHEB_KMAX + 2;
+
+bool cheb_chain_shape(int n, int* B, int* pt) {
+    if (n <= 256 && n % 64 == 0) {
+        *B = n;
+        *pt = 1;
+        return true;
+    }
+    for (int b : {256, 512}) {
+        if (n % b) continue;
+        const int p = n / b;
+        if ((p & (p - 1)) == 0 && p <= (b == 256 ? 8 : 16)) {
+            *B = b;
+            *pt = p;
+            return true;
+        }
+    }
+    return false;
+}
+
+struct ChebStats {
+    double worst = 0.0;
+    unsigned terms = 0, substeps = 0;
+    bool noconv = false, nonfinite = false;
+};
+
+// u <- exp(tau Op) u for Op = J(W)^T (or J(W) with ltv_fwd), the chunk's
+// W in w with halos wl, wr.
+template <int PT>
+__device__ __forceinline__ void cheb_factor(const KrylovArgs& a, double (&u)[PT],
+                                            const double (&w)[PT], double wl, double wr,
+                                            double tau, double* red, double* xch,
+                                            double* coef, ChebStats& st) {
+    const int t = threadIdx.x, B = blockDim.x;
+    auto coefs = [&](int q, double& lw, double& d, double& up) {
+        const double Wm = q == 0 ? wl : w[q - 1], Wp = q == PT - 1 ? wr : w[q + 1];
+        lw = a.ltv_fwd ? a.nuh2 + a.inv2h * w[q] : a.nuh2 - a.inv2h * Wm;
+        up = a.ltv_fwd ? a.nuh2 - a.inv2h * w[q] : a.nuh2 + a.inv2h * Wp;
+        d = -2.0 * a.nuh2 - a.inv2h * (Wp - Wm);
+    };
+    double lo = INFINITY, hi = -INFINITY, ss = 0.0;
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+        double lw, d, up;
+        coefs(q, lw, d, up);
+        const double o = fabs(lw) + fabs(up);
+        lo = fmin(lo, d - o);
+        hi = fmax(hi, d + o);
+        ss += u[q] * u[q];
+    }
+    hi = block_max(hi, red);
+    lo = -block_max(-lo, red);
+    double nu = sqrt(block_sum(ss, red));
+    if (!(nu > 0.0) || !isfinite(lo) || !isfinite(hi)) {
+        // a zero vector stays zero; a non-finite one is recorded
+        if (!isfinite(nu) || !isfinite(lo) || !isfinite(hi)) st.nonfinite = true;
+        return;
+    }
+    const double room = (double)(CHEB_KMAX - 40);
+    const double gmax = fmax(1.0, room - 6.0 * sqrt(room));
+    int ns = (int)ceil(0.5 * tau * (hi - lo) / gmax);
+    if (ns < 1) ns = 1;
+    const double ts = tau / ns;
+    const double c = 0.5 * ts * (hi + lo);
+    const double g = fmax(0.5 * ts * (hi - lo), 0.5);
+    const int kc = (int)fmin((double)CHEB_KMAX, g + 6.0 * sqrt(g) + 40.0);
+    // every thread has read the previous factor's coefficients: the
+    // reductions above passed barriers since
+    if (t == 0) {
+        // Miller's backward recurrence I_{k-1} = I_{k+1} + (2k/g) I_k, from
+        // far above kc, normalised by e^g = I_0 + 2 sum I_k
+        const double r2 = 2.0 / g;
+        const int top = kc + 64;
+        double ip = 0.0, ik = 1e-200, sum = 0.0;
+        for (int k = top; k >= 1; --k) {
+            if (k <= kc + 1) coef[k] = ik;
+            sum += 2.0 * ik;
+            const double im = ip + (k * r2) * ik;
+            ip = ik;
+            ik = im;
+            if (ik > 1e200) {
+                for (int j = k; j <= kc + 1; ++j) coef[j] *= 1e-200;
+                ip *= 1e-200;
+                ik *= 1e-200;
+                sum *= 1e-200;
+            }
+        }
+        coef[0] = ik;
+        sum += ik;
+        const double inv = 1.0 / sum;
+        for (int k = 0; k <= kc + 1; ++k) coef[k] *= inv;
+    }
+    __syncthreads();
+    int ka = kc - 1;
+    for (int k = (int)ceil(g) > 1 ? (int)ceil(g) : 1; k < kc; ++k)
+        if (coef[k] + coef[k + 1] <= a.tol * 0.0625) {
+            ka = k;
+            break;
+        }
+    const double scale = exp(c + g), ig = 1.0 / g;
+    int slotx = 0;
+    auto ahat = [&](const double (&x)[PT], double (&z)[PT]) {
+        double* e = xch + slotx * 2 * B;
+        e[t] = x[0];
+        e[B + t] = x[PT - 1];
+        __syncthreads();
+        const double xl = e[B + (t == 0 ? B - 1 : t - 1)];
+        const double xr = e[t == B - 1 ? 0 : t + 1];
+        slotx ^= 1;
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            double lw, d, up;
+            coefs(q, lw, d, up);
+            const double xm = q == 0 ? xl : x[q - 1], xp = q == PT - 1 ? xr : x[q + 1];
+            z[q] = (ts * (lw * xm + d * x[q] + up * xp) - c * x[q]) * ig;
+        }
+    };
+    for (int sub = 0; sub < ns; ++sub) {
+        double t0[PT], t1[PT], acc[PT], z[PT];
+#pragma unroll
+        for (int q = 0; q < PT; ++q) t0[q] = u[q];
+        ahat(u, t1);
+        ++st.terms;
+#pragma unroll
+        for (int q = 0; q < PT; ++q) acc[q] = coef[0] * u[q] + 2.0 * coef[1] * t1[q];
+        double prev = INFINITY;
+        bool conv = false;
+        int slot = 0;
+        int k = 2;
+        while (k <= kc) {
+            const bool two = k + 1 <= kc;
+            double s1 = 0.0, s2 = 0.0;
+            for (int e = 0; e < (two ? 2 : 1); ++e) {
+                ahat(t1, z);
+                ++st.terms;
+                const double ck = 2.0 * coef[k + e];
+                double sq = 0.0;
+#pragma unroll
+                for (int q = 0; q < PT; ++q) {
+                    const double tn = 2.0 * z[q] - t0[q];
+                    t0[q] = t1[q];
+                    t1[q] = tn;
+                    acc[q] += ck * tn;
+                    sq += tn * tn;
+                }
+                (e == 0 ? s1 : s2) = ck * ck * sq;
+            }
+            if (k + 1 >= ka) {
+                block_sum2(s1, s2, red, slot);
+                const double n1 = scale * sqrt(s1), n2 = scale * sqrt(s2);
+                if (prev + n1 <= a.tol * nu) {
+                    conv = true;
+                    st.worst = fmax(st.worst, (prev + n1) / nu);
+                    break;
+                }
+                if (two && n1 + n2 <= a.tol * nu) {
+                    conv = true;
+                    st.worst = fmax(st.worst, (n1 + n2) / nu);
+                    break;
+                }
+                prev = two ? n2 : n1;
+            }
+            k += two ? 2 : 1;
+        }
+        if (!conv) {
+            st.noconv = true;
+            st.worst = fmax(st.worst, isfinite(prev) ? prev / nu : 1.0);
+        }
+        double s2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            u[q] = scale * acc[q];
+            s2 += u[q] * u[q];
+        }
+        if (sub + 1 < ns) nu = sqrt(block_sum(s2, red));
+    }
+    st.substeps += ns;
+}
+
+template <int PT>
+__device__ __forceinline__ void dev_cheb_chain(const KrylovArgs& a, double* lds) {
+    if (a.skip && *a.skip) return;
+    const int n = a.n, t = threadIdx.x, B = blockDim.x, base = t * PT;
+    double* red = lds;
+    double* xch = lds + 128;
+    double* coef = xch + 4 * B;
+    double u[PT];
+#pragma unroll
+    for (int q = 0; q < PT; ++q) u[q] = a.vin[base + q];
+    const int nexp = a.ltv_one ? a.npieces : 2 * a.npieces;
+    ChebStats st;
+    int nextadd = 0;
+    for (int q = 0; q < nexp; ++q) {
+        const double* W = a.wop + (size_t)q * n;
+        double w[PT];
+#pragma unroll
+        for (int k = 0; k < PT; ++k) w[k] = W[base + k];
+        const double wl = W[base == 0 ? n - 1 : base - 1];
+        const double wr = W[base + PT == n ? 0 : base + PT];
+        cheb_factor<PT>(a, u, w, wl, wr, a.tau, red, xch, coef, st);
+        // after a macro step (two factors, or one) that ends on a slice
+        // start, add that slice's end state
+        const bool mend = a.ltv_one || (q & 1);
+        const int mstep = a.ltv_one ? q : (q >> 1);
+        if (a.vadd && mend && nextadd < a.nadd && a.addq[nextadd] == mstep) {
+            const double* x = a.vadd + (size_t)(a.nadd - 1 - nextadd) * n + base;
+#pragma unroll
+            for (int k = 0; k < PT; ++k) u[k] += x[k];
+            if (a.vsnap) {
+                double* y = a.vsnap + (size_t)nextadd * n + base;
+#pragma unroll
+                for (int k = 0; k < PT; ++k) y[k] = u[k];
+            }
+            ++nextadd;
+        }
+    }
+    if (a.yout) {
+#pragma unroll
+        for (int q = 0; q < PT; ++q) a.yout[base + q] = u[q];
+    }
+    if (t == 0 && a.status) {
+        if (st.noconv) atomicOr(&a.status->flags, ST_NOCONV);
+        if (st.nonfinite || !(st.worst == st.worst)) atomicOr(&a.status->flags, ST_NONFINITE);
+        const double e = fabs(st.worst);
+        if (e == e) atomicMax(&a.status->max_est, (unsigned long long)__double_as_longlong(e));
+        atomicAdd(&a.status->substeps[1], (unsigned long long)st.substeps);
+        atomicAdd(&a.status->krylov_iters[1], (unsigned long long)st.terms);
+        if (a.irep) {
+            atomicAdd(&a.irep->substeps, (unsigned long long)st.substeps);
+            atomicAdd(&a.irep->iters, (unsigned long long)st.terms);
+            if (e == e)
+                atomicMax(&a.irep->max_est, (unsigned long long)__double_as_longlong(e));
+        }
+    }
+}
+
+template <int PT>
+__global__ void __launch_bounds__(512) k_cheb_chain(KrylovArgs a) {
+    __shared__ double lds[CHEB_CHAIN_LDS];
+    dev_cheb_chain<PT>(a, lds);
+}
+
+// Ragged batch: workgroup i runs the chain of entry i (a.pt points per
+// thread; all entries of a launch share the workgroup size).
+__global__ void __launch_bounds__(512) k_cheb_chain_batch(const KrylovArgs* tab) {
+    __shared__ double lds[CHEB_CHAIN_LDS];
+    const KrylovArgs a = tab[blockIdx.x];
+    if (a.n != a.pt * (int)blockDim.x) return;  // the host groups by shape
+    switch (a.pt) {
+        case 1: dev_cheb_chain<1>(a, lds); break;
+        case 2: dev_cheb_chain<2>(a, lds); break;
+        case 4: dev_cheb_chain<4>(a, lds); break;
+        case 8: dev_cheb_chain<8>(a, lds); break;
+        case 16: dev_cheb_chain<16>(a, lds); break;
+        default: break;
+    }
+}
+
 // Ragged batch of time-varying chains: workgroup i runs instance i; all
 // instances of one launch share the workgroup size, compiled for at most NT.
 template <int PT, int NT>
@@ -1998,6 +2265,16 @@ bool krylov_shape_pub(int n, int block_hint, int* B, int* pt) {
     return krylov_shape(n, block_hint, B, pt);
 }
 
+bool cheb_chain_shape_pub(int n, int* B, int* pt) { return cheb_chain_shape(n, B, pt); }
+
+hipError_t launch_cheb_chain_batch(const KrylovArgs* tab, int block, int count,
+                                   hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    if (block % 64 || block <= 0 || block > 512) return hipErrorInvalidValue;
+    k_cheb_chain_batch<<<count, block, 0, s>>>(tab);
+    return hipGetLastError();
+}
+
 hipError_t launch_krylov1d(const KrylovArgs& a, int block_hint, hipStream_t s) {
     if (a.m < 1 || a.m > M_MAX_1D || a.n < 2) return hipErrorInvalidValue;
     if (a.si && a.mode != KM_LTV && (a.n & (a.n - 1))) return hipErrorInvalidValue;
@@ -2013,6 +2290,18 @@ hipError_t launch_krylov1d(const KrylovArgs& a, int block_hint, hipStream_t s) {
     if (a.mode == KM_LTV) {
         if (!a.wop) return hipErrorInvalidValue;
         if (a.si && (B & (B - 1))) return hipErrorInvalidValue;
+        int cB, cpt;
+        if (a.cheb && !a.si && !a.iout && cheb_chain_shape(a.n, &cB, &cpt)) {
+            switch (cpt) {
+                case 1: k_cheb_chain<1><<<1, cB, 0, s>>>(a); break;
+                case 2: k_cheb_chain<2><<<1, cB, 0, s>>>(a); break;
+                case 4: k_cheb_chain<4><<<1, cB, 0, s>>>(a); break;
+                case 8: k_cheb_chain<8><<<1, cB, 0, s>>>(a); break;
+                case 16: k_cheb_chain<16><<<1, cB, 0, s>>>(a); break;
+                default: return hipErrorInvalidValue;
+            }
+            return hipGetLastError();
+        }
         return a.si ? launch_pt<true, true>(a, B, pt, grid, lds, s)
                     : launch_pt<false, true>(a, B, pt, grid, lds, s);
     }
