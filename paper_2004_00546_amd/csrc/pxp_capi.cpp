@@ -1392,7 +1392,7 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
     }
     // one launch per kernel and workgroup size, the instances of one
     // contiguous
-    auto key = [&](int j) { return (kcheb[j] ? 1024 : 0) + kB[j]; };
+    auto key = [&](int j) { return (kcheb[j] ? 1 << 20 : 0) + 64 * kB[j] + ktab[j].pt; };
     std::vector<int> order(ktab.size());
     for (size_t j = 0; j < order.size(); ++j) order[j] = (int)j;
     std::stable_sort(order.begin(), order.end(),
@@ -1430,6 +1430,7 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
         int count, block;
         size_t group;
         bool cheb;
+        int pt;
     };
     std::vector<CLaunch> cl;
     {
@@ -1464,7 +1465,7 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
                 }
                 if (cks.size() > first)
                     cl.push_back({first, (int)(cks.size() - first), kB[order[j0]], g,
-                                  kcheb[order[j0]] != 0});
+                                  kcheb[order[j0]] != 0, ktab[order[j0]].pt});
             }
             j0 = j1;
         }
@@ -1509,13 +1510,14 @@ pxp_status burgers_batch_adjoint(const pxp_problem* pb, const BurgersBatch& bb,
         while (j1 < order.size() && key(order[j1]) == key(order[j0])) ++j1;
         const hipStream_t sg = (j0 > 0 && forked) ? side.st : s;
         if (kcheb[order[j0]])
-            HIPCHK(launch_cheb_chain_batch(kt + j0, kB[order[j0]], (int)(j1 - j0), sg));
+            HIPCHK(launch_cheb_chain_batch(kt + j0, kB[order[j0]], ktab[order[j0]].pt,
+                                           (int)(j1 - j0), sg));
         else
             HIPCHK(launch_krylov_ltv_batch(kt + j0, kB[order[j0]], (int)(j1 - j0), lds, sg));
         for (const CLaunch& x : cl) {
             if (x.group != g) continue;
             if (x.cheb)
-                HIPCHK(launch_cheb_chain_batch(kc + x.first, x.block, x.count, sg));
+                HIPCHK(launch_cheb_chain_batch(kc + x.first, x.block, x.pt, x.count, sg));
             else
                 HIPCHK(launch_krylov_ltv_batch(kc + x.first, x.block, x.count, lds, sg));
         }

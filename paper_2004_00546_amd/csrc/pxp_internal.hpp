@@ -268,9 +268,9 @@ hipError_t launch_krylov_ltv_batch(const KrylovArgs* tab, int block, int count,
                                    size_t lds, hipStream_t s);
 // The Chebyshev flavour's own chain kernel: the grids it covers in whole
 // chunks (B threads of pt points, B pt = n), and a ragged batch of such
-// chains (entries with a.pt set, all of workgroup size block).
+// chains (all entries of workgroup size block and a.pt == pt).
 bool cheb_chain_shape_pub(int n, int* B, int* pt);
-hipError_t launch_cheb_chain_batch(const KrylovArgs* tab, int block, int count,
+hipError_t launch_cheb_chain_batch(const KrylovArgs* tab, int block, int pt, int count,
                                    hipStream_t s);
 size_t krylov1d_lds_bytes(int n, int m, int block, int si);
 bool krylov_shape_pub(int n, int block_hint, int* B, int* pt);

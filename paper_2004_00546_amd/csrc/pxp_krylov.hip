@@ -1523,14 +1523,16 @@ __device__ __forceinline__ void cheb_factor(const KrylovArgs& a, double (&u)[PT]
     const double ts = tau / ns;
     const double c = 0.5 * ts * (hi + lo);
     const double g = fmax(0.5 * ts * (hi - lo), 0.5);
-    const int kc = (int)fmin((double)CHEB_KMAX, g + 6.0 * sqrt(g) + 40.0);
+    const int kc = (int)fmin((double)(CHEB_KMAX - 1), g + 6.0 * sqrt(g) + 40.0);
     // every thread has read the previous factor's coefficients: the
     // reductions above passed barriers since
     if (t == 0) {
         // Miller's backward recurrence I_{k-1} = I_{k+1} + (2k/g) I_k, from
-        // far above kc, normalised by e^g = I_0 + 2 sum I_k
+        // above kc (where the scaled values are below 1e-20), normalised by
+        // e^g = I_0 + 2 sum I_k; then the a priori degree into the slot
+        // after the table
         const double r2 = 2.0 / g;
-        const int top = kc + 64;
+        const int top = kc + 24;
         double ip = 0.0, ik = 1e-200, sum = 0.0;
         for (int k = top; k >= 1; --k) {
             if (k <= kc + 1) coef[k] = ik;
@@ -1549,14 +1551,16 @@ __device__ __forceinline__ void cheb_factor(const KrylovArgs& a, double (&u)[PT]
         sum += ik;
         const double inv = 1.0 / sum;
         for (int k = 0; k <= kc + 1; ++k) coef[k] *= inv;
+        int kd = kc - 1;
+        for (int k = (int)ceil(g) > 1 ? (int)ceil(g) : 1; k < kc; ++k)
+            if (coef[k] + coef[k + 1] <= a.tol * 0.0625) {
+                kd = k;
+                break;
+            }
+        coef[CHEB_KMAX + 1] = (double)kd;
     }
     __syncthreads();
-    int ka = kc - 1;
-    for (int k = (int)ceil(g) > 1 ? (int)ceil(g) : 1; k < kc; ++k)
-        if (coef[k] + coef[k + 1] <= a.tol * 0.0625) {
-            ka = k;
-            break;
-        }
+    const int ka = (int)coef[CHEB_KMAX + 1];
     const double scale = exp(c + g), ig = 1.0 / g;
     int slotx = 0;
     auto ahat = [&](const double (&x)[PT], double (&z)[PT]) {
@@ -1650,14 +1654,25 @@ __device__ __forceinline__ void dev_cheb_chain(const KrylovArgs& a, double* lds)
     const int nexp = a.ltv_one ? a.npieces : 2 * a.npieces;
     ChebStats st;
     int nextadd = 0;
-    for (int q = 0; q < nexp; ++q) {
+    // each factor's operator state, loaded one factor ahead (the series'
+    // barriers wait for LDS only)
+    double w[PT], wl, wr;
+    auto load_w = [&](int q, double (&x)[PT], double& xl, double& xr) {
         const double* W = a.wop + (size_t)q * n;
-        double w[PT];
 #pragma unroll
-        for (int k = 0; k < PT; ++k) w[k] = W[base + k];
-        const double wl = W[base == 0 ? n - 1 : base - 1];
-        const double wr = W[base + PT == n ? 0 : base + PT];
+        for (int k = 0; k < PT; ++k) x[k] = W[base + k];
+        xl = W[base == 0 ? n - 1 : base - 1];
+        xr = W[base + PT == n ? 0 : base + PT];
+    };
+    load_w(0, w, wl, wr);
+    for (int q = 0; q < nexp; ++q) {
+        double wn[PT], wnl = 0.0, wnr = 0.0;
+        if (q + 1 < nexp) load_w(q + 1, wn, wnl, wnr);
         cheb_factor<PT>(a, u, w, wl, wr, a.tau, red, xch, coef, st);
+#pragma unroll
+        for (int k = 0; k < PT; ++k) w[k] = wn[k];
+        wl = wnl;
+        wr = wnr;
         // after a macro step (two factors, or one) that ends on a slice
         // start, add that slice's end state
         const bool mend = a.ltv_one || (q & 1);
@@ -1700,20 +1715,14 @@ __global__ void __launch_bounds__(512) k_cheb_chain(KrylovArgs a) {
     dev_cheb_chain<PT>(a, lds);
 }
 
-// Ragged batch: workgroup i runs the chain of entry i (a.pt points per
-// thread; all entries of a launch share the workgroup size).
+// Ragged batch: workgroup i runs the chain of entry i; all entries of a
+// launch share the workgroup size and PT (the host groups them so).
+template <int PT>
 __global__ void __launch_bounds__(512) k_cheb_chain_batch(const KrylovArgs* tab) {
     __shared__ double lds[CHEB_CHAIN_LDS];
     const KrylovArgs a = tab[blockIdx.x];
-    if (a.n != a.pt * (int)blockDim.x) return;  // the host groups by shape
-    switch (a.pt) {
-        case 1: dev_cheb_chain<1>(a, lds); break;
-        case 2: dev_cheb_chain<2>(a, lds); break;
-        case 4: dev_cheb_chain<4>(a, lds); break;
-        case 8: dev_cheb_chain<8>(a, lds); break;
-        case 16: dev_cheb_chain<16>(a, lds); break;
-        default: break;
-    }
+    if (a.pt != PT || a.n != PT * (int)blockDim.x) return;
+    dev_cheb_chain<PT>(a, lds);
 }
 
 // Ragged batch of time-varying chains: workgroup i runs instance i; all
@@ -2267,11 +2276,18 @@ bool krylov_shape_pub(int n, int block_hint, int* B, int* pt) {
 
 bool cheb_chain_shape_pub(int n, int* B, int* pt) { return cheb_chain_shape(n, B, pt); }
 
-hipError_t launch_cheb_chain_batch(const KrylovArgs* tab, int block, int count,
+hipError_t launch_cheb_chain_batch(const KrylovArgs* tab, int block, int pt, int count,
                                    hipStream_t s) {
     if (count <= 0) return hipSuccess;
     if (block % 64 || block <= 0 || block > 512) return hipErrorInvalidValue;
-    k_cheb_chain_batch<<<count, block, 0, s>>>(tab);
+    switch (pt) {
+        case 1: k_cheb_chain_batch<1><<<count, block, 0, s>>>(tab); break;
+        case 2: k_cheb_chain_batch<2><<<count, block, 0, s>>>(tab); break;
+        case 4: k_cheb_chain_batch<4><<<count, block, 0, s>>>(tab); break;
+        case 8: k_cheb_chain_batch<8><<<count, block, 0, s>>>(tab); break;
+        case 16: k_cheb_chain_batch<16><<<count, block, 0, s>>>(tab); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
