@@ -247,7 +247,15 @@ def run_oracle(insts, sample, threads):
 
 # ---- roofline models of the kernel classes ------------------------------------
 
-def class_models(insts, problems, args, counters):
+# Burgers: flop per point per RK4 stage (central advection and diffusion,
+# the stage update and the step sum) and per Chebyshev term (stencil
+# coefficients from W, the 3-point stencil, the shift and scale, the
+# three-term recurrence and the weighted sum)
+BURGERS_FLOPS = 14.0
+CHEB_FLOPS = 18.0
+
+
+def class_models(insts, problems, args, counters, nl_k=None):
     """Per kernel class: (bound, algorithmic quantity per class launch, unit
     word, description).  counters: {cls: (substeps, iters, reorth)} per step
     of the direct (0) and adjoint (1) exponentials."""
@@ -322,6 +330,37 @@ def class_models(insts, problems, args, counters):
                 "alu", adj_terms * (POIS_FLOPS + 2.0), "flop",
                 "k_pois2d, the adjoint piece with its time integral: terms x points x "
                 "%g flop" % (POIS_FLOPS + 2.0))
+    burgers = all(x["op"] == "burgers1d" for x in insts)
+    if burgers:
+        # one workgroup per march or chain: FP64 work on one CU, latency
+        # bound; the nonlinear iteration's marches stream the stage states
+        n = [int(x["nx"]) for x in insts]
+        nt = [int(x["n_steps"]) for x in insts]
+        flops = sum(4 * s * nn * BURGERS_FLOPS for s, nn in zip(nt, n))
+        out["serial_direct"] = ("alu", flops, "flop",
+                                "k_rk4_burgers_direct: the serial march, 4 stages per step at "
+                                "%g flop per point, one workgroup per instance" % BURGERS_FLOPS)
+        for cls, name in ((1, "ltv_adjoint"), (0, "krylov_direct")):
+            if counters.get(cls) and counters[cls][1]:
+                terms = counters[cls][1]
+                out[name] = ("alu", terms * n[0] * CHEB_FLOPS if len(n) == 1 else
+                             terms * sum(n) / len(n) * CHEB_FLOPS, "flop",
+                             "k_cheb_chain: %.0f series terms per step (device counter) x "
+                             "points x %g flop (stencil coefficients, stencil, recurrence, "
+                             "sum); one workgroup per chain" % (terms, CHEB_FLOPS))
+        if all(x.get("nl_paraexp") for x in insts) and len(insts) == 1 and nl_k:
+            # per iteration (nl_k of them per call, measured): the zero-start
+            # march reads every stage state, the second march reads and
+            # writes them, the averages read the step states
+            st = 4 * nt[0] * n[0] * 8
+            out["nl_iter"] = ("hbm", nl_k * 2 * st, "B",
+                              "k_burgers_nl_march from the corrected starts: reads the "
+                              "previous stage states and writes the new ones (%.3g B per "
+                              "iteration, %.1f iterations)" % (2 * st, nl_k))
+            out["slices"] = ("hbm", nl_k * (st + nt[0] * n[0] * 8), "B",
+                             "k_burgers_nl_march from zero (reads the stage states) and "
+                             "k_nl_slice_mean (reads the step states), %.1f iterations"
+                             % nl_k)
     if one_lin and len(insts) == 1 and counters.get(0):
         inst, p = insts[0], problems[0]
         n = inst["nx"]
@@ -477,7 +516,8 @@ def measure(args, name, torch, _lib, api, workloads, steps, serial_steps, with_o
         log("rel errors (max over %d sampled instance(s))" % len(sample), err,
             "oracle %.2f s wall on %d thread(s), %.2f s summed" % (wall, threads, orc["cpu"]))
 
-    models = class_models(insts, pxp.problems, args, counters)
+    nl_k = (sum(r.get("nl_iterations", 0) for r in report) / steps) if report else None
+    models = class_models(insts, pxp.problems, args, counters, nl_k)
     traffic = {}
     if inst["op"] == "advdiff2d_upwind":
         tr = profiled_traffic("k_pois2d_tree", "%s_kernels.md" % name, "pxp_expo2d.hip")

@@ -339,9 +339,10 @@ pxp_status pxp_device_counters(void* ws, size_t ws_bytes, void* stream,
                                uint64_t* reorth_passes);
 
 /* The same counters for one class of exponentials: cls = 0 the direct
- * pieces (eq. hom), cls = 1 the adjoint pieces (eqs. adjHomNormal,
- * adjhomfinal, the absorbed adjoint's pieces and the time-varying Magnus
- * chains).  For the Taylor flavour the iteration counter holds Taylor terms.
+ * pieces (eq. hom, and the nonlinear iteration's chain), cls = 1 the
+ * adjoint pieces (eqs. adjHomNormal, adjhomfinal, the absorbed adjoint's
+ * pieces and the time-varying Magnus chains).  For the Taylor and
+ * Chebyshev flavours the iteration counter holds series terms.
  * The uniformised 2D exponentials fix their terms before the launch and do
  * not count.  PXP_EINVAL for another cls. */
 pxp_status pxp_device_counters_class(void* ws, size_t ws_bytes, void* stream, int32_t cls,

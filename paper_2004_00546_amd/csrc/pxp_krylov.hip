@@ -249,7 +249,10 @@ struct Core {
             const double e = fabs(est_rel);
             if (e == e)
                 atomicMax(&a.status->max_est, (unsigned long long)__double_as_longlong(e));
-            const int cls = (a.adj || a.mode == KM_SINGLE || a.mode == KM_LTV) ? 1 : 0;
+            // the forward time-varying chain (the nonlinear direct) counts
+            // with the direct class
+            const int cls =
+                (a.adj || a.mode == KM_SINGLE || (a.mode == KM_LTV && !a.ltv_fwd)) ? 1 : 0;
             atomicAdd(&a.status->substeps[cls], (unsigned long long)substeps);
             atomicAdd(&a.status->krylov_iters[cls], (unsigned long long)iters);
             atomicAdd(&a.status->reorth[cls], (unsigned long long)nre);
@@ -1698,8 +1701,9 @@ __device__ __forceinline__ void dev_cheb_chain(const KrylovArgs& a, double* lds)
         if (st.nonfinite || !(st.worst == st.worst)) atomicOr(&a.status->flags, ST_NONFINITE);
         const double e = fabs(st.worst);
         if (e == e) atomicMax(&a.status->max_est, (unsigned long long)__double_as_longlong(e));
-        atomicAdd(&a.status->substeps[1], (unsigned long long)st.substeps);
-        atomicAdd(&a.status->krylov_iters[1], (unsigned long long)st.terms);
+        const int cls = a.ltv_fwd ? 0 : 1;  // the nonlinear direct's chain: direct
+        atomicAdd(&a.status->substeps[cls], (unsigned long long)st.substeps);
+        atomicAdd(&a.status->krylov_iters[cls], (unsigned long long)st.terms);
         if (a.irep) {
             atomicAdd(&a.irep->substeps, (unsigned long long)st.substeps);
             atomicAdd(&a.irep->iters, (unsigned long long)st.terms);

@@ -93,3 +93,24 @@ def test_hybrid_bounds_follow_eq_nonequip():
     d = [b[i + 1] - b[i] for i in range(len(b) - 1)]
     for i in range(3):
         assert abs(d[i + 1] / d[i] - 2.0 / 3.0) < 0.1
+
+
+def test_burgers_class_models():
+    """The Burgers models: the serial march's flop, the Chebyshev chains'
+    flop from the term counters (direct class: the nonlinear chain), and
+    the nonlinear iteration's marches as HBM bytes, scaled by the measured
+    iterations per call."""
+    from paper_2004_00546_amd import api, workloads
+    inst = workloads.make("burgers1d_nl")[0]
+    n, nt = inst["nx"], inst["n_steps"]
+    prob = api.make_problem(inst)
+    m = bench.class_models([inst], [prob], None, {0: (64, 1000.0, 0), 1: (256, 6000.0, 0)},
+                           nl_k=5.0)
+    assert m["serial_direct"][1] == 4 * nt * n * bench.BURGERS_FLOPS
+    assert m["krylov_direct"][1] == 1000.0 * n * bench.CHEB_FLOPS
+    assert m["ltv_adjoint"][1] == 6000.0 * n * bench.CHEB_FLOPS
+    st = 4 * nt * n * 8
+    assert m["nl_iter"] == ("hbm", 5.0 * 2 * st, "B", m["nl_iter"][3])
+    assert m["slices"][1] == 5.0 * (st + nt * n * 8)
+    # without the measured iteration count the marches have no model
+    assert "nl_iter" not in bench.class_models([inst], [prob], None, {}, nl_k=None)
