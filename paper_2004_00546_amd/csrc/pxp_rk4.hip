@@ -854,26 +854,25 @@ __device__ __forceinline__ void dev_burgers_nl_march(
     for (int q = 0; q < PT; ++q) y[q] = y0 ? y0[base + q] : 0.0;
     const int64_t a = (int64_t)p * S;
     const double cf[4] = {0.0, 0.5, 0.5, 1.0};
-    // one RK4 step from y with the previous iterate's stage states O[k]
-    auto step = [&](int64_t s, const double (&O)[4][PT]) {
-        double Y[PT], F[PT], acc[PT];
+    double Y[PT], F[PT], acc[PT];
+    // stage k of step s from y with the previous iterate's stage state O
+    auto stage = [&](int64_t s, int k, const double (&O)[PT]) {
+        // stage state from the previous stage's slope
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            // stage state from the previous stage's slope
+        for (int q = 0; q < PT; ++q) Y[q] = (k == 0) ? y[q] : y[q] + cf[k] * dt * F[q];
+        if (st_new) {
+            double* w = st_new + (size_t)(s * 4 + k) * n;
 #pragma unroll
-            for (int q = 0; q < PT; ++q) Y[q] = (k == 0) ? y[q] : y[q] + cf[k] * dt * F[q];
-            if (st_new) {
-                double* w = st_new + (size_t)(s * 4 + k) * n;
-#pragma unroll
-                for (int q = 0; q < PT; ++q) w[base + q] = Y[q];
-            }
-            double l[2], r[2];
-            const double* arr[2] = {Y, O[k]};
-            exch<PT, 2, 2>(arr, lds, buf, l, r);
-            nl_rhs<PT>(Y, O[k], l[0], r[0], l[1], r[1], ub, dub, inv2h, nuh2, F);
-#pragma unroll
-            for (int q = 0; q < PT; ++q) acc[q] = (k == 0) ? F[q] : acc[q] + ((k == 3) ? 1.0 : 2.0) * F[q];
+            for (int q = 0; q < PT; ++q) w[base + q] = Y[q];
         }
+        double l[2], r[2];
+        const double* arr[2] = {Y, O};
+        exch<PT, 2, 2>(arr, lds, buf, l, r);
+        nl_rhs<PT>(Y, O, l[0], r[0], l[1], r[1], ub, dub, inv2h, nuh2, F);
+#pragma unroll
+        for (int q = 0; q < PT; ++q) acc[q] = (k == 0) ? F[q] : acc[q] + ((k == 3) ? 1.0 : 2.0) * F[q];
+    };
+    auto finish = [&]() {
 #pragma unroll
         for (int q = 0; q < PT; ++q) y[q] += (dt / 6.0) * acc[q];
     };
@@ -886,14 +885,18 @@ __device__ __forceinline__ void dev_burgers_nl_march(
         }
     };
     if constexpr (PT <= 8) {
-        // the previous stage states are loaded one step ahead: the workgroup
-        // barriers of the stage exchanges wait for LDS only, so the loads of
-        // step s + 1 are in flight while step s is computed
+        // the previous stage states are loaded one step ahead, issued after
+        // the first stage's exchange: the workgroup barriers wait for LDS
+        // only, so the loads of step s + 1 are in flight during stages 1-3
         double Oc[4][PT], On[4][PT];
         load_step(a, Oc);
         for (int64_t s = a; s < a + S; ++s) {
+            stage(s, 0, Oc[0]);
             if (s + 1 < a + S) load_step(s + 1, On);
-            step(s, Oc);
+            stage(s, 1, Oc[1]);
+            stage(s, 2, Oc[2]);
+            stage(s, 3, Oc[3]);
+            finish();
 #pragma unroll
             for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -905,7 +908,9 @@ __device__ __forceinline__ void dev_burgers_nl_march(
         for (int64_t s = a; s < a + S; ++s) {
             double Oc[4][PT];
             load_step(s, Oc);
-            step(s, Oc);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) stage(s, k, Oc[k]);
+            finish();
         }
     }
     if (vend) {
