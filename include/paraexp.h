@@ -84,11 +84,13 @@ enum { PXP_CTRL_FORCING = 0, PXP_CTRL_IC = 1 };
  * extrapolated from the contraction of those differences and the space stops
  * once it is below krylov_tol (relative to |v|).  Both Arnoldi flavours use
  * classical Gram-Schmidt with a second pass only on tenfold cancellation. */
-/* AUTO: 1D: shift-and-invert when tau * rho > 64 (rho = 4 nu/h^2 + |vx|/h,
- * tau the horizon for the linear pieces or half a slice for the Burgers
- * Magnus factors) and the grid has the cyclic-reduction shape, else TAYLOR
- * (linear problems) or CHEBYSHEV (Burgers).  2D: UNIFORM, except for the
- * CLASSIC schedule of the direct pieces, which takes TAYLOR. */
+/* AUTO: 1D linear: shift-and-invert when tau * rho > 64 (rho = 4 nu/h^2 +
+ * |vx|/h, tau the horizon) and the grid has the cyclic-reduction shape,
+ * else TAYLOR.  Burgers: CHEBYSHEV where its chain kernel covers the grid
+ * (n = 64..256, or 256 or 512 threads of up to 8 or 16 points); elsewhere
+ * shift-and-invert when half a slice times rho exceeds 64, else CHEBYSHEV.
+ * 2D: UNIFORM, except for the CLASSIC schedule of the direct pieces, which
+ * takes TAYLOR. */
 /* TAYLOR: no Arnoldi process; exp(tau Op) v by the truncated Taylor series
  * in substeps of at most theta/|Op| (theta from the remainder bound for 40
  * terms at krylov_tol), terms added until two consecutive term norms fall

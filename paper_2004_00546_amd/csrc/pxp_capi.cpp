@@ -146,6 +146,13 @@ bool use_si(const pxp_problem& p) {
     if (p.op == PXP_OP_ADVDIFF2D_UPWIND) return false;
     if (p.krylov == PXP_KRYLOV_SHIFT_INVERT) return true;
     if (p.krylov != PXP_KRYLOV_AUTO) return false;
+    // Burgers: the Chebyshev chain kernel wherever it covers the grid (it
+    // beats shift-and-invert also on the stiffest ragged instances, tau rho
+    // about 1600)
+    {
+        int cb, cp;
+        if (p.op == PXP_OP_BURGERS1D && cheb_chain_shape_pub(p.nx, &cb, &cp)) return false;
+    }
     const double h = p.L / p.nx;
     const double rho = 4.0 * p.nu / (h * h) + std::fabs(p.vx) / h;
     const double tau = p.op == PXP_OP_BURGERS1D ? 0.5 * p.T / p.P : p.T;

@@ -66,7 +66,8 @@ std::vector<pxp_problem> candidates(const pxp_problem& base, int lo, int hi) {
     const bool linear = base.op != PXP_OP_BURGERS1D;
     const bool twod = base.op == PXP_OP_ADVDIFF2D_UPWIND;
     for (int P : p_candidates(base, lo, hi))
-        for (int kr : {PXP_KRYLOV_POLY, PXP_KRYLOV_SHIFT_INVERT, PXP_KRYLOV_TAYLOR})
+        for (int kr : {PXP_KRYLOV_POLY, PXP_KRYLOV_SHIFT_INVERT, PXP_KRYLOV_TAYLOR,
+                       PXP_KRYLOV_CHEBYSHEV})
             for (int sc : {PXP_SCHED_CLASSIC, PXP_SCHED_CHAIN}) {
                 if (!linear && sc == PXP_SCHED_CHAIN) continue;
                 for (int kb : {256, 512}) {

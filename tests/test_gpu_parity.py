@@ -547,9 +547,14 @@ def test_ragged_burgers_shift_invert_batch(torch, orc):
 
 
 def test_auto_flavour_ragged_equals_explicit_choice(torch):
-    """AUTO picks shift-and-invert per instance where half a slice times the
-    diffusion spectral radius exceeds 64, else the Chebyshev flavour; each
-    batched result equals the run with that flavour named explicitly."""
+    """AUTO picks the Chebyshev flavour per instance where its chain kernel
+    covers the grid; elsewhere shift-and-invert where half a slice times the
+    diffusion spectral radius exceeds 64, else Chebyshev; each batched
+    result equals the run with that flavour named explicitly."""
+    def chain_shape(n):
+        return (n <= 256 and n % 64 == 0) or any(
+            n % b == 0 and (n // b) & (n // b - 1) == 0 and n // b <= cap
+            for b, cap in ((256, 8), (512, 16)))
     insts = ragged_burgers(seed=70)
     insts[2] = dict(insts[2], P=insts[2]["n_steps"] // 64)  # long macro steps
     # (long macro steps: a loose piece tolerance keeps the Magnus check
@@ -557,10 +562,14 @@ def test_auto_flavour_ragged_equals_explicit_choice(torch):
     r = api.GradientRunner(insts, method="paraexp", krylov="auto", tol=1e-5)
     r.run()
     assert r.status()[0] == 0
-    for inst, b in zip(insts, r.results()):
+    rep = _lib.pxp_last_report(r.problems, r.ws)
+    for inst, b, rp in zip(insts, r.results(), rep):
         h = inst["L"] / inst["nx"]
-        si = 0.5 * inst["T"] / inst["P"] * 4 * inst["nu"] / h**2 > 64
-        one = run(inst, "paraexp", krylov="shift_invert" if si else "chebyshev", tol=1e-5)
+        si = (not chain_shape(inst["nx"]) and
+              0.5 * inst["T"] / inst["P"] * 4 * inst["nu"] / h**2 > 64)
+        kr = "shift_invert" if si else "chebyshev"
+        assert rp["krylov_adjoint"] == kr, (inst["nx"], rp)
+        one = run(inst, "paraexp", krylov=kr, tol=1e-5)
         assert np.array_equal(one["grad"], b["grad"]), (inst["nx"], si)
 
 
