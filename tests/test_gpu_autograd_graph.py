@@ -20,7 +20,9 @@ def torch():
 
 @pytest.mark.parametrize("wl,krylov", [("advdiff1d_n128", "poly"),
                                        ("advdiff1d_n128", "shift_invert"),
-                                       ("burgers1d_n2048", "poly")])
+                                       ("burgers1d_n2048", "poly"),
+                                       ("burgers1d_n2048", "auto"),
+                                       ("burgers1d_nl", "auto")])
 def test_autograd_matches_oracle(torch, orc, wl, krylov):
     from paper_2004_00546_amd.autograd import Problem, paraexp_loss
     inst = workloads.make(wl)[0]
