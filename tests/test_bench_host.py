@@ -114,3 +114,36 @@ def test_burgers_class_models():
     assert m["slices"][1] == 5.0 * (st + nt * n * 8)
     # without the measured iteration count the marches have no model
     assert "nl_iter" not in bench.class_models([inst], [prob], None, {}, nl_k=None)
+
+
+def test_nl_model_formulas():
+    """eq. nonLinSpeedup on measured class times: the predicted time is
+    K (S tau_I + (n_t - S) tau_H + S tau_F) + the adjoint; s > 1 exactly
+    when N exceeds the bound solved from it; the ceiling is the N -> oo
+    limit."""
+    inst = dict(n_steps=8192, P=128, nl_slices=64)
+    S, Sa, nt = 128, 64, 8192
+    steps = 2
+    kern = {"slices": {"per_step_ms": 5 * 0.4}, "krylov_direct": {"per_step_ms": 5 * 1.6},
+            "nl_iter": {"per_step_ms": 5 * 0.6}, "ltv_adjoint": {"per_step_ms": 4.3},
+            "ltv_nodes": {"per_step_ms": 0.05}, "ltv_check": {"per_step_ms": 0.3}}
+    kern_ser = {"serial_direct": 7.66, "serial_reverse": 24.9}
+    report = [{"nl_iterations": 10}]
+    m = bench.nl_model(inst, kern, kern_ser, 0.018, 0.0327, report, steps)
+    assert m["iterations"] == 5.0 and m["slices"] == 64 and m["adjoint_slices"] == 128
+    ti, th, tf = 0.4 / S, 1.6 / (nt - S), 0.6 / S
+    adj = 4.3 + 0.05 + 0.3
+    assert m["predicted_ms"] == pytest.approx(5 * (S * ti + (nt - S) * th + S * tf) + adj)
+    tds, tas = 7.66 / nt, 24.9 / nt
+    tia, tha = 0.05 / Sa, 4.3 / (nt - Sa)
+    n_min = (5 * (ti + tf - th) + tia - tha) / (tds + tas - 5 * th - tha)
+    assert m["min_slices_for_speedup"] == pytest.approx(n_min)
+
+    # the bound is where the modelled speedup crosses one: eq. nonLinSpeedup
+    # with the measured per-step times at N slices of the horizon
+    def speedup(N):
+        ser = nt * (tds + tas)
+        par = 5 * (nt / N * (ti + tf) + nt * (N - 1) / N * th) + nt / N * tia + nt * (N - 1) / N * tha
+        return ser / par
+    assert speedup(n_min * 1.01) > 1.0 > speedup(n_min * 0.99)
+    assert m["ceiling_speedup"] == pytest.approx((tds + tas) / (5 * th + tha))
