@@ -87,8 +87,8 @@ enum { PXP_CTRL_FORCING = 0, PXP_CTRL_IC = 1 };
 /* AUTO: 1D linear: shift-and-invert when tau * rho > 64 (rho = 4 nu/h^2 +
  * |vx|/h, tau the horizon) and the grid has the cyclic-reduction shape,
  * else TAYLOR.  Burgers: CHEBYSHEV where its chain kernel covers the grid
- * (n = 64..256, or 256 or 512 threads of up to 8 or 16 points); elsewhere
- * shift-and-invert when half a slice times rho exceeds 64, else CHEBYSHEV.
+ * (see CHEBYSHEV); elsewhere shift-and-invert when half a slice times rho
+ * exceeds 64, else TAYLOR.
  * 2D: UNIFORM, except for the CLASSIC schedule of the direct pieces, which
  * takes TAYLOR. */
 /* TAYLOR: no Arnoldi process; exp(tau Op) v by the truncated Taylor series
@@ -107,7 +107,10 @@ enum { PXP_CTRL_FORCING = 0, PXP_CTRL_IC = 1 };
  * per pass of 16 terms, so one exponential spreads over many workgroups.
  * The adjoint's time integral uses the exact integral of every term's
  * weight against the forcing modulation. */
-/* CHEBYSHEV (Burgers only): no Arnoldi process; each exponential of the
+/* CHEBYSHEV (Burgers only, on grids its chain kernel covers in whole chunks:
+ * n a multiple of 64 up to 256, or 256 threads of 1, 2, 4 or 8 points, or
+ * 512 threads of 1, 2, 4, 8 or 16 points; PXP_EUNSUPPORTED elsewhere): no
+ * Arnoldi process; each exponential of the
  * time-varying chains, exp(tau J) v, by the Chebyshev series of exp on the
  * real interval of the Gershgorin bounds of tau J's real parts (the focal
  * interval of section 4.1's ReLPM; Chebyshev basis, coefficients the scaled

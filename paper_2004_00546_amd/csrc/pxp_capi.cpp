@@ -201,17 +201,18 @@ bool rk4_stable_cached(const pxp_problem& p) {
 
 // Taylor flavour: named, or AUTO where neither shift-and-invert nor
 // uniformisation is taken.
-bool use_taylor(const pxp_problem& p) {
-    if (p.krylov == PXP_KRYLOV_TAYLOR) return true;
-    return p.krylov == PXP_KRYLOV_AUTO && !use_si(p) && !uniform_direct(p) &&
-           p.op != PXP_OP_BURGERS1D;
-}
-
-// Chebyshev flavour: the time-varying Burgers chains, named or AUTO where
-// shift-and-invert is not taken.
+// Chebyshev flavour: the time-varying Burgers chains on the grids its
+// chain kernel covers, named or AUTO.
 bool use_cheb(const pxp_problem& p) {
     if (p.op != PXP_OP_BURGERS1D) return false;
-    return p.krylov == PXP_KRYLOV_CHEBYSHEV || (p.krylov == PXP_KRYLOV_AUTO && !use_si(p));
+    int cb, cp;
+    if (!cheb_chain_shape_pub(p.nx, &cb, &cp)) return false;
+    return p.krylov == PXP_KRYLOV_CHEBYSHEV || p.krylov == PXP_KRYLOV_AUTO;
+}
+
+bool use_taylor(const pxp_problem& p) {
+    if (p.krylov == PXP_KRYLOV_TAYLOR) return true;
+    return p.krylov == PXP_KRYLOV_AUTO && !use_si(p) && !uniform_direct(p) && !use_cheb(p);
 }
 
 // The Krylov kernels' workgroup shape for this problem exists, fits in LDS,
@@ -239,7 +240,12 @@ pxp_status validate(const pxp_problem& p) {
     if (p.sched != PXP_SCHED_CLASSIC && p.sched != PXP_SCHED_CHAIN && p.sched != PXP_SCHED_TREE)
         return PXP_EINVAL;
     if (p.krylov == PXP_KRYLOV_UNIFORM && p.op != PXP_OP_ADVDIFF2D_UPWIND) return PXP_EUNSUPPORTED;
-    if (p.krylov == PXP_KRYLOV_CHEBYSHEV && p.op != PXP_OP_BURGERS1D) return PXP_EUNSUPPORTED;
+    if (p.krylov == PXP_KRYLOV_CHEBYSHEV) {
+        // the flavour's chain kernel: Burgers grids it covers in whole chunks
+        int cb, cp;
+        if (p.op != PXP_OP_BURGERS1D || !cheb_chain_shape_pub(p.nx, &cb, &cp))
+            return PXP_EUNSUPPORTED;
+    }
     if (p.sched == PXP_SCHED_TREE && !uniform_direct(p)) return PXP_EUNSUPPORTED;
     if (p.prec != PXP_FP64 && p.prec != PXP_FP32_BULK) return PXP_EINVAL;
     if ((p.flags & ~(PXP_FLAG_ABSORBED_ADJOINT | PXP_FLAG_INTEGRAL_COST |

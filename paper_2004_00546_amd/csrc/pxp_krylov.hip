@@ -62,11 +62,6 @@ constexpr int sweep_batch(int cap) {
 
 __host__ __device__ inline size_t big_doubles(int n, int m, int block) {
     size_t vec = 2 * (size_t)n;
-    // Chebyshev flavour: the edge exchange (4 B) or the matvec buffer (n),
-    // then the coefficient table
-    const size_t cheb = (4 * (size_t)block > (size_t)n ? 4 * (size_t)block : (size_t)n) +
-                        CHEB_KMAX + 2;
-    if (cheb > vec) vec = cheb;
     // variable-coefficient solve: padded chunks (n + B) and 8 B for the
     // interface reduction
     if ((size_t)n + 9 * (size_t)block > vec) vec = (size_t)n + 9 * (size_t)block;
@@ -290,12 +285,6 @@ struct Core {
 
     __device__ __forceinline__ void expv(double tau, double ia, double ib, double* iout) {
         if (!(tau > 0.0)) return;
-        if constexpr (D::kCheb) {
-            if (a.cheb && !iout) {
-                self().expv_cheb(tau);
-                return;
-            }
-        }
         if (!SI && a.taylor) {
             self().expv_taylor(tau, ia, ib, iout);
             return;
@@ -391,7 +380,6 @@ struct Core {
 template <int PT, bool SI, bool VAR>
 struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
     using Base = Core<Ctx<PT, SI, VAR>, SI>;
-    static constexpr bool kCheb = VAR && !SI;  // the Chebyshev flavour exists
     using Base::a;
     using Base::S;
     using Base::n;
@@ -933,224 +921,6 @@ struct Ctx : Core<Ctx<PT, SI, VAR>, SI> {
         }
     }
 
-    // Chebyshev flavour (time-varying Burgers chains): V_0 <- exp(tau Op) V_0
-    // by the Chebyshev series of exp on a real interval that holds the real
-    // parts of tau Op's spectrum (the focal interval of the ReLPM of section
-    // 4.1, here the Gershgorin bounds of the current operator), in the
-    // Chebyshev basis instead of Newton form at Leja points:
-    //   exp(c + g x) = e^{c+g} (e_0 + 2 sum_{k>=1} e_k T_k(x)),
-    //   e_k = e^{-g} I_k(g)  (modified Bessel functions, scaled),
-    // c, g the interval's centre and half-width, T_k(Ah) v by the three-term
-    // recurrence with Ah = (tau Op - c)/g.  No inner products until the
-    // a priori degree (e_k + e_{k+1} <= tol/16, k >= g); from there the terms
-    // are checked in pairs until two consecutive ones are below tol |v|.
-    // Substeps keep the series within the coefficient table.  Where the
-    // workgroup covers the grid in whole chunks (B PT = n), thread t works on
-    // the contiguous points t PT .. t PT + PT - 1 with the operator's state W
-    // in registers and one barrier per term (chunk edges through LDS, two
-    // slots in turn); otherwise the generic matvec.  FP64 throughout.
-    __device__ __forceinline__ void expv_cheb(double tau) {
-        if constexpr (kCheb) {
-            const bool chunked = B * PT == n;
-            double u[PT], w[PT];
-            double wl = 0.0, wr = 0.0;
-            const int base = t * PT;
-            if (chunked) {
-                // V_0 was last written in the strided layout (the chain's
-                // additions, the start copy): other threads' points
-                __syncthreads();
-#pragma unroll
-                for (int q = 0; q < PT; ++q) {
-                    u[q] = V[base + q];
-                    w[q] = Wcur[base + q];
-                }
-                wl = Wcur[base == 0 ? n - 1 : base - 1];
-                wr = Wcur[base + PT == n ? 0 : base + PT];
-            } else {
-                this->gload(V, u);
-            }
-            // Gershgorin bounds of the real parts: row i of J(W)^T (or J(W))
-            // has diagonal d and off-diagonal entries lw, up
-            double lo = INFINITY, hi = -INFINITY;
-            auto row = [&](double Wm, double W0, double Wp) {
-                const double lw = a.ltv_fwd ? a.nuh2 + a.inv2h * W0 : a.nuh2 - a.inv2h * Wm;
-                const double up = a.ltv_fwd ? a.nuh2 - a.inv2h * W0 : a.nuh2 + a.inv2h * Wp;
-                const double d = -2.0 * a.nuh2 - a.inv2h * (Wp - Wm);
-                const double o = fabs(lw) + fabs(up);
-                lo = fmin(lo, d - o);
-                hi = fmax(hi, d + o);
-            };
-            if (chunked) {
-#pragma unroll
-                for (int q = 0; q < PT; ++q)
-                    row(q == 0 ? wl : w[q - 1], w[q], q == PT - 1 ? wr : w[q + 1]);
-            } else {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    if (!this->own(r)) continue;
-#pragma unroll
-                    for (int v = 0; v < VW; ++v) {
-                        const int i = this->gidx(r) + v;
-                        row(Wcur[i == 0 ? n - 1 : i - 1], Wcur[i], Wcur[i == n - 1 ? 0 : i + 1]);
-                    }
-                }
-            }
-            hi = block_max(hi, S.red);
-            lo = -block_max(-lo, S.red);
-            double nu = sqrt(block_sum(sumsq(u), S.red));
-            if (!(nu > 0.0) || !isfinite(lo) || !isfinite(hi)) {
-                this->flag_nonfinite(nu > 0.0 ? lo + hi : nu);
-                return;
-            }
-            // the half-width per substep keeps the degree g + 6 sqrt(g) + 40
-            // inside the coefficient table
-            const int kcap = CHEB_KMAX;
-            const double room = (double)(kcap - 40);
-            const double gmax = fmax(1.0, room - 6.0 * sqrt(room));
-            const double gfull = 0.5 * tau * (hi - lo);
-            int ns = (int)ceil(gfull / gmax);
-            if (ns < 1) ns = 1;
-            const double ts = tau / ns;
-            const double c = 0.5 * ts * (hi + lo);
-            // a wider interval still holds the spectrum: g >= 1/2 keeps the
-            // Bessel recurrence's growth per step moderate
-            const double g = fmax(0.5 * ts * (hi - lo), 0.5);
-            const int kc = (int)fmin((double)kcap, g + 6.0 * sqrt(g) + 40.0);
-            double* xch = S.big;  // chunk edges: two slots of 2 B
-            double* coef = S.big + (4 * B > n ? 4 * B : n);  // e_0 .. e_{kc + 1}
-            if (t == 0) {
-                // Miller's backward recurrence I_{k-1} = I_{k+1} + (2k/g) I_k
-                // from far above kc, normalised by e^g = I_0 + 2 sum I_k
-                const int top = kc + 64;
-                double ip = 0.0, ik = 1e-200, sum = 0.0;
-                for (int k = top; k >= 1; --k) {
-                    if (k <= kc + 1) coef[k] = ik;
-                    sum += 2.0 * ik;
-                    const double im = ip + (2.0 * k / g) * ik;
-                    ip = ik;
-                    ik = im;
-                    if (ik > 1e200) {
-                        const double sc = 1e-200;
-                        for (int j = k; j <= kc + 1; ++j) coef[j] *= sc;
-                        ip *= sc;
-                        ik *= sc;
-                        sum *= sc;
-                    }
-                }
-                coef[0] = ik;
-                sum += ik;
-                const double inv = 1.0 / sum;
-                for (int k = 0; k <= kc + 1; ++k) coef[k] *= inv;
-            }
-            __syncthreads();
-            // a priori degree
-            int ka = kc - 1;
-            for (int k = (int)ceil(g) > 1 ? (int)ceil(g) : 1; k < kc; ++k)
-                if (coef[k] + coef[k + 1] <= a.tol * 0.0625) {
-                    ka = k;
-                    break;
-                }
-            const double scale = exp(c + g);
-            const double ig = 1.0 / g;
-            int slotx = 0;
-            // z <- Ah x = (ts Op x - c x) / g
-            auto ahat = [&](const double (&x)[PT], double (&z)[PT]) {
-                if (chunked) {
-                    double* e = xch + slotx * 2 * B;
-                    e[t] = x[0];
-                    e[B + t] = x[PT - 1];
-                    __syncthreads();
-                    const double xl = e[B + (t == 0 ? B - 1 : t - 1)];
-                    const double xr = e[t == B - 1 ? 0 : t + 1];
-                    slotx ^= 1;
-#pragma unroll
-                    for (int q = 0; q < PT; ++q) {
-                        const double Wm = q == 0 ? wl : w[q - 1], Wp = q == PT - 1 ? wr : w[q + 1];
-                        const double xm = q == 0 ? xl : x[q - 1], xp = q == PT - 1 ? xr : x[q + 1];
-                        const double lw = a.ltv_fwd ? a.nuh2 + a.inv2h * w[q] : a.nuh2 - a.inv2h * Wm;
-                        const double up = a.ltv_fwd ? a.nuh2 - a.inv2h * w[q] : a.nuh2 + a.inv2h * Wp;
-                        const double d = -2.0 * a.nuh2 - a.inv2h * (Wp - Wm);
-                        z[q] = (ts * (lw * xm + d * x[q] + up * xp) - c * x[q]) * ig;
-                    }
-                } else {
-#pragma unroll
-                    for (int q = 0; q < PT; ++q) z[q] = x[q];
-                    this->apply(z, 0.0);
-#pragma unroll
-                    for (int q = 0; q < PT; ++q) z[q] = (ts * z[q] - c * x[q]) * ig;
-                }
-            };
-            bool noconv = false;
-            double worst = 0.0;
-            unsigned terms = 0;
-            for (int sub = 0; sub < ns; ++sub) {
-                double t0[PT], t1[PT], acc[PT], z[PT];
-#pragma unroll
-                for (int q = 0; q < PT; ++q) t0[q] = u[q];
-                ahat(u, t1);
-                ++terms;
-#pragma unroll
-                for (int q = 0; q < PT; ++q) acc[q] = coef[0] * u[q] + 2.0 * coef[1] * t1[q];
-                // the norm of the term before the pair (none yet)
-                double prev = INFINITY;
-                bool conv = false;
-                int slot = 0;
-                int k = 2;
-                while (k <= kc) {
-                    const bool two = k + 1 <= kc;
-                    double s1 = 0.0, s2 = 0.0;
-                    for (int e = 0; e < (two ? 2 : 1); ++e) {
-                        ahat(t1, z);
-                        ++terms;
-                        const double ck = 2.0 * coef[k + e];
-#pragma unroll
-                        for (int q = 0; q < PT; ++q) {
-                            const double tn = 2.0 * z[q] - t0[q];
-                            t0[q] = t1[q];
-                            t1[q] = tn;
-                            acc[q] += ck * tn;
-                        }
-                        if (k + 1 >= ka) (e == 0 ? s1 : s2) = ck * ck * sumsq(t1);
-                    }
-                    // pairs from the a priori degree on: both norms in one
-                    // reduction, the stop test of two consecutive terms
-                    if (k + 1 >= ka) {
-                        block_sum2(s1, s2, S.red, slot);
-                        const double n1 = scale * sqrt(s1), n2 = scale * sqrt(s2);
-                        if (prev + n1 <= a.tol * nu) {
-                            conv = true;
-                            worst = fmax(worst, (prev + n1) / nu);
-                            break;
-                        }
-                        if (two && n1 + n2 <= a.tol * nu) {
-                            conv = true;
-                            worst = fmax(worst, (n1 + n2) / nu);
-                            break;
-                        }
-                        prev = two ? n2 : n1;
-                    }
-                    k += two ? 2 : 1;
-                }
-                if (!conv) {
-                    noconv = true;
-                    worst = fmax(worst, isfinite(prev) ? prev / nu : 1.0);
-                }
-#pragma unroll
-                for (int q = 0; q < PT; ++q) u[q] = scale * acc[q];
-                if (sub + 1 < ns) nu = sqrt(block_sum(sumsq(u), S.red));
-            }
-            if (chunked) {
-                // every thread's reads of V happened before the first barrier
-#pragma unroll
-                for (int q = 0; q < PT; ++q) V[base + q] = u[q];
-            } else {
-                this->gstore(V, u);
-            }
-            this->report(worst, noconv, (unsigned)ns, terms);
-            __syncthreads();
-        }
-    }
-
     // hcol[k] = <V_k, z> for k <= j, KD basis vectors at a time (at most
     // 8, and at most 32 doubles per thread: sweep_batch).  The KD per-thread partial sums
     // are reduced inside the wave by recursive halving (log2 KD exchange
@@ -1452,15 +1222,28 @@ __global__ void __launch_bounds__(krylov_max_block(PT)) k_krylov1d(KrylovArgs a)
     dev_krylov1d<PT, SI, VAR>(a, blockIdx.x, lds);
 }
 
-// ---- the Chebyshev flavour's own chain kernel -----------------------------
-// A time-varying chain (KM_LTV with the Chebyshev flavour) in one
-// workgroup whose B threads cover the grid in whole chunks (B PT = n):
-// thread t keeps points t PT .. t PT + PT - 1 of the chain vector in
-// registers from the start vector to the result, each factor's operator
-// state W beside it (its two halo values loaded once per factor), and each
-// series term exchanges only the chunk edges through LDS (two slots in
-// turn, one barrier per term).  The series is the one of Ctx::expv_cheb.
-// LDS: 128 doubles for reductions, 4 B for the edges, the coefficients.
+// ---- the Chebyshev flavour: its own chain kernel ---------------------------
+// Each factor exp(tau Op) v of a time-varying chain (Op = J(W)^T, or J(W)
+// with ltv_fwd) by the Chebyshev series of exp on a real interval that
+// holds the real parts of tau Op's spectrum (the focal interval of the
+// ReLPM of section 4.1, here the Gershgorin bounds of the current operator),
+// in the Chebyshev basis instead of Newton form at Leja points:
+//   exp(c + g x) = e^{c+g} (e_0 + 2 sum_{k>=1} e_k T_k(x)),
+//   e_k = e^{-g} I_k(g)  (modified Bessel functions, scaled),
+// c, g the interval's centre and half-width, T_k(Ah) v by the three-term
+// recurrence with Ah = (tau Op - c)/g.  No inner products until the a priori
+// degree (e_k + e_{k+1} <= tol/16, k >= g); from there the terms are checked
+// in pairs until two consecutive ones are below tol |v|.  Substeps keep the
+// series within the coefficient table.
+//
+// A chain runs in one workgroup whose B threads cover the grid in whole
+// chunks (B PT = n): thread t keeps points t PT .. t PT + PT - 1 of the
+// chain vector in registers from the start vector to the result, each
+// factor's operator state W beside it (its two halo values loaded once per
+// factor, the next factor's during the current one), and each series term
+// exchanges only the chunk edges through LDS (two slots in turn, one
+// barrier per term).  LDS: 128 doubles for reductions, 4 B for the edges,
+// the coefficients and the a priori degree.
 constexpr int CHEB_CHAIN_LDS = 128 + 4 * 512 + CHEB_KMAX + 2;
 
 bool cheb_chain_shape(int n, int* B, int* pt) {
@@ -1782,7 +1565,6 @@ __device__ __forceinline__ void wave_halve(double (&part)[KD], int lane) {
 
 struct Ctx2 : Core<Ctx2, false> {
     using Base = Core<Ctx2, false>;
-    static constexpr bool kCheb = false;
     using Base::a;
     using Base::S;
     using Base::n;
@@ -2311,7 +2093,10 @@ hipError_t launch_krylov1d(const KrylovArgs& a, int block_hint, hipStream_t s) {
         if (!a.wop) return hipErrorInvalidValue;
         if (a.si && (B & (B - 1))) return hipErrorInvalidValue;
         int cB, cpt;
-        if (a.cheb && !a.si && !a.iout && cheb_chain_shape(a.n, &cB, &cpt)) {
+        if (a.cheb) {
+            // the Chebyshev flavour runs in its own kernel only (problems
+            // whose grid it does not cover are refused at validation)
+            if (a.si || a.iout || !cheb_chain_shape(a.n, &cB, &cpt)) return hipErrorInvalidValue;
             switch (cpt) {
                 case 1: k_cheb_chain<1><<<1, cB, 0, s>>>(a); break;
                 case 2: k_cheb_chain<2><<<1, cB, 0, s>>>(a); break;

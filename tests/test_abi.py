@@ -313,3 +313,15 @@ def test_nl_paraexp_rules_on_host(lib):
     with pytest.raises(_lib.PxpError) as e:
         _lib.pxp_workspace_size([api.make_problem(lin, krylov="poly")])
     assert e.value.code == _lib.PXP_EUNSUPPORTED
+
+
+def test_chebyshev_flavour_rules_on_host(lib):
+    """The Chebyshev flavour is the Burgers chains' (its own chain kernel):
+    named for a linear problem it is refused, for the Burgers workload's
+    grid accepted."""
+    lin = workloads.make("advdiff1d_n128")[0]
+    with pytest.raises(_lib.PxpError) as e:
+        _lib.pxp_workspace_size([api.make_problem(lin, krylov="chebyshev")])
+    assert e.value.code == _lib.PXP_EUNSUPPORTED
+    burg = workloads.make("burgers1d_n2048")[0]
+    assert _lib.pxp_workspace_size([api.make_problem(burg, krylov="chebyshev")]) > 0

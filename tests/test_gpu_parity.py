@@ -549,8 +549,8 @@ def test_ragged_burgers_shift_invert_batch(torch, orc):
 def test_auto_flavour_ragged_equals_explicit_choice(torch):
     """AUTO picks the Chebyshev flavour per instance where its chain kernel
     covers the grid; elsewhere shift-and-invert where half a slice times the
-    diffusion spectral radius exceeds 64, else Chebyshev; each batched
-    result equals the run with that flavour named explicitly."""
+    diffusion spectral radius exceeds 64, else Taylor; each batched result
+    equals the run with that flavour named explicitly."""
     def chain_shape(n):
         return (n <= 256 and n % 64 == 0) or any(
             n % b == 0 and (n // b) & (n // b - 1) == 0 and n // b <= cap
@@ -565,9 +565,8 @@ def test_auto_flavour_ragged_equals_explicit_choice(torch):
     rep = _lib.pxp_last_report(r.problems, r.ws)
     for inst, b, rp in zip(insts, r.results(), rep):
         h = inst["L"] / inst["nx"]
-        si = (not chain_shape(inst["nx"]) and
-              0.5 * inst["T"] / inst["P"] * 4 * inst["nu"] / h**2 > 64)
-        kr = "shift_invert" if si else "chebyshev"
+        si = 0.5 * inst["T"] / inst["P"] * 4 * inst["nu"] / h**2 > 64
+        kr = "chebyshev" if chain_shape(inst["nx"]) else ("shift_invert" if si else "taylor")
         assert rp["krylov_adjoint"] == kr, (inst["nx"], rp)
         one = run(inst, "paraexp", krylov=kr, tol=1e-5)
         assert np.array_equal(one["grad"], b["grad"]), (inst["nx"], si)
