@@ -138,6 +138,26 @@ def test_nl_own_slice_count(torch, orc):
     assert code == 0 and eq < FP64_GATE and eg < FP64_GATE
 
 
+@pytest.mark.parametrize("krylov", ["taylor", "shift_invert", "poly", "chebyshev"])
+def test_nl_chain_flavours(torch, orc, krylov):
+    """The chain of the linearised slice exponentials through every flavour
+    of the forward Jacobian J(W) (the shared Krylov kernel's forward
+    matvec, its shift-and-invert rows of I - gamma J(W) and its Taylor norm
+    bound; the Chebyshev chain kernel): the fixed point equals the serial
+    march up to the piece tolerance."""
+    inst = burgers(P=64, nl_iters=8)
+    want = orc.gradient(inst)
+    r = api.GradientRunner([inst], method="paraexp", krylov=krylov, tol=1e-11)
+    r.run()
+    got = r.results()[0]
+    rep = _lib.pxp_last_report(r.problems, r.ws)[0]
+    eq, eg = rel(got["qT"], want["qT"]), rel(got["grad"], want["grad"])
+    say("nl chain %s: qT %.2e grad %.2e, direct flavour %s, %d iterations" % (
+        krylov, eq, eg, rep["krylov_direct"], rep["nl_iterations"]))
+    assert rep["krylov_direct"] == krylov and rep["sched"] == "chain"
+    assert eq < 1e-11 and eg < 1e-9
+
+
 def test_nl_one_slice_is_the_serial_march(torch, orc):
     """P = 1: no slice start comes from an exponential, so the fixed point
     is the serial march to rounding."""
