@@ -416,49 +416,109 @@ __device__ __forceinline__ void burgers_rhs(const R (&Y)[PT], R l, R r, R inv2h,
     }
 }
 
-// One Burgers RK4 step in registers (stages exchanged through LDS); the
-// state is the compensated pair (y, yc).
+// One Burgers RK4 step in registers; the state is the compensated pair
+// (y, yc).  With 8 or more points per thread the chunk edges are exchanged
+// once per step: each thread takes four points of y from either neighbour
+// and evaluates the stages on its own points plus a halo that shrinks by
+// one point per stage (own +-3, +-2, +-1, own), in the LDS region after
+// the exchange buffers (8 B .. 24 B values, two slots in turn); every value
+// is computed as the stage-by-stage exchange computes it, so the result is
+// the same bit for bit with one barrier per step instead of four.  Fewer
+// points per thread exchange every stage.
 template <int PT, int NB, typename R>
 __device__ __forceinline__ void burgers_step(R (&y)[PT], R (&yc)[PT], R dt,
                                              R inv2h, R nuh2, R* lds, int& buf) {
-    R acc[PT], Y[PT], k[PT], l[1], r[1];
-    {
-        const R* arr[1] = {y};
-        exch<PT, 1, NB>(arr, lds, buf, l, r);
-    }
-    burgers_rhs<PT, R>(y, l[0], r[0], inv2h, nuh2, k);
+    if constexpr (PT >= 8) {
+        constexpr int H = 4, E = PT + 2 * H;  // extended index i <-> point i - H
+        const int t = threadIdx.x, B = blockDim.x;
+        R* e = lds + 8 * B + buf * 8 * B;
 #pragma unroll
-    for (int q = 0; q < PT; ++q) {
-        acc[q] = k[q];
-        Y[q] = y[q] + (R)0.5 * dt * k[q];
-    }
-    {
-        const R* arr[1] = {Y};
-        exch<PT, 1, NB>(arr, lds, buf, l, r);
-    }
-    burgers_rhs<PT, R>(Y, l[0], r[0], inv2h, nuh2, k);
+        for (int j = 0; j < H; ++j) {
+            e[j * B + t] = y[j];
+            e[(H + j) * B + t] = y[PT - H + j];
+        }
+        __syncthreads();
+        const int tl = (t == 0) ? B - 1 : t - 1;
+        const int tr = (t == B - 1) ? 0 : t + 1;
+        R y0[E], Y[E], k[E], acc[PT];
 #pragma unroll
-    for (int q = 0; q < PT; ++q) {
-        acc[q] += (R)2 * k[q];
-        Y[q] = y[q] + (R)0.5 * dt * k[q];
-    }
-    {
-        const R* arr[1] = {Y};
-        exch<PT, 1, NB>(arr, lds, buf, l, r);
-    }
-    burgers_rhs<PT, R>(Y, l[0], r[0], inv2h, nuh2, k);
+        for (int j = 0; j < H; ++j) {
+            y0[j] = e[(H + j) * B + tl];
+            y0[H + PT + j] = e[j * B + tr];
+        }
 #pragma unroll
-    for (int q = 0; q < PT; ++q) {
-        acc[q] += (R)2 * k[q];
-        Y[q] = y[q] + dt * k[q];
-    }
-    {
-        const R* arr[1] = {Y};
-        exch<PT, 1, NB>(arr, lds, buf, l, r);
-    }
-    burgers_rhs<PT, R>(Y, l[0], r[0], inv2h, nuh2, k);
+        for (int q = 0; q < PT; ++q) y0[H + q] = y[q];
+        buf ^= 1;
+        // the right-hand side at extended indices [a, b) from Y
+        auto rhs = [&](const R (&Z)[E], int a, int b) {
 #pragma unroll
-    for (int q = 0; q < PT; ++q) kadd<R>(y[q], yc[q], (dt / (R)6) * (acc[q] + k[q]));
+            for (int i = 0; i < E; ++i) {
+                if (i < a || i >= b) continue;
+                k[i] = -Z[i] * ((Z[i + 1] - Z[i - 1]) * inv2h) +
+                       nuh2 * ((Z[i + 1] + Z[i - 1]) - (R)2 * Z[i]);
+            }
+        };
+        rhs(y0, 1, E - 1);
+#pragma unroll
+        for (int i = 1; i < E - 1; ++i) {
+            if (i >= H && i < H + PT) acc[i - H] = k[i];
+            Y[i] = y0[i] + (R)0.5 * dt * k[i];
+        }
+        rhs(Y, 2, E - 2);
+#pragma unroll
+        for (int i = 2; i < E - 2; ++i) {
+            if (i >= H && i < H + PT) acc[i - H] += (R)2 * k[i];
+            Y[i] = y0[i] + (R)0.5 * dt * k[i];
+        }
+        rhs(Y, 3, E - 3);
+#pragma unroll
+        for (int i = 3; i < E - 3; ++i) {
+            if (i >= H && i < H + PT) acc[i - H] += (R)2 * k[i];
+            Y[i] = y0[i] + dt * k[i];
+        }
+        rhs(Y, H, H + PT);
+#pragma unroll
+        for (int q = 0; q < PT; ++q) kadd<R>(y[q], yc[q], (dt / (R)6) * (acc[q] + k[H + q]));
+    } else {
+        R acc[PT], Y[PT], k[PT], l[1], r[1];
+        {
+            const R* arr[1] = {y};
+            exch<PT, 1, NB>(arr, lds, buf, l, r);
+        }
+        burgers_rhs<PT, R>(y, l[0], r[0], inv2h, nuh2, k);
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            acc[q] = k[q];
+            Y[q] = y[q] + (R)0.5 * dt * k[q];
+        }
+        {
+            const R* arr[1] = {Y};
+            exch<PT, 1, NB>(arr, lds, buf, l, r);
+        }
+        burgers_rhs<PT, R>(Y, l[0], r[0], inv2h, nuh2, k);
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            acc[q] += (R)2 * k[q];
+            Y[q] = y[q] + (R)0.5 * dt * k[q];
+        }
+        {
+            const R* arr[1] = {Y};
+            exch<PT, 1, NB>(arr, lds, buf, l, r);
+        }
+        burgers_rhs<PT, R>(Y, l[0], r[0], inv2h, nuh2, k);
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            acc[q] += (R)2 * k[q];
+            Y[q] = y[q] + dt * k[q];
+        }
+        {
+            const R* arr[1] = {Y};
+            exch<PT, 1, NB>(arr, lds, buf, l, r);
+        }
+        burgers_rhs<PT, R>(Y, l[0], r[0], inv2h, nuh2, k);
+#pragma unroll
+        for (int q = 0; q < PT; ++q) kadd<R>(y[q], yc[q], (dt / (R)6) * (acc[q] + k[q]));
+    }
 }
 
 // The march over steps [rg.s0, rg.s1) from y0 (the state at s0) to yT
@@ -1219,7 +1279,7 @@ hipError_t launch_rk4_burgers_direct(const double* y0, double* yT, double* ckpt,
     if (!pick_shape(n, block_hint, &block, &pt)) return hipErrorInvalidValue;
     const double h = L / n;
     BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
-    const size_t lds = sizeof(double) * 4 * block;
+    const size_t lds = sizeof(double) * (pt >= 8 ? 24 : 4) * block;
     BurgersRange rg{0, n_t, nullptr, 0.0, nullptr, 0, 0};
     if (rgp) rg = *rgp;
     if (rg.s0 < 0 || rg.s1 > n_t || rg.s0 >= rg.s1) return hipErrorInvalidValue;
@@ -1237,7 +1297,7 @@ hipError_t launch_burgers_nodes(const double* ckpt, double* W, int n, int64_t n_
     if (S <= 0 || n_t % S) return hipErrorInvalidValue;
     const double h = L / n;
     BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
-    const size_t lds = sizeof(double) * 4 * block;
+    const size_t lds = sizeof(double) * (pt >= 8 ? 24 : 4) * block;
     const int Q = (int)(n_t / S);
     if (count < 0) count = Q - qbase;
     if (qbase < 0 || count <= 0 || qbase + count > Q) return hipErrorInvalidValue;
@@ -1256,7 +1316,7 @@ hipError_t launch_rk4_burgers_reverse(const double* ckpt, const double* lamT,
         return hipErrorInvalidValue;
     const double h = L / n;
     BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
-    const size_t lds = sizeof(double) * 8 * block;
+    const size_t lds = sizeof(double) * (pt >= 8 ? 24 : 8) * block;
     BurgersRange rg{0, n_t, nullptr, 0.0, nullptr, 0, 0};
     if (rgp) rg = *rgp;
     if (rg.s0 < 0 || rg.s1 > n_t || rg.s0 >= rg.s1 || rg.s0 % c || rg.s1 % c)
@@ -1326,7 +1386,7 @@ hipError_t launch_burgers_adj_slices(const double* ckpt, const double* tgt, doub
         return hipErrorInvalidValue;
     const double h = L / n;
     BurgersC bc{1.0 / (2.0 * h), nu / (h * h)};
-    const size_t lds = sizeof(double) * 8 * block;
+    const size_t lds = sizeof(double) * (pt >= 8 ? 24 : 8) * block;
     PXP_DISPATCH_PT(pt, k_burgers_adj_slices, double,
                     <<<count, block, lds, s>>>(ckpt, tgt, gw, seg, mu, bounds, s_first, n,
                                                n_t, c, dt, bc))
@@ -1336,7 +1396,7 @@ hipError_t launch_burgers_adj_slices(const double* ckpt, const double* tgt, doub
 hipError_t launch_burgers_batch(int which, const BurgersDesc* tab, int count,
                                 int total_blocks, int fp32, hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    const size_t lds = sizeof(double) * 8 * 256;
+    const size_t lds = sizeof(double) * 24 * 256;
     const int grid = (which == 2) ? total_blocks : count;
     if (which == 0) {
         if (fp32) k_burgers_direct_batch<float><<<grid, 256, lds, s>>>(tab);
@@ -1345,7 +1405,7 @@ hipError_t launch_burgers_batch(int which, const BurgersDesc* tab, int count,
         if (fp32) k_burgers_reverse_batch<float><<<grid, 256, lds, s>>>(tab);
         else k_burgers_reverse_batch<double><<<grid, 256, lds, s>>>(tab);
     } else if (which == 3) {
-        const size_t lds512 = sizeof(double) * 8 * 512;
+        const size_t lds512 = sizeof(double) * 24 * 512;
         if (fp32) k_burgers_reverse_batch512<float><<<grid, 512, lds512, s>>>(tab);
         else k_burgers_reverse_batch512<double><<<grid, 512, lds512, s>>>(tab);
     } else {
