@@ -322,7 +322,8 @@ def class_models(insts, problems, args, counters, nl_k=None):
                 "halves' states and Lambda shares and writes its state and share (6 "
                 "vectors per pair; the root's share is Lambda); %.3g term-points "
                 "beside it" % adj_terms)
-        else:
+        elif all(int(p.krylov) in (2, 4) for p in problems):
+            # the adjoint piece by uniformisation (AUTO or named)
             lam = [sten2d_mu(x) * x["T"] for x in insts]
             adj_terms = sum(pois_terms(min(l, 600.0), tol) * math.ceil(l / 600.0) * nn
                             for l, nn in zip(lam, n))

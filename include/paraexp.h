@@ -79,7 +79,11 @@ enum { PXP_CTRL_FORCING = 0, PXP_CTRL_IC = 1 };
  * beta h_{k+1,k} |e_k^T exp(ts H_k) e_1| <= krylov_tol beta ts/tau, with an
  * early exit every 4 dimensions from 8 on. */
 /* SHIFT_INVERT: Arnoldi on (I - gamma A)^{-1}, gamma = si_gamma times the
- * exponential's time, one step over the whole time.  From about m/2 the
+ * exponential's time, one step over the whole time.  The solve: periodic
+ * tridiagonal (1D, the Burgers Jacobian with variable coefficients), or, in
+ * 2D (named only; power-of-two grids of at most 256 x 256, terminal cost),
+ * the constant-coefficient five-point operator divided out mode by mode in
+ * the 2D Fourier basis.  From about m/2 the
  * approximation is compared with the previous check's; the error is
  * extrapolated from the contraction of those differences and the space stops
  * once it is below krylov_tol (relative to |v|).  Both Arnoldi flavours use
@@ -207,7 +211,8 @@ typedef struct {
     double T, omega, beta;           /* horizon, s(t) = sin(omega t), weight   */
     double krylov_tol;               /* relative a-posteriori tolerance        */
     double si_gamma;                 /* shift-and-invert shift as a fraction of
-                                        the exponential's time (0 = 0.2)      */
+                                        the exponential's time (0 = 0.2 in
+                                        1D, 0.05 in 2D)                       */
     int32_t hyb_slices;              /* integral cost, Burgers: adjoint slices
                                         of the hybrid scheme (0 = P)          */
     int32_t hyb_group;               /* slices per adjoint launch (0 = 4)      */

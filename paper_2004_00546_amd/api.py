@@ -10,7 +10,7 @@ from . import _lib
 
 def make_problem(inst: dict, krylov: str = "shift_invert", sched: str = "classic",
                  tol: float = 1e-10, block: int = 0, kblock: int = 0,
-                 si_gamma: float = 0.2, absorbed: bool = False,
+                 si_gamma: float = 0.0, absorbed: bool = False,
                  P: int | None = None, m: int | None = None,
                  prec: str = "fp64") -> _lib.pxp_problem:
     p = _lib.pxp_problem()
@@ -40,7 +40,7 @@ def make_problem(inst: dict, krylov: str = "shift_invert", sched: str = "classic
     p.omega = float(inst.get("omega", 1.0))
     p.beta = float(inst.get("beta", 0.0))
     p.krylov_tol = float(tol)
-    p.si_gamma = float(si_gamma)
+    p.si_gamma = float(si_gamma)  # 0: the library's default for the operator
     # hybrid scheme of the Burgers integral cost: adjoint slices and their
     # partition (eq. nonEquiP)
     p.hyb_slices = int(inst.get("hyb_slices", 0))

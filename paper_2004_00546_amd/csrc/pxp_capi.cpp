@@ -143,7 +143,8 @@ bool rk4_stable_advdiff1d(const pxp_problem& p) {
 // exceeds 64, and the grid allows the cyclic-reduction shape; otherwise the
 // Taylor flavour.
 bool use_si(const pxp_problem& p) {
-    if (p.op == PXP_OP_ADVDIFF2D_UPWIND) return false;
+    // 2D: named only (the Fourier solve; AUTO takes uniformisation)
+    if (p.op == PXP_OP_ADVDIFF2D_UPWIND) return p.krylov == PXP_KRYLOV_SHIFT_INVERT;
     if (p.krylov == PXP_KRYLOV_SHIFT_INVERT) return true;
     if (p.krylov != PXP_KRYLOV_AUTO) return false;
     // Burgers: the Chebyshev chain kernel wherever it covers the grid (it
@@ -284,17 +285,19 @@ pxp_status validate(const pxp_problem& p) {
         // band marches and uniformised exponentials: power-of-two rows of
         // 64..256 points, whole bands of 16 rows (at most 4 steps per slice:
         // checked per method); streamed Krylov: 2048-point multiples,
-        // polynomial or Taylor flavour; FP64
+        // polynomial, Taylor or shift-and-invert flavour (the last on
+        // power-of-two grids of at most 256 x 256, for the Fourier solve); FP64
         if (p.nx < 64 || p.nx > 256 || !is_pow2(p.nx)) return PXP_EUNSUPPORTED;
         if (p.ny < BAND_ROWS || p.ny % BAND_ROWS) return PXP_EUNSUPPORTED;
         if (p.vx < 0.0 || p.vy < 0.0 || !std::isfinite(p.vy)) return PXP_EUNSUPPORTED;
         if (p.prec != PXP_FP64) return PXP_EUNSUPPORTED;
-        if (p.krylov == PXP_KRYLOV_SHIFT_INVERT) return PXP_EUNSUPPORTED;
+        if (use_si(p) && !fft2_grid(p.nx, p.ny)) return PXP_EUNSUPPORTED;
         if (p.krylov == PXP_KRYLOV_UNIFORM && p.sched == PXP_SCHED_CLASSIC)
             return PXP_EUNSUPPORTED;
         if (!uniform_direct(p) || !uniform_adjoint(p)) {
             if (grid_n(p) % (2 * KRYLOV2D_BLOCK)) return PXP_EUNSUPPORTED;
-            if (p.m < 1 || krylov2d_lds_bytes(p.m) > 160 * 1024) return PXP_EUNSUPPORTED;
+            if (p.m < 1 || krylov2d_lds_bytes(p.m, use_si(p)) > 160 * 1024)
+                return PXP_EUNSUPPORTED;
             // the Taylor flavour keeps four vectors in the basis region
             if (use_taylor(p) && p.m < 3) return PXP_EUNSUPPORTED;
         }
@@ -793,7 +796,12 @@ KrylovArgs kargs(const Ctx& c, Tri op) {
     a.n = c.n();
     a.m = c.p.m;
     a.tol = c.p.krylov_tol;
-    a.gamma_frac = (c.p.si_gamma > 0.0) ? c.p.si_gamma : 0.2;
+    // shift gamma = gamma_frac tau: 0.2 in 1D; the 2D upwind operator's
+    // advection reaches further into the complex plane and its spaces
+    // converge fastest near 0.05 (a random vector on a 64 x 64 grid,
+    // tau = 0.7: relative error 6e-11 at dimension 28, against 4e-6 at 0.2)
+    a.gamma_frac = (c.p.si_gamma > 0.0) ? c.p.si_gamma
+                                        : (c.p.op == PXP_OP_ADVDIFF2D_UPWIND ? 0.05 : 0.2);
     a.op = op;
     a.basis = c.at(c.L.basis);
     a.status = c.st;
@@ -2062,6 +2070,32 @@ pxp_status run_levels(const std::vector<std::vector<std::vector<PJob>>>& per, Po
 // per instance -> qT.  tgt (nullable; per instance, nullable): for the
 // integral-cost instances, also the step sources and the cost partials
 // (nparts[j] receives their count).
+// Launches the 2D Krylov entries of kt: the shift-and-invert entries (a.si)
+// and the others as separate launches (the kernel is specialised on the
+// flavour); each group's table goes to its own part of dk, its entries'
+// first workgroups numbered from zero.
+pxp_status launch_krylov2d_groups(const std::vector<KrylovArgs>& kt, KrylovArgs* dk,
+                                  hipStream_t s) {
+    size_t off = 0;
+    for (int si = 0; si < 2; ++si) {
+        std::vector<KrylovArgs> g;
+        int blk = 0;
+        size_t lds = 0;
+        for (KrylovArgs a : kt) {
+            if ((a.si != 0) != (si != 0)) continue;
+            a.blk0 = blk;
+            blk += a.mode == KM_CLASSIC ? a.npieces : 1;
+            lds = std::max(lds, krylov2d_lds_bytes(a.m, si));
+            g.push_back(a);
+        }
+        if (g.empty()) continue;
+        HIPCHK(launch_upload(dk + off, g.data(), g.size() * sizeof(KrylovArgs), s));
+        HIPCHK(launch_krylov2d(dk + off, (int)g.size(), blk, lds, si, s));
+        off += g.size();
+    }
+    return PXP_OK;
+}
+
 pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, void* ws,
                            const Layout& Ly, const std::vector<const double*>& init,
                            const std::vector<const double*>& F,
@@ -2221,7 +2255,6 @@ pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, v
         if (p.P == 1 || uniform_direct(p)) continue;
         Ctx c = make_ctx(p, ws, Ly, idx[j], s);
         KrylovArgs a = kargs(c, Tri{0.0, 0.0, 0.0});
-        a.si = 0;
         a.op5 = advdiff2d_sten(p);
         a.anorm = sten_norm(a.op5);
         a.nx = p.nx;
@@ -2244,11 +2277,9 @@ pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, v
     }
     if (!kt.empty()) {
         auto* dk = reinterpret_cast<KrylovArgs*>(static_cast<char*>(ws) + Ly.ktab);
-        HIPCHK(launch_upload(dk, kt.data(), kt.size() * sizeof(KrylovArgs), s));
-        size_t lds = 0;
-        for (const KrylovArgs& a : kt) lds = std::max(lds, krylov2d_lds_bytes(a.m));
         ProfScope ps(PXP_K_KRYLOV_DIRECT, s);
-        HIPCHK(launch_krylov2d(dk, (int)kt.size(), kblk, lds, s));
+        const pxp_status st = launch_krylov2d_groups(kt, dk, s);
+        if (st != PXP_OK) return st;
     }
     // (3) superposition
     for (size_t j = 0; j < idx.size(); ++j) {
@@ -2474,7 +2505,6 @@ pxp_status adjoint_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, 
         if (uniform_adjoint(p)) continue;
         Ctx c = make_ctx(p, ws, Ly, idx[j], s);
         KrylovArgs a = kargs(c, Tri{0.0, 0.0, 0.0});
-        a.si = 0;
         a.op5 = transpose5(advdiff2d_sten(p));
         a.anorm = sten_norm(a.op5);
         a.nx = p.nx;
@@ -2492,12 +2522,8 @@ pxp_status adjoint_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, 
     }
     if (kt.empty()) return PXP_OK;
     auto* dk = reinterpret_cast<KrylovArgs*>(static_cast<char*>(ws) + Ly.ktab);
-    HIPCHK(launch_upload(dk, kt.data(), kt.size() * sizeof(KrylovArgs), s));
-    size_t lds = 0;
-    for (const KrylovArgs& a : kt) lds = std::max(lds, krylov2d_lds_bytes(a.m));
     ProfScope ps(PXP_K_KRYLOV_ADJOINT, s);
-    HIPCHK(launch_krylov2d(dk, (int)kt.size(), (int)kt.size(), lds, s));
-    return PXP_OK;
+    return launch_krylov2d_groups(kt, dk, s);
 }
 
 }  // namespace

@@ -337,9 +337,12 @@ hipError_t launch_apply5(const double* x, double* out, int nx, int ny, Sten5 op,
 // 2D Krylov pieces, vectors streamed from global memory, one workgroup per
 // piece: KM_CLASSIC (npieces workgroups), KM_CHAIN or KM_SINGLE (one).
 // Entries of `tab` own workgroups blk0 .. (next entry's blk0) - 1.
+// si: every entry is a shift-and-invert entry (the Fourier solve; the grid
+// passes fft2_grid), else none is.
 hipError_t launch_krylov2d(const KrylovArgs* tab, int count, int total_blocks,
-                           size_t lds, hipStream_t s);
-size_t krylov2d_lds_bytes(int m);
+                           size_t lds, int si, hipStream_t s);
+size_t krylov2d_lds_bytes(int m, int si);
+bool fft2_grid(int nx, int ny);
 constexpr int KRYLOV2D_BLOCK = 1024;
 
 // ---- 2D exponential actions by uniformisation -------------------------------

@@ -1545,7 +1545,7 @@ __global__ void __launch_bounds__(NT) k_krylov_ltv_batch(const KrylovArgs* tab) 
 // r < n / (2B), of every vector, and each Arnoldi step streams them: the
 // five-point stencil writes the new vector, the Gram-Schmidt passes read the
 // basis (8 vectors per exchange round for the dots) and update the new vector
-// in place.  Polynomial Krylov only.
+// in place.  Polynomial and Taylor flavours, and shift-and-invert (below).
 template <int KD, int O>
 __device__ __forceinline__ void wave_halve(double (&part)[KD], int lane) {
     if constexpr (KD > 1) {
@@ -1563,8 +1563,94 @@ __device__ __forceinline__ void wave_halve(double (&part)[KD], int lane) {
     }
 }
 
-struct Ctx2 : Core<Ctx2, false> {
-    using Base = Core<Ctx2, false>;
+// ---- 2D shift-and-invert: (I - gamma A)^{-1} by Fourier diagonalisation ----
+// The five-point operator has constant coefficients on a periodic grid, so
+// the Fourier mode exp(i(thx col + thy row)) (thx = 2 pi kx / nx, thy =
+// 2 pi ky / ny) is an eigenvector with eigenvalue
+//   lam = c + w e^{-i thx} + e e^{i thx} + s e^{-i thy} + n e^{i thy},
+// and the solve divides each mode by 1 - gamma lam.  It runs in place on
+// the output vector in three passes of one workgroup:
+//   rows:    the real DFT of every row (radix-2 in LDS, one wave per row),
+//            packed into the row's nx doubles: slot 0 the mode kx = 0, slot
+//            1 the mode kx = nx/2 (both real for real data), slots 2kx,
+//            2kx + 1 the complex mode 0 < kx < nx/2;
+//   columns: for each kx (one wave per kx), the DFT along y of that slot's
+//            column, the division, the inverse DFT along y; the kx = 0 and
+//            nx/2 columns have real y-operators and stay real;
+//   rows:    the inverse real DFT of every row.
+// nx and ny are powers of two of at most FFT2_MAX; the twiddle table
+// e^{-2 pi i k / FFT2_MAX} stays in LDS for the whole launch.
+constexpr int FFT2_MAX = 256;
+
+// Doubles of the Krylov layout in LDS: Core's regions for dimension m up to
+// its small dense scratch S.big, then that scratch (shared with the dot
+// partials of KRYLOV2D_BLOCK threads).
+__host__ __device__ constexpr size_t krylov2d_big_doubles(int m) {
+    return (size_t)(m + 1) * (KRYLOV2D_BLOCK / 64) > 6 * (size_t)m * m + 5 * (size_t)m + 8
+               ? (size_t)(m + 1) * (KRYLOV2D_BLOCK / 64)
+               : 6 * (size_t)m * m + 5 * (size_t)m + 8;
+}
+__host__ __device__ constexpr size_t krylov2d_core_doubles(int m) {
+    return 128 + (size_t)(((m + 1 + 7) / 8) * 8) * 2 + 8 + (size_t)(m + 1) * m + UT_DOUBLES +
+           krylov2d_big_doubles(m);
+}
+// Shift-and-invert: the per-wave FFT buffers share S.big (the solve runs
+// between the small dense phases, and nothing in S.big outlives a solve: the
+// checks keep their coefficients in S.yprev, and the final coefficients are
+// formed after the last solve); the twiddle table follows the larger of the
+// two.
+constexpr size_t FFT2_BUF_DOUBLES = (size_t)(KRYLOV2D_BLOCK / WAVE) * 2 * FFT2_MAX;
+__host__ __device__ constexpr size_t krylov2d_si_doubles(int m) {
+    return krylov2d_core_doubles(m) - krylov2d_big_doubles(m) +
+           (krylov2d_big_doubles(m) > FFT2_BUF_DOUBLES ? krylov2d_big_doubles(m)
+                                                       : FFT2_BUF_DOUBLES) +
+           2 * FFT2_MAX;
+}
+
+__device__ __forceinline__ int bitrev(int j, int lb) {
+    return lb == 0 ? 0 : (int)(__brev((unsigned)j) >> (32 - lb));
+}
+
+__device__ __forceinline__ double2 cmul(double2 u, double2 v) {
+    return make_double2(u.x * v.x - u.y * v.y, u.x * v.y + u.y * v.x);
+}
+
+// In-place radix-2 transform of the L points in buf (L a power of two,
+// L <= FFT2_MAX) by the lanes of one wave.  dit: the input is in bit-reversed
+// order and the output in natural order (decimation in time); otherwise the
+// reverse (decimation in frequency).  inv: e^{+2 pi i jk / L} (unscaled).
+// Every stage ends at a workgroup barrier, so all waves call it with the
+// same L whether or not their buffer holds a transform (act).
+__device__ __forceinline__ void wave_fft(double2* buf, const double2* tw, int L, bool dit,
+                                         bool inv, bool act, int lane) {
+    const int nb = L >> 1;
+    for (int s = 0; (1 << s) < L; ++s) {
+        const int len = dit ? (2 << s) : (L >> s), half = len >> 1;
+        const int ts = FFT2_MAX / len;
+        if (act) {
+            for (int b = lane; b < nb; b += WAVE) {
+                const int grp = b / half, pos = b - grp * half;
+                const int i0 = grp * len + pos, i1 = i0 + half;
+                double2 w = tw[pos * ts];
+                if (inv) w.y = -w.y;
+                const double2 u = buf[i0], v = buf[i1];
+                if (dit) {
+                    const double2 tv = cmul(v, w);
+                    buf[i0] = make_double2(u.x + tv.x, u.y + tv.y);
+                    buf[i1] = make_double2(u.x - tv.x, u.y - tv.y);
+                } else {
+                    buf[i0] = make_double2(u.x + v.x, u.y + v.y);
+                    buf[i1] = cmul(make_double2(u.x - v.x, u.y - v.y), w);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <bool SI>
+struct Ctx2 : Core<Ctx2<SI>, SI> {
+    using Base = Core<Ctx2<SI>, SI>;
     using Base::a;
     using Base::S;
     using Base::n;
@@ -1575,11 +1661,126 @@ struct Ctx2 : Core<Ctx2, false> {
     using Base::nre;
     double* V;
     int G, nx, ny;
+    double2* fbuf;  // shift-and-invert: this wave's FFT buffer
+    double2* tw;    // shift-and-invert: twiddle table
 
     __device__ Ctx2(const KrylovArgs& a_, double* lds, double* V_)
-        : Base(a_, lds), V(V_), G(a_.n / (2 * blockDim.x)), nx(a_.nx), ny(a_.ny) {}
+        : Base(a_, lds), V(V_), G(a_.n / (2 * blockDim.x)), nx(a_.nx), ny(a_.ny) {
+        if constexpr (SI) {
+            tw = reinterpret_cast<double2*>(lds + krylov2d_si_doubles(a_.m) - 2 * FFT2_MAX);
+            fbuf = reinterpret_cast<double2*>(S.big) + (size_t)wave_id() * FFT2_MAX;
+            for (int k = t; k < FFT2_MAX; k += B) {
+                double sn, cs;
+                sincospi(-2.0 * (double)k / (double)FFT2_MAX, &sn, &cs);
+                tw[k] = make_double2(cs, sn);
+            }
+            __syncthreads();
+        }
+    }
 
     __device__ __forceinline__ void before_space(double) {}
+
+    // dst = (I - gamma A)^{-1} src (all of src visible to the workgroup; dst
+    // complete at the caller's next barrier).  src and dst are distinct.
+    __device__ void solve(const double* __restrict__ src, double* __restrict__ dst,
+                          double gamma) {
+        const int lane = lane_id(), wv = wave_id(), nw = num_waves();
+        const int lx = 31 - __clz(nx), ly = 31 - __clz(ny), hx = nx >> 1;
+        // rows: real DFT, packed
+        for (int r0 = 0; r0 < ny; r0 += nw) {
+            const int r = r0 + wv;
+            const bool act = r < ny;
+            if (act)
+                for (int j = lane; j < nx; j += WAVE)
+                    fbuf[bitrev(j, lx)] = make_double2(src[(size_t)r * nx + j], 0.0);
+            __syncthreads();
+            wave_fft(fbuf, tw, nx, true, false, act, lane);
+            if (act) {
+                double* row = dst + (size_t)r * nx;
+                for (int k = lane; k <= hx; k += WAVE) {
+                    const double2 X = fbuf[k];
+                    if (k == 0)
+                        row[0] = X.x;
+                    else if (k == hx)
+                        row[1] = X.x;
+                    else
+                        *reinterpret_cast<double2*>(row + 2 * k) = X;
+                }
+            }
+            __syncthreads();
+        }
+        // columns: DFT along y, division by 1 - gamma lam, inverse DFT
+        const Sten5 o = a.op5;
+        const double scale = 1.0 / ((double)nx * (double)ny);
+        for (int k0 = 0; k0 <= hx; k0 += nw) {
+            const int kx = k0 + wv;
+            const bool act = kx <= hx;
+            const bool real = kx == 0 || kx == hx;
+            const int slot = kx == 0 ? 0 : (kx == hx ? 1 : 2 * kx);
+            if (act)
+                for (int j = lane; j < ny; j += WAVE) {
+                    const double* p = dst + (size_t)j * nx + slot;
+                    fbuf[bitrev(j, ly)] = real ? make_double2(p[0], 0.0)
+                                               : *reinterpret_cast<const double2*>(p);
+                }
+            __syncthreads();
+            wave_fft(fbuf, tw, ny, true, false, act, lane);
+            if (act) {
+                // with E = e^{-i th} (a table entry), w E + e conj(E) has
+                // real part (w + e) Re E and imaginary part (w - e) Im E
+                const double2 ex = tw[kx * (FFT2_MAX / nx)];
+                const double lxr = o.c + (o.w + o.e) * ex.x;
+                const double lxi = (o.w - o.e) * ex.y;
+                for (int ky = lane; ky < ny; ky += WAVE) {
+                    const double2 ey = tw[ky * (FFT2_MAX / ny)];
+                    // mr + i mi = 1 - gamma lam
+                    const double mr = 1.0 - gamma * (lxr + (o.s + o.n) * ey.x);
+                    const double mi = -gamma * (lxi + (o.s - o.n) * ey.y);
+                    const double d = scale / (mr * mr + mi * mi);
+                    const double2 z = fbuf[ky];
+                    fbuf[ky] = make_double2((z.x * mr + z.y * mi) * d, (z.y * mr - z.x * mi) * d);
+                }
+            }
+            __syncthreads();
+            wave_fft(fbuf, tw, ny, false, true, act, lane);
+            if (act)
+                for (int j = lane; j < ny; j += WAVE) {
+                    double* p = dst + (size_t)j * nx + slot;
+                    const double2 z = fbuf[bitrev(j, ly)];
+                    if (real)
+                        p[0] = z.x;
+                    else
+                        *reinterpret_cast<double2*>(p) = z;
+                }
+            __syncthreads();
+        }
+        // rows: inverse real DFT (Hermitian completion of the packed modes)
+        for (int r0 = 0; r0 < ny; r0 += nw) {
+            const int r = r0 + wv;
+            const bool act = r < ny;
+            double* row = dst + (size_t)r * nx;
+            if (act)
+                for (int k = lane; k < nx; k += WAVE) {
+                    double2 X;
+                    if (k == 0)
+                        X = make_double2(row[0], 0.0);
+                    else if (k == hx)
+                        X = make_double2(row[1], 0.0);
+                    else if (k < hx)
+                        X = *reinterpret_cast<const double2*>(row + 2 * k);
+                    else {
+                        X = *reinterpret_cast<const double2*>(row + 2 * (nx - k));
+                        X.y = -X.y;
+                    }
+                    fbuf[k] = X;
+                }
+            __syncthreads();
+            wave_fft(fbuf, tw, nx, false, true, act, lane);
+            if (act)
+                for (int j = lane; j < nx; j += WAVE) row[j] = fbuf[bitrev(j, lx)].x;
+            __syncthreads();
+        }
+    }
 
     __device__ __forceinline__ double2 ld2(const double* p, int g) const {
         return *reinterpret_cast<const double2*>(p + 2 * (size_t)g);
@@ -1688,11 +1889,11 @@ struct Ctx2 : Core<Ctx2, false> {
     }
 
     // Arnoldi from the (unnormalised) vector in V_0; same contract as
-    // Ctx::arnoldi (polynomial flavour).
+    // Ctx::arnoldi (both flavours: the shift-and-invert space from the
+    // Fourier solve, with the same extrapolated checks from about m/2 on).
     __device__ __forceinline__ int arnoldi(double gamma, double& beta, bool& bd,
                                            double ts = 0.0, double tolb_rel = 0.0,
                                            bool* conv = nullptr, double* est_out = nullptr) {
-        (void)gamma;
         beta = sqrt(block_sum(sumsq(V), S.red));
         bd = false;
         for (int o = t; o < (m + 1) * m; o += B) S.H[o] = 0.0;
@@ -1703,10 +1904,17 @@ struct Ctx2 : Core<Ctx2, false> {
         }
         scale(V, 1.0 / beta);
         int me = m;
+        this->si_kc = 0;
+        this->si_gp = 0;
+        this->si_dp = -1.0;
+        int knext = (m / 8 > 1 ? m / 8 : 1) * 4;  // first shift-and-invert check
         for (int j = 0; j < m; ++j) {
             double* w = V + (size_t)(j + 1) * n;
             __syncthreads();  // V_j complete: the stencil reads neighbours
-            apply(V + (size_t)j * n, w);
+            if constexpr (SI)
+                solve(V + (size_t)j * n, w, gamma);
+            else
+                apply(V + (size_t)j * n, w);
             // classical Gram-Schmidt, second pass by the DGKS criterion
             double nrm2 = 0.0, col = 0.0;
             for (int pass = 0; pass < 2; ++pass) {
@@ -1728,7 +1936,7 @@ struct Ctx2 : Core<Ctx2, false> {
                 break;
             }
             const int k = j + 1;
-            if (conv && ts > 0.0 && k < m && k >= 8 && (k % 4) == 0) {
+            if (!SI && conv && ts > 0.0 && k < m && k >= 8 && (k % 4) == 0) {
                 const double e1 = small_exp(k, ts, 0.0, S.vy);
                 const double est = beta * nrm * e1;
                 if (est <= tolb_rel * beta) {
@@ -1737,6 +1945,36 @@ struct Ctx2 : Core<Ctx2, false> {
                     me = k;
                     break;
                 }
+            }
+            if (SI && conv && ts > 0.0 && k < m && k == knext) {
+                // as in Ctx::arnoldi: the difference to the previous check's
+                // approximation, extrapolated by the observed contraction
+                small_exp(k, ts, gamma, S.vy);
+                int step = 4;
+                if (this->si_kc > 0) {
+                    const double d = this->si_diff(k);
+                    const int g = k - this->si_kc;
+                    const double est = this->si_extrapolate(d, this->si_dp, g, this->si_gp);
+                    __syncthreads();
+                    if (est <= tolb_rel) {
+                        *conv = true;
+                        if (est_out) *est_out = est;
+                        me = k;
+                        break;
+                    }
+                    if (this->si_dp > 0.0 && d < this->si_dp && est > 0.0) {
+                        const double r4 = pow(d / this->si_dp, 4.0 / (double)this->si_gp);
+                        const double blocks = ceil(log(tolb_rel / est) / log(r4));
+                        if (blocks > 1.0) step = 4 * (int)fmin(blocks, (double)m);
+                    }
+                    this->si_dp = d;
+                    this->si_gp = g;
+                }
+                knext = k + step < m - 4 ? k + step : m - 4;
+                if (knext < k + 4) knext = k + 4;
+                this->si_kc = k;
+                for (int q = t; q < k; q += B) S.yprev[q] = S.vy[q];
+                __syncthreads();
             }
             scale(w, 1.0 / nrm);
         }
@@ -1930,10 +2168,11 @@ struct Ctx2 : Core<Ctx2, false> {
     }
 };
 
+template <bool SI>
 __device__ __forceinline__ void dev_krylov2d(const KrylovArgs& a, int piece, double* lds) {
     const int n = a.n;
     double* V = a.basis + (size_t)piece * (a.m + 1) * n;
-    Ctx2 c(a, lds, V);
+    Ctx2<SI> c(a, lds, V);
     const double* vin = (a.mode == KM_CLASSIC) ? a.vin + (size_t)piece * n : a.vin;
     c.copy(vin, V);
     double* iout = (a.mode == KM_SINGLE) ? a.iout : nullptr;
@@ -1952,6 +2191,7 @@ __device__ __forceinline__ void dev_krylov2d(const KrylovArgs& a, int piece, dou
     if (y) c.copy(V, y);
 }
 
+template <bool SI>
 __global__ void __launch_bounds__(KRYLOV2D_BLOCK) k_krylov2d(const KrylovArgs* tab, int count) {
     extern __shared__ double lds[];
     const int b = blockIdx.x;
@@ -1961,7 +2201,7 @@ __global__ void __launch_bounds__(KRYLOV2D_BLOCK) k_krylov2d(const KrylovArgs* t
     const int piece = b - a.blk0;
     if (a.mode != KM_CLASSIC && piece > 0) return;
     if (a.mode == KM_CLASSIC && piece >= a.npieces) return;
-    dev_krylov2d(a, piece, lds);
+    dev_krylov2d<SI>(a, piece, lds);
 }
 
 template <bool SI, bool VAR>
@@ -2018,22 +2258,25 @@ size_t krylov1d_lds_bytes(int n, int m, int block, int si) {
     return d * sizeof(double);
 }
 
-size_t krylov2d_lds_bytes(int m) {
-    const int ldr = ((m + 1 + 7) / 8) * 8;
-    const size_t part = (size_t)(m + 1) * (KRYLOV2D_BLOCK / 64);
-    const size_t sm = 6 * (size_t)m * m + 5 * (size_t)m + 8;
-    const size_t d = 128 + ldr + 8 + (size_t)(m + 1) * m + ldr + UT_DOUBLES +
-                     (part > sm ? part : sm);
-    return d * sizeof(double);
+size_t krylov2d_lds_bytes(int m, int si) {
+    return (si ? krylov2d_si_doubles(m) : krylov2d_core_doubles(m)) * sizeof(double);
+}
+
+bool fft2_grid(int nx, int ny) {
+    auto p2 = [](int v) { return v >= 2 && (v & (v - 1)) == 0; };
+    return p2(nx) && p2(ny) && nx <= FFT2_MAX && ny <= FFT2_MAX;
 }
 
 hipError_t launch_krylov2d(const KrylovArgs* tab, int count, int total_blocks,
-                           size_t lds, hipStream_t s) {
+                           size_t lds, int si, hipStream_t s) {
     if (count <= 0 || total_blocks <= 0) return hipSuccess;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    (void)hipFuncSetAttribute((const void*)k_krylov2d,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_krylov2d<<<total_blocks, KRYLOV2D_BLOCK, lds, s>>>(tab, count);
+    const void* kern = si ? (const void*)k_krylov2d<true> : (const void*)k_krylov2d<false>;
+    (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (si)
+        k_krylov2d<true><<<total_blocks, KRYLOV2D_BLOCK, lds, s>>>(tab, count);
+    else
+        k_krylov2d<false><<<total_blocks, KRYLOV2D_BLOCK, lds, s>>>(tab, count);
     return hipGetLastError();
 }
 

@@ -70,6 +70,9 @@ std::vector<pxp_problem> candidates(const pxp_problem& base, int lo, int hi) {
                        PXP_KRYLOV_CHEBYSHEV})
             for (int sc : {PXP_SCHED_CLASSIC, PXP_SCHED_CHAIN}) {
                 if (!linear && sc == PXP_SCHED_CHAIN) continue;
+                // 2D shift-and-invert pays two 2D Fourier transforms per
+                // Krylov dimension: a named choice, not a tuning candidate
+                if (twod && kr == PXP_KRYLOV_SHIFT_INVERT) continue;
                 for (int kb : {256, 512}) {
                     if (twod && kb == 512) continue;
                     pxp_problem c = base;

@@ -126,7 +126,8 @@ def test_calls_fail_before_enqueue(lib):
 
 def test_2d_shape_and_precision_rules():
     """2D problems: power-of-two rows of 64..256 points, whole 16-row bands,
-    2048-point multiples, non-negative velocities, FP64, polynomial Krylov;
+    2048-point multiples, non-negative velocities, FP64; shift-and-invert on
+    power-of-two grids;
     the Paraexp path takes at most four RK4 steps per slice (checked when a
     call names the method)."""
     import math
@@ -145,11 +146,25 @@ def test_2d_shape_and_precision_rules():
         with pytest.raises(_lib.PxpError) as e:
             _lib.pxp_workspace_size([p])
         assert e.value.code == code, change
-    for kw, code in [(dict(krylov="shift_invert"), _lib.PXP_EUNSUPPORTED),
-                     (dict(krylov="poly", prec="fp32_bulk"), _lib.PXP_EUNSUPPORTED)]:
+    for kw, code in [(dict(krylov="poly", prec="fp32_bulk"), _lib.PXP_EUNSUPPORTED)]:
         with pytest.raises(_lib.PxpError) as e:
             _lib.pxp_workspace_size([api.make_problem(base, **kw)])
         assert e.value.code == code, kw
+    # shift-and-invert (the Fourier solve): power-of-two grids of at most
+    # 256 x 256, a Krylov dimension whose LDS layout (the FFT buffers share
+    # the small dense scratch) fits in 160 KB, terminal cost only
+    assert _lib.pxp_workspace_size([api.make_problem(base, krylov="shift_invert")]) > 0
+    assert _lib.pxp_workspace_size([api.make_problem(dict(base, m=50),
+                                                     krylov="shift_invert")]) > 0
+    for change in [dict(ny=48, basis=np.zeros((1, 64 * 48))), dict(m=60)]:
+        with pytest.raises(_lib.PxpError) as e:
+            _lib.pxp_workspace_size([api.make_problem(dict(base, **change),
+                                                      krylov="shift_invert")])
+        assert e.value.code == _lib.PXP_EUNSUPPORTED, change
+    with pytest.raises(_lib.PxpError) as e:
+        _lib.pxp_workspace_size([api.make_problem(dict(base, cost="integral"),
+                                                  krylov="shift_invert", sched="tree")])
+    assert e.value.code == _lib.PXP_EUNSUPPORTED
     # eight steps per slice: sized and accepted, refused by the Paraexp call
     p8 = api.make_problem(dict(base, P=8), krylov="poly")
     assert _lib.pxp_workspace_size([p8]) > 0

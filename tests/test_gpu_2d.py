@@ -207,3 +207,86 @@ def run_flavour(inst, krylov, **kw):
     out = r.results()[0]
     out["status"], out["est"] = r.status()
     return out
+
+
+# ---- shift-and-invert flavour: Krylov on (I - gamma A)^{-1}, Fourier solve ----
+
+def test_adjoint_piece_2d_si_vs_fourier(torch):
+    """lambda(0) = exp(T A^T) lambda_T and its time integral Lambda from one
+    shift-and-invert space of the transposed operator (the 2D periodic
+    solve by Fourier diagonalisation in every Arnoldi step), against the
+    Fourier closed forms."""
+    inst = small2d(nx=64, ny=64, T=0.7, nt=64, P=16, m=50)
+    n = inst["nx"] * inst["ny"]
+    lamT = np.asarray(inst["u_tgt"])
+    p = api.make_problem(inst, krylov="shift_invert", tol=1e-11)
+    dev = torch.device("cuda:0")
+    f64 = dict(dtype=torch.float64, device=dev)
+    ws = torch.empty(_lib.pxp_workspace_size([p]), dtype=torch.uint8, device=dev)
+    _lib.pxp_workspace_init(ws)
+    lam0 = torch.zeros(n, **f64)
+    Lam = torch.zeros(n, **f64)
+    say("2d si adjoint piece: 64 x 64, m=50")
+    _lib.paraexp_adjoint([p], torch.tensor(lamT, **f64), lam0, Lam, ws)
+    code, est = _lib.pxp_device_status(ws)
+    lam_eig = fourier.eigenvalues(inst)
+    want0 = fourier.exp_action_T(inst, inst["T"], lamT, lam_eig)
+    mu = np.conj(lam_eig)
+    T, w = inst["T"], inst["omega"]
+    tr = (w * np.exp(mu * T) - mu * np.sin(w * T) - w * np.cos(w * T)) / (mu ** 2 + w ** 2)
+    wantL = fourier._ifft(inst, tr * fourier._fft(inst, lamT))
+    e0, eL = rel(lam0.cpu().numpy(), want0), rel(Lam.cpu().numpy(), wantL)
+    say("2d si adjoint piece: lam0 %.2e Lambda %.2e est %.1e code %d" % (e0, eL, est, code))
+    assert code == 0
+    assert e0 < 1e-9 and eL < 1e-9
+
+
+@pytest.mark.parametrize("sched", ["chain", "classic"])
+def test_paraexp_2d_si_matches_oracle(torch, orc, sched):
+    inst = small2d(P=16)
+    say("2d si paraexp %s: 64 x 32, P=16" % sched)
+    got = run_flavour(inst, "shift_invert", sched=sched, tol=1e-11)
+    want = orc.gradient(inst)
+    e = rel(got["grad"], want["grad"])
+    say("2d si %s: qT %.2e grad %.2e status %d" % (
+        sched, rel(got["qT"], want["qT"]), e, got["status"]))
+    assert got["status"] == 0
+    assert rel(got["qT"], want["qT"]) < FP64_GATE and e < FP64_GATE
+
+
+def test_mixed_flavour_2d_batch_equals_one_by_one(torch):
+    """A batch with polynomial and shift-and-invert instances (two launches
+    of the 2D Krylov kernel, one per flavour) gives each instance the
+    bits of its own call."""
+    insts = [small2d(seed=20), small2d(nx=128, ny=32, seed=21, T=0.4),
+             small2d(nx=64, ny=64, seed=22, nt=32, P=8, T=0.25)]
+    kinds = ["shift_invert", "poly", "shift_invert"]
+    say("2d mixed flavour batch")
+    probs = [api.make_problem(i, krylov=k, sched="classic", tol=1e-11)
+             for i, k in zip(insts, kinds)]
+    r = api.GradientRunner(insts, method="paraexp", problems=probs)
+    r.run()
+    code, _ = r.status()
+    assert code == 0
+    for inst, k, b in zip(insts, kinds, r.results()):
+        one = run_flavour(inst, k, sched="classic", tol=1e-11)
+        assert np.array_equal(one["grad"], b["grad"]), k
+        assert np.array_equal(one["qT"], b["qT"]), k
+
+
+def test_workload_2d_si_sample(torch, orc):
+    """The shortest instance of the 256 x 256 workload (P = 256, Krylov
+    dimension 50) with shift-and-invert pieces, classic schedule (255
+    independent pieces, each its own space), against the oracle."""
+    import time
+    full = workloads.make("advdiff2d_256")
+    inst = min(full, key=lambda x: x["n_steps"])
+    say("2d workload si classic: T=%.3f nt=%d" % (inst["T"], inst["n_steps"]))
+    t0 = time.perf_counter()
+    got = run_flavour(inst, "shift_invert", sched="classic")
+    dt = time.perf_counter() - t0
+    want = orc.gradient(inst)
+    e = rel(got["grad"], want["grad"])
+    say("2d workload si classic: grad %.2e qT %.2e status %d (%.2f s with setup)" % (
+        e, rel(got["qT"], want["qT"]), got["status"], dt))
+    assert got["status"] == 0 and e < FP64_GATE
