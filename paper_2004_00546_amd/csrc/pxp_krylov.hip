@@ -1615,36 +1615,42 @@ __device__ __forceinline__ double2 cmul(double2 u, double2 v) {
     return make_double2(u.x * v.x - u.y * v.y, u.x * v.y + u.y * v.x);
 }
 
+// Orders one wave's LDS accesses: the wave's LDS operations complete in
+// issue order, so a compiler fence at wavefront scope is all a transform
+// stage needs between writing points and reading other lanes' points.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // In-place radix-2 transform of the L points in buf (L a power of two,
 // L <= FFT2_MAX) by the lanes of one wave.  dit: the input is in bit-reversed
 // order and the output in natural order (decimation in time); otherwise the
 // reverse (decimation in frequency).  inv: e^{+2 pi i jk / L} (unscaled).
-// Every stage ends at a workgroup barrier, so all waves call it with the
-// same L whether or not their buffer holds a transform (act).
+// Wave-local: the caller orders the buffer's writes before the call.
 __device__ __forceinline__ void wave_fft(double2* buf, const double2* tw, int L, bool dit,
-                                         bool inv, bool act, int lane) {
+                                         bool inv, int lane) {
     const int nb = L >> 1;
     for (int s = 0; (1 << s) < L; ++s) {
         const int len = dit ? (2 << s) : (L >> s), half = len >> 1;
         const int ts = FFT2_MAX / len;
-        if (act) {
-            for (int b = lane; b < nb; b += WAVE) {
-                const int grp = b / half, pos = b - grp * half;
-                const int i0 = grp * len + pos, i1 = i0 + half;
-                double2 w = tw[pos * ts];
-                if (inv) w.y = -w.y;
-                const double2 u = buf[i0], v = buf[i1];
-                if (dit) {
-                    const double2 tv = cmul(v, w);
-                    buf[i0] = make_double2(u.x + tv.x, u.y + tv.y);
-                    buf[i1] = make_double2(u.x - tv.x, u.y - tv.y);
-                } else {
-                    buf[i0] = make_double2(u.x + v.x, u.y + v.y);
-                    buf[i1] = cmul(make_double2(u.x - v.x, u.y - v.y), w);
-                }
+        for (int b = lane; b < nb; b += WAVE) {
+            const int grp = b / half, pos = b - grp * half;
+            const int i0 = grp * len + pos, i1 = i0 + half;
+            double2 w = tw[pos * ts];
+            if (inv) w.y = -w.y;
+            const double2 u = buf[i0], v = buf[i1];
+            if (dit) {
+                const double2 tv = cmul(v, w);
+                buf[i0] = make_double2(u.x + tv.x, u.y + tv.y);
+                buf[i1] = make_double2(u.x - tv.x, u.y - tv.y);
+            } else {
+                buf[i0] = make_double2(u.x + v.x, u.y + v.y);
+                buf[i1] = cmul(make_double2(u.x - v.x, u.y - v.y), w);
             }
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -1681,105 +1687,94 @@ struct Ctx2 : Core<Ctx2<SI>, SI> {
     __device__ __forceinline__ void before_space(double) {}
 
     // dst = (I - gamma A)^{-1} src (all of src visible to the workgroup; dst
-    // complete at the caller's next barrier).  src and dst are distinct.
+    // complete on return).  src and dst are distinct.  Each wave takes rows
+    // (or x-wavenumbers) on its own; the workgroup meets only between passes.
     __device__ void solve(const double* __restrict__ src, double* __restrict__ dst,
                           double gamma) {
         const int lane = lane_id(), wv = wave_id(), nw = num_waves();
         const int lx = 31 - __clz(nx), ly = 31 - __clz(ny), hx = nx >> 1;
         // rows: real DFT, packed
-        for (int r0 = 0; r0 < ny; r0 += nw) {
-            const int r = r0 + wv;
-            const bool act = r < ny;
-            if (act)
-                for (int j = lane; j < nx; j += WAVE)
-                    fbuf[bitrev(j, lx)] = make_double2(src[(size_t)r * nx + j], 0.0);
-            __syncthreads();
-            wave_fft(fbuf, tw, nx, true, false, act, lane);
-            if (act) {
-                double* row = dst + (size_t)r * nx;
-                for (int k = lane; k <= hx; k += WAVE) {
-                    const double2 X = fbuf[k];
-                    if (k == 0)
-                        row[0] = X.x;
-                    else if (k == hx)
-                        row[1] = X.x;
-                    else
-                        *reinterpret_cast<double2*>(row + 2 * k) = X;
-                }
+        for (int r = wv; r < ny; r += nw) {
+            for (int j = lane; j < nx; j += WAVE)
+                fbuf[bitrev(j, lx)] = make_double2(src[(size_t)r * nx + j], 0.0);
+            wave_sync();
+            wave_fft(fbuf, tw, nx, true, false, lane);
+            double* row = dst + (size_t)r * nx;
+            for (int k = lane; k <= hx; k += WAVE) {
+                const double2 X = fbuf[k];
+                if (k == 0)
+                    row[0] = X.x;
+                else if (k == hx)
+                    row[1] = X.x;
+                else
+                    *reinterpret_cast<double2*>(row + 2 * k) = X;
             }
-            __syncthreads();
+            wave_sync();
         }
+        __syncthreads();
         // columns: DFT along y, division by 1 - gamma lam, inverse DFT
         const Sten5 o = a.op5;
         const double scale = 1.0 / ((double)nx * (double)ny);
-        for (int k0 = 0; k0 <= hx; k0 += nw) {
-            const int kx = k0 + wv;
-            const bool act = kx <= hx;
+        for (int kx = wv; kx <= hx; kx += nw) {
             const bool real = kx == 0 || kx == hx;
             const int slot = kx == 0 ? 0 : (kx == hx ? 1 : 2 * kx);
-            if (act)
-                for (int j = lane; j < ny; j += WAVE) {
-                    const double* p = dst + (size_t)j * nx + slot;
-                    fbuf[bitrev(j, ly)] = real ? make_double2(p[0], 0.0)
-                                               : *reinterpret_cast<const double2*>(p);
-                }
-            __syncthreads();
-            wave_fft(fbuf, tw, ny, true, false, act, lane);
-            if (act) {
-                // with E = e^{-i th} (a table entry), w E + e conj(E) has
-                // real part (w + e) Re E and imaginary part (w - e) Im E
-                const double2 ex = tw[kx * (FFT2_MAX / nx)];
-                const double lxr = o.c + (o.w + o.e) * ex.x;
-                const double lxi = (o.w - o.e) * ex.y;
-                for (int ky = lane; ky < ny; ky += WAVE) {
-                    const double2 ey = tw[ky * (FFT2_MAX / ny)];
-                    // mr + i mi = 1 - gamma lam
-                    const double mr = 1.0 - gamma * (lxr + (o.s + o.n) * ey.x);
-                    const double mi = -gamma * (lxi + (o.s - o.n) * ey.y);
-                    const double d = scale / (mr * mr + mi * mi);
-                    const double2 z = fbuf[ky];
-                    fbuf[ky] = make_double2((z.x * mr + z.y * mi) * d, (z.y * mr - z.x * mi) * d);
-                }
+            for (int j = lane; j < ny; j += WAVE) {
+                const double* p = dst + (size_t)j * nx + slot;
+                fbuf[bitrev(j, ly)] =
+                    real ? make_double2(p[0], 0.0) : *reinterpret_cast<const double2*>(p);
             }
-            __syncthreads();
-            wave_fft(fbuf, tw, ny, false, true, act, lane);
-            if (act)
-                for (int j = lane; j < ny; j += WAVE) {
-                    double* p = dst + (size_t)j * nx + slot;
-                    const double2 z = fbuf[bitrev(j, ly)];
-                    if (real)
-                        p[0] = z.x;
-                    else
-                        *reinterpret_cast<double2*>(p) = z;
-                }
-            __syncthreads();
+            wave_sync();
+            wave_fft(fbuf, tw, ny, true, false, lane);
+            // with E = e^{-i th} (a table entry), w E + e conj(E) has real
+            // part (w + e) Re E and imaginary part (w - e) Im E
+            const double2 ex = tw[kx * (FFT2_MAX / nx)];
+            const double lxr = o.c + (o.w + o.e) * ex.x;
+            const double lxi = (o.w - o.e) * ex.y;
+            for (int ky = lane; ky < ny; ky += WAVE) {
+                const double2 ey = tw[ky * (FFT2_MAX / ny)];
+                // mr + i mi = 1 - gamma lam
+                const double mr = 1.0 - gamma * (lxr + (o.s + o.n) * ey.x);
+                const double mi = -gamma * (lxi + (o.s - o.n) * ey.y);
+                const double d = scale / (mr * mr + mi * mi);
+                const double2 z = fbuf[ky];
+                fbuf[ky] = make_double2((z.x * mr + z.y * mi) * d, (z.y * mr - z.x * mi) * d);
+            }
+            wave_sync();
+            wave_fft(fbuf, tw, ny, false, true, lane);
+            for (int j = lane; j < ny; j += WAVE) {
+                double* p = dst + (size_t)j * nx + slot;
+                const double2 z = fbuf[bitrev(j, ly)];
+                if (real)
+                    p[0] = z.x;
+                else
+                    *reinterpret_cast<double2*>(p) = z;
+            }
+            wave_sync();
         }
+        __syncthreads();
         // rows: inverse real DFT (Hermitian completion of the packed modes)
-        for (int r0 = 0; r0 < ny; r0 += nw) {
-            const int r = r0 + wv;
-            const bool act = r < ny;
+        for (int r = wv; r < ny; r += nw) {
             double* row = dst + (size_t)r * nx;
-            if (act)
-                for (int k = lane; k < nx; k += WAVE) {
-                    double2 X;
-                    if (k == 0)
-                        X = make_double2(row[0], 0.0);
-                    else if (k == hx)
-                        X = make_double2(row[1], 0.0);
-                    else if (k < hx)
-                        X = *reinterpret_cast<const double2*>(row + 2 * k);
-                    else {
-                        X = *reinterpret_cast<const double2*>(row + 2 * (nx - k));
-                        X.y = -X.y;
-                    }
-                    fbuf[k] = X;
+            for (int k = lane; k < nx; k += WAVE) {
+                double2 X;
+                if (k == 0)
+                    X = make_double2(row[0], 0.0);
+                else if (k == hx)
+                    X = make_double2(row[1], 0.0);
+                else if (k < hx)
+                    X = *reinterpret_cast<const double2*>(row + 2 * k);
+                else {
+                    X = *reinterpret_cast<const double2*>(row + 2 * (nx - k));
+                    X.y = -X.y;
                 }
-            __syncthreads();
-            wave_fft(fbuf, tw, nx, false, true, act, lane);
-            if (act)
-                for (int j = lane; j < nx; j += WAVE) row[j] = fbuf[bitrev(j, lx)].x;
-            __syncthreads();
+                fbuf[k] = X;
+            }
+            wave_sync();
+            wave_fft(fbuf, tw, nx, false, true, lane);
+            for (int j = lane; j < nx; j += WAVE) row[j] = fbuf[bitrev(j, lx)].x;
+            wave_sync();
         }
+        __syncthreads();
     }
 
     __device__ __forceinline__ double2 ld2(const double* p, int g) const {
