@@ -290,3 +290,24 @@ def test_workload_2d_si_sample(torch, orc):
     say("2d workload si classic: grad %.2e qT %.2e status %d (%.2f s with setup)" % (
         e, rel(got["qT"], want["qT"]), got["status"], dt))
     assert got["status"] == 0 and e < FP64_GATE
+
+
+@pytest.mark.parametrize("krylov,sched", [("shift_invert", "classic"), ("poly", "chain"),
+                                          ("auto", "tree")])
+def test_nan_input_2d_sets_nonfinite_status(torch, krylov, sched):
+    """A NaN in the 2D initial state comes back as PXP_ENONFINITE on the
+    Krylov flavours and on uniformisation, and a clean run after it reports
+    OK again."""
+    inst = small2d(P=16)
+    q0 = np.zeros(inst["nx"] * inst["ny"])
+    q0[100] = np.nan
+    say("2d nan input: %s %s" % (krylov, sched))
+    r = api.GradientRunner([dict(inst, q0=q0)], method="paraexp", krylov=krylov,
+                           sched=sched, tol=1e-10)
+    r.run()
+    code, _ = r.status()
+    assert code == _lib.PXP_ENONFINITE, (krylov, code)
+    r2 = api.GradientRunner([inst], method="paraexp", krylov=krylov, sched=sched, tol=1e-10)
+    r2.run()
+    code2, _ = r2.status()
+    assert code2 == 0, (krylov, code2)
