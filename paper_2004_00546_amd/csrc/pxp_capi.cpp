@@ -2247,9 +2247,9 @@ pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, v
                     (*nparts)[who[e]] = st[e].items * (st[e].ny / st[e].rows);
         }
     }
-    // Krylov pieces: classic (P-1 workgroups) or chain (one)
+    // Krylov pieces: classic (P-1 workgroups) or chain (one); the
+    // workgroups are numbered per flavour group at launch
     std::vector<KrylovArgs> kt;
-    int kblk = 0;
     for (size_t j = 0; j < idx.size(); ++j) {
         const pxp_problem& p = pb[idx[j]];
         if (p.P == 1 || uniform_direct(p)) continue;
@@ -2261,17 +2261,14 @@ pxp_status direct_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, v
         a.ny = p.ny;
         a.vin = c.at(c.L.slices);
         a.tau = p.T / p.P;
-        a.blk0 = kblk;
         if (p.sched == PXP_SCHED_CLASSIC) {
             a.mode = KM_CLASSIC;
             a.npieces = p.P - 1;
             a.yout = c.at(c.L.pieces);
-            kblk += p.P - 1;
         } else {
             a.mode = KM_CHAIN;
             a.npieces = p.P;
             a.yout = c.at(c.L.chain);
-            kblk += 1;
         }
         kt.push_back(a);
     }
@@ -2517,7 +2514,6 @@ pxp_status adjoint_2d_batch(const pxp_problem* pb, const std::vector<int>& idx, 
         a.tau = p.T;
         a.ia = p.omega * p.T;
         a.ib = -p.omega;
-        a.blk0 = (int)kt.size();
         kt.push_back(a);
     }
     if (kt.empty()) return PXP_OK;
