@@ -211,22 +211,28 @@ def run_flavour(inst, krylov, **kw):
 
 # ---- shift-and-invert flavour: Krylov on (I - gamma A)^{-1}, Fourier solve ----
 
-def test_adjoint_piece_2d_si_vs_fourier(torch):
+@pytest.mark.parametrize("nx,ny,nt,tol,gate", [(64, 64, 64, 1e-11, 1e-9),
+                                              (128, 32, 128, 1e-10, 1e-9),
+                                              (256, 16, 128, 1e-9, 1e-8)])
+def test_adjoint_piece_2d_si_vs_fourier(torch, nx, ny, nt, tol, gate):
     """lambda(0) = exp(T A^T) lambda_T and its time integral Lambda from one
     shift-and-invert space of the transposed operator (the 2D periodic
     solve by Fourier diagonalisation in every Arnoldi step), against the
-    Fourier closed forms."""
-    inst = small2d(nx=64, ny=64, T=0.7, nt=64, P=16, m=50)
+    Fourier closed forms, on square and flat grids (a 16-point column
+    transform on the 256 x 16 grid).  A random lambda_T excites every mode;
+    the flat grids' wider spectra converge more slowly, hence their looser
+    tolerances."""
+    inst = small2d(nx=nx, ny=ny, T=0.7, nt=nt, P=16, m=50)
     n = inst["nx"] * inst["ny"]
     lamT = np.asarray(inst["u_tgt"])
-    p = api.make_problem(inst, krylov="shift_invert", tol=1e-11)
+    p = api.make_problem(inst, krylov="shift_invert", tol=tol)
     dev = torch.device("cuda:0")
     f64 = dict(dtype=torch.float64, device=dev)
     ws = torch.empty(_lib.pxp_workspace_size([p]), dtype=torch.uint8, device=dev)
     _lib.pxp_workspace_init(ws)
     lam0 = torch.zeros(n, **f64)
     Lam = torch.zeros(n, **f64)
-    say("2d si adjoint piece: 64 x 64, m=50")
+    say("2d si adjoint piece: %d x %d, m=50" % (nx, ny))
     _lib.paraexp_adjoint([p], torch.tensor(lamT, **f64), lam0, Lam, ws)
     code, est = _lib.pxp_device_status(ws)
     lam_eig = fourier.eigenvalues(inst)
@@ -238,7 +244,7 @@ def test_adjoint_piece_2d_si_vs_fourier(torch):
     e0, eL = rel(lam0.cpu().numpy(), want0), rel(Lam.cpu().numpy(), wantL)
     say("2d si adjoint piece: lam0 %.2e Lambda %.2e est %.1e code %d" % (e0, eL, est, code))
     assert code == 0
-    assert e0 < 1e-9 and eL < 1e-9
+    assert e0 < gate and eL < gate
 
 
 @pytest.mark.parametrize("sched", ["chain", "classic"])
