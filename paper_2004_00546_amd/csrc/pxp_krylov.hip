@@ -114,6 +114,9 @@ struct Core {
     // gap in dimensions between those two checks.
     int si_kc = 0, si_gp = 0;
     double si_dp = -1.0;
+    // Error of an approximation: the extrapolated difference to the previous
+    // check (si_extrapolate), or, with si_plain, the difference itself.
+    bool si_plain = false;
 
     __device__ Core(const KrylovArgs& a_, double* lds)
         : a(a_), n(a_.n), m(a_.m), B(blockDim.x), t(threadIdx.x) {
@@ -304,7 +307,8 @@ struct Core {
                 // after a breakdown the space is exact
                 if (!bd && si_kc > 0 && si_kc < me) {
                     small_exp(me, tau, gamma, S.vy);
-                    est = si_extrapolate(si_diff(me), si_dp, me - si_kc, si_gp);
+                    est = si_plain ? si_diff(me)
+                                   : si_extrapolate(si_diff(me), si_dp, me - si_kc, si_gp);
                     __syncthreads();
                 } else if (!bd && me > 1) {
                     small_exp(me - 1, tau, gamma, S.vy2);
@@ -1673,6 +1677,9 @@ struct Ctx2 : Core<Ctx2<SI>, SI> {
     __device__ Ctx2(const KrylovArgs& a_, double* lds, double* V_)
         : Base(a_, lds), V(V_), G(a_.n / (2 * blockDim.x)), nx(a_.nx), ny(a_.ny) {
         if constexpr (SI) {
+            // the 2D spaces' differences need not contract geometrically
+            // (advection): the error is taken as the difference itself
+            this->si_plain = true;
             tw = reinterpret_cast<double2*>(lds + krylov2d_si_doubles(a_.m) - 2 * FFT2_MAX);
             fbuf = reinterpret_cast<double2*>(S.big) + (size_t)wave_id() * FFT2_MAX;
             for (int k = t; k < FFT2_MAX; k += B) {
@@ -1942,14 +1949,14 @@ struct Ctx2 : Core<Ctx2<SI>, SI> {
                 }
             }
             if (SI && conv && ts > 0.0 && k < m && k == knext) {
-                // as in Ctx::arnoldi: the difference to the previous check's
-                // approximation, extrapolated by the observed contraction
+                // as in Ctx::arnoldi, with the difference to the previous
+                // check's approximation itself as the error (si_plain)
                 small_exp(k, ts, gamma, S.vy);
                 int step = 4;
                 if (this->si_kc > 0) {
                     const double d = this->si_diff(k);
                     const int g = k - this->si_kc;
-                    const double est = this->si_extrapolate(d, this->si_dp, g, this->si_gp);
+                    const double est = d;
                     __syncthreads();
                     if (est <= tolb_rel) {
                         *conv = true;
