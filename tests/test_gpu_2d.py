@@ -317,3 +317,38 @@ def test_nan_input_2d_sets_nonfinite_status(torch, krylov, sched):
     r2.run()
     code2, _ = r2.status()
     assert code2 == 0, (krylov, code2)
+
+
+def test_graph_replay_mixed_flavour_2d(torch):
+    """A 2D batch of shift-and-invert and polynomial instances (two table
+    uploads and two launches of the 2D Krylov kernel per phase) captured in
+    a graph: every replay, with eager runs in between, gives the eager
+    bits."""
+    insts = [small2d(seed=30), small2d(nx=128, ny=32, seed=31, T=0.4)]
+    probs = [api.make_problem(i, krylov=k, sched="classic", tol=1e-11)
+             for i, k in zip(insts, ["shift_invert", "poly"])]
+    say("2d mixed flavour graph replay")
+    r = api.GradientRunner(insts, method="paraexp", problems=probs)
+    r.run()
+    eager = r.results()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        r.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        r.run()
+    for rep in range(3):
+        r.grad.zero_()
+        r.qT.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(r.results(), eager):
+            assert np.array_equal(a["grad"], b["grad"]), rep
+            assert np.array_equal(a["qT"], b["qT"]), rep
+        r.run()
+        torch.cuda.synchronize()
+    assert r.status()[0] == 0
