@@ -205,6 +205,7 @@ def run_flavour(inst, krylov, **kw):
     r = api.GradientRunner([inst], method="paraexp", krylov=krylov, **kw)
     r.run()
     out = r.results()[0]
+    out["report"] = _lib.pxp_last_report(r.problems, r.ws)[0]
     out["status"], out["est"] = r.status()
     return out
 
@@ -258,6 +259,9 @@ def test_paraexp_2d_si_matches_oracle(torch, orc, sched):
         sched, rel(got["qT"], want["qT"]), e, got["status"]))
     assert got["status"] == 0
     assert rel(got["qT"], want["qT"]) < FP64_GATE and e < FP64_GATE
+    rep = got["report"]
+    assert rep["krylov_direct"] == "shift_invert" and rep["krylov_adjoint"] == "shift_invert"
+    assert rep["sched"] == sched and rep["iterations"] > 0
 
 
 def test_mixed_flavour_2d_batch_equals_one_by_one(torch):
