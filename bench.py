@@ -409,6 +409,8 @@ def measure(args, name, torch, _lib, api, workloads, steps, serial_steps, with_o
     insts = workloads.make(name)
     if args.instances > 0 and name == args.workload:
         insts = insts[:args.instances]
+    if args.pick and name == args.workload:
+        insts = [insts[int(i)] for i in args.pick.split(",")]
     if name == args.workload:
         for key, v in (("hyb_slices", args.hyb_slices), ("hyb_k", args.hyb_k),
                        ("hyb_group", args.hyb_group), ("nl_iters", args.nl_iters),
@@ -696,6 +698,9 @@ def main():
                     help="iterative nonlinear direct: slices of the iteration")
     ap.add_argument("--slices", type=int, default=None,
                     help="override the workload's slice count P")
+    ap.add_argument("--pick", default="",
+                    help="comma-separated instance indices of the workload to run "
+                         "(e.g. one diffusivity of advdiff2d_icost)")
     ap.add_argument("--instances", type=int, default=0,
                     help="use only the first K instances of a batch workload (0 = all)")
     ap.add_argument("--oracle-budget", type=float, default=2.5e8,
