@@ -9,7 +9,9 @@ backward, paper section 3.5),
 (Krylov pieces, or the Magnus chain for Burgers) and
 ``pxp_reduce_gradient`` (eqs. paramupdate, initupdate); the incoming
 gradient gJ scales the result.  Every step runs in libparaexp.so; torch only
-holds the device buffers.
+holds the device buffers.  Terminal cost only: an integral-cost problem is
+refused by ``pxp_cost`` (its cost needs the trajectory, which the one-call
+gradient forms), and the forward raises.
 """
 from __future__ import annotations
 
